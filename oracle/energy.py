@@ -1,0 +1,171 @@
+"""Expectation values <psi|H|psi> / <psi|psi> of H = sum_t H_t (Eq. 5).
+
+Cached (Sec. IV-B): two full boundary contractions, one from the top and one
+from the bottom, store every intermediate boundary MPS.  A one-site or
+horizontal two-site term on row i is then a contraction of a three-row strip
+(top environment of row i-1, row i, bottom environment of row i+1); a
+vertical term on rows i, i+1 uses a four-row strip.  Each term is the ratio
+strip(term) / strip(identity) evaluated with the same left/right strip
+environments, so all scale factors cancel.
+
+Uncached (test-only cross-check): every term is an independent full
+boundary-MPS contraction of <psi|H_t|psi>, divided by <psi|psi>.
+
+A term is (sites, op): sites a tuple of (i, j); op is [2,2] (out, in) for one
+site or [2,2,2,2] (out1, out2, in1, in2) for two nearest-neighbour sites with
+site 1 left of / above site 2.
+"""
+import numpy as np
+
+from .bmps import BOTTOM, TOP, boundary_pass, peps_norm
+
+
+def operator_schmidt(op2, tol=1e-14):
+    """op2[P1,P2,p1,p2] = sum_k A_k[P1,p1] B_k[P2,p2]."""
+    d = op2.shape[0]
+    M = op2.transpose(0, 2, 1, 3).reshape(d * d, d * d)
+    U, s, Vh = np.linalg.svd(M)
+    keep = s > tol * s[0]
+    A = (U[:, keep] * s[keep]).T.reshape(-1, d, d)
+    B = Vh[keep].reshape(-1, d, d)
+    return list(zip(A, B))
+
+
+def _trivial_env(ncol, dtype):
+    return [np.ones((1, 1, 1, 1), dtype=dtype) for _ in range(ncol)]
+
+
+def _col3(L, Tp, T, O, B, Bt):
+    return np.einsum("tlLb,tuUs,udlrp,Pp,UDLRP,bdDc->srRc",
+                     L, Tp, T, O, B.conj(), Bt, optimize=True)
+
+
+def _col4(L, Tp, T1, O1, B1, T2, O2, B2, Bt):
+    return np.einsum("tlLmMb,tuUs,uvlrp,Pp,UVLRP,vdmnq,Qq,VDMNQ,bdDc->srRnNc",
+                     L, Tp, T1, O1, B1.conj(), T2, O2, B2.conj(), Bt, optimize=True)
+
+
+def _norm(x):
+    n = np.linalg.norm(x)
+    return x / n if n > 0 else x
+
+
+def _row_terms(top, ket_row, bot, terms_here, d, dtype):
+    """Three-row strip for one-site and horizontal terms of one lattice row."""
+    n = len(ket_row)
+    I = np.eye(d, dtype=dtype)
+    Ls = [np.ones((1, 1, 1, 1), dtype=dtype)]
+    for j in range(n):
+        Ls.append(_norm(_col3(Ls[-1], top[j], ket_row[j], I, ket_row[j], bot[j])))
+    # right environments by mirroring the transfer: contract from the right
+    Rs = [np.ones((1, 1, 1, 1), dtype=dtype)]
+    for j in reversed(range(n)):
+        R = np.einsum("srRc,tuUs,udlrp,Pp,UDLRP,bdDc->tlLb", Rs[-1], top[j], ket_row[j], I,
+                      ket_row[j].conj(), bot[j], optimize=True)
+        Rs.append(_norm(R))
+    Rs = Rs[::-1]  # Rs[j] = environment right of column j-1 (covers columns j..n-1)
+    out = []
+    for sites, op in terms_here:
+        j = sites[0][1]
+        if len(sites) == 1:
+            num = np.vdot(Rs[j + 1].conj(), _col3(Ls[j], top[j], ket_row[j], op, ket_row[j], bot[j]))
+            den = np.vdot(Rs[j + 1].conj(), _col3(Ls[j], top[j], ket_row[j], I, ket_row[j], bot[j]))
+        else:
+            num = 0.0
+            for A, B in operator_schmidt(op):
+                X = _col3(Ls[j], top[j], ket_row[j], A, ket_row[j], bot[j])
+                X = _col3(X, top[j + 1], ket_row[j + 1], B, ket_row[j + 1], bot[j + 1])
+                num = num + np.vdot(Rs[j + 2].conj(), X)
+            X = _col3(Ls[j], top[j], ket_row[j], I, ket_row[j], bot[j])
+            X = _col3(X, top[j + 1], ket_row[j + 1], I, ket_row[j + 1], bot[j + 1])
+            den = np.vdot(Rs[j + 2].conj(), X)
+        out.append((sites, num / den))
+    return out
+
+
+def _pair_terms(top, row1, row2, bot, terms_here, d, dtype):
+    """Four-row strip for vertical terms between two lattice rows."""
+    n = len(row1)
+    I = np.eye(d, dtype=dtype)
+    one = np.ones((1,) * 6, dtype=dtype)
+    Ls = [one]
+    for j in range(n):
+        Ls.append(_norm(_col4(Ls[-1], top[j], row1[j], I, row1[j], row2[j], I, row2[j], bot[j])))
+    Rs = [one]
+    for j in reversed(range(n)):
+        R = np.einsum("srRnNc,tuUs,uvlrp,Pp,UVLRP,vdmnq,Qq,VDMNQ,bdDc->tlLmMb", Rs[-1], top[j],
+                      row1[j], I, row1[j].conj(), row2[j], I, row2[j].conj(), bot[j], optimize=True)
+        Rs.append(_norm(R))
+    Rs = Rs[::-1]
+    out = []
+    for sites, op in terms_here:
+        j = sites[0][1]
+        num = 0.0
+        for A, B in operator_schmidt(op):
+            X = _col4(Ls[j], top[j], row1[j], A, row1[j], row2[j], B, row2[j], bot[j])
+            num = num + np.vdot(Rs[j + 1].conj(), X)
+        X = _col4(Ls[j], top[j], row1[j], I, row1[j], row2[j], I, row2[j], bot[j])
+        den = np.vdot(Rs[j + 1].conj(), X)
+        out.append((sites, num / den))
+    return out
+
+
+def peps_energy_cached(ket, terms, m, p, q, seed):
+    """Returns (energy, per-term values in the order of ``terms``)."""
+    nrow, ncol = len(ket), len(ket[0])
+    d = ket[0][0].shape[4]
+    dtype = np.result_type(*[t for row in ket for t in row], np.float64)
+    top_envs, _ = boundary_pass(ket, ket, TOP, m, p, q, seed)
+    bot_envs, _ = boundary_pass(ket, ket, BOTTOM, m, p, q, seed)
+    triv = _trivial_env(ncol, dtype)
+
+    def top_of(i):   # boundary above row i (rows 0..i-1 absorbed)
+        return triv if i == 0 else top_envs[i - 1]
+
+    def bot_of(i):   # boundary below row i (rows nrow-1..i+1 absorbed)
+        return triv if i == nrow - 1 else bot_envs[nrow - 2 - i]
+
+    values = {}
+    for i in range(nrow):
+        here = [(k, t) for k, t in enumerate(terms)
+                if all(s[0] == i for s in t[0])]
+        if here:
+            res = _row_terms(top_of(i), ket[i], bot_of(i), [t for _, t in here], d, dtype)
+            for (k, _), (_, v) in zip(here, res):
+                values[k] = v
+    for i in range(nrow - 1):
+        here = [(k, t) for k, t in enumerate(terms)
+                if len(t[0]) == 2 and t[0][0][0] == i and t[0][1][0] == i + 1]
+        if here:
+            res = _pair_terms(top_of(i), ket[i], ket[i + 1], bot_of(i + 1),
+                              [t for _, t in here], d, dtype)
+            for (k, _), (_, v) in zip(here, res):
+                values[k] = v
+    per_term = np.array([values[k] for k in range(len(terms))])
+    return per_term.sum(), per_term
+
+
+def _value(log_abs, phase):
+    return phase * np.exp(log_abs)
+
+
+def peps_energy_uncached(ket, terms, m, p, q, seed):
+    """Eq. 5 term by term: each <psi|H_t|psi> is its own boundary contraction."""
+    ln, ph = peps_norm(ket, m, p, q, seed)
+    per_term = []
+    for sites, op in terms:
+        if len(sites) == 1:
+            parts = [((op,), sites)]
+        else:
+            parts = [((A, B), sites) for A, B in operator_schmidt(op)]
+        val = 0.0
+        for ops, ss in parts:
+            mod = [[t for t in row] for row in ket]
+            for o, (i, j) in zip(ops, ss):
+                mod[i][j] = np.einsum("Pp,udlrp->udlrP", o, ket[i][j])
+            l2, p2 = peps_norm(mod, m, p, q, seed, bra=ket)
+            # <ket|O ket> : bra = ket (conjugated), ket = modified
+            val = val + _value(l2 - ln, p2 / ph)
+        per_term.append(val)
+    per_term = np.array(per_term)
+    return per_term.sum(), per_term

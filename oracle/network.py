@@ -1,0 +1,85 @@
+"""The implicit operators on which einsumsvd runs (Sec. III-B, Alg. 3; Sec. IV-A).
+
+Zip-up step (two-layer, Fig. 5 / Alg. 3):  the carry V[a,x,X,b,h,H] from the
+previous column, the boundary tensor S[b,u,U,c] of this column, the ket site
+T[u,y,h,g,p] and the bra site B[U,Y,H,G,p] (used complex-conjugated) form
+
+    A[(a,x,X), (y,Y,c,g,G)] = sum_{b,h,H,u,U,p} V S T conj(B)
+
+Rows are the legs that stay with the finished boundary tensor, columns the
+legs that move on with the next carry.  The two layers are never merged into
+one double-layer tensor (Sec. III-B, two-layer BMPS).
+
+Pair network: two adjacent boundary tensors Bl[a,u,U,b], Br[b,v,V,c] and two
+horizontally adjacent ket/bra site pairs T1[u,x,1,h,p], T2[v,y,h,1,q]:
+
+    A[(a,x,X), (y,Y,c)] = sum Bl Br T1 conj(T1) T2 conj(T2)
+"""
+import numpy as np
+
+
+class ImplicitOperator:
+    """A linear operator known only through contractions (Alg. 4 needs A X and A^* Y)."""
+
+    def __init__(self, rows_shape, cols_shape, fwd, adj, explicit):
+        self.rows_shape = tuple(rows_shape)
+        self.cols_shape = tuple(cols_shape)
+        self.n_rows = int(np.prod(rows_shape))
+        self.n_cols = int(np.prod(cols_shape))
+        self._fwd, self._adj, self._explicit = fwd, adj, explicit
+
+    def apply(self, X):
+        k = X.shape[1]
+        return self._fwd(X.reshape(self.cols_shape + (k,))).reshape(self.n_rows, k)
+
+    def apply_adj(self, Y):
+        k = Y.shape[1]
+        return self._adj(Y.reshape(self.rows_shape + (k,))).reshape(self.n_cols, k)
+
+    def explicit(self):
+        return self._explicit().reshape(self.n_rows, self.n_cols)
+
+
+def zipup_operator(V, S, T, B):
+    a, x, X, b, h, H = V.shape
+    _, u, U, c = S.shape
+    _, y, _, g, _ = T.shape
+    _, Y, _, G, _ = B.shape
+    Bc = B.conj()
+
+    def fwd(Om):
+        return np.einsum("axXbhH,buUc,uyhgp,UYHGp,yYcgGj->axXj", V, S, T, Bc, Om, optimize=True)
+
+    def adj(P):
+        return np.einsum("axXbhH,buUc,uyhgp,UYHGp,axXj->yYcgGj",
+                         V.conj(), S.conj(), T.conj(), B, P, optimize=True)
+
+    def explicit():
+        return np.einsum("axXbhH,buUc,uyhgp,UYHGp->axXyYcgG", V, S, T, Bc, optimize=True)
+
+    return ImplicitOperator((a, x, X), (y, Y, c, g, G), fwd, adj, explicit)
+
+
+def pair_operator(Bl, Br, T1, T2, T1b=None, T2b=None):
+    T1b = T1 if T1b is None else T1b
+    T2b = T2 if T2b is None else T2b
+    a, u, U, b = Bl.shape
+    _, v, V, c = Br.shape
+    x, X, y, Y = T1.shape[1], T1b.shape[1], T2.shape[1], T2b.shape[1]
+    # drop the dim-1 outer horizontal legs
+    t1, t1b = T1[:, :, 0, :, :], T1b[:, :, 0, :, :].conj()
+    t2, t2b = T2[:, :, :, 0, :], T2b[:, :, :, 0, :].conj()
+    sub = "auUb,bvVc,uxhp,UXHp,vyhq,VYHq"
+
+    def fwd(Om):
+        return np.einsum(sub + ",yYcj->axXj", Bl, Br, t1, t1b, t2, t2b, Om, optimize=True)
+
+    def adj(P):
+        return np.einsum(sub + ",axXj->yYcj", Bl.conj(), Br.conj(), t1.conj(), t1b.conj(),
+                         t2.conj(), t2b.conj(), P, optimize=True)
+
+    def explicit():
+        return np.einsum(sub + "->axXyYc", Bl, Br, t1, t1b, t2, t2b, optimize=True)
+
+    return ImplicitOperator((a, x, X), (y, Y, c), fwd, adj, explicit)
+

@@ -1,0 +1,54 @@
+"""einsumsvd: the definition (explicit truncated SVD) and the method
+(randomized SVD on an implicit operator, Alg. 4).
+
+Sec. II-C defines einsumsvd as: contract a tensor network, matricize it by
+splitting its open legs into a left and a right group, compute a low-rank
+factorization (truncated SVD) and fold the factors back into two tensors
+joined by one new leg.  Sec. IV-A replaces the explicit SVD by a randomized
+SVD that only needs the products A @ X and A^* @ Y, which are evaluated as
+tensor contractions without ever forming A.
+"""
+import numpy as np
+
+
+def truncated_svd(A, m):
+    """Definition: full LAPACK SVD of the explicit matrix, first m' = min(m, rows,
+    cols) triplets, singular values non-increasing."""
+    U, s, Vh = np.linalg.svd(A, full_matrices=False)
+    mp = min(m, A.shape[0], A.shape[1])
+    return U[:, :mp], s[:mp], Vh[:mp]
+
+
+def sketch_width(m, p, n_rows, n_cols):
+    """k = min(m + p, rows, cols): target rank plus oversampling, capped by the
+    matrix shape (oversampling is not part of Alg. 4 itself, which sketches with
+    exactly the target rank; it follows Halko et al., cited in Sec. IV-A)."""
+    return min(m + p, n_rows, n_cols)
+
+
+def orthogonalize(Y):
+    """Orthonormal basis of range(Y) (Householder QR, reduced)."""
+    return np.linalg.qr(Y, mode="reduced")[0]
+
+
+def randomized_svd(apply, apply_adj, n_rows, n_cols, m, q, omega):
+    """Alg. 4 on an implicit operator A (n_rows x n_cols).
+
+    apply(X)      -> A @ X        for X of shape (n_cols, k)
+    apply_adj(Y)  -> A^* @ Y      for Y of shape (n_rows, k)
+    omega         -> the sketch, shape (n_cols, k)
+    q             -> number of power iterations (Alg. 4's iteration count)
+
+    Returns U (n_rows x m'), s (m'), Vh (m' x n_cols) with m' = min(m, k).
+    """
+    k = omega.shape[1]
+    assert omega.shape == (n_cols, k) and k <= min(n_rows, n_cols)
+    P = orthogonalize(apply(omega))
+    for _ in range(q):
+        Q = orthogonalize(apply_adj(P))
+        P = orthogonalize(apply(Q))
+    B = apply_adj(P).conj().T            # P^* A, shape (k, n_cols)
+    Ut, s, Vh = np.linalg.svd(B, full_matrices=False)
+    mp = min(m, k)
+    return P @ Ut[:, :mp], s[:mp], Vh[:mp]
+

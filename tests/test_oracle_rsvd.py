@@ -1,0 +1,170 @@
+"""Pins of the oracle's sketch generator and einsumsvd (definition and Alg. 4)."""
+import os
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import rsvd
+from oracle.network import pair_operator, zipup_operator
+from oracle.sketch import mix64, sketch
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def test_splitmix64_reference_vector():
+    vals = [int(l) for l in open(os.path.join(GOLDEN, "splitmix64_seed1234567.txt"))
+            if l.strip() and not l.startswith("#")]
+    phi = np.uint64(0x9E3779B97F4A7C15)
+    with np.errstate(over="ignore"):
+        got = [int(mix64(np.uint64(1234567) + np.uint64(i + 1) * phi)) for i in range(5)]
+    assert got == vals
+
+
+def test_sketch_range_and_moments():
+    om = sketch(7, 3, 5000, 40)
+    assert om.dtype == np.float64 and om.shape == (5000, 40)
+    assert om.min() >= -1.0 and om.max() < 1.0
+    # uniform on [-1, 1): mean 0, variance 1/3 (loose statistical bounds)
+    assert abs(om.mean()) < 0.01 and abs(om.var() - 1 / 3) < 0.01
+    # values lie on the 2^-52 grid, so x = (om + 1) * 2^52 is an integer < 2^53
+    x = (om + 1.0) * 2.0 ** 52
+    assert np.all(x == np.floor(x)) and x.max() < 2.0 ** 53
+
+
+def test_sketch_streams_differ_and_repeat():
+    a = sketch(1, 5, 10, 4)
+    assert np.array_equal(a, sketch(1, 5, 10, 4))
+    assert not np.array_equal(a, sketch(1, 6, 10, 4))
+    assert not np.array_equal(a, sketch(2, 5, 10, 4))
+    # prefix property: element i does not depend on the total size
+    b = sketch(1, 5, 20, 4)
+    assert np.array_equal(a, b[:10])
+
+
+def _rand(shape, rng, complex_):
+    x = rng.standard_normal(shape)
+    if complex_:
+        x = x + 1j * rng.standard_normal(shape)
+    return x
+
+
+def test_truncated_svd_eckart_young():
+    rng = np.random.default_rng(0)
+    A = rng.standard_normal((30, 20)) @ np.diag(0.7 ** np.arange(20)) @ rng.standard_normal((20, 25))
+    full = np.linalg.svd(A, compute_uv=False)
+    for m in (1, 5, 12):
+        U, s, Vh = rsvd.truncated_svd(A, m)
+        R = A - (U * s) @ Vh
+        assert np.isclose(np.linalg.norm(R) ** 2, np.sum(full[m:] ** 2), rtol=1e-10)
+        assert np.isclose(np.linalg.norm(R, 2), full[m], rtol=1e-10)
+        assert np.allclose(U.T @ U, np.eye(m), atol=1e-13)
+        assert np.allclose(Vh @ Vh.T, np.eye(m), atol=1e-13)
+        assert np.all(np.diff(s) <= 0)
+
+
+def _zip_inputs(rng, a, x, b, h, u, c, y, g, d, complex_):
+    V = _rand((a, x, x, b, h, h), rng, complex_)
+    S = _rand((b, u, u, c), rng, complex_)
+    T = _rand((u, y, h, g, d), rng, complex_)
+    B = _rand((u, y, h, g, d), rng, complex_)
+    return V, S, T, B
+
+
+@pytest.mark.parametrize("complex_", [False, True])
+def test_operator_adjoint_identity(complex_):
+    """<Y, A X> = <A^* Y, X>, and the implicit products equal the explicit matrix."""
+    rng = np.random.default_rng(1)
+    op = zipup_operator(*_zip_inputs(rng, 3, 2, 2, 2, 2, 3, 2, 2, 2, complex_))
+    X = _rand((op.n_cols, 5), rng, complex_)
+    Y = _rand((op.n_rows, 5), rng, complex_)
+    lhs = np.vdot(Y, op.apply(X))
+    rhs = np.vdot(op.apply_adj(Y), X)
+    assert np.isclose(lhs, rhs, rtol=1e-12)
+    A = op.explicit()
+    assert np.allclose(op.apply(X), A @ X, rtol=1e-12, atol=1e-12)
+    assert np.allclose(op.apply_adj(Y), A.conj().T @ Y, rtol=1e-12, atol=1e-12)
+
+
+def test_zipup_operator_by_loops():
+    """Brute-force sum over every index on a tiny case."""
+    rng = np.random.default_rng(2)
+    V, S, T, B = _zip_inputs(rng, 2, 2, 1, 2, 2, 2, 1, 2, 2, True)
+    op = zipup_operator(V, S, T, B)
+    A = op.explicit().reshape(op.rows_shape + op.cols_shape)
+    ref = np.zeros_like(A)
+    it = np.ndindex
+    for (a, x, X) in it(*op.rows_shape):
+        for (y, Y, c, g, G) in it(*op.cols_shape):
+            acc = 0
+            for (b, h, H, u, U, p) in it(V.shape[3], V.shape[4], V.shape[5], S.shape[1],
+                                         S.shape[2], T.shape[4]):
+                acc += V[a, x, X, b, h, H] * S[b, u, U, c] * T[u, y, h, g, p] * np.conj(B[U, Y, H, G, p])
+            ref[a, x, X, y, Y, c, g, G] = acc
+    assert np.allclose(A, ref, rtol=1e-13, atol=1e-14)
+
+
+@pytest.mark.parametrize("complex_", [False, True])
+def test_rsvd_exact_regime_equals_definition(complex_):
+    """k = min(rows, cols): the randomized SVD reproduces A and its spectrum."""
+    rng = np.random.default_rng(3)
+    op = zipup_operator(*_zip_inputs(rng, 2, 2, 2, 2, 2, 2, 2, 1, 2, complex_))
+    A = op.explicit()
+    kmax = min(op.n_rows, op.n_cols)
+    om = sketch(11, 1, op.n_cols, kmax)
+    U, s, Vh = rsvd.randomized_svd(op.apply, op.apply_adj, op.n_rows, op.n_cols, kmax, 1, om)
+    assert np.allclose((U * s) @ Vh, A, atol=1e-13 * np.abs(A).max() * 10)
+    s_ref = np.linalg.svd(A, compute_uv=False)
+    assert np.allclose(s, s_ref[:kmax], atol=1e-13 * s_ref[0])
+    assert np.allclose(U.conj().T @ U, np.eye(kmax), atol=1e-13)
+
+
+def test_rsvd_low_rank_recovered_exactly():
+    """rank(A) <= k: range(A Omega) = range(A), so the result is exact."""
+    rng = np.random.default_rng(4)
+    # carry with inner dims b*h*H = 1*2*2 = 4 limits the rank to 4
+    op = zipup_operator(*_zip_inputs(rng, 4, 3, 1, 2, 2, 3, 3, 2, 2, False))
+    A = op.explicit()
+    s_ref = np.linalg.svd(A, compute_uv=False)
+    assert s_ref[4] < 1e-13 * s_ref[0]
+    om = sketch(5, 9, op.n_cols, 6)
+    U, s, Vh = rsvd.randomized_svd(op.apply, op.apply_adj, op.n_rows, op.n_cols, 4, 0, om)
+    assert np.allclose((U * s) @ Vh, A, atol=1e-12 * s_ref[0])
+    assert np.allclose(s, s_ref[:4], rtol=1e-12)
+
+
+def test_rsvd_basis_invariance(monkeypatch):
+    """The output depends only on the ranges of the sketches: replacing the
+    orthonormal basis by a rotated one changes nothing but rounding."""
+    rng = np.random.default_rng(5)
+    op = zipup_operator(*_zip_inputs(rng, 3, 2, 3, 2, 2, 3, 2, 2, 2, True))
+    om = sketch(3, 2, op.n_cols, 10)
+    U0, s0, V0 = rsvd.randomized_svd(op.apply, op.apply_adj, op.n_rows, op.n_cols, 6, 2, om)
+    orig = rsvd.orthogonalize
+
+    def rotated(Y):
+        Q = orig(Y)
+        Z = np.linalg.qr(rng.standard_normal((Q.shape[1],) * 2)
+                         + 1j * rng.standard_normal((Q.shape[1],) * 2))[0]
+        return Q @ Z
+
+    monkeypatch.setattr(rsvd, "orthogonalize", rotated)
+    U1, s1, V1 = rsvd.randomized_svd(op.apply, op.apply_adj, op.n_rows, op.n_cols, 6, 2, om)
+    assert np.allclose(s0, s1, rtol=1e-11)
+    assert np.allclose((U0 * s0) @ V0, (U1 * s1) @ V1, atol=1e-11 * s0[0])
+
+
+def test_rsvd_near_optimal_on_pair_network():
+    """Halko-type bound: with oversampling and power iterations the error is
+    close to the optimal rank-m error (soft check, reported ratio <= 1.5)."""
+    Bl, Br, T1, T2 = synth.pair_instance(m=6, D=2, d=2, seed=0, instance=0)
+    op = pair_operator(Bl, Br, T1, T2)
+    A = op.explicit()
+    m, k = 6, 10
+    om = sketch(0, 1, op.n_cols, k)
+    U, s, Vh = rsvd.randomized_svd(op.apply, op.apply_adj, op.n_rows, op.n_cols, m, 2, om)
+    s_ref = np.linalg.svd(A, compute_uv=False)
+    opt = np.sqrt(np.sum(s_ref[m:] ** 2))
+    err = np.linalg.norm(A - (U * s) @ Vh)
+    assert opt <= err <= 1.5 * opt
+    assert np.all(s <= s_ref[:m] * (1 + 1e-12))  # Ritz values never exceed the true ones
