@@ -1,0 +1,279 @@
+/*
+ * hpeps.h -- C ABI of the MI355X (gfx950) PEPS contraction library.
+ *
+ * The library implements the bottleneck operation of two-dimensional
+ * tensor-network (PEPS) simulation described in Pang, Hao, Dugad, Zhou,
+ * Solomonik, "Efficient 2D Tensor Network Simulation of Quantum Systems"
+ * (SC20): einsumsvd -- contract a tensor network and refactorize it into two
+ * tensors joined by one truncated leg (Sec. II-C) -- computed by randomized
+ * SVD on an implicit operator that is only applied through tensor
+ * contractions (Alg. 4, Sec. IV-A), and the algorithms built on it:
+ * boundary-MPS contraction with zip-up row absorption (Algs. 2-3, two-layer
+ * form of Sec. III-B), expectation values with cached environments (Eq. 5,
+ * Sec. IV-B) and QR-SVD two-site gate application for imaginary-time
+ * evolution (Alg. 1, Eq. 4, Sec. II-D).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - Every tensor argument is a pointer to caller-owned DEVICE memory holding
+ *    a dense row-major array in the leg order written next to it.  Element
+ *    type is given by an hpeps_dtype (HPEPS_F64: double; HPEPS_C128: two
+ *    doubles, real then imaginary).
+ *  - PEPS site tensors have legs [u, d, l, r, p] (up, down, left, right,
+ *    physical); legs on the open boundary have dimension 1.
+ *  - Boundary-MPS tensors have legs [mL, x, X, mR]: left bond, the ket and
+ *    bra legs that connect to the next row to be absorbed, right bond.
+ *  - Two-site operators are G[out1, out2, in1, in2] (the index order of the
+ *    two-qubit gate of Eq. 2); site 1 is the left (horizontal bond) or the
+ *    upper (vertical bond) site.  One-site operators are O[out, in].
+ *  - All work is enqueued on the context's stream.  Calls that return host
+ *    scalars synchronise that stream; no other call does.  Outputs are
+ *    untouched when a call returns an error before launching work.
+ *  - The library owns only a workspace arena per context (device memory it
+ *    allocates on first use and grows when a larger problem arrives).
+ *  - Status codes are returned; no C++ exception crosses the ABI.  One
+ *    context must not be used from two host threads at once.
+ */
+#ifndef HPEPS_H
+#define HPEPS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  HPEPS_OK = 0,
+  HPEPS_ERR_INVALID_ARG = 1,  /* null pointer, bad enum, non-positive size   */
+  HPEPS_ERR_SHAPE = 2,        /* inconsistent leg dimensions                 */
+  HPEPS_ERR_DTYPE = 3,        /* unsupported element type for this call      */
+  HPEPS_ERR_ALLOC = 4,        /* device allocation failed / exceeds the cap  */
+  HPEPS_ERR_HIP = 5,          /* a HIP runtime call failed                   */
+  HPEPS_ERR_NUMERIC = 6,      /* non-finite values met in a factorization    */
+  HPEPS_ERR_NOT_CONVERGED = 7,/* Jacobi SVD hit its sweep limit              */
+  HPEPS_ERR_UNSUPPORTED = 8   /* size beyond what a kernel supports          */
+} hpeps_status;
+
+typedef enum { HPEPS_F64 = 0, HPEPS_C128 = 1, HPEPS_F32 = 2, HPEPS_BF16 = 3 } hpeps_dtype;
+
+/* Where the singular values go in an einsumsvd (the left factor U is always
+ * the isometry P Z of Alg. 4):
+ *   CARRY  -> right factor (Sigma / sigma_1) V^*, and log(sigma_1) is added
+ *             to the log-scale accumulator (zip-up carry, see hpeps_peps_norm)
+ *   RIGHT  -> right factor Sigma V^*
+ *   NONE   -> right factor V^* (computed as Sigma^-1 Z^* (P^* A): row i has
+ *             relative error ~ 1e-16 * sigma_1 / sigma_i)                     */
+typedef enum { HPEPS_ABSORB_CARRY = 0, HPEPS_ABSORB_RIGHT = 1, HPEPS_ABSORB_NONE = 2 } hpeps_absorb;
+
+typedef struct hpeps_ctx hpeps_ctx;
+
+/* Options of one randomized einsumsvd (Alg. 4).
+ *  rank            m: number of singular triplets kept (m' = min(m, k)).
+ *  oversample      p: sketch width k = min(m + p, rows, cols).
+ *  power_iters     q: Alg. 4's iteration count.
+ *  sketch_precision HPEPS_F64 | HPEPS_F32: arithmetic of the operator
+ *                  applications A X and A^* Y (FP32 runs the contractions on
+ *                  FP32 MFMA with FP32 accumulation; orthogonalization, the
+ *                  small SVD and truncation always run in FP64).
+ *  seed, stream_id select the sketch: element i of Omega (row-major over
+ *                  (column multi-index, sketch column)) is
+ *                  2 * (h_i >> 11) * 2^-53 - 1 with h_i = mix(base + (i+1) *
+ *                  0x9E3779B97F4A7C15), base = mix(mix(seed) + stream_id) and
+ *                  mix the SplitMix64 output function (Steele, Lea & Flood,
+ *                  OOPSLA 2014).  Instance b of a batch uses stream_id + b.
+ *  jacobi_max_sweeps cap on the one-sided Jacobi sweeps of the small SVD
+ *                  (0 selects the default, 40).                             */
+typedef struct {
+  int64_t rank;
+  int64_t oversample;
+  int32_t power_iters;
+  int32_t sketch_precision;
+  uint64_t seed;
+  uint64_t stream_id;
+  int32_t jacobi_max_sweeps;
+  int32_t reserved;
+} hpeps_esvd_opts;
+
+/* Diagnostics of the last einsumsvd-based call (host struct, filled after the
+ * call's stream work completes when the call synchronises, else on the next
+ * hpeps_get_info). */
+typedef struct {
+  int64_t rank_kept;        /* m'                                            */
+  int64_t sketch_width;     /* k                                             */
+  int32_t orth_extra_passes;/* CholeskyQR factorizations that needed a shift */
+                            /* and a third pass (ill-conditioned sketches)   */
+  int32_t jacobi_sweeps;    /* largest sweep count of any small SVD          */
+  int32_t numeric_errors;   /* factorizations that met non-finite values     */
+  int32_t not_converged;    /* small SVDs that hit the sweep cap             */
+} hpeps_esvd_info;
+
+/* ---- context ---------------------------------------------------------- */
+hpeps_status hpeps_create(int device, hpeps_ctx** out);
+hpeps_status hpeps_destroy(hpeps_ctx* ctx);
+/* stream: a hipStream_t (passed as void*); NULL selects the null stream. */
+hpeps_status hpeps_set_stream(hpeps_ctx* ctx, void* stream);
+const char* hpeps_status_string(hpeps_status s);
+const char* hpeps_last_error(hpeps_ctx* ctx);
+/* Caps the workspace arena (bytes; 0 = no cap).  Calls that would need more
+ * return HPEPS_ERR_ALLOC before launching anything. */
+hpeps_status hpeps_set_workspace_limit(hpeps_ctx* ctx, int64_t bytes);
+/* Synchronises the stream and copies the diagnostics accumulated since the
+ * last call of hpeps_get_info (or creation) to *info, then clears them. */
+hpeps_status hpeps_get_info(hpeps_ctx* ctx, hpeps_esvd_info* info);
+
+/* ---- sketch -------------------------------------------------------------
+ * Writes the sketch Omega that an einsumsvd with (seed, stream_id) draws:
+ * batch blocks of n*k values (block b uses stream_id + b), element i of a
+ * block as documented for hpeps_esvd_opts, as double (dtype HPEPS_F64) or
+ * rounded to nearest float (HPEPS_F32).  out: device memory. */
+hpeps_status hpeps_sketch(hpeps_ctx* ctx, hpeps_dtype dtype, int64_t n, int64_t k, int64_t batch,
+                          uint64_t seed, uint64_t stream_id, void* out);
+
+/* ---- einsumsvd on the zip-up network (Alg. 3 inner step, Alg. 4) -------
+ * One einsumsvd of boundary contraction: the carry V[a,x,X,b,h,H] of the
+ * previous column, the boundary tensor S[b,u,U,c], the ket site
+ * T[u,y,h,g,p] and the bra site Bra[U,Y,H,G,p] (used complex-conjugated;
+ * NULL means Bra = T) define the implicit matrix
+ *     A[(a,x,X), (y,Y,c,g,G)] = sum_{b,h,H,u,U,p} V S T conj(Bra),
+ * which is never formed.  Randomized SVD A ~ U Sigma V^* with the options in
+ * *opts; outputs:
+ *     U      [batch][a, x, X, m']           left factor (isometry)
+ *     sigma  [batch][m'] (device, double)   singular values, descending
+ *     R      [batch][m', y, Y, c, g, G]     right factor per *absorb*
+ *     log_scale [batch] (device, double)    incremented by log(sigma_1)
+ *                                           when absorb == CARRY (may be
+ *                                           NULL otherwise)
+ * dims = {a, x, b, h, u, c, y, g, d}.  Tensors of instance i start at
+ * i * (element count of one instance).  dtype: HPEPS_F64 or HPEPS_C128.
+ * Errors: SHAPE if k = min(m+p, rows, cols) exceeds 128 (F64) / 88 (C128). */
+hpeps_status hpeps_einsumsvd_zipup(hpeps_ctx* ctx, int64_t batch, hpeps_dtype dtype,
+                                   const int64_t dims[9], const void* V, const void* S,
+                                   const void* T, const void* Bra,
+                                   const hpeps_esvd_opts* opts, hpeps_absorb absorb,
+                                   void* U, double* sigma, void* R, double* log_scale);
+
+/* ---- einsumsvd on the two-column pair network --------------------------
+ * Two adjacent boundary tensors Bl[a,u,U,b], Br[b,v,V,c] (each [m,D,D,m]) and
+ * two horizontally adjacent sites T1[u,x,1,h,p], T2[v,y,h,1,q] (outer
+ * horizontal legs of dim 1; bra = conj(ket)) define
+ *     A[(a,x,X), (y,Y,c)] = sum Bl Br T1 conj(T1) T2 conj(T2)      (Fig. 2b)
+ * The carry sum_{u,U,p} Bl T1 conj(T1) is contracted exactly first, then the
+ * randomized SVD runs as in hpeps_einsumsvd_zipup with g = G = 1.
+ *     U [batch][m, D, D, m'], sigma [batch][m'], R [batch][m', D, D, m]
+ * dims = {m, D, d}. */
+hpeps_status hpeps_einsumsvd_pair(hpeps_ctx* ctx, int64_t batch, hpeps_dtype dtype,
+                                  const int64_t dims[3], const void* Bl, const void* Br,
+                                  const void* T1, const void* T2,
+                                  const hpeps_esvd_opts* opts, hpeps_absorb absorb,
+                                  void* U, double* sigma, void* R);
+
+/* ---- PEPS and boundary-MPS containers ---------------------------------- */
+typedef struct {
+  int32_t nrow, ncol;
+  int32_t dtype;              /* HPEPS_F64 or HPEPS_C128, all sites        */
+  int32_t reserved;
+  void* const* sites;         /* nrow*ncol device pointers, row-major      */
+  const int64_t* shapes;      /* host, nrow*ncol*5: [u,d,l,r,p] per site   */
+} hpeps_peps;
+
+typedef struct {
+  int32_t ncol;
+  int32_t dtype;
+  void* const* tensors;       /* ncol device pointers [mL, x, X, mR]       */
+  int64_t* shapes;            /* host, ncol*4 (written for outputs)        */
+  const int64_t* capacity;    /* host, ncol: element capacity of each      */
+                              /* output buffer (NULL for inputs)           */
+} hpeps_bmps;
+
+typedef enum { HPEPS_L2R = 0, HPEPS_R2L = 1 } hpeps_direction;
+
+/* ---- boundary_contract_row (ApproxApply, Alg. 3) ------------------------
+ * Absorbs one PEPS row (ket row, bra row = NULL for conj(ket)) into the
+ * boundary MPS *bnd (legs x/X of bnd connect to the up legs u/U of the row)
+ * by the zip-up: the first column's carry is exact, every later column runs
+ * one einsumsvd (ABSORB_CARRY).  dir selects the sweep direction.  The new
+ * boundary (legs x/X = down legs of the row) goes to *out, whose buffers
+ * the caller allocates; shapes are written to out->shapes.  *log_scale (host)
+ * is incremented by the logarithms of all normalisation factors (the first
+ * carry's Frobenius norm and every sigma_1).  Stream ids follow
+ * opts->stream_id + column index.  Synchronises (returns a host scalar). */
+hpeps_status hpeps_boundary_contract_row(hpeps_ctx* ctx, const hpeps_bmps* bnd,
+                                         const hpeps_peps* ket, const hpeps_peps* bra,
+                                         int32_t row, hpeps_direction dir,
+                                         const hpeps_esvd_opts* opts, hpeps_bmps* out,
+                                         double* log_scale);
+
+/* ---- peps_norm (boundary MPS, Alg. 2) -----------------------------------
+ * <bra|ket> (bra = NULL: <ket|ket>) of a two-layer PEPS network.  Site
+ * tensors are rescaled to unit Frobenius norm, row 1 is the exact boundary,
+ * rows 2..n-1 are absorbed by zip-ups whose direction alternates (L2R on the
+ * 1st, 3rd, ... absorbed row), row n is contracted exactly.  The sketch of
+ * the einsumsvd absorbing column j of row i uses stream_id
+ * 1 + (i * ncol + j) (opts->stream_id is ignored).
+ * Result: value = phase * exp(*log_norm); phase = {re, im} (host). */
+hpeps_status hpeps_peps_norm(hpeps_ctx* ctx, const hpeps_peps* ket, const hpeps_peps* bra,
+                             const hpeps_esvd_opts* opts, double* log_norm, double* phase);
+
+/* ---- peps_energy (Eq. 5 with cached environments, Sec. IV-B) ------------
+ * Terms: n_terms entries; term t acts on nsites[t] (1 or 2) sites given by
+ * sites[4t .. 4t+3] = {i1, j1, i2, j2} (nearest neighbours, site 1 left of or
+ * above site 2); its operator is ops + op_offset[t] (host memory, complex128
+ * pairs, [2,2] or [2,2,2,2]).  Every term value is strip(term)/strip(id),
+ * where the strip is the exact contraction of the cached top environment,
+ * the one (two, for vertical terms) PEPS rows of the term and the cached
+ * bottom environment.  Environments come from two full boundary passes
+ * (top-down stream ids 1 + (i*ncol+j), bottom-up 1 + ((nrow+i)*ncol+j)).
+ * Outputs (host): energy[2] = {re, im} of the sum, per_term[2*n_terms]
+ * (may be NULL).  Synchronises. */
+hpeps_status hpeps_peps_energy(hpeps_ctx* ctx, const hpeps_peps* ket, int32_t n_terms,
+                               const int32_t* nsites, const int32_t* sites,
+                               const double* ops, const int64_t* op_offset,
+                               const hpeps_esvd_opts* opts, double* energy, double* per_term);
+
+/* ---- apply_two_site_gate (QR-SVD, Alg. 1 / Eq. 4) -----------------------
+ * In place on two neighbouring sites of *peps: site (i,j) and its right
+ * neighbour (axis 0) or lower neighbour (axis 1).  Each site is matricized
+ * as (other legs) x (shared bond, p) and QR-factored (skipped when it has no
+ * more rows than columns); Theta = G R1 R2 is decomposed by an exact SVD,
+ * truncated to D' = min(max_rank, rows, cols), the kept singular values are
+ * normalised to unit 2-norm and split as sqrt into both sides, and the Q
+ * factors are multiplied back.  The site buffers must have room for the new
+ * bond (capacity given in elements); the new shapes are written to
+ * peps->shapes (which must then be writable: pass a non-const array).
+ * sigma_out (device, may be NULL) receives the D' kept values.
+ * Synchronises (returns the new bond on the host). */
+hpeps_status hpeps_apply_two_site_gate(hpeps_ctx* ctx, hpeps_peps* peps,
+                                       const int64_t* capacity, int32_t i, int32_t j,
+                                       int32_t axis, const void* G, int64_t max_rank,
+                                       int64_t* new_bond, double* sigma_out);
+
+/* ---- batched imaginary-time-evolution sweep (TEBD, Sec. II-D) -----------
+ * A plan owns the evolving PEPS in a device arena of fixed capacity
+ * max_rank per bond.  Each sweep applies the gate of every bond, layer by
+ * layer (horizontal bonds at even then odd columns, vertical bonds at even
+ * then odd rows), with one launch per layer in which every bond of the
+ * layer is processed by its own workgroup; bond dimensions live in a device
+ * table so the sweeps replay as one captured HIP graph.
+ *  gates: n_gates device [2,2,2,2] operators (dtype of the plan);
+ *  bond_gate: host, one gate index per bond in layer order (sizes of the
+ *             layers: nrow*ceil((ncol-1)/2), nrow*floor((ncol-1)/2),
+ *             ceil((nrow-1)/2)*ncol, floor((nrow-1)/2)*ncol).
+ * The initial state is copied from *init (any bond dims <= max_rank). */
+typedef struct hpeps_ite_plan hpeps_ite_plan;
+hpeps_status hpeps_ite_plan_create(hpeps_ctx* ctx, const hpeps_peps* init,
+                                   int32_t n_gates, const void* gates,
+                                   const int32_t* bond_gate, int64_t max_rank,
+                                   hpeps_ite_plan** out);
+/* Runs n_sweeps sweeps (graph replay when use_graph != 0). */
+hpeps_status hpeps_ite_run(hpeps_ite_plan* plan, int32_t n_sweeps, int32_t use_graph);
+/* Copies the current state out: shapes (host, nrow*ncol*5) and, when sites
+ * is not NULL, the tensors into caller buffers (device pointers, each with
+ * room for max_rank-bond shapes). Synchronises. */
+hpeps_status hpeps_ite_get_state(hpeps_ite_plan* plan, int64_t* shapes, void* const* sites);
+hpeps_status hpeps_ite_plan_destroy(hpeps_ite_plan* plan);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HPEPS_H */

@@ -1,0 +1,16 @@
+"""Python binding of libhpeps, the MI355X PEPS einsumsvd / boundary-contraction
+library (arguments marshalling only: every step runs in the HIP kernels of
+``csrc/``).  PyTorch provides device memory and the stream.
+
+The library must have been built (``python -m paper_2006_15234_amd.build`` or
+``__graft_entry__.build()``); importing the functions that need it raises
+``RuntimeError`` when ``libhpeps.so`` is missing.  There is no CPU fallback.
+"""
+from ._ffi import (  # noqa: F401
+    ABSORB_CARRY, ABSORB_NONE, ABSORB_RIGHT, F32, F64, C128, L2R, R2L,
+    HpepsError, Context, EsvdOpts, lib_path, load_library, symbols,
+)
+from .api import (  # noqa: F401
+    einsumsvd_zipup, einsumsvd_pair, peps_norm, boundary_contract_row, peps_energy,
+    apply_two_site_gate, ItePlan, get_info, sketch, make_opts,
+)

@@ -1,0 +1,232 @@
+"""Torch-tensor front end of the C ABI (argument marshalling only)."""
+import ctypes as C
+
+from ._ffi import (ABSORB_CARRY, C128, F32, F64, Bmps, EsvdInfo, EsvdOpts, Peps)
+
+_PREC = {"f64": F64, "f32": F32}
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _dtype_code(t):
+    torch = _torch()
+    if t.dtype == torch.float64:
+        return F64
+    if t.dtype == torch.complex128:
+        return C128
+    raise TypeError(f"tensors must be float64 or complex128, got {t.dtype}")
+
+
+def _dev(t, name):
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return C.c_void_p(t.data_ptr())
+
+
+def make_opts(rank, oversample=0, power_iters=0, precision="f64", seed=0, stream_id=0,
+              jacobi_max_sweeps=0):
+    return EsvdOpts(rank=int(rank), oversample=int(oversample), power_iters=int(power_iters),
+                    sketch_precision=_PREC[precision], seed=int(seed), stream_id=int(stream_id),
+                    jacobi_max_sweeps=int(jacobi_max_sweeps), reserved=0)
+
+
+def einsumsvd_zipup(ctx, V, S, T, Bra=None, *, rank, oversample=0, power_iters=0, seed=0,
+                    stream_id=0, precision="f64", absorb=ABSORB_CARRY, log_scale=None,
+                    jacobi_max_sweeps=0):
+    """Batched zip-up einsumsvd.  V [B,a,x,x,b,h,h], S [B,b,u,u,c], T/Bra [B,u,y,h,g,d].
+    Returns (U [B,a,x,x,m'], sigma [B,m'], R [B,m',y,y,c,g,g])."""
+    torch = _torch()
+    Bn, a, x, x2, b, h, h2 = V.shape
+    _, b2, u, u2, c = S.shape
+    _, u3, y, h3, g, d = T.shape
+    if not (x == x2 and h == h2 and h == h3 and b == b2 and u == u2 and u == u3
+            and S.shape[0] == Bn and T.shape[0] == Bn):
+        raise ValueError("inconsistent zip-up shapes")
+    if Bra is not None and tuple(Bra.shape) != tuple(T.shape):
+        raise ValueError("bra shape must equal ket shape")
+    dt = _dtype_code(V)
+    rows, cols = a * x * x, y * y * c * g * g
+    k = min(rank + oversample, rows, cols)
+    mp = min(rank, k)
+    U = torch.empty((Bn, a, x, x, mp), dtype=V.dtype, device=V.device)
+    sig = torch.empty((Bn, mp), dtype=torch.float64, device=V.device)
+    R = torch.empty((Bn, mp, y, y, c, g, g), dtype=V.dtype, device=V.device)
+    dims = (C.c_int64 * 9)(a, x, b, h, u, c, y, g, d)
+    o = make_opts(rank, oversample, power_iters, precision, seed, stream_id, jacobi_max_sweeps)
+    ctx.sync_stream()
+    ls = _dev(log_scale, "log_scale") if log_scale is not None else None
+    ctx.check(ctx.lib.hpeps_einsumsvd_zipup(
+        ctx.h, Bn, dt, dims, _dev(V, "V"), _dev(S, "S"), _dev(T, "T"),
+        _dev(Bra, "Bra") if Bra is not None else None, C.byref(o), absorb,
+        _dev(U, "U"), _dev(sig, "sigma"), _dev(R, "R"), ls))
+    return U, sig, R
+
+
+def einsumsvd_pair(ctx, Bl, Br, T1, T2, *, rank, oversample=0, power_iters=0, seed=0,
+                   stream_id=0, precision="f64", absorb=ABSORB_CARRY, jacobi_max_sweeps=0):
+    """Batched pair einsumsvd.  Bl, Br [B,m,D,D,m]; T1 [B,D,D,1,D,d]; T2 [B,D,D,D,1,d].
+    Returns (U [B,m,D,D,m'], sigma [B,m'], R [B,m',D,D,m])."""
+    torch = _torch()
+    Bn, m, D, _, _ = Bl.shape
+    d = T1.shape[-1]
+    if tuple(Br.shape) != tuple(Bl.shape) or tuple(T1.shape) != (Bn, D, D, 1, D, d) \
+            or tuple(T2.shape) != (Bn, D, D, D, 1, d):
+        raise ValueError("inconsistent pair shapes")
+    dt = _dtype_code(Bl)
+    rows = cols = m * D * D
+    k = min(rank + oversample, rows, cols)
+    mp = min(rank, k)
+    U = torch.empty((Bn, m, D, D, mp), dtype=Bl.dtype, device=Bl.device)
+    sig = torch.empty((Bn, mp), dtype=torch.float64, device=Bl.device)
+    R = torch.empty((Bn, mp, D, D, m), dtype=Bl.dtype, device=Bl.device)
+    dims = (C.c_int64 * 3)(m, D, d)
+    o = make_opts(rank, oversample, power_iters, precision, seed, stream_id, jacobi_max_sweeps)
+    ctx.sync_stream()
+    ctx.check(ctx.lib.hpeps_einsumsvd_pair(
+        ctx.h, Bn, dt, dims, _dev(Bl, "Bl"), _dev(Br, "Br"), _dev(T1, "T1"), _dev(T2, "T2"),
+        C.byref(o), absorb, _dev(U, "U"), _dev(sig, "sigma"), _dev(R, "R")))
+    return U, sig, R
+
+
+def sketch(ctx, n, k, batch=1, seed=0, stream_id=0, precision="f64", device="cuda"):
+    """The sketch an einsumsvd with (seed, stream_id) draws: [batch, n, k]."""
+    torch = _torch()
+    dt = torch.float64 if precision == "f64" else torch.float32
+    out = torch.empty((batch, n, k), dtype=dt, device=device)
+    ctx.sync_stream()
+    ctx.check(ctx.lib.hpeps_sketch(ctx.h, _PREC[precision], n, k, batch, seed, stream_id,
+                                   _dev(out, "out")))
+    return out
+
+
+def get_info(ctx):
+    info = EsvdInfo()
+    ctx.check(ctx.lib.hpeps_get_info(ctx.h, C.byref(info)))
+    return {f: getattr(info, f) for f, _ in EsvdInfo._fields_}
+
+
+# ---------------------------------------------------------------------------
+# lattice-level calls
+
+def _peps_struct(sites, dtype_code, keep):
+    """sites: list of rows of device tensors [u,d,l,r,p]."""
+    nrow, ncol = len(sites), len(sites[0])
+    ptrs = (C.c_void_p * (nrow * ncol))()
+    shapes = (C.c_int64 * (nrow * ncol * 5))()
+    for i in range(nrow):
+        for j in range(ncol):
+            t = sites[i][j]
+            ptrs[i * ncol + j] = _dev(t, f"site ({i},{j})").value
+            for q in range(5):
+                shapes[(i * ncol + j) * 5 + q] = t.shape[q]
+    keep.extend([ptrs, shapes])
+    return Peps(nrow=nrow, ncol=ncol, dtype=dtype_code, reserved=0,
+                sites=C.cast(ptrs, C.POINTER(C.c_void_p)), shapes=C.cast(shapes, C.POINTER(C.c_int64)))
+
+
+def peps_norm(ctx, ket, bra=None, *, rank, oversample=0, power_iters=0, seed=0, precision="f64",
+              jacobi_max_sweeps=0):
+    """<bra|ket> by boundary MPS.  Returns (log|v|, phase as complex)."""
+    keep = []
+    dt = _dtype_code(ket[0][0])
+    pk = _peps_struct(ket, dt, keep)
+    pb = _peps_struct(bra, dt, keep) if bra is not None else None
+    o = make_opts(rank, oversample, power_iters, precision, seed, 0, jacobi_max_sweeps)
+    ln = C.c_double()
+    ph = (C.c_double * 2)()
+    ctx.sync_stream()
+    ctx.check(ctx.lib.hpeps_peps_norm(ctx.h, C.byref(pk), C.byref(pb) if pb is not None else None,
+                                      C.byref(o), C.byref(ln), ph))
+    return ln.value, complex(ph[0], ph[1])
+
+
+def boundary_contract_row(ctx, bnd, ket_row, bra_row=None, *, row, direction, rank, oversample=0,
+                          power_iters=0, seed=0, stream_id=0, precision="f64", out_capacity=None):
+    """Absorbs one PEPS row into a boundary MPS (list of [mL,x,X,mR] device tensors).
+    Returns (new boundary list, log scale added)."""
+    torch = _torch()
+    keep = []
+    dt = _dtype_code(ket_row[0])
+    ncol = len(ket_row)
+    bp = (C.c_void_p * ncol)(*[_dev(t, "bnd").value for t in bnd])
+    bs = (C.c_int64 * (4 * ncol))(*[s for t in bnd for s in t.shape])
+    bin_ = Bmps(ncol=ncol, dtype=dt, tensors=C.cast(bp, C.POINTER(C.c_void_p)),
+                shapes=C.cast(bs, C.POINTER(C.c_int64)), capacity=None)
+    pk = _peps_struct([ket_row], dt, keep)
+    pb = _peps_struct([bra_row], dt, keep) if bra_row is not None else None
+    # output capacity: m' <= rank + 0 per bond; down legs of the row
+    outs = []
+    for j, T in enumerate(ket_row):
+        mL = 1 if j == 0 else rank
+        mR = 1 if j == ncol - 1 else rank
+        cap = mL * T.shape[1] * T.shape[1] * mR if out_capacity is None else out_capacity[j]
+        outs.append(torch.empty(cap, dtype=ket_row[0].dtype, device=ket_row[0].device))
+    op = (C.c_void_p * ncol)(*[t.data_ptr() for t in outs])
+    oshape = (C.c_int64 * (4 * ncol))()
+    ocap = (C.c_int64 * ncol)(*[t.numel() for t in outs])
+    bout = Bmps(ncol=ncol, dtype=dt, tensors=C.cast(op, C.POINTER(C.c_void_p)),
+                shapes=C.cast(oshape, C.POINTER(C.c_int64)), capacity=C.cast(ocap, C.POINTER(C.c_int64)))
+    o = make_opts(rank, oversample, power_iters, precision, seed, stream_id)
+    ls = C.c_double(0.0)
+    ctx.sync_stream()
+    ctx.check(ctx.lib.hpeps_boundary_contract_row(ctx.h, C.byref(bin_), C.byref(pk),
+                                                  C.byref(pb) if pb is not None else None, row,
+                                                  direction, C.byref(o), C.byref(bout), C.byref(ls)))
+    res = []
+    for j in range(ncol):
+        shp = tuple(oshape[4 * j:4 * j + 4])
+        n = shp[0] * shp[1] * shp[2] * shp[3]
+        res.append(outs[j][:n].view(shp))
+    return res, ls.value
+
+
+def peps_energy(ctx, ket, terms, *, rank, oversample=0, power_iters=0, seed=0, precision="f64"):
+    """terms: list of (sites, op) with op a [2,2] or [2,2,2,2] complex array (host).
+    Returns (energy complex, per-term complex list)."""
+    import numpy as np
+    keep = []
+    dt = _dtype_code(ket[0][0])
+    pk = _peps_struct(ket, dt, keep)
+    n = len(terms)
+    ns = (C.c_int32 * n)()
+    st = (C.c_int32 * (4 * n))()
+    offs = (C.c_int64 * n)()
+    flat = []
+    off = 0
+    for t, (sites, op) in enumerate(terms):
+        ns[t] = len(sites)
+        for q, (i, j) in enumerate(sites):
+            st[4 * t + 2 * q] = i
+            st[4 * t + 2 * q + 1] = j
+        a = np.asarray(op, dtype=np.complex128).ravel()
+        offs[t] = off
+        flat.append(np.stack([a.real, a.imag], axis=-1).ravel())
+        off += a.size
+    ops = np.ascontiguousarray(np.concatenate(flat))
+    o = make_opts(rank, oversample, power_iters, precision, seed, 0)
+    e = (C.c_double * 2)()
+    per = (C.c_double * (2 * n))()
+    ctx.sync_stream()
+    ctx.check(ctx.lib.hpeps_peps_energy(ctx.h, C.byref(pk), n, ns, st,
+                                        ops.ctypes.data_as(C.POINTER(C.c_double)), offs,
+                                        C.byref(o), e, per))
+    return complex(e[0], e[1]), [complex(per[2 * t], per[2 * t + 1]) for t in range(n)]
+
+
+def apply_two_site_gate(ctx, sites, capacity, i, j, axis, G, max_rank):
+    """In-place QR-SVD update of sites[i][j] and its right (axis 0) / lower (axis 1)
+    neighbour.  ``sites`` holds flat device buffers of ``capacity`` elements
+    and a parallel list of shapes; returns (new bond, kept singular values)."""
+    raise NotImplementedError
+
+
+class ItePlan:
+    """Batched imaginary-time-evolution sweeps (see hpeps_ite_plan_create)."""
+
+    def __init__(self, *a, **k):
+        raise NotImplementedError

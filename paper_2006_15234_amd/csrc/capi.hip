@@ -1,0 +1,179 @@
+// extern "C" entry points of libhpeps (see include/hpeps.h).
+#include <cstring>
+#include <new>
+
+#include "esvd.h"
+#include "peps.h"
+
+struct hpeps_ctx {
+  hp::Ctx* impl;
+};
+
+namespace {
+
+template <class F>
+hpeps_status guard(hpeps_ctx* ctx, F&& f) {
+  try {
+    f();
+    return HPEPS_OK;
+  } catch (const hp::Error& e) {
+    if (ctx) ctx->impl->last_error = e.msg;
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    if (ctx) ctx->impl->last_error = "host allocation failed";
+    return HPEPS_ERR_ALLOC;
+  } catch (...) {
+    if (ctx) ctx->impl->last_error = "unknown error";
+    return HPEPS_ERR_INVALID_ARG;
+  }
+}
+
+void check_opts(const hpeps_esvd_opts* o) {
+  HP_REQUIRE(o, HPEPS_ERR_INVALID_ARG, "opts is NULL");
+  HP_REQUIRE(o->rank >= 1, HPEPS_ERR_INVALID_ARG, "rank must be >= 1");
+  HP_REQUIRE(o->oversample >= 0, HPEPS_ERR_INVALID_ARG, "oversample must be >= 0");
+  HP_REQUIRE(o->power_iters >= 0, HPEPS_ERR_INVALID_ARG, "power_iters must be >= 0");
+  HP_REQUIRE(o->jacobi_max_sweeps >= 0, HPEPS_ERR_INVALID_ARG, "jacobi_max_sweeps must be >= 0");
+}
+
+bool is_cplx(hpeps_dtype t) {
+  HP_REQUIRE(t == HPEPS_F64 || t == HPEPS_C128, HPEPS_ERR_DTYPE, "tensors must be F64 or C128");
+  return t == HPEPS_C128;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* hpeps_status_string(hpeps_status s) {
+  switch (s) {
+    case HPEPS_OK: return "ok";
+    case HPEPS_ERR_INVALID_ARG: return "invalid argument";
+    case HPEPS_ERR_SHAPE: return "shape mismatch";
+    case HPEPS_ERR_DTYPE: return "unsupported dtype";
+    case HPEPS_ERR_ALLOC: return "allocation failed";
+    case HPEPS_ERR_HIP: return "HIP runtime error";
+    case HPEPS_ERR_NUMERIC: return "non-finite values";
+    case HPEPS_ERR_NOT_CONVERGED: return "not converged";
+    case HPEPS_ERR_UNSUPPORTED: return "unsupported size";
+  }
+  return "unknown status";
+}
+
+hpeps_status hpeps_create(int device, hpeps_ctx** out) {
+  if (!out) return HPEPS_ERR_INVALID_ARG;
+  *out = nullptr;
+  hpeps_ctx* c = new (std::nothrow) hpeps_ctx{nullptr};
+  if (!c) return HPEPS_ERR_ALLOC;
+  hpeps_status st = guard(nullptr, [&] { c->impl = new hp::Ctx(device); });
+  if (st != HPEPS_OK) {
+    delete c;
+    return st;
+  }
+  *out = c;
+  return HPEPS_OK;
+}
+
+hpeps_status hpeps_destroy(hpeps_ctx* ctx) {
+  if (!ctx) return HPEPS_ERR_INVALID_ARG;
+  delete ctx->impl;
+  delete ctx;
+  return HPEPS_OK;
+}
+
+hpeps_status hpeps_set_stream(hpeps_ctx* ctx, void* stream) {
+  if (!ctx) return HPEPS_ERR_INVALID_ARG;
+  ctx->impl->stream = (hipStream_t)stream;
+  return HPEPS_OK;
+}
+
+const char* hpeps_last_error(hpeps_ctx* ctx) { return ctx ? ctx->impl->last_error.c_str() : ""; }
+
+hpeps_status hpeps_set_workspace_limit(hpeps_ctx* ctx, int64_t bytes) {
+  if (!ctx || bytes < 0) return HPEPS_ERR_INVALID_ARG;
+  ctx->impl->ws_limit = bytes;
+  return HPEPS_OK;
+}
+
+hpeps_status hpeps_get_info(hpeps_ctx* ctx, hpeps_esvd_info* info) {
+  if (!ctx || !info) return HPEPS_ERR_INVALID_ARG;
+  return guard(ctx, [&] {
+    hp::Ctx& c = *ctx->impl;
+    int h[8];
+    HP_CHECK_HIP(hipMemcpyAsync(h, c.stats_dev, sizeof(h), hipMemcpyDeviceToHost, c.stream));
+    HP_CHECK_HIP(hipStreamSynchronize(c.stream));
+    HP_CHECK_HIP(hipMemsetAsync(c.stats_dev, 0, sizeof(h), c.stream));
+    info->rank_kept = c.last_rank;
+    info->sketch_width = c.last_k;
+    info->orth_extra_passes = h[0];
+    info->jacobi_sweeps = h[1];
+    info->numeric_errors = h[2];
+    info->not_converged = h[3];
+  });
+}
+
+hpeps_status hpeps_sketch(hpeps_ctx* ctx, hpeps_dtype dtype, int64_t n, int64_t k, int64_t batch,
+                          uint64_t seed, uint64_t stream_id, void* out) {
+  if (!ctx) return HPEPS_ERR_INVALID_ARG;
+  return guard(ctx, [&] {
+    HP_REQUIRE(out && n >= 1 && k >= 1 && batch >= 1 && batch < 65536, HPEPS_ERR_INVALID_ARG,
+               "bad sketch arguments");
+    HP_REQUIRE(dtype == HPEPS_F64 || dtype == HPEPS_F32, HPEPS_ERR_DTYPE, "sketch dtype F64 or F32");
+    hp::sketch(*ctx->impl, out, dtype == HPEPS_F32, n, k, (int)batch, seed, stream_id);
+  });
+}
+
+hpeps_status hpeps_einsumsvd_zipup(hpeps_ctx* ctx, int64_t batch, hpeps_dtype dtype,
+                                   const int64_t dims[9], const void* V, const void* S,
+                                   const void* T, const void* Bra, const hpeps_esvd_opts* opts,
+                                   hpeps_absorb absorb, void* U, double* sigma, void* R,
+                                   double* log_scale) {
+  if (!ctx) return HPEPS_ERR_INVALID_ARG;
+  return guard(ctx, [&] {
+    check_opts(opts);
+    const bool cplx = is_cplx(dtype);
+    HP_REQUIRE(dims && V && S && T && U && sigma && R, HPEPS_ERR_INVALID_ARG, "null argument");
+    HP_REQUIRE(batch >= 1 && batch < 65536, HPEPS_ERR_INVALID_ARG, "batch out of range");
+    HP_REQUIRE(absorb >= HPEPS_ABSORB_CARRY && absorb <= HPEPS_ABSORB_NONE, HPEPS_ERR_INVALID_ARG,
+               "bad absorb mode");
+    for (int i = 0; i < 9; ++i) HP_REQUIRE(dims[i] >= 1, HPEPS_ERR_SHAPE, "dims must be >= 1");
+    hp::ZipDims z;
+    z.a = dims[0]; z.x = dims[1]; z.b = dims[2]; z.h = dims[3]; z.u = dims[4];
+    z.c = dims[5]; z.y = dims[6]; z.g = dims[7]; z.d = dims[8];
+    hp::ZipOperands op{V, S, T, Bra ? Bra : T};
+    hp::Ctx& c = *ctx->impl;
+    c.ws_reset();
+    hp::zip_esvd(c, cplx, z, op, (int)batch, *opts, absorb, U, sigma, R, log_scale);
+  });
+}
+
+hpeps_status hpeps_einsumsvd_pair(hpeps_ctx* ctx, int64_t batch, hpeps_dtype dtype,
+                                  const int64_t dims[3], const void* Bl, const void* Br,
+                                  const void* T1, const void* T2, const hpeps_esvd_opts* opts,
+                                  hpeps_absorb absorb, void* U, double* sigma, void* R) {
+  if (!ctx) return HPEPS_ERR_INVALID_ARG;
+  return guard(ctx, [&] {
+    check_opts(opts);
+    const bool cplx = is_cplx(dtype);
+    HP_REQUIRE(dims && Bl && Br && T1 && T2 && U && sigma && R, HPEPS_ERR_INVALID_ARG, "null argument");
+    HP_REQUIRE(batch >= 1 && batch < 65536, HPEPS_ERR_INVALID_ARG, "batch out of range");
+    HP_REQUIRE(absorb >= HPEPS_ABSORB_CARRY && absorb <= HPEPS_ABSORB_NONE, HPEPS_ERR_INVALID_ARG,
+               "bad absorb mode");
+    const int64_t m = dims[0], D = dims[1], d = dims[2];
+    HP_REQUIRE(m >= 1 && D >= 1 && d >= 1, HPEPS_ERR_SHAPE, "dims must be >= 1");
+    hp::Ctx& c = *ctx->impl;
+    c.ws_reset();
+    const int es = cplx ? 2 : 1;
+    // exact carry over the left column: V[a,x,X,b,h,H]
+    hp::CarryDims cd;
+    cd.a = m; cd.u = D; cd.b = m; cd.x = D; cd.h = D; cd.d = d;
+    double* V = c.ws<double>(batch * m * D * D * m * D * D * es);
+    hp::form_carry(c, cplx, cd, Bl, T1, T1, V, (int)batch);
+    hp::ZipDims z;
+    z.a = m; z.x = D; z.b = m; z.h = D; z.u = D; z.c = m; z.y = D; z.g = 1; z.d = d;
+    hp::ZipOperands op{V, Br, T2, T2};
+    hp::zip_esvd(c, cplx, z, op, (int)batch, *opts, absorb, U, sigma, R, nullptr);
+  });
+}
+
+}  // extern "C"

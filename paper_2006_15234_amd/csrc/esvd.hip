@@ -1,0 +1,442 @@
+// einsumsvd by randomized SVD on the implicit zip-up operator (Alg. 4 on
+// the network of Alg. 3's inner step, two-layer form of Sec. III-B).
+//
+// The operator A[(a,x,X),(y,Y,c,g,G)] = sum V[a,x,X,b,h,H] S[b,u,U,c]
+// T[u,y,h,g,p] conj(Bra[U,Y,H,G,p]) is applied right to left as four
+// gathered GEMMs (ket, bra, boundary, carry); its adjoint mirrors them.
+// Per einsumsvd: sketch, q+1 forward and q+1 adjoint applications, a
+// CholeskyQR orthogonalization after each, a CholeskyQR of B^* = A^* P to
+// obtain the k x k factor R_B, a one-sided Jacobi SVD of R_B^H, and two
+// factor products.  Every step is a kernel on the context stream; the only
+// host work is the launch sequence.
+#include <algorithm>
+#include <cmath>
+
+#include "esvd.h"
+
+namespace hp {
+
+namespace {
+
+// strides of the per-instance tensors (row-major in the documented leg order)
+struct ZipStrides {
+  // V[a,x,X,b,h,H]
+  int64_t Va, Vx, VX, Vb, Vh, VH;
+  // S[b,u,U,c]
+  int64_t Sb, Su, SU, Sc;
+  // T / Bra [u,y,h,g,p]
+  int64_t Tu, Ty, Th, Tg, Tp;
+  explicit ZipStrides(const ZipDims& d) {
+    VH = 1; Vh = d.h; Vb = d.h * d.h; VX = d.b * Vb; Vx = d.x * VX; Va = d.x * Vx;
+    Sc = 1; SU = d.c; Su = d.u * SU; Sb = d.u * Su;
+    Tp = 1; Tg = d.d; Th = d.g * Tg; Ty = d.h * Th; Tu = d.y * Ty;
+  }
+};
+
+}  // namespace
+
+int64_t ZipDims::rows() const { return a * x * x; }
+int64_t ZipDims::cols() const { return y * y * c * g * g; }
+int64_t ZipDims::v_size() const { return a * x * x * b * h * h; }
+int64_t ZipDims::s_size() const { return b * u * u * c; }
+int64_t ZipDims::t_size() const { return u * y * h * g * d; }
+
+// ---------------------------------------------------------------------------
+// operator applications
+
+void zip_apply(Ctx& ctx, Prec prec, const ZipDims& z, const ZipOperands& op, int batch,
+               int64_t k, bool adjoint, const void* X, void* Y, bool y_f64, const ZipWork& w) {
+  const ZipStrides s(z);
+  const int64_t a = z.a, x = z.x, b = z.b, h = z.h, u = z.u, c = z.c, y = z.y, g = z.g, d = z.d;
+  const bool cplx = prec == Prec::C128;
+  const int64_t rows = z.rows(), cols = z.cols();
+  // per-instance element counts of inputs / intermediates
+  const int64_t nV = z.v_size(), nS = z.s_size(), nT = z.t_size();
+  const int64_t nW1 = u * h * d * y * c * g * k;  // [u,h,p,Y,c,G,j] or [Y,G,p,u,h,c,j]
+  const int64_t nW2 = u * h * u * h * c * k;      // [U,H,u,h,c,j]
+  const int64_t nW3 = b * h * h * k;              // [b,h,H,j]
+  // W2 strides [U,H,u,h,c,j]
+  const int64_t w2j = 1, w2c = k, w2h = c * k, w2u = h * w2h, w2H = u * w2u, w2U = h * w2H;
+  // W3 strides [b,h,H,j]
+  const int64_t w3j = 1, w3H = k, w3h = h * k, w3b = h * w3h;
+  const bool f32 = prec == Prec::F32;
+
+  auto call = [&](const GemmDesc& dsc, const void* A, int64_t sA, bool cA, const void* B, int64_t sB,
+                  bool cB, void* C, int64_t sC, bool out_f64) {
+    GemmCall gc;
+    gc.A = A;
+    gc.B = B;
+    gc.C = C;
+    gc.sA = sA;
+    gc.sB = sB;
+    gc.sC = sC;
+    gc.batch = batch;
+    gc.conjA = cA;
+    gc.conjB = cB;
+    gc.out_f64 = out_f64;
+    gemm(ctx, prec, dsc, gc);
+  };
+
+  if (!adjoint) {
+    // X[y,Y,c,g,G,j]
+    const int64_t xj = 1, xG = k, xg = g * k, xc = g * xg, xY = c * xc, xy = y * xY;
+    // s1: W1[u,h,p | Y,c,G,j] = sum_{y,g} T[u,y,h,g,p] X[y,Y,c,g,G,j]
+    {
+      const int64_t w1j = 1, w1G = k, w1c = g * k, w1Y = c * w1c, w1p = y * w1Y, w1h = d * w1p, w1u = h * w1h;
+      GemmDesc D;
+      D.M = u * h * d; D.K = y * g; D.N = y * c * g * k;
+      D.Am.add(u, s.Tu).add(h, s.Th).add(d, s.Tp);
+      D.Ak.add(y, s.Ty).add(g, s.Tg);
+      D.Bk.add(y, xy).add(g, xg);
+      D.Bn.add(y, xY).add(c, xc).add(g, xG).add(k, xj);
+      D.Cm.add(u, w1u).add(h, w1h).add(d, w1p);
+      D.Cn.add(y, w1Y).add(c, w1c).add(g, w1G).add(k, w1j);
+      call(D, op.T, nT, false, X, cols * k, false, w.W1, nW1, false);
+    }
+    // s2: W2[U,H | u,h,c,j] = sum_{Y,G,p} conj(Bra[U,Y,H,G,p]) W1[u,h,p,Y,c,G,j]
+    {
+      const int64_t w1j = 1, w1G = k, w1c = g * k, w1Y = c * w1c, w1p = y * w1Y, w1h = d * w1p, w1u = h * w1h;
+      GemmDesc D;
+      D.M = u * h; D.K = y * g * d; D.N = u * h * c * k;
+      D.Am.add(u, s.Tu).add(h, s.Th);
+      D.Ak.add(y, s.Ty).add(g, s.Tg).add(d, s.Tp);
+      D.Bk.add(y, w1Y).add(g, w1G).add(d, w1p);
+      D.Bn.add(u, w1u).add(h, w1h).add(c, w1c).add(k, w1j);
+      D.Cm.add(u, w2U).add(h, w2H);
+      D.Cn.add(u, w2u).add(h, w2h).add(c, w2c).add(k, w2j);
+      call(D, op.Bra, nT, true, w.W1, nW1, false, w.W2, nW2, false);
+    }
+    // s3: W3[b | h,H,j] = sum_{u,U,c} S[b,u,U,c] W2[U,H,u,h,c,j]
+    {
+      GemmDesc D;
+      D.M = b; D.K = u * u * c; D.N = h * h * k;
+      D.Am.add(b, s.Sb);
+      D.Ak.add(u, s.Su).add(u, s.SU).add(c, s.Sc);
+      D.Bk.add(u, w2u).add(u, w2U).add(c, w2c);
+      D.Bn.add(h, w2h).add(h, w2H).add(k, w2j);
+      D.Cm.add(b, w3b);
+      D.Cn.add(h, w3h).add(h, w3H).add(k, w3j);
+      call(D, op.S, nS, false, w.W2, nW2, false, w.W3, nW3, false);
+    }
+    // s4: Y[a,x,X | j] = sum_{b,h,H} V[a,x,X,b,h,H] W3[b,h,H,j]
+    {
+      GemmDesc D;
+      D.M = rows; D.K = b * h * h; D.N = k;
+      D.Am.add(a, s.Va).add(x, s.Vx).add(x, s.VX);
+      D.Ak.add(b, s.Vb).add(h, s.Vh).add(h, s.VH);
+      D.Bk.add(b, w3b).add(h, w3h).add(h, w3H);
+      D.Bn.add(k, w3j);
+      D.Cm.add(rows, k);
+      D.Cn.add(k, 1);
+      call(D, op.V, nV, false, w.W3, nW3, false, Y, rows * k, y_f64 || !f32);
+    }
+  } else {
+    // P[a,x,X,j]
+    // t4: W3[b,h,H | j] = sum_{a,x,X} conj(V[a,x,X,b,h,H]) P[a,x,X,j]
+    {
+      GemmDesc D;
+      D.M = b * h * h; D.K = rows; D.N = k;
+      D.Am.add(b, s.Vb).add(h, s.Vh).add(h, s.VH);
+      D.Ak.add(a, s.Va).add(x, s.Vx).add(x, s.VX);
+      D.Bk.add(rows, k);
+      D.Bn.add(k, 1);
+      D.Cm.add(b, w3b).add(h, w3h).add(h, w3H);
+      D.Cn.add(k, w3j);
+      call(D, op.V, nV, true, X, rows * k, false, w.W3, nW3, false);
+    }
+    // t3: W2[u,U,c | h,H,j] = sum_b conj(S[b,u,U,c]) W3[b,h,H,j]   (W2 stored [U,H,u,h,c,j])
+    {
+      GemmDesc D;
+      D.M = u * u * c; D.K = b; D.N = h * h * k;
+      D.Am.add(u, s.Su).add(u, s.SU).add(c, s.Sc);
+      D.Ak.add(b, s.Sb);
+      D.Bk.add(b, w3b);
+      D.Bn.add(h, w3h).add(h, w3H).add(k, w3j);
+      D.Cm.add(u, w2u).add(u, w2U).add(c, w2c);
+      D.Cn.add(h, w2h).add(h, w2H).add(k, w2j);
+      call(D, op.S, nS, true, w.W3, nW3, false, w.W2, nW2, false);
+    }
+    // t2: W1[Y,G,p | u,h,c,j] = sum_{U,H} Bra[U,Y,H,G,p] W2[U,H,u,h,c,j]
+    const int64_t v1j = 1, v1c = k, v1h = c * k, v1u = h * v1h, v1p = u * v1u, v1G = d * v1p, v1Y = g * v1G;
+    {
+      GemmDesc D;
+      D.M = y * g * d; D.K = u * h; D.N = u * h * c * k;
+      D.Am.add(y, s.Ty).add(g, s.Tg).add(d, s.Tp);
+      D.Ak.add(u, s.Tu).add(h, s.Th);
+      D.Bk.add(u, w2U).add(h, w2H);
+      D.Bn.add(u, w2u).add(h, w2h).add(c, w2c).add(k, w2j);
+      D.Cm.add(y, v1Y).add(g, v1G).add(d, v1p);
+      D.Cn.add(u, v1u).add(h, v1h).add(c, v1c).add(k, v1j);
+      call(D, op.Bra, nT, false, w.W2, nW2, false, w.W1, nW1, false);
+    }
+    // t1: Z[y,g | Y,c,G,j] = sum_{u,h,p} conj(T[u,y,h,g,p]) W1[Y,G,p,u,h,c,j]
+    {
+      const int64_t zj = 1, zG = k, zg = g * k, zc = g * zg, zY = c * zc, zy = y * zY;
+      GemmDesc D;
+      D.M = y * g; D.K = u * h * d; D.N = y * c * g * k;
+      D.Am.add(y, s.Ty).add(g, s.Tg);
+      D.Ak.add(u, s.Tu).add(h, s.Th).add(d, s.Tp);
+      D.Bk.add(u, v1u).add(h, v1h).add(d, v1p);
+      D.Bn.add(y, v1Y).add(c, v1c).add(g, v1G).add(k, v1j);
+      D.Cm.add(y, zy).add(g, zg);
+      D.Cn.add(y, zY).add(c, zc).add(g, zG).add(k, zj);
+      call(D, op.T, nT, true, w.W1, nW1, false, Y, cols * k, y_f64 || !f32);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// P = Y R^-1 for n x k Y (batch stride n k), optional pass-through flags
+static void apply_rinv(Ctx& ctx, bool cplx, const double* Y, int64_t n, int64_t k, int batch,
+                       const double* Rinv, double* P, const int* copy_flags) {
+  GemmDesc D;
+  D.M = n; D.K = k; D.N = k;
+  D.Am.add(n, k);
+  D.Ak.add(k, 1);
+  D.Bk.add(k, k);
+  D.Bn.add(k, 1);
+  D.Cm.add(n, k);
+  D.Cn.add(k, 1);
+  GemmCall c;
+  c.A = Y;
+  c.B = Rinv;
+  c.C = P;
+  c.sA = c.sC = n * k;
+  c.sB = k * k;
+  c.batch = batch;
+  c.copy_if_zero = copy_flags;
+  gemm(ctx, cplx ? Prec::C128 : Prec::F64, D, c);
+}
+
+// Orthonormal basis of range(Y): result in P; Y is overwritten.
+void orthogonalize(Ctx& ctx, bool cplx, double* Y, double* P, int64_t n, int64_t k, int batch,
+                   const OrthWork& w) {
+  gram(ctx, cplx, Y, n, k, batch, w.G, nullptr);
+  chol_inv(ctx, cplx, w.G, n, k, batch, 1, w.Rinv, nullptr, w.flags);
+  apply_rinv(ctx, cplx, Y, n, k, batch, w.Rinv, P, nullptr);
+  gram(ctx, cplx, P, n, k, batch, w.G, nullptr);
+  chol_inv(ctx, cplx, w.G, n, k, batch, 2, w.Rinv, nullptr, w.flags);
+  apply_rinv(ctx, cplx, P, n, k, batch, w.Rinv, Y, nullptr);
+  gram(ctx, cplx, Y, n, k, batch, w.G, nullptr);
+  chol_inv(ctx, cplx, w.G, n, k, batch, 3, w.Rinv, nullptr, w.flags);
+  apply_rinv(ctx, cplx, Y, n, k, batch, w.Rinv, P, w.flags);
+  stats_reduce(ctx, w.flags, nullptr, batch, ctx.stats_dev);
+}
+
+// R factor of the CholeskyQR of Y (accumulated over the passes) into Racc.
+static void cholqr_r(Ctx& ctx, bool cplx, const double* Y, double* S1, double* S2, int64_t n,
+                     int64_t k, int batch, const OrthWork& w) {
+  gram(ctx, cplx, Y, n, k, batch, w.G, nullptr);
+  chol_inv(ctx, cplx, w.G, n, k, batch, 1, w.Rinv, w.Racc, w.flags);
+  apply_rinv(ctx, cplx, Y, n, k, batch, w.Rinv, S1, nullptr);
+  gram(ctx, cplx, S1, n, k, batch, w.G, nullptr);
+  chol_inv(ctx, cplx, w.G, n, k, batch, 2, w.Rinv, w.Racc, w.flags);
+  apply_rinv(ctx, cplx, S1, n, k, batch, w.Rinv, S2, w.flags);
+  gram(ctx, cplx, S2, n, k, batch, w.G, nullptr);
+  chol_inv(ctx, cplx, w.G, n, k, batch, 3, w.Rinv, w.Racc, w.flags);
+  stats_reduce(ctx, w.flags, nullptr, batch, ctx.stats_dev);
+}
+
+// ---------------------------------------------------------------------------
+
+int64_t sketch_width(int64_t m, int64_t p, int64_t rows, int64_t cols) {
+  return std::min(m + p, std::min(rows, cols));
+}
+
+void zip_esvd(Ctx& ctx, bool cplx, const ZipDims& z, const ZipOperands& op64, int batch,
+              const hpeps_esvd_opts& o, hpeps_absorb absorb, void* U, double* sigma, void* R,
+              double* log_scale) {
+  const int64_t rows = z.rows(), cols = z.cols();
+  const int64_t k = sketch_width(o.rank, o.oversample, rows, cols);
+  const int64_t mp = std::min<int64_t>(o.rank, k);
+  HP_REQUIRE(k >= 1, HPEPS_ERR_SHAPE, "empty einsumsvd");
+  HP_REQUIRE(k <= (cplx ? 88 : 128), HPEPS_ERR_SHAPE, "sketch width k exceeds the small-SVD limit");
+  const bool f32 = o.sketch_precision == HPEPS_F32;
+  HP_REQUIRE(!(f32 && cplx), HPEPS_ERR_DTYPE, "FP32 sketches are real-only");
+  HP_REQUIRE(o.sketch_precision == HPEPS_F64 || o.sketch_precision == HPEPS_F32, HPEPS_ERR_DTYPE,
+             "sketch precision must be F64 or F32");
+  const Prec prec = cplx ? Prec::C128 : (f32 ? Prec::F32 : Prec::F64);
+  const int es = cplx ? 2 : 1;  // doubles per element
+  const int max_sweeps = o.jacobi_max_sweeps > 0 ? o.jacobi_max_sweeps : 40;
+  ctx.last_rank = mp;
+  ctx.last_k = k;
+
+  // workspace
+  const int64_t nb = batch;
+  double* Xc0 = ctx.ws<double>(nb * cols * k * es);
+  double* Xc1 = ctx.ws<double>(nb * cols * k * es);
+  double* Xc2 = ctx.ws<double>(nb * cols * k * es);
+  double* Xr0 = ctx.ws<double>(nb * rows * k * es);
+  double* Xr1 = ctx.ws<double>(nb * rows * k * es);
+  const int64_t esz = f32 ? 4 : 8 * es;  // bytes per intermediate element
+  ZipWork w;
+  w.W1 = ctx.ws_alloc(nb * z.u * z.h * z.d * z.y * z.c * z.g * k * esz);
+  w.W2 = ctx.ws_alloc(nb * z.u * z.h * z.u * z.h * z.c * k * esz);
+  w.W3 = ctx.ws_alloc(nb * z.b * z.h * z.h * k * esz);
+  OrthWork ow;
+  ow.G = ctx.ws<double>(nb * k * k * es);
+  ow.Rinv = ctx.ws<double>(nb * k * k * es);
+  ow.Racc = ctx.ws<double>(nb * k * k * es);
+  ow.flags = ctx.ws<int>(nb);
+  double* Z = ctx.ws<double>(nb * k * k * es);
+  double* sig = ctx.ws<double>(nb * k);
+  double* isig = ctx.ws<double>(nb * k);
+  double* isig1 = ctx.ws<double>(nb);
+  int* sweeps = ctx.ws<int>(nb);
+
+  // operands in the apply precision
+  ZipOperands op = op64;
+  float* xin32 = nullptr;
+  if (f32) {
+    float* V32 = ctx.ws<float>(nb * z.v_size());
+    float* S32 = ctx.ws<float>(nb * z.s_size());
+    float* T32 = ctx.ws<float>(nb * z.t_size());
+    float* B32 = ctx.ws<float>(nb * z.t_size());
+    convert_f64_to_f32(ctx, (const double*)op64.V, V32, nb * z.v_size());
+    convert_f64_to_f32(ctx, (const double*)op64.S, S32, nb * z.s_size());
+    convert_f64_to_f32(ctx, (const double*)op64.T, T32, nb * z.t_size());
+    convert_f64_to_f32(ctx, (const double*)op64.Bra, B32, nb * z.t_size());
+    op.V = V32;
+    op.S = S32;
+    op.T = T32;
+    op.Bra = B32;
+    xin32 = ctx.ws<float>(nb * std::max(rows, cols) * k);
+  }
+  auto apply = [&](bool adj, const double* X, double* Y) {
+    const void* xin = X;
+    if (f32) {
+      convert_f64_to_f32(ctx, X, xin32, nb * (adj ? rows : cols) * k);
+      xin = xin32;
+    }
+    zip_apply(ctx, prec, z, op, batch, k, adj, xin, Y, true, w);
+  };
+
+  // Alg. 4
+  if (f32) {
+    sketch(ctx, xin32, true, cols, k, batch, o.seed, o.stream_id);
+    zip_apply(ctx, prec, z, op, batch, k, false, xin32, Xr0, true, w);
+  } else {
+    sketch(ctx, Xc0, false, cols, k, batch, o.seed, o.stream_id);
+    zip_apply(ctx, prec, z, op, batch, k, false, Xc0, Xr0, true, w);
+  }
+  orthogonalize(ctx, cplx, Xr0, Xr1, rows, k, batch, ow);          // P in Xr1
+  for (int it = 0; it < o.power_iters; ++it) {
+    apply(true, Xr1, Xc0);
+    orthogonalize(ctx, cplx, Xc0, Xc1, cols, k, batch, ow);        // Q in Xc1
+    apply(false, Xc1, Xr0);
+    orthogonalize(ctx, cplx, Xr0, Xr1, rows, k, batch, ow);        // P in Xr1
+  }
+  apply(true, Xr1, Xc0);                                           // B^* = A^* P
+  cholqr_r(ctx, cplx, Xc0, Xc1, Xc2, cols, k, batch, ow);          // R_B in Racc
+  jacobi_svd(ctx, cplx, ow.Racc, k, batch, max_sweeps, Z, sig, isig, isig1,
+             absorb == HPEPS_ABSORB_CARRY ? log_scale : nullptr, sweeps);
+  stats_reduce(ctx, nullptr, sweeps, batch, ctx.stats_dev);
+
+  const Prec p64 = cplx ? Prec::C128 : Prec::F64;
+  // U = P Z[:, :m']  -> [rows, m']
+  {
+    GemmDesc D;
+    D.M = rows; D.K = k; D.N = mp;
+    D.Am.add(rows, k);
+    D.Ak.add(k, 1);
+    D.Bk.add(k, k);
+    D.Bn.add(mp, 1);
+    D.Cm.add(rows, mp);
+    D.Cn.add(mp, 1);
+    GemmCall c;
+    c.A = Xr1;
+    c.B = Z;
+    c.C = U;
+    c.sA = rows * k;
+    c.sB = k * k;
+    c.sC = rows * mp;
+    c.batch = batch;
+    gemm(ctx, p64, D, c);
+  }
+  // right factor: (B^* Z[:, :m'])^H  -> [m', cols], scaled per *absorb*
+  {
+    GemmDesc D;
+    D.M = cols; D.K = k; D.N = mp;
+    D.Am.add(cols, k);
+    D.Ak.add(k, 1);
+    D.Bk.add(k, k);
+    D.Bn.add(mp, 1);
+    D.Cm.add(cols, 1);
+    D.Cn.add(mp, cols);
+    GemmCall c;
+    c.A = Xc0;
+    c.B = Z;
+    c.C = R;
+    c.sA = cols * k;
+    c.sB = k * k;
+    c.sC = mp * cols;
+    c.batch = batch;
+    c.conjC = cplx;
+    if (absorb == HPEPS_ABSORB_CARRY) c.scale = isig1;
+    if (absorb == HPEPS_ABSORB_NONE) {
+      c.nscale = isig;
+      c.nscale_ld = k;
+    }
+    gemm(ctx, p64, D, c);
+  }
+  copy_sigma(ctx, sig, k, mp, batch, sigma);
+}
+
+// ---------------------------------------------------------------------------
+// exact carry of one column: V[a,x,X,b,h,H] = sum_{u,U,p} L[a,u,U,b] T[u,x,1,h,p] conj(Bra[U,X,1,H,p])
+void form_carry(Ctx& ctx, bool cplx, const CarryDims& cd, const void* L, const void* T,
+                const void* Bra, void* V, int batch) {
+  const int64_t a = cd.a, u = cd.u, b = cd.b, x = cd.x, h = cd.h, d = cd.d;
+  const Prec p = cplx ? Prec::C128 : Prec::F64;
+  const int es = cplx ? 2 : 1;
+  // L strides [a,u,U,b]
+  const int64_t Lb = 1, LU = b, Lu = u * b, La = u * u * b;
+  // T strides [u,x,1,h,p]
+  const int64_t Tp = 1, Th = d, Tx = h * d, Tu = x * h * d;
+  // X1[a,U,b,x,h,p]
+  const int64_t Xp = 1, Xh = d, Xx = h * d, Xb = x * Xx, XU = b * Xb, Xa = u * XU;
+  // V[a,x,X,b,h,H]
+  const int64_t VH = 1, Vh = h, Vb = h * h, VX = b * Vb, Vx = x * VX, Va = x * Vx;
+  double* X1 = ctx.ws<double>((int64_t)batch * a * u * b * x * h * d * es);
+  {
+    GemmDesc D;
+    D.M = a * u * b; D.K = u; D.N = x * h * d;
+    D.Am.add(a, La).add(u, LU).add(b, Lb);
+    D.Ak.add(u, Lu);
+    D.Bk.add(u, Tu);
+    D.Bn.add(x, Tx).add(h, Th).add(d, Tp);
+    D.Cm.add(a, Xa).add(u, XU).add(b, Xb);
+    D.Cn.add(x, Xx).add(h, Xh).add(d, Xp);
+    GemmCall c;
+    c.A = L;
+    c.B = T;
+    c.C = X1;
+    c.sA = a * u * u * b;
+    c.sB = u * x * h * d;
+    c.sC = a * u * b * x * h * d;
+    c.batch = batch;
+    gemm(ctx, p, D, c);
+  }
+  {
+    GemmDesc D;
+    D.M = a * b * x * h; D.K = u * d; D.N = x * h;
+    D.Am.add(a, Xa).add(b, Xb).add(x, Xx).add(h, Xh);
+    D.Ak.add(u, XU).add(d, Xp);
+    D.Bk.add(u, Tu).add(d, Tp);
+    D.Bn.add(x, Tx).add(h, Th);
+    D.Cm.add(a, Va).add(b, Vb).add(x, Vx).add(h, Vh);
+    D.Cn.add(x, VX).add(h, VH);
+    GemmCall c;
+    c.A = X1;
+    c.B = Bra;
+    c.C = V;
+    c.sA = a * u * b * x * h * d;
+    c.sB = u * x * h * d;
+    c.sC = a * x * x * b * h * h;
+    c.batch = batch;
+    c.conjB = cplx;
+    gemm(ctx, p, D, c);
+  }
+}
+
+}  // namespace hp

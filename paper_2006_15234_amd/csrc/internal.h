@@ -1,0 +1,166 @@
+// Internal declarations of the hpeps library (not part of the ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <hip/hip_complex.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/hpeps.h"
+
+namespace hp {
+
+// ---------------------------------------------------------------------------
+// errors
+struct Error {
+  hpeps_status code;
+  std::string msg;
+};
+
+#define HP_CHECK_HIP(expr)                                                        \
+  do {                                                                            \
+    hipError_t e_ = (expr);                                                       \
+    if (e_ != hipSuccess)                                                         \
+      throw ::hp::Error{HPEPS_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)}; \
+  } while (0)
+
+#define HP_REQUIRE(cond, code, msg)                       \
+  do {                                                    \
+    if (!(cond)) throw ::hp::Error{code, std::string(msg)}; \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// index maps: a linear index i over a list of modes (last mode fastest) maps
+// to the element offset sum_m idx_m * stride_m.
+constexpr int kMaxModes = 8;
+struct IndexMap {
+  int n = 0;
+  int64_t dim[kMaxModes];
+  int64_t stride[kMaxModes];
+  int64_t size() const {
+    int64_t s = 1;
+    for (int i = 0; i < n; ++i) s *= dim[i];
+    return s;
+  }
+  IndexMap& add(int64_t d, int64_t s) {
+    dim[n] = d;
+    stride[n] = s;
+    ++n;
+    return *this;
+  }
+  std::string key() const;
+};
+
+// Row-major strides of a shape.
+std::vector<int64_t> rm_strides(const std::vector<int64_t>& shape);
+
+// ---------------------------------------------------------------------------
+// GEMM with gathered operands:
+//   C[b][rC[m] + cC[n]] = scale * sum_k A[b][rA[m] + cA[k]] * B[b][rB[k] + cB[n]]
+enum class Prec { F64, C128, F32 };
+
+struct GemmDesc {
+  IndexMap Am, Ak, Bk, Bn, Cm, Cn;  // M/K/N index maps of each operand
+  int64_t M = 0, N = 0, K = 0;
+};
+
+struct GemmCall {
+  const void* A = nullptr;
+  const void* B = nullptr;
+  void* C = nullptr;
+  int64_t sA = 0, sB = 0, sC = 0;  // batch strides (elements)
+  int batch = 1;
+  bool conjA = false, conjB = false, conjC = false;
+  double alpha = 1.0;
+  const double* scale = nullptr;   // per batch multiplier (device) or null
+  const double* nscale = nullptr;  // per (batch, n) multiplier (device) or null
+  int64_t nscale_ld = 0;
+  bool accumulate = false;         // C += result
+  const int* copy_if_zero = nullptr; // per batch flag: when 0, C := A (no product)
+  // storage types (F32 compute only): inputs float; output float or double
+  bool out_f64 = true;
+  // per-instance element counts of A, B, C: every gathered offset is checked
+  // against them on the host before the launch (0 = the operand is not checked)
+  int64_t nA = 0, nB = 0, nC = 0;
+};
+
+class Ctx;
+void gemm(Ctx& ctx, Prec prec, const GemmDesc& d, const GemmCall& c);
+
+// ---------------------------------------------------------------------------
+// small dense linear algebra kernels (launchers)
+// Gram: G[b] = Y[b]^H Y[b] (Y: n x k row-major, batch stride n*k); G k x k.
+void gram(Ctx& ctx, bool cplx, const void* Y, int64_t n, int64_t k, int batch, double* G,
+          const int* active);
+// CholeskyQR step on G (k x k, Hermitian): writes Rinv (k x k upper).  pass 1
+// may shift; flags[b] bit 1 is set when a third pass is needed, bit 2 on
+// non-finite values.  pass 3 is skipped (Rinv = I) unless bit 1 is set.
+// Racc (optional): pass 1 writes R, later passes Racc <- R Racc.
+void chol_inv(Ctx& ctx, bool cplx, const double* G, int64_t n_rows, int64_t k, int batch,
+              int pass, double* Rinv, double* Racc, int* flags);
+// One-sided Jacobi SVD of K = Racc^H (k x k) per batch: writes Z (k x k,
+// left singular vectors of K in columns, sorted by descending sigma), sigma
+// (k), inv_sigma (k), inv_sigma1 (1); log_scale (optional) += log sigma_1;
+// stats[b] = sweeps used (negative if the cap was hit).
+void jacobi_svd(Ctx& ctx, bool cplx, const double* Racc, int64_t k, int batch, int max_sweeps,
+                double* Z, double* sigma, double* inv_sigma, double* inv_sigma1,
+                double* log_scale, int* stats);
+// Sketch generator (see hpeps.h); writes n*k values per batch instance,
+// instance b uses stream_id + b.  out is double or float (f32).
+void sketch(Ctx& ctx, void* out, bool f32, int64_t n, int64_t k, int batch, uint64_t seed,
+            uint64_t stream_id);
+// Elementwise conversion and scaling helpers.
+void convert_f64_to_f32(Ctx& ctx, const double* in, float* out, int64_t n);
+void fill_zero(Ctx& ctx, void* p, int64_t bytes);
+// Frobenius norm of x (n doubles, or n complex if cplx) per batch (batch
+// stride n elements); x is divided by the norm and log_scale[b] += log(norm).
+void normalize(Ctx& ctx, bool cplx, void* x, int64_t n, int batch, double* log_scale);
+// diag(out)[..] helpers for tests of the gemm itself are not exported.
+void copy_sigma(Ctx& ctx, const double* sigma_k, int64_t k, int64_t mp, int batch, double* out);
+void stats_reduce(Ctx& ctx, const int* flags, const int* sweeps, int batch, int* acc);
+
+// ---------------------------------------------------------------------------
+// context: stream, workspace arena, cached index tables, diagnostics
+class Ctx {
+ public:
+  explicit Ctx(int device);
+  ~Ctx();
+  int device;
+  hipStream_t stream = nullptr;
+  std::string last_error;
+  int64_t ws_limit = 0;
+
+  // device index table for an IndexMap (int32 offsets), cached
+  const int* table(const IndexMap& m);
+
+  // workspace: a bump allocator that is reset at the start of every ABI call
+  void ws_reset();
+  void* ws_alloc(int64_t bytes);
+  template <class T>
+  T* ws(int64_t n) { return reinterpret_cast<T*>(ws_alloc(n * (int64_t)sizeof(T))); }
+  // reserve at least bytes for the coming call (grows the arena; syncs)
+  void ws_reserve(int64_t bytes);
+
+  // diagnostics accumulator on the device: [extra passes, max sweeps,
+  // numeric errors, not converged]
+  int* stats_dev = nullptr;
+  int64_t last_rank = 0, last_k = 0;
+
+ private:
+  std::map<std::string, int*> tables_;
+  struct Chunk {
+    char* base = nullptr;
+    int64_t cap = 0;
+  };
+  std::vector<Chunk> chunks_;
+  int cur_ = 0;
+  int64_t ws_off_ = 0;
+};
+
+// Launch-size helper
+inline unsigned cdiv(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
+
+}  // namespace hp

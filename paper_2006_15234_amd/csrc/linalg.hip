@@ -1,0 +1,546 @@
+// Small dense kernels of the randomized SVD (Alg. 4): sketch generation,
+// Gram matrices, CholeskyQR factor/inverse with an automatic shift, the
+// one-sided Jacobi SVD of the k x k projected factor, and helpers.
+//
+// Orthogonalization (Alg. 4 "orthogonalize") runs through a small Gram
+// matrix, as in the paper's reshape-avoiding orthogonalization (Alg. 5),
+// but factors it by Cholesky instead of an eigendecomposition:
+//   pass 1:  G = Y^H Y, R = chol(G) (retried with the shift of shifted
+//            CholeskyQR -- Fukaya, Kannan, Nakatsukasa, Zhang, Yamamoto,
+//            SIAM J. Sci. Comput. 42 (2020) -- when it breaks down or the
+//            factor is too ill-conditioned), P1 = Y R^-1
+//   pass 2:  the same on P1 (CholeskyQR2, Yamamoto et al. 2015)
+//   pass 3:  only for sketches flagged in pass 1.
+// Every small factorization runs in one 1024-thread workgroup per instance
+// with the k x k matrix resident in LDS (up to 128 KB of the 160 KB).
+#include <algorithm>
+#include <cmath>
+
+#include "internal.h"
+
+namespace hp {
+
+namespace {
+
+struct cd {
+  double re, im;
+};
+__device__ __forceinline__ cd cmul(cd a, cd b) { return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
+__device__ __forceinline__ cd cconj(cd a) { return {a.re, -a.im}; }
+
+template <bool CPLX>
+struct S;
+template <>
+struct S<false> {
+  using T = double;
+  static __device__ __forceinline__ double re(double x) { return x; }
+  static __device__ __forceinline__ double abs2(double x) { return x * x; }
+  static __device__ __forceinline__ double mul(double a, double b) { return a * b; }
+  static __device__ __forceinline__ double conjmul(double a, double b) { return a * b; }  // conj(a)*b
+  static __device__ __forceinline__ double conj(double a) { return a; }
+  static __device__ __forceinline__ double scale(double a, double s) { return a * s; }
+  static __device__ __forceinline__ double zero() { return 0.0; }
+  static __device__ __forceinline__ double one() { return 1.0; }
+  static __device__ __forceinline__ double sub(double a, double b) { return a - b; }
+  static __device__ __forceinline__ double add(double a, double b) { return a + b; }
+  static __device__ __forceinline__ bool finite(double a) { return isfinite(a); }
+};
+template <>
+struct S<true> {
+  using T = cd;
+  static __device__ __forceinline__ double re(cd x) { return x.re; }
+  static __device__ __forceinline__ double abs2(cd x) { return x.re * x.re + x.im * x.im; }
+  static __device__ __forceinline__ cd mul(cd a, cd b) { return cmul(a, b); }
+  static __device__ __forceinline__ cd conjmul(cd a, cd b) { return cmul(cconj(a), b); }
+  static __device__ __forceinline__ cd conj(cd a) { return cconj(a); }
+  static __device__ __forceinline__ cd scale(cd a, double s) { return {a.re * s, a.im * s}; }
+  static __device__ __forceinline__ cd zero() { return {0.0, 0.0}; }
+  static __device__ __forceinline__ cd one() { return {1.0, 0.0}; }
+  static __device__ __forceinline__ cd sub(cd a, cd b) { return {a.re - b.re, a.im - b.im}; }
+  static __device__ __forceinline__ cd add(cd a, cd b) { return {a.re + b.re, a.im + b.im}; }
+  static __device__ __forceinline__ bool finite(cd a) { return isfinite(a.re) && isfinite(a.im); }
+};
+
+constexpr int kSmallThreads = 1024;
+constexpr int FLAG_THIRD_PASS = 2;
+constexpr int FLAG_NUMERIC = 4;
+
+// ---------------------------------------------------------------------------
+// sketch generator (SplitMix64 output function, counter based)
+__device__ __forceinline__ uint64_t mix64(uint64_t z) {
+  z ^= z >> 30;
+  z *= 0xBF58476D1CE4E5B9ull;
+  z ^= z >> 27;
+  z *= 0x94D049BB133111EBull;
+  z ^= z >> 31;
+  return z;
+}
+
+template <class TO>
+__global__ void sketch_kernel(TO* out, long long nk, uint64_t seed, uint64_t stream_id) {
+  const int b = blockIdx.y;
+  const uint64_t base = mix64(mix64(seed) + stream_id + (uint64_t)b);
+  TO* o = out + (long long)b * nk;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < nk;
+       i += (long long)gridDim.x * blockDim.x) {
+    const uint64_t h = mix64(base + (uint64_t)(i + 1) * 0x9E3779B97F4A7C15ull);
+    // (h >> 11) < 2^53 converts exactly; the affine map below is exact too.
+    const double v = 2.0 * (double)(h >> 11) * 0x1p-53 - 1.0;
+    o[i] = (TO)v;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Cholesky + triangular inverse of one k x k Gram matrix per workgroup.
+template <bool CPLX>
+__global__ __launch_bounds__(kSmallThreads) void chol_inv_kernel(const double* Gall, long long n_rows,
+                                                                  int k, int pass, double* Rinv_all,
+                                                                  double* Racc_all, int* flags) {
+  using T = typename S<CPLX>::T;
+  extern __shared__ double smem[];
+  T* L = reinterpret_cast<T*>(smem);
+  __shared__ int fail;
+  __shared__ double red[kSmallThreads / 64];
+  __shared__ double dmin_s, dmax_s;
+  const int b = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
+  const long long kk = (long long)k * k;
+  const T* G = reinterpret_cast<const T*>(Gall) + b * kk;
+  T* Rinv = reinterpret_cast<T*>(Rinv_all) + b * kk;
+  T* Racc = Racc_all ? reinterpret_cast<T*>(Racc_all) + b * kk : nullptr;
+  int f = flags[b];
+
+  auto write_identity = [&]() {
+    for (long long e = tid; e < kk; e += nt) Rinv[e] = (e / k == e % k) ? S<CPLX>::one() : S<CPLX>::zero();
+  };
+  if (pass == 3 && !(f & FLAG_THIRD_PASS)) {
+    write_identity();
+    return;
+  }
+  if (pass == 1) f = 0;
+
+  // trace of G for the shift
+  double tr = 0.0;
+  for (int i = tid; i < k; i += nt) tr += S<CPLX>::re(G[(long long)i * k + i]);
+  for (int o = 32; o > 0; o >>= 1) tr += __shfl_xor(tr, o);
+  if ((tid & 63) == 0) red[tid >> 6] = tr;
+  __syncthreads();
+  if (tid == 0) {
+    double s = 0;
+    for (int w = 0; w < nt / 64; ++w) s += red[w];
+    red[0] = s;
+  }
+  __syncthreads();
+  tr = red[0];
+  // shifted CholeskyQR: s = 11 (n k + k (k + 1)) u ||Y||^2, with ||Y||_2^2 <= trace(G)
+  const double shift = 11.0 * ((double)n_rows * k + (double)k * (k + 1)) * 0x1p-53 * tr;
+
+  for (int attempt = 0; attempt < 2; ++attempt) {
+    for (long long e = tid; e < kk; e += nt) {
+      T v = G[e];
+      if (attempt == 1 && e / k == e % k) {
+        if constexpr (CPLX) v.re += shift; else v += shift;
+      }
+      L[e] = v;
+    }
+    if (tid == 0) fail = 0;
+    __syncthreads();
+    for (int j = 0; j < k; ++j) {
+      if (tid == 0) {
+        const double d = S<CPLX>::re(L[(long long)j * k + j]);
+        if (!(d > 0.0) || !isfinite(d)) fail = 1;
+        else L[(long long)j * k + j] = S<CPLX>::scale(S<CPLX>::one(), sqrt(d));
+      }
+      __syncthreads();
+      if (fail) break;
+      const double inv = 1.0 / S<CPLX>::re(L[(long long)j * k + j]);
+      for (int l = j + 1 + tid; l < k; l += nt) L[(long long)j * k + l] = S<CPLX>::scale(L[(long long)j * k + l], inv);
+      __syncthreads();
+      const int r = k - j - 1;
+      for (int e = tid; e < r * r; e += nt) {
+        const int i = j + 1 + e / r, l = j + 1 + e % r;
+        if (l >= i)
+          L[(long long)i * k + l] = S<CPLX>::sub(L[(long long)i * k + l],
+                                                 S<CPLX>::conjmul(L[(long long)j * k + i], L[(long long)j * k + l]));
+      }
+      __syncthreads();
+    }
+    if (!fail) {
+      // conditioning estimate from the diagonal of R
+      if (tid == 0) {
+        double mn = 1e300, mx = 0;
+        for (int i = 0; i < k; ++i) {
+          const double d = S<CPLX>::re(L[(long long)i * k + i]);
+          mn = fmin(mn, d);
+          mx = fmax(mx, d);
+        }
+        dmin_s = mn;
+        dmax_s = mx;
+      }
+      __syncthreads();
+      const bool illcond = dmin_s < 1e-7 * dmax_s;
+      if (attempt == 0 && illcond && pass == 1) {
+        f |= FLAG_THIRD_PASS;
+        __syncthreads();
+        continue;  // redo with the shift
+      }
+      break;
+    }
+    f |= FLAG_THIRD_PASS;
+    __syncthreads();
+  }
+  if (fail) {
+    f |= FLAG_NUMERIC;
+    write_identity();
+    if (tid == 0) flags[b] = f;
+    return;
+  }
+  // zero the strictly lower part (the Cholesky above only touched the upper)
+  for (long long e = tid; e < kk; e += nt)
+    if (e / k > e % k) L[e] = S<CPLX>::zero();
+  __syncthreads();
+
+  // Racc <- R (pass 1) or R * Racc (later passes)
+  if (Racc) {
+    if (pass == 1) {
+      for (long long e = tid; e < kk; e += nt) Racc[e] = L[e];
+    } else {
+      T tmp[16];
+      int cnt = 0;
+      for (long long e = tid; e < kk; e += nt, ++cnt) {
+        const int i = (int)(e / k), l = (int)(e % k);
+        T s = S<CPLX>::zero();
+        for (int t = i; t <= l; ++t) s = S<CPLX>::add(s, S<CPLX>::mul(L[(long long)i * k + t], Racc[(long long)t * k + l]));
+        tmp[cnt] = s;
+      }
+      __syncthreads();
+      cnt = 0;
+      for (long long e = tid; e < kk; e += nt, ++cnt) Racc[e] = tmp[cnt];
+    }
+  }
+  __syncthreads();
+
+  // in-place inverse of the upper-triangular R, column by column
+  for (int j = 0; j < k; ++j) {
+    T x = S<CPLX>::zero();
+    const T ljj = L[(long long)j * k + j];
+    const double invd = 1.0 / S<CPLX>::re(ljj);
+    if (tid < j) {
+      for (int t = tid; t < j; ++t) x = S<CPLX>::add(x, S<CPLX>::mul(L[(long long)tid * k + t], L[(long long)t * k + j]));
+    }
+    __syncthreads();
+    if (tid < j) L[(long long)tid * k + j] = S<CPLX>::scale(x, -invd);
+    if (tid == j) L[(long long)j * k + j] = S<CPLX>::scale(S<CPLX>::one(), invd);
+    __syncthreads();
+  }
+  for (long long e = tid; e < kk; e += nt) Rinv[e] = L[e];
+  if (tid == 0) flags[b] = f;
+}
+
+// ---------------------------------------------------------------------------
+// One-sided (Hestenes) Jacobi SVD of K = Racc^H, columns rotated in the
+// parallel round-robin order; one wavefront per column pair.
+template <bool CPLX>
+__global__ __launch_bounds__(kSmallThreads) void jacobi_kernel(const double* Racc_all, int k, int max_sweeps,
+                                                               double* Z_all, double* sigma_all,
+                                                               double* inv_sigma_all, double* inv_sigma1,
+                                                               double* log_scale, int* stats) {
+  using T = typename S<CPLX>::T;
+  extern __shared__ double smem[];
+  const int n = (k + 1) / 2 * 2;  // even number of columns (one zero column if k is odd)
+  T* Kc = reinterpret_cast<T*>(smem);  // column-major: Kc[c * k + r]
+  __shared__ int rotated;
+  __shared__ int perm[128];
+  __shared__ double nrm[128];
+  const int b = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
+  const long long kk = (long long)k * k;
+  const T* R = reinterpret_cast<const T*>(Racc_all) + b * kk;
+  // column c of K = R^H is the conjugated row c of R
+  for (long long e = tid; e < (long long)n * k; e += nt) {
+    const int c = (int)(e / k), r = (int)(e % k);
+    Kc[e] = (c < k) ? S<CPLX>::conj(R[(long long)c * k + r]) : S<CPLX>::zero();
+  }
+  __syncthreads();
+  const int wave = tid >> 6, lane = tid & 63, nw = nt >> 6;
+  const double tol = sqrt((double)k) * 0x1p-52;
+  int sweep = 0;
+  bool converged = false;
+  for (sweep = 0; sweep < max_sweeps; ++sweep) {
+    if (tid == 0) rotated = 0;
+    __syncthreads();
+    for (int round = 0; round < n - 1; ++round) {
+      for (int p = wave; p < n / 2; p += nw) {
+        // circle method: position 0 fixed, the others rotate
+        auto at = [&](int pos) { return pos == 0 ? 0 : 1 + (pos - 1 + round) % (n - 1); };
+        const int ca = at(p), cb = at(n - 1 - p);
+        T* x = Kc + (long long)ca * k;
+        T* y = Kc + (long long)cb * k;
+        double a2 = 0, b2 = 0, gr = 0, gi = 0;
+        for (int r = lane; r < k; r += 64) {
+          const T xv = x[r], yv = y[r];
+          a2 += S<CPLX>::abs2(xv);
+          b2 += S<CPLX>::abs2(yv);
+          if constexpr (CPLX) {
+            const cd g = cmul(cconj(xv), yv);
+            gr += g.re;
+            gi += g.im;
+          } else {
+            gr += xv * yv;
+          }
+        }
+        for (int o = 32; o > 0; o >>= 1) {
+          a2 += __shfl_xor(a2, o);
+          b2 += __shfl_xor(b2, o);
+          gr += __shfl_xor(gr, o);
+          if constexpr (CPLX) gi += __shfl_xor(gi, o);
+        }
+        const double ga = sqrt(gr * gr + gi * gi);
+        if (a2 > 0 && b2 > 0 && ga > tol * sqrt(a2) * sqrt(b2)) {
+          const double zeta = (b2 - a2) / (2.0 * ga);
+          const double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+          const double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
+          // y~ = conj(e) y with e = gamma / |gamma|, then a real rotation of (x, y~)
+          const double er = gr / ga, ei = gi / ga;
+          for (int r = lane; r < k; r += 64) {
+            const T xv = x[r];
+            T yt;
+            if constexpr (CPLX) {
+              const T yv = y[r];
+              yt = {er * yv.re + ei * yv.im, er * yv.im - ei * yv.re};
+              x[r] = {c * xv.re - s * yt.re, c * xv.im - s * yt.im};
+              y[r] = {s * xv.re + c * yt.re, s * xv.im + c * yt.im};
+            } else {
+              yt = er * y[r];
+              x[r] = c * xv - s * yt;
+              y[r] = s * xv + c * yt;
+            }
+          }
+          if (lane == 0) rotated = 1;
+        }
+      }
+      __syncthreads();
+    }
+    __syncthreads();
+    if (!rotated) {
+      converged = true;
+      ++sweep;
+      break;
+    }
+    __syncthreads();
+  }
+  // singular values = column norms; sort descending (stable in column index)
+  for (int c = wave; c < k; c += nw) {
+    double a2 = 0;
+    for (int r = lane; r < k; r += 64) a2 += S<CPLX>::abs2(Kc[(long long)c * k + r]);
+    for (int o = 32; o > 0; o >>= 1) a2 += __shfl_xor(a2, o);
+    if (lane == 0) nrm[c] = sqrt(a2);
+  }
+  __syncthreads();
+  if (tid == 0) {
+    for (int i = 0; i < k; ++i) perm[i] = i;
+    for (int i = 1; i < k; ++i) {
+      const int v = perm[i];
+      int j = i - 1;
+      while (j >= 0 && nrm[perm[j]] < nrm[v]) {
+        perm[j + 1] = perm[j];
+        --j;
+      }
+      perm[j + 1] = v;
+    }
+  }
+  __syncthreads();
+  T* Z = reinterpret_cast<T*>(Z_all) + b * kk;
+  for (long long e = tid; e < kk; e += nt) {
+    const int r = (int)(e / k), i = (int)(e % k);
+    const int c = perm[i];
+    const double s = nrm[c];
+    Z[e] = s > 0 ? S<CPLX>::scale(Kc[(long long)c * k + r], 1.0 / s) : S<CPLX>::zero();
+  }
+  for (int i = tid; i < k; i += nt) {
+    const double s = nrm[perm[i]];
+    sigma_all[(long long)b * k + i] = s;
+    inv_sigma_all[(long long)b * k + i] = s > 0 ? 1.0 / s : 0.0;
+  }
+  if (tid == 0) {
+    const double s1 = nrm[perm[0]];
+    inv_sigma1[b] = s1 > 0 ? 1.0 / s1 : 0.0;
+    if (log_scale) log_scale[b] += log(s1);
+    stats[b] = converged ? sweep : -sweep;
+  }
+}
+
+__global__ void f64_to_f32_kernel(const double* in, float* out, long long n) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    out[i] = (float)in[i];
+}
+
+// Frobenius norm per batch instance: block partial sums, then finalize.
+__global__ void sumsq_partial_kernel(const double* x, long long n, double* part) {
+  const int b = blockIdx.y;
+  const double* xb = x + (long long)b * n;
+  double s = 0;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    s += xb[i] * xb[i];
+  __shared__ double red[16];
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0;
+    for (int w = 0; w < (int)blockDim.x / 64; ++w) t += red[w];
+    part[(long long)b * gridDim.x + blockIdx.x] = t;
+  }
+}
+
+__global__ void norm_finalize_kernel(const double* part, int nparts, double* inv_norm, double* log_scale) {
+  const int b = blockIdx.x;
+  if (threadIdx.x == 0) {
+    double t = 0;
+    for (int i = 0; i < nparts; ++i) t += part[(long long)b * nparts + i];
+    const double nr = sqrt(t);
+    inv_norm[b] = nr > 0 ? 1.0 / nr : 1.0;
+    if (log_scale && nr > 0) log_scale[b] += log(nr);
+  }
+}
+
+__global__ void scale_kernel(double* x, long long n, const double* s) {
+  const int b = blockIdx.y;
+  double* xb = x + (long long)b * n;
+  const double f = s[b];
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    xb[i] *= f;
+}
+
+__global__ void copy_sigma_kernel(const double* sk, int k, int mp, int batch, double* out) {
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < batch * mp; t += gridDim.x * blockDim.x) {
+    const int b = t / mp, i = t % mp;
+    out[t] = sk[(long long)b * k + i];
+  }
+}
+
+__global__ void stats_kernel(const int* flags, const int* sweeps, int batch, int* acc) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    for (int b = 0; b < batch; ++b) {
+      if (flags) {
+        if (flags[b] & FLAG_THIRD_PASS) acc[0] += 1;
+        if (flags[b] & FLAG_NUMERIC) acc[2] += 1;
+      }
+      if (sweeps) {
+        const int s = sweeps[b];
+        acc[1] = max(acc[1], s < 0 ? -s : s);
+        if (s < 0) acc[3] += 1;
+      }
+    }
+  }
+}
+
+size_t small_lds_bytes(int k, bool cplx) { return (size_t)k * k * (cplx ? 16 : 8); }
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// host launchers
+
+void sketch(Ctx& ctx, void* out, bool f32, int64_t n, int64_t k, int batch, uint64_t seed,
+            uint64_t stream_id) {
+  const long long nk = (long long)n * k;
+  dim3 grid((unsigned)std::min<long long>(cdiv(nk, 256), 2048), (unsigned)batch);
+  if (f32)
+    sketch_kernel<float><<<grid, 256, 0, ctx.stream>>>((float*)out, nk, seed, stream_id);
+  else
+    sketch_kernel<double><<<grid, 256, 0, ctx.stream>>>((double*)out, nk, seed, stream_id);
+  HP_CHECK_HIP(hipGetLastError());
+}
+
+void gram(Ctx& ctx, bool cplx, const void* Y, int64_t n, int64_t k, int batch, double* G,
+          const int* /*active*/) {
+  GemmDesc d;
+  d.M = k;
+  d.N = k;
+  d.K = n;
+  d.Am.add(k, 1);   // A = Y^H: row i -> column i of Y
+  d.Ak.add(n, k);
+  d.Bk.add(n, k);   // B = Y
+  d.Bn.add(k, 1);
+  d.Cm.add(k, k);
+  d.Cn.add(k, 1);
+  GemmCall c;
+  c.A = Y;
+  c.B = Y;
+  c.C = G;
+  c.sA = c.sB = n * k;
+  c.sC = k * k;
+  c.batch = batch;
+  c.conjA = cplx;
+  gemm(ctx, cplx ? Prec::C128 : Prec::F64, d, c);
+}
+
+void chol_inv(Ctx& ctx, bool cplx, const double* G, int64_t n_rows, int64_t k, int batch, int pass,
+              double* Rinv, double* Racc, int* flags) {
+  const size_t lds = small_lds_bytes((int)k, cplx);
+  HP_REQUIRE(lds <= 160 * 1024 - 1024, HPEPS_ERR_UNSUPPORTED, "sketch width too large for LDS");
+  if (cplx) {
+    HP_CHECK_HIP(hipFuncSetAttribute((const void*)chol_inv_kernel<true>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    chol_inv_kernel<true><<<batch, kSmallThreads, lds, ctx.stream>>>(G, n_rows, (int)k, pass, Rinv, Racc, flags);
+  } else {
+    HP_CHECK_HIP(hipFuncSetAttribute((const void*)chol_inv_kernel<false>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    chol_inv_kernel<false><<<batch, kSmallThreads, lds, ctx.stream>>>(G, n_rows, (int)k, pass, Rinv, Racc, flags);
+  }
+  HP_CHECK_HIP(hipGetLastError());
+}
+
+void jacobi_svd(Ctx& ctx, bool cplx, const double* Racc, int64_t k, int batch, int max_sweeps,
+                double* Z, double* sigma, double* inv_sigma, double* inv_sigma1, double* log_scale,
+                int* stats) {
+  HP_REQUIRE(k <= 128, HPEPS_ERR_UNSUPPORTED, "small SVD supports k <= 128");
+  const int n = (int)((k + 1) / 2 * 2);
+  const size_t lds = (size_t)n * k * (cplx ? 16 : 8);
+  HP_REQUIRE(lds <= 160 * 1024 - 2048, HPEPS_ERR_UNSUPPORTED, "small SVD too large for LDS");
+  if (cplx) {
+    HP_CHECK_HIP(hipFuncSetAttribute((const void*)jacobi_kernel<true>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    jacobi_kernel<true><<<batch, kSmallThreads, lds, ctx.stream>>>(Racc, (int)k, max_sweeps, Z, sigma, inv_sigma,
+                                                                   inv_sigma1, log_scale, stats);
+  } else {
+    HP_CHECK_HIP(hipFuncSetAttribute((const void*)jacobi_kernel<false>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    jacobi_kernel<false><<<batch, kSmallThreads, lds, ctx.stream>>>(Racc, (int)k, max_sweeps, Z, sigma, inv_sigma,
+                                                                    inv_sigma1, log_scale, stats);
+  }
+  HP_CHECK_HIP(hipGetLastError());
+}
+
+void convert_f64_to_f32(Ctx& ctx, const double* in, float* out, int64_t n) {
+  if (n <= 0) return;
+  f64_to_f32_kernel<<<std::min<unsigned>(cdiv(n, 256), 4096), 256, 0, ctx.stream>>>(in, out, n);
+  HP_CHECK_HIP(hipGetLastError());
+}
+
+void fill_zero(Ctx& ctx, void* p, int64_t bytes) {
+  HP_CHECK_HIP(hipMemsetAsync(p, 0, bytes, ctx.stream));
+}
+
+void normalize(Ctx& ctx, bool cplx, void* x, int64_t n, int batch, double* log_scale) {
+  const int64_t nd = cplx ? 2 * n : n;  // a complex array is 2n doubles; same sum of squares
+  const int nparts = (int)std::min<int64_t>(cdiv(nd, 256 * 4), 256);
+  double* part = ctx.ws<double>((int64_t)nparts * batch);
+  double* inv = ctx.ws<double>(batch);
+  sumsq_partial_kernel<<<dim3(nparts, batch), 256, 0, ctx.stream>>>((const double*)x, nd, part);
+  norm_finalize_kernel<<<batch, 64, 0, ctx.stream>>>(part, nparts, inv, log_scale);
+  scale_kernel<<<dim3(std::min<unsigned>(cdiv(nd, 256), 1024), batch), 256, 0, ctx.stream>>>((double*)x, nd, inv);
+  HP_CHECK_HIP(hipGetLastError());
+}
+
+void copy_sigma(Ctx& ctx, const double* sigma_k, int64_t k, int64_t mp, int batch, double* out) {
+  copy_sigma_kernel<<<std::max<unsigned>(1, cdiv(batch * mp, 256)), 256, 0, ctx.stream>>>(sigma_k, (int)k, (int)mp,
+                                                                                          batch, out);
+  HP_CHECK_HIP(hipGetLastError());
+}
+
+void stats_reduce(Ctx& ctx, const int* flags, const int* sweeps, int batch, int* acc) {
+  stats_kernel<<<1, 64, 0, ctx.stream>>>(flags, sweeps, batch, acc);
+  HP_CHECK_HIP(hipGetLastError());
+}
+
+}  // namespace hp
