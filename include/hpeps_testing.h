@@ -1,0 +1,48 @@
+/*
+ * hpeps_testing.h -- kernel-level entry points of libhpeps used by the unit
+ * parity tests (each exposes one stage of the randomized SVD of Alg. 4 on
+ * its own).  Same conventions as hpeps.h: device pointers to dense
+ * row-major arrays, batch instances stored back to back, dtype HPEPS_F64 or
+ * HPEPS_C128 (complex as interleaved double pairs), work on the context's
+ * stream, status codes returned, nothing synchronised.
+ */
+#ifndef HPEPS_TESTING_H
+#define HPEPS_TESTING_H
+
+#include "hpeps.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* C[b] = op(A[b]) @ B[b] with A [M,K] (trans_a = 0) or [K,M] read as its
+ * (conjugate, for C128) transpose (trans_a = 1), B [K,N], C [M,N].  This is
+ * the gathered MFMA GEMM every contraction of the library goes through. */
+hpeps_status hpeps_test_gemm(hpeps_ctx* ctx, hpeps_dtype dtype, int64_t batch, int64_t M,
+                             int64_t N, int64_t K, int32_t trans_a, const void* A, const void* B,
+                             void* C);
+
+/* Orthonormal basis P [n,k] of range(Y) for Y [n,k] (CholeskyQR with the
+ * shifted first pass and the conditional third pass, the "orthogonalize" of
+ * Alg. 4).  Y is overwritten. */
+hpeps_status hpeps_test_orthogonalize(hpeps_ctx* ctx, hpeps_dtype dtype, int64_t batch, int64_t n,
+                                      int64_t k, void* Y, void* P);
+
+/* Small SVD stage: for the upper-triangular R [k,k] writes Z [k,k] (left
+ * singular vectors of R^H, columns sorted by descending singular value) and
+ * sigma [k] (double).  One-sided Jacobi. */
+hpeps_status hpeps_test_small_svd(hpeps_ctx* ctx, hpeps_dtype dtype, int64_t batch, int64_t k,
+                                  const void* R, void* Z, double* sigma);
+
+/* One application of the zip-up operator (see hpeps_einsumsvd_zipup): with
+ * adjoint = 0, Y [rows,k] = A X for X [cols,k]; with adjoint = 1,
+ * Y [cols,k] = A^* X for X [rows,k]. */
+hpeps_status hpeps_test_zip_apply(hpeps_ctx* ctx, hpeps_dtype dtype, int64_t batch,
+                                  const int64_t dims[9], const void* V, const void* S,
+                                  const void* T, const void* Bra, int64_t k, int32_t adjoint,
+                                  const void* X, void* Y);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HPEPS_TESTING_H */

@@ -47,12 +47,19 @@ def zipup_operator(V, S, T, B):
     _, Y, _, G, _ = B.shape
     Bc = B.conj()
 
+    # one pairwise contraction per tensor of the network (multi-operand
+    # einsum path searches can pick orders that are orders of magnitude slower)
     def fwd(Om):
-        return np.einsum("axXbhH,buUc,uyhgp,UYHGp,yYcgGj->axXj", V, S, T, Bc, Om, optimize=True)
+        W = np.einsum("uyhgp,yYcgGj->uhpYcGj", T, Om)
+        W = np.einsum("UYHGp,uhpYcGj->uhUHcj", Bc, W)
+        W = np.einsum("buUc,uhUHcj->bhHj", S, W)
+        return np.einsum("axXbhH,bhHj->axXj", V, W)
 
     def adj(P):
-        return np.einsum("axXbhH,buUc,uyhgp,UYHGp,axXj->yYcgGj",
-                         V.conj(), S.conj(), T.conj(), B, P, optimize=True)
+        W = np.einsum("axXbhH,axXj->bhHj", V.conj(), P)
+        W = np.einsum("buUc,bhHj->uhUHcj", S.conj(), W)
+        W = np.einsum("UYHGp,uhUHcj->uhpYcGj", B, W)
+        return np.einsum("uyhgp,uhpYcGj->yYcgGj", T.conj(), W)
 
     def explicit():
         return np.einsum("axXbhH,buUc,uyhgp,UYHGp->axXyYcgG", V, S, T, Bc, optimize=True)
@@ -72,11 +79,20 @@ def pair_operator(Bl, Br, T1, T2, T1b=None, T2b=None):
     sub = "auUb,bvVc,uxhp,UXHp,vyhq,VYHq"
 
     def fwd(Om):
-        return np.einsum(sub + ",yYcj->axXj", Bl, Br, t1, t1b, t2, t2b, Om, optimize=True)
+        W = np.einsum("vyhq,yYcj->vhqYcj", t2, Om)
+        W = np.einsum("VYHq,vhqYcj->vhVHcj", t2b, W)
+        W = np.einsum("bvVc,vhVHcj->bhHj", Br, W)
+        W = np.einsum("auUb,bhHj->auUhHj", Bl, W)
+        W = np.einsum("uxhp,auUhHj->axpUHj", t1, W)
+        return np.einsum("UXHp,axpUHj->axXj", t1b, W)
 
     def adj(P):
-        return np.einsum(sub + ",axXj->yYcj", Bl.conj(), Br.conj(), t1.conj(), t1b.conj(),
-                         t2.conj(), t2b.conj(), P, optimize=True)
+        W = np.einsum("UXHp,axXj->axpUHj", t1b.conj(), P)
+        W = np.einsum("uxhp,axpUHj->auUhHj", t1.conj(), W)
+        W = np.einsum("auUb,auUhHj->bhHj", Bl.conj(), W)
+        W = np.einsum("bvVc,bhHj->vhVHcj", Br.conj(), W)
+        W = np.einsum("VYHq,vhVHcj->vhqYcj", t2b.conj(), W)
+        return np.einsum("vyhq,vhqYcj->yYcj", t2.conj(), W)
 
     def explicit():
         return np.einsum(sub + "->axXyYc", Bl, Br, t1, t1b, t2, t2b, optimize=True)

@@ -79,6 +79,13 @@ _SIGS = {
     "hpeps_ite_run": (C.c_int, [_P, C.c_int32, C.c_int32]),
     "hpeps_ite_get_state": (C.c_int, [_P, _I64P, C.POINTER(C.c_void_p)]),
     "hpeps_ite_plan_destroy": (C.c_int, [_P]),
+    # include/hpeps_testing.h
+    "hpeps_test_gemm": (C.c_int, [_P, C.c_int, C.c_int64, C.c_int64, C.c_int64, C.c_int64,
+                                  C.c_int32, _P, _P, _P]),
+    "hpeps_test_orthogonalize": (C.c_int, [_P, C.c_int, C.c_int64, C.c_int64, C.c_int64, _P, _P]),
+    "hpeps_test_small_svd": (C.c_int, [_P, C.c_int, C.c_int64, C.c_int64, _P, _P, _P]),
+    "hpeps_test_zip_apply": (C.c_int, [_P, C.c_int, C.c_int64, _I64P, _P, _P, _P, _P, C.c_int64,
+                                       C.c_int32, _P, _P]),
 }
 
 

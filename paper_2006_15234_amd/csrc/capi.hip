@@ -5,10 +5,6 @@
 #include "esvd.h"
 #include "peps.h"
 
-struct hpeps_ctx {
-  hp::Ctx* impl;
-};
-
 namespace {
 
 template <class F>

@@ -316,7 +316,7 @@ void zip_esvd(Ctx& ctx, bool cplx, const ZipDims& z, const ZipOperands& op64, in
     sketch(ctx, xin32, true, cols, k, batch, o.seed, o.stream_id);
     zip_apply(ctx, prec, z, op, batch, k, false, xin32, Xr0, true, w);
   } else {
-    sketch(ctx, Xc0, false, cols, k, batch, o.seed, o.stream_id);
+    sketch(ctx, Xc0, false, cols, k, batch, o.seed, o.stream_id, cplx);
     zip_apply(ctx, prec, z, op, batch, k, false, Xc0, Xr0, true, w);
   }
   orthogonalize(ctx, cplx, Xr0, Xr1, rows, k, batch, ow);          // P in Xr1

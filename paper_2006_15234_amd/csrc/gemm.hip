@@ -276,14 +276,16 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
     }
   }
 
-  // epilogue: lane holds rows 4*lk + r, column li of each 16x16 tile
+  // epilogue: accumulator register r of a lane holds column li of each 16x16
+  // tile and row lk + 4 r (f64 MFMA) or 4 lk + r (f32 MFMA) -- measured layouts
 #pragma unroll
   for (int i = 0; i < TM; ++i)
 #pragma unroll
     for (int j = 0; j < TN; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int m = m0 + wm * TM * 16 + i * 16 + lk * 4 + r;
+        const int row = (sizeof(TC) == 8) ? (lk + 4 * r) : (lk * 4 + r);
+        const int m = m0 + wm * TM * 16 + i * 16 + row;
         const int n = n0 + wn * TN * 16 + j * 16 + li;
         if (m >= g.M || n >= g.N) continue;
         double re, im = 0.0;

@@ -111,7 +111,7 @@ void jacobi_svd(Ctx& ctx, bool cplx, const double* Racc, int64_t k, int batch, i
 // Sketch generator (see hpeps.h); writes n*k values per batch instance,
 // instance b uses stream_id + b.  out is double or float (f32).
 void sketch(Ctx& ctx, void* out, bool f32, int64_t n, int64_t k, int batch, uint64_t seed,
-            uint64_t stream_id);
+            uint64_t stream_id, bool cplx_out = false);
 // Elementwise conversion and scaling helpers.
 void convert_f64_to_f32(Ctx& ctx, const double* in, float* out, int64_t n);
 void fill_zero(Ctx& ctx, void* p, int64_t bytes);
@@ -164,3 +164,8 @@ class Ctx {
 inline unsigned cdiv(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
 
 }  // namespace hp
+
+// the opaque handle of the ABI
+struct hpeps_ctx {
+  hp::Ctx* impl;
+};

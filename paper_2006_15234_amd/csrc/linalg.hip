@@ -76,17 +76,20 @@ __device__ __forceinline__ uint64_t mix64(uint64_t z) {
   return z;
 }
 
+// stride = 2 writes the values as the real parts of a complex array (the
+// imaginary parts are set to zero): the sketch is real for complex operators.
 template <class TO>
-__global__ void sketch_kernel(TO* out, long long nk, uint64_t seed, uint64_t stream_id) {
+__global__ void sketch_kernel(TO* out, long long nk, uint64_t seed, uint64_t stream_id, int stride) {
   const int b = blockIdx.y;
   const uint64_t base = mix64(mix64(seed) + stream_id + (uint64_t)b);
-  TO* o = out + (long long)b * nk;
+  TO* o = out + (long long)b * nk * stride;
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < nk;
        i += (long long)gridDim.x * blockDim.x) {
     const uint64_t h = mix64(base + (uint64_t)(i + 1) * 0x9E3779B97F4A7C15ull);
     // (h >> 11) < 2^53 converts exactly; the affine map below is exact too.
     const double v = 2.0 * (double)(h >> 11) * 0x1p-53 - 1.0;
-    o[i] = (TO)v;
+    o[i * stride] = (TO)v;
+    if (stride == 2) o[i * 2 + 1] = (TO)0;
   }
 }
 
@@ -441,13 +444,14 @@ size_t small_lds_bytes(int k, bool cplx) { return (size_t)k * k * (cplx ? 16 : 8
 // host launchers
 
 void sketch(Ctx& ctx, void* out, bool f32, int64_t n, int64_t k, int batch, uint64_t seed,
-            uint64_t stream_id) {
+            uint64_t stream_id, bool cplx_out) {
   const long long nk = (long long)n * k;
   dim3 grid((unsigned)std::min<long long>(cdiv(nk, 256), 2048), (unsigned)batch);
+  HP_REQUIRE(!(f32 && cplx_out), HPEPS_ERR_DTYPE, "complex sketches are FP64");
   if (f32)
-    sketch_kernel<float><<<grid, 256, 0, ctx.stream>>>((float*)out, nk, seed, stream_id);
+    sketch_kernel<float><<<grid, 256, 0, ctx.stream>>>((float*)out, nk, seed, stream_id, 1);
   else
-    sketch_kernel<double><<<grid, 256, 0, ctx.stream>>>((double*)out, nk, seed, stream_id);
+    sketch_kernel<double><<<grid, 256, 0, ctx.stream>>>((double*)out, nk, seed, stream_id, cplx_out ? 2 : 1);
   HP_CHECK_HIP(hipGetLastError());
 }
 

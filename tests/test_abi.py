@@ -7,14 +7,17 @@ import re
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "hpeps.h")
+INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(ROOT, "paper_2006_15234_amd", "libhpeps.so")
 
 
 def declared():
-    src = open(HEADER).read()
-    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(hpeps_[a-z0-9_]+)\s*\(", src)))
+    names = set()
+    for f in sorted(os.listdir(INCLUDE)):
+        if f.endswith(".h"):
+            src = re.sub(r"/\*.*?\*/", "", open(os.path.join(INCLUDE, f)).read(), flags=re.S)
+            names |= set(re.findall(r"\b(hpeps_[a-z0-9_]+)\s*\(", src))
+    return sorted(names)
 
 
 def test_header_declares_entry_points():

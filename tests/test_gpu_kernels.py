@@ -1,0 +1,153 @@
+"""Kernel-level GPU parity: the gathered MFMA GEMM, CholeskyQR
+orthogonalization, the one-sided Jacobi small SVD and one zip-up operator
+application, each against plain CPU arithmetic (numpy / the oracle)."""
+import ctypes as C
+
+import numpy as np
+import pytest
+
+from oracle.network import zipup_operator
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+hp = pytest.importorskip("paper_2006_15234_amd")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    return hp.Context(0)
+
+
+def _rand(rng, shape, cplx):
+    x = rng.standard_normal(shape)
+    if cplx:
+        x = x + 1j * rng.standard_normal(shape)
+    return x
+
+
+def _dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def _p(t):
+    return C.c_void_p(t.data_ptr())
+
+
+@pytest.mark.parametrize("cplx", [False, True])
+@pytest.mark.parametrize("shape", [(1, 1, 1), (16, 16, 4), (17, 33, 5), (64, 64, 64), (130, 47, 300),
+                                   (44, 44, 1296), (3, 200, 7), (1296, 44, 44)])
+@pytest.mark.parametrize("trans", [0, 1])
+def test_gemm(ctx, cplx, shape, trans):
+    M, N, K = shape
+    rng = np.random.default_rng(M * 1000 + N * 10 + K)
+    B = 2
+    A = _rand(rng, (B, K, M) if trans else (B, M, K), cplx)
+    Bm = _rand(rng, (B, K, N), cplx)
+    dA, dB = _dev(A), _dev(Bm)
+    dC = torch.zeros((B, M, N), dtype=dA.dtype, device="cuda")
+    ctx.sync_stream()
+    ctx.check(ctx.lib.hpeps_test_gemm(ctx.h, hp.C128 if cplx else hp.F64, B, M, N, K, trans,
+                                      _p(dA), _p(dB), _p(dC)))
+    out = dC.cpu().numpy()
+    for b in range(B):
+        opA = A[b].conj().T if trans else A[b]
+        ref = opA @ Bm[b]
+        assert np.max(np.abs(out[b] - ref)) <= 1e-13 * max(1.0, np.abs(ref).max()) * np.sqrt(K)
+
+
+@pytest.mark.parametrize("cplx", [False, True])
+@pytest.mark.parametrize("nk", [(8, 8), (100, 7), (1296, 44), (5000, 108), (300, 128)])
+def test_orthogonalize(ctx, cplx, nk):
+    n, k = nk
+    if cplx and k > 88:
+        pytest.skip("complex small factorizations are limited to k <= 88")
+    rng = np.random.default_rng(n + k)
+    B = 2
+    Y = _rand(rng, (B, n, k), cplx)
+    dY = _dev(Y)
+    dP = torch.zeros_like(dY)
+    ctx.sync_stream()
+    ctx.check(ctx.lib.hpeps_test_orthogonalize(ctx.h, hp.C128 if cplx else hp.F64, B, n, k,
+                                               _p(dY), _p(dP)))
+    P = dP.cpu().numpy()
+    for b in range(B):
+        assert np.max(np.abs(P[b].conj().T @ P[b] - np.eye(k))) < 1e-13
+        # same range: the projector onto range(Y) fixes Y
+        Q = np.linalg.qr(Y[b])[0]
+        assert np.max(np.abs(P[b] @ (P[b].conj().T @ Q) - Q)) < 1e-12
+
+
+def test_orthogonalize_ill_conditioned(ctx):
+    """kappa ~ 1e12: the shifted first pass plus a third pass still orthonormalize."""
+    rng = np.random.default_rng(0)
+    n, k = 2000, 40
+    U = np.linalg.qr(rng.standard_normal((n, k)))[0]
+    V = np.linalg.qr(rng.standard_normal((k, k)))[0]
+    Y = (U * np.logspace(0, -12, k)) @ V.T
+    dY = _dev(Y[None])
+    dP = torch.zeros_like(dY)
+    ctx.sync_stream()
+    ctx.check(ctx.lib.hpeps_test_orthogonalize(ctx.h, hp.F64, 1, n, k, _p(dY), _p(dP)))
+    P = dP.cpu().numpy()[0]
+    info = hp.get_info(ctx)
+    assert info["orth_extra_passes"] >= 1
+    assert np.max(np.abs(P.T @ P - np.eye(k))) < 1e-12
+    # leading directions (well above the shift) are reproduced
+    lead = U[:, :20]
+    assert np.max(np.abs(P @ (P.T @ lead) - lead)) < 1e-8
+
+
+@pytest.mark.parametrize("cplx", [False, True])
+@pytest.mark.parametrize("k", [1, 2, 7, 44, 108])
+def test_small_svd(ctx, cplx, k):
+    if cplx and k > 88:
+        pytest.skip("complex small factorizations are limited to k <= 88")
+    rng = np.random.default_rng(k)
+    B = 2
+    R = np.triu(_rand(rng, (B, k, k), cplx))
+    dR = _dev(R)
+    dZ = torch.zeros_like(dR)
+    ds = torch.zeros((B, k), dtype=torch.float64, device="cuda")
+    ctx.sync_stream()
+    ctx.check(ctx.lib.hpeps_test_small_svd(ctx.h, hp.C128 if cplx else hp.F64, B, k, _p(dR), _p(dZ),
+                                           _p(ds)))
+    Z, s = dZ.cpu().numpy(), ds.cpu().numpy()
+    for b in range(B):
+        K = R[b].conj().T
+        ref = np.linalg.svd(K, compute_uv=False)
+        assert np.max(np.abs(s[b] - ref)) < 1e-13 * ref[0] * k
+        assert np.max(np.abs(Z[b].conj().T @ Z[b] - np.eye(k))) < 1e-12
+        # Z spans the left singular subspaces: Z^H K K^H Z = diag(s^2)
+        M = Z[b].conj().T @ K @ K.conj().T @ Z[b]
+        assert np.max(np.abs(M - np.diag(s[b] ** 2))) < 1e-12 * ref[0] ** 2 * k
+
+
+@pytest.mark.parametrize("cplx", [False, True])
+@pytest.mark.parametrize("dims", [(1, 2, 1, 2, 2, 3, 2, 2, 2), (3, 2, 2, 3, 2, 4, 2, 1, 2),
+                                  (5, 3, 4, 2, 3, 5, 3, 2, 2)])
+def test_zip_apply(ctx, cplx, dims):
+    a, x, b, h, u, c, y, g, d = dims
+    rng = np.random.default_rng(sum(dims))
+    V = _rand(rng, (a, x, x, b, h, h), cplx)
+    S = _rand(rng, (b, u, u, c), cplx)
+    T = _rand(rng, (u, y, h, g, d), cplx)
+    Bra = _rand(rng, (u, y, h, g, d), cplx)
+    op = zipup_operator(V, S, T, Bra)
+    k = 5
+    X = _rand(rng, (op.n_cols, k), cplx)
+    P = _rand(rng, (op.n_rows, k), cplx)
+    dd = (C.c_int64 * 9)(*dims)
+    dt = hp.C128 if cplx else hp.F64
+    tV, tS, tT, tB = _dev(V[None]), _dev(S[None]), _dev(T[None]), _dev(Bra[None])
+    dX, dP = _dev(X[None]), _dev(P[None])
+    dY = torch.zeros((1, op.n_rows, k), dtype=dX.dtype, device="cuda")
+    dZ = torch.zeros((1, op.n_cols, k), dtype=dX.dtype, device="cuda")
+    ctx.sync_stream()
+    ctx.check(ctx.lib.hpeps_test_zip_apply(ctx.h, dt, 1, dd, _p(tV), _p(tS), _p(tT), _p(tB), k, 0,
+                                           _p(dX), _p(dY)))
+    ctx.check(ctx.lib.hpeps_test_zip_apply(ctx.h, dt, 1, dd, _p(tV), _p(tS), _p(tT), _p(tB), k, 1,
+                                           _p(dP), _p(dZ)))
+    Y, Z = dY.cpu().numpy()[0], dZ.cpu().numpy()[0]
+    ry, rz = op.apply(X), op.apply_adj(P)
+    assert np.max(np.abs(Y - ry)) < 1e-12 * np.abs(ry).max()
+    assert np.max(np.abs(Z - rz)) < 1e-12 * np.abs(rz).max()
