@@ -122,6 +122,28 @@ hpeps_status hpeps_set_workspace_limit(hpeps_ctx* ctx, int64_t bytes);
  * last call of hpeps_get_info (or creation) to *info, then clears them. */
 hpeps_status hpeps_get_info(hpeps_ctx* ctx, hpeps_esvd_info* info);
 
+/* ---- live kernel timing ---------------------------------------------------
+ * While profiling is on, every kernel launch of the context whose class name
+ * contains `filter` (all launches when filter is NULL or "") is bracketed by
+ * two HIP events on the context stream.  Class names: "gemm_<prec>_<BM>x<BN>"
+ * for the gathered MFMA GEMM (prec f64, c128, f32, f32o32 for FP32 output),
+ * "chol_inv", "jacobi_svd".  hpeps_profile_read synchronises the stream,
+ * writes up to max_entries aggregates (launch count, summed kernel time in
+ * ms, summed algorithmic flops -- 2 M N K per product, times 4 for complex --
+ * and summed algorithmic operand bytes) and clears the records; profiling
+ * stays on until hpeps_profile_stop. */
+typedef struct {
+  char name[64];
+  int64_t launches;
+  double ms;
+  double flops;
+  double bytes;
+} hpeps_profile_entry;
+hpeps_status hpeps_profile_start(hpeps_ctx* ctx, const char* filter);
+hpeps_status hpeps_profile_stop(hpeps_ctx* ctx);
+hpeps_status hpeps_profile_read(hpeps_ctx* ctx, int32_t max_entries, hpeps_profile_entry* out,
+                                int32_t* n_out);
+
 /* ---- sketch -------------------------------------------------------------
  * Writes the sketch Omega that an einsumsvd with (seed, stream_id) draws:
  * batch blocks of n*k values (block b uses stream_id + b), element i of a

@@ -60,6 +60,9 @@ _SIGS = {
     "hpeps_last_error": (C.c_char_p, [_P]),
     "hpeps_set_workspace_limit": (C.c_int, [_P, C.c_int64]),
     "hpeps_get_info": (C.c_int, [_P, C.POINTER(EsvdInfo)]),
+    "hpeps_profile_start": (C.c_int, [_P, C.c_char_p]),
+    "hpeps_profile_stop": (C.c_int, [_P]),
+    "hpeps_profile_read": (C.c_int, [_P, C.c_int32, C.c_void_p, C.POINTER(C.c_int32)]),
     "hpeps_sketch": (C.c_int, [_P, C.c_int, C.c_int64, C.c_int64, C.c_int64, C.c_uint64,
                                C.c_uint64, _P]),
     "hpeps_einsumsvd_zipup": (C.c_int, [_P, C.c_int64, C.c_int, _I64P, _P, _P, _P, _P,

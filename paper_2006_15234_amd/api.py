@@ -104,6 +104,30 @@ def sketch(ctx, n, k, batch=1, seed=0, stream_id=0, precision="f64", device="cud
     return out
 
 
+class ProfileEntry(C.Structure):
+    _fields_ = [("name", C.c_char * 64), ("launches", C.c_int64), ("ms", C.c_double),
+                ("flops", C.c_double), ("bytes", C.c_double)]
+
+
+def profile_start(ctx, filter=None):
+    """Start live per-kernel timing with HIP events (see hpeps_profile_start)."""
+    ctx.check(ctx.lib.hpeps_profile_start(ctx.h, filter.encode() if filter else None))
+
+
+def profile_stop(ctx):
+    ctx.check(ctx.lib.hpeps_profile_stop(ctx.h))
+
+
+def profile_read(ctx):
+    """Synchronises and returns {class: dict(launches, ms, flops, bytes)}; clears."""
+    buf = (ProfileEntry * 128)()
+    n = C.c_int32()
+    ctx.sync_stream()
+    ctx.check(ctx.lib.hpeps_profile_read(ctx.h, 128, C.cast(buf, C.c_void_p), C.byref(n)))
+    return {buf[i].name.decode(): dict(launches=buf[i].launches, ms=buf[i].ms, flops=buf[i].flops,
+                                       bytes=buf[i].bytes) for i in range(min(n.value, 128))}
+
+
 def get_info(ctx):
     info = EsvdInfo()
     ctx.check(ctx.lib.hpeps_get_info(ctx.h, C.byref(info)))

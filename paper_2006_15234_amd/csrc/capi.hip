@@ -108,6 +108,41 @@ hpeps_status hpeps_get_info(hpeps_ctx* ctx, hpeps_esvd_info* info) {
   });
 }
 
+hpeps_status hpeps_profile_start(hpeps_ctx* ctx, const char* filter) {
+  if (!ctx) return HPEPS_ERR_INVALID_ARG;
+  ctx->impl->prof_on = true;
+  ctx->impl->prof_filter = filter ? filter : "";
+  return HPEPS_OK;
+}
+
+hpeps_status hpeps_profile_stop(hpeps_ctx* ctx) {
+  if (!ctx) return HPEPS_ERR_INVALID_ARG;
+  ctx->impl->prof_on = false;
+  return HPEPS_OK;
+}
+
+hpeps_status hpeps_profile_read(hpeps_ctx* ctx, int32_t max_entries, hpeps_profile_entry* out,
+                                int32_t* n_out) {
+  if (!ctx || !n_out || (max_entries > 0 && !out)) return HPEPS_ERR_INVALID_ARG;
+  return guard(ctx, [&] {
+    auto agg = ctx->impl->prof_read();
+    int32_t n = 0;
+    for (auto& a : agg) {
+      if (a.launches == 0) continue;
+      if (n < max_entries) {
+        std::memset(out[n].name, 0, sizeof(out[n].name));
+        std::strncpy(out[n].name, a.name.c_str(), sizeof(out[n].name) - 1);
+        out[n].launches = a.launches;
+        out[n].ms = a.ms;
+        out[n].flops = a.flops;
+        out[n].bytes = a.bytes;
+      }
+      ++n;
+    }
+    *n_out = n;
+  });
+}
+
 hpeps_status hpeps_sketch(hpeps_ctx* ctx, hpeps_dtype dtype, int64_t n, int64_t k, int64_t batch,
                           uint64_t seed, uint64_t stream_id, void* out) {
   if (!ctx) return HPEPS_ERR_INVALID_ARG;

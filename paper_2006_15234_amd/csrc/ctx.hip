@@ -42,7 +42,61 @@ Ctx::Ctx(int dev) : device(dev) {
   HP_CHECK_HIP(hipMemset(stats_dev, 0, 8 * sizeof(int)));
 }
 
+hipEvent_t Ctx::next_event() {
+  if (ev_used_ == ev_pool_.size()) {
+    hipEvent_t e;
+    HP_CHECK_HIP(hipEventCreate(&e));
+    ev_pool_.push_back(e);
+  }
+  return ev_pool_[ev_used_++];
+}
+
+int Ctx::prof_begin(const std::string& cls) {
+  if (!prof_on) return -1;
+  if (!prof_filter.empty() && cls.find(prof_filter) == std::string::npos) return -1;
+  auto it = prof_ids_.find(cls);
+  int id;
+  if (it == prof_ids_.end()) {
+    id = (int)prof_names_.size();
+    prof_names_.push_back(cls);
+    prof_ids_[cls] = id;
+  } else {
+    id = it->second;
+  }
+  ProfRec r{id, next_event(), next_event(), 0, 0};
+  HP_CHECK_HIP(hipEventRecord(r.a, stream));
+  prof_recs_.push_back(r);
+  return (int)prof_recs_.size() - 1;
+}
+
+void Ctx::prof_end(int rec, double flops, double bytes) {
+  if (rec < 0) return;
+  ProfRec& r = prof_recs_[rec];
+  HP_CHECK_HIP(hipEventRecord(r.b, stream));
+  r.flops = flops;
+  r.bytes = bytes;
+}
+
+std::vector<Ctx::ProfAgg> Ctx::prof_read() {
+  HP_CHECK_HIP(hipStreamSynchronize(stream));
+  std::vector<ProfAgg> agg(prof_names_.size());
+  for (size_t i = 0; i < agg.size(); ++i) agg[i].name = prof_names_[i];
+  for (auto& r : prof_recs_) {
+    float ms = 0;
+    HP_CHECK_HIP(hipEventElapsedTime(&ms, r.a, r.b));
+    ProfAgg& a = agg[r.cls];
+    a.launches += 1;
+    a.ms += ms;
+    a.flops += r.flops;
+    a.bytes += r.bytes;
+  }
+  prof_recs_.clear();
+  ev_used_ = 0;
+  return agg;
+}
+
 Ctx::~Ctx() {
+  for (auto e : ev_pool_) (void)hipEventDestroy(e);
   (void)hipDeviceSynchronize();
   for (auto& kv : tables_) (void)hipFree(kv.second);
   for (auto& c : chunks_) (void)hipFree(c.base);

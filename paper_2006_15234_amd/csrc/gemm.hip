@@ -476,6 +476,14 @@ void gemm(Ctx& ctx, Prec prec, const GemmDesc& d, const GemmCall& c) {
   const unsigned gx = ((unsigned)a.ntotal + 7) / 8 * 8;
   dim3 grid(gx, (unsigned)(c.batch * ksplit));
   hipStream_t st = ctx.stream;
+  int rec = -1;
+  if (ctx.prof_on) {
+    static const char* pn[] = {"f64", "c128", "f32"};
+    const std::string name = std::string("gemm_") + pn[(int)prec] +
+                             (prec == Prec::F32 && !c.out_f64 ? "o32" : "") + "_" +
+                             std::to_string(cf.BM()) + "x" + std::to_string(cf.BN());
+    rec = ctx.prof_begin(name);
+  }
   switch (prec) {
     case Prec::F64:
       launch_cfg<double, false, double, double>(ci, grid, st, a);
@@ -498,6 +506,14 @@ void gemm(Ctx& ctx, Prec prec, const GemmDesc& d, const GemmCall& c) {
       break;
   }
   HP_CHECK_HIP(hipGetLastError());
+  if (rec >= 0) {
+    // algorithmic work of the product: 2 M N K per instance (complex: 4 real
+    // products per multiply-add); bytes: each operand element once
+    const double mnk = 2.0 * (double)d.M * (double)d.N * (double)d.K * c.batch * (cplx ? 4 : 1);
+    const double elt = prec == Prec::F32 ? 4.0 : (cplx ? 16.0 : 8.0);
+    const double byt = ((double)d.M * d.K + (double)d.K * d.N + (double)d.M * d.N) * c.batch * elt;
+    ctx.prof_end(rec, mnk, byt);
+  }
 }
 
 }  // namespace hp

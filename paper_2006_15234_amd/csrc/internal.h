@@ -149,6 +149,35 @@ class Ctx {
   int* stats_dev = nullptr;
   int64_t last_rank = 0, last_k = 0;
 
+  // Live kernel timing with HIP events on the context stream.  While
+  // profiling is on, launches whose class name contains `prof_filter` (all
+  // when empty) are bracketed by two events; prof_read aggregates per class.
+  bool prof_on = false;
+  std::string prof_filter;
+  int prof_begin(const std::string& cls);            // -1 when not recorded
+  void prof_end(int rec, double flops, double bytes);
+  struct ProfAgg {
+    std::string name;
+    int64_t launches = 0;
+    double ms = 0, flops = 0, bytes = 0;
+  };
+  std::vector<ProfAgg> prof_read();                  // synchronises, clears
+
+ private:
+  struct ProfRec {
+    int cls;
+    hipEvent_t a, b;
+    double flops, bytes;
+  };
+  std::vector<ProfRec> prof_recs_;
+  std::vector<hipEvent_t> ev_pool_;
+  size_t ev_used_ = 0;
+  std::vector<std::string> prof_names_;
+  std::map<std::string, int> prof_ids_;
+  hipEvent_t next_event();
+
+ public:
+
  private:
   std::map<std::string, int*> tables_;
   struct Chunk {

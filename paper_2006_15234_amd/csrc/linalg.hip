@@ -482,6 +482,7 @@ void chol_inv(Ctx& ctx, bool cplx, const double* G, int64_t n_rows, int64_t k, i
               double* Rinv, double* Racc, int* flags) {
   const size_t lds = small_lds_bytes((int)k, cplx);
   HP_REQUIRE(lds <= 160 * 1024 - 1024, HPEPS_ERR_UNSUPPORTED, "sketch width too large for LDS");
+  const int rec = ctx.prof_begin("chol_inv");
   if (cplx) {
     HP_CHECK_HIP(hipFuncSetAttribute((const void*)chol_inv_kernel<true>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
@@ -492,6 +493,7 @@ void chol_inv(Ctx& ctx, bool cplx, const double* G, int64_t n_rows, int64_t k, i
     chol_inv_kernel<false><<<batch, kSmallThreads, lds, ctx.stream>>>(G, n_rows, (int)k, pass, Rinv, Racc, flags);
   }
   HP_CHECK_HIP(hipGetLastError());
+  ctx.prof_end(rec, (double)batch * k * k * k / 3.0 * (cplx ? 4 : 1), 0.0);
 }
 
 void jacobi_svd(Ctx& ctx, bool cplx, const double* Racc, int64_t k, int batch, int max_sweeps,
@@ -501,6 +503,17 @@ void jacobi_svd(Ctx& ctx, bool cplx, const double* Racc, int64_t k, int batch, i
   const int n = (int)((k + 1) / 2 * 2);
   const size_t lds = (size_t)n * k * (cplx ? 16 : 8);
   HP_REQUIRE(lds <= 160 * 1024 - 2048, HPEPS_ERR_UNSUPPORTED, "small SVD too large for LDS");
+  const int rec = ctx.prof_begin("jacobi_svd");
+  struct EndRec {
+    Ctx& c;
+    int r;
+    ~EndRec() {
+      try {
+        c.prof_end(r, 0.0, 0.0);
+      } catch (...) {
+      }
+    }
+  } end_rec{ctx, rec};
   if (cplx) {
     HP_CHECK_HIP(hipFuncSetAttribute((const void*)jacobi_kernel<true>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
