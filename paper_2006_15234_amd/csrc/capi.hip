@@ -174,7 +174,9 @@ hpeps_status hpeps_einsumsvd_zipup(hpeps_ctx* ctx, int64_t batch, hpeps_dtype dt
     hp::ZipOperands op{V, S, T, Bra ? Bra : T};
     hp::Ctx& c = *ctx->impl;
     c.ws_reset();
-    hp::zip_esvd(c, cplx, z, op, (int)batch, *opts, absorb, U, sigma, R, log_scale);
+    const int64_t k = hp::sketch_width(opts->rank, opts->oversample, z.rows(), z.cols());
+    hp::zip_esvd(c, cplx, z, hp::ZipLayout::row_major(z), op, (int)batch, *opts, absorb,
+                 hp::ZipOut::row_major(z, std::min<int64_t>(opts->rank, k)), U, sigma, R, log_scale);
   });
 }
 
@@ -199,11 +201,13 @@ hpeps_status hpeps_einsumsvd_pair(hpeps_ctx* ctx, int64_t batch, hpeps_dtype dty
     hp::CarryDims cd;
     cd.a = m; cd.u = D; cd.b = m; cd.x = D; cd.h = D; cd.d = d;
     double* V = c.ws<double>(batch * m * D * D * m * D * D * es);
-    hp::form_carry(c, cplx, cd, Bl, T1, T1, V, (int)batch);
+    hp::form_carry(c, cplx, cd, hp::CarryLayout::row_major(cd), Bl, T1, T1, V, (int)batch);
     hp::ZipDims z;
     z.a = m; z.x = D; z.b = m; z.h = D; z.u = D; z.c = m; z.y = D; z.g = 1; z.d = d;
     hp::ZipOperands op{V, Br, T2, T2};
-    hp::zip_esvd(c, cplx, z, op, (int)batch, *opts, absorb, U, sigma, R, nullptr);
+    const int64_t k = hp::sketch_width(opts->rank, opts->oversample, z.rows(), z.cols());
+    hp::zip_esvd(c, cplx, z, hp::ZipLayout::row_major(z), op, (int)batch, *opts, absorb,
+                 hp::ZipOut::row_major(z, std::min<int64_t>(opts->rank, k)), U, sigma, R, nullptr);
   });
 }
 

@@ -15,6 +15,18 @@ struct ZipDims {
   int64_t t_size() const;
 };
 
+// Element strides of every leg of the four operands (any permutation of the
+// stored legs: mirrored sweeps are stride permutations) and the per-instance
+// extents used for bounds checks and batch strides.
+struct ZipLayout {
+  int64_t V[6];  // a, x, X, b, h, H
+  int64_t S[4];  // b, u, U, c
+  int64_t T[5];  // u, y, h, g, p
+  int64_t B[5];  // U, Y, H, G, p
+  int64_t nV = 0, nS = 0, nT = 0, nB = 0;
+  static ZipLayout row_major(const ZipDims& z);
+};
+
 struct ZipOperands {
   const void* V = nullptr;
   const void* S = nullptr;
@@ -35,11 +47,20 @@ struct OrthWork {
   int* flags = nullptr;
 };
 
+// Output placement of the two factors: U[(a,x,X), i] at Urows + Ucol(i),
+// R[i, (y,Y,c,g,G)] at Rrow(i) + Rcols; extents per instance.
+struct ZipOut {
+  IndexMap Urows, Ucol, Rrow, Rcols;
+  int64_t nU = 0, nR = 0;
+  static ZipOut row_major(const ZipDims& z, int64_t mp);
+};
+
 // A X (adjoint = false, X: cols x k) or A^* X (X: rows x k) for the zip-up
 // operator; Y is written as double when y_f64 (F32 applies), else in the
 // apply precision.
-void zip_apply(Ctx& ctx, Prec prec, const ZipDims& z, const ZipOperands& op, int batch, int64_t k,
-               bool adjoint, const void* X, void* Y, bool y_f64, const ZipWork& w);
+void zip_apply(Ctx& ctx, Prec prec, const ZipDims& z, const ZipLayout& L, const ZipOperands& op,
+               int batch, int64_t k, bool adjoint, const void* X, void* Y, bool y_f64,
+               const ZipWork& w);
 
 void orthogonalize(Ctx& ctx, bool cplx, double* Y, double* P, int64_t n, int64_t k, int batch,
                    const OrthWork& w);
@@ -47,16 +68,33 @@ void orthogonalize(Ctx& ctx, bool cplx, double* Y, double* P, int64_t n, int64_t
 int64_t sketch_width(int64_t m, int64_t p, int64_t rows, int64_t cols);
 
 // Randomized einsumsvd (Alg. 4) of the zip-up operator; operands are FP64 /
-// complex128 device arrays (batch-strided by their per-instance sizes).
-void zip_esvd(Ctx& ctx, bool cplx, const ZipDims& z, const ZipOperands& op, int batch,
-              const hpeps_esvd_opts& o, hpeps_absorb absorb, void* U, double* sigma, void* R,
-              double* log_scale);
+// complex128 device arrays (instances back to back with the extents of L).
+void zip_esvd(Ctx& ctx, bool cplx, const ZipDims& z, const ZipLayout& L, const ZipOperands& op,
+              int batch, const hpeps_esvd_opts& o, hpeps_absorb absorb, const ZipOut& out,
+              void* U, double* sigma, void* R, double* log_scale);
 
-// Exact carry V[a,x,X,b,h,H] = sum_{u,U,p} L[a,u,U,b] T[u,x,1,h,p] conj(Bra[U,X,1,H,p]).
+// Exact carry V[a,x,X,b,h,H] = sum_{u,U,p} L[a,u,U,b] T[u,x,h,p] conj(Bra[U,X,H,p])
+// (the left leg of T and Bra has dim 1 and is skipped); V is row-major.
 struct CarryDims {
   int64_t a = 1, u = 1, b = 1, x = 1, h = 1, d = 1;
 };
-void form_carry(Ctx& ctx, bool cplx, const CarryDims& cd, const void* L, const void* T,
-                const void* Bra, void* V, int batch);
+struct CarryLayout {
+  int64_t L[4];  // a, u, U, b
+  int64_t T[4];  // u, x, h, p
+  int64_t B[4];  // U, X, H, p
+  int64_t nL = 0, nT = 0, nB = 0;
+  static CarryLayout row_major(const CarryDims& c);  // T, Bra stored [u,x,1,h,p]
+};
+void form_carry(Ctx& ctx, bool cplx, const CarryDims& cd, const CarryLayout& cl, const void* L,
+                const void* T, const void* Bra, void* V, int batch);
+
+// workspace scope: everything allocated after mark() is reused after release
+struct WsScope {
+  Ctx& c;
+  int chunk;
+  int64_t off;
+  explicit WsScope(Ctx& ctx);
+  ~WsScope();
+};
 
 }  // namespace hp

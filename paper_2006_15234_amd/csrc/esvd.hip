@@ -16,42 +16,58 @@
 
 namespace hp {
 
-namespace {
-
-// strides of the per-instance tensors (row-major in the documented leg order)
-struct ZipStrides {
-  // V[a,x,X,b,h,H]
-  int64_t Va, Vx, VX, Vb, Vh, VH;
-  // S[b,u,U,c]
-  int64_t Sb, Su, SU, Sc;
-  // T / Bra [u,y,h,g,p]
-  int64_t Tu, Ty, Th, Tg, Tp;
-  explicit ZipStrides(const ZipDims& d) {
-    VH = 1; Vh = d.h; Vb = d.h * d.h; VX = d.b * Vb; Vx = d.x * VX; Va = d.x * Vx;
-    Sc = 1; SU = d.c; Su = d.u * SU; Sb = d.u * Su;
-    Tp = 1; Tg = d.d; Th = d.g * Tg; Ty = d.h * Th; Tu = d.y * Ty;
-  }
-};
-
-}  // namespace
-
 int64_t ZipDims::rows() const { return a * x * x; }
 int64_t ZipDims::cols() const { return y * y * c * g * g; }
 int64_t ZipDims::v_size() const { return a * x * x * b * h * h; }
 int64_t ZipDims::s_size() const { return b * u * u * c; }
 int64_t ZipDims::t_size() const { return u * y * h * g * d; }
 
+ZipLayout ZipLayout::row_major(const ZipDims& z) {
+  ZipLayout L;
+  L.V[5] = 1; L.V[4] = z.h; L.V[3] = z.h * z.h; L.V[2] = z.b * L.V[3]; L.V[1] = z.x * L.V[2]; L.V[0] = z.x * L.V[1];
+  L.S[3] = 1; L.S[2] = z.c; L.S[1] = z.u * z.c; L.S[0] = z.u * L.S[1];
+  L.T[4] = 1; L.T[3] = z.d; L.T[2] = z.g * z.d; L.T[1] = z.h * L.T[2]; L.T[0] = z.y * L.T[1];
+  for (int i = 0; i < 5; ++i) L.B[i] = L.T[i];
+  L.nV = z.v_size();
+  L.nS = z.s_size();
+  L.nT = L.nB = z.t_size();
+  return L;
+}
+
+ZipOut ZipOut::row_major(const ZipDims& z, int64_t mp) {
+  ZipOut o;
+  const int64_t rows = z.rows(), cols = z.cols();
+  o.Urows.add(rows, mp);
+  o.Ucol.add(mp, 1);
+  o.Rrow.add(mp, cols);
+  o.Rcols.add(cols, 1);
+  o.nU = rows * mp;
+  o.nR = mp * cols;
+  return o;
+}
+
+CarryLayout CarryLayout::row_major(const CarryDims& c) {
+  CarryLayout L;
+  L.L[3] = 1; L.L[2] = c.b; L.L[1] = c.u * c.b; L.L[0] = c.u * L.L[1];
+  // [u, x, 1, h, p]
+  L.T[3] = 1; L.T[2] = c.d; L.T[1] = c.h * c.d; L.T[0] = c.x * L.T[1];
+  for (int i = 0; i < 4; ++i) L.B[i] = L.T[i];
+  L.nL = c.a * c.u * c.u * c.b;
+  L.nT = L.nB = c.u * c.x * c.h * c.d;
+  return L;
+}
+
+WsScope::WsScope(Ctx& ctx) : c(ctx), chunk(ctx.ws_chunk()), off(ctx.ws_offset()) {}
+WsScope::~WsScope() { c.ws_restore(chunk, off); }
+
 // ---------------------------------------------------------------------------
 // operator applications
 
-void zip_apply(Ctx& ctx, Prec prec, const ZipDims& z, const ZipOperands& op, int batch,
-               int64_t k, bool adjoint, const void* X, void* Y, bool y_f64, const ZipWork& w) {
-  const ZipStrides s(z);
+void zip_apply(Ctx& ctx, Prec prec, const ZipDims& z, const ZipLayout& L, const ZipOperands& op,
+               int batch, int64_t k, bool adjoint, const void* X, void* Y, bool y_f64,
+               const ZipWork& w) {
   const int64_t a = z.a, x = z.x, b = z.b, h = z.h, u = z.u, c = z.c, y = z.y, g = z.g, d = z.d;
-  const bool cplx = prec == Prec::C128;
   const int64_t rows = z.rows(), cols = z.cols();
-  // per-instance element counts of inputs / intermediates
-  const int64_t nV = z.v_size(), nS = z.s_size(), nT = z.t_size();
   const int64_t nW1 = u * h * d * y * c * g * k;  // [u,h,p,Y,c,G,j] or [Y,G,p,u,h,c,j]
   const int64_t nW2 = u * h * u * h * c * k;      // [U,H,u,h,c,j]
   const int64_t nW3 = b * h * h * k;              // [b,h,H,j]
@@ -60,16 +76,17 @@ void zip_apply(Ctx& ctx, Prec prec, const ZipDims& z, const ZipOperands& op, int
   // W3 strides [b,h,H,j]
   const int64_t w3j = 1, w3H = k, w3h = h * k, w3b = h * w3h;
   const bool f32 = prec == Prec::F32;
+  const int64_t *sV = L.V, *sS = L.S, *sT = L.T, *sB = L.B;
 
-  auto call = [&](const GemmDesc& dsc, const void* A, int64_t sA, bool cA, const void* B, int64_t sB,
-                  bool cB, void* C, int64_t sC, bool out_f64) {
+  auto call = [&](const GemmDesc& dsc, const void* A, int64_t nA, bool cA, const void* B, int64_t nB,
+                  bool cB, void* C, int64_t nC, bool out_f64) {
     GemmCall gc;
     gc.A = A;
     gc.B = B;
     gc.C = C;
-    gc.sA = sA;
-    gc.sB = sB;
-    gc.sC = sC;
+    gc.sA = nA;
+    gc.sB = nB;
+    gc.sC = nC;
     gc.batch = batch;
     gc.conjA = cA;
     gc.conjB = cB;
@@ -80,107 +97,105 @@ void zip_apply(Ctx& ctx, Prec prec, const ZipDims& z, const ZipOperands& op, int
   if (!adjoint) {
     // X[y,Y,c,g,G,j]
     const int64_t xj = 1, xG = k, xg = g * k, xc = g * xg, xY = c * xc, xy = y * xY;
+    const int64_t w1j = 1, w1G = k, w1c = g * k, w1Y = c * w1c, w1p = y * w1Y, w1h = d * w1p, w1u = h * w1h;
     // s1: W1[u,h,p | Y,c,G,j] = sum_{y,g} T[u,y,h,g,p] X[y,Y,c,g,G,j]
     {
-      const int64_t w1j = 1, w1G = k, w1c = g * k, w1Y = c * w1c, w1p = y * w1Y, w1h = d * w1p, w1u = h * w1h;
       GemmDesc D;
       D.M = u * h * d; D.K = y * g; D.N = y * c * g * k;
-      D.Am.add(u, s.Tu).add(h, s.Th).add(d, s.Tp);
-      D.Ak.add(y, s.Ty).add(g, s.Tg);
+      D.Am.add(u, sT[0]).add(h, sT[2]).add(d, sT[4]);
+      D.Ak.add(y, sT[1]).add(g, sT[3]);
       D.Bk.add(y, xy).add(g, xg);
       D.Bn.add(y, xY).add(c, xc).add(g, xG).add(k, xj);
       D.Cm.add(u, w1u).add(h, w1h).add(d, w1p);
       D.Cn.add(y, w1Y).add(c, w1c).add(g, w1G).add(k, w1j);
-      call(D, op.T, nT, false, X, cols * k, false, w.W1, nW1, false);
+      call(D, op.T, L.nT, false, X, cols * k, false, w.W1, nW1, false);
     }
     // s2: W2[U,H | u,h,c,j] = sum_{Y,G,p} conj(Bra[U,Y,H,G,p]) W1[u,h,p,Y,c,G,j]
     {
-      const int64_t w1j = 1, w1G = k, w1c = g * k, w1Y = c * w1c, w1p = y * w1Y, w1h = d * w1p, w1u = h * w1h;
       GemmDesc D;
       D.M = u * h; D.K = y * g * d; D.N = u * h * c * k;
-      D.Am.add(u, s.Tu).add(h, s.Th);
-      D.Ak.add(y, s.Ty).add(g, s.Tg).add(d, s.Tp);
+      D.Am.add(u, sB[0]).add(h, sB[2]);
+      D.Ak.add(y, sB[1]).add(g, sB[3]).add(d, sB[4]);
       D.Bk.add(y, w1Y).add(g, w1G).add(d, w1p);
       D.Bn.add(u, w1u).add(h, w1h).add(c, w1c).add(k, w1j);
       D.Cm.add(u, w2U).add(h, w2H);
       D.Cn.add(u, w2u).add(h, w2h).add(c, w2c).add(k, w2j);
-      call(D, op.Bra, nT, true, w.W1, nW1, false, w.W2, nW2, false);
+      call(D, op.Bra, L.nB, true, w.W1, nW1, false, w.W2, nW2, false);
     }
     // s3: W3[b | h,H,j] = sum_{u,U,c} S[b,u,U,c] W2[U,H,u,h,c,j]
     {
       GemmDesc D;
       D.M = b; D.K = u * u * c; D.N = h * h * k;
-      D.Am.add(b, s.Sb);
-      D.Ak.add(u, s.Su).add(u, s.SU).add(c, s.Sc);
+      D.Am.add(b, sS[0]);
+      D.Ak.add(u, sS[1]).add(u, sS[2]).add(c, sS[3]);
       D.Bk.add(u, w2u).add(u, w2U).add(c, w2c);
       D.Bn.add(h, w2h).add(h, w2H).add(k, w2j);
       D.Cm.add(b, w3b);
       D.Cn.add(h, w3h).add(h, w3H).add(k, w3j);
-      call(D, op.S, nS, false, w.W2, nW2, false, w.W3, nW3, false);
+      call(D, op.S, L.nS, false, w.W2, nW2, false, w.W3, nW3, false);
     }
     // s4: Y[a,x,X | j] = sum_{b,h,H} V[a,x,X,b,h,H] W3[b,h,H,j]
     {
       GemmDesc D;
       D.M = rows; D.K = b * h * h; D.N = k;
-      D.Am.add(a, s.Va).add(x, s.Vx).add(x, s.VX);
-      D.Ak.add(b, s.Vb).add(h, s.Vh).add(h, s.VH);
+      D.Am.add(a, sV[0]).add(x, sV[1]).add(x, sV[2]);
+      D.Ak.add(b, sV[3]).add(h, sV[4]).add(h, sV[5]);
       D.Bk.add(b, w3b).add(h, w3h).add(h, w3H);
       D.Bn.add(k, w3j);
       D.Cm.add(rows, k);
       D.Cn.add(k, 1);
-      call(D, op.V, nV, false, w.W3, nW3, false, Y, rows * k, y_f64 || !f32);
+      call(D, op.V, L.nV, false, w.W3, nW3, false, Y, rows * k, y_f64 || !f32);
     }
   } else {
-    // P[a,x,X,j]
     // t4: W3[b,h,H | j] = sum_{a,x,X} conj(V[a,x,X,b,h,H]) P[a,x,X,j]
     {
       GemmDesc D;
       D.M = b * h * h; D.K = rows; D.N = k;
-      D.Am.add(b, s.Vb).add(h, s.Vh).add(h, s.VH);
-      D.Ak.add(a, s.Va).add(x, s.Vx).add(x, s.VX);
+      D.Am.add(b, sV[3]).add(h, sV[4]).add(h, sV[5]);
+      D.Ak.add(a, sV[0]).add(x, sV[1]).add(x, sV[2]);
       D.Bk.add(rows, k);
       D.Bn.add(k, 1);
       D.Cm.add(b, w3b).add(h, w3h).add(h, w3H);
       D.Cn.add(k, w3j);
-      call(D, op.V, nV, true, X, rows * k, false, w.W3, nW3, false);
+      call(D, op.V, L.nV, true, X, rows * k, false, w.W3, nW3, false);
     }
     // t3: W2[u,U,c | h,H,j] = sum_b conj(S[b,u,U,c]) W3[b,h,H,j]   (W2 stored [U,H,u,h,c,j])
     {
       GemmDesc D;
       D.M = u * u * c; D.K = b; D.N = h * h * k;
-      D.Am.add(u, s.Su).add(u, s.SU).add(c, s.Sc);
-      D.Ak.add(b, s.Sb);
+      D.Am.add(u, sS[1]).add(u, sS[2]).add(c, sS[3]);
+      D.Ak.add(b, sS[0]);
       D.Bk.add(b, w3b);
       D.Bn.add(h, w3h).add(h, w3H).add(k, w3j);
       D.Cm.add(u, w2u).add(u, w2U).add(c, w2c);
       D.Cn.add(h, w2h).add(h, w2H).add(k, w2j);
-      call(D, op.S, nS, true, w.W3, nW3, false, w.W2, nW2, false);
+      call(D, op.S, L.nS, true, w.W3, nW3, false, w.W2, nW2, false);
     }
     // t2: W1[Y,G,p | u,h,c,j] = sum_{U,H} Bra[U,Y,H,G,p] W2[U,H,u,h,c,j]
     const int64_t v1j = 1, v1c = k, v1h = c * k, v1u = h * v1h, v1p = u * v1u, v1G = d * v1p, v1Y = g * v1G;
     {
       GemmDesc D;
       D.M = y * g * d; D.K = u * h; D.N = u * h * c * k;
-      D.Am.add(y, s.Ty).add(g, s.Tg).add(d, s.Tp);
-      D.Ak.add(u, s.Tu).add(h, s.Th);
+      D.Am.add(y, sB[1]).add(g, sB[3]).add(d, sB[4]);
+      D.Ak.add(u, sB[0]).add(h, sB[2]);
       D.Bk.add(u, w2U).add(h, w2H);
       D.Bn.add(u, w2u).add(h, w2h).add(c, w2c).add(k, w2j);
       D.Cm.add(y, v1Y).add(g, v1G).add(d, v1p);
       D.Cn.add(u, v1u).add(h, v1h).add(c, v1c).add(k, v1j);
-      call(D, op.Bra, nT, false, w.W2, nW2, false, w.W1, nW1, false);
+      call(D, op.Bra, L.nB, false, w.W2, nW2, false, w.W1, nW1, false);
     }
     // t1: Z[y,g | Y,c,G,j] = sum_{u,h,p} conj(T[u,y,h,g,p]) W1[Y,G,p,u,h,c,j]
     {
       const int64_t zj = 1, zG = k, zg = g * k, zc = g * zg, zY = c * zc, zy = y * zY;
       GemmDesc D;
       D.M = y * g; D.K = u * h * d; D.N = y * c * g * k;
-      D.Am.add(y, s.Ty).add(g, s.Tg);
-      D.Ak.add(u, s.Tu).add(h, s.Th).add(d, s.Tp);
+      D.Am.add(y, sT[1]).add(g, sT[3]);
+      D.Ak.add(u, sT[0]).add(h, sT[2]).add(d, sT[4]);
       D.Bk.add(u, v1u).add(h, v1h).add(d, v1p);
       D.Bn.add(y, v1Y).add(c, v1c).add(g, v1G).add(k, v1j);
       D.Cm.add(y, zy).add(g, zg);
       D.Cn.add(y, zY).add(c, zc).add(g, zG).add(k, zj);
-      call(D, op.T, nT, true, w.W1, nW1, false, Y, cols * k, y_f64 || !f32);
+      call(D, op.T, L.nT, true, w.W1, nW1, false, Y, cols * k, y_f64 || !f32);
     }
   }
 }
@@ -243,9 +258,10 @@ int64_t sketch_width(int64_t m, int64_t p, int64_t rows, int64_t cols) {
   return std::min(m + p, std::min(rows, cols));
 }
 
-void zip_esvd(Ctx& ctx, bool cplx, const ZipDims& z, const ZipOperands& op64, int batch,
-              const hpeps_esvd_opts& o, hpeps_absorb absorb, void* U, double* sigma, void* R,
-              double* log_scale) {
+void zip_esvd(Ctx& ctx, bool cplx, const ZipDims& z, const ZipLayout& L, const ZipOperands& op64,
+              int batch, const hpeps_esvd_opts& o, hpeps_absorb absorb, const ZipOut& out,
+              void* U, double* sigma, void* R, double* log_scale) {
+  WsScope scope(ctx);
   const int64_t rows = z.rows(), cols = z.cols();
   const int64_t k = sketch_width(o.rank, o.oversample, rows, cols);
   const int64_t mp = std::min<int64_t>(o.rank, k);
@@ -255,6 +271,9 @@ void zip_esvd(Ctx& ctx, bool cplx, const ZipDims& z, const ZipOperands& op64, in
   HP_REQUIRE(!(f32 && cplx), HPEPS_ERR_DTYPE, "FP32 sketches are real-only");
   HP_REQUIRE(o.sketch_precision == HPEPS_F64 || o.sketch_precision == HPEPS_F32, HPEPS_ERR_DTYPE,
              "sketch precision must be F64 or F32");
+  HP_REQUIRE(out.Urows.size() == rows && out.Ucol.size() == mp && out.Rrow.size() == mp &&
+                 out.Rcols.size() == cols,
+             HPEPS_ERR_SHAPE, "output layout does not match the factor shapes");
   const Prec prec = cplx ? Prec::C128 : (f32 ? Prec::F32 : Prec::F64);
   const int es = cplx ? 2 : 1;  // doubles per element
   const int max_sweeps = o.jacobi_max_sweeps > 0 ? o.jacobi_max_sweeps : 40;
@@ -288,14 +307,14 @@ void zip_esvd(Ctx& ctx, bool cplx, const ZipDims& z, const ZipOperands& op64, in
   ZipOperands op = op64;
   float* xin32 = nullptr;
   if (f32) {
-    float* V32 = ctx.ws<float>(nb * z.v_size());
-    float* S32 = ctx.ws<float>(nb * z.s_size());
-    float* T32 = ctx.ws<float>(nb * z.t_size());
-    float* B32 = ctx.ws<float>(nb * z.t_size());
-    convert_f64_to_f32(ctx, (const double*)op64.V, V32, nb * z.v_size());
-    convert_f64_to_f32(ctx, (const double*)op64.S, S32, nb * z.s_size());
-    convert_f64_to_f32(ctx, (const double*)op64.T, T32, nb * z.t_size());
-    convert_f64_to_f32(ctx, (const double*)op64.Bra, B32, nb * z.t_size());
+    float* V32 = ctx.ws<float>(nb * L.nV);
+    float* S32 = ctx.ws<float>(nb * L.nS);
+    float* T32 = ctx.ws<float>(nb * L.nT);
+    float* B32 = ctx.ws<float>(nb * L.nB);
+    convert_f64_to_f32(ctx, (const double*)op64.V, V32, nb * L.nV);
+    convert_f64_to_f32(ctx, (const double*)op64.S, S32, nb * L.nS);
+    convert_f64_to_f32(ctx, (const double*)op64.T, T32, nb * L.nT);
+    convert_f64_to_f32(ctx, (const double*)op64.Bra, B32, nb * L.nB);
     op.V = V32;
     op.S = S32;
     op.T = T32;
@@ -308,16 +327,16 @@ void zip_esvd(Ctx& ctx, bool cplx, const ZipDims& z, const ZipOperands& op64, in
       convert_f64_to_f32(ctx, X, xin32, nb * (adj ? rows : cols) * k);
       xin = xin32;
     }
-    zip_apply(ctx, prec, z, op, batch, k, adj, xin, Y, true, w);
+    zip_apply(ctx, prec, z, L, op, batch, k, adj, xin, Y, true, w);
   };
 
   // Alg. 4
   if (f32) {
     sketch(ctx, xin32, true, cols, k, batch, o.seed, o.stream_id);
-    zip_apply(ctx, prec, z, op, batch, k, false, xin32, Xr0, true, w);
+    zip_apply(ctx, prec, z, L, op, batch, k, false, xin32, Xr0, true, w);
   } else {
     sketch(ctx, Xc0, false, cols, k, batch, o.seed, o.stream_id, cplx);
-    zip_apply(ctx, prec, z, op, batch, k, false, Xc0, Xr0, true, w);
+    zip_apply(ctx, prec, z, L, op, batch, k, false, Xc0, Xr0, true, w);
   }
   orthogonalize(ctx, cplx, Xr0, Xr1, rows, k, batch, ow);          // P in Xr1
   for (int it = 0; it < o.power_iters; ++it) {
@@ -333,7 +352,7 @@ void zip_esvd(Ctx& ctx, bool cplx, const ZipDims& z, const ZipOperands& op64, in
   stats_reduce(ctx, nullptr, sweeps, batch, ctx.stats_dev);
 
   const Prec p64 = cplx ? Prec::C128 : Prec::F64;
-  // U = P Z[:, :m']  -> [rows, m']
+  // U = P Z[:, :m']
   {
     GemmDesc D;
     D.M = rows; D.K = k; D.N = mp;
@@ -341,19 +360,19 @@ void zip_esvd(Ctx& ctx, bool cplx, const ZipDims& z, const ZipOperands& op64, in
     D.Ak.add(k, 1);
     D.Bk.add(k, k);
     D.Bn.add(mp, 1);
-    D.Cm.add(rows, mp);
-    D.Cn.add(mp, 1);
+    D.Cm = out.Urows;
+    D.Cn = out.Ucol;
     GemmCall c;
     c.A = Xr1;
     c.B = Z;
     c.C = U;
     c.sA = rows * k;
     c.sB = k * k;
-    c.sC = rows * mp;
+    c.sC = out.nU;
     c.batch = batch;
     gemm(ctx, p64, D, c);
   }
-  // right factor: (B^* Z[:, :m'])^H  -> [m', cols], scaled per *absorb*
+  // right factor: (B^* Z[:, :m'])^H, scaled per *absorb*
   {
     GemmDesc D;
     D.M = cols; D.K = k; D.N = mp;
@@ -361,15 +380,15 @@ void zip_esvd(Ctx& ctx, bool cplx, const ZipDims& z, const ZipOperands& op64, in
     D.Ak.add(k, 1);
     D.Bk.add(k, k);
     D.Bn.add(mp, 1);
-    D.Cm.add(cols, 1);
-    D.Cn.add(mp, cols);
+    D.Cm = out.Rcols;
+    D.Cn = out.Rrow;
     GemmCall c;
     c.A = Xc0;
     c.B = Z;
     c.C = R;
     c.sA = cols * k;
     c.sB = k * k;
-    c.sC = mp * cols;
+    c.sC = out.nR;
     c.batch = batch;
     c.conjC = cplx;
     if (absorb == HPEPS_ABSORB_CARRY) c.scale = isig1;
@@ -379,41 +398,39 @@ void zip_esvd(Ctx& ctx, bool cplx, const ZipDims& z, const ZipOperands& op64, in
     }
     gemm(ctx, p64, D, c);
   }
-  copy_sigma(ctx, sig, k, mp, batch, sigma);
+  if (sigma) copy_sigma(ctx, sig, k, mp, batch, sigma);
 }
 
 // ---------------------------------------------------------------------------
-// exact carry of one column: V[a,x,X,b,h,H] = sum_{u,U,p} L[a,u,U,b] T[u,x,1,h,p] conj(Bra[U,X,1,H,p])
-void form_carry(Ctx& ctx, bool cplx, const CarryDims& cd, const void* L, const void* T,
-                const void* Bra, void* V, int batch) {
+// exact carry of one column: V[a,x,X,b,h,H] = sum_{u,U,p} L[a,u,U,b] T[u,x,h,p] conj(Bra[U,X,H,p])
+void form_carry(Ctx& ctx, bool cplx, const CarryDims& cd, const CarryLayout& cl, const void* L,
+                const void* T, const void* Bra, void* V, int batch) {
+  WsScope scope(ctx);
   const int64_t a = cd.a, u = cd.u, b = cd.b, x = cd.x, h = cd.h, d = cd.d;
   const Prec p = cplx ? Prec::C128 : Prec::F64;
   const int es = cplx ? 2 : 1;
-  // L strides [a,u,U,b]
-  const int64_t Lb = 1, LU = b, Lu = u * b, La = u * u * b;
-  // T strides [u,x,1,h,p]
-  const int64_t Tp = 1, Th = d, Tx = h * d, Tu = x * h * d;
   // X1[a,U,b,x,h,p]
   const int64_t Xp = 1, Xh = d, Xx = h * d, Xb = x * Xx, XU = b * Xb, Xa = u * XU;
   // V[a,x,X,b,h,H]
   const int64_t VH = 1, Vh = h, Vb = h * h, VX = b * Vb, Vx = x * VX, Va = x * Vx;
-  double* X1 = ctx.ws<double>((int64_t)batch * a * u * b * x * h * d * es);
+  const int64_t nX1 = a * u * b * x * h * d, nV = a * x * x * b * h * h;
+  double* X1 = ctx.ws<double>((int64_t)batch * nX1 * es);
   {
     GemmDesc D;
     D.M = a * u * b; D.K = u; D.N = x * h * d;
-    D.Am.add(a, La).add(u, LU).add(b, Lb);
-    D.Ak.add(u, Lu);
-    D.Bk.add(u, Tu);
-    D.Bn.add(x, Tx).add(h, Th).add(d, Tp);
+    D.Am.add(a, cl.L[0]).add(u, cl.L[2]).add(b, cl.L[3]);
+    D.Ak.add(u, cl.L[1]);
+    D.Bk.add(u, cl.T[0]);
+    D.Bn.add(x, cl.T[1]).add(h, cl.T[2]).add(d, cl.T[3]);
     D.Cm.add(a, Xa).add(u, XU).add(b, Xb);
     D.Cn.add(x, Xx).add(h, Xh).add(d, Xp);
     GemmCall c;
     c.A = L;
     c.B = T;
     c.C = X1;
-    c.sA = a * u * u * b;
-    c.sB = u * x * h * d;
-    c.sC = a * u * b * x * h * d;
+    c.sA = cl.nL;
+    c.sB = cl.nT;
+    c.sC = nX1;
     c.batch = batch;
     gemm(ctx, p, D, c);
   }
@@ -422,17 +439,17 @@ void form_carry(Ctx& ctx, bool cplx, const CarryDims& cd, const void* L, const v
     D.M = a * b * x * h; D.K = u * d; D.N = x * h;
     D.Am.add(a, Xa).add(b, Xb).add(x, Xx).add(h, Xh);
     D.Ak.add(u, XU).add(d, Xp);
-    D.Bk.add(u, Tu).add(d, Tp);
-    D.Bn.add(x, Tx).add(h, Th);
+    D.Bk.add(u, cl.B[0]).add(d, cl.B[3]);
+    D.Bn.add(x, cl.B[1]).add(h, cl.B[2]);
     D.Cm.add(a, Va).add(b, Vb).add(x, Vx).add(h, Vh);
     D.Cn.add(x, VX).add(h, VH);
     GemmCall c;
     c.A = X1;
     c.B = Bra;
     c.C = V;
-    c.sA = a * u * b * x * h * d;
-    c.sB = u * x * h * d;
-    c.sC = a * x * x * b * h * h;
+    c.sA = nX1;
+    c.sB = cl.nB;
+    c.sC = nV;
     c.batch = batch;
     c.conjB = cplx;
     gemm(ctx, p, D, c);

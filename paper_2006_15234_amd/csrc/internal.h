@@ -115,6 +115,11 @@ void sketch(Ctx& ctx, void* out, bool f32, int64_t n, int64_t k, int batch, uint
 // Elementwise conversion and scaling helpers.
 void convert_f64_to_f32(Ctx& ctx, const double* in, float* out, int64_t n);
 void fill_zero(Ctx& ctx, void* p, int64_t bytes);
+// p[0..n) = v (complex: real part v, imaginary part 0), by a kernel (no memset
+// nodes, so the call can sit in a captured graph)
+void fill_value(Ctx& ctx, double* p, int64_t n, double v, bool cplx);
+// dst[0..1] = src as a complex number (imaginary part 0 for real src)
+void copy_scalar(Ctx& ctx, const double* src, bool cplx, double* dst);
 // Frobenius norm of x (n doubles, or n complex if cplx) per batch (batch
 // stride n elements); x is divided by the norm and log_scale[b] += log(norm).
 void normalize(Ctx& ctx, bool cplx, void* x, int64_t n, int batch, double* log_scale);
@@ -143,6 +148,14 @@ class Ctx {
   T* ws(int64_t n) { return reinterpret_cast<T*>(ws_alloc(n * (int64_t)sizeof(T))); }
   // reserve at least bytes for the coming call (grows the arena; syncs)
   void ws_reserve(int64_t bytes);
+  // scoped reuse: the position can be saved and restored (all work is on one
+  // stream, so later kernels run after the earlier users of the memory)
+  int ws_chunk() const { return cur_; }
+  int64_t ws_offset() const { return ws_off_; }
+  void ws_restore(int chunk, int64_t off) {
+    cur_ = chunk;
+    ws_off_ = off;
+  }
 
   // diagnostics accumulator on the device: [extra passes, max sweeps,
   // numeric errors, not converged]

@@ -438,6 +438,24 @@ __global__ void stats_kernel(const int* flags, const int* sweeps, int batch, int
 
 size_t small_lds_bytes(int k, bool cplx) { return (size_t)k * k * (cplx ? 16 : 8); }
 
+__global__ void fill_value_kernel(double* p, long long n, double v, int cplx) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    if (cplx) {
+      p[2 * i] = v;
+      p[2 * i + 1] = 0.0;
+    } else {
+      p[i] = v;
+    }
+  }
+}
+
+__global__ void copy_scalar_kernel(const double* src, int cplx, double* dst) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    dst[0] = src[0];
+    dst[1] = cplx ? src[1] : 0.0;
+  }
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -536,6 +554,18 @@ void convert_f64_to_f32(Ctx& ctx, const double* in, float* out, int64_t n) {
 
 void fill_zero(Ctx& ctx, void* p, int64_t bytes) {
   HP_CHECK_HIP(hipMemsetAsync(p, 0, bytes, ctx.stream));
+}
+
+void fill_value(Ctx& ctx, double* p, int64_t n, double v, bool cplx) {
+  if (n <= 0) return;
+  fill_value_kernel<<<std::max<unsigned>(1, std::min<unsigned>(cdiv(n, 256), 1024)), 256, 0, ctx.stream>>>(
+      p, n, v, cplx ? 1 : 0);
+  HP_CHECK_HIP(hipGetLastError());
+}
+
+void copy_scalar(Ctx& ctx, const double* src, bool cplx, double* dst) {
+  copy_scalar_kernel<<<1, 64, 0, ctx.stream>>>(src, cplx ? 1 : 0, dst);
+  HP_CHECK_HIP(hipGetLastError());
 }
 
 void normalize(Ctx& ctx, bool cplx, void* x, int64_t n, int batch, double* log_scale) {

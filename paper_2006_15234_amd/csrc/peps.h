@@ -1,5 +1,88 @@
 // Boundary-MPS contraction, norms, energies and two-site updates (internals).
 #pragma once
+#include <array>
+
 #include "esvd.h"
 
-namespace hp {}  // namespace hp
+namespace hp {
+
+// A tensor in device memory with its leg dims (row-major, contiguous).
+struct DevTensor {
+  void* p = nullptr;
+  std::vector<int64_t> dims;
+  int64_t size() const {
+    int64_t s = 1;
+    for (auto d : dims) s *= d;
+    return s;
+  }
+};
+
+enum Side { kTop = 0, kBottom = 1 };
+enum Dir { kL2R = 0, kR2L = 1 };
+
+// A site [u,d,l,r,p] seen in an oriented frame: roles (up, down, left, right,
+// phys) -> dims and strides of the stored tensor.
+struct SiteView {
+  const void* p = nullptr;
+  int64_t n[5];
+  int64_t s[5];
+  int64_t extent = 0;
+};
+SiteView orient_site(const DevTensor& t, Side side, Dir dir);
+
+// A boundary tensor [mL, x, X, mR] seen in an oriented frame: roles (left, x,
+// X, right).
+struct BndView {
+  const void* p = nullptr;
+  int64_t n[4];
+  int64_t s[4];
+  int64_t extent = 0;
+};
+BndView orient_bnd(const DevTensor& t, Dir dir);
+
+// Exact first-row boundary: out[j] = [l*L, x, X, r*R] (x: down legs for
+// side kTop, up legs for kBottom), each normalised; log_dev += logs.
+void first_row_boundary(Ctx& ctx, bool cplx, const std::vector<SiteView>& ket,
+                        const std::vector<SiteView>& bra, std::vector<DevTensor>& out,
+                        double* log_dev);
+
+// Output shapes of a zip-up absorption (host-side shape propagation).
+std::vector<std::array<int64_t, 4>> absorb_shapes(const std::vector<BndView>& bnd,
+                                                  const std::vector<SiteView>& ket, int64_t m,
+                                                  int64_t p);
+
+// One ApproxApply (Alg. 3) in the oriented frame: views are listed in sweep
+// order; out[j] receive the canonical [mL,x,X,mR] tensors of the same sweep
+// position (their dims are set here); dir tells how to store them.
+void absorb_row(Ctx& ctx, bool cplx, const std::vector<BndView>& bnd,
+                const std::vector<SiteView>& ket, const std::vector<SiteView>& bra, Dir dir,
+                const hpeps_esvd_opts& o, const std::vector<uint64_t>& stream_ids,
+                std::vector<DevTensor>& out, double* log_dev);
+
+// Exact contraction of a boundary MPS with a last row (its far legs of dim 1)
+// in the oriented frame (L2R); writes the (complex) scalar mantissa to
+// result_dev (2 doubles) and adds the logs to log_dev.
+void contract_last_row(Ctx& ctx, bool cplx, const std::vector<BndView>& bnd,
+                       const std::vector<SiteView>& ket, const std::vector<SiteView>& bra,
+                       double* result_dev, double* log_dev);
+
+// Host view of an ABI PEPS.
+struct Lattice {
+  int nrow = 0, ncol = 0;
+  bool cplx = false;
+  std::vector<DevTensor> sites;  // row-major
+  const DevTensor& at(int i, int j) const { return sites[(size_t)i * ncol + j]; }
+};
+Lattice lattice_from_abi(const hpeps_peps* p);
+
+// Copies every site into the workspace divided by its Frobenius norm; the
+// logarithms of the norms are added to log_dev.
+Lattice normalized_copy(Ctx& ctx, const Lattice& L, double* log_dev);
+
+// Boundary pass from one side storing every intermediate boundary MPS:
+// envs[t] = boundary after the first t+1 rows seen from `side`.
+void boundary_pass(Ctx& ctx, const Lattice& ket, const Lattice& bra, Side side,
+                   const hpeps_esvd_opts& o, int upto, std::vector<std::vector<DevTensor>>& envs,
+                   double* log_dev);
+
+}  // namespace hp

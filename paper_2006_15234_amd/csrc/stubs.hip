@@ -2,15 +2,6 @@
 #include "internal.h"
 
 extern "C" {
-hpeps_status hpeps_boundary_contract_row(hpeps_ctx*, const hpeps_bmps*, const hpeps_peps*,
-                                         const hpeps_peps*, int32_t, hpeps_direction,
-                                         const hpeps_esvd_opts*, hpeps_bmps*, double*) {
-  return HPEPS_ERR_UNSUPPORTED;
-}
-hpeps_status hpeps_peps_norm(hpeps_ctx*, const hpeps_peps*, const hpeps_peps*, const hpeps_esvd_opts*,
-                             double*, double*) {
-  return HPEPS_ERR_UNSUPPORTED;
-}
 hpeps_status hpeps_peps_energy(hpeps_ctx*, const hpeps_peps*, int32_t, const int32_t*, const int32_t*,
                                const double*, const int64_t*, const hpeps_esvd_opts*, double*, double*) {
   return HPEPS_ERR_UNSUPPORTED;

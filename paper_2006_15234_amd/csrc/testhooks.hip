@@ -100,8 +100,8 @@ hpeps_status hpeps_test_zip_apply(hpeps_ctx* ctx, hpeps_dtype dtype, int64_t bat
     w.W2 = c.ws<double>(batch * z.u * z.h * z.u * z.h * z.c * k * es);
     w.W3 = c.ws<double>(batch * z.b * z.h * z.h * k * es);
     hp::ZipOperands op{V, S, T, Bra ? Bra : T};
-    hp::zip_apply(c, cplx ? hp::Prec::C128 : hp::Prec::F64, z, op, (int)batch, k, adjoint != 0, X, Y,
-                  true, w);
+    hp::zip_apply(c, cplx ? hp::Prec::C128 : hp::Prec::F64, z, hp::ZipLayout::row_major(z), op,
+                  (int)batch, k, adjoint != 0, X, Y, true, w);
   });
 }
 
