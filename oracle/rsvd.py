@@ -50,5 +50,24 @@ def randomized_svd(apply, apply_adj, n_rows, n_cols, m, q, omega):
     B = apply_adj(P).conj().T            # P^* A, shape (k, n_cols)
     Ut, s, Vh = np.linalg.svd(B, full_matrices=False)
     mp = min(m, k)
-    return P @ Ut[:, :mp], s[:mp], Vh[:mp]
+    return fix_gauge(P @ Ut[:, :mp], s[:mp], Vh[:mp])
+
+
+def fix_gauge(U, s, Vh):
+    """Canonical phase of each singular pair: the entry of largest magnitude of
+    U[:, i] (the first one on ties) is made real positive and V^*[i, :] is
+    counter-rotated, so U diag(s) V^* is unchanged.  The paper leaves this
+    phase free; it matters because a later randomized SVD sketches the
+    resulting tensors in their index basis, so every implementation has to
+    make the same choice to reproduce the same numbers."""
+    U = U.copy()
+    Vh = Vh.copy()
+    for i in range(U.shape[1]):
+        r = int(np.argmax(np.abs(U[:, i])))
+        a = U[r, i]
+        if a != 0:
+            ph = a / abs(a)
+            U[:, i] *= np.conj(ph)
+            Vh[i, :] *= ph
+    return U, s, Vh
 

@@ -169,20 +169,22 @@ def peps_norm(ctx, ket, bra=None, *, rank, oversample=0, power_iters=0, seed=0, 
     return ln.value, complex(ph[0], ph[1])
 
 
-def boundary_contract_row(ctx, bnd, ket_row, bra_row=None, *, row, direction, rank, oversample=0,
+def boundary_contract_row(ctx, bnd, ket, bra=None, *, row, direction, rank, oversample=0,
                           power_iters=0, seed=0, stream_id=0, precision="f64", out_capacity=None):
-    """Absorbs one PEPS row into a boundary MPS (list of [mL,x,X,mR] device tensors).
-    Returns (new boundary list, log scale added)."""
+    """Absorbs row ``row`` of the lattice ``ket`` (list of rows of device site
+    tensors; ``bra`` likewise, None for conj(ket)) into a boundary MPS (list of
+    [mL,x,X,mR] device tensors).  Returns (new boundary list, log scale added)."""
     torch = _torch()
     keep = []
+    ket_row = ket[row]
     dt = _dtype_code(ket_row[0])
     ncol = len(ket_row)
     bp = (C.c_void_p * ncol)(*[_dev(t, "bnd").value for t in bnd])
     bs = (C.c_int64 * (4 * ncol))(*[s for t in bnd for s in t.shape])
     bin_ = Bmps(ncol=ncol, dtype=dt, tensors=C.cast(bp, C.POINTER(C.c_void_p)),
                 shapes=C.cast(bs, C.POINTER(C.c_int64)), capacity=None)
-    pk = _peps_struct([ket_row], dt, keep)
-    pb = _peps_struct([bra_row], dt, keep) if bra_row is not None else None
+    pk = _peps_struct(ket, dt, keep)
+    pb = _peps_struct(bra, dt, keep) if bra is not None else None
     # output capacity: m' <= rank + 0 per bond; down legs of the row
     outs = []
     for j, T in enumerate(ket_row):

@@ -352,6 +352,29 @@ void zip_esvd(Ctx& ctx, bool cplx, const ZipDims& z, const ZipLayout& L, const Z
   stats_reduce(ctx, nullptr, sweeps, batch, ctx.stats_dev);
 
   const Prec p64 = cplx ? Prec::C128 : Prec::F64;
+  // canonical phase of the kept singular pairs: U = P Z is formed once in a
+  // row-major scratch, Z's columns are rotated, then the factors are formed
+  {
+    double* Ut = ctx.ws<double>(nb * rows * mp * es);
+    GemmDesc D;
+    D.M = rows; D.K = k; D.N = mp;
+    D.Am.add(rows, k);
+    D.Ak.add(k, 1);
+    D.Bk.add(k, k);
+    D.Bn.add(mp, 1);
+    D.Cm.add(rows, mp);
+    D.Cn.add(mp, 1);
+    GemmCall c;
+    c.A = Xr1;
+    c.B = Z;
+    c.C = Ut;
+    c.sA = rows * k;
+    c.sB = k * k;
+    c.sC = rows * mp;
+    c.batch = batch;
+    gemm(ctx, p64, D, c);
+    gauge_fix(ctx, cplx, Ut, rows, mp, Z, k, batch);
+  }
   // U = P Z[:, :m']
   {
     GemmDesc D;

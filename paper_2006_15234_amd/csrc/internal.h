@@ -118,6 +118,11 @@ void fill_zero(Ctx& ctx, void* p, int64_t bytes);
 // p[0..n) = v (complex: real part v, imaginary part 0), by a kernel (no memset
 // nodes, so the call can sit in a captured graph)
 void fill_value(Ctx& ctx, double* p, int64_t n, double v, bool cplx);
+// Canonical phase of singular pairs: U (row-major rows x mp per instance) is
+// the left factor P Z; column i of Z (k x k) is rotated so that the
+// largest-magnitude entry of U[:, i] (first on ties) becomes real positive.
+void gauge_fix(Ctx& ctx, bool cplx, const double* U, int64_t rows, int64_t mp, double* Z, int64_t k,
+               int batch);
 // dst[0..1] = src as a complex number (imaginary part 0 for real src)
 void copy_scalar(Ctx& ctx, const double* src, bool cplx, double* dst);
 // Frobenius norm of x (n doubles, or n complex if cplx) per batch (batch

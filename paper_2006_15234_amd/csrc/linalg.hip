@@ -376,13 +376,44 @@ __global__ void f64_to_f32_kernel(const double* in, float* out, long long n) {
     out[i] = (float)in[i];
 }
 
-// Frobenius norm per batch instance: block partial sums, then finalize.
-__global__ void sumsq_partial_kernel(const double* x, long long n, double* part) {
+// Frobenius norm per batch instance, safe against underflow and overflow:
+// pass 1 finds max|x| (block partials, then a finalize), pass 2 sums
+// (x / max)^2; norm = max * sqrt(sum).
+__global__ void absmax_partial_kernel(const double* x, long long n, double* part) {
   const int b = blockIdx.y;
   const double* xb = x + (long long)b * n;
   double s = 0;
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
-    s += xb[i] * xb[i];
+    s = fmax(s, fabs(xb[i]));
+  __shared__ double red[16];
+  for (int o = 32; o > 0; o >>= 1) s = fmax(s, __shfl_xor(s, o));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0;
+    for (int w = 0; w < (int)blockDim.x / 64; ++w) t = fmax(t, red[w]);
+    part[(long long)b * gridDim.x + blockIdx.x] = t;
+  }
+}
+
+__global__ void absmax_finalize_kernel(const double* part, int nparts, double* mx) {
+  const int b = blockIdx.x;
+  if (threadIdx.x == 0) {
+    double t = 0;
+    for (int i = 0; i < nparts; ++i) t = fmax(t, part[(long long)b * nparts + i]);
+    mx[b] = t;
+  }
+}
+
+__global__ void sumsq_partial_kernel(const double* x, long long n, const double* mx, double* part) {
+  const int b = blockIdx.y;
+  const double* xb = x + (long long)b * n;
+  const double f = mx[b] > 0 ? 1.0 / mx[b] : 1.0;
+  double s = 0;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    const double v = xb[i] * f;
+    s += v * v;
+  }
   __shared__ double red[16];
   for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
@@ -394,14 +425,21 @@ __global__ void sumsq_partial_kernel(const double* x, long long n, double* part)
   }
 }
 
-__global__ void norm_finalize_kernel(const double* part, int nparts, double* inv_norm, double* log_scale) {
+// inv_norm[b] holds 1/max on entry (scale of the sums); writes 1/norm
+__global__ void norm_finalize_kernel(const double* part, int nparts, const double* mx, double* inv_norm,
+                                     double* log_scale) {
   const int b = blockIdx.x;
   if (threadIdx.x == 0) {
     double t = 0;
     for (int i = 0; i < nparts; ++i) t += part[(long long)b * nparts + i];
-    const double nr = sqrt(t);
-    inv_norm[b] = nr > 0 ? 1.0 / nr : 1.0;
-    if (log_scale && nr > 0) log_scale[b] += log(nr);
+    const double m = mx[b];
+    if (m > 0 && t > 0) {
+      // 1/norm = (1/m) / sqrt(t), computed without forming m * sqrt(t)
+      inv_norm[b] = (1.0 / m) / sqrt(t);
+      if (log_scale) log_scale[b] += log(m) + 0.5 * log(t);
+    } else {
+      inv_norm[b] = 1.0;
+    }
   }
 }
 
@@ -446,6 +484,59 @@ __global__ void fill_value_kernel(double* p, long long n, double v, int cplx) {
     } else {
       p[i] = v;
     }
+  }
+}
+
+// Canonical phase of the singular vectors: for each column i < mp of the
+// left factor U = P Z (row-major rows x mp, one instance per block), find the
+// entry of largest magnitude (first index on ties) and rotate column i of Z
+// by its conjugate phase, so that entry becomes real positive.
+template <bool CPLX>
+__global__ __launch_bounds__(256) void gauge_fix_kernel(const double* Uall, long long rows, int mp, double* Zall,
+                                                        int k) {
+  using T = typename S<CPLX>::T;
+  const int b = blockIdx.x, tid = threadIdx.x;
+  const T* U = reinterpret_cast<const T*>(Uall) + (long long)b * rows * mp;
+  T* Z = reinterpret_cast<T*>(Zall) + (long long)b * k * k;
+  __shared__ double sv[256];
+  __shared__ long long si[256];
+  __shared__ T phase;
+  for (int i = 0; i < mp; ++i) {
+    double best = -1.0;
+    long long bi = 0;
+    for (long long r = tid; r < rows; r += blockDim.x) {
+      const double v = S<CPLX>::abs2(U[r * mp + i]);
+      if (v > best) {  // strict: keeps the first index of this thread's stride
+        best = v;
+        bi = r;
+      }
+    }
+    sv[tid] = best;
+    si[tid] = bi;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+      if (tid < s) {
+        const double v2 = sv[tid + s];
+        const long long i2 = si[tid + s];
+        if (v2 > sv[tid] || (v2 == sv[tid] && i2 < si[tid])) {
+          sv[tid] = v2;
+          si[tid] = i2;
+        }
+      }
+      __syncthreads();
+    }
+    if (tid == 0) {
+      const T a = U[si[0] * mp + i];
+      const double m = sqrt(S<CPLX>::abs2(a));
+      if constexpr (CPLX) {
+        phase = m > 0 ? T{a.re / m, -a.im / m} : T{1.0, 0.0};  // conj(a)/|a|
+      } else {
+        phase = (a < 0) ? -1.0 : 1.0;
+      }
+    }
+    __syncthreads();
+    for (int r = tid; r < k; r += blockDim.x) Z[(long long)r * k + i] = S<CPLX>::mul(Z[(long long)r * k + i], phase);
+    __syncthreads();
   }
 }
 
@@ -563,6 +654,15 @@ void fill_value(Ctx& ctx, double* p, int64_t n, double v, bool cplx) {
   HP_CHECK_HIP(hipGetLastError());
 }
 
+void gauge_fix(Ctx& ctx, bool cplx, const double* U, int64_t rows, int64_t mp, double* Z, int64_t k,
+               int batch) {
+  if (cplx)
+    gauge_fix_kernel<true><<<batch, 256, 0, ctx.stream>>>(U, rows, (int)mp, Z, (int)k);
+  else
+    gauge_fix_kernel<false><<<batch, 256, 0, ctx.stream>>>(U, rows, (int)mp, Z, (int)k);
+  HP_CHECK_HIP(hipGetLastError());
+}
+
 void copy_scalar(Ctx& ctx, const double* src, bool cplx, double* dst) {
   copy_scalar_kernel<<<1, 64, 0, ctx.stream>>>(src, cplx ? 1 : 0, dst);
   HP_CHECK_HIP(hipGetLastError());
@@ -572,9 +672,12 @@ void normalize(Ctx& ctx, bool cplx, void* x, int64_t n, int batch, double* log_s
   const int64_t nd = cplx ? 2 * n : n;  // a complex array is 2n doubles; same sum of squares
   const int nparts = (int)std::min<int64_t>(cdiv(nd, 256 * 4), 256);
   double* part = ctx.ws<double>((int64_t)nparts * batch);
+  double* mx = ctx.ws<double>(batch);
   double* inv = ctx.ws<double>(batch);
-  sumsq_partial_kernel<<<dim3(nparts, batch), 256, 0, ctx.stream>>>((const double*)x, nd, part);
-  norm_finalize_kernel<<<batch, 64, 0, ctx.stream>>>(part, nparts, inv, log_scale);
+  absmax_partial_kernel<<<dim3(nparts, batch), 256, 0, ctx.stream>>>((const double*)x, nd, part);
+  absmax_finalize_kernel<<<batch, 64, 0, ctx.stream>>>(part, nparts, mx);
+  sumsq_partial_kernel<<<dim3(nparts, batch), 256, 0, ctx.stream>>>((const double*)x, nd, mx, part);
+  norm_finalize_kernel<<<batch, 64, 0, ctx.stream>>>(part, nparts, mx, inv, log_scale);
   scale_kernel<<<dim3(std::min<unsigned>(cdiv(nd, 256), 1024), batch), 256, 0, ctx.stream>>>((double*)x, nd, inv);
   HP_CHECK_HIP(hipGetLastError());
 }

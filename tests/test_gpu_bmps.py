@@ -105,7 +105,7 @@ def test_boundary_contract_row(ctx, direction, cplx):
     sids = [stream_id(0, nrow, ncol, 1, j) for j in range(ncol)]
     ref, ls, _ = bmps.absorb_row(bnd, peps[1], peps[1], direction, m, p, q, 9, sids)
     dbnd = [torch.from_numpy(np.ascontiguousarray(S)).cuda() for S in bnd]
-    out, lsg = hp.boundary_contract_row(ctx, dbnd, dev_lattice(peps)[1], row=1,
+    out, lsg = hp.boundary_contract_row(ctx, dbnd, dev_lattice(peps), row=1,
                                         direction=direction, rank=m, oversample=p, power_iters=q,
                                         seed=9, stream_id=sids[0])
     got = [t.cpu().numpy() for t in out]

@@ -168,3 +168,18 @@ def test_rsvd_near_optimal_on_pair_network():
     err = np.linalg.norm(A - (U * s) @ Vh)
     assert opt <= err <= 1.5 * opt
     assert np.all(s <= s_ref[:m] * (1 + 1e-12))  # Ritz values never exceed the true ones
+
+
+def test_fix_gauge_canonical_and_product_invariant():
+    rng = np.random.default_rng(8)
+    U = np.linalg.qr(rng.standard_normal((9, 4)) + 1j * rng.standard_normal((9, 4)))[0]
+    s = np.array([3.0, 2.0, 1.0, 0.5])
+    Vh = np.linalg.qr(rng.standard_normal((7, 4)) + 1j * rng.standard_normal((7, 4)))[0].T.conj()
+    U2, s2, V2 = rsvd.fix_gauge(U, s, Vh)
+    assert np.allclose((U2 * s2) @ V2, (U * s) @ Vh, atol=1e-14)
+    for i in range(4):
+        r = np.argmax(np.abs(U2[:, i]))
+        assert U2[r, i].real > 0 and abs(U2[r, i].imag) < 1e-15
+    # idempotent, and any column phase change is undone
+    U3, _, V3 = rsvd.fix_gauge(U2 * np.exp(1j * np.arange(4)), s2, V2 * np.exp(-1j * np.arange(4))[:, None])
+    assert np.allclose(U3, U2, atol=1e-14) and np.allclose(V3, V2, atol=1e-14)
