@@ -53,20 +53,30 @@ def randomized_svd(apply, apply_adj, n_rows, n_cols, m, q, omega):
     return fix_gauge(P @ Ut[:, :mp], s[:mp], Vh[:mp])
 
 
+def gauge_vector(n):
+    """The fixed vector w (length n) that defines the canonical phase: the
+    counter-based uniform values of the sketch generator with seed 0 and
+    stream 0, one column."""
+    from .sketch import sketch
+    return sketch(0, 0, n, 1)[:, 0]
+
+
 def fix_gauge(U, s, Vh):
-    """Canonical phase of each singular pair: the entry of largest magnitude of
-    U[:, i] (the first one on ties) is made real positive and V^*[i, :] is
+    """Canonical phase of each singular pair: the projection w . U[:, i] on the
+    fixed vector w of gauge_vector is made real positive and V^*[i, :] is
     counter-rotated, so U diag(s) V^* is unchanged.  The paper leaves this
     phase free; it matters because a later randomized SVD sketches the
     resulting tensors in their index basis, so every implementation has to
-    make the same choice to reproduce the same numbers."""
+    make the same choice to reproduce the same numbers.  (A rule based on the
+    largest entry is not usable: in <psi|psi> networks the ket/bra symmetry
+    produces entries of exactly equal magnitude.)"""
     U = U.copy()
     Vh = Vh.copy()
+    w = gauge_vector(U.shape[0])
     for i in range(U.shape[1]):
-        r = int(np.argmax(np.abs(U[:, i])))
-        a = U[r, i]
-        if a != 0:
-            ph = a / abs(a)
+        z = w @ U[:, i]
+        if z != 0:
+            ph = z / abs(z)
             U[:, i] *= np.conj(ph)
             Vh[i, :] *= ph
     return U, s, Vh

@@ -488,9 +488,12 @@ __global__ void fill_value_kernel(double* p, long long n, double v, int cplx) {
 }
 
 // Canonical phase of the singular vectors: for each column i < mp of the
-// left factor U = P Z (row-major rows x mp, one instance per block), find the
-// entry of largest magnitude (first index on ties) and rotate column i of Z
-// by its conjugate phase, so that entry becomes real positive.
+// left factor U = P Z (row-major rows x mp, one instance per block), the
+// projection z = w . U[:, i] on the fixed vector w (the sketch generator's
+// values for seed 0, stream 0, one column) is made real positive by rotating
+// column i of Z by conj(z)/|z|.  A projection on a generic vector is immune
+// to the exact magnitude ties that the ket/bra symmetry of <psi|psi>
+// networks creates between entries.
 template <bool CPLX>
 __global__ __launch_bounds__(256) void gauge_fix_kernel(const double* Uall, long long rows, int mp, double* Zall,
                                                         int k) {
@@ -498,40 +501,38 @@ __global__ __launch_bounds__(256) void gauge_fix_kernel(const double* Uall, long
   const int b = blockIdx.x, tid = threadIdx.x;
   const T* U = reinterpret_cast<const T*>(Uall) + (long long)b * rows * mp;
   T* Z = reinterpret_cast<T*>(Zall) + (long long)b * k * k;
-  __shared__ double sv[256];
-  __shared__ long long si[256];
+  __shared__ double sr[256], si[256];
   __shared__ T phase;
+  const uint64_t base = mix64(mix64(0ull) + 0ull);
   for (int i = 0; i < mp; ++i) {
-    double best = -1.0;
-    long long bi = 0;
+    double zr = 0.0, zi = 0.0;
     for (long long r = tid; r < rows; r += blockDim.x) {
-      const double v = S<CPLX>::abs2(U[r * mp + i]);
-      if (v > best) {  // strict: keeps the first index of this thread's stride
-        best = v;
-        bi = r;
+      const uint64_t h = mix64(base + (uint64_t)(r + 1) * 0x9E3779B97F4A7C15ull);
+      const double w = 2.0 * (double)(h >> 11) * 0x1p-53 - 1.0;
+      const T u = U[r * mp + i];
+      if constexpr (CPLX) {
+        zr += w * u.re;
+        zi += w * u.im;
+      } else {
+        zr += w * u;
       }
     }
-    sv[tid] = best;
-    si[tid] = bi;
+    sr[tid] = zr;
+    si[tid] = zi;
     __syncthreads();
     for (int s = blockDim.x / 2; s > 0; s >>= 1) {
       if (tid < s) {
-        const double v2 = sv[tid + s];
-        const long long i2 = si[tid + s];
-        if (v2 > sv[tid] || (v2 == sv[tid] && i2 < si[tid])) {
-          sv[tid] = v2;
-          si[tid] = i2;
-        }
+        sr[tid] += sr[tid + s];
+        si[tid] += si[tid + s];
       }
       __syncthreads();
     }
     if (tid == 0) {
-      const T a = U[si[0] * mp + i];
-      const double m = sqrt(S<CPLX>::abs2(a));
+      const double m = sqrt(sr[0] * sr[0] + si[0] * si[0]);
       if constexpr (CPLX) {
-        phase = m > 0 ? T{a.re / m, -a.im / m} : T{1.0, 0.0};  // conj(a)/|a|
+        phase = m > 0 ? T{sr[0] / m, -si[0] / m} : T{1.0, 0.0};  // conj(z)/|z|
       } else {
-        phase = (a < 0) ? -1.0 : 1.0;
+        phase = (sr[0] < 0) ? -1.0 : 1.0;
       }
     }
     __syncthreads();

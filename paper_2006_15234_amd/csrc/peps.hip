@@ -506,8 +506,10 @@ hpeps_status hpeps_peps_norm(hpeps_ctx* ctx, const hpeps_peps* ket, const hpeps_
         HP_REQUIRE(K.sites[q].dims[e] == B.sites[q].dims[e], HPEPS_ERR_SHAPE, "bra and ket shapes differ");
     double* dev = c.ws<double>(4);  // log, result re/im
     hp::fill_value(c, dev, 1, 0.0, false);
+    // the bra layer is rescaled separately even when it is the ket itself:
+    // both layers' norms enter <bra|ket>
     hp::Lattice Kn = hp::normalized_copy(c, K, dev);
-    hp::Lattice Bn = bra ? hp::normalized_copy(c, B, dev) : Kn;
+    hp::Lattice Bn = hp::normalized_copy(c, B, dev);
     std::vector<hp::BndView> bv;
     std::vector<hp::SiteView> kv, brv;
     std::vector<std::vector<hp::DevTensor>> envs;

@@ -177,9 +177,11 @@ def test_fix_gauge_canonical_and_product_invariant():
     Vh = np.linalg.qr(rng.standard_normal((7, 4)) + 1j * rng.standard_normal((7, 4)))[0].T.conj()
     U2, s2, V2 = rsvd.fix_gauge(U, s, Vh)
     assert np.allclose((U2 * s2) @ V2, (U * s) @ Vh, atol=1e-14)
+    w = rsvd.gauge_vector(9)
+    assert np.array_equal(w, sketch(0, 0, 9, 1)[:, 0])
     for i in range(4):
-        r = np.argmax(np.abs(U2[:, i]))
-        assert U2[r, i].real > 0 and abs(U2[r, i].imag) < 1e-15
+        z = w @ U2[:, i]
+        assert z.real > 0 and abs(z.imag) < 1e-14
     # idempotent, and any column phase change is undone
     U3, _, V3 = rsvd.fix_gauge(U2 * np.exp(1j * np.arange(4)), s2, V2 * np.exp(-1j * np.arange(4))[:, None])
     assert np.allclose(U3, U2, atol=1e-14) and np.allclose(V3, V2, atol=1e-14)
