@@ -244,15 +244,93 @@ def peps_energy(ctx, ket, terms, *, rank, oversample=0, power_iters=0, seed=0, p
     return complex(e[0], e[1]), [complex(per[2 * t], per[2 * t + 1]) for t in range(n)]
 
 
-def apply_two_site_gate(ctx, sites, capacity, i, j, axis, G, max_rank):
-    """In-place QR-SVD update of sites[i][j] and its right (axis 0) / lower (axis 1)
-    neighbour.  ``sites`` holds flat device buffers of ``capacity`` elements
-    and a parallel list of shapes; returns (new bond, kept singular values)."""
-    raise NotImplementedError
+def apply_two_site_gate(ctx, sites, i, j, axis, G, max_rank):
+    """QR-SVD update (Alg. 1) of sites[i][j] and its right (axis 0) or lower
+    (axis 1) neighbour with the gate G[out1,out2,in1,in2] (device tensor).
+    ``sites`` is a list of rows of device tensors [u,d,l,r,p]; returns
+    (new lattice as a list of rows, kept singular values on the device)."""
+    torch = _torch()
+    nrow, ncol = len(sites), len(sites[0])
+    d = sites[0][0].shape[4]
+    cap = max_rank ** 4 * d
+    bufs = [[torch.zeros(cap, dtype=sites[0][0].dtype, device=sites[0][0].device) for _ in range(ncol)]
+            for _ in range(nrow)]
+    for r in range(nrow):
+        for c in range(ncol):
+            bufs[r][c][:sites[r][c].numel()] = sites[r][c].reshape(-1)
+    ptrs = (C.c_void_p * (nrow * ncol))(*[bufs[r][c].data_ptr() for r in range(nrow) for c in range(ncol)])
+    shapes = (C.c_int64 * (nrow * ncol * 5))(*[s for r in range(nrow) for c in range(ncol)
+                                               for s in sites[r][c].shape])
+    capa = (C.c_int64 * (nrow * ncol))(*([cap] * (nrow * ncol)))
+    pk = Peps(nrow=nrow, ncol=ncol, dtype=_dtype_code(sites[0][0]), reserved=0,
+              sites=C.cast(ptrs, C.POINTER(C.c_void_p)), shapes=C.cast(shapes, C.POINTER(C.c_int64)))
+    sig = torch.zeros(max_rank, dtype=torch.float64, device=sites[0][0].device)
+    nb = C.c_int64()
+    Gd = G.contiguous()
+    ctx.sync_stream()
+    ctx.check(ctx.lib.hpeps_apply_two_site_gate(ctx.h, C.byref(pk), capa, i, j, axis, _dev(Gd, "G"),
+                                                max_rank, C.byref(nb), _dev(sig, "sigma")))
+    out = []
+    for r in range(nrow):
+        row = []
+        for c in range(ncol):
+            shp = tuple(shapes[(r * ncol + c) * 5:(r * ncol + c) * 5 + 5])
+            n = shp[0] * shp[1] * shp[2] * shp[3] * shp[4]
+            row.append(bufs[r][c][:n].view(shp))
+        out.append(row)
+    return out, sig[:nb.value]
 
 
 class ItePlan:
-    """Batched imaginary-time-evolution sweeps (see hpeps_ite_plan_create)."""
+    """Batched imaginary-time-evolution sweeps (TEBD with QR-SVD updates).
 
-    def __init__(self, *a, **k):
-        raise NotImplementedError
+    peps: list of rows of device tensors (initial state, bonds <= max_rank);
+    gates: device tensor [n_gates, d, d, d, d]; bond_gate: gate index of every
+    bond in layer order (horizontal even columns, horizontal odd columns,
+    vertical even rows, vertical odd rows)."""
+
+    def __init__(self, ctx, peps, gates, bond_gate, max_rank):
+        keep = []
+        self.ctx = ctx
+        self.nrow, self.ncol = len(peps), len(peps[0])
+        self.dtype = peps[0][0].dtype
+        self.device = peps[0][0].device
+        pk = _peps_struct(peps, _dtype_code(peps[0][0]), keep)
+        bg = (C.c_int32 * len(bond_gate))(*bond_gate)
+        self.gates = gates.contiguous()
+        h = C.c_void_p()
+        ctx.sync_stream()
+        ctx.check(ctx.lib.hpeps_ite_plan_create(ctx.h, C.byref(pk), self.gates.shape[0],
+                                                _dev(self.gates, "gates"), bg, max_rank, C.byref(h)))
+        self.h = h
+
+    def run(self, n_sweeps, use_graph=True):
+        self.ctx.sync_stream()
+        self.ctx.check(self.ctx.lib.hpeps_ite_run(self.h, n_sweeps, 1 if use_graph else 0))
+
+    def shapes(self):
+        n = self.nrow * self.ncol
+        shp = (C.c_int64 * (5 * n))()
+        self.ctx.check(self.ctx.lib.hpeps_ite_get_state(self.h, shp, None))
+        return [tuple(shp[5 * q:5 * q + 5]) for q in range(n)]
+
+    def state(self):
+        """Copies of the current site tensors (list of rows of device tensors)."""
+        torch = _torch()
+        shp = self.shapes()
+        outs = [torch.empty(s, dtype=self.dtype, device=self.device) for s in shp]
+        ptrs = (C.c_void_p * len(outs))(*[t.data_ptr() for t in outs])
+        shp2 = (C.c_int64 * (5 * len(outs)))()
+        self.ctx.check(self.ctx.lib.hpeps_ite_get_state(self.h, shp2, ptrs))
+        return [outs[r * self.ncol:(r + 1) * self.ncol] for r in range(self.nrow)]
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            self.ctx.lib.hpeps_ite_plan_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

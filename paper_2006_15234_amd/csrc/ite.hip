@@ -1,0 +1,665 @@
+// Two-site gate application by QR-SVD (Alg. 1, Eq. 4) and batched TEBD
+// sweeps for imaginary-time evolution (Sec. II-D).
+//
+// One workgroup updates one bond entirely on chip:
+//   1. each site is matricized as (other legs) x (shared bond, p) while it
+//      is gathered into LDS; when it has more rows than columns it is
+//      Householder-QR factored in LDS (the reflectors are parked in a
+//      per-bond global scratch), otherwise Q = I and R is the site itself;
+//   2. Theta = G R1 R2 (d^2 x d^2 gate, tiny);
+//   3. one-sided Jacobi SVD of Theta (<= 32 x 32) with accumulated right
+//      vectors, truncation to D' = min(Dmax, rows, cols), normalisation of the
+//      kept values and the sqrt(s) split;
+//   4. T' = Q [R~; 0] by applying the reflectors in reverse order, scattered
+//      straight into the canonical [u,d,l,r,p] layout with the new bond.
+// Bond dimensions live in a device table, so a whole sweep (four launches,
+// one per layer of non-overlapping bonds) is a static sequence that is
+// captured once in a HIP graph and replayed.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "peps.h"
+
+struct hpeps_ite_plan {
+  hp::Ctx* ctx = nullptr;
+  int nrow = 0, ncol = 0, d = 0;
+  int64_t dmax = 0, cap = 0;
+  double* sites = nullptr;
+  int* dims = nullptr;
+  int* bonds[4] = {nullptr, nullptr, nullptr, nullptr};
+  int nb[4] = {0, 0, 0, 0};
+  double* gates = nullptr;
+  double* scratch = nullptr;
+  int64_t scratch_per = 0;
+  double* sigma = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipStream_t gstream = nullptr;
+  hipEvent_t ev[2] = {nullptr, nullptr};
+};
+
+namespace hp {
+namespace {
+
+constexpr int kT = 256;     // threads per bond workgroup
+constexpr int kMaxTh = 32;  // Theta is at most 32 x 32 (D <= 8, d = 2 or D d^2 <= 32)
+
+struct IteArgs {
+  double* sites;
+  long long cap;
+  int* dims;
+  const int* bonds;  // per bond: s1, s2, axis, gate
+  const double* gates;
+  int dmax;
+  double* scratch;
+  long long scratch_per;
+  double* sigma;     // per bond: dmax values (or null)
+  int max_rows, max_cols;
+};
+
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+// Householder QR in place of the column-major rows x cols matrix A (cols <=
+// rows).  Reflector j is stored in A[j][j..rows) (unnormalised v with
+// H = I - tau v v^T); diag receives R's diagonal.
+__device__ void householder_qr(double* A, int rows, int cols, double* tau, double* diag, double* red) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = kT / 64;
+  for (int j = 0; j < cols; ++j) {
+    double* x = A + (long long)j * rows;
+    double s = 0;
+    for (int r = j + tid; r < rows; r += kT) s += x[r] * x[r];
+    s = wave_sum(s);
+    if (lane == 0) red[wave] = s;
+    __syncthreads();
+    double nrm2 = 0;
+    for (int w = 0; w < nw; ++w) nrm2 += red[w];
+    const double x0 = x[j];
+    __syncthreads();
+    if (nrm2 == 0.0) {
+      if (tid == 0) {
+        tau[j] = 0.0;
+        diag[j] = 0.0;
+      }
+      __syncthreads();
+      continue;
+    }
+    const double alpha = -copysign(sqrt(nrm2), x0);
+    const double v0 = x0 - alpha;
+    const double vn2 = nrm2 - x0 * x0 + v0 * v0;
+    const double t = vn2 > 0 ? 2.0 / vn2 : 0.0;
+    if (tid == 0) {
+      x[j] = v0;
+      tau[j] = t;
+      diag[j] = alpha;
+    }
+    __syncthreads();
+    for (int l = j + 1 + wave; l < cols; l += nw) {
+      double* y = A + (long long)l * rows;
+      double dot = 0;
+      for (int r = j + lane; r < rows; r += 64) dot += x[r] * y[r];
+      dot = wave_sum(dot) * t;
+      for (int r = j + lane; r < rows; r += 64) y[r] -= dot * x[r];
+    }
+    __syncthreads();
+  }
+}
+
+// B (column-major rows x nbc) := Q B with Q = H_0 ... H_{cols-1}.
+__device__ void apply_q(const double* A, int rows, int cols, const double* tau, double* B, int nbc) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = kT / 64;
+  for (int j = cols - 1; j >= 0; --j) {
+    const double* v = A + (long long)j * rows;
+    const double t = tau[j];
+    if (t != 0.0) {
+      for (int q = wave; q < nbc; q += nw) {
+        double* y = B + (long long)q * rows;
+        double dot = 0;
+        for (int r = j + lane; r < rows; r += 64) dot += v[r] * y[r];
+        dot = wave_sum(dot) * t;
+        for (int r = j + lane; r < rows; r += 64) y[r] -= dot * v[r];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+struct SiteGeom {
+  int dims[5];
+  long long st[5];
+  int shared;    // index of the shared leg
+  int other[3];  // the other virtual legs, canonical order
+  int rows, cols;
+};
+
+__device__ void site_geom(const int* dims, int shared, SiteGeom& g) {
+  for (int i = 0; i < 5; ++i) g.dims[i] = dims[i];
+  g.st[4] = 1;
+  for (int i = 3; i >= 0; --i) g.st[i] = g.st[i + 1] * g.dims[i + 1];
+  g.shared = shared;
+  int q = 0;
+  for (int i = 0; i < 4; ++i)
+    if (i != shared) g.other[q++] = i;
+  g.rows = g.dims[g.other[0]] * g.dims[g.other[1]] * g.dims[g.other[2]];
+  g.cols = g.dims[shared] * g.dims[4];
+}
+
+// offset of matricized element (row over the other legs, col = (shared, p))
+__device__ __forceinline__ long long site_off(const SiteGeom& g, int row, int col) {
+  const int p = col % g.dims[4], h = col / g.dims[4];
+  const int o2 = row % g.dims[g.other[2]];
+  const int r1 = row / g.dims[g.other[2]];
+  const int o1 = r1 % g.dims[g.other[1]], o0 = r1 / g.dims[g.other[1]];
+  return o0 * g.st[g.other[0]] + o1 * g.st[g.other[1]] + o2 * g.st[g.other[2]] + h * g.st[g.shared] +
+         (long long)p * g.st[4];
+}
+
+__global__ __launch_bounds__(kT) void qrsvd_bond_kernel(IteArgs a) {
+  extern __shared__ double smem[];
+  const int bi = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = kT / 64;
+  const int s1 = a.bonds[4 * bi], s2 = a.bonds[4 * bi + 1], axis = a.bonds[4 * bi + 2];
+  const double* G = a.gates + (long long)a.bonds[4 * bi + 3] * 0;  // set below once d is known
+  const int matsz = a.max_rows * a.max_cols;
+  double* A = smem;                 // matricized site / reflectors
+  double* Bm = A + matsz;           // output before the scatter
+  double* R1 = Bm + matsz;          // k1 x c (row-major), k1 <= c <= max_cols
+  double* R2 = R1 + a.max_cols * a.max_cols;
+  double* Th = R2 + a.max_cols * a.max_cols;  // Theta, column-major (col * nr + row)
+  double* J = Th + kMaxTh * kMaxTh;   // right vectors, column-major
+  double* small = J + kMaxTh * kMaxTh;
+  double* tau1 = small;
+  double* tau2 = tau1 + kMaxTh;
+  double* diag = tau2 + kMaxTh;
+  double* red = diag + kMaxTh;      // nw entries
+  double* sig = red + 16;
+  double* sv = sig + kMaxTh;        // kept, normalised values
+  __shared__ int perm[kMaxTh];
+  __shared__ int rot;
+  __shared__ SiteGeom g1, g2;
+  if (tid == 0) {
+    site_geom(a.dims + 5 * s1, axis == 0 ? 3 : 1, g1);
+    site_geom(a.dims + 5 * s2, axis == 0 ? 2 : 0, g2);
+  }
+  __syncthreads();
+  const int d = g1.dims[4];
+  G = a.gates + (long long)a.bonds[4 * bi + 3] * d * d * d * d;
+  const int h = g1.dims[g1.shared];
+  double* site1 = a.sites + (long long)s1 * a.cap;
+  double* site2 = a.sites + (long long)s2 * a.cap;
+  double* scr1 = a.scratch + (long long)bi * 2 * a.scratch_per;
+  double* scr2 = scr1 + a.scratch_per;
+
+  // ---- factor both sites ------------------------------------------------
+  int k1, k2;
+  const bool qr1 = g1.rows > g1.cols, qr2 = g2.rows > g2.cols;
+  for (int s = 0; s < 2; ++s) {
+    const SiteGeom& g = s == 0 ? g1 : g2;
+    const double* site = s == 0 ? site1 : site2;
+    double* R = s == 0 ? R1 : R2;
+    double* tau = s == 0 ? tau1 : tau2;
+    double* scr = s == 0 ? scr1 : scr2;
+    const bool qr = s == 0 ? qr1 : qr2;
+    for (int e = tid; e < g.rows * g.cols; e += kT) {
+      const int col = e / g.rows, row = e % g.rows;
+      A[e] = site[site_off(g, row, col)];
+    }
+    __syncthreads();
+    if (qr) {
+      householder_qr(A, g.rows, g.cols, tau, diag, red);
+      for (int e = tid; e < g.cols * g.cols; e += kT) {
+        const int i = e / g.cols, l = e % g.cols;
+        R[e] = (i < l) ? A[(long long)l * g.rows + i] : (i == l ? diag[i] : 0.0);
+      }
+      for (int e = tid; e < g.rows * g.cols; e += kT) scr[e] = A[e];
+    } else {
+      for (int e = tid; e < g.rows * g.cols; e += kT) {
+        const int i = e / g.cols, l = e % g.cols;
+        R[e] = A[(long long)l * g.rows + i];
+      }
+    }
+    __syncthreads();
+  }
+  k1 = qr1 ? g1.cols : g1.rows;
+  k2 = qr2 ? g2.cols : g2.rows;
+
+  // ---- Theta[(k1,a),(b,l)] = sum_{h,i,j} G[a,b,i,j] R1[k1,(h,i)] R2[l,(h,j)] ----
+  const int nr = k1 * d, nc = d * k2;
+  for (int e = tid; e < nr * nc; e += kT) {
+    const int col = e / nr, row = e % nr;
+    const int kk1 = row / d, aa = row % d, bb = col / k2, ll = col % k2;
+    double acc = 0;
+    for (int i = 0; i < d; ++i)
+      for (int j = 0; j < d; ++j) {
+        const double gv = G[((aa * d + bb) * d + i) * d + j];
+        if (gv == 0.0) continue;
+        double w = 0;
+        for (int hh = 0; hh < h; ++hh) w += R1[kk1 * g1.cols + hh * d + i] * R2[ll * g2.cols + hh * d + j];
+        acc += gv * w;
+      }
+    Th[e] = acc;
+  }
+  for (int e = tid; e < nc * nc; e += kT) J[e] = (e / nc == e % nc) ? 1.0 : 0.0;
+  __syncthreads();
+
+  // ---- one-sided Jacobi on the columns of Theta (J accumulates) ----------
+  const int n = (nc + 1) / 2 * 2;
+  const double tol = sqrt((double)nr) * 0x1p-52;
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    if (tid == 0) rot = 0;
+    __syncthreads();
+    for (int round = 0; round < n - 1; ++round) {
+      for (int p = wave; p < n / 2; p += nw) {
+        auto at = [&](int pos) { return pos == 0 ? 0 : 1 + (pos - 1 + round) % (n - 1); };
+        const int ca = at(p), cb = at(n - 1 - p);
+        if (ca >= nc || cb >= nc) continue;
+        double* x = Th + (long long)ca * nr;
+        double* y = Th + (long long)cb * nr;
+        double a2 = 0, b2 = 0, gm = 0;
+        for (int r = lane; r < nr; r += 64) {
+          a2 += x[r] * x[r];
+          b2 += y[r] * y[r];
+          gm += x[r] * y[r];
+        }
+        a2 = wave_sum(a2);
+        b2 = wave_sum(b2);
+        gm = wave_sum(gm);
+        if (a2 > 0 && b2 > 0 && fabs(gm) > tol * sqrt(a2) * sqrt(b2)) {
+          const double zeta = (b2 - a2) / (2.0 * gm);
+          const double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+          const double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
+          for (int r = lane; r < nr; r += 64) {
+            const double xv = x[r], yv = y[r];
+            x[r] = c * xv - s * yv;
+            y[r] = s * xv + c * yv;
+          }
+          double* jx = J + (long long)ca * nc;
+          double* jy = J + (long long)cb * nc;
+          for (int r = lane; r < nc; r += 64) {
+            const double xv = jx[r], yv = jy[r];
+            jx[r] = c * xv - s * yv;
+            jy[r] = s * xv + c * yv;
+          }
+          if (lane == 0) rot = 1;
+        }
+      }
+      __syncthreads();
+    }
+    const bool done = rot == 0;
+    __syncthreads();
+    if (done) break;
+  }
+  for (int c = wave; c < nc; c += nw) {
+    double a2 = 0;
+    for (int r = lane; r < nr; r += 64) a2 += Th[(long long)c * nr + r] * Th[(long long)c * nr + r];
+    a2 = wave_sum(a2);
+    if (lane == 0) sig[c] = sqrt(a2);
+  }
+  __syncthreads();
+  const int Dn = min(a.dmax, min(nr, nc));
+  if (tid == 0) {
+    for (int i = 0; i < nc; ++i) perm[i] = i;
+    for (int i = 1; i < nc; ++i) {
+      const int v = perm[i];
+      int j = i - 1;
+      while (j >= 0 && sig[perm[j]] < sig[v]) {
+        perm[j + 1] = perm[j];
+        --j;
+      }
+      perm[j + 1] = v;
+    }
+    double nn = 0;
+    for (int b = 0; b < Dn; ++b) nn += sig[perm[b]] * sig[perm[b]];
+    nn = sqrt(nn);
+    for (int b = 0; b < Dn; ++b) sv[b] = nn > 0 ? sig[perm[b]] / nn : 0.0;
+    if (a.sigma)
+      for (int b = 0; b < a.dmax; ++b) a.sigma[(long long)bi * a.dmax + b] = b < Dn ? sv[b] : 0.0;
+  }
+  __syncthreads();
+
+  // ---- new sites: T' = Q [R~; 0] with columns (b, p) ---------------------
+  for (int s = 0; s < 2; ++s) {
+    const SiteGeom& g = s == 0 ? g1 : g2;
+    const bool qr = s == 0 ? qr1 : qr2;
+    const int kk = s == 0 ? k1 : k2;
+    const int ncol_out = Dn * d;
+    // R~[kk, (b, a)]
+    for (int e = tid; e < g.rows * ncol_out; e += kT) {
+      const int col = e / g.rows, row = e % g.rows;
+      double v = 0.0;
+      if (row < kk) {
+        const int b = col / d, aa = col % d;
+        const int c = perm[b];
+        const double sg = sig[c];
+        const double rs = sqrt(sv[b]);
+        if (s == 0) {
+          // X[(row, aa), b] = Theta_c[(row, aa)] / sigma_c
+          v = sg > 0 ? Th[(long long)c * nr + row * d + aa] / sg * rs : 0.0;
+        } else {
+          // Y[(aa, row), b] = J[c][(aa, row)]
+          v = J[(long long)c * nc + aa * k2 + row] * rs;
+        }
+      }
+      Bm[e] = v;
+    }
+    __syncthreads();
+    if (qr) {
+      for (int e = tid; e < g.rows * g.cols; e += kT) A[e] = (s == 0 ? scr1 : scr2)[e];
+      __syncthreads();
+      apply_q(A, g.rows, g.cols, s == 0 ? tau1 : tau2, Bm, ncol_out);
+    }
+    // scatter into the canonical layout with the new shared dimension
+    SiteGeom go = g;
+    go.dims[go.shared] = Dn;
+    go.st[4] = 1;
+    for (int i = 3; i >= 0; --i) go.st[i] = go.st[i + 1] * go.dims[i + 1];
+    go.cols = Dn * d;
+    double* site = s == 0 ? site1 : site2;
+    for (int e = tid; e < g.rows * ncol_out; e += kT) {
+      const int col = e / g.rows, row = e % g.rows;
+      site[site_off(go, row, col)] = Bm[e];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    a.dims[5 * s1 + g1.shared] = Dn;
+    a.dims[5 * s2 + g2.shared] = Dn;
+  }
+}
+
+size_t bond_lds_bytes(int max_rows, int max_cols) {
+  return (size_t)(2 * max_rows * max_cols + 2 * max_cols * max_cols + 2 * kMaxTh * kMaxTh + 5 * kMaxTh + 16) *
+         sizeof(double);
+}
+
+void check_dims(int64_t dmax, int d) {
+  HP_REQUIRE(dmax >= 1 && d >= 1, HPEPS_ERR_INVALID_ARG, "bad bond or physical dimension");
+  HP_REQUIRE(dmax * d * d <= kMaxTh, HPEPS_ERR_UNSUPPORTED, "QR-SVD kernel supports D d^2 <= 32");
+  HP_REQUIRE(bond_lds_bytes((int)(dmax * dmax * dmax), (int)(dmax * d)) <= 160 * 1024 - 4096,
+             HPEPS_ERR_UNSUPPORTED, "QR-SVD kernel: site too large for LDS (D^4 d <= 8192)");
+}
+
+void launch_layer(hipStream_t st, const IteArgs& a, int nb) {
+  if (nb == 0) return;
+  const size_t lds = bond_lds_bytes(a.max_rows, a.max_cols);
+  qrsvd_bond_kernel<<<nb, kT, lds, st>>>(a);
+}
+
+IteArgs plan_args(hpeps_ite_plan* p, int layer) {
+  IteArgs a{};
+  a.sites = p->sites;
+  a.cap = p->cap;
+  a.dims = p->dims;
+  a.bonds = p->bonds[layer];
+  a.gates = p->gates;
+  a.dmax = (int)p->dmax;
+  a.scratch = p->scratch;
+  a.scratch_per = p->scratch_per;
+  a.sigma = p->sigma;
+  a.max_rows = (int)(p->dmax * p->dmax * p->dmax);
+  a.max_cols = (int)(p->dmax * p->d);
+  return a;
+}
+
+}  // namespace
+}  // namespace hp
+
+// ---------------------------------------------------------------------------
+// ABI
+
+namespace {
+template <class F>
+hpeps_status guard_i(hp::Ctx* c, F&& f) {
+  try {
+    f();
+    return HPEPS_OK;
+  } catch (const hp::Error& e) {
+    if (c) c->last_error = e.msg;
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    if (c) c->last_error = "host allocation failed";
+    return HPEPS_ERR_ALLOC;
+  } catch (...) {
+    if (c) c->last_error = "unknown error";
+    return HPEPS_ERR_INVALID_ARG;
+  }
+}
+
+void free_plan(hpeps_ite_plan* p) {
+  if (!p) return;
+  if (p->gstream) (void)hipStreamSynchronize(p->gstream);
+  if (p->exec) (void)hipGraphExecDestroy(p->exec);
+  if (p->graph) (void)hipGraphDestroy(p->graph);
+  if (p->gstream) (void)hipStreamDestroy(p->gstream);
+  for (auto e : p->ev)
+    if (e) (void)hipEventDestroy(e);
+  (void)hipFree(p->sites);
+  (void)hipFree(p->dims);
+  for (auto& b : p->bonds) (void)hipFree(b);
+  (void)hipFree(p->gates);
+  (void)hipFree(p->scratch);
+  (void)hipFree(p->sigma);
+  delete p;
+}
+
+// layer lists of a lattice: horizontal bonds at even / odd columns, vertical
+// bonds at even / odd rows; entries (s1, s2, axis)
+std::vector<std::vector<std::array<int, 3>>> lattice_layers(int nrow, int ncol) {
+  std::vector<std::vector<std::array<int, 3>>> L(4);
+  for (int par = 0; par < 2; ++par)
+    for (int i = 0; i < nrow; ++i)
+      for (int j = par; j + 1 < ncol; j += 2) L[par].push_back({i * ncol + j, i * ncol + j + 1, 0});
+  for (int par = 0; par < 2; ++par)
+    for (int i = par; i + 1 < nrow; i += 2)
+      for (int j = 0; j < ncol; ++j) L[2 + par].push_back({i * ncol + j, (i + 1) * ncol + j, 1});
+  return L;
+}
+}  // namespace
+
+extern "C" {
+
+hpeps_status hpeps_ite_plan_create(hpeps_ctx* ctx, const hpeps_peps* init, int32_t n_gates,
+                                   const void* gates, const int32_t* bond_gate, int64_t max_rank,
+                                   hpeps_ite_plan** out) {
+  if (!ctx || !out) return HPEPS_ERR_INVALID_ARG;
+  hp::Ctx& c = *ctx->impl;
+  hpeps_ite_plan* p = nullptr;
+  hpeps_status st = guard_i(&c, [&] {
+    *out = nullptr;
+    HP_REQUIRE(gates && bond_gate && n_gates >= 1, HPEPS_ERR_INVALID_ARG, "null gates");
+    hp::Lattice L = hp::lattice_from_abi(init);
+    HP_REQUIRE(!L.cplx, HPEPS_ERR_DTYPE, "the batched QR-SVD sweep is FP64 real");
+    const int d = (int)L.sites[0].dims[4];
+    hp::check_dims(max_rank, d);
+    for (auto& t : L.sites)
+      for (int e = 0; e < 4; ++e) HP_REQUIRE(t.dims[e] <= max_rank, HPEPS_ERR_SHAPE, "initial bond exceeds max_rank");
+    p = new hpeps_ite_plan();
+    p->ctx = &c;
+    p->nrow = L.nrow;
+    p->ncol = L.ncol;
+    p->d = d;
+    p->dmax = max_rank;
+    p->cap = max_rank * max_rank * max_rank * max_rank * d;
+    const int ns = L.nrow * L.ncol;
+    HP_CHECK_HIP(hipMalloc(&p->sites, (size_t)ns * p->cap * sizeof(double)));
+    std::vector<int> dims(5 * ns);
+    for (int s = 0; s < ns; ++s) {
+      HP_CHECK_HIP(hipMemcpyAsync(p->sites + (int64_t)s * p->cap, L.sites[s].p, L.sites[s].size() * sizeof(double),
+                                  hipMemcpyDeviceToDevice, c.stream));
+      for (int e = 0; e < 5; ++e) dims[5 * s + e] = (int)L.sites[s].dims[e];
+    }
+    HP_CHECK_HIP(hipMalloc(&p->dims, dims.size() * sizeof(int)));
+    HP_CHECK_HIP(hipMemcpy(p->dims, dims.data(), dims.size() * sizeof(int), hipMemcpyHostToDevice));
+    auto layers = lattice_layers(L.nrow, L.ncol);
+    int q = 0, maxnb = 0;
+    for (int l = 0; l < 4; ++l) {
+      std::vector<int> tb;
+      for (auto& bd : layers[l]) {
+        const int gi = bond_gate[q++];
+        HP_REQUIRE(gi >= 0 && gi < n_gates, HPEPS_ERR_INVALID_ARG, "gate index out of range");
+        tb.insert(tb.end(), {bd[0], bd[1], bd[2], gi});
+      }
+      p->nb[l] = (int)layers[l].size();
+      maxnb = std::max(maxnb, p->nb[l]);
+      if (!tb.empty()) {
+        HP_CHECK_HIP(hipMalloc(&p->bonds[l], tb.size() * sizeof(int)));
+        HP_CHECK_HIP(hipMemcpy(p->bonds[l], tb.data(), tb.size() * sizeof(int), hipMemcpyHostToDevice));
+      }
+    }
+    const size_t gsz = (size_t)n_gates * d * d * d * d * sizeof(double);
+    HP_CHECK_HIP(hipMalloc(&p->gates, gsz));
+    HP_CHECK_HIP(hipMemcpyAsync(p->gates, gates, gsz, hipMemcpyDeviceToDevice, c.stream));
+    p->scratch_per = max_rank * max_rank * max_rank * max_rank * d;
+    HP_CHECK_HIP(hipMalloc(&p->scratch, (size_t)std::max(maxnb, 1) * 2 * p->scratch_per * sizeof(double)));
+    HP_CHECK_HIP(hipMalloc(&p->sigma, (size_t)std::max(maxnb, 1) * max_rank * sizeof(double)));
+    const size_t lds = hp::bond_lds_bytes((int)(max_rank * max_rank * max_rank), (int)(max_rank * d));
+    HP_CHECK_HIP(hipFuncSetAttribute((const void*)hp::qrsvd_bond_kernel,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    HP_CHECK_HIP(hipStreamSynchronize(c.stream));
+  });
+  if (st != HPEPS_OK) {
+    free_plan(p);
+    return st;
+  }
+  *out = p;
+  return HPEPS_OK;
+}
+
+hpeps_status hpeps_ite_run(hpeps_ite_plan* p, int32_t n_sweeps, int32_t use_graph) {
+  if (!p || n_sweeps < 0) return HPEPS_ERR_INVALID_ARG;
+  hp::Ctx& c = *p->ctx;
+  return guard_i(&c, [&] {
+    auto sweep = [&](hipStream_t st) {
+      for (int l = 0; l < 4; ++l) hp::launch_layer(st, hp::plan_args(p, l), p->nb[l]);
+    };
+    if (!use_graph) {
+      for (int s = 0; s < n_sweeps; ++s) sweep(c.stream);
+      HP_CHECK_HIP(hipGetLastError());
+      return;
+    }
+    // the graph is captured on the plan's own stream (default priority) and
+    // ordered after / before the context stream's work through events
+    if (!p->exec) {
+      HP_CHECK_HIP(hipStreamCreateWithFlags(&p->gstream, hipStreamNonBlocking));
+      HP_CHECK_HIP(hipEventCreateWithFlags(&p->ev[0], hipEventDisableTiming));
+      HP_CHECK_HIP(hipEventCreateWithFlags(&p->ev[1], hipEventDisableTiming));
+      HP_CHECK_HIP(hipStreamBeginCapture(p->gstream, hipStreamCaptureModeThreadLocal));
+      sweep(p->gstream);
+      HP_CHECK_HIP(hipStreamEndCapture(p->gstream, &p->graph));
+      HP_CHECK_HIP(hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0));
+    }
+    HP_CHECK_HIP(hipEventRecord(p->ev[0], c.stream));
+    HP_CHECK_HIP(hipStreamWaitEvent(p->gstream, p->ev[0], 0));
+    for (int s = 0; s < n_sweeps; ++s) HP_CHECK_HIP(hipGraphLaunch(p->exec, p->gstream));
+    HP_CHECK_HIP(hipEventRecord(p->ev[1], p->gstream));
+    HP_CHECK_HIP(hipStreamWaitEvent(c.stream, p->ev[1], 0));
+  });
+}
+
+hpeps_status hpeps_ite_get_state(hpeps_ite_plan* p, int64_t* shapes, void* const* sites) {
+  if (!p || !shapes) return HPEPS_ERR_INVALID_ARG;
+  hp::Ctx& c = *p->ctx;
+  return guard_i(&c, [&] {
+    const int ns = p->nrow * p->ncol;
+    std::vector<int> dims(5 * ns);
+    HP_CHECK_HIP(hipMemcpyAsync(dims.data(), p->dims, dims.size() * sizeof(int), hipMemcpyDeviceToHost, c.stream));
+    HP_CHECK_HIP(hipStreamSynchronize(c.stream));
+    for (int i = 0; i < 5 * ns; ++i) shapes[i] = dims[i];
+    if (sites) {
+      for (int s = 0; s < ns; ++s) {
+        int64_t sz = 1;
+        for (int e = 0; e < 5; ++e) sz *= dims[5 * s + e];
+        HP_REQUIRE(sites[s], HPEPS_ERR_INVALID_ARG, "null site buffer");
+        HP_CHECK_HIP(hipMemcpyAsync(sites[s], p->sites + (int64_t)s * p->cap, sz * sizeof(double),
+                                    hipMemcpyDeviceToDevice, c.stream));
+      }
+      HP_CHECK_HIP(hipStreamSynchronize(c.stream));
+    }
+  });
+}
+
+hpeps_status hpeps_ite_plan_destroy(hpeps_ite_plan* p) {
+  if (!p) return HPEPS_ERR_INVALID_ARG;
+  (void)hipStreamSynchronize(p->ctx->stream);
+  free_plan(p);
+  return HPEPS_OK;
+}
+
+hpeps_status hpeps_apply_two_site_gate(hpeps_ctx* ctx, hpeps_peps* peps, const int64_t* capacity, int32_t i,
+                                       int32_t j, int32_t axis, const void* G, int64_t max_rank,
+                                       int64_t* new_bond, double* sigma_out) {
+  if (!ctx) return HPEPS_ERR_INVALID_ARG;
+  hp::Ctx& c = *ctx->impl;
+  return guard_i(&c, [&] {
+    c.ws_reset();
+    HP_REQUIRE(peps && capacity && G && new_bond, HPEPS_ERR_INVALID_ARG, "null argument");
+    HP_REQUIRE(axis == 0 || axis == 1, HPEPS_ERR_INVALID_ARG, "axis must be 0 or 1");
+    hp::Lattice L = hp::lattice_from_abi(peps);
+    HP_REQUIRE(!L.cplx, HPEPS_ERR_DTYPE, "the QR-SVD kernel is FP64 real");
+    const int i2 = axis == 0 ? i : i + 1, j2 = axis == 0 ? j + 1 : j;
+    HP_REQUIRE(i >= 0 && j >= 0 && i2 < L.nrow && j2 < L.ncol, HPEPS_ERR_INVALID_ARG, "bond outside the lattice");
+    const int d = (int)L.sites[0].dims[4];
+    hp::check_dims(max_rank, d);
+    const int q1 = i * L.ncol + j, q2 = i2 * L.ncol + j2;
+    const hp::DevTensor &T1 = L.sites[q1], &T2 = L.sites[q2];
+    for (int e = 0; e < 4; ++e)
+      HP_REQUIRE(T1.dims[e] <= max_rank && T2.dims[e] <= max_rank, HPEPS_ERR_SHAPE, "bond exceeds max_rank");
+    // new bond, from the shapes alone
+    const int sh1 = axis == 0 ? 3 : 1, sh2 = axis == 0 ? 2 : 0;
+    const int64_t rows1 = T1.size() / (T1.dims[sh1] * d), rows2 = T2.size() / (T2.dims[sh2] * d);
+    const int64_t c1 = T1.dims[sh1] * d, c2 = T2.dims[sh2] * d;
+    const int64_t k1 = std::min(rows1, c1), k2 = std::min(rows2, c2);
+    const int64_t Dn = std::min<int64_t>(max_rank, std::min(k1 * d, d * k2));
+    HP_REQUIRE(capacity[q1] >= T1.size() / T1.dims[sh1] * Dn && capacity[q2] >= T2.size() / T2.dims[sh2] * Dn,
+               HPEPS_ERR_SHAPE, "site buffers too small for the new bond");
+    const int64_t cap = max_rank * max_rank * max_rank * max_rank * d;
+    double* arena = c.ws<double>(2 * cap);
+    int* dims_dev = c.ws<int>(10);
+    int* bond_dev = c.ws<int>(4);
+    double* gate_dev = c.ws<double>(d * d * d * d);
+    double* scratch = c.ws<double>(2 * cap);
+    double* sig = c.ws<double>(max_rank);
+    int hd[10], hb[4] = {0, 1, axis, 0};
+    for (int e = 0; e < 5; ++e) {
+      hd[e] = (int)T1.dims[e];
+      hd[5 + e] = (int)T2.dims[e];
+    }
+    HP_CHECK_HIP(hipMemcpyAsync(arena, T1.p, T1.size() * 8, hipMemcpyDeviceToDevice, c.stream));
+    HP_CHECK_HIP(hipMemcpyAsync(arena + cap, T2.p, T2.size() * 8, hipMemcpyDeviceToDevice, c.stream));
+    HP_CHECK_HIP(hipMemcpyAsync(dims_dev, hd, sizeof(hd), hipMemcpyHostToDevice, c.stream));
+    HP_CHECK_HIP(hipMemcpyAsync(bond_dev, hb, sizeof(hb), hipMemcpyHostToDevice, c.stream));
+    HP_CHECK_HIP(hipMemcpyAsync(gate_dev, G, d * d * d * d * 8, hipMemcpyDeviceToDevice, c.stream));
+    hp::IteArgs a{};
+    a.sites = arena;
+    a.cap = cap;
+    a.dims = dims_dev;
+    a.bonds = bond_dev;
+    a.gates = gate_dev;
+    a.dmax = (int)max_rank;
+    a.scratch = scratch;
+    a.scratch_per = cap;
+    a.sigma = sig;
+    a.max_rows = (int)(max_rank * max_rank * max_rank);
+    a.max_cols = (int)(max_rank * d);
+    const size_t lds = hp::bond_lds_bytes(a.max_rows, a.max_cols);
+    HP_CHECK_HIP(hipFuncSetAttribute((const void*)hp::qrsvd_bond_kernel,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    hp::launch_layer(c.stream, a, 1);
+    HP_CHECK_HIP(hipGetLastError());
+    int64_t* shp = const_cast<int64_t*>(peps->shapes);
+    shp[5 * q1 + sh1] = Dn;
+    shp[5 * q2 + sh2] = Dn;
+    const int64_t n1 = T1.size() / T1.dims[sh1] * Dn, n2 = T2.size() / T2.dims[sh2] * Dn;
+    HP_CHECK_HIP(hipMemcpyAsync(T1.p, arena, n1 * 8, hipMemcpyDeviceToDevice, c.stream));
+    HP_CHECK_HIP(hipMemcpyAsync(T2.p, arena + cap, n2 * 8, hipMemcpyDeviceToDevice, c.stream));
+    if (sigma_out)
+      HP_CHECK_HIP(hipMemcpyAsync(sigma_out, sig, Dn * 8, hipMemcpyDeviceToDevice, c.stream));
+    HP_CHECK_HIP(hipStreamSynchronize(c.stream));
+    *new_bond = Dn;
+  });
+}
+
+}  // extern "C"
