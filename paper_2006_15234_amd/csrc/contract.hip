@@ -1,0 +1,108 @@
+// Two-operand tensor contraction by named legs, lowered to one gathered
+// GEMM: legs present in both operands and absent from the output are summed
+// (K), legs of only one operand become the rows (M, from A) or columns
+// (N, from B) of the product, the output is written in the row-major order
+// of its leg string.  Used for the strip contractions of expectation values.
+#include "contract.h"
+
+namespace hp {
+
+TView tview(const void* p, const std::string& legs, const std::vector<int64_t>& dims,
+            const std::vector<int64_t>& strides, int64_t extent, bool conj) {
+  HP_REQUIRE(legs.size() == dims.size() && dims.size() == strides.size(), HPEPS_ERR_SHAPE,
+             "tensor view: legs/dims/strides lengths differ");
+  TView v;
+  v.p = p;
+  v.legs = legs;
+  v.dims = dims;
+  v.strides = strides;
+  v.extent = extent;
+  v.conj = conj;
+  return v;
+}
+
+TView tview_rm(const void* p, const std::string& legs, const std::vector<int64_t>& dims, bool conj) {
+  int64_t n = 1;
+  for (auto d : dims) n *= d;
+  return tview(p, legs, dims, rm_strides(dims), n, conj);
+}
+
+int64_t leg_dim(const TView& t, char c) {
+  const auto pos = t.legs.find(c);
+  return pos == std::string::npos ? -1 : t.dims[pos];
+}
+
+std::vector<int64_t> contract2(Ctx& ctx, bool cplx, const TView& A, const TView& B,
+                               const std::string& out, void* C, int64_t c_capacity) {
+  auto dim_of = [&](char c) {
+    const int64_t a = leg_dim(A, c), b = leg_dim(B, c);
+    HP_REQUIRE(a < 0 || b < 0 || a == b, HPEPS_ERR_SHAPE, std::string("leg dims differ for ") + c);
+    return a >= 0 ? a : b;
+  };
+  std::vector<int64_t> odims;
+  for (char c : out) {
+    const int64_t d = dim_of(c);
+    HP_REQUIRE(d >= 1, HPEPS_ERR_SHAPE, std::string("output leg not in the operands: ") + c);
+    HP_REQUIRE(!(leg_dim(A, c) >= 0 && leg_dim(B, c) >= 0), HPEPS_ERR_SHAPE,
+               std::string("leg in both operands and the output: ") + c);
+    odims.push_back(d);
+  }
+  const auto ost = rm_strides(odims);
+  int64_t osize = 1;
+  for (auto d : odims) osize *= d;
+  HP_REQUIRE(osize <= c_capacity, HPEPS_ERR_SHAPE, "contraction output exceeds its buffer");
+  GemmDesc D;
+  D.M = D.N = D.K = 1;
+  // M: legs of A kept in the output (output order), N: legs of B kept
+  for (size_t i = 0; i < out.size(); ++i) {
+    const char c = out[i];
+    const auto pa = A.legs.find(c);
+    if (pa != std::string::npos) {
+      D.Am.add(A.dims[pa], A.strides[pa]);
+      D.Cm.add(odims[i], ost[i]);
+      D.M *= odims[i];
+    } else {
+      const auto pb = B.legs.find(c);
+      D.Bn.add(B.dims[pb], B.strides[pb]);
+      D.Cn.add(odims[i], ost[i]);
+      D.N *= odims[i];
+    }
+  }
+  // K: legs shared by A and B and absent from the output
+  for (size_t i = 0; i < A.legs.size(); ++i) {
+    const char c = A.legs[i];
+    if (out.find(c) != std::string::npos) continue;
+    const auto pb = B.legs.find(c);
+    HP_REQUIRE(pb != std::string::npos, HPEPS_ERR_SHAPE,
+               std::string("leg of A neither summed nor kept: ") + c);
+    HP_REQUIRE(A.dims[i] == B.dims[pb], HPEPS_ERR_SHAPE, std::string("summed leg dims differ: ") + c);
+    D.Ak.add(A.dims[i], A.strides[i]);
+    D.Bk.add(B.dims[pb], B.strides[pb]);
+    D.K *= A.dims[i];
+  }
+  for (char c : B.legs)
+    HP_REQUIRE(out.find(c) != std::string::npos || A.legs.find(c) != std::string::npos, HPEPS_ERR_SHAPE,
+               std::string("leg of B neither summed nor kept: ") + c);
+  // index maps need at least one mode
+  if (D.Am.n == 0) D.Am.add(1, 0);
+  if (D.Cm.n == 0) D.Cm.add(1, 0);
+  if (D.Bn.n == 0) D.Bn.add(1, 0);
+  if (D.Cn.n == 0) D.Cn.add(1, 0);
+  if (D.Ak.n == 0) {
+    D.Ak.add(1, 0);
+    D.Bk.add(1, 0);
+  }
+  GemmCall g;
+  g.A = A.p;
+  g.B = B.p;
+  g.C = C;
+  g.sA = A.extent;
+  g.sB = B.extent;
+  g.sC = osize;
+  g.conjA = cplx && A.conj;
+  g.conjB = cplx && B.conj;
+  gemm(ctx, cplx ? Prec::C128 : Prec::F64, D, g);
+  return odims;
+}
+
+}  // namespace hp

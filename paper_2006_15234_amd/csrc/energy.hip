@@ -1,0 +1,421 @@
+// Expectation values <psi|H|psi>/<psi|psi> of H = sum_t H_t with cached
+// environments (Eq. 5, Sec. IV-B).
+//
+// Two boundary passes (top-down, bottom-up) store every intermediate boundary
+// MPS.  A one-site or horizontal two-site term on row i is read from a
+// three-layer strip (top environment of the rows above i, row i, bottom
+// environment of the rows below); a vertical term on rows i, i+1 from a
+// four-layer strip.  For every strip the left and right strip environments
+// are contracted once (the right ones as left environments of the mirrored
+// strip), then each site or bond yields a reduced density matrix by one more
+// column transfer with the physical legs left open.  A term's value is
+// tr(O rho) / tr(rho); the normalisation of the environments cancels.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "contract.h"
+#include "peps.h"
+
+namespace hp {
+namespace {
+
+struct Ten {
+  void* p = nullptr;
+  std::string legs;
+  std::vector<int64_t> dims;
+  int64_t size() const {
+    int64_t s = 1;
+    for (auto d : dims) s *= d;
+    return s;
+  }
+  TView view(bool conj = false) const { return tview_rm(p, legs, dims, conj); }
+};
+
+TView bview(const BndView& b, const std::string& legs) {
+  return tview(b.p, legs, {b.n[0], b.n[1], b.n[2], b.n[3]}, {b.s[0], b.s[1], b.s[2], b.s[3]}, b.extent);
+}
+TView sview(const SiteView& s, const std::string& legs, bool conj) {
+  return tview(s.p, legs, {s.n[0], s.n[1], s.n[2], s.n[3], s.n[4]}, {s.s[0], s.s[1], s.s[2], s.s[3], s.s[4]},
+               s.extent, conj);
+}
+
+int64_t out_size(const TView& A, const TView& B, const std::string& out) {
+  int64_t n = 1;
+  for (char c : out) {
+    const int64_t a = leg_dim(A, c), b = leg_dim(B, c);
+    n *= a >= 0 ? a : b;
+  }
+  return n;
+}
+
+Ten contract(Ctx& ctx, bool cplx, const TView& A, const TView& B, const std::string& out) {
+  Ten t;
+  t.legs = out;
+  const int64_t n = out_size(A, B, out);
+  t.p = ctx.ws<double>(n * (cplx ? 2 : 1));
+  t.dims = contract2(ctx, cplx, A, B, out, t.p, n);
+  return t;
+}
+
+std::string spectators(const std::string& legs, const std::string& core) {
+  std::string s;
+  for (char c : legs)
+    if (core.find(c) == std::string::npos) s += c;
+  return s;
+}
+
+// the last contraction of a chain writes into a buffer allocated before the
+// chain's scratch, so the scratch can be released
+Ten alloc_out(Ctx& ctx, bool cplx, const TView& A, const TView& B, const std::string& out) {
+  Ten t;
+  t.legs = out;
+  for (char c : out) {
+    const int64_t a = leg_dim(A, c), b = leg_dim(B, c);
+    t.dims.push_back(a >= 0 ? a : b);
+  }
+  t.p = ctx.ws<double>(t.size() * (cplx ? 2 : 1));
+  return t;
+}
+
+// One column of a three-layer strip: L[spec,t,l,L,b] -> L'[spec,s,r,R,c(,p,P)].
+Ten transfer3(Ctx& ctx, bool cplx, const Ten& L, const BndView& top, const SiteView& ket, const SiteView& bra,
+              const BndView& bot, bool open) {
+  const std::string sp = spectators(L.legs, "tlLb");
+  const std::string out = sp + (open ? "srRcpP" : "srRc");
+  // output dims: spectators from L, s/c from the environments, r/R/p/P from the sites
+  Ten res;
+  res.legs = out;
+  for (char ch : out) {
+    int64_t dd = leg_dim(L.view(), ch);
+    if (ch == 's') dd = top.n[3];
+    if (ch == 'c') dd = bot.n[3];
+    if (ch == 'r') dd = ket.n[3];
+    if (ch == 'R') dd = bra.n[3];
+    if (ch == 'p' || ch == 'P') dd = ket.n[4];
+    res.dims.push_back(dd);
+  }
+  res.p = ctx.ws<double>(res.size() * (cplx ? 2 : 1));
+  {
+    WsScope scope(ctx);
+    Ten x1 = contract(ctx, cplx, L.view(), bview(top, "tuUs"), sp + "lLbuUs");
+    Ten x2 = contract(ctx, cplx, x1.view(), sview(ket, "udlrp", false), sp + "LbUsdrp");
+    Ten x3 = contract(ctx, cplx, x2.view(), sview(bra, open ? "UDLRP" : "UDLRp", true),
+                      sp + (open ? "bsdrDRpP" : "bsdrDR"));
+    contract2(ctx, cplx, x3.view(), bview(bot, "bdDc"), out, res.p, res.size());
+  }
+  return res;
+}
+
+// One column of a four-layer strip: L[spec,t,l,L,m,M,b] -> L'[spec,s,r,R,n,N,c(,p,P,q,Q)].
+Ten transfer4(Ctx& ctx, bool cplx, const Ten& L, const BndView& top, const SiteView& k1, const SiteView& b1,
+              const SiteView& k2, const SiteView& b2, const BndView& bot, bool open) {
+  const std::string sp = spectators(L.legs, "tlLmMb");
+  const std::string o1 = open ? "pP" : "", o2 = open ? "qQ" : "";
+  const std::string out = sp + "srRnNc" + o1 + o2;
+  Ten res;
+  res.legs = out;
+  for (char ch : out) {
+    int64_t dd = leg_dim(L.view(), ch);
+    if (ch == 's') dd = top.n[3];
+    if (ch == 'c') dd = bot.n[3];
+    if (ch == 'r') dd = k1.n[3];
+    if (ch == 'R') dd = b1.n[3];
+    if (ch == 'n') dd = k2.n[3];
+    if (ch == 'N') dd = b2.n[3];
+    if (ch == 'p' || ch == 'P' || ch == 'q' || ch == 'Q') dd = k1.n[4];
+    res.dims.push_back(dd);
+  }
+  res.p = ctx.ws<double>(res.size() * (cplx ? 2 : 1));
+  {
+    WsScope scope(ctx);
+    Ten x1 = contract(ctx, cplx, L.view(), bview(top, "tuUs"), sp + "lLmMbuUs");
+    Ten x2 = contract(ctx, cplx, x1.view(), sview(k1, "uvlrp", false), sp + "LmMbUsvrp");
+    Ten x3 = contract(ctx, cplx, x2.view(), sview(b1, open ? "UVLRP" : "UVLRp", true), sp + "mMbsvrVR" + o1);
+    Ten x4 = contract(ctx, cplx, x3.view(), sview(k2, "vdmnq", false), sp + "MbsrVRdnq" + o1);
+    Ten x5 = contract(ctx, cplx, x4.view(), sview(b2, open ? "VDMNQ" : "VDMNq", true), sp + "bsrRdnDN" + o1 + o2);
+    contract2(ctx, cplx, x5.view(), bview(bot, "bdDc"), out, res.p, res.size());
+  }
+  return res;
+}
+
+Ten ones(Ctx& ctx, bool cplx, const std::string& legs) {
+  Ten t;
+  t.legs = legs;
+  t.dims.assign(legs.size(), 1);
+  t.p = ctx.ws<double>(cplx ? 2 : 1);
+  fill_value(ctx, (double*)t.p, 1, 1.0, cplx);
+  return t;
+}
+
+// scalar terms: out[2t..2t+1] = tr(O rho) / tr(rho) (complex)
+__global__ void expect_kernel(const double* const* rdm, const double* const* ops, const int* nsites, int d, int cplx,
+                              int nterms, double* out) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nterms) return;
+  const double* r = rdm[t];
+  const double* o = ops[t];
+  double nr = 0, ni = 0, dr = 0, di = 0;
+  auto rho = [&](long long idx, double& re, double& im) {
+    if (cplx) {
+      re = r[2 * idx];
+      im = r[2 * idx + 1];
+    } else {
+      re = r[idx];
+      im = 0;
+    }
+  };
+  if (nsites[t] == 1) {
+    for (int p = 0; p < d; ++p)
+      for (int P = 0; P < d; ++P) {
+        double re, im;
+        rho((long long)p * d + P, re, im);
+        const double orr = o[2 * (P * d + p)], oi = o[2 * (P * d + p) + 1];
+        nr += orr * re - oi * im;
+        ni += orr * im + oi * re;
+        if (p == P) {
+          dr += re;
+          di += im;
+        }
+      }
+  } else {
+    for (int p1 = 0; p1 < d; ++p1)
+      for (int P1 = 0; P1 < d; ++P1)
+        for (int p2 = 0; p2 < d; ++p2)
+          for (int P2 = 0; P2 < d; ++P2) {
+            double re, im;
+            rho(((long long)(p1 * d + P1) * d + p2) * d + P2, re, im);
+            const long long oo = ((P1 * d + P2) * d + p1) * d + p2;
+            const double orr = o[2 * oo], oi = o[2 * oo + 1];
+            nr += orr * re - oi * im;
+            ni += orr * im + oi * re;
+            if (p1 == P1 && p2 == P2) {
+              dr += re;
+              di += im;
+            }
+          }
+  }
+  const double den = dr * dr + di * di;
+  out[2 * t] = (nr * dr + ni * di) / den;
+  out[2 * t + 1] = (ni * dr - nr * di) / den;
+}
+
+}  // namespace
+}  // namespace hp
+
+// ---------------------------------------------------------------------------
+// ABI
+
+namespace {
+template <class F>
+hpeps_status guard_e(hpeps_ctx* ctx, F&& f) {
+  if (!ctx) return HPEPS_ERR_INVALID_ARG;
+  try {
+    ctx->impl->ws_reset();
+    f(*ctx->impl);
+    return HPEPS_OK;
+  } catch (const hp::Error& e) {
+    ctx->impl->last_error = e.msg;
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    ctx->impl->last_error = "host allocation failed";
+    return HPEPS_ERR_ALLOC;
+  } catch (...) {
+    ctx->impl->last_error = "unknown error";
+    return HPEPS_ERR_INVALID_ARG;
+  }
+}
+}  // namespace
+
+extern "C" hpeps_status hpeps_peps_energy(hpeps_ctx* ctx, const hpeps_peps* ket, int32_t n_terms,
+                                          const int32_t* nsites, const int32_t* sites, const double* ops,
+                                          const int64_t* op_offset, const hpeps_esvd_opts* opts, double* energy,
+                                          double* per_term) {
+  using namespace hp;
+  return guard_e(ctx, [&](Ctx& c) {
+    HP_REQUIRE(opts && opts->rank >= 1 && opts->oversample >= 0 && opts->power_iters >= 0, HPEPS_ERR_INVALID_ARG,
+               "bad einsumsvd options");
+    HP_REQUIRE(n_terms >= 0 && energy && (n_terms == 0 || (nsites && sites && ops && op_offset)),
+               HPEPS_ERR_INVALID_ARG, "null argument");
+    Lattice K = lattice_from_abi(ket);
+    const bool cplx = K.cplx;
+    const int nrow = K.nrow, ncol = K.ncol, d = (int)K.sites[0].dims[4];
+    // validate terms
+    for (int t = 0; t < n_terms; ++t) {
+      const int* s = sites + 4 * t;
+      HP_REQUIRE(nsites[t] == 1 || nsites[t] == 2, HPEPS_ERR_INVALID_ARG, "terms act on 1 or 2 sites");
+      HP_REQUIRE(s[0] >= 0 && s[0] < nrow && s[1] >= 0 && s[1] < ncol, HPEPS_ERR_INVALID_ARG, "site out of range");
+      if (nsites[t] == 2) {
+        const bool horiz = s[2] == s[0] && s[3] == s[1] + 1, vert = s[3] == s[1] && s[2] == s[0] + 1;
+        HP_REQUIRE(horiz || vert, HPEPS_ERR_INVALID_ARG, "two-site terms must be nearest neighbours, site 1 first");
+      }
+      HP_REQUIRE(op_offset[t] >= 0, HPEPS_ERR_INVALID_ARG, "bad operator offset");
+    }
+    double* logd = c.ws<double>(1);
+    fill_value(c, logd, 1, 0.0, false);
+    Lattice Kn = normalized_copy(c, K, logd);
+    std::vector<std::vector<DevTensor>> tenv, benv;
+    if (nrow > 1) {
+      boundary_pass(c, Kn, Kn, kTop, *opts, nrow - 1, tenv, logd);
+      boundary_pass(c, Kn, Kn, kBottom, *opts, nrow - 1, benv, logd);
+    }
+    // trivial environment
+    const int es = cplx ? 2 : 1;
+    std::vector<DevTensor> triv(ncol);
+    for (auto& t : triv) {
+      t.dims = {1, 1, 1, 1};
+      t.p = c.ws<double>(es);
+      fill_value(c, (double*)t.p, 1, 1.0, cplx);
+    }
+    auto top_of = [&](int i) -> const std::vector<DevTensor>& { return i == 0 ? triv : tenv[i - 1]; };
+    auto bot_of = [&](int i) -> const std::vector<DevTensor>& { return i == nrow - 1 ? triv : benv[nrow - 2 - i]; };
+    std::vector<const double*> rdm_ptr(n_terms, nullptr);
+    // one reduced density matrix slot per term (d^4 elements), allocated
+    // before the strips so that each strip's scratch can be released
+    const int64_t slot = (int64_t)d * d * d * d * es;
+    double* rdm_store = c.ws<double>(std::max<int64_t>(n_terms, 1) * slot);
+
+    // three-layer strips: one-site and horizontal terms
+    for (int i = 0; i < nrow; ++i) {
+      std::vector<int> here;
+      for (int t = 0; t < n_terms; ++t)
+        if (sites[4 * t] == i && (nsites[t] == 1 || sites[4 * t + 2] == i)) here.push_back(t);
+      if (here.empty()) continue;
+      WsScope strip_scope(c);
+      const auto& top = top_of(i);
+      const auto& bot = bot_of(i);
+      auto col = [&](int j, Dir dir, BndView& tv, SiteView& kv, SiteView& bv, BndView& btv) {
+        tv = orient_bnd(top[j], dir);
+        kv = orient_site(Kn.at(i, j), kTop, dir);
+        bv = kv;
+        btv = orient_bnd(bot[j], dir);
+      };
+      std::vector<Ten> Lenv(ncol + 1), Renv(ncol + 1);
+      Lenv[0] = ones(c, cplx, "tlLb");
+      Renv[0] = ones(c, cplx, "tlLb");
+      for (int q = 0; q < ncol; ++q) {
+        BndView tv, btv;
+        SiteView kv, bv;
+        col(q, kL2R, tv, kv, bv, btv);
+        Ten x = transfer3(c, cplx, Lenv[q], tv, kv, bv, btv, false);
+        normalize(c, cplx, x.p, x.size(), 1, logd);
+        x.legs = "tlLb";
+        Lenv[q + 1] = x;
+        col(ncol - 1 - q, kR2L, tv, kv, bv, btv);
+        Ten y = transfer3(c, cplx, Renv[q], tv, kv, bv, btv, false);
+        normalize(c, cplx, y.p, y.size(), 1, logd);
+        y.legs = "tlLb";
+        Renv[q + 1] = y;
+      }
+      std::map<std::pair<int, int>, const double*> cache;  // (j, 1|2) -> rdm
+      for (int t : here) {
+        const int j = sites[4 * t + 1];
+        const int kind = nsites[t];
+        auto key = std::make_pair(j, kind);
+        if (!cache.count(key)) {
+          BndView tv, btv;
+          SiteView kv, bv;
+          col(j, kL2R, tv, kv, bv, btv);
+          double* dst = rdm_store + (int64_t)t * slot;
+          Ten y = transfer3(c, cplx, Lenv[j], tv, kv, bv, btv, true);  // srRcpP
+          if (kind == 1) {
+            Ten R = Renv[ncol - 1 - j];
+            R.legs = "srRc";
+            contract2(c, cplx, y.view(), R.view(), "pP", dst, slot / es);
+          } else {
+            y.legs = "tlLbef";
+            col(j + 1, kL2R, tv, kv, bv, btv);
+            Ten y2 = transfer3(c, cplx, y, tv, kv, bv, btv, true);  // efsrRcpP
+            Ten R = Renv[ncol - 2 - j];
+            R.legs = "srRc";
+            contract2(c, cplx, y2.view(), R.view(), "efpP", dst, slot / es);
+          }
+          cache[key] = dst;
+        }
+        rdm_ptr[t] = cache[key];
+      }
+    }
+    // four-layer strips: vertical terms
+    for (int i = 0; i + 1 < nrow; ++i) {
+      std::vector<int> here;
+      for (int t = 0; t < n_terms; ++t)
+        if (nsites[t] == 2 && sites[4 * t] == i && sites[4 * t + 2] == i + 1) here.push_back(t);
+      if (here.empty()) continue;
+      WsScope strip_scope(c);
+      const auto& top = top_of(i);
+      const auto& bot = bot_of(i + 1);
+      auto col = [&](int j, Dir dir, BndView& tv, SiteView& k1, SiteView& k2, BndView& btv) {
+        tv = orient_bnd(top[j], dir);
+        k1 = orient_site(Kn.at(i, j), kTop, dir);
+        k2 = orient_site(Kn.at(i + 1, j), kTop, dir);
+        btv = orient_bnd(bot[j], dir);
+      };
+      std::vector<Ten> Lenv(ncol + 1), Renv(ncol + 1);
+      Lenv[0] = ones(c, cplx, "tlLmMb");
+      Renv[0] = ones(c, cplx, "tlLmMb");
+      for (int q = 0; q < ncol; ++q) {
+        BndView tv, btv;
+        SiteView k1, k2;
+        col(q, kL2R, tv, k1, k2, btv);
+        Ten x = transfer4(c, cplx, Lenv[q], tv, k1, k1, k2, k2, btv, false);
+        normalize(c, cplx, x.p, x.size(), 1, logd);
+        x.legs = "tlLmMb";
+        Lenv[q + 1] = x;
+        col(ncol - 1 - q, kR2L, tv, k1, k2, btv);
+        Ten y = transfer4(c, cplx, Renv[q], tv, k1, k1, k2, k2, btv, false);
+        normalize(c, cplx, y.p, y.size(), 1, logd);
+        y.legs = "tlLmMb";
+        Renv[q + 1] = y;
+      }
+      std::map<int, const double*> cache;
+      for (int t : here) {
+        const int j = sites[4 * t + 1];
+        if (!cache.count(j)) {
+          BndView tv, btv;
+          SiteView k1, k2;
+          col(j, kL2R, tv, k1, k2, btv);
+          Ten y = transfer4(c, cplx, Lenv[j], tv, k1, k1, k2, k2, btv, true);  // srRnNcpPqQ
+          Ten R = Renv[ncol - 1 - j];
+          R.legs = "srRnNc";
+          double* dst = rdm_store + (int64_t)t * slot;
+          contract2(c, cplx, y.view(), R.view(), "pPqQ", dst, slot / es);
+          cache[j] = dst;
+        }
+        rdm_ptr[t] = cache[j];
+      }
+    }
+    // term values on the device
+    double* res = c.ws<double>(2 * std::max(n_terms, 1));
+    if (n_terms > 0) {
+      int64_t total = 0;
+      for (int t = 0; t < n_terms; ++t) total = std::max<int64_t>(total, op_offset[t] + (nsites[t] == 1 ? d * d : d * d * d * d));
+      double* ops_dev = c.ws<double>(2 * total);
+      HP_CHECK_HIP(hipMemcpyAsync(ops_dev, ops, 2 * total * sizeof(double), hipMemcpyHostToDevice, c.stream));
+      std::vector<const double*> op_ptr(n_terms);
+      for (int t = 0; t < n_terms; ++t) op_ptr[t] = ops_dev + 2 * op_offset[t];
+      auto* rp = c.ws<const double*>(n_terms);
+      auto* op = c.ws<const double*>(n_terms);
+      int* ns = c.ws<int>(n_terms);
+      HP_CHECK_HIP(hipMemcpyAsync(rp, rdm_ptr.data(), n_terms * sizeof(void*), hipMemcpyHostToDevice, c.stream));
+      HP_CHECK_HIP(hipMemcpyAsync(op, op_ptr.data(), n_terms * sizeof(void*), hipMemcpyHostToDevice, c.stream));
+      HP_CHECK_HIP(hipMemcpyAsync(ns, nsites, n_terms * sizeof(int), hipMemcpyHostToDevice, c.stream));
+      expect_kernel<<<cdiv(n_terms, 64), 64, 0, c.stream>>>(rp, op, ns, d, cplx ? 1 : 0, n_terms, res);
+      HP_CHECK_HIP(hipGetLastError());
+    }
+    std::vector<double> h(2 * std::max(n_terms, 1));
+    HP_CHECK_HIP(hipMemcpyAsync(h.data(), res, h.size() * sizeof(double), hipMemcpyDeviceToHost, c.stream));
+    HP_CHECK_HIP(hipStreamSynchronize(c.stream));
+    double er = 0, ei = 0;
+    for (int t = 0; t < n_terms; ++t) {
+      HP_REQUIRE(std::isfinite(h[2 * t]) && std::isfinite(h[2 * t + 1]), HPEPS_ERR_NUMERIC, "non-finite term value");
+      er += h[2 * t];
+      ei += h[2 * t + 1];
+      if (per_term) {
+        per_term[2 * t] = h[2 * t];
+        per_term[2 * t + 1] = h[2 * t + 1];
+      }
+    }
+    energy[0] = er;
+    energy[1] = ei;
+  });
+}
