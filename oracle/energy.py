@@ -35,14 +35,31 @@ def _trivial_env(ncol, dtype):
     return [np.ones((1, 1, 1, 1), dtype=dtype) for _ in range(ncol)]
 
 
+# One column of a strip, one pairwise contraction per tensor (multi-operand
+# einsum path searches can be orders of magnitude slower).
 def _col3(L, Tp, T, O, B, Bt):
-    return np.einsum("tlLb,tuUs,udlrp,Pp,UDLRP,bdDc->srRc",
-                     L, Tp, T, O, B.conj(), Bt, optimize=True)
+    TO = np.einsum("Pp,udlrp->udlrP", O, T)
+    X = np.einsum("tlLb,tuUs->lLbuUs", L, Tp)
+    X = np.einsum("lLbuUs,udlrP->LbUsdrP", X, TO)
+    X = np.einsum("LbUsdrP,UDLRP->bsdrDR", X, B.conj())
+    return np.einsum("bsdrDR,bdDc->srRc", X, Bt)
 
 
 def _col4(L, Tp, T1, O1, B1, T2, O2, B2, Bt):
-    return np.einsum("tlLmMb,tuUs,uvlrp,Pp,UVLRP,vdmnq,Qq,VDMNQ,bdDc->srRnNc",
-                     L, Tp, T1, O1, B1.conj(), T2, O2, B2.conj(), Bt, optimize=True)
+    T1O = np.einsum("Pp,uvlrp->uvlrP", O1, T1)
+    T2O = np.einsum("Qq,vdmnq->vdmnQ", O2, T2)
+    X = np.einsum("tlLmMb,tuUs->lLmMbuUs", L, Tp)
+    X = np.einsum("lLmMbuUs,uvlrP->LmMbUsvrP", X, T1O)
+    X = np.einsum("LmMbUsvrP,UVLRP->mMbsvrVR", X, B1.conj())
+    X = np.einsum("mMbsvrVR,vdmnQ->MbsrVRdnQ", X, T2O)
+    X = np.einsum("MbsrVRdnQ,VDMNQ->bsrRdnDN", X, B2.conj())
+    return np.einsum("bsrRdnDN,bdDc->srRnNc", X, Bt)
+
+
+def _mirror3(Tp, T, B, Bt):
+    """The strip mirrored left-right: right environments are left ones of it."""
+    return (Tp.transpose(3, 1, 2, 0), T.transpose(0, 1, 3, 2, 4), B.transpose(0, 1, 3, 2, 4),
+            Bt.transpose(3, 1, 2, 0))
 
 
 def _norm(x):
@@ -60,9 +77,8 @@ def _row_terms(top, ket_row, bot, terms_here, d, dtype):
     # right environments by mirroring the transfer: contract from the right
     Rs = [np.ones((1, 1, 1, 1), dtype=dtype)]
     for j in reversed(range(n)):
-        R = np.einsum("srRc,tuUs,udlrp,Pp,UDLRP,bdDc->tlLb", Rs[-1], top[j], ket_row[j], I,
-                      ket_row[j].conj(), bot[j], optimize=True)
-        Rs.append(_norm(R))
+        Tp, T, B, Bt = _mirror3(top[j], ket_row[j], ket_row[j], bot[j])
+        Rs.append(_norm(_col3(Rs[-1], Tp, T, I, B, Bt)))
     Rs = Rs[::-1]  # Rs[j] = environment right of column j-1 (covers columns j..n-1)
     out = []
     for sites, op in terms_here:
@@ -93,9 +109,9 @@ def _pair_terms(top, row1, row2, bot, terms_here, d, dtype):
         Ls.append(_norm(_col4(Ls[-1], top[j], row1[j], I, row1[j], row2[j], I, row2[j], bot[j])))
     Rs = [one]
     for j in reversed(range(n)):
-        R = np.einsum("srRnNc,tuUs,uvlrp,Pp,UVLRP,vdmnq,Qq,VDMNQ,bdDc->tlLmMb", Rs[-1], top[j],
-                      row1[j], I, row1[j].conj(), row2[j], I, row2[j].conj(), bot[j], optimize=True)
-        Rs.append(_norm(R))
+        Tp, T1, _, Bt = _mirror3(top[j], row1[j], row1[j], bot[j])
+        T2 = row2[j].transpose(0, 1, 3, 2, 4)
+        Rs.append(_norm(_col4(Rs[-1], Tp, T1, I, T1, T2, I, T2, Bt)))
     Rs = Rs[::-1]
     out = []
     for sites, op in terms_here:
