@@ -35,7 +35,7 @@ struct Error {
 // ---------------------------------------------------------------------------
 // index maps: a linear index i over a list of modes (last mode fastest) maps
 // to the element offset sum_m idx_m * stride_m.
-constexpr int kMaxModes = 8;
+constexpr int kMaxModes = 12;
 struct IndexMap {
   int n = 0;
   int64_t dim[kMaxModes];
@@ -46,6 +46,7 @@ struct IndexMap {
     return s;
   }
   IndexMap& add(int64_t d, int64_t s) {
+    if (n >= kMaxModes) throw Error{HPEPS_ERR_UNSUPPORTED, "too many index modes in one operand"};
     dim[n] = d;
     stride[n] = s;
     ++n;

@@ -163,7 +163,16 @@ void absorb_row(Ctx& ctx, bool cplx, const std::vector<BndView>& bnd,
     cl.nT = ket[0].extent;
     cl.nB = bra[0].extent;
     form_carry(ctx, cplx, cd, cl, bnd[0].p, ket[0].p, bra[0].p, carry[0], 1);
-    normalize(ctx, cplx, carry[0], cd.a * cd.x * cd.x * cd.b * cd.h * cd.h, 1, log_dev);
+    const int64_t nv = cd.a * cd.x * cd.x * cd.b * cd.h * cd.h;
+    normalize(ctx, cplx, carry[0], nv, 1, log_dev);
+    if (n == 1) {
+      // a one-column row has no einsumsvd: the exact carry is the boundary
+      // ([1, x, X, 1] in either direction)
+      out[0].dims = {cd.a, cd.x, cd.x, cd.b * cd.h * cd.h};
+      HP_CHECK_HIP(hipMemcpyAsync(out[0].p, carry[0], nv * es * sizeof(double), hipMemcpyDeviceToDevice,
+                                  ctx.stream));
+      return;
+    }
   }
   int cur = 0;
   int64_t a = bnd[0].n[0], x = ket[0].n[1], b = bnd[0].n[3], h = ket[0].n[3];
