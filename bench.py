@@ -69,6 +69,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--cpu-sample", type=int, default=8,
                     help="instances the CPU oracle baseline runs (0 disables it)")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="use the size heuristic for every GEMM instead of tuning during warmup")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: --gpus {args.gpus} is not supported (this build runs "
@@ -89,6 +91,8 @@ def main():
         return hp.einsumsvd_pair(ctx, *dev, rank=RANK, oversample=OVERS, power_iters=POW, seed=0,
                                  stream_id=1, precision=prec, absorb=hp.ABSORB_NONE)
 
+    # the first warm-up step tunes the tile shape of every product (untimed)
+    hp.autotune_enable(ctx, not args.no_autotune)
     for _ in range(max(args.warmup, 1)):
         step("f64")
     torch.cuda.synchronize()
@@ -155,6 +159,7 @@ def main():
         "fp32_apply": {"value": round(flops / (ms32 * 1e-3) / 1e9, 2), "unit": "GFLOP/s",
                        "ms_per_step": round(ms32, 4), "speedup_vs_f64": round(ms / ms32, 3),
                        "eps_sigma_vs_f64": eps32},
+        "autotune": not args.no_autotune,
         "kernel_classes": {n: {"ms_per_step": round(a["ms"], 4), "launches": a["launches"]}
                            for n, a in sorted(agg.items(), key=lambda x: -x[1]["ms"])},
     }

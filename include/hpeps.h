@@ -144,6 +144,27 @@ hpeps_status hpeps_profile_stop(hpeps_ctx* ctx);
 hpeps_status hpeps_profile_read(hpeps_ctx* ctx, int32_t max_entries, hpeps_profile_entry* out,
                                 int32_t* n_out);
 
+/* ---- autotuner of the contraction kernels ----------------------------------
+ * Each contraction runs as a gathered MFMA GEMM with a tile shape, a K-step
+ * (16 or 32) and a split-K count.  By default a size heuristic chooses them.
+ * With autotuning on, the first product of every new key (precision, M, N,
+ * K, batch, operand layouts) times each variant on the call's own operands
+ * and keeps the fastest; later products of that key reuse the choice.  The
+ * tuning call synchronises the context stream.  Products that accumulate
+ * into their output, whose output overlaps an input, or that are issued
+ * during stream capture are never tuned (they use the heuristic).  Results
+ * are the same whichever variant runs, up to floating-point summation order
+ * (split-K partial sums). */
+hpeps_status hpeps_autotune_enable(hpeps_ctx* ctx, int32_t on);
+/* The tuned choices as JSON text {"gemm": {"<key>": [tile, kstep, split]}}.
+ * Writes at most cap bytes, NUL-terminated, to buf (when buf is non-NULL);
+ * *needed receives the full length + 1.  Host memory. */
+hpeps_status hpeps_autotune_export(hpeps_ctx* ctx, char* buf, int64_t cap, int64_t* needed);
+/* Merges choices from text written by hpeps_autotune_export (a context of
+ * the same device type); HPEPS_ERR_INVALID_ARG on malformed text, in which
+ * case nothing is merged. */
+hpeps_status hpeps_autotune_import(hpeps_ctx* ctx, const char* json);
+
 /* ---- sketch -------------------------------------------------------------
  * Writes the sketch Omega that an einsumsvd with (seed, stream_id) draws:
  * batch blocks of n*k values (block b uses stream_id + b), element i of a

@@ -42,6 +42,13 @@ hpeps_status hpeps_test_zip_apply(hpeps_ctx* ctx, hpeps_dtype dtype, int64_t bat
                                   const void* T, const void* Bra, int64_t k, int32_t adjoint,
                                   const void* X, void* Y);
 
+/* Forces the launch variant of every following GEMM of the context (tile
+ * shape index 0..9, K-step multiple 1 or 2, split-K count or 0 for the
+ * heuristic), so that the tests can cover each kernel instantiation;
+ * tile = -1 returns to the normal selection.  Unknown or unsupported tile
+ * indices fall back to the heuristic. */
+hpeps_status hpeps_test_gemm_variant(hpeps_ctx* ctx, int32_t tile, int32_t kstep, int32_t split);
+
 #ifdef __cplusplus
 }
 #endif

@@ -13,5 +13,6 @@ from ._ffi import (  # noqa: F401
 from .api import (  # noqa: F401
     einsumsvd_zipup, einsumsvd_pair, peps_norm, boundary_contract_row, peps_energy,
     apply_two_site_gate, ItePlan, get_info, sketch, make_opts, profile_start, profile_stop,
-    profile_read,
+    profile_read, autotune_enable, autotune_export, autotune_import, autotune_save,
+    autotune_load,
 )

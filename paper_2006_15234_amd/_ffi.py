@@ -60,6 +60,9 @@ _SIGS = {
     "hpeps_last_error": (C.c_char_p, [_P]),
     "hpeps_set_workspace_limit": (C.c_int, [_P, C.c_int64]),
     "hpeps_get_info": (C.c_int, [_P, C.POINTER(EsvdInfo)]),
+    "hpeps_autotune_enable": (C.c_int, [_P, C.c_int32]),
+    "hpeps_autotune_export": (C.c_int, [_P, C.c_char_p, C.c_int64, _I64P]),
+    "hpeps_autotune_import": (C.c_int, [_P, C.c_char_p]),
     "hpeps_profile_start": (C.c_int, [_P, C.c_char_p]),
     "hpeps_profile_stop": (C.c_int, [_P]),
     "hpeps_profile_read": (C.c_int, [_P, C.c_int32, C.c_void_p, C.POINTER(C.c_int32)]),
@@ -83,6 +86,7 @@ _SIGS = {
     "hpeps_ite_get_state": (C.c_int, [_P, _I64P, C.POINTER(C.c_void_p)]),
     "hpeps_ite_plan_destroy": (C.c_int, [_P]),
     # include/hpeps_testing.h
+    "hpeps_test_gemm_variant": (C.c_int, [_P, C.c_int32, C.c_int32, C.c_int32]),
     "hpeps_test_gemm": (C.c_int, [_P, C.c_int, C.c_int64, C.c_int64, C.c_int64, C.c_int64,
                                   C.c_int32, _P, _P, _P]),
     "hpeps_test_orthogonalize": (C.c_int, [_P, C.c_int, C.c_int64, C.c_int64, C.c_int64, _P, _P]),

@@ -128,6 +128,35 @@ def profile_read(ctx):
                                        bytes=buf[i].bytes) for i in range(min(n.value, 128))}
 
 
+def autotune_enable(ctx, on=True):
+    """Turns the per-shape GEMM autotuner of the context on or off."""
+    ctx.check(ctx.lib.hpeps_autotune_enable(ctx.h, 1 if on else 0))
+
+
+def autotune_export(ctx):
+    """The tuned GEMM variants as JSON text."""
+    need = C.c_int64()
+    ctx.check(ctx.lib.hpeps_autotune_export(ctx.h, None, 0, C.byref(need)))
+    buf = C.create_string_buffer(need.value)
+    ctx.check(ctx.lib.hpeps_autotune_export(ctx.h, buf, need.value, C.byref(need)))
+    return buf.value.decode()
+
+
+def autotune_import(ctx, text):
+    """Merges tuned variants from JSON text written by ``autotune_export``."""
+    ctx.check(ctx.lib.hpeps_autotune_import(ctx.h, text.encode()))
+
+
+def autotune_save(ctx, path):
+    with open(path, "w") as f:
+        f.write(autotune_export(ctx))
+
+
+def autotune_load(ctx, path):
+    with open(path) as f:
+        autotune_import(ctx, f.read())
+
+
 def get_info(ctx):
     info = EsvdInfo()
     ctx.check(ctx.lib.hpeps_get_info(ctx.h, C.byref(info)))

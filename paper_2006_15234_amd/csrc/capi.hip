@@ -108,6 +108,30 @@ hpeps_status hpeps_get_info(hpeps_ctx* ctx, hpeps_esvd_info* info) {
   });
 }
 
+hpeps_status hpeps_autotune_enable(hpeps_ctx* ctx, int32_t on) {
+  if (!ctx) return HPEPS_ERR_INVALID_ARG;
+  ctx->impl->autotune = on != 0;
+  return HPEPS_OK;
+}
+
+hpeps_status hpeps_autotune_export(hpeps_ctx* ctx, char* buf, int64_t cap, int64_t* needed) {
+  if (!ctx || !needed || (buf && cap <= 0)) return HPEPS_ERR_INVALID_ARG;
+  return guard(ctx, [&] {
+    const std::string s = hp::autotune_export(*ctx->impl);
+    *needed = (int64_t)s.size() + 1;
+    if (buf) {
+      const int64_t n = std::min<int64_t>(cap - 1, (int64_t)s.size());
+      memcpy(buf, s.data(), (size_t)n);
+      buf[n] = '\0';
+    }
+  });
+}
+
+hpeps_status hpeps_autotune_import(hpeps_ctx* ctx, const char* json) {
+  if (!ctx || !json) return HPEPS_ERR_INVALID_ARG;
+  return guard(ctx, [&] { hp::autotune_import(*ctx->impl, json); });
+}
+
 hpeps_status hpeps_profile_start(hpeps_ctx* ctx, const char* filter) {
   if (!ctx) return HPEPS_ERR_INVALID_ARG;
   ctx->impl->prof_on = true;

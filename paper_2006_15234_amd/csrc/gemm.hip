@@ -13,16 +13,33 @@
 // paper's reshape-avoiding design, Sec. V-C).
 //
 // Tiling: 256 threads = 4 wavefronts of 64 lanes; the block tile is
-// (WM*TM*16) x (WN*TN*16) with K-steps of 16, each wavefront owns TM x TN
+// (WM*TM*16) x (WN*TN*16) with K-steps of 16*KS, each wavefront owns TM x TN
 // 16x16 MFMA tiles (v_mfma_f64_16x16x4 for FP64 and complex128,
-// v_mfma_f32_16x16x4 for FP32).  Operand tiles are staged through LDS with a
-// register prefetch of the next K-step; the load mapping follows the
-// contiguous direction of each operand so that global loads coalesce.
-// Blocks are renumbered so that neighbouring tiles land on the same XCD
-// (consecutive hardware block ids are dealt round-robin over the 8 XCDs).
+// v_mfma_f32_16x16x4 for FP32).
+//  * LDS holds both operand tiles k-contiguous ([row][k], rows padded by 16
+//    bytes so that the 16 rows one MFMA reads fall in distinct bank groups).
+//    Lane (i, q) of a wavefront feeds the MFMA sub-steps of a K-step with the
+//    k values 4 KS q .. 4 KS q + 4 KS - 1 of its row, fetched with 128-bit LDS
+//    reads; A and B use the same k assignment, so the product is unchanged.
+//  * Two LDS stages: the global loads of K-step t+1 are in flight in
+//    registers while step t computes, then land in the other stage; one
+//    barrier per K-step.
+//  * K offsets: affine K index maps are computed (k * step); general ones
+//    are staged from their table into LDS once per block.
+//  * Work items (tile, K-split part, instance) are dealt to the 8 XCDs in
+//    contiguous ranges (consecutive hardware block ids go round-robin over
+//    the XCDs), so the tiles of one instance share an L2, and no XCD is left
+//    without work when the tile count is not a multiple of 8.
+// The tile shape, K-step and split-K count of each product come from a size
+// heuristic or from the autotuner, which times every variant on the first
+// product of a new shape/layout key and caches the winner (JSON export and
+// import through the C ABI).
 #include <algorithm>
 #include <climits>
 #include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <tuple>
 
 #include "internal.h"
 
@@ -43,10 +60,13 @@ struct GemmArgs {
   const int* cC;
   long long sA, sB, sC;
   int M, N, K;
-  int mtiles, ntiles, ntotal;
+  int mtiles, ntotal;   // tiles of one instance
   int ksplit, kchunk;
+  int nwork, per_xcd;   // ntotal * batch * ksplit work items; ceil(nwork / 8)
   int conjA, conjB, conjC;
   int a_kfast, b_kfast;
+  int tabA, tabB;       // K offsets from LDS tables (else k * step)
+  int a_kstep, b_kstep;
   int accumulate;
   double alpha;
   const double* scale;
@@ -54,6 +74,7 @@ struct GemmArgs {
   long long nscale_ld;
   const int* copy_if_zero;
   void* partial;
+  unsigned nA_bytes, nB_bytes;  // per-instance operand extents (buffer ranges)
 };
 
 template <class T>
@@ -64,12 +85,28 @@ struct Mfma<double> {
   static __device__ __forceinline__ acc_t op(double a, double b, acc_t c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
   }
+  // four consecutive values of a 16-byte aligned LDS row
+  static __device__ __forceinline__ void quad(const double* p, double* v) {
+    const double2 x = reinterpret_cast<const double2*>(p)[0];
+    const double2 y = reinterpret_cast<const double2*>(p)[1];
+    v[0] = x.x;
+    v[1] = x.y;
+    v[2] = y.x;
+    v[3] = y.y;
+  }
 };
 template <>
 struct Mfma<float> {
   using acc_t = v4f;
   static __device__ __forceinline__ acc_t op(float a, float b, acc_t c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ void quad(const float* p, float* v) {
+    const float4 x = reinterpret_cast<const float4*>(p)[0];
+    v[0] = x.x;
+    v[1] = x.y;
+    v[2] = x.z;
+    v[3] = x.w;
   }
 };
 
@@ -88,6 +125,27 @@ __device__ __forceinline__ Elem<TC, CPLX> load_in(const TIn* p, long long off, b
     e.im = conj ? (TC)(-v.y) : (TC)v.y;
   } else {
     e.re = (TC)p[off];
+    e.im = (TC)0;
+  }
+  return e;
+}
+
+typedef double d2v __attribute__((ext_vector_type(2)));
+
+// One element through a buffer resource (byte offset; zero when past the
+// extent).  Complex values are (re, im) double pairs.
+template <class TC, bool CPLX, class TIn>
+__device__ __forceinline__ Elem<TC, CPLX> buf_load(__amdgpu_buffer_rsrc_t r, unsigned off) {
+  Elem<TC, CPLX> e;
+  if constexpr (CPLX) {
+    const d2v v = __builtin_bit_cast(d2v, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+    e.re = (TC)v[0];
+    e.im = (TC)v[1];
+  } else if constexpr (sizeof(TIn) == 8) {
+    e.re = (TC)__builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+    e.im = (TC)0;
+  } else {
+    e.re = (TC)__builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
     e.im = (TC)0;
   }
   return e;
@@ -118,36 +176,51 @@ __device__ __forceinline__ void epilogue(const GemmArgs& g, int b, int m, int n,
   re *= s;
   im *= s;
   if (g.conjC) im = -im;
-  TOut* C = reinterpret_cast<TOut*>(g.C) + (CPLX ? 0 : 0);
+  TOut* C = reinterpret_cast<TOut*>(g.C);
   long long off = (long long)b * g.sC + (long long)g.rC[m] + (long long)g.cC[n];
   store_out<CPLX, TOut>(C, off, re, im, g.accumulate != 0);
 }
 
-template <class TC, bool CPLX, class TIn, class TOut, int WM, int WN, int TM, int TN>
+// Tile position of element e for an operand whose rows (M or N index) are
+// contiguous in memory: each group of 16 lanes reads 16 consecutive rows
+// (one 128-byte line) at one k, the four groups of a wavefront take four
+// consecutive k.  In the k-contiguous LDS tile ([row][k], row pitch an odd
+// multiple of 16 bytes) the 64-bit writes of each half-wavefront then hit
+// distinct banks.
+template <int R>
+__device__ __forceinline__ void tile_pos(int e, int& row, int& kk) {
+  const int li = e & 15, grp = (e >> 4) & 3, rest = e >> 6;
+  row = (rest % (R / 16)) * 16 + li;
+  kk = (rest / (R / 16)) * 4 + grp;
+}
+
+template <class TC, bool CPLX, class TIn, class TOut, int WM, int WN, int TM, int TN, int KS>
 __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
-  constexpr int BM = WM * TM * 16, BN = WN * TN * 16, BK = 16;
-  constexpr int LDA = BM + 1, LDB = BN + 1;
-  constexpr int NA = BM * BK / 256, NB = BN * BK / 256;
+  constexpr int BM = WM * TM * 16, BN = WN * TN * 16, BK = 16 * KS;
+  constexpr int LDK = BK + 16 / (int)sizeof(TC);  // row pitch (elements), odd multiple of 16 B
+  constexpr int NA = BM * BK / 256, NB = BN * BK / 256;  // elements each thread loads per K-step
+  constexpr int KQ = 4 * KS;                              // k values per lane and row per K-step
   constexpr int NP = CPLX ? 2 : 1;
+  constexpr int SA = BM * LDK, SB = BN * LDK;
+  constexpr int STAGE = NP * (SA + SB);
   using acc_t = typename Mfma<TC>::acc_t;
 
-  __shared__ TC sA[NP][BK * LDA];
-  __shared__ TC sB[NP][BK * LDB];
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  TC* sbuf = reinterpret_cast<TC*>(smem_raw);
+  int* sKA = reinterpret_cast<int*>(sbuf + 2 * STAGE);
+  int* sKB = sKA + (g.tabA ? g.kchunk : 0);
 
-  // XCD-aware renumbering of the tile index (see header comment)
-  const int nb = gridDim.x;
-  const int bid = blockIdx.x;
-  const int per = nb / 8;  // grid.x is padded to a multiple of 8
-  const int tile = (bid % 8) * per + bid / 8;
-  if (tile >= g.ntotal) return;
+  // work item of this block (see header comment)
+  const int w = (int)(blockIdx.x & 7) * g.per_xcd + (int)(blockIdx.x >> 3);
+  if (w >= g.nwork) return;
+  const int tile = w % g.ntotal;
+  const int rest = w / g.ntotal;
+  const int ks = rest % g.ksplit, b = rest / g.ksplit;
   const int mt = tile % g.mtiles, nt = tile / g.mtiles;
-  const int bz = blockIdx.y;
-  const int b = bz / g.ksplit, ks = bz % g.ksplit;
   const int m0 = mt * BM, n0 = nt * BN;
   const int tid = threadIdx.x;
 
-  const TIn* A = reinterpret_cast<const TIn*>(g.A) + (CPLX ? 0 : 0);
-  const TIn* B = reinterpret_cast<const TIn*>(g.B);
+  const TIn* A = reinterpret_cast<const TIn*>(g.A);
   const long long aoff = (long long)b * g.sA, boff = (long long)b * g.sB;
 
   if (g.copy_if_zero && g.copy_if_zero[b] == 0) {
@@ -166,54 +239,110 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
 
   const int kbeg = ks * g.kchunk;
   const int kend = min(g.K, kbeg + g.kchunk);
+  // staged K tables, zero-padded to the chunk length so that every table
+  // read of the loop below stays in range
+  if (g.tabA)
+    for (int t = tid; t < g.kchunk; t += 256) sKA[t] = kbeg + t < kend ? g.cA[kbeg + t] : 0;
+  if (g.tabB)
+    for (int t = tid; t < g.kchunk; t += 256) sKB[t] = kbeg + t < kend ? g.rB[kbeg + t] : 0;
 
-  // per-thread fixed row / column offsets of the elements this thread loads
-  int a_mm[NA], a_kk[NA], a_roff[NA];
-  int b_nn[NB], b_kk[NB], b_coff[NB];
+  // Buffer resources over this instance's operands.  A load whose byte
+  // offset lies past the extent returns zero: ragged tile edges and the K
+  // tail are padded by giving such elements the offset 0xffffffff, without
+  // branches.
+  constexpr unsigned ELT = CPLX ? 16u : (unsigned)sizeof(TIn);
+  constexpr unsigned kOut = 0xffffffffu;
+  const auto rsA = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<char*>(reinterpret_cast<const char*>(g.A) + aoff * ELT), (short)0, (int)g.nA_bytes,
+      0x00020000);
+  const auto rsB = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<char*>(reinterpret_cast<const char*>(g.B) + boff * ELT), (short)0, (int)g.nB_bytes,
+      0x00020000);
+
+  // (row, k) position of element i of this thread in a K-step tile; the
+  // mapping follows the contiguous direction of each operand so that global
+  // loads coalesce.  Kept per element: LDS slot, k within the step, and the
+  // row offset (-1 past the last row).
+  int a_lds[NA], a_kk[NA], a_roff[NA];
+  int b_lds[NB], b_kk[NB], b_coff[NB];
 #pragma unroll
   for (int i = 0; i < NA; ++i) {
     const int e = tid + i * 256;
+    int row, kk;
     if (g.a_kfast) {
-      a_kk[i] = e % BK;
-      a_mm[i] = e / BK;
+      kk = e % BK;
+      row = e / BK;
     } else {
-      a_mm[i] = e % BM;
-      a_kk[i] = e / BM;
+      tile_pos<BM>(e, row, kk);
     }
-    const int m = m0 + a_mm[i];
+    a_lds[i] = row * LDK + kk;
+    a_kk[i] = kk;
+    const int m = m0 + row;
     a_roff[i] = (m < g.M) ? g.rA[m] : -1;
   }
 #pragma unroll
   for (int i = 0; i < NB; ++i) {
     const int e = tid + i * 256;
+    int col, kk;
     if (g.b_kfast) {
-      b_kk[i] = e % BK;
-      b_nn[i] = e / BK;
+      kk = e % BK;
+      col = e / BK;
     } else {
-      b_nn[i] = e % BN;
-      b_kk[i] = e / BN;
+      tile_pos<BN>(e, col, kk);
     }
-    const int n = n0 + b_nn[i];
+    b_lds[i] = col * LDK + kk;
+    b_kk[i] = kk;
+    const int n = n0 + col;
     b_coff[i] = (n < g.N) ? g.cB[n] : -1;
   }
 
   Elem<TC, CPLX> ra[NA], rb[NB];
-  auto load_tiles = [&](int k0) {
+  auto load_global = [&](int k0) {
+    if (g.tabA) {
+#pragma unroll
+      for (int i = 0; i < NA; ++i) {
+        const int k = k0 + a_kk[i];
+        const int ko = sKA[k - kbeg];
+        const bool ok = a_roff[i] >= 0 && k < kend;
+        ra[i] = buf_load<TC, CPLX, TIn>(rsA, ok ? (unsigned)(a_roff[i] + ko) * ELT : kOut);
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < NA; ++i) {
+        const int k = k0 + a_kk[i];
+        const bool ok = a_roff[i] >= 0 && k < kend;
+        ra[i] = buf_load<TC, CPLX, TIn>(rsA, ok ? (unsigned)(a_roff[i] + k * g.a_kstep) * ELT : kOut);
+      }
+    }
+    if (g.tabB) {
+#pragma unroll
+      for (int i = 0; i < NB; ++i) {
+        const int k = k0 + b_kk[i];
+        const int ko = sKB[k - kbeg];
+        const bool ok = b_coff[i] >= 0 && k < kend;
+        rb[i] = buf_load<TC, CPLX, TIn>(rsB, ok ? (unsigned)(b_coff[i] + ko) * ELT : kOut);
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < NB; ++i) {
+        const int k = k0 + b_kk[i];
+        const bool ok = b_coff[i] >= 0 && k < kend;
+        rb[i] = buf_load<TC, CPLX, TIn>(rsB, ok ? (unsigned)(b_coff[i] + k * g.b_kstep) * ELT : kOut);
+      }
+    }
+  };
+  auto store_lds = [&](int stage) {
+    TC* sa = sbuf + stage * STAGE;
+    TC* sb = sa + NP * SA;
 #pragma unroll
     for (int i = 0; i < NA; ++i) {
-      const int k = k0 + a_kk[i];
-      if (a_roff[i] >= 0 && k < kend)
-        ra[i] = load_in<TC, CPLX, TIn>(A, aoff + a_roff[i] + g.cA[k], g.conjA != 0);
-      else
-        ra[i].re = ra[i].im = (TC)0;
+      sa[a_lds[i]] = ra[i].re;
+      if constexpr (CPLX) sa[SA + a_lds[i]] = g.conjA ? -ra[i].im : ra[i].im;
     }
 #pragma unroll
     for (int i = 0; i < NB; ++i) {
-      const int k = k0 + b_kk[i];
-      if (b_coff[i] >= 0 && k < kend)
-        rb[i] = load_in<TC, CPLX, TIn>(B, boff + g.rB[k] + b_coff[i], g.conjB != 0);
-      else
-        rb[i].re = rb[i].im = (TC)0;
+      sb[b_lds[i]] = rb[i].re;
+      if constexpr (CPLX) sb[SB + b_lds[i]] = g.conjB ? -rb[i].im : rb[i].im;
     }
   };
 
@@ -229,51 +358,64 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
   const int wm = wave % WM, wn = wave / WM;
   const int li = lane & 15, lk = lane >> 4;
 
-  if (kbeg < kend) load_tiles(kbeg);
-  for (int k0 = kbeg; k0 < kend; k0 += BK) {
-    __syncthreads();
+  auto compute = [&](int stage) {
+    const TC* sa = sbuf + stage * STAGE + (wm * TM * 16 + li) * LDK + lk * KQ;
+    const TC* sb = sbuf + stage * STAGE + NP * SA + (wn * TN * 16 + li) * LDK + lk * KQ;
+    TC ar[TM][KQ], br[TN][KQ];
 #pragma unroll
-    for (int i = 0; i < NA; ++i) {
-      sA[0][a_kk[i] * LDA + a_mm[i]] = ra[i].re;
-      if constexpr (CPLX) sA[NP - 1][a_kk[i] * LDA + a_mm[i]] = ra[i].im;
-    }
+    for (int i = 0; i < TM; ++i)
 #pragma unroll
-    for (int i = 0; i < NB; ++i) {
-      sB[0][b_kk[i] * LDB + b_nn[i]] = rb[i].re;
-      if constexpr (CPLX) sB[NP - 1][b_kk[i] * LDB + b_nn[i]] = rb[i].im;
-    }
-    __syncthreads();
-    if (k0 + BK < kend) load_tiles(k0 + BK);
+      for (int q = 0; q < KS; ++q) Mfma<TC>::quad(sa + i * 16 * LDK + 4 * q, &ar[i][4 * q]);
 #pragma unroll
-    for (int kk = 0; kk < BK; kk += 4) {
-      TC ar[TM], br[TN];
+    for (int j = 0; j < TN; ++j)
 #pragma unroll
-      for (int i = 0; i < TM; ++i) ar[i] = sA[0][(kk + lk) * LDA + wm * TM * 16 + i * 16 + li];
+      for (int q = 0; q < KS; ++q) Mfma<TC>::quad(sb + j * 16 * LDK + 4 * q, &br[j][4 * q]);
+    if constexpr (!CPLX) {
 #pragma unroll
-      for (int j = 0; j < TN; ++j) br[j] = sB[0][(kk + lk) * LDB + wn * TN * 16 + j * 16 + li];
-      if constexpr (!CPLX) {
+      for (int s = 0; s < KQ; ++s)
 #pragma unroll
         for (int i = 0; i < TM; ++i)
 #pragma unroll
-          for (int j = 0; j < TN; ++j) acc[0][i][j] = Mfma<TC>::op(ar[i], br[j], acc[0][i][j]);
-      } else {
-        TC ai[TM], bi[TN];
+          for (int j = 0; j < TN; ++j) acc[0][i][j] = Mfma<TC>::op(ar[i][s], br[j][s], acc[0][i][j]);
+    } else {
+      TC ai[TM][KQ], bi[TN][KQ];
 #pragma unroll
-        for (int i = 0; i < TM; ++i) ai[i] = sA[1][(kk + lk) * LDA + wm * TM * 16 + i * 16 + li];
+      for (int i = 0; i < TM; ++i)
 #pragma unroll
-        for (int j = 0; j < TN; ++j) bi[j] = sB[1][(kk + lk) * LDB + wn * TN * 16 + j * 16 + li];
-        // acc[0] = Re*Re, acc[1] = Im*Im, acc[2] = Re*Im, acc[3] = Im*Re
+        for (int q = 0; q < KS; ++q) Mfma<TC>::quad(sa + SA + i * 16 * LDK + 4 * q, &ai[i][4 * q]);
+#pragma unroll
+      for (int j = 0; j < TN; ++j)
+#pragma unroll
+        for (int q = 0; q < KS; ++q) Mfma<TC>::quad(sb + SB + j * 16 * LDK + 4 * q, &bi[j][4 * q]);
+      // acc[0] = Re*Re, acc[1] = Im*Im, acc[2] = Re*Im, acc[3] = Im*Re
+#pragma unroll
+      for (int s = 0; s < KQ; ++s)
 #pragma unroll
         for (int i = 0; i < TM; ++i)
 #pragma unroll
           for (int j = 0; j < TN; ++j) {
-            acc[0][i][j] = Mfma<TC>::op(ar[i], br[j], acc[0][i][j]);
-            acc[1][i][j] = Mfma<TC>::op(ai[i], bi[j], acc[1][i][j]);
-            acc[2][i][j] = Mfma<TC>::op(ar[i], bi[j], acc[2][i][j]);
-            acc[3][i][j] = Mfma<TC>::op(ai[i], br[j], acc[3][i][j]);
+            acc[0][i][j] = Mfma<TC>::op(ar[i][s], br[j][s], acc[0][i][j]);
+            acc[1][i][j] = Mfma<TC>::op(ai[i][s], bi[j][s], acc[1][i][j]);
+            acc[2][i][j] = Mfma<TC>::op(ar[i][s], bi[j][s], acc[2][i][j]);
+            acc[3][i][j] = Mfma<TC>::op(ai[i][s], br[j][s], acc[3][i][j]);
           }
-      }
     }
+  };
+
+  __syncthreads();  // K offset tables staged
+  if (kbeg < kend) {
+    load_global(kbeg);
+    store_lds(0);
+  }
+  __syncthreads();
+  int cur = 0;
+  for (int k0 = kbeg; k0 < kend; k0 += BK) {
+    const bool more = k0 + BK < kend;
+    if (more) load_global(k0 + BK);
+    compute(cur);
+    if (more) store_lds(cur ^ 1);
+    __syncthreads();
+    cur ^= 1;
   }
 
   // epilogue: accumulator register r of a lane holds column li of each 16x16
@@ -340,21 +482,36 @@ __global__ void splitk_reduce_kernel(GemmArgs g, int batch) {
 
 namespace {
 
+constexpr int kLdsBytes = 160 * 1024;
+
 struct Cfg {
   int WM, WN, TM, TN;
   int BM() const { return WM * TM * 16; }
   int BN() const { return WN * TN * 16; }
 };
 
-// Tile shapes: a square default and skinny variants for the many products
-// whose N (sketch width k <= 128) or M is small.
+// Tile shapes: square defaults and skinny variants for the many products
+// whose N (sketch width k <= 128) or M (a bond or physical dimension) is small.
 const Cfg kCfgs[] = {
-    {2, 2, 2, 2},  // 64 x 64
-    {4, 1, 2, 3},  // 128 x 48
-    {4, 1, 2, 2},  // 128 x 32
-    {1, 4, 3, 2},  // 48 x 128
-    {2, 2, 2, 4},  // 64 x 128
+    {2, 2, 2, 2},  // 0: 64 x 64
+    {4, 1, 2, 3},  // 1: 128 x 48
+    {4, 1, 2, 2},  // 2: 128 x 32
+    {1, 4, 3, 2},  // 3: 48 x 128
+    {2, 2, 2, 4},  // 4: 64 x 128
+    {2, 2, 4, 2},  // 5: 128 x 64
+    {2, 2, 4, 4},  // 6: 128 x 128
+    {1, 4, 1, 4},  // 7: 16 x 256
+    {4, 1, 4, 1},  // 8: 256 x 16
+    {1, 4, 2, 2},  // 9: 32 x 128
 };
+constexpr int kNumCfgs = sizeof(kCfgs) / sizeof(kCfgs[0]);
+
+// complex products keep four accumulator sets: only shapes with at most four
+// MFMA tiles per wavefront fit the register file
+bool cfg_ok(int ci, bool cplx) { return !cplx || kCfgs[ci].TM * kCfgs[ci].TN <= 4; }
+// the 32-deep K-step doubles the staging registers: complex products and the
+// 16-tile 128 x 128 shape would spill
+bool ks_ok(int ci, int ks, bool cplx) { return ks == 1 || (ks == 2 && !cplx && ci != 6); }
 
 int pick_cfg(int64_t M, int64_t N, bool cplx) {
   auto waste = [&](const Cfg& c) {
@@ -364,10 +521,9 @@ int pick_cfg(int64_t M, int64_t N, bool cplx) {
   };
   int best = 0;
   double bw = 1e30;
-  for (int i = 0; i < 5; ++i) {
-    // complex products keep four accumulator sets: only the 2x2-tile shapes fit
-    if (cplx && kCfgs[i].TM * kCfgs[i].TN > 4) continue;
-    // prefer larger tiles at equal waste (more reuse)
+  for (int i = 0; i < kNumCfgs; ++i) {
+    if (!cfg_ok(i, cplx)) continue;
+    // prefer larger tiles at equal waste (more reuse per loaded element)
     const double w = waste(kCfgs[i]) * (1.0 + 0.02 * (4096.0 / (kCfgs[i].BM() * kCfgs[i].BN())));
     if (w < bw) {
       bw = w;
@@ -377,15 +533,45 @@ int pick_cfg(int64_t M, int64_t N, bool cplx) {
   return best;
 }
 
-template <class TC, bool CPLX, class TIn, class TOut>
-void launch_cfg(int ci, dim3 grid, hipStream_t st, const GemmArgs& a) {
-  switch (ci) {
-    case 0: gemm_kernel<TC, CPLX, TIn, TOut, 2, 2, 2, 2><<<grid, 256, 0, st>>>(a); break;
-    case 1: gemm_kernel<TC, CPLX, TIn, TOut, 4, 1, 2, 3><<<grid, 256, 0, st>>>(a); break;
-    case 2: gemm_kernel<TC, CPLX, TIn, TOut, 4, 1, 2, 2><<<grid, 256, 0, st>>>(a); break;
-    case 3: gemm_kernel<TC, CPLX, TIn, TOut, 1, 4, 3, 2><<<grid, 256, 0, st>>>(a); break;
-    default: gemm_kernel<TC, CPLX, TIn, TOut, 2, 2, 2, 4><<<grid, 256, 0, st>>>(a); break;
+template <class TC, bool CPLX, class TIn, class TOut, int WM, int WN, int TM, int TN, int KS>
+void launch_one(unsigned grid, size_t lds, hipStream_t st, const GemmArgs& a) {
+  if constexpr ((CPLX && (TM * TN > 4 || KS > 1)) || (TM * TN > 8 && KS > 1)) {
+    throw Error{HPEPS_ERR_UNSUPPORTED, "gemm variant not available"};
+  } else {
+    auto kern = gemm_kernel<TC, CPLX, TIn, TOut, WM, WN, TM, TN, KS>;
+    // dynamic LDS above the default 64 KB needs the function attribute raised
+    static size_t lds_allowed = 64 * 1024;
+    if (lds > lds_allowed) {
+      HP_CHECK_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+      lds_allowed = lds;
+    }
+    kern<<<grid, 256, lds, st>>>(a);
   }
+}
+
+template <class TC, bool CPLX, class TIn, class TOut, int KS>
+void launch_cfg(int ci, unsigned grid, size_t lds, hipStream_t st, const GemmArgs& a) {
+  switch (ci) {
+    case 0: launch_one<TC, CPLX, TIn, TOut, 2, 2, 2, 2, KS>(grid, lds, st, a); break;
+    case 1: launch_one<TC, CPLX, TIn, TOut, 4, 1, 2, 3, KS>(grid, lds, st, a); break;
+    case 2: launch_one<TC, CPLX, TIn, TOut, 4, 1, 2, 2, KS>(grid, lds, st, a); break;
+    case 3: launch_one<TC, CPLX, TIn, TOut, 1, 4, 3, 2, KS>(grid, lds, st, a); break;
+    case 4: launch_one<TC, CPLX, TIn, TOut, 2, 2, 2, 4, KS>(grid, lds, st, a); break;
+    case 5: launch_one<TC, CPLX, TIn, TOut, 2, 2, 4, 2, KS>(grid, lds, st, a); break;
+    case 6: launch_one<TC, CPLX, TIn, TOut, 2, 2, 4, 4, KS>(grid, lds, st, a); break;
+    case 7: launch_one<TC, CPLX, TIn, TOut, 1, 4, 1, 4, KS>(grid, lds, st, a); break;
+    case 8: launch_one<TC, CPLX, TIn, TOut, 4, 1, 4, 1, KS>(grid, lds, st, a); break;
+    default: launch_one<TC, CPLX, TIn, TOut, 1, 4, 2, 2, KS>(grid, lds, st, a); break;
+  }
+}
+
+template <class TC, bool CPLX, class TIn, class TOut>
+void launch_ks(int ci, int ks, unsigned grid, size_t lds, hipStream_t st, const GemmArgs& a) {
+  if (ks == 2)
+    launch_cfg<TC, CPLX, TIn, TOut, 2>(ci, grid, lds, st, a);
+  else
+    launch_cfg<TC, CPLX, TIn, TOut, 1>(ci, grid, lds, st, a);
 }
 
 bool innermost_is_k(const IndexMap& mm, const IndexMap& kk) {
@@ -396,6 +582,182 @@ bool innermost_is_k(const IndexMap& mm, const IndexMap& kk) {
   for (int i = 0; i < kk.n; ++i)
     if (kk.dim[i] > 1) sk = std::min(sk, kk.stride[i]);
   return sk < sm;
+}
+
+// Step of an index map whose offsets are i * step for every linear index i
+// (modes nest without gaps); -1 when the map is not affine.
+int64_t affine_step(const IndexMap& m) {
+  int64_t step = -1, span = 1;  // span: element count of the faster modes
+  for (int i = m.n - 1; i >= 0; --i) {
+    if (m.dim[i] == 1) continue;
+    if (step < 0)
+      step = m.stride[i];
+    else if (m.stride[i] != step * span)
+      return -1;
+    span *= m.dim[i];
+  }
+  return step < 0 ? 0 : step;
+}
+
+// Everything a launch needs besides the shared arguments.
+struct Plan {
+  int ci = 0, ks = 1;
+  int64_t ksplit = 1, kchunk = 1;
+  size_t lds = 0;
+  unsigned grid = 0;
+};
+
+Plan make_plan(Prec prec, const GemmDesc& d, const GemmCall& c, const GemmArgs& a, GemmVariant v) {
+  const bool cplx = prec == Prec::C128;
+  Plan p;
+  p.ci = (v.cfg >= 0 && v.cfg < kNumCfgs && cfg_ok(v.cfg, cplx)) ? v.cfg : pick_cfg(d.M, d.N, cplx);
+  p.ks = v.ks == 1 || v.ks == 2 ? v.ks : 1;
+  if (!ks_ok(p.ci, p.ks, cplx)) p.ks = 1;
+  const Cfg cf = kCfgs[p.ci];
+  const int64_t ntotal = (int64_t)cdiv(d.M, cf.BM()) * cdiv(d.N, cf.BN());
+  const int bk = 16 * p.ks;
+  // split K when the tile grid alone gives fewer than ~4 blocks per CU
+  int64_t ksplit = 1;
+  const int64_t blocks = ntotal * c.batch;
+  if (v.split > 0)
+    ksplit = v.split;
+  else if (blocks < 1024 && d.K >= 256)
+    ksplit = std::max<int64_t>(1, std::min<int64_t>((1024 + blocks - 1) / blocks, d.K / 128));
+  if (c.copy_if_zero) ksplit = 1;
+  ksplit = std::min<int64_t>(ksplit, std::max<int64_t>(1, d.K / bk));
+  int64_t kchunk = (d.K + ksplit - 1) / ksplit;
+  // the staged K tables must fit next to the two operand stages
+  const int elt_c = prec == Prec::F32 ? 4 : 8;
+  const int ldk = bk + 16 / elt_c;
+  const int64_t stage_bytes = 2LL * (cplx ? 2 : 1) * (cf.BM() + cf.BN()) * ldk * elt_c;
+  const int ntab = a.tabA + a.tabB;
+  if (ntab > 0) {
+    const int64_t kmax = (kLdsBytes - stage_bytes) / (4 * ntab) / bk * bk;
+    HP_REQUIRE(kmax >= bk, HPEPS_ERR_UNSUPPORTED, "gemm tile does not fit in LDS");
+    kchunk = std::min(kchunk, kmax);
+  }
+  kchunk = std::max<int64_t>(bk, (kchunk + bk - 1) / bk * bk);
+  ksplit = std::max<int64_t>(1, (d.K + kchunk - 1) / kchunk);
+  if (c.copy_if_zero) HP_REQUIRE(ksplit == 1, HPEPS_ERR_UNSUPPORTED, "pass-through gemm too long");
+  const int64_t nwork = ntotal * c.batch * ksplit;
+  HP_REQUIRE(nwork < (1LL << 30), HPEPS_ERR_UNSUPPORTED, "gemm launch too large");
+  p.ksplit = ksplit;
+  p.kchunk = kchunk;
+  p.lds = (size_t)(stage_bytes + (int64_t)ntab * kchunk * 4);
+  p.grid = (unsigned)((nwork + 7) / 8) * 8u;
+  return p;
+}
+
+// Enqueues the product with plan p (split-K partials from the workspace).
+void run_plan(Ctx& ctx, Prec prec, const GemmDesc& d, const GemmCall& c, GemmArgs a, const Plan& p) {
+  const bool cplx = prec == Prec::C128;
+  const Cfg cf = kCfgs[p.ci];
+  a.mtiles = (int)cdiv(d.M, cf.BM());
+  a.ntotal = (int)(a.mtiles * (int64_t)cdiv(d.N, cf.BN()));
+  a.ksplit = (int)p.ksplit;
+  a.kchunk = (int)p.kchunk;
+  a.nwork = (int)((int64_t)a.ntotal * c.batch * p.ksplit);
+  a.per_xcd = (int)(p.grid / 8);
+  a.partial = nullptr;
+  if (p.ksplit > 1)
+    a.partial = ctx.ws_alloc((int64_t)c.batch * p.ksplit * d.M * d.N * (cplx ? 16 : 8));
+  hipStream_t st = ctx.stream;
+  switch (prec) {
+    case Prec::F64:
+      launch_ks<double, false, double, double>(p.ci, p.ks, p.grid, p.lds, st, a);
+      if (p.ksplit > 1) splitk_reduce_kernel<false, double><<<1024, 256, 0, st>>>(a, c.batch);
+      break;
+    case Prec::C128:
+      launch_ks<double, true, double, double>(p.ci, p.ks, p.grid, p.lds, st, a);
+      if (p.ksplit > 1) splitk_reduce_kernel<true, double><<<1024, 256, 0, st>>>(a, c.batch);
+      break;
+    case Prec::F32:
+      if (c.out_f64) {
+        launch_ks<float, false, float, double>(p.ci, p.ks, p.grid, p.lds, st, a);
+        if (p.ksplit > 1) splitk_reduce_kernel<false, double><<<1024, 256, 0, st>>>(a, c.batch);
+      } else {
+        launch_ks<float, false, float, float>(p.ci, p.ks, p.grid, p.lds, st, a);
+        if (p.ksplit > 1) splitk_reduce_kernel<false, float><<<1024, 256, 0, st>>>(a, c.batch);
+      }
+      break;
+  }
+  HP_CHECK_HIP(hipGetLastError());
+}
+
+std::string tune_key(Prec prec, const GemmDesc& d, const GemmCall& c, const GemmArgs& a) {
+  char buf[160];
+  snprintf(buf, sizeof(buf), "%s_M%lld_N%lld_K%lld_b%d_a%d%d_b%d%d",
+           prec == Prec::F64 ? "f64" : prec == Prec::C128 ? "c128" : (c.out_f64 ? "f32" : "f32o32"),
+           (long long)d.M, (long long)d.N, (long long)d.K, c.batch, a.a_kfast, a.tabA, a.b_kfast,
+           a.tabB);
+  return buf;
+}
+
+// A product may be re-run for timing only when it is idempotent: no
+// accumulation into C and C disjoint from A and B.
+bool tunable(Ctx& ctx, Prec prec, const GemmCall& c, int64_t nA, int64_t nB, int64_t nC) {
+  if (c.accumulate) return false;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(ctx.stream, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone)
+    return false;
+  const int64_t ein = prec == Prec::F32 ? 4 : (prec == Prec::C128 ? 16 : 8);
+  const int64_t eout = prec == Prec::F32 && !c.out_f64 ? 4 : (prec == Prec::C128 ? 16 : 8);
+  auto range = [](const void* p, int64_t s, int64_t n, int batch, int64_t e) {
+    const char* b = static_cast<const char*>(p);
+    return std::make_pair(b, b + ((int64_t)(batch - 1) * s + n) * e);
+  };
+  const auto ra = range(c.A, c.sA, nA, c.batch, ein), rb = range(c.B, c.sB, nB, c.batch, ein),
+             rc = range(c.C, c.sC, nC, c.batch, eout);
+  auto overlap = [](std::pair<const char*, const char*> x, std::pair<const char*, const char*> y) {
+    return x.first < y.second && y.first < x.second;
+  };
+  return !overlap(rc, ra) && !overlap(rc, rb);
+}
+
+GemmVariant tune(Ctx& ctx, Prec prec, const GemmDesc& d, const GemmCall& c, const GemmArgs& a) {
+  const bool cplx = prec == Prec::C128;
+  hipEvent_t e0, e1;
+  HP_CHECK_HIP(hipEventCreate(&e0));
+  HP_CHECK_HIP(hipEventCreate(&e1));
+  GemmVariant best;
+  float best_ms = 1e30f;
+  std::vector<std::tuple<int, int, int64_t>> seen;
+  for (int ci = 0; ci < kNumCfgs; ++ci) {
+    if (!cfg_ok(ci, cplx)) continue;
+    for (int ks = 1; ks <= 2; ++ks) {
+      if (!ks_ok(ci, ks, cplx)) continue;
+      const int64_t h = make_plan(prec, d, c, a, GemmVariant{ci, ks, 0}).ksplit;
+      for (int64_t sp : {(int64_t)0, (int64_t)1, 2 * h, 4 * h}) {
+        GemmVariant v{ci, ks, (int)sp};
+        Plan p;
+        try {
+          p = make_plan(prec, d, c, a, v);
+        } catch (const Error&) {
+          continue;
+        }
+        const auto id = std::make_tuple(p.ci, p.ks, p.ksplit);
+        if (std::find(seen.begin(), seen.end(), id) != seen.end()) continue;
+        seen.push_back(id);
+        const int chunk = ctx.ws_chunk();
+        const int64_t off = ctx.ws_offset();
+        run_plan(ctx, prec, d, c, a, p);  // warm-up (also first-launch setup)
+        HP_CHECK_HIP(hipEventRecord(e0, ctx.stream));
+        for (int r = 0; r < 3; ++r) run_plan(ctx, prec, d, c, a, p);
+        HP_CHECK_HIP(hipEventRecord(e1, ctx.stream));
+        HP_CHECK_HIP(hipEventSynchronize(e1));
+        float ms = 0;
+        HP_CHECK_HIP(hipEventElapsedTime(&ms, e0, e1));
+        ctx.ws_restore(chunk, off);
+        if (ms < best_ms) {
+          best_ms = ms;
+          best = GemmVariant{p.ci, p.ks, (int)p.ksplit};
+        }
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return best;
 }
 
 }  // namespace
@@ -420,6 +782,8 @@ void gemm(Ctx& ctx, Prec prec, const GemmDesc& d, const GemmCall& c) {
   HP_REQUIRE(nB > 0 && maxoff(d.Bk, d.Bn) < nB, HPEPS_ERR_SHAPE, "gemm B access out of bounds");
   HP_REQUIRE(nC > 0 && maxoff(d.Cm, d.Cn) < nC, HPEPS_ERR_SHAPE, "gemm C access out of bounds");
   if (c.copy_if_zero) HP_REQUIRE(d.K == d.N, HPEPS_ERR_SHAPE, "pass-through gemm needs K == N");
+  HP_REQUIRE(c.batch >= 1, HPEPS_ERR_INVALID_ARG, "gemm batch must be >= 1");
+  const bool cplx = prec == Prec::C128;
   GemmArgs a{};
   a.A = c.A;
   a.B = c.B;
@@ -447,65 +811,45 @@ void gemm(Ctx& ctx, Prec prec, const GemmDesc& d, const GemmCall& c) {
   a.nscale = c.nscale;
   a.nscale_ld = c.nscale_ld;
   a.copy_if_zero = c.copy_if_zero;
+  // per-instance extents for the buffer resources (byte offsets are 32-bit)
+  const int64_t elt_in = prec == Prec::F32 ? 4 : (cplx ? 16 : 8);
+  HP_REQUIRE(nA * elt_in < (1LL << 32) - 16 && nB * elt_in < (1LL << 32) - 16, HPEPS_ERR_UNSUPPORTED,
+             "gemm operand exceeds 4 GiB per instance");
+  a.nA_bytes = (unsigned)(nA * elt_in);
+  a.nB_bytes = (unsigned)(nB * elt_in);
+  // K offsets: affine maps are computed in the kernel, others staged in LDS
+  const int64_t stepA = affine_step(d.Ak), stepB = affine_step(d.Bk);
+  const bool affA = stepA >= 0 && stepA * std::max<int64_t>(d.K, 1) < (1LL << 31);
+  const bool affB = stepB >= 0 && stepB * std::max<int64_t>(d.K, 1) < (1LL << 31);
+  a.tabA = affA ? 0 : 1;
+  a.tabB = affB ? 0 : 1;
+  a.a_kstep = affA ? (int)stepA : 0;
+  a.b_kstep = affB ? (int)stepB : 0;
 
-  const int ci = pick_cfg(d.M, d.N, prec == Prec::C128);
-  const Cfg cf = kCfgs[ci];
-  a.mtiles = (int)cdiv(d.M, cf.BM());
-  a.ntiles = (int)cdiv(d.N, cf.BN());
-  a.ntotal = a.mtiles * a.ntiles;
-
-  // split K when the tile grid alone cannot fill the 256 CUs
-  int ksplit = 1;
-  const int64_t blocks = (int64_t)a.ntotal * c.batch;
-  if (blocks < 512 && d.K > 256 && !c.copy_if_zero) {
-    ksplit = (int)std::min<int64_t>((1024 + blocks - 1) / blocks, (d.K + 255) / 256);
-    ksplit = std::max(1, std::min(ksplit, 4096 / std::max(1, c.batch)));
+  // launch variant: forced, tuned, tuned now, or the heuristic
+  GemmVariant v = ctx.gemm_force;
+  if (v.cfg < 0) {
+    const std::string key = tune_key(prec, d, c, a);
+    auto it = ctx.gemm_tuned.find(key);
+    if (it != ctx.gemm_tuned.end()) {
+      v = it->second;
+    } else if (ctx.autotune && tunable(ctx, prec, c, nA, nB, nC)) {
+      v = tune(ctx, prec, d, c, a);
+      ctx.gemm_tuned[key] = v;
+    }
   }
-  int kchunk = (int)d.K;
-  if (ksplit > 1) {
-    kchunk = (int)(((d.K + ksplit - 1) / ksplit + 15) / 16 * 16);
-    ksplit = (int)((d.K + kchunk - 1) / kchunk);
-  }
-  a.ksplit = ksplit;
-  a.kchunk = std::max(kchunk, 1);
-  const bool cplx = prec == Prec::C128;
-  if (ksplit > 1) {
-    a.partial = ctx.ws_alloc((int64_t)c.batch * ksplit * d.M * d.N * (cplx ? 16 : 8));
-  }
-  HP_REQUIRE(c.batch * ksplit < 65536, HPEPS_ERR_UNSUPPORTED, "gemm batch too large");
-  const unsigned gx = ((unsigned)a.ntotal + 7) / 8 * 8;
-  dim3 grid(gx, (unsigned)(c.batch * ksplit));
-  hipStream_t st = ctx.stream;
+  const Plan p = make_plan(prec, d, c, a, v);
+  const Cfg cf = kCfgs[p.ci];
   int rec = -1;
   if (ctx.prof_on) {
     static const char* pn[] = {"f64", "c128", "f32"};
     const std::string name = std::string("gemm_") + pn[(int)prec] +
                              (prec == Prec::F32 && !c.out_f64 ? "o32" : "") + "_" +
-                             std::to_string(cf.BM()) + "x" + std::to_string(cf.BN());
+                             std::to_string(cf.BM()) + "x" + std::to_string(cf.BN()) + "k" +
+                             std::to_string(16 * p.ks);
     rec = ctx.prof_begin(name);
   }
-  switch (prec) {
-    case Prec::F64:
-      launch_cfg<double, false, double, double>(ci, grid, st, a);
-      if (ksplit > 1)
-        splitk_reduce_kernel<false, double><<<1024, 256, 0, st>>>(a, c.batch);
-      break;
-    case Prec::C128:
-      launch_cfg<double, true, double, double>(ci, grid, st, a);
-      if (ksplit > 1)
-        splitk_reduce_kernel<true, double><<<1024, 256, 0, st>>>(a, c.batch);
-      break;
-    case Prec::F32:
-      if (c.out_f64) {
-        launch_cfg<float, false, float, double>(ci, grid, st, a);
-        if (ksplit > 1) splitk_reduce_kernel<false, double><<<1024, 256, 0, st>>>(a, c.batch);
-      } else {
-        launch_cfg<float, false, float, float>(ci, grid, st, a);
-        if (ksplit > 1) splitk_reduce_kernel<false, float><<<1024, 256, 0, st>>>(a, c.batch);
-      }
-      break;
-  }
-  HP_CHECK_HIP(hipGetLastError());
+  run_plan(ctx, prec, d, c, a, p);
   if (rec >= 0) {
     // algorithmic work of the product: 2 M N K per instance (complex: 4 real
     // products per multiply-add); bytes: each operand element once
@@ -514,6 +858,49 @@ void gemm(Ctx& ctx, Prec prec, const GemmDesc& d, const GemmCall& c) {
     const double byt = ((double)d.M * d.K + (double)d.K * d.N + (double)d.M * d.N) * c.batch * elt;
     ctx.prof_end(rec, mnk, byt);
   }
+}
+
+// ---------------------------------------------------------------------------
+// autotune cache as JSON: {"gemm": {"<key>": [cfg, ks, split], ...}}
+
+std::string autotune_export(const Ctx& ctx) {
+  std::string s = "{\"gemm\": {";
+  bool first = true;
+  for (const auto& kv : ctx.gemm_tuned) {
+    char buf[64];
+    snprintf(buf, sizeof(buf), "[%d, %d, %d]", kv.second.cfg, kv.second.ks, kv.second.split);
+    if (!first) s += ", ";
+    s += "\"" + kv.first + "\": " + buf;
+    first = false;
+  }
+  s += "}}";
+  return s;
+}
+
+void autotune_import(Ctx& ctx, const std::string& json) {
+  // entries are "key": [int, int, int]; keys hold no quotes or brackets
+  size_t pos = json.find("\"gemm\"");
+  HP_REQUIRE(pos != std::string::npos, HPEPS_ERR_INVALID_ARG, "autotune JSON has no \"gemm\" object");
+  pos = json.find('{', pos);
+  HP_REQUIRE(pos != std::string::npos, HPEPS_ERR_INVALID_ARG, "autotune JSON is malformed");
+  std::map<std::string, GemmVariant> parsed;
+  while (true) {
+    const size_t q0 = json.find_first_of("\"}", pos + 1);
+    HP_REQUIRE(q0 != std::string::npos, HPEPS_ERR_INVALID_ARG, "autotune JSON is malformed");
+    if (json[q0] == '}') break;
+    const size_t q1 = json.find('"', q0 + 1);
+    const size_t lb = q1 == std::string::npos ? q1 : json.find('[', q1);
+    const size_t rb = lb == std::string::npos ? lb : json.find(']', lb);
+    HP_REQUIRE(rb != std::string::npos, HPEPS_ERR_INVALID_ARG, "autotune JSON is malformed");
+    GemmVariant v;
+    HP_REQUIRE(sscanf(json.c_str() + lb, "[%d , %d , %d ]", &v.cfg, &v.ks, &v.split) == 3,
+               HPEPS_ERR_INVALID_ARG, "autotune JSON entry is malformed");
+    HP_REQUIRE(v.cfg >= 0 && v.cfg < kNumCfgs && (v.ks == 1 || v.ks == 2) && v.split >= 0,
+               HPEPS_ERR_INVALID_ARG, "autotune JSON entry out of range");
+    parsed[json.substr(q0 + 1, q1 - q0 - 1)] = v;
+    pos = rb;
+  }
+  for (auto& kv : parsed) ctx.gemm_tuned[kv.first] = kv.second;
 }
 
 }  // namespace hp

@@ -88,8 +88,19 @@ struct GemmCall {
   int64_t nA = 0, nB = 0, nC = 0;
 };
 
+// Launch variant of the GEMM kernel: tile shape index, K-step multiple
+// (K-step = 16 ks) and split-K count (0 = chosen by the size heuristic).
+struct GemmVariant {
+  int cfg = -1;
+  int ks = 0;
+  int split = 0;
+};
+
 class Ctx;
 void gemm(Ctx& ctx, Prec prec, const GemmDesc& d, const GemmCall& c);
+// JSON text of the tuned variants of a context / merge such a text into it
+std::string autotune_export(const Ctx& ctx);
+void autotune_import(Ctx& ctx, const std::string& json);
 
 // ---------------------------------------------------------------------------
 // small dense linear algebra kernels (launchers)
@@ -181,6 +192,14 @@ class Ctx {
     double ms = 0, flops = 0, bytes = 0;
   };
   std::vector<ProfAgg> prof_read();                  // synchronises, clears
+
+  // GEMM variant selection: a forced variant (cfg >= 0; kernel tests), the
+  // tuned cache keyed by shape / layout / precision, and the autotune switch
+  // (when on, the first product of a new key times every variant and keeps
+  // the fastest; that call synchronises the stream)
+  GemmVariant gemm_force;
+  bool autotune = false;
+  std::map<std::string, GemmVariant> gemm_tuned;
 
  private:
   struct ProfRec {

@@ -105,4 +105,10 @@ hpeps_status hpeps_test_zip_apply(hpeps_ctx* ctx, hpeps_dtype dtype, int64_t bat
   });
 }
 
+hpeps_status hpeps_test_gemm_variant(hpeps_ctx* ctx, int32_t tile, int32_t kstep, int32_t split) {
+  if (!ctx || split < 0) return HPEPS_ERR_INVALID_ARG;
+  ctx->impl->gemm_force = hp::GemmVariant{tile < 0 ? -1 : tile, kstep, split};
+  return HPEPS_OK;
+}
+
 }  // extern "C"
