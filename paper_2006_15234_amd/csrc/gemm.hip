@@ -40,6 +40,7 @@
 #include <cstdio>
 #include <cstring>
 #include <tuple>
+#include <type_traits>
 
 #include "internal.h"
 
@@ -135,17 +136,18 @@ typedef double d2v __attribute__((ext_vector_type(2)));
 // One element through a buffer resource (byte offset; zero when past the
 // extent).  Complex values are (re, im) double pairs.
 template <class TC, bool CPLX, class TIn>
-__device__ __forceinline__ Elem<TC, CPLX> buf_load(__amdgpu_buffer_rsrc_t r, unsigned off) {
+__device__ __forceinline__ Elem<TC, CPLX> buf_load(__amdgpu_buffer_rsrc_t r, unsigned off,
+                                                   unsigned soff = 0) {
   Elem<TC, CPLX> e;
   if constexpr (CPLX) {
-    const d2v v = __builtin_bit_cast(d2v, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+    const d2v v = __builtin_bit_cast(d2v, __builtin_amdgcn_raw_buffer_load_b128(r, off, soff, 0));
     e.re = (TC)v[0];
     e.im = (TC)v[1];
   } else if constexpr (sizeof(TIn) == 8) {
-    e.re = (TC)__builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+    e.re = (TC)__builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, soff, 0));
     e.im = (TC)0;
   } else {
-    e.re = (TC)__builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+    e.re = (TC)__builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, soff, 0));
     e.im = (TC)0;
   }
   return e;
@@ -265,6 +267,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
   // row offset (-1 past the last row).
   int a_lds[NA], a_kk[NA], a_roff[NA];
   int b_lds[NB], b_kk[NB], b_coff[NB];
+  unsigned a_base[NA], b_base[NB];
 #pragma unroll
   for (int i = 0; i < NA; ++i) {
     const int e = tid + i * 256;
@@ -279,6 +282,9 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
     a_kk[i] = kk;
     const int m = m0 + row;
     a_roff[i] = (m < g.M) ? g.rA[m] : -1;
+    // byte offset of (row, kk) at k = 0 on the affine path; rows past M read
+    // row 0 instead (those accumulator rows are never stored)
+    a_base[i] = (unsigned)(max(a_roff[i], 0) + kk * g.a_kstep) * ELT;
   }
 #pragma unroll
   for (int i = 0; i < NB; ++i) {
@@ -294,44 +300,58 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
     b_kk[i] = kk;
     const int n = n0 + col;
     b_coff[i] = (n < g.N) ? g.cB[n] : -1;
+    b_base[i] = (unsigned)(max(b_coff[i], 0) + kk * g.b_kstep) * ELT;
   }
 
   Elem<TC, CPLX> ra[NA], rb[NB];
-  auto load_global = [&](int k0) {
-    if (g.tabA) {
+  // K-step starting at k0.  A full step of an affine operand needs no
+  // per-element arithmetic: the k offset goes into the scalar offset of the
+  // buffer load.  The partial last step and table-gathered operands check
+  // every element (k past the end reads zero).
+  auto load_global = [&](int k0, bool full) {
+    if (!g.tabA && full) {
+      const unsigned so = (unsigned)(k0 * g.a_kstep) * ELT;
+#pragma unroll
+      for (int i = 0; i < NA; ++i) ra[i] = buf_load<TC, CPLX, TIn>(rsA, a_base[i], so);
+    } else if (g.tabA) {
 #pragma unroll
       for (int i = 0; i < NA; ++i) {
         const int k = k0 + a_kk[i];
         const int ko = sKA[k - kbeg];
-        const bool ok = a_roff[i] >= 0 && k < kend;
+        const bool ok = (a_roff[i] >= 0) & (k < kend);
         ra[i] = buf_load<TC, CPLX, TIn>(rsA, ok ? (unsigned)(a_roff[i] + ko) * ELT : kOut);
       }
     } else {
 #pragma unroll
       for (int i = 0; i < NA; ++i) {
         const int k = k0 + a_kk[i];
-        const bool ok = a_roff[i] >= 0 && k < kend;
+        const bool ok = (a_roff[i] >= 0) & (k < kend);
         ra[i] = buf_load<TC, CPLX, TIn>(rsA, ok ? (unsigned)(a_roff[i] + k * g.a_kstep) * ELT : kOut);
       }
     }
-    if (g.tabB) {
+    if (!g.tabB && full) {
+      const unsigned so = (unsigned)(k0 * g.b_kstep) * ELT;
+#pragma unroll
+      for (int i = 0; i < NB; ++i) rb[i] = buf_load<TC, CPLX, TIn>(rsB, b_base[i], so);
+    } else if (g.tabB) {
 #pragma unroll
       for (int i = 0; i < NB; ++i) {
         const int k = k0 + b_kk[i];
         const int ko = sKB[k - kbeg];
-        const bool ok = b_coff[i] >= 0 && k < kend;
+        const bool ok = (b_coff[i] >= 0) & (k < kend);
         rb[i] = buf_load<TC, CPLX, TIn>(rsB, ok ? (unsigned)(b_coff[i] + ko) * ELT : kOut);
       }
     } else {
 #pragma unroll
       for (int i = 0; i < NB; ++i) {
         const int k = k0 + b_kk[i];
-        const bool ok = b_coff[i] >= 0 && k < kend;
+        const bool ok = (b_coff[i] >= 0) & (k < kend);
         rb[i] = buf_load<TC, CPLX, TIn>(rsB, ok ? (unsigned)(b_coff[i] + k * g.b_kstep) * ELT : kOut);
       }
     }
   };
-  auto store_lds = [&](int stage) {
+  auto store_lds = [&](auto stage_c) {
+    constexpr int stage = decltype(stage_c)::value;
     TC* sa = sbuf + stage * STAGE;
     TC* sb = sa + NP * SA;
 #pragma unroll
@@ -358,7 +378,8 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
   const int wm = wave % WM, wn = wave / WM;
   const int li = lane & 15, lk = lane >> 4;
 
-  auto compute = [&](int stage) {
+  auto compute = [&](auto stage_c) {
+    constexpr int stage = decltype(stage_c)::value;
     const TC* sa = sbuf + stage * STAGE + (wm * TM * 16 + li) * LDK + lk * KQ;
     const TC* sb = sbuf + stage * STAGE + NP * SA + (wn * TN * 16 + li) * LDK + lk * KQ;
     TC ar[TM][KQ], br[TN][KQ];
@@ -402,21 +423,37 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
     }
   };
 
+  // K-steps t = 0 .. nsteps-1 alternate between the two LDS stages (t % 2);
+  // the loop is unrolled by two so that stage offsets are immediates
+  const std::integral_constant<int, 0> st0;
+  const std::integral_constant<int, 1> st1;
+  const int nsteps = kend > kbeg ? (kend - kbeg + BK - 1) / BK : 0;
+  const bool last_full = (kend - kbeg) % BK == 0;
+  auto full = [&](int t) { return t < nsteps - 1 || last_full; };
   __syncthreads();  // K offset tables staged
-  if (kbeg < kend) {
-    load_global(kbeg);
-    store_lds(0);
+  if (nsteps > 0) {
+    load_global(kbeg, full(0));
+    store_lds(st0);
   }
   __syncthreads();
-  int cur = 0;
-  for (int k0 = kbeg; k0 < kend; k0 += BK) {
-    const bool more = k0 + BK < kend;
-    if (more) load_global(k0 + BK);
-    compute(cur);
-    if (more) store_lds(cur ^ 1);
+  int t = 0;
+  // The scheduling barriers keep the LDS stores (which wait for the global
+  // loads) behind the MFMAs of the step, so that the loads are in flight
+  // while the step computes.
+  for (; t + 1 < nsteps; t += 2) {
+    load_global(kbeg + (t + 1) * BK, full(t + 1));
+    compute(st0);
+    __builtin_amdgcn_sched_barrier(0);
+    store_lds(st1);
     __syncthreads();
-    cur ^= 1;
+    const bool more = t + 2 < nsteps;
+    if (more) load_global(kbeg + (t + 2) * BK, full(t + 2));
+    compute(st1);
+    __builtin_amdgcn_sched_barrier(0);
+    if (more) store_lds(st0);
+    __syncthreads();
   }
+  if (t < nsteps) compute(st0);
 
   // epilogue: accumulator register r of a lane holds column li of each 16x16
   // tile and row lk + 4 r (f64 MFMA) or 4 lk + r (f32 MFMA) -- measured layouts

@@ -94,18 +94,55 @@ __global__ void sketch_kernel(TO* out, long long nk, uint64_t seed, uint64_t str
 }
 
 // ---------------------------------------------------------------------------
-// Cholesky + triangular inverse of one k x k Gram matrix per workgroup.
+// Wavefront sum of a double with DPP lane moves (no LDS traffic): quad
+// butterflies, half-row and row mirrors, then the two row broadcasts; lane 63
+// ends with the total, which is read back as a wave-uniform value.  Every
+// lane of the wavefront must be active.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_add(double v) {
+  const long long x = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)x, CTRL, ROW_MASK, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(x >> 32), CTRL, ROW_MASK, 0xf, false);
+  return v + __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned)lo);
+}
+__device__ __forceinline__ double wave_sum(double v) {
+  v = dpp_add<0xb1, 0xf>(v);   // quad_perm [1,0,3,2]
+  v = dpp_add<0x4e, 0xf>(v);   // quad_perm [2,3,0,1]
+  v = dpp_add<0x141, 0xf>(v);  // row_half_mirror
+  v = dpp_add<0x140, 0xf>(v);  // row_mirror
+  v = dpp_add<0x142, 0xa>(v);  // row_bcast:15 into rows 1 and 3
+  v = dpp_add<0x143, 0xc>(v);  // row_bcast:31 into rows 2 and 3
+  const long long x = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_readlane((int)x, 63);
+  const int hi = __builtin_amdgcn_readlane((int)(x >> 32), 63);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+// ---------------------------------------------------------------------------
+// Cholesky factor and its inverse for one k x k Gram matrix per workgroup.
+// Gaussian elimination of the Hermitian G without pivoting: step j subtracts
+// (conj(A[j,i]) / d_j) row j from every row i > j, with d_j = A[j,j].  The
+// upper triangle ends as U = D R (R = chol(G), G = R^H R, D = diag(sqrt d))
+// and the same row operations applied to the identity give the unit lower
+// triangular M with M G = U, i.e. M = D R^-H; M is kept in the strict lower
+// triangle of the same array.  Hence R = D^-1 U and R^-1 = M^H D^-1 without
+// a separate triangular inversion.  Step j reads row j and writes rows > j
+// only: one barrier per step.  Rows are dealt to the wavefronts, columns to
+// the lanes (no integer division in the loop).
+constexpr int kCholThreads = 512;
+constexpr int kCholRows = 4;  // rows per wavefront batch
+
 template <bool CPLX>
-__global__ __launch_bounds__(kSmallThreads) void chol_inv_kernel(const double* Gall, long long n_rows,
-                                                                  int k, int pass, double* Rinv_all,
-                                                                  double* Racc_all, int* flags) {
+__global__ __launch_bounds__(kCholThreads) void chol_inv_kernel(const double* Gall, long long n_rows,
+                                                                 int k, int pass, double* Rinv_all,
+                                                                 double* Racc_all, int* flags) {
   using T = typename S<CPLX>::T;
   extern __shared__ double smem[];
-  T* L = reinterpret_cast<T*>(smem);
-  __shared__ int fail;
-  __shared__ double red[kSmallThreads / 64];
-  __shared__ double dmin_s, dmax_s;
+  T* A = reinterpret_cast<T*>(smem);
+  __shared__ double dg[128];
+  __shared__ double red[kCholThreads / 64];
   const int b = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
+  const int wave = tid >> 6, lane = tid & 63, nw = nt >> 6;
   const long long kk = (long long)k * k;
   const T* G = reinterpret_cast<const T*>(Gall) + b * kk;
   T* Rinv = reinterpret_cast<T*>(Rinv_all) + b * kk;
@@ -124,63 +161,79 @@ __global__ __launch_bounds__(kSmallThreads) void chol_inv_kernel(const double* G
   // trace of G for the shift
   double tr = 0.0;
   for (int i = tid; i < k; i += nt) tr += S<CPLX>::re(G[(long long)i * k + i]);
-  for (int o = 32; o > 0; o >>= 1) tr += __shfl_xor(tr, o);
-  if ((tid & 63) == 0) red[tid >> 6] = tr;
+  tr = wave_sum(tr);
+  if (lane == 0) red[wave] = tr;
   __syncthreads();
-  if (tid == 0) {
-    double s = 0;
-    for (int w = 0; w < nt / 64; ++w) s += red[w];
-    red[0] = s;
-  }
-  __syncthreads();
-  tr = red[0];
+  tr = 0.0;
+  for (int w = 0; w < nw; ++w) tr += red[w];
   // shifted CholeskyQR: s = 11 (n k + k (k + 1)) u ||Y||^2, with ||Y||_2^2 <= trace(G)
   const double shift = 11.0 * ((double)n_rows * k + (double)k * (k + 1)) * 0x1p-53 * tr;
 
+  bool ok = false;
   for (int attempt = 0; attempt < 2; ++attempt) {
-    for (long long e = tid; e < kk; e += nt) {
-      T v = G[e];
-      if (attempt == 1 && e / k == e % k) {
-        if constexpr (CPLX) v.re += shift; else v += shift;
-      }
-      L[e] = v;
-    }
-    if (tid == 0) fail = 0;
-    __syncthreads();
-    for (int j = 0; j < k; ++j) {
-      if (tid == 0) {
-        const double d = S<CPLX>::re(L[(long long)j * k + j]);
-        if (!(d > 0.0) || !isfinite(d)) fail = 1;
-        else L[(long long)j * k + j] = S<CPLX>::scale(S<CPLX>::one(), sqrt(d));
-      }
-      __syncthreads();
-      if (fail) break;
-      const double inv = 1.0 / S<CPLX>::re(L[(long long)j * k + j]);
-      for (int l = j + 1 + tid; l < k; l += nt) L[(long long)j * k + l] = S<CPLX>::scale(L[(long long)j * k + l], inv);
-      __syncthreads();
-      const int r = k - j - 1;
-      for (int e = tid; e < r * r; e += nt) {
-        const int i = j + 1 + e / r, l = j + 1 + e % r;
-        if (l >= i)
-          L[(long long)i * k + l] = S<CPLX>::sub(L[(long long)i * k + l],
-                                                 S<CPLX>::conjmul(L[(long long)j * k + i], L[(long long)j * k + l]));
-      }
-      __syncthreads();
-    }
-    if (!fail) {
-      // conditioning estimate from the diagonal of R
-      if (tid == 0) {
-        double mn = 1e300, mx = 0;
-        for (int i = 0; i < k; ++i) {
-          const double d = S<CPLX>::re(L[(long long)i * k + i]);
-          mn = fmin(mn, d);
-          mx = fmax(mx, d);
+    // upper triangle of G (+ shift), zero strict lower triangle (M = I)
+    for (int i = wave; i < k; i += nw)
+      for (int c = lane; c < k; c += 64) {
+        T v = c >= i ? G[(long long)i * k + c] : S<CPLX>::zero();
+        if (attempt == 1 && c == i) {
+          if constexpr (CPLX) v.re += shift; else v += shift;
         }
-        dmin_s = mn;
-        dmax_s = mx;
+        A[(long long)i * k + c] = v;
+      }
+    __syncthreads();
+    ok = true;
+    for (int j = 0; j < k; ++j) {
+      const double d = S<CPLX>::re(A[(long long)j * k + j]);  // same value in every thread
+      if (!(d > 0.0) || !isfinite(d)) {
+        ok = false;
+        break;
+      }
+      if (tid == 0) dg[j] = d;
+      const double invd = 1.0 / d;
+      const T* Aj = A + (long long)j * k;
+      // row j once per step (the lane's columns c = lane, lane + 64); M[j, j] = 1
+      T ajc[2];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int c = lane + 64 * h;
+        ajc[h] = c < k ? (c == j ? S<CPLX>::one() : Aj[c]) : S<CPLX>::zero();
+      }
+      // rows i > j in batches of kCholRows per wavefront, loads issued together
+      for (int i0 = j + 1 + wave; i0 < k; i0 += nw * kCholRows) {
+        T mu[kCholRows], aic[kCholRows][2];
+#pragma unroll
+        for (int q = 0; q < kCholRows; ++q) {
+          const int i = i0 + q * nw;
+          // multiplier of row i: conj(A[j, i]) / d_j
+          mu[q] = i < k ? S<CPLX>::scale(S<CPLX>::conj(Aj[i]), invd) : S<CPLX>::zero();
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            const int c = lane + 64 * h;
+            aic[q][h] = (i < k && c < k) ? A[(long long)i * k + c] : S<CPLX>::zero();
+          }
+        }
+#pragma unroll
+        for (int q = 0; q < kCholRows; ++q) {
+          const int i = i0 + q * nw;
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            const int c = lane + 64 * h;
+            // upper (c >= i): U; strict lower (c <= j): M; between: untouched
+            if (i < k && c < k && (c >= i || c <= j))
+              A[(long long)i * k + c] = S<CPLX>::sub(aic[q][h], S<CPLX>::mul(mu[q], ajc[h]));
+          }
+        }
       }
       __syncthreads();
-      const bool illcond = dmin_s < 1e-7 * dmax_s;
+    }
+    if (ok) {
+      // conditioning estimate from the diagonal of R
+      double mn = 1e300, mx = 0;
+      for (int i = 0; i < k; ++i) {
+        mn = fmin(mn, dg[i]);
+        mx = fmax(mx, dg[i]);
+      }
+      const bool illcond = sqrt(mn) < 1e-7 * sqrt(mx);
       if (attempt == 0 && illcond && pass == 1) {
         f |= FLAG_THIRD_PASS;
         __syncthreads();
@@ -191,62 +244,75 @@ __global__ __launch_bounds__(kSmallThreads) void chol_inv_kernel(const double* G
     f |= FLAG_THIRD_PASS;
     __syncthreads();
   }
-  if (fail) {
+  if (!ok) {
     f |= FLAG_NUMERIC;
     write_identity();
     if (tid == 0) flags[b] = f;
     return;
   }
-  // zero the strictly lower part (the Cholesky above only touched the upper)
-  for (long long e = tid; e < kk; e += nt)
-    if (e / k > e % k) L[e] = S<CPLX>::zero();
-  __syncthreads();
-
-  // Racc <- R (pass 1) or R * Racc (later passes)
+  // R[i, l] = U[i, l] / sqrt(d_i) (l >= i), R^-1[a, c] = conj(M[c, a]) / sqrt(d_c) (a <= c)
+  auto R_at = [&](int i, int l) -> T {
+    if (l < i) return S<CPLX>::zero();
+    return l == i ? S<CPLX>::scale(S<CPLX>::one(), sqrt(dg[i]))
+                  : S<CPLX>::scale(A[(long long)i * k + l], 1.0 / sqrt(dg[i]));
+  };
+  // Racc <- R (pass 1) or R * Racc (later passes; staged through Rinv)
   if (Racc) {
     if (pass == 1) {
-      for (long long e = tid; e < kk; e += nt) Racc[e] = L[e];
+      for (long long e = tid; e < kk; e += nt) Racc[e] = R_at((int)(e / k), (int)(e % k));
     } else {
-      T tmp[16];
-      int cnt = 0;
-      for (long long e = tid; e < kk; e += nt, ++cnt) {
+      for (long long e = tid; e < kk; e += nt) {
         const int i = (int)(e / k), l = (int)(e % k);
-        T s = S<CPLX>::zero();
-        for (int t = i; t <= l; ++t) s = S<CPLX>::add(s, S<CPLX>::mul(L[(long long)i * k + t], Racc[(long long)t * k + l]));
-        tmp[cnt] = s;
+        T sacc = S<CPLX>::zero();
+        const double inv_ri = 1.0 / sqrt(dg[i]);
+        for (int t = i; t <= l; ++t) {
+          const T rit = t == i ? S<CPLX>::scale(S<CPLX>::one(), sqrt(dg[i]))
+                               : S<CPLX>::scale(A[(long long)i * k + t], inv_ri);
+          sacc = S<CPLX>::add(sacc, S<CPLX>::mul(rit, Racc[(long long)t * k + l]));
+        }
+        Rinv[e] = sacc;
       }
       __syncthreads();
-      cnt = 0;
-      for (long long e = tid; e < kk; e += nt, ++cnt) Racc[e] = tmp[cnt];
+      for (long long e = tid; e < kk; e += nt) Racc[e] = Rinv[e];
+      __syncthreads();
     }
   }
-  __syncthreads();
-
-  // in-place inverse of the upper-triangular R, column by column
-  for (int j = 0; j < k; ++j) {
-    T x = S<CPLX>::zero();
-    const T ljj = L[(long long)j * k + j];
-    const double invd = 1.0 / S<CPLX>::re(ljj);
-    if (tid < j) {
-      for (int t = tid; t < j; ++t) x = S<CPLX>::add(x, S<CPLX>::mul(L[(long long)tid * k + t], L[(long long)t * k + j]));
-    }
-    __syncthreads();
-    if (tid < j) L[(long long)tid * k + j] = S<CPLX>::scale(x, -invd);
-    if (tid == j) L[(long long)j * k + j] = S<CPLX>::scale(S<CPLX>::one(), invd);
-    __syncthreads();
+  for (long long e = tid; e < kk; e += nt) {
+    const int a = (int)(e / k), c = (int)(e % k);
+    T v = S<CPLX>::zero();
+    if (c == a) v = S<CPLX>::scale(S<CPLX>::one(), 1.0 / sqrt(dg[a]));
+    else if (c > a) v = S<CPLX>::scale(S<CPLX>::conj(A[(long long)c * k + a]), 1.0 / sqrt(dg[c]));
+    Rinv[e] = v;
   }
-  for (long long e = tid; e < kk; e += nt) Rinv[e] = L[e];
   if (tid == 0) flags[b] = f;
 }
 
 // ---------------------------------------------------------------------------
 // One-sided (Hestenes) Jacobi SVD of K = Racc^H, columns rotated in the
-// parallel round-robin order; one wavefront per column pair.
+// parallel round-robin (circle) order.  A group of 16 lanes owns one column
+// pair of a round (lane i holds rows i, i + 16, ... of both columns), so a
+// wavefront rotates four pairs with the same instructions and the three inner
+// products of a pair are row-local DPP sums; the workgroup has one wavefront
+// per four pairs and one barrier per round.  (Every wavefront instruction
+// occupies its SIMD for four cycles: the rotation arithmetic, identical in
+// all lanes of a group, is shared by four pairs instead of repeated per pair.)
+constexpr int kJacMaxThreads = 1024;  // 64 pairs (k <= 128) / 4 per wavefront
+constexpr int kJacRows = 8;           // rows per lane: k <= 16 * 8
+
+// Sum over the 16 lanes of a DPP row, returned in all of them.
+__device__ __forceinline__ double row_sum16(double v) {
+  v = dpp_add<0xb1, 0xf>(v);   // quad_perm [1,0,3,2]
+  v = dpp_add<0x4e, 0xf>(v);   // quad_perm [2,3,0,1]
+  v = dpp_add<0x141, 0xf>(v);  // row_half_mirror
+  v = dpp_add<0x140, 0xf>(v);  // row_mirror
+  return v;
+}
+
 template <bool CPLX>
-__global__ __launch_bounds__(kSmallThreads) void jacobi_kernel(const double* Racc_all, int k, int max_sweeps,
-                                                               double* Z_all, double* sigma_all,
-                                                               double* inv_sigma_all, double* inv_sigma1,
-                                                               double* log_scale, int* stats) {
+__global__ __launch_bounds__(kJacMaxThreads) void jacobi_kernel(const double* Racc_all, int k, int max_sweeps,
+                                                                double* Z_all, double* sigma_all,
+                                                                double* inv_sigma_all, double* inv_sigma1,
+                                                                double* log_scale, int* stats) {
   using T = typename S<CPLX>::T;
   extern __shared__ double smem[];
   const int n = (k + 1) / 2 * 2;  // even number of columns (one zero column if k is odd)
@@ -264,65 +330,75 @@ __global__ __launch_bounds__(kSmallThreads) void jacobi_kernel(const double* Rac
   }
   __syncthreads();
   const int wave = tid >> 6, lane = tid & 63, nw = nt >> 6;
+  const int li = lane & 15;
+  const int npairs = n / 2;
+  const int pair = tid >> 4;  // lane group = column pair of the round
+  const bool active = pair < npairs;
   const double tol = sqrt((double)k) * 0x1p-52;
+  const double tol2 = tol * tol;
   int sweep = 0;
   bool converged = false;
   for (sweep = 0; sweep < max_sweeps; ++sweep) {
     if (tid == 0) rotated = 0;
     __syncthreads();
     for (int round = 0; round < n - 1; ++round) {
-      for (int p = wave; p < n / 2; p += nw) {
-        // circle method: position 0 fixed, the others rotate
-        auto at = [&](int pos) { return pos == 0 ? 0 : 1 + (pos - 1 + round) % (n - 1); };
-        const int ca = at(p), cb = at(n - 1 - p);
-        T* x = Kc + (long long)ca * k;
-        T* y = Kc + (long long)cb * k;
-        double a2 = 0, b2 = 0, gr = 0, gi = 0;
-        for (int r = lane; r < k; r += 64) {
-          const T xv = x[r], yv = y[r];
-          a2 += S<CPLX>::abs2(xv);
-          b2 += S<CPLX>::abs2(yv);
-          if constexpr (CPLX) {
-            const cd g = cmul(cconj(xv), yv);
-            gr += g.re;
-            gi += g.im;
-          } else {
-            gr += xv * yv;
-          }
+      // circle method: position 0 fixed, the others rotate
+      auto at = [&](int pos) { return pos == 0 ? 0 : 1 + (pos - 1 + round) % (n - 1); };
+      const int ca = active ? at(pair) : 0, cb = active ? at(n - 1 - pair) : 0;
+      T* xc = Kc + (long long)ca * k;
+      T* yc = Kc + (long long)cb * k;
+      T x[kJacRows], y[kJacRows];
+      double a2 = 0, b2 = 0, gr = 0, gi = 0;
+#pragma unroll
+      for (int h = 0; h < kJacRows; ++h) {
+        const int r = li + 16 * h;
+        const bool in = active && r < k;
+        x[h] = in ? xc[r] : S<CPLX>::zero();
+        y[h] = in ? yc[r] : S<CPLX>::zero();
+        a2 += S<CPLX>::abs2(x[h]);
+        b2 += S<CPLX>::abs2(y[h]);
+        if constexpr (CPLX) {
+          const cd g = cmul(cconj(x[h]), y[h]);
+          gr += g.re;
+          gi += g.im;
+        } else {
+          gr += x[h] * y[h];
         }
-        for (int o = 32; o > 0; o >>= 1) {
-          a2 += __shfl_xor(a2, o);
-          b2 += __shfl_xor(b2, o);
-          gr += __shfl_xor(gr, o);
-          if constexpr (CPLX) gi += __shfl_xor(gi, o);
-        }
-        const double ga = sqrt(gr * gr + gi * gi);
-        if (a2 > 0 && b2 > 0 && ga > tol * sqrt(a2) * sqrt(b2)) {
-          const double zeta = (b2 - a2) / (2.0 * ga);
-          const double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-          const double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
-          // y~ = conj(e) y with e = gamma / |gamma|, then a real rotation of (x, y~)
-          const double er = gr / ga, ei = gi / ga;
-          for (int r = lane; r < k; r += 64) {
-            const T xv = x[r];
-            T yt;
+      }
+      a2 = row_sum16(a2);
+      b2 = row_sum16(b2);
+      gr = row_sum16(gr);
+      if constexpr (CPLX) gi = row_sum16(gi);
+      const double g2 = gr * gr + gi * gi;
+      if (active && a2 > 0 && b2 > 0 && g2 > tol2 * a2 * b2) {
+        const double ga = CPLX ? sqrt(g2) : fabs(gr);
+        const double inv_ga = 1.0 / ga;
+        const double zeta = 0.5 * (b2 - a2) * inv_ga;
+        const double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+        const double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
+        // y~ = conj(e) y with e = gamma / |gamma|, then a real rotation of (x, y~)
+        const double er = gr * inv_ga, ei = gi * inv_ga;
+#pragma unroll
+        for (int h = 0; h < kJacRows; ++h) {
+          const int r = li + 16 * h;
+          if (r < k) {
+            const T xv = x[h];
             if constexpr (CPLX) {
-              const T yv = y[r];
-              yt = {er * yv.re + ei * yv.im, er * yv.im - ei * yv.re};
-              x[r] = {c * xv.re - s * yt.re, c * xv.im - s * yt.im};
-              y[r] = {s * xv.re + c * yt.re, s * xv.im + c * yt.im};
+              const T yv = y[h];
+              const T yt = {er * yv.re + ei * yv.im, er * yv.im - ei * yv.re};
+              xc[r] = {c * xv.re - s * yt.re, c * xv.im - s * yt.im};
+              yc[r] = {s * xv.re + c * yt.re, s * xv.im + c * yt.im};
             } else {
-              yt = er * y[r];
-              x[r] = c * xv - s * yt;
-              y[r] = s * xv + c * yt;
+              const T yt = er * y[h];
+              xc[r] = c * xv - s * yt;
+              yc[r] = s * xv + c * yt;
             }
           }
-          if (lane == 0) rotated = 1;
         }
+        if (li == 0) rotated = 1;
       }
       __syncthreads();
     }
-    __syncthreads();
     if (!rotated) {
       converged = true;
       ++sweep;
@@ -334,7 +410,7 @@ __global__ __launch_bounds__(kSmallThreads) void jacobi_kernel(const double* Rac
   for (int c = wave; c < k; c += nw) {
     double a2 = 0;
     for (int r = lane; r < k; r += 64) a2 += S<CPLX>::abs2(Kc[(long long)c * k + r]);
-    for (int o = 32; o > 0; o >>= 1) a2 += __shfl_xor(a2, o);
+    a2 = wave_sum(a2);
     if (lane == 0) nrm[c] = sqrt(a2);
   }
   __syncthreads();
@@ -591,16 +667,17 @@ void gram(Ctx& ctx, bool cplx, const void* Y, int64_t n, int64_t k, int batch, d
 void chol_inv(Ctx& ctx, bool cplx, const double* G, int64_t n_rows, int64_t k, int batch, int pass,
               double* Rinv, double* Racc, int* flags) {
   const size_t lds = small_lds_bytes((int)k, cplx);
-  HP_REQUIRE(lds <= 160 * 1024 - 1024, HPEPS_ERR_UNSUPPORTED, "sketch width too large for LDS");
+  HP_REQUIRE(k <= 128 && lds <= 160 * 1024 - 2048, HPEPS_ERR_UNSUPPORTED,
+             "sketch width too large for the small factorizations (k <= 128, complex k <= 88)");
   const int rec = ctx.prof_begin("chol_inv");
   if (cplx) {
     HP_CHECK_HIP(hipFuncSetAttribute((const void*)chol_inv_kernel<true>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    chol_inv_kernel<true><<<batch, kSmallThreads, lds, ctx.stream>>>(G, n_rows, (int)k, pass, Rinv, Racc, flags);
+    chol_inv_kernel<true><<<batch, kCholThreads, lds, ctx.stream>>>(G, n_rows, (int)k, pass, Rinv, Racc, flags);
   } else {
     HP_CHECK_HIP(hipFuncSetAttribute((const void*)chol_inv_kernel<false>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    chol_inv_kernel<false><<<batch, kSmallThreads, lds, ctx.stream>>>(G, n_rows, (int)k, pass, Rinv, Racc, flags);
+    chol_inv_kernel<false><<<batch, kCholThreads, lds, ctx.stream>>>(G, n_rows, (int)k, pass, Rinv, Racc, flags);
   }
   HP_CHECK_HIP(hipGetLastError());
   ctx.prof_end(rec, (double)batch * k * k * k / 3.0 * (cplx ? 4 : 1), 0.0);
@@ -611,6 +688,8 @@ void jacobi_svd(Ctx& ctx, bool cplx, const double* Racc, int64_t k, int batch, i
                 int* stats) {
   HP_REQUIRE(k <= 128, HPEPS_ERR_UNSUPPORTED, "small SVD supports k <= 128");
   const int n = (int)((k + 1) / 2 * 2);
+  // one wavefront per four column pairs
+  const int threads = std::max(64, (n / 2 + 3) / 4 * 64);
   const size_t lds = (size_t)n * k * (cplx ? 16 : 8);
   HP_REQUIRE(lds <= 160 * 1024 - 2048, HPEPS_ERR_UNSUPPORTED, "small SVD too large for LDS");
   const int rec = ctx.prof_begin("jacobi_svd");
@@ -627,12 +706,12 @@ void jacobi_svd(Ctx& ctx, bool cplx, const double* Racc, int64_t k, int batch, i
   if (cplx) {
     HP_CHECK_HIP(hipFuncSetAttribute((const void*)jacobi_kernel<true>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    jacobi_kernel<true><<<batch, kSmallThreads, lds, ctx.stream>>>(Racc, (int)k, max_sweeps, Z, sigma, inv_sigma,
+    jacobi_kernel<true><<<batch, threads, lds, ctx.stream>>>(Racc, (int)k, max_sweeps, Z, sigma, inv_sigma,
                                                                    inv_sigma1, log_scale, stats);
   } else {
     HP_CHECK_HIP(hipFuncSetAttribute((const void*)jacobi_kernel<false>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    jacobi_kernel<false><<<batch, kSmallThreads, lds, ctx.stream>>>(Racc, (int)k, max_sweeps, Z, sigma, inv_sigma,
+    jacobi_kernel<false><<<batch, threads, lds, ctx.stream>>>(Racc, (int)k, max_sweeps, Z, sigma, inv_sigma,
                                                                     inv_sigma1, log_scale, stats);
   }
   HP_CHECK_HIP(hipGetLastError());
