@@ -457,25 +457,29 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
 
   // epilogue: accumulator register r of a lane holds column li of each 16x16
   // tile and row lk + 4 r (f64 MFMA) or 4 lk + r (f32 MFMA) -- measured layouts
+  auto acc_val = [&](int i, int j, int r, double& re, double& im) {
+    if constexpr (CPLX) {
+      re = (double)acc[0][i][j][r] - (double)acc[1][i][j][r];
+      im = (double)acc[2][i][j][r] + (double)acc[3][i][j][r];
+    } else {
+      re = (double)acc[0][i][j][r];
+      im = 0.0;
+    }
+  };
+  if (g.ksplit > 1) {
+    double* P = reinterpret_cast<double*>(g.partial);
 #pragma unroll
-  for (int i = 0; i < TM; ++i)
+    for (int i = 0; i < TM; ++i)
 #pragma unroll
-    for (int j = 0; j < TN; ++j)
+      for (int j = 0; j < TN; ++j)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = (sizeof(TC) == 8) ? (lk + 4 * r) : (lk * 4 + r);
-        const int m = m0 + wm * TM * 16 + i * 16 + row;
-        const int n = n0 + wn * TN * 16 + j * 16 + li;
-        if (m >= g.M || n >= g.N) continue;
-        double re, im = 0.0;
-        if constexpr (CPLX) {
-          re = (double)acc[0][i][j][r] - (double)acc[1][i][j][r];
-          im = (double)acc[2][i][j][r] + (double)acc[3][i][j][r];
-        } else {
-          re = (double)acc[0][i][j][r];
-        }
-        if (g.ksplit > 1) {
-          double* P = reinterpret_cast<double*>(g.partial);
+        for (int r = 0; r < 4; ++r) {
+          const int row = (sizeof(TC) == 8) ? (lk + 4 * r) : (lk * 4 + r);
+          const int m = m0 + wm * TM * 16 + i * 16 + row;
+          const int n = n0 + wn * TN * 16 + j * 16 + li;
+          if (m >= g.M || n >= g.N) continue;
+          double re, im;
+          acc_val(i, j, r, re, im);
           const long long idx = (((long long)b * g.ksplit + ks) * g.M + m) * (long long)g.N + n;
           if constexpr (CPLX) {
             P[2 * idx] = re;
@@ -483,10 +487,39 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
           } else {
             P[idx] = re;
           }
-        } else {
-          epilogue<TC, CPLX, TIn, TOut>(g, b, m, n, re, im);
         }
+    return;
+  }
+  // column offsets and column scales of this lane's outputs, loaded once
+  int coff[TN];
+  double cs[TN];
+  const double sb = g.alpha * (g.scale ? g.scale[b] : 1.0);
+#pragma unroll
+  for (int j = 0; j < TN; ++j) {
+    const int n = n0 + wn * TN * 16 + j * 16 + li;
+    coff[j] = n < g.N ? g.cC[n] : -1;
+    cs[j] = (g.nscale && n < g.N) ? sb * g.nscale[(long long)b * g.nscale_ld + n] : sb;
+  }
+  TOut* Cb = reinterpret_cast<TOut*>(g.C);
+  const long long cbase = (long long)b * g.sC;
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = (sizeof(TC) == 8) ? (lk + 4 * r) : (lk * 4 + r);
+      const int m = m0 + wm * TM * 16 + i * 16 + row;
+      const int roff = m < g.M ? g.rC[m] : -1;
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+        if (roff < 0 || coff[j] < 0) continue;
+        double re, im;
+        acc_val(i, j, r, re, im);
+        re *= cs[j];
+        im *= cs[j];
+        if (g.conjC) im = -im;
+        store_out<CPLX, TOut>(Cb, cbase + roff + coff[j], re, im, g.accumulate != 0);
       }
+    }
 }
 
 // Sum of split-K partials followed by the epilogue (fixed order: deterministic).
