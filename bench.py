@@ -16,8 +16,9 @@ value: algorithmic GFLOP/s of the FP64 path, counted with the fixed formula
   2(q+1) F_A + (q+1) [F_QR(mD^2,k) + F_QR(mD^2,k)] + 2 m k (2 m D^2)
 with F_A = 4 k (m^2 D^4 + d D^5 m + d D^4 m) and F_QR(n,k) = 2 n k^2 - 2 k^3/3,
 independent of how the kernels actually evaluate it.  The same step with
-FP32 operator applications (FP64 orthogonalization and SVD) is reported
-beside it with its singular-value deviation from the FP64 result.
+FP32 and with BF16 operator applications (FP32 accumulation; FP64
+orthogonalization and SVD) is reported beside it with its singular-value
+deviation from the FP64 result.
 """
 import argparse
 import json
@@ -231,6 +232,18 @@ def main():
     s32 = out32[1].cpu().numpy()
     eps32 = float(np.max(np.abs(s32 - s64) / s64[:, :1]))
 
+    # BF16 operator applications (FP32 accumulation), same inputs and sketch streams
+    for _ in range(max(args.warmup, 1)):
+        step("bf16")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        out16 = step("bf16")
+    torch.cuda.synchronize()
+    ms16 = (time.perf_counter() - t0) * 1e3 / args.steps
+    s16 = out16[1].cpu().numpy()
+    eps16 = float(np.max(np.abs(s16 - s64) / s64[:, :1]))
+
     roofline = dominant_roofline(dominant, prof)
     res = {
         "metric": "einsumsvd GFLOP/s & boundary-contraction sweep time vs plain FP64, same GPU, at fixed eps",
@@ -254,12 +267,15 @@ def main():
         "fp32_apply": {"value": round(flops / (ms32 * 1e-3) / 1e9, 2), "unit": "GFLOP/s",
                        "ms_per_step": round(ms32, 4), "speedup_vs_f64": round(ms / ms32, 3),
                        "eps_sigma_vs_f64": eps32},
+        "bf16_apply": {"value": round(flops / (ms16 * 1e-3) / 1e9, 2), "unit": "GFLOP/s",
+                       "ms_per_step": round(ms16, 4), "speedup_vs_f64": round(ms / ms16, 3),
+                       "eps_sigma_vs_f64": eps16},
         "autotune": not args.no_autotune,
         "kernel_classes": {n: {"ms_per_step": round(a["ms"], 4), "launches": a["launches"]}
                            for n, a in sorted(agg.items(), key=lambda x: -x[1]["ms"])},
     }
     if args.d8 > 0:
-        del dev, out, out32
+        del dev, out, out32, out16
         res["variant_d8"] = d8_variant(hp, ctx, args.d8)
     if args.cpu_sample > 0:
         res["cpu_baseline"] = cpu_baseline(args.cpu_sample)

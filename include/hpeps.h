@@ -72,10 +72,14 @@ typedef struct hpeps_ctx hpeps_ctx;
  *  rank            m: number of singular triplets kept (m' = min(m, k)).
  *  oversample      p: sketch width k = min(m + p, rows, cols).
  *  power_iters     q: Alg. 4's iteration count.
- *  sketch_precision HPEPS_F64 | HPEPS_F32: arithmetic of the operator
- *                  applications A X and A^* Y (FP32 runs the contractions on
- *                  FP32 MFMA with FP32 accumulation; orthogonalization, the
- *                  small SVD and truncation always run in FP64).
+ *  sketch_precision HPEPS_F64 | HPEPS_F32 | HPEPS_BF16: arithmetic of the
+ *                  operator applications A X and A^* Y.  FP32 runs the
+ *                  contractions on FP32 MFMA with FP32 accumulation; BF16
+ *                  rounds the operands and the sketch panels to bfloat16 and
+ *                  runs them on BF16 MFMA with FP32 accumulation (intermediate
+ *                  stages stored in BF16, the panel fed to the orthogonalization
+ *                  in FP64).  Orthogonalization, the small SVD and truncation
+ *                  always run in FP64.  FP32 and BF16 are real-only.
  *  seed, stream_id select the sketch: element i of Omega (row-major over
  *                  (column multi-index, sketch column)) is
  *                  2 * (h_i >> 11) * 2^-53 - 1 with h_i = mix(base + (i+1) *
@@ -125,9 +129,10 @@ hpeps_status hpeps_get_info(hpeps_ctx* ctx, hpeps_esvd_info* info);
 /* ---- live kernel timing ---------------------------------------------------
  * While profiling is on, every kernel launch of the context whose class name
  * contains `filter` (all launches when filter is NULL or "") is bracketed by
- * two HIP events on the context stream.  Class names: "gemm_<prec>_<BM>x<BN>"
- * for the gathered MFMA GEMM (prec f64, c128, f32, f32o32 for FP32 output),
- * "chol_inv", "jacobi_svd".  hpeps_profile_read synchronises the stream,
+ * two HIP events on the context stream.  Class names:
+ * "gemm_<prec>_<BM>x<BN>k<BK>" for the gathered MFMA GEMM with a BM x BN tile
+ * and BK-deep K-steps (prec f64, c128, f32, bf16 with FP64 output; f32o32,
+ * bf16o16 with FP32 / BF16 output), "chol_inv", "jacobi_svd".  hpeps_profile_read synchronises the stream,
  * writes up to max_entries aggregates (launch count, summed kernel time in
  * ms, summed algorithmic flops -- 2 M N K per product, times 4 for complex --
  * and summed algorithmic operand bytes) and clears the records; profiling

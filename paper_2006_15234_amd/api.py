@@ -1,9 +1,9 @@
 """Torch-tensor front end of the C ABI (argument marshalling only)."""
 import ctypes as C
 
-from ._ffi import (ABSORB_CARRY, C128, F32, F64, Bmps, EsvdInfo, EsvdOpts, Peps)
+from ._ffi import (ABSORB_CARRY, C128, F32, BF16, F64, Bmps, EsvdInfo, EsvdOpts, Peps)
 
-_PREC = {"f64": F64, "f32": F32}
+_PREC = {"f64": F64, "f32": F32, "bf16": BF16}
 
 
 def _torch():

@@ -75,7 +75,7 @@ void zip_apply(Ctx& ctx, Prec prec, const ZipDims& z, const ZipLayout& L, const 
   const int64_t w2j = 1, w2c = k, w2h = c * k, w2u = h * w2h, w2H = u * w2u, w2U = h * w2H;
   // W3 strides [b,h,H,j]
   const int64_t w3j = 1, w3H = k, w3h = h * k, w3b = h * w3h;
-  const bool f32 = prec == Prec::F32;
+  const bool f32 = prec == Prec::F32 || prec == Prec::BF16;  // narrow operands
   const int64_t *sV = L.V, *sS = L.S, *sT = L.T, *sB = L.B;
 
   auto call = [&](const GemmDesc& dsc, const void* A, int64_t nA, bool cA, const void* B, int64_t nB,
@@ -268,13 +268,15 @@ void zip_esvd(Ctx& ctx, bool cplx, const ZipDims& z, const ZipLayout& L, const Z
   HP_REQUIRE(k >= 1, HPEPS_ERR_SHAPE, "empty einsumsvd");
   HP_REQUIRE(k <= (cplx ? 88 : 128), HPEPS_ERR_SHAPE, "sketch width k exceeds the small-SVD limit");
   const bool f32 = o.sketch_precision == HPEPS_F32;
-  HP_REQUIRE(!(f32 && cplx), HPEPS_ERR_DTYPE, "FP32 sketches are real-only");
-  HP_REQUIRE(o.sketch_precision == HPEPS_F64 || o.sketch_precision == HPEPS_F32, HPEPS_ERR_DTYPE,
-             "sketch precision must be F64 or F32");
+  const bool bf16 = o.sketch_precision == HPEPS_BF16;
+  const bool narrow = f32 || bf16;
+  HP_REQUIRE(!(narrow && cplx), HPEPS_ERR_DTYPE, "FP32 and BF16 sketches are real-only");
+  HP_REQUIRE(o.sketch_precision == HPEPS_F64 || narrow, HPEPS_ERR_DTYPE,
+             "sketch precision must be F64, F32 or BF16");
   HP_REQUIRE(out.Urows.size() == rows && out.Ucol.size() == mp && out.Rrow.size() == mp &&
                  out.Rcols.size() == cols,
              HPEPS_ERR_SHAPE, "output layout does not match the factor shapes");
-  const Prec prec = cplx ? Prec::C128 : (f32 ? Prec::F32 : Prec::F64);
+  const Prec prec = cplx ? Prec::C128 : (f32 ? Prec::F32 : (bf16 ? Prec::BF16 : Prec::F64));
   const int es = cplx ? 2 : 1;  // doubles per element
   const int max_sweeps = o.jacobi_max_sweeps > 0 ? o.jacobi_max_sweeps : 40;
   ctx.last_rank = mp;
@@ -287,7 +289,7 @@ void zip_esvd(Ctx& ctx, bool cplx, const ZipDims& z, const ZipLayout& L, const Z
   double* Xc2 = ctx.ws<double>(nb * cols * k * es);
   double* Xr0 = ctx.ws<double>(nb * rows * k * es);
   double* Xr1 = ctx.ws<double>(nb * rows * k * es);
-  const int64_t esz = f32 ? 4 : 8 * es;  // bytes per intermediate element
+  const int64_t esz = f32 ? 4 : (bf16 ? 2 : 8 * es);  // bytes per intermediate element
   ZipWork w;
   w.W1 = ctx.ws_alloc(nb * z.u * z.h * z.d * z.y * z.c * z.g * k * esz);
   w.W2 = ctx.ws_alloc(nb * z.u * z.h * z.u * z.h * z.c * k * esz);
@@ -306,6 +308,21 @@ void zip_esvd(Ctx& ctx, bool cplx, const ZipDims& z, const ZipLayout& L, const Z
   // operands in the apply precision
   ZipOperands op = op64;
   float* xin32 = nullptr;
+  void* xin16 = nullptr;
+  if (bf16) {
+    void* parts[4];
+    const void* src[4] = {op64.V, op64.S, op64.T, op64.Bra};
+    const int64_t cnt[4] = {L.nV, L.nS, L.nT, L.nB};
+    for (int i = 0; i < 4; ++i) {
+      parts[i] = ctx.ws_alloc(nb * cnt[i] * 2);
+      convert_f64_to_bf16(ctx, (const double*)src[i], parts[i], nb * cnt[i]);
+    }
+    op.V = parts[0];
+    op.S = parts[1];
+    op.T = parts[2];
+    op.Bra = parts[3];
+    xin16 = ctx.ws_alloc(nb * std::max(rows, cols) * k * 2);
+  }
   if (f32) {
     float* V32 = ctx.ws<float>(nb * L.nV);
     float* S32 = ctx.ws<float>(nb * L.nS);
@@ -327,6 +344,10 @@ void zip_esvd(Ctx& ctx, bool cplx, const ZipDims& z, const ZipLayout& L, const Z
       convert_f64_to_f32(ctx, X, xin32, nb * (adj ? rows : cols) * k);
       xin = xin32;
     }
+    if (bf16) {
+      convert_f64_to_bf16(ctx, X, xin16, nb * (adj ? rows : cols) * k);
+      xin = xin16;
+    }
     zip_apply(ctx, prec, z, L, op, batch, k, adj, xin, Y, true, w);
   };
 
@@ -334,6 +355,9 @@ void zip_esvd(Ctx& ctx, bool cplx, const ZipDims& z, const ZipLayout& L, const Z
   if (f32) {
     sketch(ctx, xin32, true, cols, k, batch, o.seed, o.stream_id);
     zip_apply(ctx, prec, z, L, op, batch, k, false, xin32, Xr0, true, w);
+  } else if (bf16) {
+    sketch(ctx, Xc0, false, cols, k, batch, o.seed, o.stream_id);
+    apply(false, Xc0, Xr0);
   } else {
     sketch(ctx, Xc0, false, cols, k, batch, o.seed, o.stream_id, cplx);
     zip_apply(ctx, prec, z, L, op, batch, k, false, Xc0, Xr0, true, w);

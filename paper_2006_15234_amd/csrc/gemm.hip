@@ -83,6 +83,7 @@ struct Mfma;
 template <>
 struct Mfma<double> {
   using acc_t = v4d;
+  static constexpr int kvals = 1;
   static __device__ __forceinline__ acc_t op(double a, double b, acc_t c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
   }
@@ -99,6 +100,7 @@ struct Mfma<double> {
 template <>
 struct Mfma<float> {
   using acc_t = v4f;
+  static constexpr int kvals = 1;
   static __device__ __forceinline__ acc_t op(float a, float b, acc_t c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
   }
@@ -110,6 +112,31 @@ struct Mfma<float> {
     v[3] = x.w;
   }
 };
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+template <>
+struct Mfma<__bf16> {
+  using acc_t = v4f;
+  // v_mfma_f32_16x16x32_bf16: each lane supplies 8 consecutive k of its row
+  static constexpr int kvals = 8;
+  static __device__ __forceinline__ acc_t op8(const __bf16* a, const __bf16* b, acc_t c) {
+    bf16x8 av, bv;
+    __builtin_memcpy(&av, a, 16);
+    __builtin_memcpy(&bv, b, 16);
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, c, 0, 0, 0);
+  }
+};
+
+// N consecutive values of a 16-byte aligned LDS row, as 128-bit reads
+template <class T, int N>
+__device__ __forceinline__ void lds_read(const T* p, T* v) {
+  static_assert((N * sizeof(T)) % 16 == 0, "whole 16-byte chunks");
+#pragma unroll
+  for (int c = 0; c < (int)(N * sizeof(T) / 16); ++c) {
+    const float4 x = reinterpret_cast<const float4*>(p)[c];
+    __builtin_memcpy(v + c * (16 / sizeof(T)), &x, 16);
+  }
+}
 
 // storage helpers -----------------------------------------------------------
 template <class TC, bool CPLX>
@@ -146,6 +173,9 @@ __device__ __forceinline__ Elem<TC, CPLX> buf_load(__amdgpu_buffer_rsrc_t r, uns
   } else if constexpr (sizeof(TIn) == 8) {
     e.re = (TC)__builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, soff, 0));
     e.im = (TC)0;
+  } else if constexpr (sizeof(TIn) == 2) {
+    e.re = (TC)__builtin_bit_cast(__bf16, __builtin_amdgcn_raw_buffer_load_b16(r, off, soff, 0));
+    e.im = (TC)0;
   } else {
     e.re = (TC)__builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, soff, 0));
     e.im = (TC)0;
@@ -165,7 +195,10 @@ __device__ __forceinline__ void store_out(TOut* C, long long off, double re, dou
     *c = make_double2(re, im);
   } else {
     if (acc) re += (double)C[off];
-    C[off] = (TOut)re;
+    if constexpr (sizeof(TOut) == 8)
+      C[off] = (TOut)re;
+    else
+      C[off] = (TOut)(float)re;
   }
 }
 
@@ -380,18 +413,22 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
 
   auto compute = [&](auto stage_c) {
     constexpr int stage = decltype(stage_c)::value;
+    constexpr int KV = Mfma<TC>::kvals;  // k values per lane per MFMA
     const TC* sa = sbuf + stage * STAGE + (wm * TM * 16 + li) * LDK + lk * KQ;
     const TC* sb = sbuf + stage * STAGE + NP * SA + (wn * TN * 16 + li) * LDK + lk * KQ;
     TC ar[TM][KQ], br[TN][KQ];
 #pragma unroll
-    for (int i = 0; i < TM; ++i)
+    for (int i = 0; i < TM; ++i) lds_read<TC, KQ>(sa + i * 16 * LDK, ar[i]);
 #pragma unroll
-      for (int q = 0; q < KS; ++q) Mfma<TC>::quad(sa + i * 16 * LDK + 4 * q, &ar[i][4 * q]);
+    for (int j = 0; j < TN; ++j) lds_read<TC, KQ>(sb + j * 16 * LDK, br[j]);
+    if constexpr (KV > 1) {
 #pragma unroll
-    for (int j = 0; j < TN; ++j)
+      for (int s8 = 0; s8 < KQ; s8 += KV)
 #pragma unroll
-      for (int q = 0; q < KS; ++q) Mfma<TC>::quad(sb + j * 16 * LDK + 4 * q, &br[j][4 * q]);
-    if constexpr (!CPLX) {
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+          for (int j = 0; j < TN; ++j) acc[0][i][j] = Mfma<TC>::op8(&ar[i][s8], &br[j][s8], acc[0][i][j]);
+    } else if constexpr (!CPLX) {
 #pragma unroll
       for (int s = 0; s < KQ; ++s)
 #pragma unroll
@@ -401,13 +438,9 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
     } else {
       TC ai[TM][KQ], bi[TN][KQ];
 #pragma unroll
-      for (int i = 0; i < TM; ++i)
+      for (int i = 0; i < TM; ++i) lds_read<TC, KQ>(sa + SA + i * 16 * LDK, ai[i]);
 #pragma unroll
-        for (int q = 0; q < KS; ++q) Mfma<TC>::quad(sa + SA + i * 16 * LDK + 4 * q, &ai[i][4 * q]);
-#pragma unroll
-      for (int j = 0; j < TN; ++j)
-#pragma unroll
-        for (int q = 0; q < KS; ++q) Mfma<TC>::quad(sb + SB + j * 16 * LDK + 4 * q, &bi[j][4 * q]);
+      for (int j = 0; j < TN; ++j) lds_read<TC, KQ>(sb + SB + j * 16 * LDK, bi[j]);
       // acc[0] = Re*Re, acc[1] = Im*Im, acc[2] = Re*Im, acc[3] = Im*Re
 #pragma unroll
       for (int s = 0; s < KQ; ++s)
@@ -474,7 +507,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
       for (int j = 0; j < TN; ++j)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int row = (sizeof(TC) == 8) ? (lk + 4 * r) : (lk * 4 + r);
+          const int row = (sizeof(TC) == 8) ? (lk + 4 * r) : (lk * 4 + r);  // f64 / f32-accumulator layouts
           const int m = m0 + wm * TM * 16 + i * 16 + row;
           const int n = n0 + wn * TN * 16 + j * 16 + li;
           if (m >= g.M || n >= g.N) continue;
@@ -506,7 +539,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
   for (int i = 0; i < TM; ++i)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int row = (sizeof(TC) == 8) ? (lk + 4 * r) : (lk * 4 + r);
+      const int row = (sizeof(TC) == 8) ? (lk + 4 * r) : (lk * 4 + r);  // f64 / f32-accumulator layouts
       const int m = m0 + wm * TM * 16 + i * 16 + row;
       const int roff = m < g.M ? g.rC[m] : -1;
 #pragma unroll
@@ -582,6 +615,11 @@ bool cfg_ok(int ci, bool cplx) { return !cplx || kCfgs[ci].TM * kCfgs[ci].TN <= 
 // the 32-deep K-step doubles the staging registers: complex products and the
 // 16-tile 128 x 128 shape would spill
 bool ks_ok(int ci, int ks, bool cplx) { return ks == 1 || (ks == 2 && !cplx && ci != 6); }
+// BF16 products need 32-deep K-steps (one v_mfma_f32_16x16x32_bf16 per tile and step)
+bool ks_ok(int ci, int ks, Prec prec) {
+  if (prec == Prec::BF16) return ks == 2 && ci != 6;
+  return ks_ok(ci, ks, prec == Prec::C128);
+}
 
 int pick_cfg(int64_t M, int64_t N, bool cplx) {
   auto waste = [&](const Cfg& c) {
@@ -682,7 +720,11 @@ Plan make_plan(Prec prec, const GemmDesc& d, const GemmCall& c, const GemmArgs& 
   Plan p;
   p.ci = (v.cfg >= 0 && v.cfg < kNumCfgs && cfg_ok(v.cfg, cplx)) ? v.cfg : pick_cfg(d.M, d.N, cplx);
   p.ks = v.ks == 1 || v.ks == 2 ? v.ks : 1;
-  if (!ks_ok(p.ci, p.ks, cplx)) p.ks = 1;
+  if (prec == Prec::BF16) {
+    p.ks = 2;
+    if (p.ci == 6) p.ci = 5;
+  }
+  if (!ks_ok(p.ci, p.ks, prec)) p.ks = 1;
   const Cfg cf = kCfgs[p.ci];
   const int64_t ntotal = (int64_t)cdiv(d.M, cf.BM()) * cdiv(d.N, cf.BN());
   const int bk = 16 * p.ks;
@@ -697,7 +739,7 @@ Plan make_plan(Prec prec, const GemmDesc& d, const GemmCall& c, const GemmArgs& 
   ksplit = std::min<int64_t>(ksplit, std::max<int64_t>(1, d.K / bk));
   int64_t kchunk = (d.K + ksplit - 1) / ksplit;
   // the staged K tables must fit next to the two operand stages
-  const int elt_c = prec == Prec::F32 ? 4 : 8;
+  const int elt_c = prec == Prec::F32 ? 4 : (prec == Prec::BF16 ? 2 : 8);
   const int ldk = bk + 16 / elt_c;
   const int64_t stage_bytes = 2LL * (cplx ? 2 : 1) * (cf.BM() + cf.BN()) * ldk * elt_c;
   const int ntab = a.tabA + a.tabB;
@@ -750,6 +792,15 @@ void run_plan(Ctx& ctx, Prec prec, const GemmDesc& d, const GemmCall& c, GemmArg
         if (p.ksplit > 1) splitk_reduce_kernel<false, float><<<1024, 256, 0, st>>>(a, c.batch);
       }
       break;
+    case Prec::BF16:
+      if (c.out_f64) {
+        launch_cfg<__bf16, false, __bf16, double, 2>(p.ci, p.grid, p.lds, st, a);
+        if (p.ksplit > 1) splitk_reduce_kernel<false, double><<<1024, 256, 0, st>>>(a, c.batch);
+      } else {
+        launch_cfg<__bf16, false, __bf16, __bf16, 2>(p.ci, p.grid, p.lds, st, a);
+        if (p.ksplit > 1) splitk_reduce_kernel<false, __bf16><<<1024, 256, 0, st>>>(a, c.batch);
+      }
+      break;
   }
   HP_CHECK_HIP(hipGetLastError());
 }
@@ -770,8 +821,9 @@ bool tunable(Ctx& ctx, Prec prec, const GemmCall& c, int64_t nA, int64_t nB, int
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   if (hipStreamIsCapturing(ctx.stream, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone)
     return false;
-  const int64_t ein = prec == Prec::F32 ? 4 : (prec == Prec::C128 ? 16 : 8);
-  const int64_t eout = prec == Prec::F32 && !c.out_f64 ? 4 : (prec == Prec::C128 ? 16 : 8);
+  const int64_t ein = prec == Prec::F32 ? 4 : prec == Prec::BF16 ? 2 : (prec == Prec::C128 ? 16 : 8);
+  const int64_t eout = c.out_f64 || prec == Prec::F64 || prec == Prec::C128 ? (prec == Prec::C128 ? 16 : 8)
+                                                                            : ein;
   auto range = [](const void* p, int64_t s, int64_t n, int batch, int64_t e) {
     const char* b = static_cast<const char*>(p);
     return std::make_pair(b, b + ((int64_t)(batch - 1) * s + n) * e);
@@ -795,7 +847,7 @@ GemmVariant tune(Ctx& ctx, Prec prec, const GemmDesc& d, const GemmCall& c, cons
   for (int ci = 0; ci < kNumCfgs; ++ci) {
     if (!cfg_ok(ci, cplx)) continue;
     for (int ks = 1; ks <= 2; ++ks) {
-      if (!ks_ok(ci, ks, cplx)) continue;
+      if (!ks_ok(ci, ks, prec)) continue;
       const int64_t h = make_plan(prec, d, c, a, GemmVariant{ci, ks, 0}).ksplit;
       for (int64_t sp : {(int64_t)0, (int64_t)1, 2 * h, 4 * h}) {
         GemmVariant v{ci, ks, (int)sp};
@@ -882,7 +934,7 @@ void gemm(Ctx& ctx, Prec prec, const GemmDesc& d, const GemmCall& c) {
   a.nscale_ld = c.nscale_ld;
   a.copy_if_zero = c.copy_if_zero;
   // per-instance extents for the buffer resources (byte offsets are 32-bit)
-  const int64_t elt_in = prec == Prec::F32 ? 4 : (cplx ? 16 : 8);
+  const int64_t elt_in = prec == Prec::F32 ? 4 : prec == Prec::BF16 ? 2 : (cplx ? 16 : 8);
   HP_REQUIRE(nA * elt_in < (1LL << 32) - 16 && nB * elt_in < (1LL << 32) - 16, HPEPS_ERR_UNSUPPORTED,
              "gemm operand exceeds 4 GiB per instance");
   a.nA_bytes = (unsigned)(nA * elt_in);
@@ -912,9 +964,10 @@ void gemm(Ctx& ctx, Prec prec, const GemmDesc& d, const GemmCall& c) {
   const Cfg cf = kCfgs[p.ci];
   int rec = -1;
   if (ctx.prof_on) {
-    static const char* pn[] = {"f64", "c128", "f32"};
+    static const char* pn[] = {"f64", "c128", "f32", "bf16"};
     const std::string name = std::string("gemm_") + pn[(int)prec] +
-                             (prec == Prec::F32 && !c.out_f64 ? "o32" : "") + "_" +
+                             (prec == Prec::F32 && !c.out_f64 ? "o32" : "") +
+                             (prec == Prec::BF16 && !c.out_f64 ? "o16" : "") + "_" +
                              std::to_string(cf.BM()) + "x" + std::to_string(cf.BN()) + "k" +
                              std::to_string(16 * p.ks);
     rec = ctx.prof_begin(name);
@@ -924,7 +977,7 @@ void gemm(Ctx& ctx, Prec prec, const GemmDesc& d, const GemmCall& c) {
     // algorithmic work of the product: 2 M N K per instance (complex: 4 real
     // products per multiply-add); bytes: each operand element once
     const double mnk = 2.0 * (double)d.M * (double)d.N * (double)d.K * c.batch * (cplx ? 4 : 1);
-    const double elt = prec == Prec::F32 ? 4.0 : (cplx ? 16.0 : 8.0);
+    const double elt = prec == Prec::F32 ? 4.0 : prec == Prec::BF16 ? 2.0 : (cplx ? 16.0 : 8.0);
     const double byt = ((double)d.M * d.K + (double)d.K * d.N + (double)d.M * d.N) * c.batch * elt;
     ctx.prof_end(rec, mnk, byt);
   }

@@ -61,7 +61,8 @@ std::vector<int64_t> rm_strides(const std::vector<int64_t>& shape);
 // ---------------------------------------------------------------------------
 // GEMM with gathered operands:
 //   C[b][rC[m] + cC[n]] = scale * sum_k A[b][rA[m] + cA[k]] * B[b][rB[k] + cB[n]]
-enum class Prec { F64, C128, F32 };
+// F32 / BF16: inputs in that type, FP32 accumulation; output FP64 or the input type
+enum class Prec { F64, C128, F32, BF16 };
 
 struct GemmDesc {
   IndexMap Am, Ak, Bk, Bn, Cm, Cn;  // M/K/N index maps of each operand
@@ -81,7 +82,8 @@ struct GemmCall {
   int64_t nscale_ld = 0;
   bool accumulate = false;         // C += result
   const int* copy_if_zero = nullptr; // per batch flag: when 0, C := A (no product)
-  // storage types (F32 compute only): inputs float; output float or double
+  // storage types (F32 / BF16 compute only): inputs float / bf16; output that
+  // type, or double when out_f64
   bool out_f64 = true;
   // per-instance element counts of A, B, C: every gathered offset is checked
   // against them on the host before the launch (0 = the operand is not checked)
@@ -126,6 +128,8 @@ void sketch(Ctx& ctx, void* out, bool f32, int64_t n, int64_t k, int batch, uint
             uint64_t stream_id, bool cplx_out = false);
 // Elementwise conversion and scaling helpers.
 void convert_f64_to_f32(Ctx& ctx, const double* in, float* out, int64_t n);
+// round to nearest even bfloat16 (out: n 16-bit values)
+void convert_f64_to_bf16(Ctx& ctx, const double* in, void* out, int64_t n);
 void fill_zero(Ctx& ctx, void* p, int64_t bytes);
 // p[0..n) = v (complex: real part v, imaginary part 0), by a kernel (no memset
 // nodes, so the call can sit in a captured graph)

@@ -447,6 +447,11 @@ __global__ __launch_bounds__(kJacMaxThreads) void jacobi_kernel(const double* Ra
   }
 }
 
+__global__ void f64_to_bf16_kernel(const double* in, __bf16* out, long long n) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    out[i] = (__bf16)in[i];
+}
+
 __global__ void f64_to_f32_kernel(const double* in, float* out, long long n) {
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
     out[i] = (float)in[i];
@@ -714,6 +719,13 @@ void jacobi_svd(Ctx& ctx, bool cplx, const double* Racc, int64_t k, int batch, i
     jacobi_kernel<false><<<batch, threads, lds, ctx.stream>>>(Racc, (int)k, max_sweeps, Z, sigma, inv_sigma,
                                                                     inv_sigma1, log_scale, stats);
   }
+  HP_CHECK_HIP(hipGetLastError());
+}
+
+void convert_f64_to_bf16(Ctx& ctx, const double* in, void* out, int64_t n) {
+  if (n <= 0) return;
+  f64_to_bf16_kernel<<<std::min<unsigned>(cdiv(n, 256), 4096), 256, 0, ctx.stream>>>(
+      in, static_cast<__bf16*>(out), n);
   HP_CHECK_HIP(hipGetLastError());
 }
 

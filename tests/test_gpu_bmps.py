@@ -80,6 +80,16 @@ def test_norm_fp32_sketch(ctx):
     assert abs(ln - lo) < 1e-4
 
 
+@pytest.mark.parametrize("m,p,q", [(6, 4, 2), (16, 8, 2)])
+def test_norm_bf16_sketch(ctx, m, p, q):
+    """BF16 operator applications: the log norm within 3e-2 of the FP64 oracle."""
+    peps = synth.random_peps(5, 5, D=2, seed=11)
+    lo, _ = bmps.peps_norm(peps, m=m, p=p, q=q, seed=0)
+    ln, _ = hp.peps_norm(ctx, dev_lattice(peps), rank=m, oversample=p, power_iters=q, seed=0,
+                         precision="bf16")
+    assert abs(ln - lo) < 3e-2
+
+
 def test_norm_tiny_scale_is_finite(ctx):
     peps = synth.random_peps(4, 4, D=2, seed=4)
     ref, _ = hp.peps_norm(ctx, dev_lattice(peps), rank=4, oversample=4, power_iters=1)

@@ -157,6 +157,45 @@ def test_pair_fp32_sketch(ctx):
         assert np.max(np.abs(prod - (Uo * so) @ Vho)) <= 1e-4 * so[0] * 10
 
 
+@pytest.mark.parametrize("shape", [(12, 3, 2, 16, 8, 3), (20, 4, 2, 24, 8, 2)])
+def test_pair_bf16_sketch(ctx, shape):
+    """BF16 operator applications (FP32 accumulation, FP64 factorizations): singular values
+    normwise within 3e-2 of the FP64 oracle on the same (unrounded) sketch."""
+    m, D, d, rank, p, q = shape
+    inst = [synth.pair_instance(m, D, d, seed=9, instance=i) for i in range(2)]
+    st = [np.stack([t[j] for t in inst]) for j in range(4)]
+    U, s, R = hp.einsumsvd_pair(ctx, *[_dev(t) for t in st], rank=rank, oversample=p,
+                                power_iters=q, seed=1, stream_id=5, precision="bf16",
+                                absorb=hp.ABSORB_NONE)
+    U, s, R = U.cpu().numpy(), s.cpu().numpy(), R.cpu().numpy()
+    for i in range(2):
+        op = pair_operator(*inst[i])
+        k = rsvd.sketch_width(rank, p, op.n_rows, op.n_cols)
+        om = oracle_sketch(1, 5 + i, op.n_cols, k)
+        Uo, so, Vho = rsvd.randomized_svd(op.apply, op.apply_adj, op.n_rows, op.n_cols, rank, q, om)
+        assert np.max(np.abs(s[i] - so)) <= 3e-2 * so[0]
+        # the left factor is an isometry to FP64 accuracy (orthogonalization stays FP64)
+        Ui = U[i].reshape(-1, rank)
+        assert np.max(np.abs(Ui.T @ Ui - np.eye(rank))) < 1e-10
+
+
+def test_pair_full_size_bf16(ctx):
+    """The benchmarked configuration in BF16: instances 0 and 63, singular values normwise
+    within 3e-2 of the FP64 oracle."""
+    m, D, d, rank, p, q, B = 36, 6, 2, 36, 8, 2, 64
+    inst = [synth.pair_instance(m, D, d, seed=0, instance=i) for i in range(B)]
+    st = [np.stack([t[j] for t in inst]) for j in range(4)]
+    U, s, R = hp.einsumsvd_pair(ctx, *[_dev(t) for t in st], rank=rank, oversample=p,
+                                power_iters=q, seed=0, stream_id=1, precision="bf16",
+                                absorb=hp.ABSORB_NONE)
+    s = s.cpu().numpy()
+    for i in (0, B - 1):
+        op = pair_operator(*inst[i])
+        om = oracle_sketch(0, 1 + i, op.n_cols, rank + p)
+        _, so, _ = rsvd.randomized_svd(op.apply, op.apply_adj, op.n_rows, op.n_cols, rank, q, om)
+        assert np.max(np.abs(s[i] - so)) <= 3e-2 * so[0]
+
+
 def test_pair_full_size_sampled(ctx):
     """The benchmarked configuration (m=36, D=6, d=2, rank 36, p=8, q=2, 64
     instances): instances 0 and 63 against the oracle."""
