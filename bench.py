@@ -143,6 +143,54 @@ def d8_variant(hp, ctx, steps, m=64, D=8, d=2, rank=64, p=8, q=2, batch=16):
             "kernel_classes": {n: round(a["ms"], 4) for n, a in sorted(agg.items(), key=lambda x: -x[1]["ms"])}}
 
 
+def c3_flops(n=12, D=10, d=2, m=100, p=8, q=1):
+    """Algorithmic flops of one peps_norm of an n x n lattice: the bulk einsumsvd count of
+    the zip-up operator (s1, s2: 2 d D^6 m k each; s3, s4: 2 D^4 m^2 k each) times the
+    (n-2)(n-1) truncating steps, plus the orthogonalizations and factor products."""
+    k = m + p
+    fa = 4 * d * D ** 6 * m * k + 4 * D ** 4 * m * m * k
+    rows, cols = m * D * D, m * D ** 4
+    fqr = lambda nn: 2 * nn * k * k - 2 * k ** 3 / 3
+    step = 2 * (q + 1) * fa + (q + 1) * (fqr(rows) + fqr(cols)) + 2 * m * k * (rows + cols)
+    return step * (n - 2) * (n - 1)
+
+
+def c3_norm(hp, n=12, D=10, d=2, m=100, p=8):
+    """peps_norm of a 12 x 12 lattice, bond 10, boundary bond 100 (FP64 q=1; FP32 and BF16
+    q=2), iid N(0,1) sites normalised: time per norm and log-norm deviation from FP64."""
+    import numpy as np
+    import torch
+
+    import synth
+    peps = synth.random_peps(n, n, D=D, seed=0)
+    dev = [[torch.from_numpy(np.ascontiguousarray(t)).cuda() for t in row] for row in peps]
+    ctx = hp.Context(0)
+    out = {"workload": f"peps_norm {n}x{n} D={D} d={d} m={m} p={p}"}
+    ref = None
+    for prec, q in (("f64", 1), ("f32", 2), ("bf16", 2)):
+        hp.peps_norm(ctx, dev, rank=m, oversample=p, power_iters=q, precision=prec)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ln, ph = hp.peps_norm(ctx, dev, rank=m, oversample=p, power_iters=q, precision=prec)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        if ref is None:
+            ref = ln
+            hp.profile_start(ctx)
+            hp.peps_norm(ctx, dev, rank=m, oversample=p, power_iters=q, precision=prec)
+            agg = hp.profile_read(ctx)
+            hp.profile_stop(ctx)
+            out["f64_kernel_classes"] = {
+                k: {"ms": round(a["ms"], 2), "launches": a["launches"],
+                    "tflops": round(a["flops"] / max(a["ms"], 1e-9) / 1e9, 2)}
+                for k, a in sorted(agg.items(), key=lambda x: -x[1]["ms"])[:12]}
+        fl = c3_flops(n, D, d, m, p, q)
+        out[prec] = {"q": q, "s_per_norm": round(dt, 4), "log_norm": ln,
+                     "dlog_vs_f64": abs(ln - ref), "alg_tflops": round(fl / dt / 1e12, 3),
+                     "frac_of_fp64_peak": round(fl / dt / 1e12 / MFMA_F64_PEAK_TFLOPS, 4)}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -159,6 +207,8 @@ def main():
                     help="write the tuned choices (loaded + new) to this file after the run")
     ap.add_argument("--d8", type=int, default=3,
                     help="timed steps of the D=8, m=64 variant reported beside the main line (0 skips)")
+    ap.add_argument("--c3", action="store_true",
+                    help="only time peps_norm of the 12x12, D=10, m=100 lattice in FP64, FP32 and BF16")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a device-to-device copy of MIB MiB (reference for the HBM byte counters)")
     args = ap.parse_args()
@@ -182,6 +232,10 @@ def main():
 
     import paper_2006_15234_amd as hp
     import synth
+
+    if args.c3:
+        print(json.dumps(c3_norm(hp)))
+        return
 
     inst = [synth.pair_instance(M, DB, DP, seed=0, instance=i) for i in range(BATCH)]
     dev = [torch.from_numpy(np.stack([t[j] for t in inst])).cuda() for j in range(4)]

@@ -621,20 +621,38 @@ bool ks_ok(int ci, int ks, Prec prec) {
   return ks_ok(ci, ks, prec == Prec::C128);
 }
 
-int pick_cfg(int64_t M, int64_t N, bool cplx) {
-  auto waste = [&](const Cfg& c) {
-    const double bm = c.BM(), bn = c.BN();
-    const double tm = std::ceil(M / bm) * bm, tn = std::ceil(N / bn) * bn;
-    return (tm * tn) / double(M * N);
-  };
+// Tile shape from a simple cost model: time = max(padded MFMA work at a
+// shape-dependent efficiency, HBM traffic with the re-reads the tiling
+// implies), divided by the fill of the chip.  An operand is re-read once per
+// tile row (B) or column (A) unless one instance of it fits in an L2 share.
+double tile_cost(const Cfg& c, int64_t M, int64_t N, int64_t K, int64_t batch, double elt) {
+  const double mt = std::ceil(M / double(c.BM())), nt = std::ceil(N / double(c.BN()));
+  const double work = 2.0 * mt * c.BM() * nt * c.BN() * std::max<int64_t>(K, 1) * batch;
+  // MFMA efficiency grows with the MFMA tiles a wavefront owns (LDS reads
+  // per MFMA fall); the 16-tile shape runs at one wavefront per SIMD
+  static const double eff_by_tiles[17] = {0, .30, .45, .55, .70, .70, .75, .75, .80,
+                                          .80, .80, .80, .80, .80, .80, .80, .70};
+  const double eff = eff_by_tiles[std::min(16, c.TM * c.TN)];
+  const double l2 = 2.0 * 1024 * 1024;
+  const double a = double(M) * K * elt, b = double(K) * N * elt, cc = double(M) * N * elt;
+  const double bytes = batch * (a * (a < l2 ? 1 : nt) + b * (b < l2 ? 1 : mt) + cc);
+  // compute and memory overlap imperfectly
+  const double tc = work / (78.6e12 * eff), tm = bytes / 6.0e12;
+  const double t = std::max(tc, tm) + 0.25 * std::min(tc, tm);
+  // long-K products are split when the tile grid is small (see make_plan)
+  double blocks = mt * nt * batch;
+  if (blocks < 1024 && K >= 256) blocks *= std::min(std::ceil(1024.0 / blocks), double(K / 128));
+  return t / std::min(1.0, blocks / 512.0);
+}
+
+int pick_cfg(int64_t M, int64_t N, int64_t K, int64_t batch, bool cplx, double elt) {
   int best = 0;
-  double bw = 1e30;
+  double bc = 1e300;
   for (int i = 0; i < kNumCfgs; ++i) {
     if (!cfg_ok(i, cplx)) continue;
-    // prefer larger tiles at equal waste (more reuse per loaded element)
-    const double w = waste(kCfgs[i]) * (1.0 + 0.02 * (4096.0 / (kCfgs[i].BM() * kCfgs[i].BN())));
-    if (w < bw) {
-      bw = w;
+    const double c = tile_cost(kCfgs[i], M, N, K, batch, elt);
+    if (c < bc * 0.999) {
+      bc = c;
       best = i;
     }
   }
@@ -718,7 +736,10 @@ struct Plan {
 Plan make_plan(Prec prec, const GemmDesc& d, const GemmCall& c, const GemmArgs& a, GemmVariant v) {
   const bool cplx = prec == Prec::C128;
   Plan p;
-  p.ci = (v.cfg >= 0 && v.cfg < kNumCfgs && cfg_ok(v.cfg, cplx)) ? v.cfg : pick_cfg(d.M, d.N, cplx);
+  p.ci = (v.cfg >= 0 && v.cfg < kNumCfgs && cfg_ok(v.cfg, cplx))
+             ? v.cfg
+             : pick_cfg(d.M, d.N, d.K, c.batch, cplx,
+                        prec == Prec::F32 ? 4.0 : prec == Prec::BF16 ? 2.0 : (cplx ? 16.0 : 8.0));
   p.ks = v.ks == 1 || v.ks == 2 ? v.ks : 1;
   if (prec == Prec::BF16) {
     p.ks = 2;
