@@ -216,6 +216,42 @@ hpeps_status hpeps_einsumsvd_pair(hpeps_ctx* ctx, int64_t batch, hpeps_dtype dty
                                   const hpeps_esvd_opts* opts, hpeps_absorb absorb,
                                   void* U, double* sigma, void* R);
 
+/* ---- adjoint of the pair einsumsvd (reverse mode) -------------------------
+ * Vector-Jacobian product of hpeps_einsumsvd_pair with the sketch held fixed.
+ * The paper differentiates nothing; this is the derivative of Alg. 4 as it
+ * runs (every CholeskyQR and the small SVD differentiated), for optimizing
+ * PEPS tensors against quantities built from the einsumsvd outputs.  Given
+ * the cotangents of the outputs
+ *     dU [batch][m, D, D, m'], dsigma [batch][m'] (device double; NULL = 0),
+ *     dR [batch][m', D, D, m]
+ * it writes the gradients of the real loss into gBl, gBr, gT1, gT2 (device,
+ * caller-owned, the shapes of Bl, Br, T1, T2, overwritten); complex tensors
+ * get the conjugate Wirtinger gradient dL/dRe + i dL/dIm.  The forward pass
+ * is recomputed inside the call from the same inputs and opts (same sketch,
+ * same outputs), then the reverse sweep runs on the GPU: truncated-SVD
+ * backward, CholeskyQR backward of every orthogonalization, the adjoint of
+ * every operator application, and the contraction of the operator cotangent
+ * with the network for each tensor.  The 1 / (s_j^2 - s_i^2) factors of the
+ * SVD backward are Lorentzian-broadened, d / (d^2 + broadening * s_1^4) with
+ * d = s_j^2 - s_i^2 (0 where d = 0); broadening = 0 gives the exact
+ * derivative, a small value (1e-12) bounds the gradient of (near-)degenerate
+ * spectra.  The result is the exact derivative of the algorithm for losses
+ * that do not depend on the phase of the singular vectors (the canonical
+ * phase choice is not differentiated).
+ *   absorb: HPEPS_ABSORB_NONE or RIGHT, as in the forward call; the
+ *   sketch_precision of opts must be HPEPS_F64.  Workspace: a few times the
+ *   forward call's (all panels of the power iteration are kept).
+ * Errors: as hpeps_einsumsvd_pair; HPEPS_ERR_UNSUPPORTED for the CARRY mode,
+ * HPEPS_ERR_DTYPE for a non-FP64 sketch, HPEPS_ERR_INVALID_ARG for a
+ * negative broadening. */
+hpeps_status hpeps_einsumsvd_pair_backward(hpeps_ctx* ctx, int64_t batch, hpeps_dtype dtype,
+                                           const int64_t dims[3], const void* Bl, const void* Br,
+                                           const void* T1, const void* T2,
+                                           const hpeps_esvd_opts* opts, hpeps_absorb absorb,
+                                           double broadening, const void* dU, const double* dsigma,
+                                           const void* dR, void* gBl, void* gBr, void* gT1,
+                                           void* gT2);
+
 /* ---- PEPS and boundary-MPS containers ---------------------------------- */
 typedef struct {
   int32_t nrow, ncol;
@@ -278,6 +314,39 @@ hpeps_status hpeps_peps_energy(hpeps_ctx* ctx, const hpeps_peps* ket, int32_t n_
                                const int32_t* nsites, const int32_t* sites,
                                const double* ops, const int64_t* op_offset,
                                const hpeps_esvd_opts* opts, double* energy, double* per_term);
+
+/* ---- gradients of peps_norm / peps_energy (reverse mode) -----------------
+ * The paper evaluates these quantities; it does not differentiate them.
+ * These calls give their gradients with respect to every site tensor, for
+ * variational optimisation of the PEPS: the forward contraction runs once
+ * while a reverse-mode tape records every product, exact carry and
+ * einsumsvd (with the FP64 sketch, same stream ids as the forward call), then
+ * the tape is walked backwards on the GPU.  Each einsumsvd's adjoint
+ * recomputes its own power iteration from the kept inputs (checkpoint and
+ * recompute per einsumsvd; boundary tensors and carries stay in the
+ * workspace).  The Frobenius and sigma_1 rescalings are constants of the
+ * derivative: the energy is a ratio and log<psi|psi> a log-derivative, so
+ * neither depends on them.  Derivatives of the canonical phase of every
+ * singular pair are included.  broadening: Lorentzian width of the SVD
+ * backward, as in hpeps_einsumsvd_pair_backward (0 = exact).
+ *   grads: nrow*ncol device pointers (row-major over sites), each a
+ *   caller-owned buffer with the shape and dtype of its site, overwritten
+ *   with dL/dRe + i dL/dIm.  Workspace grows with the whole contraction
+ *   (every boundary tensor, carry and strip intermediate is kept).
+ * hpeps_peps_norm_backward: L = log<psi|psi> (bra = ket), value to
+ *   *log_norm.
+ * hpeps_peps_energy_backward: L = Re E with E the energy of
+ *   hpeps_peps_energy (same term arguments), E to energy[2].
+ * Both synchronise.  Errors as the forward calls; HPEPS_ERR_INVALID_ARG for
+ * a null gradient pointer or a negative broadening. */
+hpeps_status hpeps_peps_norm_backward(hpeps_ctx* ctx, const hpeps_peps* ket,
+                                      const hpeps_esvd_opts* opts, double broadening,
+                                      void* const* grads, double* log_norm);
+hpeps_status hpeps_peps_energy_backward(hpeps_ctx* ctx, const hpeps_peps* ket, int32_t n_terms,
+                                        const int32_t* nsites, const int32_t* sites,
+                                        const double* ops, const int64_t* op_offset,
+                                        const hpeps_esvd_opts* opts, double broadening,
+                                        void* const* grads, double* energy);
 
 /* ---- apply_two_site_gate (QR-SVD, Alg. 1 / Eq. 4) -----------------------
  * In place on two neighbouring sites of *peps: site (i,j) and its right

@@ -72,12 +72,20 @@ _SIGS = {
                                         C.POINTER(EsvdOpts), C.c_int, _P, _P, _P, _P]),
     "hpeps_einsumsvd_pair": (C.c_int, [_P, C.c_int64, C.c_int, _I64P, _P, _P, _P, _P,
                                        C.POINTER(EsvdOpts), C.c_int, _P, _P, _P]),
+    "hpeps_einsumsvd_pair_backward": (C.c_int, [_P, C.c_int64, C.c_int, _I64P, _P, _P, _P, _P,
+                                                C.POINTER(EsvdOpts), C.c_int, C.c_double, _P,
+                                                _P, _P, _P, _P, _P, _P]),
     "hpeps_boundary_contract_row": (C.c_int, [_P, C.POINTER(Bmps), C.POINTER(Peps), C.POINTER(Peps),
                                               C.c_int32, C.c_int, C.POINTER(EsvdOpts),
                                               C.POINTER(Bmps), _DP]),
     "hpeps_peps_norm": (C.c_int, [_P, C.POINTER(Peps), C.POINTER(Peps), C.POINTER(EsvdOpts), _DP, _DP]),
     "hpeps_peps_energy": (C.c_int, [_P, C.POINTER(Peps), C.c_int32, C.POINTER(C.c_int32),
                                     C.POINTER(C.c_int32), _DP, _I64P, C.POINTER(EsvdOpts), _DP, _DP]),
+    "hpeps_peps_norm_backward": (C.c_int, [_P, C.POINTER(Peps), C.POINTER(EsvdOpts), C.c_double,
+                                           C.POINTER(C.c_void_p), _DP]),
+    "hpeps_peps_energy_backward": (C.c_int, [_P, C.POINTER(Peps), C.c_int32, C.POINTER(C.c_int32),
+                                             C.POINTER(C.c_int32), _DP, _I64P, C.POINTER(EsvdOpts),
+                                             C.c_double, C.POINTER(C.c_void_p), _DP]),
     "hpeps_apply_two_site_gate": (C.c_int, [_P, C.POINTER(Peps), _I64P, C.c_int32, C.c_int32,
                                             C.c_int32, _P, C.c_int64, _I64P, _P]),
     "hpeps_ite_plan_create": (C.c_int, [_P, C.POINTER(Peps), C.c_int32, _P, C.POINTER(C.c_int32),

@@ -1,7 +1,8 @@
 """Torch-tensor front end of the C ABI (argument marshalling only)."""
 import ctypes as C
 
-from ._ffi import (ABSORB_CARRY, C128, F32, BF16, F64, Bmps, EsvdInfo, EsvdOpts, Peps)
+from ._ffi import (ABSORB_CARRY, ABSORB_NONE, C128, F32, BF16, F64, Bmps, EsvdInfo, EsvdOpts,
+                   Peps)
 
 _PREC = {"f64": F64, "f32": F32, "bf16": BF16}
 
@@ -91,6 +92,72 @@ def einsumsvd_pair(ctx, Bl, Br, T1, T2, *, rank, oversample=0, power_iters=0, se
         ctx.h, Bn, dt, dims, _dev(Bl, "Bl"), _dev(Br, "Br"), _dev(T1, "T1"), _dev(T2, "T2"),
         C.byref(o), absorb, _dev(U, "U"), _dev(sig, "sigma"), _dev(R, "R")))
     return U, sig, R
+
+
+def einsumsvd_pair_backward(ctx, Bl, Br, T1, T2, dU, dsigma, dR, *, rank, oversample=0,
+                            power_iters=0, seed=0, stream_id=0, absorb=ABSORB_NONE,
+                            jacobi_max_sweeps=0, broadening=0.0):
+    """Vector-Jacobian product of einsumsvd_pair (FP64 sketch, absorb NONE or RIGHT): the
+    cotangents dU, dsigma (None = 0), dR of its outputs give (gBl, gBr, gT1, gT2), the
+    conjugate-Wirtinger gradients of the real loss with respect to the four inputs.
+    broadening: Lorentzian width of the SVD backward's 1/(s_j^2 - s_i^2), relative to
+    s_1^4 (0 = exact derivative)."""
+    torch = _torch()
+    Bn, m, D, _, _ = Bl.shape
+    d = T1.shape[-1]
+    rows = m * D * D
+    k = min(rank + oversample, rows, rows)
+    mp = min(rank, k)
+    if tuple(dU.shape) != (Bn, m, D, D, mp) or tuple(dR.shape) != (Bn, mp, D, D, m) \
+            or (dsigma is not None and tuple(dsigma.shape) != (Bn, mp)):
+        raise ValueError("cotangent shapes do not match the outputs")
+    dt = _dtype_code(Bl)
+    for t, nm in ((dU, "dU"), (dR, "dR")):
+        if t.dtype != Bl.dtype:
+            raise TypeError(f"{nm} must have the dtype of the inputs")
+    if dsigma is not None and dsigma.dtype != torch.float64:
+        raise TypeError("dsigma must be float64")
+    grads = [torch.empty_like(t) for t in (Bl, Br, T1, T2)]
+    dims = (C.c_int64 * 3)(m, D, d)
+    o = make_opts(rank, oversample, power_iters, "f64", seed, stream_id, jacobi_max_sweeps)
+    ctx.sync_stream()
+    ctx.check(ctx.lib.hpeps_einsumsvd_pair_backward(
+        ctx.h, Bn, dt, dims, _dev(Bl, "Bl"), _dev(Br, "Br"), _dev(T1, "T1"), _dev(T2, "T2"),
+        C.byref(o), absorb, float(broadening), _dev(dU, "dU"), _dev(dsigma, "dsigma") if dsigma is not None else None,
+        _dev(dR, "dR"), *[_dev(g, "grad") for g in grads]))
+    return tuple(grads)
+
+
+def einsumsvd_pair_autograd(ctx, Bl, Br, T1, T2, *, rank, oversample=0, power_iters=0, seed=0,
+                            stream_id=0, absorb=ABSORB_NONE, jacobi_max_sweeps=0, broadening=0.0):
+    """einsumsvd_pair as a differentiable torch function: forward and backward both run
+    in the library (the backward recomputes the forward with the same sketch)."""
+    torch = _torch()
+    kw = dict(rank=rank, oversample=oversample, power_iters=power_iters, seed=seed,
+              stream_id=stream_id, absorb=absorb, jacobi_max_sweeps=jacobi_max_sweeps)
+
+    class _PairEsvd(torch.autograd.Function):
+        @staticmethod
+        def forward(fctx, Bl, Br, T1, T2):
+            fctx.save_for_backward(Bl, Br, T1, T2)
+            return einsumsvd_pair(ctx, Bl, Br, T1, T2, precision="f64", **kw)
+
+        @staticmethod
+        def backward(fctx, gU, gs, gR):
+            Bl, Br, T1, T2 = fctx.saved_tensors
+            mp = min(rank, min(rank + oversample, Bl.shape[1] * Bl.shape[2] ** 2))
+            shapeU = (Bl.shape[0], Bl.shape[1], Bl.shape[2], Bl.shape[2], mp)
+            shapeR = (Bl.shape[0], mp, Bl.shape[2], Bl.shape[2], Bl.shape[1])
+            gU = torch.zeros(shapeU, dtype=Bl.dtype, device=Bl.device) if gU is None \
+                else gU.contiguous()
+            gR = torch.zeros(shapeR, dtype=Bl.dtype, device=Bl.device) if gR is None \
+                else gR.contiguous()
+            gs = None if gs is None else gs.contiguous()
+            return einsumsvd_pair_backward(ctx, Bl.contiguous(), Br.contiguous(), T1.contiguous(),
+                                           T2.contiguous(), gU, gs, gR, broadening=broadening,
+                                           **kw)
+
+    return _PairEsvd.apply(Bl, Br, T1, T2)
 
 
 def sketch(ctx, n, k, batch=1, seed=0, stream_id=0, precision="f64", device="cuda"):
@@ -240,13 +307,8 @@ def boundary_contract_row(ctx, bnd, ket, bra=None, *, row, direction, rank, over
     return res, ls.value
 
 
-def peps_energy(ctx, ket, terms, *, rank, oversample=0, power_iters=0, seed=0, precision="f64"):
-    """terms: list of (sites, op) with op a [2,2] or [2,2,2,2] complex array (host).
-    Returns (energy complex, per-term complex list)."""
+def _terms_arrays(terms):
     import numpy as np
-    keep = []
-    dt = _dtype_code(ket[0][0])
-    pk = _peps_struct(ket, dt, keep)
     n = len(terms)
     ns = (C.c_int32 * n)()
     st = (C.c_int32 * (4 * n))()
@@ -262,7 +324,17 @@ def peps_energy(ctx, ket, terms, *, rank, oversample=0, power_iters=0, seed=0, p
         offs[t] = off
         flat.append(np.stack([a.real, a.imag], axis=-1).ravel())
         off += a.size
-    ops = np.ascontiguousarray(np.concatenate(flat))
+    ops = np.ascontiguousarray(np.concatenate(flat)) if flat else np.zeros(2)
+    return n, ns, st, offs, ops
+
+
+def peps_energy(ctx, ket, terms, *, rank, oversample=0, power_iters=0, seed=0, precision="f64"):
+    """terms: list of (sites, op) with op a [2,2] or [2,2,2,2] complex array (host).
+    Returns (energy complex, per-term complex list)."""
+    keep = []
+    dt = _dtype_code(ket[0][0])
+    pk = _peps_struct(ket, dt, keep)
+    n, ns, st, offs, ops = _terms_arrays(terms)
     o = make_opts(rank, oversample, power_iters, precision, seed, 0)
     e = (C.c_double * 2)()
     per = (C.c_double * (2 * n))()
@@ -271,6 +343,49 @@ def peps_energy(ctx, ket, terms, *, rank, oversample=0, power_iters=0, seed=0, p
                                         ops.ctypes.data_as(C.POINTER(C.c_double)), offs,
                                         C.byref(o), e, per))
     return complex(e[0], e[1]), [complex(per[2 * t], per[2 * t + 1]) for t in range(n)]
+
+
+def _grad_buffers(ket):
+    torch = _torch()
+    grads = [[torch.empty_like(t) for t in row] for row in ket]
+    flat = [g for row in grads for g in row]
+    arr = (C.c_void_p * len(flat))(*[_dev(g, "grad").value for g in flat])
+    return grads, arr
+
+
+def peps_energy_backward(ctx, ket, terms, *, rank, oversample=0, power_iters=0, seed=0,
+                         broadening=0.0):
+    """Gradient of Re E, E = <psi|H|psi> / <psi|psi> from the cached-environment
+    contraction (same terms and options as peps_energy, FP64 sketch), with respect to
+    every site tensor (conjugate Wirtinger for complex sites).  Returns (energy complex,
+    gradients as rows of device tensors shaped like the sites)."""
+    keep = []
+    dt = _dtype_code(ket[0][0])
+    pk = _peps_struct(ket, dt, keep)
+    n, ns, st, offs, ops = _terms_arrays(terms)
+    o = make_opts(rank, oversample, power_iters, "f64", seed, 0)
+    grads, arr = _grad_buffers(ket)
+    e = (C.c_double * 2)()
+    ctx.sync_stream()
+    ctx.check(ctx.lib.hpeps_peps_energy_backward(
+        ctx.h, C.byref(pk), n, ns, st, ops.ctypes.data_as(C.POINTER(C.c_double)), offs, C.byref(o),
+        float(broadening), C.cast(arr, C.POINTER(C.c_void_p)), e))
+    return complex(e[0], e[1]), grads
+
+
+def peps_norm_backward(ctx, ket, *, rank, oversample=0, power_iters=0, seed=0, broadening=0.0):
+    """Gradient of log <psi|psi> (boundary-MPS contraction, FP64 sketch) with respect to
+    every site tensor.  Returns (log <psi|psi>, gradients as rows of device tensors)."""
+    keep = []
+    dt = _dtype_code(ket[0][0])
+    pk = _peps_struct(ket, dt, keep)
+    o = make_opts(rank, oversample, power_iters, "f64", seed, 0)
+    grads, arr = _grad_buffers(ket)
+    ln = C.c_double()
+    ctx.sync_stream()
+    ctx.check(ctx.lib.hpeps_peps_norm_backward(ctx.h, C.byref(pk), C.byref(o), float(broadening),
+                                               C.cast(arr, C.POINTER(C.c_void_p)), C.byref(ln)))
+    return ln.value, grads
 
 
 def apply_two_site_gate(ctx, sites, i, j, axis, G, max_rank):

@@ -235,4 +235,50 @@ hpeps_status hpeps_einsumsvd_pair(hpeps_ctx* ctx, int64_t batch, hpeps_dtype dty
   });
 }
 
+hpeps_status hpeps_einsumsvd_pair_backward(hpeps_ctx* ctx, int64_t batch, hpeps_dtype dtype,
+                                           const int64_t dims[3], const void* Bl, const void* Br,
+                                           const void* T1, const void* T2,
+                                           const hpeps_esvd_opts* opts, hpeps_absorb absorb,
+                                           double broadening, const void* dU, const double* dsigma,
+                                           const void* dR, void* gBl, void* gBr, void* gT1,
+                                           void* gT2) {
+  if (!ctx) return HPEPS_ERR_INVALID_ARG;
+  return guard(ctx, [&] {
+    check_opts(opts);
+    const bool cplx = is_cplx(dtype);
+    HP_REQUIRE(dims && Bl && Br && T1 && T2 && dU && dR && gBl && gBr && gT1 && gT2,
+               HPEPS_ERR_INVALID_ARG, "null argument");
+    HP_REQUIRE(batch >= 1 && batch < 65536, HPEPS_ERR_INVALID_ARG, "batch out of range");
+    HP_REQUIRE(absorb == HPEPS_ABSORB_NONE || absorb == HPEPS_ABSORB_RIGHT, HPEPS_ERR_UNSUPPORTED,
+               "the adjoint supports the NONE and RIGHT absorb modes");
+    const int64_t m = dims[0], D = dims[1], d = dims[2];
+    HP_REQUIRE(m >= 1 && D >= 1 && d >= 1, HPEPS_ERR_SHAPE, "dims must be >= 1");
+    hp::Ctx& c = *ctx->impl;
+    c.ws_reset();
+    const int es = cplx ? 2 : 1;
+    hp::CarryDims cd;
+    cd.a = m; cd.u = D; cd.b = m; cd.x = D; cd.h = D; cd.d = d;
+    const hp::CarryLayout cl = hp::CarryLayout::row_major(cd);
+    const int64_t nV = m * D * D * m * D * D, nT = D * D * D * d;
+    double* V = c.ws<double>(batch * nV * es);
+    hp::form_carry(c, cplx, cd, cl, Bl, T1, T1, V, (int)batch);
+    hp::ZipDims z;
+    z.a = m; z.x = D; z.b = m; z.h = D; z.u = D; z.c = m; z.y = D; z.g = 1; z.d = d;
+    hp::ZipOperands op{V, Br, T2, T2};
+    double* gV = c.ws<double>(batch * nV * es);
+    hp::fill_zero(c, gV, batch * nV * es * 8);
+    const int64_t nB = m * D * D * m;
+    hp::fill_zero(c, gBl, batch * nB * es * 8);
+    hp::fill_zero(c, gBr, batch * nB * es * 8);
+    hp::fill_zero(c, gT1, batch * nT * es * 8);
+    hp::fill_zero(c, gT2, batch * nT * es * 8);
+    const int64_t k = hp::sketch_width(opts->rank, opts->oversample, z.rows(), z.cols());
+    // T2 serves as ket and bra: both gradients accumulate into gT2 (same for T1)
+    hp::zip_esvd_backward(c, cplx, z, hp::ZipLayout::row_major(z), op, (int)batch, *opts, absorb,
+                          broadening, hp::ZipOut::row_major(z, std::min<int64_t>(opts->rank, k)), dU,
+                          dsigma, dR, gV, gBr, gT2, gT2);
+    hp::carry_backward(c, cplx, cd, cl, Bl, T1, T1, gV, gBl, gT1, gT1, (int)batch);
+  });
+}
+
 }  // extern "C"

@@ -16,6 +16,7 @@
 
 #include "contract.h"
 #include "peps.h"
+#include "tape.h"
 
 namespace hp {
 namespace {
@@ -200,8 +201,283 @@ __global__ void expect_kernel(const double* const* rdm, const double* const* ops
   out[2 * t + 1] = (ni * dr - nr * di) / den;
 }
 
+// Cotangent of the reduced density matrices for the loss Re sum_t E_t,
+// E_t = tr(O_t rho_t) / tr(rho_t): rhobar_t = conj(dE_t / drho_t) with
+// dE / drho[e] = O-coefficient of rho[e] / tr(rho) - [e diagonal] E / tr(rho)
+// (real lattices: the real part).  Terms that share a matrix accumulate one
+// after the other (one workgroup, a barrier between terms).
+__global__ void expect_bwd_kernel(const double* const* rdm, const double* const* ops, const int* nsites,
+                                  const double* val, int d, int cplx, int nterms, double* const* grad) {
+  for (int t = 0; t < nterms; ++t) {
+    const double* r = rdm[t];
+    const double* o = ops[t];
+    double* g = grad[t];
+    const int two = nsites[t] == 2;
+    // tr(rho)
+    double dr = 0, di = 0;
+    const int nd = two ? d * d : d;
+    for (int q = 0; q < nd; ++q) {
+      long long idx;
+      if (two) {
+        const int p1 = q / d, p2 = q % d;
+        idx = ((long long)(p1 * d + p1) * d + p2) * d + p2;
+      } else {
+        idx = (long long)q * d + q;
+      }
+      dr += cplx ? r[2 * idx] : r[idx];
+      di += cplx ? r[2 * idx + 1] : 0.0;
+    }
+    const double den = dr * dr + di * di;
+    const double er = val[2 * t], ei = val[2 * t + 1];
+    const int nel = two ? d * d * d * d : d * d;
+    for (int e = threadIdx.x; e < nel; e += blockDim.x) {
+      long long oo;
+      bool diag;
+      if (two) {
+        const int P2 = e % d, p2 = (e / d) % d, P1 = (e / (d * d)) % d, p1 = e / (d * d * d);
+        oo = ((long long)(P1 * d + P2) * d + p1) * d + p2;
+        diag = p1 == P1 && p2 == P2;
+      } else {
+        const int P = e % d, p = e / d;
+        oo = (long long)P * d + p;
+        diag = p == P;
+      }
+      double ar = o[2 * oo], ai = o[2 * oo + 1];
+      if (diag) {
+        ar -= er;
+        ai -= ei;
+      }
+      // (ar + i ai) / (dr + i di)
+      const double vr = (ar * dr + ai * di) / den, vi = (ai * dr - ar * di) / den;
+      if (cplx) {
+        g[2 * e] += vr;
+        g[2 * e + 1] -= vi;
+      } else {
+        g[e] += vr;
+      }
+    }
+    __syncthreads();
+  }
+}
+
 }  // namespace
 }  // namespace hp
+
+namespace hp {
+
+void check_terms(const Lattice& K, int n_terms, const int32_t* nsites, const int32_t* sites,
+                 const int64_t* op_offset) {
+  const int nrow = K.nrow, ncol = K.ncol;
+  for (int t = 0; t < n_terms; ++t) {
+    const int* s = sites + 4 * t;
+    HP_REQUIRE(nsites[t] == 1 || nsites[t] == 2, HPEPS_ERR_INVALID_ARG, "terms act on 1 or 2 sites");
+    HP_REQUIRE(s[0] >= 0 && s[0] < nrow && s[1] >= 0 && s[1] < ncol, HPEPS_ERR_INVALID_ARG, "site out of range");
+    if (nsites[t] == 2) {
+      const bool horiz = s[2] == s[0] && s[3] == s[1] + 1, vert = s[3] == s[1] && s[2] == s[0] + 1;
+      HP_REQUIRE(horiz || vert, HPEPS_ERR_INVALID_ARG, "two-site terms must be nearest neighbours, site 1 first");
+    }
+    HP_REQUIRE(op_offset[t] >= 0, HPEPS_ERR_INVALID_ARG, "bad operator offset");
+  }
+}
+
+// Reduced density matrices rho_t (device, d^2 or d^4 elements, row-major
+// [p, P] / [p1, P1, p2, P2]) of every term from the cached environments;
+// terms on the same site or bond share one matrix.
+std::vector<const double*> energy_rdms(Ctx& c, const Lattice& K, int n_terms, const int32_t* nsites,
+                                       const int32_t* sites, const hpeps_esvd_opts& o) {
+  const bool cplx = K.cplx;
+  const int nrow = K.nrow, ncol = K.ncol, d = (int)K.sites[0].dims[4];
+  double* logd = c.ws<double>(1);
+  fill_value(c, logd, 1, 0.0, false);
+  Lattice Kn = normalized_copy(c, K, logd);
+  std::vector<std::vector<DevTensor>> tenv, benv;
+  if (nrow > 1) {
+    boundary_pass(c, Kn, Kn, kTop, o, nrow - 1, tenv, logd);
+    boundary_pass(c, Kn, Kn, kBottom, o, nrow - 1, benv, logd);
+  }
+  // trivial environment
+  const int es = cplx ? 2 : 1;
+  std::vector<DevTensor> triv(ncol);
+  for (auto& t : triv) {
+    t.dims = {1, 1, 1, 1};
+    t.p = c.ws<double>(es);
+    fill_value(c, (double*)t.p, 1, 1.0, cplx);
+  }
+  auto top_of = [&](int i) -> const std::vector<DevTensor>& { return i == 0 ? triv : tenv[i - 1]; };
+  auto bot_of = [&](int i) -> const std::vector<DevTensor>& { return i == nrow - 1 ? triv : benv[nrow - 2 - i]; };
+  std::vector<const double*> rdm_ptr(n_terms, nullptr);
+  // one reduced density matrix slot per term (d^4 elements), allocated
+  // before the strips so that each strip's scratch can be released
+  const int64_t slot = (int64_t)d * d * d * d * es;
+  double* rdm_store = c.ws<double>(std::max<int64_t>(n_terms, 1) * slot);
+
+  // three-layer strips: one-site and horizontal terms
+  for (int i = 0; i < nrow; ++i) {
+    std::vector<int> here;
+    for (int t = 0; t < n_terms; ++t)
+      if (sites[4 * t] == i && (nsites[t] == 1 || sites[4 * t + 2] == i)) here.push_back(t);
+    if (here.empty()) continue;
+    WsScope strip_scope(c);
+    const auto& top = top_of(i);
+    const auto& bot = bot_of(i);
+    auto col = [&](int j, Dir dir, BndView& tv, SiteView& kv, SiteView& bv, BndView& btv) {
+      tv = orient_bnd(top[j], dir);
+      kv = orient_site(Kn.at(i, j), kTop, dir);
+      bv = kv;
+      btv = orient_bnd(bot[j], dir);
+    };
+    std::vector<Ten> Lenv(ncol + 1), Renv(ncol + 1);
+    Lenv[0] = ones(c, cplx, "tlLb");
+    Renv[0] = ones(c, cplx, "tlLb");
+    for (int q = 0; q < ncol; ++q) {
+      BndView tv, btv;
+      SiteView kv, bv;
+      col(q, kL2R, tv, kv, bv, btv);
+      Ten x = transfer3(c, cplx, Lenv[q], tv, kv, bv, btv, false);
+      normalize(c, cplx, x.p, x.size(), 1, logd);
+      x.legs = "tlLb";
+      Lenv[q + 1] = x;
+      col(ncol - 1 - q, kR2L, tv, kv, bv, btv);
+      Ten y = transfer3(c, cplx, Renv[q], tv, kv, bv, btv, false);
+      normalize(c, cplx, y.p, y.size(), 1, logd);
+      y.legs = "tlLb";
+      Renv[q + 1] = y;
+    }
+    std::map<std::pair<int, int>, const double*> cache;  // (j, 1|2) -> rdm
+    for (int t : here) {
+      const int j = sites[4 * t + 1];
+      const int kind = nsites[t];
+      auto key = std::make_pair(j, kind);
+      if (!cache.count(key)) {
+        BndView tv, btv;
+        SiteView kv, bv;
+        col(j, kL2R, tv, kv, bv, btv);
+        double* dst = rdm_store + (int64_t)t * slot;
+        Ten y = transfer3(c, cplx, Lenv[j], tv, kv, bv, btv, true);  // srRcpP
+        if (kind == 1) {
+          Ten R = Renv[ncol - 1 - j];
+          R.legs = "srRc";
+          contract2(c, cplx, y.view(), R.view(), "pP", dst, slot / es);
+        } else {
+          y.legs = "tlLbef";
+          col(j + 1, kL2R, tv, kv, bv, btv);
+          Ten y2 = transfer3(c, cplx, y, tv, kv, bv, btv, true);  // efsrRcpP
+          Ten R = Renv[ncol - 2 - j];
+          R.legs = "srRc";
+          contract2(c, cplx, y2.view(), R.view(), "efpP", dst, slot / es);
+        }
+        cache[key] = dst;
+      }
+      rdm_ptr[t] = cache[key];
+    }
+  }
+  // four-layer strips: vertical terms
+  for (int i = 0; i + 1 < nrow; ++i) {
+    std::vector<int> here;
+    for (int t = 0; t < n_terms; ++t)
+      if (nsites[t] == 2 && sites[4 * t] == i && sites[4 * t + 2] == i + 1) here.push_back(t);
+    if (here.empty()) continue;
+    WsScope strip_scope(c);
+    const auto& top = top_of(i);
+    const auto& bot = bot_of(i + 1);
+    auto col = [&](int j, Dir dir, BndView& tv, SiteView& k1, SiteView& k2, BndView& btv) {
+      tv = orient_bnd(top[j], dir);
+      k1 = orient_site(Kn.at(i, j), kTop, dir);
+      k2 = orient_site(Kn.at(i + 1, j), kTop, dir);
+      btv = orient_bnd(bot[j], dir);
+    };
+    std::vector<Ten> Lenv(ncol + 1), Renv(ncol + 1);
+    Lenv[0] = ones(c, cplx, "tlLmMb");
+    Renv[0] = ones(c, cplx, "tlLmMb");
+    for (int q = 0; q < ncol; ++q) {
+      BndView tv, btv;
+      SiteView k1, k2;
+      col(q, kL2R, tv, k1, k2, btv);
+      Ten x = transfer4(c, cplx, Lenv[q], tv, k1, k1, k2, k2, btv, false);
+      normalize(c, cplx, x.p, x.size(), 1, logd);
+      x.legs = "tlLmMb";
+      Lenv[q + 1] = x;
+      col(ncol - 1 - q, kR2L, tv, k1, k2, btv);
+      Ten y = transfer4(c, cplx, Renv[q], tv, k1, k1, k2, k2, btv, false);
+      normalize(c, cplx, y.p, y.size(), 1, logd);
+      y.legs = "tlLmMb";
+      Renv[q + 1] = y;
+    }
+    std::map<int, const double*> cache;
+    for (int t : here) {
+      const int j = sites[4 * t + 1];
+      if (!cache.count(j)) {
+        BndView tv, btv;
+        SiteView k1, k2;
+        col(j, kL2R, tv, k1, k2, btv);
+        Ten y = transfer4(c, cplx, Lenv[j], tv, k1, k1, k2, k2, btv, true);  // srRnNcpPqQ
+        Ten R = Renv[ncol - 1 - j];
+        R.legs = "srRnNc";
+        double* dst = rdm_store + (int64_t)t * slot;
+        contract2(c, cplx, y.view(), R.view(), "pPqQ", dst, slot / es);
+        cache[j] = dst;
+      }
+      rdm_ptr[t] = cache[j];
+    }
+  }
+  return rdm_ptr;
+}
+
+// Term values tr(O rho) / tr(rho) on the device (2 doubles per term).
+struct TermsDev {
+  double* res = nullptr;
+  const double* const* rp = nullptr;
+  const double* const* op = nullptr;
+  const int* ns = nullptr;
+};
+
+TermsDev term_values(Ctx& c, bool cplx, int d, int n_terms, const int32_t* nsites, const double* ops,
+                     const int64_t* op_offset, const std::vector<const double*>& rdm_ptr) {
+  TermsDev t;
+  t.res = c.ws<double>(2 * std::max(n_terms, 1));
+  if (n_terms == 0) return t;
+  int64_t total = 0;
+  for (int q = 0; q < n_terms; ++q)
+    total = std::max<int64_t>(total, op_offset[q] + (nsites[q] == 1 ? d * d : d * d * d * d));
+  double* ops_dev = c.ws<double>(2 * total);
+  HP_CHECK_HIP(hipMemcpyAsync(ops_dev, ops, 2 * total * sizeof(double), hipMemcpyHostToDevice, c.stream));
+  std::vector<const double*> op_ptr(n_terms);
+  for (int q = 0; q < n_terms; ++q) op_ptr[q] = ops_dev + 2 * op_offset[q];
+  auto* rp = c.ws<const double*>(n_terms);
+  auto* op = c.ws<const double*>(n_terms);
+  int* ns = c.ws<int>(n_terms);
+  HP_CHECK_HIP(hipMemcpyAsync(rp, rdm_ptr.data(), n_terms * sizeof(void*), hipMemcpyHostToDevice, c.stream));
+  HP_CHECK_HIP(hipMemcpyAsync(op, op_ptr.data(), n_terms * sizeof(void*), hipMemcpyHostToDevice, c.stream));
+  HP_CHECK_HIP(hipMemcpyAsync(ns, nsites, n_terms * sizeof(int), hipMemcpyHostToDevice, c.stream));
+  expect_kernel<<<cdiv(n_terms, 64), 64, 0, c.stream>>>(rp, op, ns, d, cplx ? 1 : 0, n_terms, t.res);
+  HP_CHECK_HIP(hipGetLastError());
+  t.rp = rp;
+  t.op = op;
+  t.ns = ns;
+  return t;
+}
+
+// Synchronises; energy = sum of the term values, per_term optional.
+void read_energy(Ctx& c, const TermsDev& t, int n_terms, double* energy, double* per_term) {
+  std::vector<double> h(2 * std::max(n_terms, 1));
+  HP_CHECK_HIP(hipMemcpyAsync(h.data(), t.res, h.size() * sizeof(double), hipMemcpyDeviceToHost, c.stream));
+  HP_CHECK_HIP(hipStreamSynchronize(c.stream));
+  double er = 0, ei = 0;
+  for (int q = 0; q < n_terms; ++q) {
+    HP_REQUIRE(std::isfinite(h[2 * q]) && std::isfinite(h[2 * q + 1]), HPEPS_ERR_NUMERIC, "non-finite term value");
+    er += h[2 * q];
+    ei += h[2 * q + 1];
+    if (per_term) {
+      per_term[2 * q] = h[2 * q];
+      per_term[2 * q + 1] = h[2 * q + 1];
+    }
+  }
+  energy[0] = er;
+  energy[1] = ei;
+}
+
+}  // namespace hp
+
 
 // ---------------------------------------------------------------------------
 // ABI
@@ -215,15 +491,26 @@ hpeps_status guard_e(hpeps_ctx* ctx, F&& f) {
     f(*ctx->impl);
     return HPEPS_OK;
   } catch (const hp::Error& e) {
+    ctx->impl->tape = nullptr;
     ctx->impl->last_error = e.msg;
     return e.code;
   } catch (const std::bad_alloc&) {
+    ctx->impl->tape = nullptr;
     ctx->impl->last_error = "host allocation failed";
     return HPEPS_ERR_ALLOC;
   } catch (...) {
+    ctx->impl->tape = nullptr;
     ctx->impl->last_error = "unknown error";
     return HPEPS_ERR_INVALID_ARG;
   }
+}
+
+void check_energy_args(const hpeps_esvd_opts* opts, int32_t n_terms, const int32_t* nsites, const int32_t* sites,
+                       const double* ops, const int64_t* op_offset, const double* energy) {
+  HP_REQUIRE(opts && opts->rank >= 1 && opts->oversample >= 0 && opts->power_iters >= 0, HPEPS_ERR_INVALID_ARG,
+             "bad einsumsvd options");
+  HP_REQUIRE(n_terms >= 0 && energy && (n_terms == 0 || (nsites && sites && ops && op_offset)),
+             HPEPS_ERR_INVALID_ARG, "null argument");
 }
 }  // namespace
 
@@ -233,189 +520,44 @@ extern "C" hpeps_status hpeps_peps_energy(hpeps_ctx* ctx, const hpeps_peps* ket,
                                           double* per_term) {
   using namespace hp;
   return guard_e(ctx, [&](Ctx& c) {
-    HP_REQUIRE(opts && opts->rank >= 1 && opts->oversample >= 0 && opts->power_iters >= 0, HPEPS_ERR_INVALID_ARG,
-               "bad einsumsvd options");
-    HP_REQUIRE(n_terms >= 0 && energy && (n_terms == 0 || (nsites && sites && ops && op_offset)),
-               HPEPS_ERR_INVALID_ARG, "null argument");
+    check_energy_args(opts, n_terms, nsites, sites, ops, op_offset, energy);
     Lattice K = lattice_from_abi(ket);
-    const bool cplx = K.cplx;
-    const int nrow = K.nrow, ncol = K.ncol, d = (int)K.sites[0].dims[4];
-    // validate terms
-    for (int t = 0; t < n_terms; ++t) {
-      const int* s = sites + 4 * t;
-      HP_REQUIRE(nsites[t] == 1 || nsites[t] == 2, HPEPS_ERR_INVALID_ARG, "terms act on 1 or 2 sites");
-      HP_REQUIRE(s[0] >= 0 && s[0] < nrow && s[1] >= 0 && s[1] < ncol, HPEPS_ERR_INVALID_ARG, "site out of range");
-      if (nsites[t] == 2) {
-        const bool horiz = s[2] == s[0] && s[3] == s[1] + 1, vert = s[3] == s[1] && s[2] == s[0] + 1;
-        HP_REQUIRE(horiz || vert, HPEPS_ERR_INVALID_ARG, "two-site terms must be nearest neighbours, site 1 first");
-      }
-      HP_REQUIRE(op_offset[t] >= 0, HPEPS_ERR_INVALID_ARG, "bad operator offset");
-    }
-    double* logd = c.ws<double>(1);
-    fill_value(c, logd, 1, 0.0, false);
-    Lattice Kn = normalized_copy(c, K, logd);
-    std::vector<std::vector<DevTensor>> tenv, benv;
-    if (nrow > 1) {
-      boundary_pass(c, Kn, Kn, kTop, *opts, nrow - 1, tenv, logd);
-      boundary_pass(c, Kn, Kn, kBottom, *opts, nrow - 1, benv, logd);
-    }
-    // trivial environment
-    const int es = cplx ? 2 : 1;
-    std::vector<DevTensor> triv(ncol);
-    for (auto& t : triv) {
-      t.dims = {1, 1, 1, 1};
-      t.p = c.ws<double>(es);
-      fill_value(c, (double*)t.p, 1, 1.0, cplx);
-    }
-    auto top_of = [&](int i) -> const std::vector<DevTensor>& { return i == 0 ? triv : tenv[i - 1]; };
-    auto bot_of = [&](int i) -> const std::vector<DevTensor>& { return i == nrow - 1 ? triv : benv[nrow - 2 - i]; };
-    std::vector<const double*> rdm_ptr(n_terms, nullptr);
-    // one reduced density matrix slot per term (d^4 elements), allocated
-    // before the strips so that each strip's scratch can be released
-    const int64_t slot = (int64_t)d * d * d * d * es;
-    double* rdm_store = c.ws<double>(std::max<int64_t>(n_terms, 1) * slot);
+    check_terms(K, n_terms, nsites, sites, op_offset);
+    const auto rdm = energy_rdms(c, K, n_terms, nsites, sites, *opts);
+    const TermsDev t = term_values(c, K.cplx, (int)K.sites[0].dims[4], n_terms, nsites, ops, op_offset, rdm);
+    read_energy(c, t, n_terms, energy, per_term);
+  });
+}
 
-    // three-layer strips: one-site and horizontal terms
-    for (int i = 0; i < nrow; ++i) {
-      std::vector<int> here;
-      for (int t = 0; t < n_terms; ++t)
-        if (sites[4 * t] == i && (nsites[t] == 1 || sites[4 * t + 2] == i)) here.push_back(t);
-      if (here.empty()) continue;
-      WsScope strip_scope(c);
-      const auto& top = top_of(i);
-      const auto& bot = bot_of(i);
-      auto col = [&](int j, Dir dir, BndView& tv, SiteView& kv, SiteView& bv, BndView& btv) {
-        tv = orient_bnd(top[j], dir);
-        kv = orient_site(Kn.at(i, j), kTop, dir);
-        bv = kv;
-        btv = orient_bnd(bot[j], dir);
-      };
-      std::vector<Ten> Lenv(ncol + 1), Renv(ncol + 1);
-      Lenv[0] = ones(c, cplx, "tlLb");
-      Renv[0] = ones(c, cplx, "tlLb");
-      for (int q = 0; q < ncol; ++q) {
-        BndView tv, btv;
-        SiteView kv, bv;
-        col(q, kL2R, tv, kv, bv, btv);
-        Ten x = transfer3(c, cplx, Lenv[q], tv, kv, bv, btv, false);
-        normalize(c, cplx, x.p, x.size(), 1, logd);
-        x.legs = "tlLb";
-        Lenv[q + 1] = x;
-        col(ncol - 1 - q, kR2L, tv, kv, bv, btv);
-        Ten y = transfer3(c, cplx, Renv[q], tv, kv, bv, btv, false);
-        normalize(c, cplx, y.p, y.size(), 1, logd);
-        y.legs = "tlLb";
-        Renv[q + 1] = y;
-      }
-      std::map<std::pair<int, int>, const double*> cache;  // (j, 1|2) -> rdm
-      for (int t : here) {
-        const int j = sites[4 * t + 1];
-        const int kind = nsites[t];
-        auto key = std::make_pair(j, kind);
-        if (!cache.count(key)) {
-          BndView tv, btv;
-          SiteView kv, bv;
-          col(j, kL2R, tv, kv, bv, btv);
-          double* dst = rdm_store + (int64_t)t * slot;
-          Ten y = transfer3(c, cplx, Lenv[j], tv, kv, bv, btv, true);  // srRcpP
-          if (kind == 1) {
-            Ten R = Renv[ncol - 1 - j];
-            R.legs = "srRc";
-            contract2(c, cplx, y.view(), R.view(), "pP", dst, slot / es);
-          } else {
-            y.legs = "tlLbef";
-            col(j + 1, kL2R, tv, kv, bv, btv);
-            Ten y2 = transfer3(c, cplx, y, tv, kv, bv, btv, true);  // efsrRcpP
-            Ten R = Renv[ncol - 2 - j];
-            R.legs = "srRc";
-            contract2(c, cplx, y2.view(), R.view(), "efpP", dst, slot / es);
-          }
-          cache[key] = dst;
-        }
-        rdm_ptr[t] = cache[key];
-      }
-    }
-    // four-layer strips: vertical terms
-    for (int i = 0; i + 1 < nrow; ++i) {
-      std::vector<int> here;
-      for (int t = 0; t < n_terms; ++t)
-        if (nsites[t] == 2 && sites[4 * t] == i && sites[4 * t + 2] == i + 1) here.push_back(t);
-      if (here.empty()) continue;
-      WsScope strip_scope(c);
-      const auto& top = top_of(i);
-      const auto& bot = bot_of(i + 1);
-      auto col = [&](int j, Dir dir, BndView& tv, SiteView& k1, SiteView& k2, BndView& btv) {
-        tv = orient_bnd(top[j], dir);
-        k1 = orient_site(Kn.at(i, j), kTop, dir);
-        k2 = orient_site(Kn.at(i + 1, j), kTop, dir);
-        btv = orient_bnd(bot[j], dir);
-      };
-      std::vector<Ten> Lenv(ncol + 1), Renv(ncol + 1);
-      Lenv[0] = ones(c, cplx, "tlLmMb");
-      Renv[0] = ones(c, cplx, "tlLmMb");
-      for (int q = 0; q < ncol; ++q) {
-        BndView tv, btv;
-        SiteView k1, k2;
-        col(q, kL2R, tv, k1, k2, btv);
-        Ten x = transfer4(c, cplx, Lenv[q], tv, k1, k1, k2, k2, btv, false);
-        normalize(c, cplx, x.p, x.size(), 1, logd);
-        x.legs = "tlLmMb";
-        Lenv[q + 1] = x;
-        col(ncol - 1 - q, kR2L, tv, k1, k2, btv);
-        Ten y = transfer4(c, cplx, Renv[q], tv, k1, k1, k2, k2, btv, false);
-        normalize(c, cplx, y.p, y.size(), 1, logd);
-        y.legs = "tlLmMb";
-        Renv[q + 1] = y;
-      }
-      std::map<int, const double*> cache;
-      for (int t : here) {
-        const int j = sites[4 * t + 1];
-        if (!cache.count(j)) {
-          BndView tv, btv;
-          SiteView k1, k2;
-          col(j, kL2R, tv, k1, k2, btv);
-          Ten y = transfer4(c, cplx, Lenv[j], tv, k1, k1, k2, k2, btv, true);  // srRnNcpPqQ
-          Ten R = Renv[ncol - 1 - j];
-          R.legs = "srRnNc";
-          double* dst = rdm_store + (int64_t)t * slot;
-          contract2(c, cplx, y.view(), R.view(), "pPqQ", dst, slot / es);
-          cache[j] = dst;
-        }
-        rdm_ptr[t] = cache[j];
-      }
-    }
-    // term values on the device
-    double* res = c.ws<double>(2 * std::max(n_terms, 1));
+extern "C" hpeps_status hpeps_peps_energy_backward(hpeps_ctx* ctx, const hpeps_peps* ket, int32_t n_terms,
+                                                   const int32_t* nsites, const int32_t* sites, const double* ops,
+                                                   const int64_t* op_offset, const hpeps_esvd_opts* opts,
+                                                   double broadening, void* const* grads, double* energy) {
+  using namespace hp;
+  return guard_e(ctx, [&](Ctx& c) {
+    check_energy_args(opts, n_terms, nsites, sites, ops, op_offset, energy);
+    HP_REQUIRE(grads, HPEPS_ERR_INVALID_ARG, "null gradient array");
+    HP_REQUIRE(broadening >= 0.0, HPEPS_ERR_INVALID_ARG, "broadening must be >= 0");
+    Lattice K = lattice_from_abi(ket);
+    check_terms(K, n_terms, nsites, sites, op_offset);
+    for (size_t q = 0; q < K.sites.size(); ++q) HP_REQUIRE(grads[q], HPEPS_ERR_INVALID_ARG, "null gradient pointer");
+    const int d = (int)K.sites[0].dims[4];
+    Tape tape(K.cplx);
+    for (auto& s : K.sites) tape.mark_input(s.p, s.size());
+    c.tape = &tape;
+    const auto rdm = energy_rdms(c, K, n_terms, nsites, sites, *opts);
+    c.tape = nullptr;
+    const TermsDev t = term_values(c, K.cplx, d, n_terms, nsites, ops, op_offset, rdm);
     if (n_terms > 0) {
-      int64_t total = 0;
-      for (int t = 0; t < n_terms; ++t) total = std::max<int64_t>(total, op_offset[t] + (nsites[t] == 1 ? d * d : d * d * d * d));
-      double* ops_dev = c.ws<double>(2 * total);
-      HP_CHECK_HIP(hipMemcpyAsync(ops_dev, ops, 2 * total * sizeof(double), hipMemcpyHostToDevice, c.stream));
-      std::vector<const double*> op_ptr(n_terms);
-      for (int t = 0; t < n_terms; ++t) op_ptr[t] = ops_dev + 2 * op_offset[t];
-      auto* rp = c.ws<const double*>(n_terms);
-      auto* op = c.ws<const double*>(n_terms);
-      int* ns = c.ws<int>(n_terms);
-      HP_CHECK_HIP(hipMemcpyAsync(rp, rdm_ptr.data(), n_terms * sizeof(void*), hipMemcpyHostToDevice, c.stream));
-      HP_CHECK_HIP(hipMemcpyAsync(op, op_ptr.data(), n_terms * sizeof(void*), hipMemcpyHostToDevice, c.stream));
-      HP_CHECK_HIP(hipMemcpyAsync(ns, nsites, n_terms * sizeof(int), hipMemcpyHostToDevice, c.stream));
-      expect_kernel<<<cdiv(n_terms, 64), 64, 0, c.stream>>>(rp, op, ns, d, cplx ? 1 : 0, n_terms, res);
+      std::vector<double*> gr(n_terms);
+      for (int q = 0; q < n_terms; ++q) gr[q] = tape.grad(c, rdm[q]);
+      auto* gp = c.ws<double*>(n_terms);
+      HP_CHECK_HIP(hipMemcpyAsync(gp, gr.data(), n_terms * sizeof(void*), hipMemcpyHostToDevice, c.stream));
+      expect_bwd_kernel<<<1, 256, 0, c.stream>>>(t.rp, t.op, t.ns, t.res, d, K.cplx ? 1 : 0, n_terms, gp);
       HP_CHECK_HIP(hipGetLastError());
     }
-    std::vector<double> h(2 * std::max(n_terms, 1));
-    HP_CHECK_HIP(hipMemcpyAsync(h.data(), res, h.size() * sizeof(double), hipMemcpyDeviceToHost, c.stream));
-    HP_CHECK_HIP(hipStreamSynchronize(c.stream));
-    double er = 0, ei = 0;
-    for (int t = 0; t < n_terms; ++t) {
-      HP_REQUIRE(std::isfinite(h[2 * t]) && std::isfinite(h[2 * t + 1]), HPEPS_ERR_NUMERIC, "non-finite term value");
-      er += h[2 * t];
-      ei += h[2 * t + 1];
-      if (per_term) {
-        per_term[2 * t] = h[2 * t];
-        per_term[2 * t + 1] = h[2 * t + 1];
-      }
-    }
-    energy[0] = er;
-    energy[1] = ei;
+    tape.backward(c, broadening);
+    write_site_grads(c, tape, K, grads);
+    read_energy(c, t, n_terms, energy, nullptr);
   });
 }

@@ -57,13 +57,19 @@ struct ZipOut {
 
 // A X (adjoint = false, X: cols x k) or A^* X (X: rows x k) for the zip-up
 // operator; Y is written as double when y_f64 (F32 applies), else in the
-// apply precision.
+// apply precision.  With Y == nullptr the last stage is skipped and the
+// first three stages' results stay in w (forward: W1 [u,h,p,Y,c,G,j],
+// W2 [U,H,u,h,c,j], W3 [b,h,H,j]; adjoint: W3, W2 as forward, W1 [Y,G,p,u,h,c,j]).
 void zip_apply(Ctx& ctx, Prec prec, const ZipDims& z, const ZipLayout& L, const ZipOperands& op,
                int batch, int64_t k, bool adjoint, const void* X, void* Y, bool y_f64,
                const ZipWork& w);
 
 void orthogonalize(Ctx& ctx, bool cplx, double* Y, double* P, int64_t n, int64_t k, int batch,
-                   const OrthWork& w);
+                   const OrthWork& w, double* Rt_inv = nullptr);
+// R factor of the CholeskyQR of Y (accumulated over the passes) into w.Racc;
+// S1, S2: n x k scratch panels
+void cholqr_r(Ctx& ctx, bool cplx, const double* Y, double* S1, double* S2, int64_t n, int64_t k,
+              int batch, const OrthWork& w);
 
 int64_t sketch_width(int64_t m, int64_t p, int64_t rows, int64_t cols);
 
@@ -87,6 +93,23 @@ struct CarryLayout {
 };
 void form_carry(Ctx& ctx, bool cplx, const CarryDims& cd, const CarryLayout& cl, const void* L,
                 const void* T, const void* Bra, void* V, int batch);
+
+// Adjoint of zip_esvd (FP64 / complex128 sketch): cotangents of U, sigma
+// (NULL = 0) and R, stored with the placement of `out`, are turned into the
+// gradients of V, S, T, Bra (layouts of L), ACCUMULATED into gV, gS, gT, gBra
+// (gT and gBra may alias).  CARRY treats s_1 as a constant (the carry scale
+// only moves the logarithmic accumulator).  broadening: Lorentzian width of
+// the 1 / (s_j^2 - s_i^2) terms, relative to s_1^4.
+void zip_esvd_backward(Ctx& ctx, bool cplx, const ZipDims& z, const ZipLayout& L,
+                       const ZipOperands& op, int batch, const hpeps_esvd_opts& o,
+                       hpeps_absorb absorb, double broadening, const ZipOut& out, const void* dU,
+                       const double* dsigma, const void* dR, void* gV, void* gS, void* gT,
+                       void* gBra);
+// Adjoint of form_carry: cotangent gV (row-major V) accumulated into gL, gT,
+// gBra (gT and gBra may alias).
+void carry_backward(Ctx& ctx, bool cplx, const CarryDims& cd, const CarryLayout& cl, const void* Lm,
+                    const void* T, const void* Bra, const void* gV, void* gL, void* gT, void* gBra,
+                    int batch);
 
 // workspace scope: everything allocated after mark() is reused after release
 struct WsScope {

@@ -13,6 +13,7 @@
 #include <cmath>
 
 #include "esvd.h"
+#include "tape.h"
 
 namespace hp {
 
@@ -58,7 +59,9 @@ CarryLayout CarryLayout::row_major(const CarryDims& c) {
 }
 
 WsScope::WsScope(Ctx& ctx) : c(ctx), chunk(ctx.ws_chunk()), off(ctx.ws_offset()) {}
-WsScope::~WsScope() { c.ws_restore(chunk, off); }
+WsScope::~WsScope() {
+  if (!tape_keeps_workspace(c)) c.ws_restore(chunk, off);
+}
 
 // ---------------------------------------------------------------------------
 // operator applications
@@ -135,7 +138,7 @@ void zip_apply(Ctx& ctx, Prec prec, const ZipDims& z, const ZipLayout& L, const 
       call(D, op.S, L.nS, false, w.W2, nW2, false, w.W3, nW3, false);
     }
     // s4: Y[a,x,X | j] = sum_{b,h,H} V[a,x,X,b,h,H] W3[b,h,H,j]
-    {
+    if (Y) {
       GemmDesc D;
       D.M = rows; D.K = b * h * h; D.N = k;
       D.Am.add(a, sV[0]).add(x, sV[1]).add(x, sV[2]);
@@ -185,7 +188,7 @@ void zip_apply(Ctx& ctx, Prec prec, const ZipDims& z, const ZipLayout& L, const 
       call(D, op.Bra, L.nB, false, w.W2, nW2, false, w.W1, nW1, false);
     }
     // t1: Z[y,g | Y,c,G,j] = sum_{u,h,p} conj(T[u,y,h,g,p]) W1[Y,G,p,u,h,c,j]
-    {
+    if (Y) {
       const int64_t zj = 1, zG = k, zg = g * k, zc = g * zg, zY = c * zc, zy = y * zY;
       GemmDesc D;
       D.M = y * g; D.K = u * h * d; D.N = y * c * g * k;
@@ -223,23 +226,55 @@ static void apply_rinv(Ctx& ctx, bool cplx, const double* Y, int64_t n, int64_t 
   gemm(ctx, cplx ? Prec::C128 : Prec::F64, D, c);
 }
 
-// Orthonormal basis of range(Y): result in P; Y is overwritten.
+// Rt <- Rt * Rinv (k x k, upper triangular, per instance); the product is
+// formed in the scratch S and copied back
+static void chain_rinv(Ctx& ctx, bool cplx, double* Rt, const double* Rinv, double* S, int64_t k,
+                       int batch) {
+  GemmDesc D;
+  D.M = k; D.K = k; D.N = k;
+  D.Am.add(k, k);
+  D.Ak.add(k, 1);
+  D.Bk.add(k, k);
+  D.Bn.add(k, 1);
+  D.Cm.add(k, k);
+  D.Cn.add(k, 1);
+  GemmCall c;
+  c.A = Rt;
+  c.B = Rinv;
+  c.C = S;
+  c.sA = c.sB = c.sC = k * k;
+  c.batch = batch;
+  gemm(ctx, cplx ? Prec::C128 : Prec::F64, D, c);
+  HP_CHECK_HIP(hipMemcpyAsync(Rt, S, (size_t)batch * k * k * (cplx ? 16 : 8), hipMemcpyDeviceToDevice,
+                              ctx.stream));
+}
+
+// Orthonormal basis of range(Y): result in P; Y is overwritten.  Rt_inv
+// (optional, k x k per instance) receives the inverse of the total factor R
+// with Y = P R (the product of the passes' inverses).
 void orthogonalize(Ctx& ctx, bool cplx, double* Y, double* P, int64_t n, int64_t k, int batch,
-                   const OrthWork& w) {
+                   const OrthWork& w, double* Rt_inv) {
+  WsScope scope(ctx);
+  double* S = Rt_inv ? ctx.ws<double>((int64_t)batch * k * k * (cplx ? 2 : 1)) : nullptr;
   gram(ctx, cplx, Y, n, k, batch, w.G, nullptr);
   chol_inv(ctx, cplx, w.G, n, k, batch, 1, w.Rinv, nullptr, w.flags);
   apply_rinv(ctx, cplx, Y, n, k, batch, w.Rinv, P, nullptr);
+  if (Rt_inv)
+    HP_CHECK_HIP(hipMemcpyAsync(Rt_inv, w.Rinv, (size_t)batch * k * k * (cplx ? 16 : 8),
+                                hipMemcpyDeviceToDevice, ctx.stream));
   gram(ctx, cplx, P, n, k, batch, w.G, nullptr);
   chol_inv(ctx, cplx, w.G, n, k, batch, 2, w.Rinv, nullptr, w.flags);
   apply_rinv(ctx, cplx, P, n, k, batch, w.Rinv, Y, nullptr);
+  if (Rt_inv) chain_rinv(ctx, cplx, Rt_inv, w.Rinv, S, k, batch);
   gram(ctx, cplx, Y, n, k, batch, w.G, nullptr);
   chol_inv(ctx, cplx, w.G, n, k, batch, 3, w.Rinv, nullptr, w.flags);
   apply_rinv(ctx, cplx, Y, n, k, batch, w.Rinv, P, w.flags);
+  if (Rt_inv) chain_rinv(ctx, cplx, Rt_inv, w.Rinv, S, k, batch);
   stats_reduce(ctx, w.flags, nullptr, batch, ctx.stats_dev);
 }
 
 // R factor of the CholeskyQR of Y (accumulated over the passes) into Racc.
-static void cholqr_r(Ctx& ctx, bool cplx, const double* Y, double* S1, double* S2, int64_t n,
+void cholqr_r(Ctx& ctx, bool cplx, const double* Y, double* S1, double* S2, int64_t n,
                      int64_t k, int batch, const OrthWork& w) {
   gram(ctx, cplx, Y, n, k, batch, w.G, nullptr);
   chol_inv(ctx, cplx, w.G, n, k, batch, 1, w.Rinv, w.Racc, w.flags);
@@ -261,6 +296,11 @@ int64_t sketch_width(int64_t m, int64_t p, int64_t rows, int64_t cols) {
 void zip_esvd(Ctx& ctx, bool cplx, const ZipDims& z, const ZipLayout& L, const ZipOperands& op64,
               int batch, const hpeps_esvd_opts& o, hpeps_absorb absorb, const ZipOut& out,
               void* U, double* sigma, void* R, double* log_scale) {
+  if (taping(ctx)) {
+    HP_REQUIRE(!sigma, HPEPS_ERR_UNSUPPORTED, "tape: singular values are not a differentiable output");
+    tape_zip(ctx, cplx, z, L, op64, batch, o, absorb, out, U, R);
+  }
+  TapeSuspend unrecorded(ctx);
   WsScope scope(ctx);
   const int64_t rows = z.rows(), cols = z.cols();
   const int64_t k = sketch_width(o.rank, o.oversample, rows, cols);
@@ -452,6 +492,8 @@ void zip_esvd(Ctx& ctx, bool cplx, const ZipDims& z, const ZipLayout& L, const Z
 // exact carry of one column: V[a,x,X,b,h,H] = sum_{u,U,p} L[a,u,U,b] T[u,x,h,p] conj(Bra[U,X,H,p])
 void form_carry(Ctx& ctx, bool cplx, const CarryDims& cd, const CarryLayout& cl, const void* L,
                 const void* T, const void* Bra, void* V, int batch) {
+  tape_carry(ctx, cplx, cd, cl, L, T, Bra, V, batch);
+  TapeSuspend unrecorded(ctx);
   WsScope scope(ctx);
   const int64_t a = cd.a, u = cd.u, b = cd.b, x = cd.x, h = cd.h, d = cd.d;
   const Prec p = cplx ? Prec::C128 : Prec::F64;

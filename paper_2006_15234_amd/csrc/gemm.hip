@@ -926,6 +926,7 @@ void gemm(Ctx& ctx, Prec prec, const GemmDesc& d, const GemmCall& c) {
   HP_REQUIRE(nC > 0 && maxoff(d.Cm, d.Cn) < nC, HPEPS_ERR_SHAPE, "gemm C access out of bounds");
   if (c.copy_if_zero) HP_REQUIRE(d.K == d.N, HPEPS_ERR_SHAPE, "pass-through gemm needs K == N");
   HP_REQUIRE(c.batch >= 1, HPEPS_ERR_INVALID_ARG, "gemm batch must be >= 1");
+  tape_gemm(ctx, prec, d, c);
   const bool cplx = prec == Prec::C128;
   GemmArgs a{};
   a.A = c.A;

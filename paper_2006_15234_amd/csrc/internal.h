@@ -99,6 +99,7 @@ struct GemmVariant {
 };
 
 class Ctx;
+class Tape;
 void gemm(Ctx& ctx, Prec prec, const GemmDesc& d, const GemmCall& c);
 // JSON text of the tuned variants of a context / merge such a text into it
 std::string autotune_export(const Ctx& ctx);
@@ -136,7 +137,8 @@ void fill_zero(Ctx& ctx, void* p, int64_t bytes);
 void fill_value(Ctx& ctx, double* p, int64_t n, double v, bool cplx);
 // Canonical phase of singular pairs: U (row-major rows x mp per instance) is
 // the left factor P Z; column i of Z (k x k) is rotated so that the
-// largest-magnitude entry of U[:, i] (first on ties) becomes real positive.
+// projection of U[:, i] on a fixed counter-generated vector becomes real
+// positive.
 void gauge_fix(Ctx& ctx, bool cplx, const double* U, int64_t rows, int64_t mp, double* Z, int64_t k,
                int batch);
 // dst[0..1] = src as a complex number (imaginary part 0 for real src)
@@ -144,9 +146,37 @@ void copy_scalar(Ctx& ctx, const double* src, bool cplx, double* dst);
 // Frobenius norm of x (n doubles, or n complex if cplx) per batch (batch
 // stride n elements); x is divided by the norm and log_scale[b] += log(norm).
 void normalize(Ctx& ctx, bool cplx, void* x, int64_t n, int batch, double* log_scale);
+// x[b][0..nd) *= s[b] (nd doubles per instance)
+void scale_by(Ctx& ctx, double* x, int64_t nd, const double* s, int batch);
+// hooks of the reverse-mode tape (no-ops unless a tape records)
+void tape_gemm(Ctx& ctx, Prec prec, const GemmDesc& d, const GemmCall& c);
+void tape_scale(Ctx& ctx, bool cplx, double* x, int64_t n, const double* s, int batch);
+void tape_copy(Ctx& ctx, bool cplx, void* dst, const void* src, int64_t n);
+bool tape_keeps_workspace(const Ctx& ctx);
 // diag(out)[..] helpers for tests of the gemm itself are not exported.
 void copy_sigma(Ctx& ctx, const double* sigma_k, int64_t k, int64_t mp, int batch, double* out);
 void stats_reduce(Ctx& ctx, const int* flags, const int* sweeps, int batch, int* acc);
+// einsumsvd adjoint helpers (k x k / panel elementwise work, one workgroup per instance)
+void svd_bwd_core(Ctx& ctx, bool cplx, const double* ZZ, const double* VV, const double* s,
+                  const double* sbar, int64_t k, int batch, double eps, double* G1H);
+void copyltu_neg(Ctx& ctx, bool cplx, double* M, int64_t k, int batch);
+void axpy(Ctx& ctx, double* y, const double* x, double alpha, int64_t n);
+void axpy_colscale(Ctx& ctx, bool cplx, double* Y, const double* X, const double* d, int64_t rows,
+                   int64_t k, int batch);
+// Vbar[c, i] = conj(dR[i, c]) s_i rscale (s, rscale nullable = 1), zero for i >= mp
+void vbar_from_dr(Ctx& ctx, bool cplx, const double* dR, const double* s, const double* rscale,
+                  int64_t cols, int64_t mp, int64_t k, int batch, double* Vbar);
+// sbar_i = dsigma_i + (right ? rscale Re sum_c dR[i, c] V[c, i] : 0), zero for i >= mp
+void sigma_bar(Ctx& ctx, bool cplx, const double* dsigma, const double* dR, const double* V,
+               const double* rscale, int64_t cols, int64_t mp, int64_t k, int batch, bool right,
+               double* sbar);
+// cotangent of U through the canonical phase choice (complex; see the kernel)
+void gauge_backward(Ctx& ctx, double* dU, const double* U, const double* dR, const double* V,
+                    const double* s, const double* rscale, int64_t rows, int64_t cols, int64_t mp,
+                    int64_t k, int batch);
+// dst[b] (row-major rows.size() x cols.size()) = src[b * sSrc + rows(r) + cols(c)]
+void gather2d(Ctx& ctx, bool cplx, const void* src, int64_t sSrc, const IndexMap& rows,
+              const IndexMap& cols, void* dst, int batch);
 
 // ---------------------------------------------------------------------------
 // context: stream, workspace arena, cached index tables, diagnostics
@@ -204,6 +234,11 @@ class Ctx {
   GemmVariant gemm_force;
   bool autotune = false;
   std::map<std::string, GemmVariant> gemm_tuned;
+
+  // reverse-mode recording (set only inside a backward ABI call): while a
+  // tape records, products, in-place rescalings, exact carries, einsumsvds
+  // and copies are logged, and workspace scopes do not release memory
+  Tape* tape = nullptr;
 
  private:
   struct ProfRec {

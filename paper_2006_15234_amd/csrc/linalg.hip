@@ -447,6 +447,222 @@ __global__ __launch_bounds__(kJacMaxThreads) void jacobi_kernel(const double* Ra
   }
 }
 
+// ---------------------------------------------------------------------------
+// Small kernels of the einsumsvd adjoint (one workgroup per instance)
+
+// G1^H for the truncated-SVD backward of M = Z Sigma V^H (k x k per instance):
+//   C = (F o (ZZ - ZZ^H)) S + S (F o (VV - VV^H)) + diag(sbar + i Im(ZZ_ii) / s_i)
+//   G1 = C - S^-1 VV^H,   F_ij = d / (d^2 + eps s_1^4), d = s_j^2 - s_i^2
+// (F_ij = 0 where d = 0, and on the diagonal) with ZZ = Z^H Zbar, VV = V^H Vbar:
+// eps is a width relative to the largest singular value (scale invariant).
+template <bool CPLX>
+__global__ void svd_bwd_core_kernel(const double* ZZall, const double* VVall, const double* sall,
+                                    const double* sball, int k, double eps, double* G1Hall) {
+  using T = typename S<CPLX>::T;
+  const int b = blockIdx.x;
+  const long long kk = (long long)k * k;
+  const T* ZZ = reinterpret_cast<const T*>(ZZall) + b * kk;
+  const T* VV = reinterpret_cast<const T*>(VVall) + b * kk;
+  const double* s = sall + (long long)b * k;
+  const double* sb = sball + (long long)b * k;
+  T* G1H = reinterpret_cast<T*>(G1Hall) + b * kk;
+  const double w = eps * (s[0] * s[0]) * (s[0] * s[0]);
+  for (long long e = threadIdx.x; e < kk; e += blockDim.x) {
+    const int i = (int)(e / k), j = (int)(e % k);
+    const double dd = s[j] * s[j] - s[i] * s[i];
+    const double F = (i == j || dd == 0.0) ? 0.0 : dd / (dd * dd + w);
+    const double inv_si = s[i] > 0 ? 1.0 / s[i] : 0.0;
+    T c = S<CPLX>::add(S<CPLX>::scale(S<CPLX>::sub(ZZ[e], S<CPLX>::conj(ZZ[(long long)j * k + i])), F * s[j]),
+                       S<CPLX>::scale(S<CPLX>::sub(VV[e], S<CPLX>::conj(VV[(long long)j * k + i])), F * s[i]));
+    if (i == j) {
+      if constexpr (CPLX) {
+        c.re += sb[i];
+        c.im += ZZ[e].im * inv_si;
+      } else {
+        c += sb[i];
+      }
+    }
+    const T g = S<CPLX>::sub(c, S<CPLX>::scale(S<CPLX>::conj(VV[(long long)j * k + i]), inv_si));
+    G1H[(long long)j * k + i] = S<CPLX>::conj(g);
+  }
+}
+
+// M <- tril(-M, -1) + tril(-M, -1)^H - Re diag(M) (in place; the strict upper
+// part is overwritten).  The real diagonal is the QR backward's for R with a
+// real positive diagonal: Q^H dQ then has an imaginary diagonal that the
+// loss only sees through phases, which the R gauge fixes.
+template <bool CPLX>
+__global__ void copyltu_neg_kernel(double* Mall, int k) {
+  using T = typename S<CPLX>::T;
+  T* M = reinterpret_cast<T*>(Mall) + (long long)blockIdx.x * k * k;
+  for (long long e = threadIdx.x; e < (long long)k * k; e += blockDim.x) {
+    const int i = (int)(e / k), j = (int)(e % k);
+    if (j > i) continue;
+    T v = S<CPLX>::sub(S<CPLX>::zero(), M[e]);
+    if constexpr (CPLX) {
+      if (i == j) v.im = 0.0;
+    }
+    M[e] = v;
+    if (j < i) M[(long long)j * k + i] = S<CPLX>::conj(v);
+  }
+}
+
+// y += alpha x over n doubles
+__global__ void axpy_kernel(double* y, const double* x, double alpha, long long n) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    y[i] += alpha * x[i];
+}
+
+// Y[r, i] += X[r, i] * d[i] (rows x k per instance, d: k per instance)
+template <bool CPLX>
+__global__ void axpy_colscale_kernel(double* Yall, const double* Xall, const double* dall, long long rows, int k) {
+  using T = typename S<CPLX>::T;
+  const int b = blockIdx.y;
+  T* Y = reinterpret_cast<T*>(Yall) + b * rows * k;
+  const T* X = reinterpret_cast<const T*>(Xall) + b * rows * k;
+  const double* d = dall + (long long)b * k;
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < rows * k; e += (long long)gridDim.x * blockDim.x)
+    Y[e] = S<CPLX>::add(Y[e], S<CPLX>::scale(X[e], d[e % k]));
+}
+
+// Vbar[c, i] = conj(dR[i, c]) * (s ? s[i] : 1) * (rs ? rs[b] : 1) for i < mp,
+// 0 for mp <= i < k
+template <bool CPLX>
+__global__ void vbar_kernel(const double* dRall, const double* sall, const double* rs, long long cols, int mp,
+                            int k, double* Vall) {
+  using T = typename S<CPLX>::T;
+  const int b = blockIdx.y;
+  const T* dR = reinterpret_cast<const T*>(dRall) + b * (long long)mp * cols;
+  T* Vb = reinterpret_cast<T*>(Vall) + b * cols * k;
+  const double f = rs ? rs[b] : 1.0;
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < cols * k; e += (long long)gridDim.x * blockDim.x) {
+    const long long c = e / k;
+    const int i = (int)(e % k);
+    T v = S<CPLX>::zero();
+    if (i < mp)
+      v = S<CPLX>::scale(S<CPLX>::conj(dR[(long long)i * cols + c]), (sall ? sall[(long long)b * k + i] : 1.0) * f);
+    Vb[e] = v;
+  }
+}
+
+// sbar[i] = dsigma[i] (+ rs Re sum_c dR[i, c] V[c, i] when right) for i < mp, 0 beyond
+template <bool CPLX>
+__global__ void sbar_kernel(const double* dsall, const double* dRall, const double* Vall, const double* rs,
+                            long long cols, int mp, int k, int right, double* sball) {
+  using T = typename S<CPLX>::T;
+  __shared__ double red[4];
+  const int b = blockIdx.x, tid = threadIdx.x;
+  const T* dR = reinterpret_cast<const T*>(dRall) + b * (long long)mp * cols;
+  const T* V = reinterpret_cast<const T*>(Vall) + b * cols * k;
+  const double f = rs ? rs[b] : 1.0;
+  for (int i = 0; i < k; ++i) {
+    double acc = 0.0;
+    if (right && i < mp)
+      for (long long c = tid; c < cols; c += blockDim.x) acc += S<CPLX>::re(S<CPLX>::mul(dR[(long long)i * cols + c], V[c * k + i]));
+    acc = wave_sum(acc);
+    if ((tid & 63) == 0) red[tid >> 6] = acc;
+    __syncthreads();
+    if (tid == 0) {
+      double t = 0.0;
+      for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += red[w];
+      sball[(long long)b * k + i] = i < mp ? (dsall ? dsall[(long long)b * mp + i] : 0.0) + f * t : 0.0;
+    }
+    __syncthreads();
+  }
+}
+
+// Derivative of the canonical phase choice (complex only).  For each kept
+// pair i the output U[:, i] = U0[:, i] e^{-i th} and R[i, :] = e^{i th} R0[i, :]
+// with th = arg(w . U0[:, i]); at the fixed point z = w . U[:, i] is real
+// positive.  The loss sees th through
+//   thbar = Im <dU_i, U_i> - Im <dR_i, R_i>,   R[i, c] = sc_i conj(V[c, i]),
+// and th through z: dU[:, i] += w * (i thbar / z).  sc_i = (s ? s_i : 1) * (rs ? rs : 1).
+// dU, U: rows x mp; dR: mp x cols; V: cols x k (row-major per instance).
+__global__ __launch_bounds__(256) void gauge_bwd_kernel(double* dUall, const double* Uall, const double* dRall,
+                                                        const double* Vall, const double* sall, const double* rs,
+                                                        long long rows, long long cols, int mp, int k) {
+  using T = S<true>::T;
+  const int b = blockIdx.x, tid = threadIdx.x;
+  T* dU = reinterpret_cast<T*>(dUall) + (long long)b * rows * mp;
+  const T* U = reinterpret_cast<const T*>(Uall) + (long long)b * rows * mp;
+  const T* dR = reinterpret_cast<const T*>(dRall) + (long long)b * mp * cols;
+  const T* V = reinterpret_cast<const T*>(Vall) + (long long)b * cols * k;
+  __shared__ double r0[256], r1[256], r2[256];
+  __shared__ double coef;
+  const uint64_t base = mix64(mix64(0ull) + 0ull);
+  const double f = rs ? rs[b] : 1.0;
+  for (int i = 0; i < mp; ++i) {
+    double a = 0.0, zr = 0.0, bb = 0.0;
+    for (long long r = tid; r < rows; r += blockDim.x) {
+      const uint64_t h = mix64(base + (uint64_t)(r + 1) * 0x9E3779B97F4A7C15ull);
+      const double w = 2.0 * (double)(h >> 11) * 0x1p-53 - 1.0;
+      const T u = U[r * mp + i], du = dU[r * mp + i];
+      a += du.re * u.im - du.im * u.re;  // Im(conj(du) u)
+      zr += w * u.re;
+    }
+    for (long long c = tid; c < cols; c += blockDim.x) {
+      const T x = S<true>::mul(dR[(long long)i * cols + c], V[c * k + i]);
+      bb += x.im;
+    }
+    r0[tid] = a;
+    r1[tid] = zr;
+    r2[tid] = bb;
+    __syncthreads();
+    for (int st = blockDim.x / 2; st > 0; st >>= 1) {
+      if (tid < st) {
+        r0[tid] += r0[tid + st];
+        r1[tid] += r1[tid + st];
+        r2[tid] += r2[tid + st];
+      }
+      __syncthreads();
+    }
+    if (tid == 0) {
+      const double sc = (sall ? sall[(long long)b * k + i] : 1.0) * f;
+      // Im <dR_i, R_i> = Im sum conj(dR) sc conj(V) = -sc Im sum dR V
+      const double thbar = r0[0] + sc * r2[0];
+      coef = r1[0] > 0.0 ? thbar / r1[0] : 0.0;
+    }
+    __syncthreads();
+    const double cf = coef;
+    for (long long r = tid; r < rows; r += blockDim.x) {
+      const uint64_t h = mix64(base + (uint64_t)(r + 1) * 0x9E3779B97F4A7C15ull);
+      const double w = 2.0 * (double)(h >> 11) * 0x1p-53 - 1.0;
+      dU[r * mp + i].im += w * cf;
+    }
+    __syncthreads();
+  }
+}
+
+// dst[b][r * ncols + c] = src[b * sSrc + rowmap(r) + colmap(c)] (row-major
+// mode nesting in both maps: the last mode varies fastest)
+struct Map2D {
+  int nr = 0, nc = 0;
+  long long rd[kMaxModes], rst[kMaxModes], cd[kMaxModes], cst[kMaxModes];
+};
+
+__device__ inline long long map_offset(long long idx, int n, const long long* dims, const long long* str) {
+  long long off = 0;
+  for (int t = n - 1; t >= 0; --t) {
+    const long long q = idx / dims[t];
+    off += (idx - q * dims[t]) * str[t];
+    idx = q;
+  }
+  return off;
+}
+
+template <bool CPLX>
+__global__ void gather2d_kernel(const double* srcall, long long sSrc, Map2D m, long long rows, long long cols,
+                                double* dstall) {
+  using T = typename S<CPLX>::T;
+  const int b = blockIdx.y;
+  const T* src = reinterpret_cast<const T*>(srcall) + b * sSrc;
+  T* dst = reinterpret_cast<T*>(dstall) + b * rows * cols;
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < rows * cols; e += (long long)gridDim.x * blockDim.x) {
+    const long long r = e / cols, c = e - r * cols;
+    dst[e] = src[map_offset(r, m.nr, m.rd, m.rst) + map_offset(c, m.nc, m.cd, m.cst)];
+  }
+}
+
 __global__ void f64_to_bf16_kernel(const double* in, __bf16* out, long long n) {
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
     out[i] = (__bf16)in[i];
@@ -722,6 +938,93 @@ void jacobi_svd(Ctx& ctx, bool cplx, const double* Racc, int64_t k, int batch, i
   HP_CHECK_HIP(hipGetLastError());
 }
 
+void svd_bwd_core(Ctx& ctx, bool cplx, const double* ZZ, const double* VV, const double* s,
+                  const double* sbar, int64_t k, int batch, double eps, double* G1H) {
+  if (cplx)
+    svd_bwd_core_kernel<true><<<batch, 256, 0, ctx.stream>>>(ZZ, VV, s, sbar, (int)k, eps, G1H);
+  else
+    svd_bwd_core_kernel<false><<<batch, 256, 0, ctx.stream>>>(ZZ, VV, s, sbar, (int)k, eps, G1H);
+  HP_CHECK_HIP(hipGetLastError());
+}
+
+void copyltu_neg(Ctx& ctx, bool cplx, double* M, int64_t k, int batch) {
+  if (cplx)
+    copyltu_neg_kernel<true><<<batch, 256, 0, ctx.stream>>>(M, (int)k);
+  else
+    copyltu_neg_kernel<false><<<batch, 256, 0, ctx.stream>>>(M, (int)k);
+  HP_CHECK_HIP(hipGetLastError());
+}
+
+void axpy(Ctx& ctx, double* y, const double* x, double alpha, int64_t n) {
+  if (n <= 0) return;
+  axpy_kernel<<<std::min<unsigned>(cdiv(n, 256), 4096), 256, 0, ctx.stream>>>(y, x, alpha, n);
+  HP_CHECK_HIP(hipGetLastError());
+}
+
+void axpy_colscale(Ctx& ctx, bool cplx, double* Y, const double* X, const double* d, int64_t rows,
+                   int64_t k, int batch) {
+  dim3 grid(std::min<unsigned>(cdiv(rows * k, 256), 1024), batch);
+  if (cplx)
+    axpy_colscale_kernel<true><<<grid, 256, 0, ctx.stream>>>(Y, X, d, rows, (int)k);
+  else
+    axpy_colscale_kernel<false><<<grid, 256, 0, ctx.stream>>>(Y, X, d, rows, (int)k);
+  HP_CHECK_HIP(hipGetLastError());
+}
+
+void vbar_from_dr(Ctx& ctx, bool cplx, const double* dR, const double* s, const double* rscale,
+                  int64_t cols, int64_t mp, int64_t k, int batch, double* Vbar) {
+  dim3 grid(std::min<unsigned>(cdiv(cols * k, 256), 1024), batch);
+  if (cplx)
+    vbar_kernel<true><<<grid, 256, 0, ctx.stream>>>(dR, s, rscale, cols, (int)mp, (int)k, Vbar);
+  else
+    vbar_kernel<false><<<grid, 256, 0, ctx.stream>>>(dR, s, rscale, cols, (int)mp, (int)k, Vbar);
+  HP_CHECK_HIP(hipGetLastError());
+}
+
+void sigma_bar(Ctx& ctx, bool cplx, const double* dsigma, const double* dR, const double* V,
+               const double* rscale, int64_t cols, int64_t mp, int64_t k, int batch, bool right,
+               double* sbar) {
+  if (cplx)
+    sbar_kernel<true><<<batch, 256, 0, ctx.stream>>>(dsigma, dR, V, rscale, cols, (int)mp, (int)k, right, sbar);
+  else
+    sbar_kernel<false><<<batch, 256, 0, ctx.stream>>>(dsigma, dR, V, rscale, cols, (int)mp, (int)k, right, sbar);
+  HP_CHECK_HIP(hipGetLastError());
+}
+
+void gauge_backward(Ctx& ctx, double* dU, const double* U, const double* dR, const double* V,
+                    const double* s, const double* rscale, int64_t rows, int64_t cols, int64_t mp,
+                    int64_t k, int batch) {
+  gauge_bwd_kernel<<<batch, 256, 0, ctx.stream>>>(dU, U, dR, V, s, rscale, rows, cols, (int)mp, (int)k);
+  HP_CHECK_HIP(hipGetLastError());
+}
+
+void gather2d(Ctx& ctx, bool cplx, const void* src, int64_t sSrc, const IndexMap& rows,
+              const IndexMap& cols, void* dst, int batch) {
+  Map2D m;
+  m.nr = rows.n;
+  m.nc = cols.n;
+  for (int t = 0; t < rows.n; ++t) {
+    m.rd[t] = rows.dim[t];
+    m.rst[t] = rows.stride[t];
+  }
+  for (int t = 0; t < cols.n; ++t) {
+    m.cd[t] = cols.dim[t];
+    m.cst[t] = cols.stride[t];
+  }
+  const int64_t nr = rows.size(), nc = cols.size();
+  if (nr * nc == 0) return;
+  int64_t maxoff = 0;
+  for (int t = 0; t < rows.n; ++t) maxoff += (rows.dim[t] - 1) * rows.stride[t];
+  for (int t = 0; t < cols.n; ++t) maxoff += (cols.dim[t] - 1) * cols.stride[t];
+  HP_REQUIRE(maxoff < sSrc, HPEPS_ERR_SHAPE, "gather out of bounds");
+  dim3 grid(std::min<unsigned>(cdiv(nr * nc, 256), 1024), batch);
+  if (cplx)
+    gather2d_kernel<true><<<grid, 256, 0, ctx.stream>>>((const double*)src, sSrc, m, nr, nc, (double*)dst);
+  else
+    gather2d_kernel<false><<<grid, 256, 0, ctx.stream>>>((const double*)src, sSrc, m, nr, nc, (double*)dst);
+  HP_CHECK_HIP(hipGetLastError());
+}
+
 void convert_f64_to_bf16(Ctx& ctx, const double* in, void* out, int64_t n) {
   if (n <= 0) return;
   f64_to_bf16_kernel<<<std::min<unsigned>(cdiv(n, 256), 4096), 256, 0, ctx.stream>>>(
@@ -771,6 +1074,13 @@ void normalize(Ctx& ctx, bool cplx, void* x, int64_t n, int batch, double* log_s
   sumsq_partial_kernel<<<dim3(nparts, batch), 256, 0, ctx.stream>>>((const double*)x, nd, mx, part);
   norm_finalize_kernel<<<batch, 64, 0, ctx.stream>>>(part, nparts, mx, inv, log_scale);
   scale_kernel<<<dim3(std::min<unsigned>(cdiv(nd, 256), 1024), batch), 256, 0, ctx.stream>>>((double*)x, nd, inv);
+  HP_CHECK_HIP(hipGetLastError());
+  tape_scale(ctx, cplx, (double*)x, n, inv, batch);
+}
+
+void scale_by(Ctx& ctx, double* x, int64_t nd, const double* s, int batch) {
+  if (nd <= 0) return;
+  scale_kernel<<<dim3(std::min<unsigned>(cdiv(nd, 256), 1024), batch), 256, 0, ctx.stream>>>(x, nd, s);
   HP_CHECK_HIP(hipGetLastError());
 }
 

@@ -64,7 +64,7 @@ void absorb_row(Ctx& ctx, bool cplx, const std::vector<BndView>& bnd,
 // result_dev (2 doubles) and adds the logs to log_dev.
 void contract_last_row(Ctx& ctx, bool cplx, const std::vector<BndView>& bnd,
                        const std::vector<SiteView>& ket, const std::vector<SiteView>& bra,
-                       double* result_dev, double* log_dev);
+                       double* result_dev, double* log_dev, double** final_E = nullptr);
 
 // Host view of an ABI PEPS.
 struct Lattice {
@@ -75,6 +75,9 @@ struct Lattice {
 };
 Lattice lattice_from_abi(const hpeps_peps* p);
 
+// Copies the accumulated gradient of every site of K (zero where none
+// flowed) into the caller's per-site buffers.
+void write_site_grads(Ctx& ctx, const Tape& tape, const Lattice& K, void* const* grads);
 // Copies every site into the workspace divided by its Frobenius norm; the
 // logarithms of the norms are added to log_dev.
 Lattice normalized_copy(Ctx& ctx, const Lattice& L, double* log_dev);

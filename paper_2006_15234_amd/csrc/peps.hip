@@ -17,6 +17,7 @@
 #include <cstring>
 
 #include "peps.h"
+#include "tape.h"
 
 namespace hp {
 
@@ -171,6 +172,7 @@ void absorb_row(Ctx& ctx, bool cplx, const std::vector<BndView>& bnd,
       out[0].dims = {cd.a, cd.x, cd.x, cd.b * cd.h * cd.h};
       HP_CHECK_HIP(hipMemcpyAsync(out[0].p, carry[0], nv * es * sizeof(double), hipMemcpyDeviceToDevice,
                                   ctx.stream));
+      tape_copy(ctx, cplx, out[0].p, carry[0], nv);
       return;
     }
   }
@@ -228,6 +230,8 @@ void absorb_row(Ctx& ctx, bool cplx, const std::vector<BndView>& bnd,
     }
     hpeps_esvd_opts oj = o;
     oj.stream_id = stream_ids[j];
+    // a recording tape needs every carry kept: no ping-pong reuse
+    if (taping(ctx) && j + 1 < n) Rp = carry[1 - cur] = ctx.ws<double>(maxv * es);
     ZipOperands op{carry[cur], bnd[j].p, ket[j].p, bra[j].p};
     zip_esvd(ctx, cplx, z, L, op, 1, oj, HPEPS_ABSORB_CARRY, zo, U.p, nullptr, Rp, log_dev);
     cur = 1 - cur;
@@ -240,7 +244,7 @@ void absorb_row(Ctx& ctx, bool cplx, const std::vector<BndView>& bnd,
 
 void contract_last_row(Ctx& ctx, bool cplx, const std::vector<BndView>& bnd,
                        const std::vector<SiteView>& ket, const std::vector<SiteView>& bra,
-                       double* result_dev, double* log_dev) {
+                       double* result_dev, double* log_dev, double** final_E) {
   const Prec pr = cplx ? Prec::C128 : Prec::F64;
   const int es = cplx ? 2 : 1;
   const size_t n = ket.size();
@@ -261,6 +265,11 @@ void contract_last_row(Ctx& ctx, bool cplx, const std::vector<BndView>& bnd,
   fill_value(ctx, E[0], 1, 1.0, cplx);
   int cur = 0;
   for (size_t j = 0; j < n; ++j) {
+    if (taping(ctx)) {  // a recording tape keeps every intermediate
+      E[1 - cur] = ctx.ws<double>(maxe * es);
+      X1 = ctx.ws<double>(max1 * es);
+      X2 = ctx.ws<double>(max2 * es);
+    }
     const BndView& S = bnd[j];
     const SiteView &T = ket[j], &B = bra[j];
     const int64_t b = S.n[0], u = S.n[1], U = S.n[2], c = S.n[3];
@@ -318,6 +327,7 @@ void contract_last_row(Ctx& ctx, bool cplx, const std::vector<BndView>& bnd,
   // the last E is a single element; normalize divided it by |E|, so recover
   // the mantissa as phase only: result = E (unit modulus) and log holds |E|
   copy_scalar(ctx, E[cur], cplx, result_dev);
+  if (final_E) *final_E = E[cur];
 }
 
 Lattice lattice_from_abi(const hpeps_peps* p) {
@@ -353,12 +363,25 @@ Lattice lattice_from_abi(const hpeps_peps* p) {
   return L;
 }
 
+void write_site_grads(Ctx& ctx, const Tape& tape, const Lattice& K, void* const* grads) {
+  const int es = K.cplx ? 2 : 1;
+  for (size_t q = 0; q < K.sites.size(); ++q) {
+    const int64_t bytes = K.sites[q].size() * es * (int64_t)sizeof(double);
+    const double* g = tape.grad_if_live(K.sites[q].p);
+    if (g)
+      HP_CHECK_HIP(hipMemcpyAsync(grads[q], g, bytes, hipMemcpyDeviceToDevice, ctx.stream));
+    else
+      fill_zero(ctx, grads[q], bytes);
+  }
+}
+
 Lattice normalized_copy(Ctx& ctx, const Lattice& L, double* log_dev) {
   Lattice out = L;
   const int es = L.cplx ? 2 : 1;
   for (auto& t : out.sites) {
     double* p = ctx.ws<double>(t.size() * es);
     HP_CHECK_HIP(hipMemcpyAsync(p, t.p, t.size() * es * sizeof(double), hipMemcpyDeviceToDevice, ctx.stream));
+    tape_copy(ctx, L.cplx, p, t.p, t.size());
     normalize(ctx, L.cplx, p, t.size(), 1, log_dev);
     t.p = p;
   }
@@ -426,12 +449,15 @@ hpeps_status guard_p(hpeps_ctx* ctx, F&& f) {
     f(*ctx->impl);
     return HPEPS_OK;
   } catch (const hp::Error& e) {
+    ctx->impl->tape = nullptr;
     ctx->impl->last_error = e.msg;
     return e.code;
   } catch (const std::bad_alloc&) {
+    ctx->impl->tape = nullptr;
     ctx->impl->last_error = "host allocation failed";
     return HPEPS_ERR_ALLOC;
   } catch (...) {
+    ctx->impl->tape = nullptr;
     ctx->impl->last_error = "unknown error";
     return HPEPS_ERR_INVALID_ARG;
   }
@@ -441,6 +467,44 @@ void check_opts_p(const hpeps_esvd_opts* o) {
   HP_REQUIRE(o, HPEPS_ERR_INVALID_ARG, "opts is NULL");
   HP_REQUIRE(o->rank >= 1 && o->oversample >= 0 && o->power_iters >= 0 && o->jacobi_max_sweeps >= 0,
              HPEPS_ERR_INVALID_ARG, "bad einsumsvd options");
+}
+// <bra|ket> by boundary MPS: dev[0] += log scale, dev[1..2] = phase; the
+// final unit-modulus mantissa buffer is returned through final_E.
+void norm_run(hp::Ctx& c, const hp::Lattice& K, const hp::Lattice& B, const hpeps_esvd_opts& o, double* dev,
+              double** final_E) {
+  HP_REQUIRE(B.nrow == K.nrow && B.ncol == K.ncol && B.cplx == K.cplx, HPEPS_ERR_SHAPE,
+             "bra and ket lattices differ");
+  for (size_t q = 0; q < K.sites.size(); ++q)
+    for (int e = 0; e < 5; ++e)
+      HP_REQUIRE(K.sites[q].dims[e] == B.sites[q].dims[e], HPEPS_ERR_SHAPE, "bra and ket shapes differ");
+  hp::fill_value(c, dev, 1, 0.0, false);
+  // the bra layer is rescaled separately even when it is the ket itself:
+  // both layers' norms enter <bra|ket>
+  hp::Lattice Kn = hp::normalized_copy(c, K, dev);
+  hp::Lattice Bn = hp::normalized_copy(c, B, dev);
+  std::vector<hp::BndView> bv;
+  std::vector<hp::SiteView> kv, brv;
+  std::vector<std::vector<hp::DevTensor>> envs;
+  std::vector<hp::DevTensor> triv;
+  if (K.nrow == 1) {
+    const int es = K.cplx ? 2 : 1;
+    for (int j = 0; j < K.ncol; ++j) {
+      hp::DevTensor t;
+      t.dims = {1, 1, 1, 1};
+      t.p = c.ws<double>(es);
+      hp::fill_value(c, (double*)t.p, 1, 1.0, K.cplx);
+      triv.push_back(t);
+    }
+    for (int j = 0; j < K.ncol; ++j) bv.push_back(hp::orient_bnd(triv[j], hp::kL2R));
+  } else {
+    hp::boundary_pass(c, Kn, Bn, hp::kTop, o, K.nrow - 1, envs, dev);
+    for (int j = 0; j < K.ncol; ++j) bv.push_back(hp::orient_bnd(envs.back()[j], hp::kL2R));
+  }
+  for (int j = 0; j < K.ncol; ++j) {
+    kv.push_back(hp::orient_site(Kn.at(K.nrow - 1, j), hp::kTop, hp::kL2R));
+    brv.push_back(hp::orient_site(Bn.at(K.nrow - 1, j), hp::kTop, hp::kL2R));
+  }
+  hp::contract_last_row(c, K.cplx, bv, kv, brv, dev + 1, dev, final_E);
 }
 }  // namespace
 
@@ -508,40 +572,8 @@ hpeps_status hpeps_peps_norm(hpeps_ctx* ctx, const hpeps_peps* ket, const hpeps_
     HP_REQUIRE(log_norm && phase, HPEPS_ERR_INVALID_ARG, "null output");
     hp::Lattice K = hp::lattice_from_abi(ket);
     hp::Lattice B = bra ? hp::lattice_from_abi(bra) : K;
-    HP_REQUIRE(B.nrow == K.nrow && B.ncol == K.ncol && B.cplx == K.cplx, HPEPS_ERR_SHAPE,
-               "bra and ket lattices differ");
-    for (size_t q = 0; q < K.sites.size(); ++q)
-      for (int e = 0; e < 5; ++e)
-        HP_REQUIRE(K.sites[q].dims[e] == B.sites[q].dims[e], HPEPS_ERR_SHAPE, "bra and ket shapes differ");
     double* dev = c.ws<double>(4);  // log, result re/im
-    hp::fill_value(c, dev, 1, 0.0, false);
-    // the bra layer is rescaled separately even when it is the ket itself:
-    // both layers' norms enter <bra|ket>
-    hp::Lattice Kn = hp::normalized_copy(c, K, dev);
-    hp::Lattice Bn = hp::normalized_copy(c, B, dev);
-    std::vector<hp::BndView> bv;
-    std::vector<hp::SiteView> kv, brv;
-    std::vector<std::vector<hp::DevTensor>> envs;
-    std::vector<hp::DevTensor> triv;
-    if (K.nrow == 1) {
-      const int es = K.cplx ? 2 : 1;
-      for (int j = 0; j < K.ncol; ++j) {
-        hp::DevTensor t;
-        t.dims = {1, 1, 1, 1};
-        t.p = c.ws<double>(es);
-        hp::fill_value(c, (double*)t.p, 1, 1.0, K.cplx);
-        triv.push_back(t);
-      }
-      for (int j = 0; j < K.ncol; ++j) bv.push_back(hp::orient_bnd(triv[j], hp::kL2R));
-    } else {
-      hp::boundary_pass(c, Kn, Bn, hp::kTop, *opts, K.nrow - 1, envs, dev);
-      for (int j = 0; j < K.ncol; ++j) bv.push_back(hp::orient_bnd(envs.back()[j], hp::kL2R));
-    }
-    for (int j = 0; j < K.ncol; ++j) {
-      kv.push_back(hp::orient_site(Kn.at(K.nrow - 1, j), hp::kTop, hp::kL2R));
-      brv.push_back(hp::orient_site(Bn.at(K.nrow - 1, j), hp::kTop, hp::kL2R));
-    }
-    hp::contract_last_row(c, K.cplx, bv, kv, brv, dev + 1, dev);
+    norm_run(c, K, B, *opts, dev, nullptr);
     double h[3];
     HP_CHECK_HIP(hipMemcpyAsync(h, dev, sizeof(h), hipMemcpyDeviceToHost, c.stream));
     HP_CHECK_HIP(hipStreamSynchronize(c.stream));
@@ -550,6 +582,35 @@ hpeps_status hpeps_peps_norm(hpeps_ctx* ctx, const hpeps_peps* ket, const hpeps_
     *log_norm = h[0];
     phase[0] = h[1];
     phase[1] = h[2];
+  });
+}
+
+hpeps_status hpeps_peps_norm_backward(hpeps_ctx* ctx, const hpeps_peps* ket, const hpeps_esvd_opts* opts,
+                                      double broadening, void* const* grads, double* log_norm) {
+  return guard_p(ctx, [&](hp::Ctx& c) {
+    check_opts_p(opts);
+    HP_REQUIRE(grads && log_norm, HPEPS_ERR_INVALID_ARG, "null argument");
+    HP_REQUIRE(broadening >= 0.0, HPEPS_ERR_INVALID_ARG, "broadening must be >= 0");
+    hp::Lattice K = hp::lattice_from_abi(ket);
+    for (size_t q = 0; q < K.sites.size(); ++q) HP_REQUIRE(grads[q], HPEPS_ERR_INVALID_ARG, "null gradient pointer");
+    double* dev = c.ws<double>(4);
+    hp::Tape tape(K.cplx);
+    for (auto& s : K.sites) tape.mark_input(s.p, s.size());
+    double* E = nullptr;
+    c.tape = &tape;
+    norm_run(c, K, K, *opts, dev, &E);
+    c.tape = nullptr;
+    // d log|E| / dE (conjugate Wirtinger) = E / |E|^2 = E: the final mantissa
+    // has unit modulus after its rescaling
+    HP_CHECK_HIP(hipMemcpyAsync(tape.grad(c, E), E, (K.cplx ? 2 : 1) * sizeof(double), hipMemcpyDeviceToDevice,
+                                c.stream));
+    tape.backward(c, broadening);
+    hp::write_site_grads(c, tape, K, grads);
+    double h = 0;
+    HP_CHECK_HIP(hipMemcpyAsync(&h, dev, sizeof(double), hipMemcpyDeviceToHost, c.stream));
+    HP_CHECK_HIP(hipStreamSynchronize(c.stream));
+    HP_REQUIRE(std::isfinite(h), HPEPS_ERR_NUMERIC, "non-finite norm");
+    *log_norm = h;
   });
 }
 
