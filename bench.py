@@ -18,7 +18,9 @@ with F_A = 4 k (m^2 D^4 + d D^5 m + d D^4 m) and F_QR(n,k) = 2 n k^2 - 2 k^3/3,
 independent of how the kernels actually evaluate it.  The same step with
 FP32 and with BF16 operator applications (FP32 accumulation; FP64
 orthogonalization and SVD) is reported beside it with its singular-value
-deviation from the FP64 result.
+deviation from the FP64 result.  Side blocks: the D=8 boundary-bond-64
+variant of the step, and the reverse-mode gradient of the 8x8 D=4 complex
+Heisenberg energy (time of the energy and of energy plus gradient).
 """
 import argparse
 import json
@@ -191,6 +193,46 @@ def c3_norm(hp, n=12, D=10, d=2, m=100, p=8):
     return out
 
 
+def c5_gradient(hp, reps, n=8, D=4, d=2, m=16, p=8, q=1):
+    """Variational-energy gradient of an n x n complex128 PEPS (bond D, Heisenberg J=1
+    on every nearest-neighbour bond): time of the cached-environment energy and of its
+    reverse-mode gradient with respect to all n*n sites (both include the two boundary
+    passes with boundary bond m)."""
+    import numpy as np
+    import torch
+
+    import synth
+    peps = synth.random_peps(n, n, D=D, seed=0, complex_=True)
+    dev = [[torch.from_numpy(np.ascontiguousarray(t)).cuda() for t in row] for row in peps]
+    Hb = synth.heisenberg_bond_hamiltonian()
+    terms = [((s1, s2), Hb) for layer in synth.lattice_bonds(n, n) for (s1, s2) in layer]
+    ctx = hp.Context(0)
+    kw = dict(rank=m, oversample=p, power_iters=q, seed=0)
+    hp.peps_energy(ctx, dev, terms, **kw)
+    hp.peps_energy_backward(ctx, dev, terms, **kw)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        e, _ = hp.peps_energy(ctx, dev, terms, **kw)
+    torch.cuda.synchronize()
+    fwd = (time.perf_counter() - t0) / reps
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        e2, _ = hp.peps_energy_backward(ctx, dev, terms, **kw)
+    torch.cuda.synchronize()
+    bwd = (time.perf_counter() - t0) / reps
+    hp.profile_start(ctx)
+    hp.peps_energy_backward(ctx, dev, terms, **kw)
+    agg = hp.profile_read(ctx)
+    hp.profile_stop(ctx)
+    return {"workload": f"energy gradient {n}x{n} D={D} d={d} complex128 Heisenberg, m={m} p={p} q={q}",
+            "sites": n * n, "terms": len(terms), "energy": [e.real, e.imag],
+            "energy_ms": round(fwd * 1e3, 2), "energy_and_gradient_ms": round(bwd * 1e3, 2),
+            "gradient_over_energy": round(bwd / fwd, 2),
+            "gradient_kernel_classes": {k: {"ms": round(a["ms"], 2), "launches": a["launches"]}
+                                        for k, a in sorted(agg.items(), key=lambda x: -x[1]["ms"])[:8]}}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -207,6 +249,8 @@ def main():
                     help="write the tuned choices (loaded + new) to this file after the run")
     ap.add_argument("--d8", type=int, default=3,
                     help="timed steps of the D=8, m=64 variant reported beside the main line (0 skips)")
+    ap.add_argument("--c5", type=int, default=2, metavar="REPS",
+                    help="time the 8x8 D=4 complex energy gradient this many times (0 skips)")
     ap.add_argument("--c3", action="store_true",
                     help="only time peps_norm of the 12x12, D=10, m=100 lattice in FP64, FP32 and BF16")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -328,6 +372,8 @@ def main():
         "kernel_classes": {n: {"ms_per_step": round(a["ms"], 4), "launches": a["launches"]}
                            for n, a in sorted(agg.items(), key=lambda x: -x[1]["ms"])},
     }
+    if args.c5 > 0:
+        res["c5_gradient"] = c5_gradient(hp, args.c5)
     if args.d8 > 0:
         del dev, out, out32, out16
         res["variant_d8"] = d8_variant(hp, ctx, args.d8)
