@@ -49,6 +49,14 @@ hpeps_status hpeps_test_zip_apply(hpeps_ctx* ctx, hpeps_dtype dtype, int64_t bat
  * indices fall back to the heuristic. */
 hpeps_status hpeps_test_gemm_variant(hpeps_ctx* ctx, int32_t tile, int32_t kstep, int32_t split);
 
+/* Forces the contraction order of the zip-up operator's two middle stages
+ * for every following operator application of the context: 0 = chosen by
+ * the cost model, 1 = bra stage then boundary stage (intermediate
+ * [U,H,u,h,c,j]), 2 = boundary stage then bra stage (intermediate
+ * [b,U,h,p,Y,G,j]).  Both orders compute the same product (Table II's
+ * network, two contraction sequences). */
+hpeps_status hpeps_test_zip_order(hpeps_ctx* ctx, int32_t order);
+
 #ifdef __cplusplus
 }
 #endif

@@ -55,14 +55,26 @@ struct ZipOut {
   static ZipOut row_major(const ZipDims& z, int64_t mp);
 };
 
+// Contraction order of the middle two stages of an operator application.
+// Classic: bra then boundary, through W2 [U,H,u,h,c,j] (D^4 m k values);
+// BoundaryFirst: boundary then bra, through Z [b,U,h,p,Y,G,j] (m d D^3 k
+// values for the pair network) at d D^5 m^2 k instead of d D^6 m k +
+// D^4 m^2 k flops -- the smaller intermediate pays off where the stages are
+// bound by HBM traffic rather than by MFMA work.  Auto asks zip_order.
+enum class ZipOrder { Auto, Classic, BoundaryFirst };
+ZipOrder zip_order(const Ctx& ctx, Prec prec, const ZipDims& z, int64_t k, int batch);
+// element count of the W2 work buffer (large enough for either order)
+int64_t zip_w2_elems(const ZipDims& z, int64_t k);
+
 // A X (adjoint = false, X: cols x k) or A^* X (X: rows x k) for the zip-up
 // operator; Y is written as double when y_f64 (F32 applies), else in the
-// apply precision.  With Y == nullptr the last stage is skipped and the
-// first three stages' results stay in w (forward: W1 [u,h,p,Y,c,G,j],
-// W2 [U,H,u,h,c,j], W3 [b,h,H,j]; adjoint: W3, W2 as forward, W1 [Y,G,p,u,h,c,j]).
+// apply precision.  With Y == nullptr (classic order only) the last stage is
+// skipped and the first three stages' results stay in w (forward: W1
+// [u,h,p,Y,c,G,j], W2 [U,H,u,h,c,j], W3 [b,h,H,j]; adjoint: W3, W2 as
+// forward, W1 [Y,G,p,u,h,c,j]).
 void zip_apply(Ctx& ctx, Prec prec, const ZipDims& z, const ZipLayout& L, const ZipOperands& op,
                int batch, int64_t k, bool adjoint, const void* X, void* Y, bool y_f64,
-               const ZipWork& w);
+               const ZipWork& w, ZipOrder order = ZipOrder::Auto);
 
 void orthogonalize(Ctx& ctx, bool cplx, double* Y, double* P, int64_t n, int64_t k, int batch,
                    const OrthWork& w, double* Rt_inv = nullptr);

@@ -66,10 +66,50 @@ WsScope::~WsScope() {
 // ---------------------------------------------------------------------------
 // operator applications
 
+int64_t zip_w2_elems(const ZipDims& z, int64_t k) {
+  const int64_t w2 = z.u * z.h * z.u * z.h * z.c * k;           // [U,H,u,h,c,j]
+  const int64_t zz = z.b * z.u * z.h * z.d * z.y * z.g * k;     // [b,U,h,p,Y,G,j]
+  return std::max(w2, zz);
+}
+
+// Time model of one product: the larger of its MFMA time (an effective rate
+// per precision, scaled down when a tile dimension is below 16) and its HBM
+// time (every operand element moved once at 3.2 TB/s, the rate the gathered
+// GEMM sustains on these streaming shapes; 41 TF/s FP64 on the MFMA-bound
+// ones).
+static double stage_time(Prec prec, int64_t M, int64_t N, int64_t K, int64_t elems, int batch) {
+  const bool cplx = prec == Prec::C128;
+  const double rate = prec == Prec::BF16 ? 200e12 : prec == Prec::F32 ? 80e12 : 40e12;
+  const double elt = prec == Prec::BF16 ? 2 : prec == Prec::F32 ? 4 : cplx ? 16 : 8;
+  const double fill = std::min<double>(1.0, (double)std::min(M, N) / 16.0);
+  const double flops = 2.0 * M * N * K * (cplx ? 4 : 1) * batch;
+  return std::max(flops / (rate * fill), elems * elt * batch / 3.2e12);
+}
+
+ZipOrder zip_order(const Ctx& ctx, Prec prec, const ZipDims& z, int64_t k, int batch) {
+  if (ctx.zip_order_force == 1) return ZipOrder::Classic;
+  if (ctx.zip_order_force == 2) return ZipOrder::BoundaryFirst;
+  const int64_t b = z.b, h = z.h, u = z.u, c = z.c, y = z.y, g = z.g, d = z.d;
+  const int64_t nW1 = u * h * d * y * c * g * k, nW2 = u * h * u * h * c * k, nW3 = b * h * h * k;
+  const int64_t nZ = b * u * h * d * y * g * k, nS = b * u * u * c, nB = u * y * h * g * d;
+  const double classic = stage_time(prec, u * h, u * h * c * k, y * g * d, nW1 + nW2 + nB, batch) +
+                         stage_time(prec, b, h * h * k, u * u * c, nW2 + nW3 + nS, batch);
+  const double bfirst = stage_time(prec, b * u, h * d * y * g * k, u * c, nW1 + nZ + nS, batch) +
+                        stage_time(prec, h, b * h * k, u * y * g * d, nZ + nW3 + nB, batch);
+  return bfirst < 0.9 * classic ? ZipOrder::BoundaryFirst : ZipOrder::Classic;
+}
+
 void zip_apply(Ctx& ctx, Prec prec, const ZipDims& z, const ZipLayout& L, const ZipOperands& op,
                int batch, int64_t k, bool adjoint, const void* X, void* Y, bool y_f64,
-               const ZipWork& w) {
+               const ZipWork& w, ZipOrder order) {
   const int64_t a = z.a, x = z.x, b = z.b, h = z.h, u = z.u, c = z.c, y = z.y, g = z.g, d = z.d;
+  if (order == ZipOrder::Auto) order = zip_order(ctx, prec, z, k, batch);
+  HP_REQUIRE(Y || order == ZipOrder::Classic, HPEPS_ERR_INVALID_ARG,
+             "kept stage results exist in the classic order only");
+  const bool bfirst = order == ZipOrder::BoundaryFirst;
+  // Z[b,U,h,p,Y,G,j] (boundary-first order; shares the W2 buffer)
+  const int64_t nZ = b * u * h * d * y * g * k;
+  const int64_t zj = 1, zG = k, zY = g * k, zp = y * zY, zh = d * zp, zU = h * zh, zb = u * zU;
   const int64_t rows = z.rows(), cols = z.cols();
   const int64_t nW1 = u * h * d * y * c * g * k;  // [u,h,p,Y,c,G,j] or [Y,G,p,u,h,c,j]
   const int64_t nW2 = u * h * u * h * c * k;      // [U,H,u,h,c,j]
@@ -113,8 +153,34 @@ void zip_apply(Ctx& ctx, Prec prec, const ZipDims& z, const ZipLayout& L, const 
       D.Cn.add(y, w1Y).add(c, w1c).add(g, w1G).add(k, w1j);
       call(D, op.T, L.nT, false, X, cols * k, false, w.W1, nW1, false);
     }
+    if (bfirst) {
+      // s2': Z[b,U | h,p,Y,G,j] = sum_{u,c} S[b,u,U,c] W1[u,h,p,Y,c,G,j]
+      {
+        GemmDesc D;
+        D.M = b * u; D.K = u * c; D.N = h * d * y * g * k;
+        D.Am.add(b, sS[0]).add(u, sS[2]);
+        D.Ak.add(u, sS[1]).add(c, sS[3]);
+        D.Bk.add(u, w1u).add(c, w1c);
+        D.Bn.add(h, w1h).add(d, w1p).add(y, w1Y).add(g, w1G).add(k, w1j);
+        D.Cm.add(b, zb).add(u, zU);
+        D.Cn.add(h, zh).add(d, zp).add(y, zY).add(g, zG).add(k, zj);
+        call(D, op.S, L.nS, false, w.W1, nW1, false, w.W2, nZ, false);
+      }
+      // s3': W3[H | b,h,j] = sum_{U,Y,G,p} conj(Bra[U,Y,H,G,p]) Z[b,U,h,p,Y,G,j]
+      {
+        GemmDesc D;
+        D.M = h; D.K = u * y * g * d; D.N = b * h * k;
+        D.Am.add(h, sB[2]);
+        D.Ak.add(u, sB[0]).add(y, sB[1]).add(g, sB[3]).add(d, sB[4]);
+        D.Bk.add(u, zU).add(y, zY).add(g, zG).add(d, zp);
+        D.Bn.add(b, zb).add(h, zh).add(k, zj);
+        D.Cm.add(h, w3H);
+        D.Cn.add(b, w3b).add(h, w3h).add(k, w3j);
+        call(D, op.Bra, L.nB, true, w.W2, nZ, false, w.W3, nW3, false);
+      }
+    }
     // s2: W2[U,H | u,h,c,j] = sum_{Y,G,p} conj(Bra[U,Y,H,G,p]) W1[u,h,p,Y,c,G,j]
-    {
+    if (!bfirst) {
       GemmDesc D;
       D.M = u * h; D.K = y * g * d; D.N = u * h * c * k;
       D.Am.add(u, sB[0]).add(h, sB[2]);
@@ -126,7 +192,7 @@ void zip_apply(Ctx& ctx, Prec prec, const ZipDims& z, const ZipLayout& L, const 
       call(D, op.Bra, L.nB, true, w.W1, nW1, false, w.W2, nW2, false);
     }
     // s3: W3[b | h,H,j] = sum_{u,U,c} S[b,u,U,c] W2[U,H,u,h,c,j]
-    {
+    if (!bfirst) {
       GemmDesc D;
       D.M = b; D.K = u * u * c; D.N = h * h * k;
       D.Am.add(b, sS[0]);
@@ -163,7 +229,7 @@ void zip_apply(Ctx& ctx, Prec prec, const ZipDims& z, const ZipLayout& L, const 
       call(D, op.V, L.nV, true, X, rows * k, false, w.W3, nW3, false);
     }
     // t3: W2[u,U,c | h,H,j] = sum_b conj(S[b,u,U,c]) W3[b,h,H,j]   (W2 stored [U,H,u,h,c,j])
-    {
+    if (!bfirst) {
       GemmDesc D;
       D.M = u * u * c; D.K = b; D.N = h * h * k;
       D.Am.add(u, sS[1]).add(u, sS[2]).add(c, sS[3]);
@@ -176,7 +242,32 @@ void zip_apply(Ctx& ctx, Prec prec, const ZipDims& z, const ZipLayout& L, const 
     }
     // t2: W1[Y,G,p | u,h,c,j] = sum_{U,H} Bra[U,Y,H,G,p] W2[U,H,u,h,c,j]
     const int64_t v1j = 1, v1c = k, v1h = c * k, v1u = h * v1h, v1p = u * v1u, v1G = d * v1p, v1Y = g * v1G;
-    {
+    if (bfirst) {
+      // t3': Z[U,Y,G,p | b,h,j] = sum_H Bra[U,Y,H,G,p] W3[b,h,H,j]   (Z stored [b,U,h,p,Y,G,j])
+      {
+        GemmDesc D;
+        D.M = u * y * g * d; D.K = h; D.N = b * h * k;
+        D.Am.add(u, sB[0]).add(y, sB[1]).add(g, sB[3]).add(d, sB[4]);
+        D.Ak.add(h, sB[2]);
+        D.Bk.add(h, w3H);
+        D.Bn.add(b, w3b).add(h, w3h).add(k, w3j);
+        D.Cm.add(u, zU).add(y, zY).add(g, zG).add(d, zp);
+        D.Cn.add(b, zb).add(h, zh).add(k, zj);
+        call(D, op.Bra, L.nB, false, w.W3, nW3, false, w.W2, nZ, false);
+      }
+      // t2': W1[u,c | h,p,Y,G,j] = sum_{b,U} conj(S[b,u,U,c]) Z[b,U,h,p,Y,G,j]
+      {
+        GemmDesc D;
+        D.M = u * c; D.K = b * u; D.N = h * d * y * g * k;
+        D.Am.add(u, sS[1]).add(c, sS[3]);
+        D.Ak.add(b, sS[0]).add(u, sS[2]);
+        D.Bk.add(b, zb).add(u, zU);
+        D.Bn.add(h, zh).add(d, zp).add(y, zY).add(g, zG).add(k, zj);
+        D.Cm.add(u, v1u).add(c, v1c);
+        D.Cn.add(h, v1h).add(d, v1p).add(y, v1Y).add(g, v1G).add(k, v1j);
+        call(D, op.S, L.nS, true, w.W2, nZ, false, w.W1, nW1, false);
+      }
+    } else {
       GemmDesc D;
       D.M = y * g * d; D.K = u * h; D.N = u * h * c * k;
       D.Am.add(y, sB[1]).add(g, sB[3]).add(d, sB[4]);
@@ -189,15 +280,15 @@ void zip_apply(Ctx& ctx, Prec prec, const ZipDims& z, const ZipLayout& L, const 
     }
     // t1: Z[y,g | Y,c,G,j] = sum_{u,h,p} conj(T[u,y,h,g,p]) W1[Y,G,p,u,h,c,j]
     if (Y) {
-      const int64_t zj = 1, zG = k, zg = g * k, zc = g * zg, zY = c * zc, zy = y * zY;
+      const int64_t oj = 1, oG = k, og = g * k, oc = g * og, oY = c * oc, oy = y * oY;
       GemmDesc D;
       D.M = y * g; D.K = u * h * d; D.N = y * c * g * k;
       D.Am.add(y, sT[1]).add(g, sT[3]);
       D.Ak.add(u, sT[0]).add(h, sT[2]).add(d, sT[4]);
       D.Bk.add(u, v1u).add(h, v1h).add(d, v1p);
       D.Bn.add(y, v1Y).add(c, v1c).add(g, v1G).add(k, v1j);
-      D.Cm.add(y, zy).add(g, zg);
-      D.Cn.add(y, zY).add(c, zc).add(g, zG).add(k, zj);
+      D.Cm.add(y, oy).add(g, og);
+      D.Cn.add(y, oY).add(c, oc).add(g, oG).add(k, oj);
       call(D, op.T, L.nT, true, w.W1, nW1, false, Y, cols * k, y_f64 || !f32);
     }
   }
@@ -332,7 +423,7 @@ void zip_esvd(Ctx& ctx, bool cplx, const ZipDims& z, const ZipLayout& L, const Z
   const int64_t esz = f32 ? 4 : (bf16 ? 2 : 8 * es);  // bytes per intermediate element
   ZipWork w;
   w.W1 = ctx.ws_alloc(nb * z.u * z.h * z.d * z.y * z.c * z.g * k * esz);
-  w.W2 = ctx.ws_alloc(nb * z.u * z.h * z.u * z.h * z.c * k * esz);
+  w.W2 = ctx.ws_alloc(nb * zip_w2_elems(z, k) * esz);
   w.W3 = ctx.ws_alloc(nb * z.b * z.h * z.h * k * esz);
   OrthWork ow;
   ow.G = ctx.ws<double>(nb * k * k * es);

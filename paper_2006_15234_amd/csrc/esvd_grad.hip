@@ -105,8 +105,8 @@ static void zip_vjp_term(Ctx& ctx, bool cplx, const ZipDims& z, const ZipLayout&
   const int64_t a = z.a, x = z.x, b = z.b, h = z.h, u = z.u, c = z.c, y = z.y, g = z.g, d = z.d;
   const int64_t rows = z.rows(), cols = z.cols();
   // R through s1..s3, L through t4..t2
-  zip_apply(ctx, p, z, L, op, batch, k, false, Rt, nullptr, true, wR);
-  zip_apply(ctx, p, z, L, op, batch, k, true, Lt, nullptr, true, wL);
+  zip_apply(ctx, p, z, L, op, batch, k, false, Rt, nullptr, true, wR, ZipOrder::Classic);
+  zip_apply(ctx, p, z, L, op, batch, k, true, Lt, nullptr, true, wL, ZipOrder::Classic);
   // stage layouts (as in zip_apply)
   const int64_t nW1 = u * h * d * y * c * g * k, nW2 = u * h * u * h * c * k, nW3 = b * h * h * k;
   const int64_t w2j = 1, w2c = k, w2h = c * k, w2u = h * w2h, w2H = u * w2u, w2U = h * w2H;
@@ -202,7 +202,7 @@ void zip_esvd_backward(Ctx& ctx, bool cplx, const ZipDims& z, const ZipLayout& L
   // ---- forward recompute, keeping the panels
   ZipWork w;
   w.W1 = R_(z.u * z.h * z.d * z.y * z.c * z.g * k);
-  w.W2 = R_(z.u * z.h * z.u * z.h * z.c * k);
+  w.W2 = R_(zip_w2_elems(z, k));
   w.W3 = R_(z.b * z.h * z.h * k);
   OrthWork ow;
   ow.G = R_(k * k);

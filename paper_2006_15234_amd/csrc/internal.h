@@ -239,6 +239,9 @@ class Ctx {
   // tape records, products, in-place rescalings, exact carries, einsumsvds
   // and copies are logged, and workspace scopes do not release memory
   Tape* tape = nullptr;
+  // contraction order of the zip-up operator's middle stages: 0 chosen by
+  // the cost model, 1 classic, 2 boundary first (kernel tests)
+  int zip_order_force = 0;
 
  private:
   struct ProfRec {

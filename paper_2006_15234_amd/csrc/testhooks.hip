@@ -97,12 +97,18 @@ hpeps_status hpeps_test_zip_apply(hpeps_ctx* ctx, hpeps_dtype dtype, int64_t bat
     const int es = cplx ? 2 : 1;
     hp::ZipWork w;
     w.W1 = c.ws<double>(batch * z.u * z.h * z.d * z.y * z.c * z.g * k * es);
-    w.W2 = c.ws<double>(batch * z.u * z.h * z.u * z.h * z.c * k * es);
+    w.W2 = c.ws<double>(batch * hp::zip_w2_elems(z, k) * es);
     w.W3 = c.ws<double>(batch * z.b * z.h * z.h * k * es);
     hp::ZipOperands op{V, S, T, Bra ? Bra : T};
     hp::zip_apply(c, cplx ? hp::Prec::C128 : hp::Prec::F64, z, hp::ZipLayout::row_major(z), op,
                   (int)batch, k, adjoint != 0, X, Y, true, w);
   });
+}
+
+hpeps_status hpeps_test_zip_order(hpeps_ctx* ctx, int32_t order) {
+  if (!ctx || order < 0 || order > 2) return HPEPS_ERR_INVALID_ARG;
+  ctx->impl->zip_order_force = order;
+  return HPEPS_OK;
 }
 
 hpeps_status hpeps_test_gemm_variant(hpeps_ctx* ctx, int32_t tile, int32_t kstep, int32_t split) {

@@ -225,3 +225,58 @@ def test_errors_are_reported(ctx):
     with pytest.raises(hp.HpepsError) as e:  # rows 800, cols 400: k = 150 > 128
         hp.einsumsvd_zipup(ctx, big, S2, T, rank=150)
     assert e.value.code == 2
+
+
+@pytest.mark.parametrize("order", [1, 2])
+@pytest.mark.parametrize("prec,cplx", [("f64", False), ("f64", True), ("f32", False), ("bf16", False)])
+def test_pair_both_contraction_orders(ctx, order, prec, cplx):
+    """The pair einsumsvd with each contraction order of the operator's middle stages
+    forced, against the FP64 oracle (1e-10 FP64, 1e-4 FP32, 3e-2 BF16)."""
+    m, D, d, rank, p, q = 12, 3, 2, 16, 8, 2
+    B = 2
+    inst = [synth.pair_instance(m, D, d, seed=19, instance=i, complex_=cplx) for i in range(B)]
+    st = [np.stack([t[j] for t in inst]) for j in range(4)]
+    ctx.check(ctx.lib.hpeps_test_zip_order(ctx.h, order))
+    try:
+        U, s, R = hp.einsumsvd_pair(ctx, *[_dev(t) for t in st], rank=rank, oversample=p,
+                                    power_iters=q, seed=4, stream_id=8, precision=prec,
+                                    absorb=hp.ABSORB_NONE)
+    finally:
+        ctx.check(ctx.lib.hpeps_test_zip_order(ctx.h, 0))
+    U, s, R = U.cpu().numpy(), s.cpu().numpy(), R.cpu().numpy()
+    tol = {"f64": 1e-10, "f32": 1e-4, "bf16": 3e-2}[prec]
+    for i in range(B):
+        op = pair_operator(*inst[i])
+        k = rsvd.sketch_width(rank, p, op.n_rows, op.n_cols)
+        om = oracle_sketch(4, 8 + i, op.n_cols, k)
+        Uo, so, Vho = rsvd.randomized_svd(op.apply, op.apply_adj, op.n_rows, op.n_cols, rank, q, om)
+        if prec == "f64":
+            _check(U[i].reshape(-1, rank), s[i], R[i].reshape(rank, -1), Uo, so, Vho, tol,
+                   hp.ABSORB_NONE)
+        else:
+            assert np.max(np.abs(s[i] - so)) <= tol * so[0]
+
+
+@pytest.mark.parametrize("order", [1, 2])
+def test_zipup_both_contraction_orders(ctx, order):
+    """A general zip-up einsumsvd (every leg > 1, complex) with each order forced."""
+    a, x, b, h, u, c, y, g, d = 4, 2, 3, 2, 2, 3, 2, 2, 2
+    rng = np.random.default_rng(5)
+    V = _rand(rng, (a, x, x, b, h, h), True)
+    S = _rand(rng, (b, u, u, c), True)
+    T = _rand(rng, (u, y, h, g, d), True)
+    Bra = _rand(rng, (u, y, h, g, d), True)
+    rank, p, q = 6, 3, 1
+    ctx.check(ctx.lib.hpeps_test_zip_order(ctx.h, order))
+    try:
+        U, s, R = hp.einsumsvd_zipup(ctx, _dev(V[None]), _dev(S[None]), _dev(T[None]),
+                                     _dev(Bra[None]), rank=rank, oversample=p, power_iters=q,
+                                     seed=2, stream_id=3, absorb=hp.ABSORB_NONE)
+    finally:
+        ctx.check(ctx.lib.hpeps_test_zip_order(ctx.h, 0))
+    op = zipup_operator(V, S, T, Bra)
+    k = rsvd.sketch_width(rank, p, op.n_rows, op.n_cols)
+    Uo, so, Vho = rsvd.randomized_svd(op.apply, op.apply_adj, op.n_rows, op.n_cols, rank, q,
+                                      oracle_sketch(2, 3, op.n_cols, k))
+    U, s, R = U.cpu().numpy()[0], s.cpu().numpy()[0], R.cpu().numpy()[0]
+    _check(U.reshape(-1, rank), s, R.reshape(rank, -1), Uo, so, Vho, 1e-10, hp.ABSORB_NONE)

@@ -125,7 +125,18 @@ def test_small_svd(ctx, cplx, k):
 @pytest.mark.parametrize("cplx", [False, True])
 @pytest.mark.parametrize("dims", [(1, 2, 1, 2, 2, 3, 2, 2, 2), (3, 2, 2, 3, 2, 4, 2, 1, 2),
                                   (5, 3, 4, 2, 3, 5, 3, 2, 2)])
-def test_zip_apply(ctx, cplx, dims):
+@pytest.mark.parametrize("order", [0, 1, 2])
+def test_zip_apply(ctx, cplx, dims, order):
+    """A X and A^* P of the zip-up operator in each contraction order of the middle
+    stages (0: cost-model choice, 1: bra then boundary, 2: boundary then bra)."""
+    ctx.check(ctx.lib.hpeps_test_zip_order(ctx.h, order))
+    try:
+        _zip_apply_case(ctx, cplx, dims)
+    finally:
+        ctx.check(ctx.lib.hpeps_test_zip_order(ctx.h, 0))
+
+
+def _zip_apply_case(ctx, cplx, dims):
     a, x, b, h, u, c, y, g, d = dims
     rng = np.random.default_rng(sum(dims))
     V = _rand(rng, (a, x, x, b, h, h), cplx)
