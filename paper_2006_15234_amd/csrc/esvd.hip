@@ -140,7 +140,16 @@ void zip_apply(Ctx& ctx, Prec prec, const ZipDims& z, const ZipLayout& L, const 
   if (!adjoint) {
     // X[y,Y,c,g,G,j]
     const int64_t xj = 1, xG = k, xg = g * k, xc = g * xg, xY = c * xc, xy = y * xY;
-    const int64_t w1j = 1, w1G = k, w1c = g * k, w1Y = c * w1c, w1p = y * w1Y, w1h = d * w1p, w1u = h * w1h;
+    // W1 [u,h,p,Y,c,G,j] (classic) or [u,c,h,p,Y,G,j] (boundary first: the
+    // next product then reads it as a plain row-major (u,c) x (h,p,Y,G,j) matrix)
+    int64_t w1j = 1, w1G = k, w1c = g * k, w1Y = c * w1c, w1p = y * w1Y, w1h = d * w1p, w1u = h * w1h;
+    if (bfirst) {
+      w1Y = g * k;
+      w1p = y * w1Y;
+      w1h = d * w1p;
+      w1c = h * w1h;
+      w1u = c * w1c;
+    }
     // s1: W1[u,h,p | Y,c,G,j] = sum_{y,g} T[u,y,h,g,p] X[y,Y,c,g,G,j]
     {
       GemmDesc D;
@@ -241,7 +250,17 @@ void zip_apply(Ctx& ctx, Prec prec, const ZipDims& z, const ZipLayout& L, const 
       call(D, op.S, L.nS, true, w.W3, nW3, false, w.W2, nW2, false);
     }
     // t2: W1[Y,G,p | u,h,c,j] = sum_{U,H} Bra[U,Y,H,G,p] W2[U,H,u,h,c,j]
-    const int64_t v1j = 1, v1c = k, v1h = c * k, v1u = h * v1h, v1p = u * v1u, v1G = d * v1p, v1Y = g * v1G;
+    // W1 [Y,G,p,u,h,c,j] (classic) or [u,c,h,p,Y,G,j] (boundary first: written
+    // by contiguous rows of the (u,c) x (h,p,Y,G,j) product)
+    int64_t v1j = 1, v1c = k, v1h = c * k, v1u = h * v1h, v1p = u * v1u, v1G = d * v1p, v1Y = g * v1G;
+    if (bfirst) {
+      v1G = k;
+      v1Y = g * k;
+      v1p = y * v1Y;
+      v1h = d * v1p;
+      v1c = h * v1h;
+      v1u = c * v1c;
+    }
     if (bfirst) {
       // t3': Z[U,Y,G,p | b,h,j] = sum_H Bra[U,Y,H,G,p] W3[b,h,H,j]   (Z stored [b,U,h,p,Y,G,j])
       {
