@@ -69,6 +69,8 @@ struct GemmArgs {
   int tabA, tabB;       // K offsets from LDS tables (else k * step)
   int a_kstep, b_kstep;
   int accumulate;
+  int rA_step, cB_step, rC_step, cC_step;  // row / column offsets m * step (-1: from the table;
+                                           // affine maps skip the dependent table load)
   double alpha;
   const double* scale;
   const double* nscale;
@@ -314,7 +316,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
     a_lds[i] = row * LDK + kk;
     a_kk[i] = kk;
     const int m = m0 + row;
-    a_roff[i] = (m < g.M) ? g.rA[m] : -1;
+    a_roff[i] = (m < g.M) ? (g.rA_step >= 0 ? m * g.rA_step : g.rA[m]) : -1;
     // byte offset of (row, kk) at k = 0 on the affine path; rows past M read
     // row 0 instead (those accumulator rows are never stored)
     a_base[i] = (unsigned)(max(a_roff[i], 0) + kk * g.a_kstep) * ELT;
@@ -332,7 +334,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
     b_lds[i] = col * LDK + kk;
     b_kk[i] = kk;
     const int n = n0 + col;
-    b_coff[i] = (n < g.N) ? g.cB[n] : -1;
+    b_coff[i] = (n < g.N) ? (g.cB_step >= 0 ? n * g.cB_step : g.cB[n]) : -1;
     b_base[i] = (unsigned)(max(b_coff[i], 0) + kk * g.b_kstep) * ELT;
   }
 
@@ -530,7 +532,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
 #pragma unroll
   for (int j = 0; j < TN; ++j) {
     const int n = n0 + wn * TN * 16 + j * 16 + li;
-    coff[j] = n < g.N ? g.cC[n] : -1;
+    coff[j] = n < g.N ? (g.cC_step >= 0 ? n * g.cC_step : g.cC[n]) : -1;
     cs[j] = (g.nscale && n < g.N) ? sb * g.nscale[(long long)b * g.nscale_ld + n] : sb;
   }
   TOut* Cb = reinterpret_cast<TOut*>(g.C);
@@ -541,7 +543,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
     for (int r = 0; r < 4; ++r) {
       const int row = (sizeof(TC) == 8) ? (lk + 4 * r) : (lk * 4 + r);  // f64 / f32-accumulator layouts
       const int m = m0 + wm * TM * 16 + i * 16 + row;
-      const int roff = m < g.M ? g.rC[m] : -1;
+      const int roff = m < g.M ? (g.rC_step >= 0 ? m * g.rC_step : g.rC[m]) : -1;
 #pragma unroll
       for (int j = 0; j < TN; ++j) {
         if (roff < 0 || coff[j] < 0) continue;
@@ -938,6 +940,10 @@ void gemm(Ctx& ctx, Prec prec, const GemmDesc& d, const GemmCall& c) {
   a.cB = ctx.table(d.Bn);
   a.rC = ctx.table(d.Cm);
   a.cC = ctx.table(d.Cn);
+  a.rA_step = (int)affine_step(d.Am);
+  a.cB_step = (int)affine_step(d.Bn);
+  a.rC_step = (int)affine_step(d.Cm);
+  a.cC_step = (int)affine_step(d.Cn);
   a.sA = c.sA;
   a.sB = c.sB;
   a.sC = c.sC;
