@@ -373,6 +373,33 @@ def peps_energy_backward(ctx, ket, terms, *, rank, oversample=0, power_iters=0, 
     return complex(e[0], e[1]), grads
 
 
+def peps_energy_autograd(ctx, ket, terms, *, rank, oversample=0, power_iters=0, seed=0,
+                         broadening=0.0):
+    """Re E as a differentiable torch scalar of the site tensors (rows of device tensors
+    with requires_grad): the forward call runs the library's energy with its reverse-mode
+    gradient in one pass (the gradient needs the forward anyway), the backward scales that
+    gradient by the incoming cotangent."""
+    torch = _torch()
+    nrow, ncol = len(ket), len(ket[0])
+    kw = dict(rank=rank, oversample=oversample, power_iters=power_iters, seed=seed,
+              broadening=broadening)
+
+    class _Energy(torch.autograd.Function):
+        @staticmethod
+        def forward(fctx, *sites):
+            lat = [[sites[i * ncol + j].detach().contiguous() for j in range(ncol)]
+                   for i in range(nrow)]
+            e, grads = peps_energy_backward(ctx, lat, terms, **kw)
+            fctx.save_for_backward(*[g for row in grads for g in row])
+            return torch.tensor(e.real, dtype=torch.float64, device=sites[0].device)
+
+        @staticmethod
+        def backward(fctx, g):
+            return tuple(g * t for t in fctx.saved_tensors)
+
+    return _Energy.apply(*[t for row in ket for t in row])
+
+
 def peps_norm_backward(ctx, ket, *, rank, oversample=0, power_iters=0, seed=0, broadening=0.0):
     """Gradient of log <psi|psi> (boundary-MPS contraction, FP64 sketch) with respect to
     every site tensor.  Returns (log <psi|psi>, gradients as rows of device tensors)."""
