@@ -19,8 +19,9 @@ independent of how the kernels actually evaluate it.  The same step with
 FP32 and with BF16 operator applications (FP32 accumulation; FP64
 orthogonalization and SVD) is reported beside it with its singular-value
 deviation from the FP64 result.  Side blocks: the D=8 boundary-bond-64
-variant of the step, and the reverse-mode gradient of the 8x8 D=4 complex
-Heisenberg energy (time of the energy and of energy plus gradient).
+variant of the step, batched ITE sweeps of a 16x16 D=8 Ising PEPS, and the
+reverse-mode gradient of the 8x8 D=4 complex Heisenberg energy (time of the
+energy and of energy plus gradient).
 """
 import argparse
 import json
@@ -33,6 +34,8 @@ sys.path.insert(0, ROOT)
 
 M, DB, DP, RANK, OVERS, POW, BATCH = 36, 6, 2, 36, 8, 2, 64
 MFMA_F64_PEAK_TFLOPS = 78.6
+MFMA_F32_PEAK_TFLOPS = 157.3
+MFMA_BF16_PEAK_TFLOPS = 2500.0
 HBM_PEAK_GBS = 8000.0
 
 
@@ -233,6 +236,45 @@ def c5_gradient(hp, reps, n=8, D=4, d=2, m=16, p=8, q=1):
                                         for k, a in sorted(agg.items(), key=lambda x: -x[1]["ms"])[:8]}}
 
 
+def c4_ite(hp, sweeps, n=16, D=8, d=2, tau=0.01, J=1.0, hfield=3.0):
+    """Batched imaginary-time evolution of an n x n transverse-field Ising PEPS: TEBD sweeps
+    of QR-SVD updates over the four layers of non-overlapping bonds (bond dimensions grow
+    from 1 to D, edge bonds uneven), the sweep loop replayed from a HIP graph."""
+    import numpy as np
+    import torch
+
+    import synth
+    layers = synth.lattice_bonds(n, n)
+    hams = synth.tfi_bond_hamiltonians(n, n, J, hfield)
+    uniq, index, bond_gate = [], {}, []
+    for layer in layers:
+        for bnd in layer:
+            G = synth.bond_gate(hams[bnd], tau)
+            key = G.tobytes()
+            if key not in index:
+                index[key] = len(uniq)
+                uniq.append(G)
+            bond_gate.append(index[key])
+    peps0 = synth.product_state_peps(n, n, d=d, seed=0)
+    ctx = hp.Context(0)
+    dev = [[torch.from_numpy(np.ascontiguousarray(t)).cuda() for t in row] for row in peps0]
+    gates = torch.from_numpy(np.stack(uniq)).cuda()
+    plan = hp.ItePlan(ctx, dev, gates, bond_gate, D)
+    plan.run(sweeps)                      # grows every bond to its final dimension
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan.run(sweeps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    shapes = plan.shapes()
+    plan.close()
+    nb = len(bond_gate)
+    return {"workload": f"ITE {n}x{n} TFI J={J} h={hfield} tau={tau}, bond {D}, d={d}, "
+                        f"{sweeps} sweeps from the grown state", "bonds_per_sweep": nb,
+            "ms_per_sweep": round(dt / sweeps * 1e3, 4), "bond_updates_per_s": round(nb * sweeps / dt, 1),
+            "max_bond": max(max(s[:4]) for s in shapes)}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -249,6 +291,8 @@ def main():
                     help="write the tuned choices (loaded + new) to this file after the run")
     ap.add_argument("--d8", type=int, default=3,
                     help="timed steps of the D=8, m=64 variant reported beside the main line (0 skips)")
+    ap.add_argument("--c4", type=int, default=50, metavar="SWEEPS",
+                    help="time this many ITE sweeps of the 16x16 D=8 TFI PEPS (0 skips)")
     ap.add_argument("--c5", type=int, default=2, metavar="REPS",
                     help="time the 8x8 D=4 complex energy gradient this many times (0 skips)")
     ap.add_argument("--c3", action="store_true",
@@ -364,14 +408,18 @@ def main():
         "roofline": dict(roofline, share_of_step=round(prof["ms"] / args.steps / ms, 4)),
         "fp32_apply": {"value": round(flops / (ms32 * 1e-3) / 1e9, 2), "unit": "GFLOP/s",
                        "ms_per_step": round(ms32, 4), "speedup_vs_f64": round(ms / ms32, 3),
+                       "frac_of_fp32_peak": round(flops / (ms32 * 1e-3) / 1e12 / MFMA_F32_PEAK_TFLOPS, 4),
                        "eps_sigma_vs_f64": eps32},
         "bf16_apply": {"value": round(flops / (ms16 * 1e-3) / 1e9, 2), "unit": "GFLOP/s",
                        "ms_per_step": round(ms16, 4), "speedup_vs_f64": round(ms / ms16, 3),
+                       "frac_of_bf16_peak": round(flops / (ms16 * 1e-3) / 1e12 / MFMA_BF16_PEAK_TFLOPS, 5),
                        "eps_sigma_vs_f64": eps16},
         "autotune": not args.no_autotune,
         "kernel_classes": {n: {"ms_per_step": round(a["ms"], 4), "launches": a["launches"]}
                            for n, a in sorted(agg.items(), key=lambda x: -x[1]["ms"])},
     }
+    if args.c4 > 0:
+        res["c4_ite"] = c4_ite(hp, args.c4)
     if args.c5 > 0:
         res["c5_gradient"] = c5_gradient(hp, args.c5)
     if args.d8 > 0:
