@@ -1,0 +1,39 @@
+// Cross-lane sums with DPP lane moves (VALU data paths, no LDS traffic).
+// Every lane of the wavefront must be active where these are called.
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace hp {
+
+// v + (v moved by the DPP control CTRL within the rows of ROW_MASK)
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_add(double v) {
+  const long long x = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)x, CTRL, ROW_MASK, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(x >> 32), CTRL, ROW_MASK, 0xf, false);
+  return v + __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+// Sum over the 16 lanes of a DPP row, returned in all of them: quad
+// butterflies, then the half-row and row mirrors.
+__device__ __forceinline__ double row_sum16(double v) {
+  v = dpp_add<0xb1, 0xf>(v);   // quad_perm [1,0,3,2]
+  v = dpp_add<0x4e, 0xf>(v);   // quad_perm [2,3,0,1]
+  v = dpp_add<0x141, 0xf>(v);  // row_half_mirror
+  v = dpp_add<0x140, 0xf>(v);  // row_mirror
+  return v;
+}
+
+// Wavefront sum, returned in every lane: row sums, then the two row
+// broadcasts leave the total in lane 63, which is read back.
+__device__ __forceinline__ double wave_sum(double v) {
+  v = row_sum16(v);
+  v = dpp_add<0x142, 0xa>(v);  // row_bcast:15 into rows 1 and 3
+  v = dpp_add<0x143, 0xc>(v);  // row_bcast:31 into rows 2 and 3
+  const long long x = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_readlane((int)x, 63);
+  const int hi = __builtin_amdgcn_readlane((int)(x >> 32), 63);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+}  // namespace hp

@@ -20,6 +20,7 @@
 #include <cstring>
 #include <new>
 
+#include "dpp.h"
 #include "peps.h"
 
 struct hpeps_ite_plan {
@@ -59,10 +60,6 @@ struct IteArgs {
   int max_rows, max_cols;
 };
 
-__device__ __forceinline__ double wave_sum(double v) {
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-  return v;
-}
 
 // Householder QR in place of the column-major rows x cols matrix A (cols <=
 // rows).  Reflector j is stored in A[j][j..rows) (unnormalised v with
@@ -246,45 +243,67 @@ __global__ __launch_bounds__(kT) void qrsvd_bond_kernel(IteArgs a) {
   __syncthreads();
 
   // ---- one-sided Jacobi on the columns of Theta (J accumulates) ----------
+  // A pair is rotated when its correlation is above sqrt(nr) eps relative to
+  // the two column norms AND above nr eps ||Theta||_F^2: Theta is often
+  // strongly rank-deficient (near product states), and two columns made of
+  // rounding noise have O(1) relative correlation forever; rotating them
+  // changes nothing above rounding level.
+  {
+    double f2 = 0;
+    for (int e = tid; e < nr * nc; e += kT) f2 += Th[e] * Th[e];
+    f2 = wave_sum(f2);
+    if (lane == 0) red[wave] = f2;
+  }
+  __syncthreads();
+  double fro2 = 0;
+  for (int w = 0; w < nw; ++w) fro2 += red[w];
+  __syncthreads();
+  const double floor_abs = nr * 0x1p-52 * fro2;
   const int n = (nc + 1) / 2 * 2;
   const double tol = sqrt((double)nr) * 0x1p-52;
+  // one 16-lane group per column pair (nc <= 32: at most 16 pairs per round,
+  // all in flight at once); a group reduces over the rows with in-group shuffles
+  const int grp = tid >> 4, gl = tid & 15;
   for (int sweep = 0; sweep < 60; ++sweep) {
     if (tid == 0) rot = 0;
     __syncthreads();
     for (int round = 0; round < n - 1; ++round) {
-      for (int p = wave; p < n / 2; p += nw) {
-        auto at = [&](int pos) { return pos == 0 ? 0 : 1 + (pos - 1 + round) % (n - 1); };
-        const int ca = at(p), cb = at(n - 1 - p);
-        if (ca >= nc || cb >= nc) continue;
-        double* x = Th + (long long)ca * nr;
-        double* y = Th + (long long)cb * nr;
-        double a2 = 0, b2 = 0, gm = 0;
-        for (int r = lane; r < nr; r += 64) {
+      int ca = nc, cb = nc;
+      if (grp < n / 2) {
+        ca = grp == 0 ? 0 : 1 + (grp - 1 + round) % (n - 1);
+        const int pb = n - 1 - grp;
+        cb = 1 + (pb - 1 + round) % (n - 1);
+      }
+      const bool act = ca < nc && cb < nc;
+      double* x = Th + (long long)(act ? ca : 0) * nr;
+      double* y = Th + (long long)(act ? cb : 0) * nr;
+      double a2 = 0, b2 = 0, gm = 0;
+      if (act)
+        for (int r = gl; r < nr; r += 16) {
           a2 += x[r] * x[r];
           b2 += y[r] * y[r];
           gm += x[r] * y[r];
         }
-        a2 = wave_sum(a2);
-        b2 = wave_sum(b2);
-        gm = wave_sum(gm);
-        if (a2 > 0 && b2 > 0 && fabs(gm) > tol * sqrt(a2) * sqrt(b2)) {
-          const double zeta = (b2 - a2) / (2.0 * gm);
-          const double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-          const double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
-          for (int r = lane; r < nr; r += 64) {
-            const double xv = x[r], yv = y[r];
-            x[r] = c * xv - s * yv;
-            y[r] = s * xv + c * yv;
-          }
-          double* jx = J + (long long)ca * nc;
-          double* jy = J + (long long)cb * nc;
-          for (int r = lane; r < nc; r += 64) {
-            const double xv = jx[r], yv = jy[r];
-            jx[r] = c * xv - s * yv;
-            jy[r] = s * xv + c * yv;
-          }
-          if (lane == 0) rot = 1;
+      a2 = row_sum16(a2);
+      b2 = row_sum16(b2);
+      gm = row_sum16(gm);
+      if (act && a2 > 0 && b2 > 0 && fabs(gm) > tol * sqrt(a2) * sqrt(b2) && fabs(gm) > floor_abs) {
+        const double zeta = (b2 - a2) / (2.0 * gm);
+        const double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+        const double c = 1.0 / sqrt(1.0 + t * t), sn = c * t;
+        for (int r = gl; r < nr; r += 16) {
+          const double xv = x[r], yv = y[r];
+          x[r] = c * xv - sn * yv;
+          y[r] = sn * xv + c * yv;
         }
+        double* jx = J + (long long)ca * nc;
+        double* jy = J + (long long)cb * nc;
+        for (int r = gl; r < nc; r += 16) {
+          const double xv = jx[r], yv = jy[r];
+          jx[r] = c * xv - sn * yv;
+          jy[r] = sn * xv + c * yv;
+        }
+        if (gl == 0) rot = 1;
       }
       __syncthreads();
     }
@@ -300,17 +319,16 @@ __global__ __launch_bounds__(kT) void qrsvd_bond_kernel(IteArgs a) {
   }
   __syncthreads();
   const int Dn = min(a.dmax, min(nr, nc));
+  // descending order, ties by index: the rank of value i is the number of
+  // values that precede it
+  if (tid < nc) {
+    const double v = sig[tid];
+    int rank = 0;
+    for (int j = 0; j < nc; ++j) rank += (sig[j] > v) || (sig[j] == v && j < tid);
+    perm[rank] = tid;
+  }
+  __syncthreads();
   if (tid == 0) {
-    for (int i = 0; i < nc; ++i) perm[i] = i;
-    for (int i = 1; i < nc; ++i) {
-      const int v = perm[i];
-      int j = i - 1;
-      while (j >= 0 && sig[perm[j]] < sig[v]) {
-        perm[j + 1] = perm[j];
-        --j;
-      }
-      perm[j + 1] = v;
-    }
     double nn = 0;
     for (int b = 0; b < Dn; ++b) nn += sig[perm[b]] * sig[perm[b]];
     nn = sqrt(nn);

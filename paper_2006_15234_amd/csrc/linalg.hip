@@ -16,6 +16,7 @@
 #include <algorithm>
 #include <cmath>
 
+#include "dpp.h"
 #include "internal.h"
 
 namespace hp {
@@ -91,31 +92,6 @@ __global__ void sketch_kernel(TO* out, long long nk, uint64_t seed, uint64_t str
     o[i * stride] = (TO)v;
     if (stride == 2) o[i * 2 + 1] = (TO)0;
   }
-}
-
-// ---------------------------------------------------------------------------
-// Wavefront sum of a double with DPP lane moves (no LDS traffic): quad
-// butterflies, half-row and row mirrors, then the two row broadcasts; lane 63
-// ends with the total, which is read back as a wave-uniform value.  Every
-// lane of the wavefront must be active.
-template <int CTRL, int ROW_MASK>
-__device__ __forceinline__ double dpp_add(double v) {
-  const long long x = __builtin_bit_cast(long long, v);
-  const int lo = __builtin_amdgcn_update_dpp(0, (int)x, CTRL, ROW_MASK, 0xf, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, (int)(x >> 32), CTRL, ROW_MASK, 0xf, false);
-  return v + __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned)lo);
-}
-__device__ __forceinline__ double wave_sum(double v) {
-  v = dpp_add<0xb1, 0xf>(v);   // quad_perm [1,0,3,2]
-  v = dpp_add<0x4e, 0xf>(v);   // quad_perm [2,3,0,1]
-  v = dpp_add<0x141, 0xf>(v);  // row_half_mirror
-  v = dpp_add<0x140, 0xf>(v);  // row_mirror
-  v = dpp_add<0x142, 0xa>(v);  // row_bcast:15 into rows 1 and 3
-  v = dpp_add<0x143, 0xc>(v);  // row_bcast:31 into rows 2 and 3
-  const long long x = __builtin_bit_cast(long long, v);
-  const int lo = __builtin_amdgcn_readlane((int)x, 63);
-  const int hi = __builtin_amdgcn_readlane((int)(x >> 32), 63);
-  return __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned)lo);
 }
 
 // ---------------------------------------------------------------------------
@@ -299,14 +275,6 @@ __global__ __launch_bounds__(kCholThreads) void chol_inv_kernel(const double* Ga
 constexpr int kJacMaxThreads = 1024;  // 64 pairs (k <= 128) / 4 per wavefront
 constexpr int kJacRows = 8;           // rows per lane: k <= 16 * 8
 
-// Sum over the 16 lanes of a DPP row, returned in all of them.
-__device__ __forceinline__ double row_sum16(double v) {
-  v = dpp_add<0xb1, 0xf>(v);   // quad_perm [1,0,3,2]
-  v = dpp_add<0x4e, 0xf>(v);   // quad_perm [2,3,0,1]
-  v = dpp_add<0x141, 0xf>(v);  // row_half_mirror
-  v = dpp_add<0x140, 0xf>(v);  // row_mirror
-  return v;
-}
 
 template <bool CPLX>
 __global__ __launch_bounds__(kJacMaxThreads) void jacobi_kernel(const double* Racc_all, int k, int max_sweeps,
