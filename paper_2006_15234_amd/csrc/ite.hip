@@ -244,10 +244,12 @@ __global__ __launch_bounds__(kT) void qrsvd_bond_kernel(IteArgs a) {
 
   // ---- one-sided Jacobi on the columns of Theta (J accumulates) ----------
   // A pair is rotated when its correlation is above sqrt(nr) eps relative to
-  // the two column norms AND above nr eps ||Theta||_F^2: Theta is often
-  // strongly rank-deficient (near product states), and two columns made of
-  // rounding noise have O(1) relative correlation forever; rotating them
-  // changes nothing above rounding level.
+  // the two column norms and above nr eps ||Theta||_F^2.  The second test
+  // leaves Theta^T Theta wrong by at most the rounding error of forming
+  // Theta (a backward-stable stop); without it, the columns of rounding
+  // noise of a rank-deficient Theta (near product states) keep O(1) relative
+  // correlation forever and the sweeps never stop.  Only the leading pairs,
+  // weighted by their singular values, enter the updated sites.
   {
     double f2 = 0;
     for (int e = tid; e < nr * nc; e += kT) f2 += Th[e] * Th[e];
@@ -262,7 +264,7 @@ __global__ __launch_bounds__(kT) void qrsvd_bond_kernel(IteArgs a) {
   const int n = (nc + 1) / 2 * 2;
   const double tol = sqrt((double)nr) * 0x1p-52;
   // one 16-lane group per column pair (nc <= 32: at most 16 pairs per round,
-  // all in flight at once); a group reduces over the rows with in-group shuffles
+  // all in flight at once); a group reduces over the rows with DPP row sums
   const int grp = tid >> 4, gl = tid & 15;
   for (int sweep = 0; sweep < 60; ++sweep) {
     if (tid == 0) rot = 0;
