@@ -99,6 +99,15 @@ typedef struct {
   int32_t reserved;
 } hpeps_esvd_opts;
 
+/* A strided dense tensor in device memory (the operands of hpeps_einsumsvd). */
+typedef struct {
+  const void* data;     /* device memory, caller-owned, dtype of the call        */
+  int32_t ndim;         /* 1..8                                                  */
+  int32_t conj;         /* nonzero: the operand enters complex-conjugated        */
+  int64_t shape[8];
+  int64_t strides[8];   /* element strides, >= 1 for every leg of extent > 1    */
+} hpeps_tensor;
+
 /* Diagnostics of the last einsumsvd-based call (host struct, filled after the
  * call's stream work completes when the call synchronises, else on the next
  * hpeps_get_info). */
@@ -177,6 +186,36 @@ hpeps_status hpeps_autotune_import(hpeps_ctx* ctx, const char* json);
  * rounded to nearest float (HPEPS_F32).  out: device memory. */
 hpeps_status hpeps_sketch(hpeps_ctx* ctx, hpeps_dtype dtype, int64_t n, int64_t k, int64_t batch,
                           uint64_t seed, uint64_t stream_id, void* out);
+
+/* ---- einsumsvd of an arbitrary network (Sec. II-C, Alg. 4) --------------
+ * The network is written as einsum subscripts over single-letter legs,
+ * "<legs of op 0>,<legs of op 1>,...-><row legs>|<column legs>", e.g. the
+ * zip-up network "axXbhH,buUc,uyhgp,UYHGp->axX|yYcgG".  Every leg either
+ * joins exactly two operands (summed) or belongs to one operand and appears
+ * once in the output.  The network is read as the matrix
+ * A[(row legs), (column legs)] and factorized A ~ U diag(sigma) V^* by the
+ * randomized SVD of Alg. 4 without forming A: the products A X and A^* Y
+ * are sequences of pairwise contractions of the network with the k-column
+ * sketch panel (next the operand sharing most legs with the running tensor),
+ * each one gathered MFMA GEMM; orthogonalization, small SVD, canonical
+ * phase, truncation and absorption are those of hpeps_einsumsvd_zipup.
+ * Operands: n_ops strided tensors (hpeps_tensor; conj = read conjugated,
+ * which is how a bra layer enters).  dtype HPEPS_F64 or HPEPS_C128;
+ * opts->sketch_precision must be HPEPS_F64.  Outputs (device, caller-owned,
+ * contiguous): U [row legs..., m'], sigma [m'] (may be NULL), R [m', column
+ * legs...] per absorb as for the zip-up call; log_scale (device, one
+ * double) is incremented by log(sigma_1) in the CARRY mode (may be NULL
+ * otherwise).  m' = min(rank, k), k = min(rank + oversample, rows, cols)
+ * (hpeps_einsumsvd_query returns rows, cols and m' without launching
+ * anything).  Errors: INVALID_ARG for malformed subscripts (a leg used three
+ * times, a repeated leg in one operand, no '|'), SHAPE for inconsistent
+ * dimensions, DTYPE, UNSUPPORTED for k > 128 (88 complex). */
+hpeps_status hpeps_einsumsvd(hpeps_ctx* ctx, hpeps_dtype dtype, const char* subscripts, int32_t n_ops,
+                             const hpeps_tensor* ops, const hpeps_esvd_opts* opts, hpeps_absorb absorb,
+                             void* U, double* sigma, void* R, double* log_scale);
+hpeps_status hpeps_einsumsvd_query(hpeps_ctx* ctx, const char* subscripts, int32_t n_ops,
+                                   const hpeps_tensor* ops, const hpeps_esvd_opts* opts, int64_t* rows,
+                                   int64_t* cols, int64_t* rank_kept);
 
 /* ---- einsumsvd on the zip-up network (Alg. 3 inner step, Alg. 4) -------
  * One einsumsvd of boundary contraction: the carry V[a,x,X,b,h,H] of the

@@ -11,7 +11,7 @@ from ._ffi import (  # noqa: F401
     HpepsError, Context, EsvdOpts, lib_path, load_library, symbols,
 )
 from .api import (  # noqa: F401
-    einsumsvd_zipup, einsumsvd_pair, einsumsvd_pair_backward, einsumsvd_pair_autograd,
+    einsumsvd, einsumsvd_zipup, einsumsvd_pair, einsumsvd_pair_backward, einsumsvd_pair_autograd,
     peps_norm, boundary_contract_row, peps_energy, peps_norm_backward, peps_energy_backward,
     peps_energy_autograd,
     apply_two_site_gate, ItePlan, get_info, sketch, make_opts, profile_start, profile_stop,

@@ -37,6 +37,11 @@ class Peps(C.Structure):
                 ("shapes", C.POINTER(C.c_int64))]
 
 
+class Tensor(C.Structure):
+    _fields_ = [("data", C.c_void_p), ("ndim", C.c_int32), ("conj", C.c_int32),
+                ("shape", C.c_int64 * 8), ("strides", C.c_int64 * 8)]
+
+
 class Bmps(C.Structure):
     _fields_ = [("ncol", C.c_int32), ("dtype", C.c_int32), ("tensors", C.POINTER(C.c_void_p)),
                 ("shapes", C.POINTER(C.c_int64)), ("capacity", C.POINTER(C.c_int64))]
@@ -68,6 +73,10 @@ _SIGS = {
     "hpeps_profile_read": (C.c_int, [_P, C.c_int32, C.c_void_p, C.POINTER(C.c_int32)]),
     "hpeps_sketch": (C.c_int, [_P, C.c_int, C.c_int64, C.c_int64, C.c_int64, C.c_uint64,
                                C.c_uint64, _P]),
+    "hpeps_einsumsvd": (C.c_int, [_P, C.c_int, C.c_char_p, C.c_int32, C.POINTER(Tensor),
+                                  C.POINTER(EsvdOpts), C.c_int, _P, _P, _P, _P]),
+    "hpeps_einsumsvd_query": (C.c_int, [_P, C.c_char_p, C.c_int32, C.POINTER(Tensor),
+                                        C.POINTER(EsvdOpts), _I64P, _I64P, _I64P]),
     "hpeps_einsumsvd_zipup": (C.c_int, [_P, C.c_int64, C.c_int, _I64P, _P, _P, _P, _P,
                                         C.POINTER(EsvdOpts), C.c_int, _P, _P, _P, _P]),
     "hpeps_einsumsvd_pair": (C.c_int, [_P, C.c_int64, C.c_int, _I64P, _P, _P, _P, _P,

@@ -2,7 +2,7 @@
 import ctypes as C
 
 from ._ffi import (ABSORB_CARRY, ABSORB_NONE, C128, F32, BF16, F64, Bmps, EsvdInfo, EsvdOpts,
-                   Peps)
+                   Peps, Tensor)
 
 _PREC = {"f64": F64, "f32": F32, "bf16": BF16}
 
@@ -34,6 +34,60 @@ def make_opts(rank, oversample=0, power_iters=0, precision="f64", seed=0, stream
     return EsvdOpts(rank=int(rank), oversample=int(oversample), power_iters=int(power_iters),
                     sketch_precision=_PREC[precision], seed=int(seed), stream_id=int(stream_id),
                     jacobi_max_sweeps=int(jacobi_max_sweeps), reserved=0)
+
+
+def _tensor_desc(t, conj, name):
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if t.dim() < 1 or t.dim() > 8:
+        raise ValueError(f"{name}: 1 to 8 legs")
+    d = Tensor(data=t.data_ptr(), ndim=t.dim(), conj=1 if conj else 0)
+    for q in range(t.dim()):
+        d.shape[q] = t.shape[q]
+        d.strides[q] = t.stride(q)
+    return d
+
+
+def _network(subscripts, tensors, conj):
+    conj = conj or [False] * len(tensors)
+    if len(conj) != len(tensors):
+        raise ValueError("one conj flag per operand")
+    descs = (Tensor * len(tensors))(*[_tensor_desc(t, c, f"operand {i}")
+                                      for i, (t, c) in enumerate(zip(tensors, conj))])
+    lhs, rhs = subscripts.split("->")
+    left, right = rhs.split("|")
+    dims = {}
+    for legs, t in zip(lhs.split(","), tensors):
+        for c, n in zip(legs, t.shape):
+            dims[c] = n
+    return descs, [dims.get(c, 0) for c in left], [dims.get(c, 0) for c in right]
+
+
+def einsumsvd(ctx, subscripts, *tensors, conj=None, rank, oversample=0, power_iters=0, seed=0,
+              stream_id=0, absorb=ABSORB_NONE, log_scale=None, jacobi_max_sweeps=0):
+    """einsumsvd of the network `subscripts` ("ab,bc->a|c": row legs left of '|', column
+    legs right of it) over strided device tensors (conj[i]: operand i enters conjugated).
+    Returns (U [row dims..., m'], sigma [m'], R [m', column dims...])."""
+    torch = _torch()
+    if not tensors:
+        raise ValueError("no operands")
+    dt = _dtype_code(tensors[0])
+    if any(t.dtype != tensors[0].dtype for t in tensors):
+        raise TypeError("operands must share one dtype")
+    descs, ldims, rdims = _network(subscripts, tensors, conj)
+    o = make_opts(rank, oversample, power_iters, "f64", seed, stream_id, jacobi_max_sweeps)
+    rows, cols, mp = C.c_int64(), C.c_int64(), C.c_int64()
+    ctx.check(ctx.lib.hpeps_einsumsvd_query(ctx.h, subscripts.encode(), len(tensors), descs, C.byref(o),
+                                            C.byref(rows), C.byref(cols), C.byref(mp)))
+    dev = tensors[0].device
+    U = torch.empty((*ldims, mp.value), dtype=tensors[0].dtype, device=dev)
+    sig = torch.empty((mp.value,), dtype=torch.float64, device=dev)
+    R = torch.empty((mp.value, *rdims), dtype=tensors[0].dtype, device=dev)
+    ctx.sync_stream()
+    ctx.check(ctx.lib.hpeps_einsumsvd(
+        ctx.h, dt, subscripts.encode(), len(tensors), descs, C.byref(o), absorb, _dev(U, "U"),
+        _dev(sig, "sigma"), _dev(R, "R"), _dev(log_scale, "log_scale") if log_scale is not None else None))
+    return U, sig, R
 
 
 def einsumsvd_zipup(ctx, V, S, T, Bra=None, *, rank, oversample=0, power_iters=0, seed=0,

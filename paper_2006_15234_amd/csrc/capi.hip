@@ -178,6 +178,34 @@ hpeps_status hpeps_sketch(hpeps_ctx* ctx, hpeps_dtype dtype, int64_t n, int64_t 
   });
 }
 
+hpeps_status hpeps_einsumsvd(hpeps_ctx* ctx, hpeps_dtype dtype, const char* subscripts, int32_t n_ops,
+                             const hpeps_tensor* ops, const hpeps_esvd_opts* opts, hpeps_absorb absorb,
+                             void* U, double* sigma, void* R, double* log_scale) {
+  if (!ctx) return HPEPS_ERR_INVALID_ARG;
+  return guard(ctx, [&] {
+    check_opts(opts);
+    const bool cplx = is_cplx(dtype);
+    HP_REQUIRE(U && R, HPEPS_ERR_INVALID_ARG, "null output");
+    HP_REQUIRE(absorb >= HPEPS_ABSORB_CARRY && absorb <= HPEPS_ABSORB_NONE, HPEPS_ERR_INVALID_ARG,
+               "bad absorb mode");
+    HP_REQUIRE(absorb != HPEPS_ABSORB_CARRY || log_scale, HPEPS_ERR_INVALID_ARG,
+               "the CARRY mode needs log_scale");
+    hp::Ctx& c = *ctx->impl;
+    c.ws_reset();
+    hp::einsumsvd_network(c, cplx, subscripts, n_ops, ops, *opts, absorb, U, sigma, R, log_scale);
+  });
+}
+
+hpeps_status hpeps_einsumsvd_query(hpeps_ctx* ctx, const char* subscripts, int32_t n_ops,
+                                   const hpeps_tensor* ops, const hpeps_esvd_opts* opts, int64_t* rows,
+                                   int64_t* cols, int64_t* rank_kept) {
+  if (!ctx) return HPEPS_ERR_INVALID_ARG;
+  return guard(ctx, [&] {
+    check_opts(opts);
+    hp::einsumsvd_query(subscripts, n_ops, ops, *opts, rows, cols, rank_kept);
+  });
+}
+
 hpeps_status hpeps_einsumsvd_zipup(hpeps_ctx* ctx, int64_t batch, hpeps_dtype dtype,
                                    const int64_t dims[9], const void* V, const void* S,
                                    const void* T, const void* Bra, const hpeps_esvd_opts* opts,

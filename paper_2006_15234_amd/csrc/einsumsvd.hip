@@ -1,0 +1,197 @@
+// einsumsvd of an arbitrary tensor network (Sec. II-C): the network given by
+// an einsum-style subscript string is read as a matrix whose rows are the
+// open legs left of '|' and whose columns are the open legs right of it,
+// and is factorized by the randomized SVD of Alg. 4 without ever being
+// formed: A X and A^* Y are evaluated as sequences of pairwise tensor
+// contractions of the network with the sketch panel (Sec. IV-A), each one
+// gathered GEMM (contract.hip).
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "contract.h"
+#include "esvd.h"
+
+namespace hp {
+namespace {
+
+constexpr char kSketchLeg = '#';  // the panel's k leg (never a subscript letter)
+
+struct Network {
+  std::vector<TView> ops;
+  std::string left, right;               // open legs of the rows / columns, in order
+  std::vector<int64_t> ldims, rdims;
+  int64_t rows = 1, cols = 1;
+};
+
+bool leg_char(char c) { return (c >= 'a' && c <= 'z') || (c >= 'A' && c <= 'Z'); }
+
+Network parse(const char* subscripts, int n_ops, const hpeps_tensor* ops, bool cplx) {
+  HP_REQUIRE(subscripts && ops && n_ops >= 1 && n_ops <= 64, HPEPS_ERR_INVALID_ARG, "bad einsumsvd operands");
+  const std::string s(subscripts);
+  const auto arrow = s.find("->");
+  HP_REQUIRE(arrow != std::string::npos, HPEPS_ERR_INVALID_ARG, "subscripts need '->'");
+  const std::string lhs = s.substr(0, arrow), rhs = s.substr(arrow + 2);
+  const auto bar = rhs.find('|');
+  HP_REQUIRE(bar != std::string::npos && rhs.find('|', bar + 1) == std::string::npos, HPEPS_ERR_INVALID_ARG,
+             "the output needs exactly one '|' between row legs and column legs");
+  Network net;
+  net.left = rhs.substr(0, bar);
+  net.right = rhs.substr(bar + 1);
+  HP_REQUIRE(!net.left.empty() && !net.right.empty(), HPEPS_ERR_INVALID_ARG, "empty row or column legs");
+  std::vector<std::string> terms;
+  size_t start = 0;
+  for (;;) {
+    const auto comma = lhs.find(',', start);
+    terms.push_back(lhs.substr(start, comma == std::string::npos ? std::string::npos : comma - start));
+    if (comma == std::string::npos) break;
+    start = comma + 1;
+  }
+  HP_REQUIRE((int)terms.size() == n_ops, HPEPS_ERR_INVALID_ARG, "subscripts and operand count differ");
+  // leg counts: every leg must appear twice over operands and output
+  int count[128] = {0};
+  int64_t dim[128];
+  std::fill(dim, dim + 128, -1);
+  for (int i = 0; i < n_ops; ++i) {
+    const std::string& t = terms[i];
+    const hpeps_tensor& o = ops[i];
+    HP_REQUIRE(o.data, HPEPS_ERR_INVALID_ARG, "null operand");
+    HP_REQUIRE(o.ndim >= 1 && o.ndim <= 8 && (int)t.size() == o.ndim, HPEPS_ERR_SHAPE,
+               "operand " + std::to_string(i) + ": legs and ndim differ");
+    std::vector<int64_t> dims(o.shape, o.shape + o.ndim), strides(o.strides, o.strides + o.ndim);
+    int64_t extent = 1;
+    for (int q = 0; q < o.ndim; ++q) {
+      const char c = t[q];
+      HP_REQUIRE(leg_char(c), HPEPS_ERR_INVALID_ARG, "legs are letters a-z, A-Z");
+      HP_REQUIRE(t.find(c) == (size_t)q, HPEPS_ERR_INVALID_ARG, "a leg repeated within one operand");
+      HP_REQUIRE(dims[q] >= 1, HPEPS_ERR_SHAPE, "dimensions must be >= 1");
+      HP_REQUIRE(strides[q] >= 1 || dims[q] == 1, HPEPS_ERR_SHAPE, "strides must be >= 1");
+      if (dims[q] == 1) strides[q] = std::max<int64_t>(strides[q], 0);
+      extent += (dims[q] - 1) * strides[q];
+      HP_REQUIRE(dim[(int)c] < 0 || dim[(int)c] == dims[q], HPEPS_ERR_SHAPE, std::string("dims of leg ") + c + " differ");
+      dim[(int)c] = dims[q];
+      ++count[(int)c];
+    }
+    net.ops.push_back(tview(o.data, t, dims, strides, extent, cplx && o.conj != 0));
+  }
+  for (char c : net.left + net.right) {
+    HP_REQUIRE(leg_char(c), HPEPS_ERR_INVALID_ARG, "legs are letters a-z, A-Z");
+    HP_REQUIRE(count[(int)c] == 1, HPEPS_ERR_INVALID_ARG,
+               std::string("open leg ") + c + " must appear in exactly one operand and once in the output");
+    ++count[(int)c];
+  }
+  for (int c = 0; c < 128; ++c)
+    HP_REQUIRE(count[c] == 0 || count[c] == 2, HPEPS_ERR_INVALID_ARG,
+               std::string("leg ") + (char)c + " must join exactly two operands or be open");
+  for (char c : net.left) {
+    net.ldims.push_back(dim[(int)c]);
+    net.rows *= dim[(int)c];
+  }
+  for (char c : net.right) {
+    net.rdims.push_back(dim[(int)c]);
+    net.cols *= dim[(int)c];
+  }
+  return net;
+}
+
+int64_t vol(const std::string& legs, const TView& A, const TView& B) {
+  int64_t n = 1;
+  for (char c : legs) {
+    const int64_t a = leg_dim(A, c);
+    n *= a >= 0 ? a : leg_dim(B, c);
+  }
+  return n;
+}
+
+// Contracts the panel X (legs `in` + k) with every operand, greedily: next
+// the operand sharing the most legs with the running tensor (ties: the
+// smaller result); the last product writes Y in the row-major order `out` + k.
+void apply_network(Ctx& ctx, bool cplx, const Network& net, bool adjoint, const double* X, double* Y, int64_t k) {
+  WsScope scope(ctx);
+  const std::string& in = adjoint ? net.left : net.right;
+  const std::string& out = adjoint ? net.right : net.left;
+  std::vector<int64_t> idims = adjoint ? net.ldims : net.rdims;
+  idims.push_back(k);
+  TView cur = tview_rm(X, in + kSketchLeg, idims);
+  std::vector<TView> rest = net.ops;
+  if (adjoint)
+    for (auto& v : rest) v.conj = cplx && !v.conj;
+  while (!rest.empty()) {
+    int best = -1, best_shared = -1;
+    int64_t best_size = 0;
+    std::string best_out;
+    for (int i = 0; i < (int)rest.size(); ++i) {
+      std::string o;
+      int shared = 0;
+      for (char c : cur.legs)
+        if (rest[i].legs.find(c) == std::string::npos) o += c; else ++shared;
+      for (char c : rest[i].legs)
+        if (cur.legs.find(c) == std::string::npos) o += c;
+      const int64_t sz = vol(o, cur, rest[i]);
+      if (shared > best_shared || (shared == best_shared && sz < best_size)) {
+        best = i;
+        best_shared = shared;
+        best_size = sz;
+        best_out = o;
+      }
+    }
+    const TView op = rest[best];
+    rest.erase(rest.begin() + best);
+    if (rest.empty()) {
+      // the legs left must be the output legs and the panel leg
+      std::string want = out + kSketchLeg;
+      HP_REQUIRE(best_out.size() == want.size(), HPEPS_ERR_INVALID_ARG, "network legs do not close");
+      for (char c : want)
+        HP_REQUIRE(best_out.find(c) != std::string::npos, HPEPS_ERR_INVALID_ARG, "network legs do not close");
+      int64_t n = 1;
+      for (char c : want) n *= std::max(leg_dim(cur, c), leg_dim(op, c));
+      contract2(ctx, cplx, cur, op, want, Y, n);
+    } else {
+      double* buf = ctx.ws<double>(best_size * (cplx ? 2 : 1));
+      const auto dims = contract2(ctx, cplx, cur, op, best_out, buf, best_size);
+      cur = tview_rm(buf, best_out, dims);
+    }
+  }
+}
+
+}  // namespace
+
+void einsumsvd_network(Ctx& ctx, bool cplx, const char* subscripts, int n_ops, const hpeps_tensor* ops,
+                       const hpeps_esvd_opts& o, hpeps_absorb absorb, void* U, double* sigma, void* R,
+                       double* log_scale) {
+  WsScope scope(ctx);
+  HP_REQUIRE(o.sketch_precision == HPEPS_F64, HPEPS_ERR_DTYPE, "network einsumsvd runs in FP64 / complex128");
+  const Network net = parse(subscripts, n_ops, ops, cplx);
+  const int64_t rows = net.rows, cols = net.cols;
+  const int64_t k = sketch_width(o.rank, o.oversample, rows, cols);
+  const int64_t mp = std::min<int64_t>(o.rank, k);
+  HP_REQUIRE(k >= 1 && k <= (cplx ? 88 : 128), HPEPS_ERR_SHAPE, "sketch width k out of range");
+  HP_REQUIRE(rows < (1LL << 31) && cols < (1LL << 31), HPEPS_ERR_UNSUPPORTED, "matrix dimension too large");
+  ctx.last_rank = mp;
+  ctx.last_k = k;
+  const int es = cplx ? 2 : 1;
+  double* Om = ctx.ws<double>(cols * k * es);
+  double* Y0 = ctx.ws<double>(rows * k * es);
+  sketch(ctx, Om, false, cols, k, 1, o.seed, o.stream_id, cplx);
+  apply_network(ctx, cplx, net, false, Om, Y0, k);
+  ZipOut out;
+  out.Urows.add(rows, mp);
+  out.Ucol.add(mp, 1);
+  out.Rrow.add(mp, cols);
+  out.Rcols.add(cols, 1);
+  out.nU = rows * mp;
+  out.nR = mp * cols;
+  rsvd_finish(ctx, cplx, rows, cols, k, mp, 1, o, absorb, out, U, sigma, R, log_scale, Y0,
+              [&](bool adj, const double* X, double* Y) { apply_network(ctx, cplx, net, adj, X, Y, k); });
+}
+
+void einsumsvd_query(const char* subscripts, int n_ops, const hpeps_tensor* ops, const hpeps_esvd_opts& o,
+                     int64_t* rows, int64_t* cols, int64_t* rank) {
+  const Network net = parse(subscripts, n_ops, ops, false);
+  const int64_t k = sketch_width(o.rank, o.oversample, net.rows, net.cols);
+  if (rows) *rows = net.rows;
+  if (cols) *cols = net.cols;
+  if (rank) *rank = std::min<int64_t>(o.rank, k);
+}
+
+}  // namespace hp

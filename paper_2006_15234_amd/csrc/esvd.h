@@ -1,5 +1,6 @@
 // einsumsvd internals shared by the ABI entry points and the boundary code.
 #pragma once
+#include <functional>
 #include "internal.h"
 
 namespace hp {
@@ -85,11 +86,31 @@ void cholqr_r(Ctx& ctx, bool cplx, const double* Y, double* S1, double* S2, int6
 
 int64_t sketch_width(int64_t m, int64_t p, int64_t rows, int64_t cols);
 
+// A X (adj = false, X: cols x k) or A^* X (adj = true, X: rows x k) of an
+// implicit operator, FP64 / complex128 panels, row-major per instance.
+using ApplyFn = std::function<void(bool adj, const double* X, double* Y)>;
+
+struct ZipOut;
+// Alg. 4 from the first product Y0 = A Omega on (orthogonalizations, power
+// iterations, projection, small SVD, canonical phase, factors).
+void rsvd_finish(Ctx& ctx, bool cplx, int64_t rows, int64_t cols, int64_t k, int64_t mp, int batch,
+                 const hpeps_esvd_opts& o, hpeps_absorb absorb, const ZipOut& out, void* U, double* sigma,
+                 void* R, double* log_scale, double* Y0, const ApplyFn& apply);
+
 // Randomized einsumsvd (Alg. 4) of the zip-up operator; operands are FP64 /
 // complex128 device arrays (instances back to back with the extents of L).
 void zip_esvd(Ctx& ctx, bool cplx, const ZipDims& z, const ZipLayout& L, const ZipOperands& op,
               int batch, const hpeps_esvd_opts& o, hpeps_absorb absorb, const ZipOut& out,
               void* U, double* sigma, void* R, double* log_scale);
+
+// einsumsvd of an arbitrary network given by subscripts ("ab,bc->a|c"):
+// rows are the open legs left of '|', columns those right of it; FP64 /
+// complex128, one instance.  U [rows, m'] and R [m', cols] row-major.
+void einsumsvd_network(Ctx& ctx, bool cplx, const char* subscripts, int n_ops, const hpeps_tensor* ops,
+                       const hpeps_esvd_opts& o, hpeps_absorb absorb, void* U, double* sigma, void* R,
+                       double* log_scale);
+void einsumsvd_query(const char* subscripts, int n_ops, const hpeps_tensor* ops, const hpeps_esvd_opts& o,
+                     int64_t* rows, int64_t* cols, int64_t* rank);
 
 // Exact carry V[a,x,X,b,h,H] = sum_{u,U,p} L[a,u,U,b] T[u,x,h,p] conj(Bra[U,X,H,p])
 // (the left leg of T and Bra has dim 1 and is skipped); V is row-major.

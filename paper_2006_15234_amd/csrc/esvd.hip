@@ -403,47 +403,22 @@ int64_t sketch_width(int64_t m, int64_t p, int64_t rows, int64_t cols) {
   return std::min(m + p, std::min(rows, cols));
 }
 
-void zip_esvd(Ctx& ctx, bool cplx, const ZipDims& z, const ZipLayout& L, const ZipOperands& op64,
-              int batch, const hpeps_esvd_opts& o, hpeps_absorb absorb, const ZipOut& out,
-              void* U, double* sigma, void* R, double* log_scale) {
-  if (taping(ctx)) {
-    HP_REQUIRE(!sigma, HPEPS_ERR_UNSUPPORTED, "tape: singular values are not a differentiable output");
-    tape_zip(ctx, cplx, z, L, op64, batch, o, absorb, out, U, R);
-  }
-  TapeSuspend unrecorded(ctx);
+// Alg. 4 after the first product: Y0 = A Omega (rows x k per instance) is
+// orthogonalized, the q power iterations and the projection B^* = A^* P run
+// through `apply` (A X for adj = false, A^* X for adj = true; FP64 /
+// complex128 panels), then the small SVD, the canonical phase and the two
+// factors follow.  Y0 is overwritten.
+void rsvd_finish(Ctx& ctx, bool cplx, int64_t rows, int64_t cols, int64_t k, int64_t mp, int batch,
+                 const hpeps_esvd_opts& o, hpeps_absorb absorb, const ZipOut& out, void* U, double* sigma,
+                 void* R, double* log_scale, double* Xr0, const ApplyFn& apply) {
   WsScope scope(ctx);
-  const int64_t rows = z.rows(), cols = z.cols();
-  const int64_t k = sketch_width(o.rank, o.oversample, rows, cols);
-  const int64_t mp = std::min<int64_t>(o.rank, k);
-  HP_REQUIRE(k >= 1, HPEPS_ERR_SHAPE, "empty einsumsvd");
-  HP_REQUIRE(k <= (cplx ? 88 : 128), HPEPS_ERR_SHAPE, "sketch width k exceeds the small-SVD limit");
-  const bool f32 = o.sketch_precision == HPEPS_F32;
-  const bool bf16 = o.sketch_precision == HPEPS_BF16;
-  const bool narrow = f32 || bf16;
-  HP_REQUIRE(!(narrow && cplx), HPEPS_ERR_DTYPE, "FP32 and BF16 sketches are real-only");
-  HP_REQUIRE(o.sketch_precision == HPEPS_F64 || narrow, HPEPS_ERR_DTYPE,
-             "sketch precision must be F64, F32 or BF16");
-  HP_REQUIRE(out.Urows.size() == rows && out.Ucol.size() == mp && out.Rrow.size() == mp &&
-                 out.Rcols.size() == cols,
-             HPEPS_ERR_SHAPE, "output layout does not match the factor shapes");
-  const Prec prec = cplx ? Prec::C128 : (f32 ? Prec::F32 : (bf16 ? Prec::BF16 : Prec::F64));
-  const int es = cplx ? 2 : 1;  // doubles per element
-  const int max_sweeps = o.jacobi_max_sweeps > 0 ? o.jacobi_max_sweeps : 40;
-  ctx.last_rank = mp;
-  ctx.last_k = k;
-
-  // workspace
+  const int es = cplx ? 2 : 1;
   const int64_t nb = batch;
+  const int max_sweeps = o.jacobi_max_sweeps > 0 ? o.jacobi_max_sweeps : 40;
   double* Xc0 = ctx.ws<double>(nb * cols * k * es);
   double* Xc1 = ctx.ws<double>(nb * cols * k * es);
   double* Xc2 = ctx.ws<double>(nb * cols * k * es);
-  double* Xr0 = ctx.ws<double>(nb * rows * k * es);
   double* Xr1 = ctx.ws<double>(nb * rows * k * es);
-  const int64_t esz = f32 ? 4 : (bf16 ? 2 : 8 * es);  // bytes per intermediate element
-  ZipWork w;
-  w.W1 = ctx.ws_alloc(nb * z.u * z.h * z.d * z.y * z.c * z.g * k * esz);
-  w.W2 = ctx.ws_alloc(nb * zip_w2_elems(z, k) * esz);
-  w.W3 = ctx.ws_alloc(nb * z.b * z.h * z.h * k * esz);
   OrthWork ow;
   ow.G = ctx.ws<double>(nb * k * k * es);
   ow.Rinv = ctx.ws<double>(nb * k * k * es);
@@ -454,64 +429,6 @@ void zip_esvd(Ctx& ctx, bool cplx, const ZipDims& z, const ZipLayout& L, const Z
   double* isig = ctx.ws<double>(nb * k);
   double* isig1 = ctx.ws<double>(nb);
   int* sweeps = ctx.ws<int>(nb);
-
-  // operands in the apply precision
-  ZipOperands op = op64;
-  float* xin32 = nullptr;
-  void* xin16 = nullptr;
-  if (bf16) {
-    void* parts[4];
-    const void* src[4] = {op64.V, op64.S, op64.T, op64.Bra};
-    const int64_t cnt[4] = {L.nV, L.nS, L.nT, L.nB};
-    for (int i = 0; i < 4; ++i) {
-      parts[i] = ctx.ws_alloc(nb * cnt[i] * 2);
-      convert_f64_to_bf16(ctx, (const double*)src[i], parts[i], nb * cnt[i]);
-    }
-    op.V = parts[0];
-    op.S = parts[1];
-    op.T = parts[2];
-    op.Bra = parts[3];
-    xin16 = ctx.ws_alloc(nb * std::max(rows, cols) * k * 2);
-  }
-  if (f32) {
-    float* V32 = ctx.ws<float>(nb * L.nV);
-    float* S32 = ctx.ws<float>(nb * L.nS);
-    float* T32 = ctx.ws<float>(nb * L.nT);
-    float* B32 = ctx.ws<float>(nb * L.nB);
-    convert_f64_to_f32(ctx, (const double*)op64.V, V32, nb * L.nV);
-    convert_f64_to_f32(ctx, (const double*)op64.S, S32, nb * L.nS);
-    convert_f64_to_f32(ctx, (const double*)op64.T, T32, nb * L.nT);
-    convert_f64_to_f32(ctx, (const double*)op64.Bra, B32, nb * L.nB);
-    op.V = V32;
-    op.S = S32;
-    op.T = T32;
-    op.Bra = B32;
-    xin32 = ctx.ws<float>(nb * std::max(rows, cols) * k);
-  }
-  auto apply = [&](bool adj, const double* X, double* Y) {
-    const void* xin = X;
-    if (f32) {
-      convert_f64_to_f32(ctx, X, xin32, nb * (adj ? rows : cols) * k);
-      xin = xin32;
-    }
-    if (bf16) {
-      convert_f64_to_bf16(ctx, X, xin16, nb * (adj ? rows : cols) * k);
-      xin = xin16;
-    }
-    zip_apply(ctx, prec, z, L, op, batch, k, adj, xin, Y, true, w);
-  };
-
-  // Alg. 4
-  if (f32) {
-    sketch(ctx, xin32, true, cols, k, batch, o.seed, o.stream_id);
-    zip_apply(ctx, prec, z, L, op, batch, k, false, xin32, Xr0, true, w);
-  } else if (bf16) {
-    sketch(ctx, Xc0, false, cols, k, batch, o.seed, o.stream_id);
-    apply(false, Xc0, Xr0);
-  } else {
-    sketch(ctx, Xc0, false, cols, k, batch, o.seed, o.stream_id, cplx);
-    zip_apply(ctx, prec, z, L, op, batch, k, false, Xc0, Xr0, true, w);
-  }
   orthogonalize(ctx, cplx, Xr0, Xr1, rows, k, batch, ow);          // P in Xr1
   for (int it = 0; it < o.power_iters; ++it) {
     apply(true, Xr1, Xc0);
@@ -596,6 +513,104 @@ void zip_esvd(Ctx& ctx, bool cplx, const ZipDims& z, const ZipLayout& L, const Z
     gemm(ctx, p64, D, c);
   }
   if (sigma) copy_sigma(ctx, sig, k, mp, batch, sigma);
+}
+
+void zip_esvd(Ctx& ctx, bool cplx, const ZipDims& z, const ZipLayout& L, const ZipOperands& op64,
+              int batch, const hpeps_esvd_opts& o, hpeps_absorb absorb, const ZipOut& out,
+              void* U, double* sigma, void* R, double* log_scale) {
+  if (taping(ctx)) {
+    HP_REQUIRE(!sigma, HPEPS_ERR_UNSUPPORTED, "tape: singular values are not a differentiable output");
+    tape_zip(ctx, cplx, z, L, op64, batch, o, absorb, out, U, R);
+  }
+  TapeSuspend unrecorded(ctx);
+  WsScope scope(ctx);
+  const int64_t rows = z.rows(), cols = z.cols();
+  const int64_t k = sketch_width(o.rank, o.oversample, rows, cols);
+  const int64_t mp = std::min<int64_t>(o.rank, k);
+  HP_REQUIRE(k >= 1, HPEPS_ERR_SHAPE, "empty einsumsvd");
+  HP_REQUIRE(k <= (cplx ? 88 : 128), HPEPS_ERR_SHAPE, "sketch width k exceeds the small-SVD limit");
+  const bool f32 = o.sketch_precision == HPEPS_F32;
+  const bool bf16 = o.sketch_precision == HPEPS_BF16;
+  const bool narrow = f32 || bf16;
+  HP_REQUIRE(!(narrow && cplx), HPEPS_ERR_DTYPE, "FP32 and BF16 sketches are real-only");
+  HP_REQUIRE(o.sketch_precision == HPEPS_F64 || narrow, HPEPS_ERR_DTYPE,
+             "sketch precision must be F64, F32 or BF16");
+  HP_REQUIRE(out.Urows.size() == rows && out.Ucol.size() == mp && out.Rrow.size() == mp &&
+                 out.Rcols.size() == cols,
+             HPEPS_ERR_SHAPE, "output layout does not match the factor shapes");
+  const Prec prec = cplx ? Prec::C128 : (f32 ? Prec::F32 : (bf16 ? Prec::BF16 : Prec::F64));
+  const int es = cplx ? 2 : 1;  // doubles per element
+  ctx.last_rank = mp;
+  ctx.last_k = k;
+
+  // workspace
+  const int64_t nb = batch;
+  double* Xc0 = ctx.ws<double>(nb * cols * k * es);  // the sketch
+  double* Xr0 = ctx.ws<double>(nb * rows * k * es);  // A Omega
+  const int64_t esz = f32 ? 4 : (bf16 ? 2 : 8 * es);  // bytes per intermediate element
+  ZipWork w;
+  w.W1 = ctx.ws_alloc(nb * z.u * z.h * z.d * z.y * z.c * z.g * k * esz);
+  w.W2 = ctx.ws_alloc(nb * zip_w2_elems(z, k) * esz);
+  w.W3 = ctx.ws_alloc(nb * z.b * z.h * z.h * k * esz);
+
+  // operands in the apply precision
+  ZipOperands op = op64;
+  float* xin32 = nullptr;
+  void* xin16 = nullptr;
+  if (bf16) {
+    void* parts[4];
+    const void* src[4] = {op64.V, op64.S, op64.T, op64.Bra};
+    const int64_t cnt[4] = {L.nV, L.nS, L.nT, L.nB};
+    for (int i = 0; i < 4; ++i) {
+      parts[i] = ctx.ws_alloc(nb * cnt[i] * 2);
+      convert_f64_to_bf16(ctx, (const double*)src[i], parts[i], nb * cnt[i]);
+    }
+    op.V = parts[0];
+    op.S = parts[1];
+    op.T = parts[2];
+    op.Bra = parts[3];
+    xin16 = ctx.ws_alloc(nb * std::max(rows, cols) * k * 2);
+  }
+  if (f32) {
+    float* V32 = ctx.ws<float>(nb * L.nV);
+    float* S32 = ctx.ws<float>(nb * L.nS);
+    float* T32 = ctx.ws<float>(nb * L.nT);
+    float* B32 = ctx.ws<float>(nb * L.nB);
+    convert_f64_to_f32(ctx, (const double*)op64.V, V32, nb * L.nV);
+    convert_f64_to_f32(ctx, (const double*)op64.S, S32, nb * L.nS);
+    convert_f64_to_f32(ctx, (const double*)op64.T, T32, nb * L.nT);
+    convert_f64_to_f32(ctx, (const double*)op64.Bra, B32, nb * L.nB);
+    op.V = V32;
+    op.S = S32;
+    op.T = T32;
+    op.Bra = B32;
+    xin32 = ctx.ws<float>(nb * std::max(rows, cols) * k);
+  }
+  auto apply = [&](bool adj, const double* X, double* Y) {
+    const void* xin = X;
+    if (f32) {
+      convert_f64_to_f32(ctx, X, xin32, nb * (adj ? rows : cols) * k);
+      xin = xin32;
+    }
+    if (bf16) {
+      convert_f64_to_bf16(ctx, X, xin16, nb * (adj ? rows : cols) * k);
+      xin = xin16;
+    }
+    zip_apply(ctx, prec, z, L, op, batch, k, adj, xin, Y, true, w);
+  };
+
+  // Alg. 4
+  if (f32) {
+    sketch(ctx, xin32, true, cols, k, batch, o.seed, o.stream_id);
+    zip_apply(ctx, prec, z, L, op, batch, k, false, xin32, Xr0, true, w);
+  } else if (bf16) {
+    sketch(ctx, Xc0, false, cols, k, batch, o.seed, o.stream_id);
+    apply(false, Xc0, Xr0);
+  } else {
+    sketch(ctx, Xc0, false, cols, k, batch, o.seed, o.stream_id, cplx);
+    zip_apply(ctx, prec, z, L, op, batch, k, false, Xc0, Xr0, true, w);
+  }
+  rsvd_finish(ctx, cplx, rows, cols, k, mp, batch, o, absorb, out, U, sigma, R, log_scale, Xr0, apply);
 }
 
 // ---------------------------------------------------------------------------
