@@ -57,14 +57,23 @@ typedef enum {
 
 typedef enum { HPEPS_F64 = 0, HPEPS_C128 = 1, HPEPS_F32 = 2, HPEPS_BF16 = 3 } hpeps_dtype;
 
-/* Where the singular values go in an einsumsvd (the left factor U is always
- * the isometry P Z of Alg. 4):
- *   CARRY  -> right factor (Sigma / sigma_1) V^*, and log(sigma_1) is added
+/* Where the singular values go in an einsumsvd; U = P Z (Alg. 4) is the
+ * isometric left factor, V^* is computed as Sigma^-1 Z^* (P^* A) (row i has
+ * relative error ~ 1e-16 * sigma_1 / sigma_i):
+ *   CARRY  -> left U, right (Sigma / sigma_1) V^*, and log(sigma_1) is added
  *             to the log-scale accumulator (zip-up carry, see hpeps_peps_norm)
- *   RIGHT  -> right factor Sigma V^*
- *   NONE   -> right factor V^* (computed as Sigma^-1 Z^* (P^* A): row i has
- *             relative error ~ 1e-16 * sigma_1 / sigma_i)                     */
-typedef enum { HPEPS_ABSORB_CARRY = 0, HPEPS_ABSORB_RIGHT = 1, HPEPS_ABSORB_NONE = 2 } hpeps_absorb;
+ *   RIGHT  -> left U, right Sigma V^*
+ *   NONE   -> left U, right V^*
+ *   LEFT   -> left U Sigma, right V^*
+ *   SQRT   -> left U Sigma^1/2, right Sigma^1/2 V^* (the split of Alg. 1)
+ * The adjoint calls support NONE and RIGHT.                                 */
+typedef enum {
+  HPEPS_ABSORB_CARRY = 0,
+  HPEPS_ABSORB_RIGHT = 1,
+  HPEPS_ABSORB_NONE = 2,
+  HPEPS_ABSORB_LEFT = 3,
+  HPEPS_ABSORB_SQRT = 4
+} hpeps_absorb;
 
 typedef struct hpeps_ctx hpeps_ctx;
 

@@ -7,7 +7,7 @@ The library must have been built (``python -m paper_2006_15234_amd.build`` or
 ``RuntimeError`` when ``libhpeps.so`` is missing.  There is no CPU fallback.
 """
 from ._ffi import (  # noqa: F401
-    ABSORB_CARRY, ABSORB_NONE, ABSORB_RIGHT, F32, F64, C128, L2R, R2L,
+    ABSORB_CARRY, ABSORB_LEFT, ABSORB_NONE, ABSORB_RIGHT, ABSORB_SQRT, F32, F64, C128, L2R, R2L,
     HpepsError, Context, EsvdOpts, lib_path, load_library, symbols,
 )
 from .api import (  # noqa: F401

@@ -5,7 +5,7 @@ import os
 _HERE = os.path.dirname(os.path.abspath(__file__))
 
 F64, C128, F32, BF16 = 0, 1, 2, 3
-ABSORB_CARRY, ABSORB_RIGHT, ABSORB_NONE = 0, 1, 2
+ABSORB_CARRY, ABSORB_RIGHT, ABSORB_NONE, ABSORB_LEFT, ABSORB_SQRT = 0, 1, 2, 3, 4
 L2R, R2L = 0, 1
 
 _STATUS = {0: "ok", 1: "invalid argument", 2: "shape mismatch", 3: "unsupported dtype",

@@ -186,7 +186,7 @@ hpeps_status hpeps_einsumsvd(hpeps_ctx* ctx, hpeps_dtype dtype, const char* subs
     check_opts(opts);
     const bool cplx = is_cplx(dtype);
     HP_REQUIRE(U && R, HPEPS_ERR_INVALID_ARG, "null output");
-    HP_REQUIRE(absorb >= HPEPS_ABSORB_CARRY && absorb <= HPEPS_ABSORB_NONE, HPEPS_ERR_INVALID_ARG,
+    HP_REQUIRE(absorb >= HPEPS_ABSORB_CARRY && absorb <= HPEPS_ABSORB_SQRT, HPEPS_ERR_INVALID_ARG,
                "bad absorb mode");
     HP_REQUIRE(absorb != HPEPS_ABSORB_CARRY || log_scale, HPEPS_ERR_INVALID_ARG,
                "the CARRY mode needs log_scale");
@@ -217,7 +217,7 @@ hpeps_status hpeps_einsumsvd_zipup(hpeps_ctx* ctx, int64_t batch, hpeps_dtype dt
     const bool cplx = is_cplx(dtype);
     HP_REQUIRE(dims && V && S && T && U && sigma && R, HPEPS_ERR_INVALID_ARG, "null argument");
     HP_REQUIRE(batch >= 1 && batch < 65536, HPEPS_ERR_INVALID_ARG, "batch out of range");
-    HP_REQUIRE(absorb >= HPEPS_ABSORB_CARRY && absorb <= HPEPS_ABSORB_NONE, HPEPS_ERR_INVALID_ARG,
+    HP_REQUIRE(absorb >= HPEPS_ABSORB_CARRY && absorb <= HPEPS_ABSORB_SQRT, HPEPS_ERR_INVALID_ARG,
                "bad absorb mode");
     for (int i = 0; i < 9; ++i) HP_REQUIRE(dims[i] >= 1, HPEPS_ERR_SHAPE, "dims must be >= 1");
     hp::ZipDims z;
@@ -242,7 +242,7 @@ hpeps_status hpeps_einsumsvd_pair(hpeps_ctx* ctx, int64_t batch, hpeps_dtype dty
     const bool cplx = is_cplx(dtype);
     HP_REQUIRE(dims && Bl && Br && T1 && T2 && U && sigma && R, HPEPS_ERR_INVALID_ARG, "null argument");
     HP_REQUIRE(batch >= 1 && batch < 65536, HPEPS_ERR_INVALID_ARG, "batch out of range");
-    HP_REQUIRE(absorb >= HPEPS_ABSORB_CARRY && absorb <= HPEPS_ABSORB_NONE, HPEPS_ERR_INVALID_ARG,
+    HP_REQUIRE(absorb >= HPEPS_ABSORB_CARRY && absorb <= HPEPS_ABSORB_SQRT, HPEPS_ERR_INVALID_ARG,
                "bad absorb mode");
     const int64_t m = dims[0], D = dims[1], d = dims[2];
     HP_REQUIRE(m >= 1 && D >= 1 && d >= 1, HPEPS_ERR_SHAPE, "dims must be >= 1");

@@ -466,7 +466,15 @@ void rsvd_finish(Ctx& ctx, bool cplx, int64_t rows, int64_t cols, int64_t k, int
     gemm(ctx, p64, D, c);
     gauge_fix(ctx, cplx, Ut, rows, mp, Z, k, batch);
   }
-  // U = P Z[:, :m']
+  // sigma^1/2 and sigma^-1/2 for the SQRT split
+  double* sq = nullptr;
+  double* isq = nullptr;
+  if (absorb == HPEPS_ABSORB_SQRT) {
+    sq = ctx.ws<double>(nb * k);
+    isq = ctx.ws<double>(nb * k);
+    sqrt_pair(ctx, sig, nb * k, sq, isq);
+  }
+  // U = P Z[:, :m'] (times Sigma or Sigma^1/2 for LEFT / SQRT)
   {
     GemmDesc D;
     D.M = rows; D.K = k; D.N = mp;
@@ -484,6 +492,10 @@ void rsvd_finish(Ctx& ctx, bool cplx, int64_t rows, int64_t cols, int64_t k, int
     c.sB = k * k;
     c.sC = out.nU;
     c.batch = batch;
+    if (absorb == HPEPS_ABSORB_LEFT || absorb == HPEPS_ABSORB_SQRT) {
+      c.nscale = absorb == HPEPS_ABSORB_LEFT ? sig : sq;
+      c.nscale_ld = k;
+    }
     gemm(ctx, p64, D, c);
   }
   // right factor: (B^* Z[:, :m'])^H, scaled per *absorb*
@@ -506,8 +518,8 @@ void rsvd_finish(Ctx& ctx, bool cplx, int64_t rows, int64_t cols, int64_t k, int
     c.batch = batch;
     c.conjC = cplx;
     if (absorb == HPEPS_ABSORB_CARRY) c.scale = isig1;
-    if (absorb == HPEPS_ABSORB_NONE) {
-      c.nscale = isig;
+    if (absorb == HPEPS_ABSORB_NONE || absorb == HPEPS_ABSORB_LEFT || absorb == HPEPS_ABSORB_SQRT) {
+      c.nscale = absorb == HPEPS_ABSORB_SQRT ? isq : isig;
       c.nscale_ld = k;
     }
     gemm(ctx, p64, D, c);

@@ -148,6 +148,8 @@ void copy_scalar(Ctx& ctx, const double* src, bool cplx, double* dst);
 void normalize(Ctx& ctx, bool cplx, void* x, int64_t n, int batch, double* log_scale);
 // x[b][0..nd) *= s[b] (nd doubles per instance)
 void scale_by(Ctx& ctx, double* x, int64_t nd, const double* s, int batch);
+// sq[i] = sqrt(s[i]), isq[i] = 1 / sq[i] (0 where s[i] = 0)
+void sqrt_pair(Ctx& ctx, const double* s, int64_t n, double* sq, double* isq);
 // hooks of the reverse-mode tape (no-ops unless a tape records)
 void tape_gemm(Ctx& ctx, Prec prec, const GemmDesc& d, const GemmCall& c);
 void tape_scale(Ctx& ctx, bool cplx, double* x, int64_t n, const double* s, int batch);

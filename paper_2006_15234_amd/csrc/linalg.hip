@@ -631,6 +631,14 @@ __global__ void gather2d_kernel(const double* srcall, long long sSrc, Map2D m, l
   }
 }
 
+__global__ void sqrt_pair_kernel(const double* s, long long n, double* sq, double* isq) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    const double r = sqrt(fmax(s[i], 0.0));
+    sq[i] = r;
+    isq[i] = r > 0 ? 1.0 / r : 0.0;
+  }
+}
+
 __global__ void f64_to_bf16_kernel(const double* in, __bf16* out, long long n) {
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
     out[i] = (__bf16)in[i];
@@ -990,6 +998,12 @@ void gather2d(Ctx& ctx, bool cplx, const void* src, int64_t sSrc, const IndexMap
     gather2d_kernel<true><<<grid, 256, 0, ctx.stream>>>((const double*)src, sSrc, m, nr, nc, (double*)dst);
   else
     gather2d_kernel<false><<<grid, 256, 0, ctx.stream>>>((const double*)src, sSrc, m, nr, nc, (double*)dst);
+  HP_CHECK_HIP(hipGetLastError());
+}
+
+void sqrt_pair(Ctx& ctx, const double* s, int64_t n, double* sq, double* isq) {
+  if (n <= 0) return;
+  sqrt_pair_kernel<<<std::min<unsigned>(cdiv(n, 256), 1024), 256, 0, ctx.stream>>>(s, n, sq, isq);
   HP_CHECK_HIP(hipGetLastError());
 }
 

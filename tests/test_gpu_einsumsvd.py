@@ -81,7 +81,9 @@ def test_zipup_network_equals_zipup_call(ctx):
 
 
 @pytest.mark.parametrize("cplx,absorb", [(False, hp.ABSORB_NONE), (True, hp.ABSORB_NONE),
-                                         (True, hp.ABSORB_RIGHT), (False, hp.ABSORB_CARRY)])
+                                         (True, hp.ABSORB_RIGHT), (False, hp.ABSORB_CARRY),
+                                         (True, hp.ABSORB_LEFT), (False, hp.ABSORB_SQRT),
+                                         (True, hp.ABSORB_SQRT)])
 def test_random_network_vs_oracle(ctx, cplx, absorb):
     """A[a,b,c] B[c,d,e] conj(C[e,f,a]) read as ((b,d), f), B passed as a transposed view."""
     rng = np.random.default_rng(11)
@@ -100,12 +102,18 @@ def test_random_network_vs_oracle(ctx, cplx, absorb):
                                       rank, q, oracle_sketch(seed, sid, M.shape[1], k))
     s = s.cpu().numpy()
     assert np.max(np.abs(s - so)) <= 1e-10 * so[0]
-    P = _product(U.cpu().numpy(), s, R.cpu().numpy(), absorb, s1=so[0])
-    if absorb == hp.ABSORB_RIGHT:
-        P = U.cpu().numpy().reshape(-1, rank) @ R.cpu().numpy().reshape(rank, -1)
-    assert np.max(np.abs(P - (Uo * so) @ Vho)) <= 1e-10 * so[0] * 10
     Um = U.cpu().numpy().reshape(-1, rank)
-    assert np.max(np.abs(Um.conj().T @ Um - np.eye(rank))) < 1e-11
+    Rm = R.cpu().numpy().reshape(rank, -1)
+    if absorb in (hp.ABSORB_RIGHT, hp.ABSORB_LEFT, hp.ABSORB_SQRT):
+        P = Um @ Rm
+    else:
+        P = _product(U.cpu().numpy(), s, R.cpu().numpy(), absorb, s1=so[0])
+    assert np.max(np.abs(P - (Uo * so) @ Vho)) <= 1e-10 * so[0] * 10
+    # the Gram matrices of the factors show where Sigma went
+    gu = {hp.ABSORB_LEFT: s ** 2, hp.ABSORB_SQRT: s}.get(absorb, np.ones(rank))
+    assert np.max(np.abs(Um.conj().T @ Um - np.diag(gu))) < 1e-11 * max(1.0, so[0] ** 2)
+    if absorb == hp.ABSORB_SQRT:
+        assert np.max(np.abs(Rm @ Rm.conj().T - np.diag(s))) < 1e-11 * max(1.0, so[0])
     if absorb == hp.ABSORB_CARRY:
         assert abs(float(ls.cpu()) - np.log(so[0])) < 1e-12
 
@@ -135,3 +143,22 @@ def test_query(ctx):
     ctx.check(ctx.lib.hpeps_einsumsvd_query(ctx.h, b"abc,cde,efa->bd|f", 3, descs, C.byref(o),
                                             C.byref(r), C.byref(c), C.byref(m)))
     assert (r.value, c.value, m.value) == (30, 26, 26)
+
+
+@pytest.mark.parametrize("absorb", [hp.ABSORB_LEFT, hp.ABSORB_SQRT])
+def test_zipup_left_and_sqrt_absorb(ctx, absorb):
+    """The batched zip-up call with Sigma in the left factor / split as sqrt: the factor
+    product equals the NONE-mode U diag(s) V^* of the same call."""
+    a, x, b, h, u, c, y, g, d = 3, 2, 3, 2, 2, 3, 2, 2, 2
+    rng = np.random.default_rng(21)
+    V = np.stack([_rand(rng, (a, x, x, b, h, h), False) for _ in range(2)])
+    S = np.stack([_rand(rng, (b, u, u, c), False) for _ in range(2)])
+    T = np.stack([_rand(rng, (u, y, h, g, d), False) for _ in range(2)])
+    kw = dict(rank=6, oversample=3, power_iters=1, seed=3, stream_id=6)
+    ops = [_dev(V), _dev(S), _dev(T)]
+    U0, s0, R0 = hp.einsumsvd_zipup(ctx, *ops, absorb=hp.ABSORB_NONE, **kw)
+    U1, s1, R1 = hp.einsumsvd_zipup(ctx, *ops, absorb=absorb, **kw)
+    for i in range(2):
+        ref = _product(U0[i].cpu().numpy(), s0[i].cpu().numpy(), R0[i].cpu().numpy(), hp.ABSORB_NONE)
+        got = U1[i].cpu().numpy().reshape(-1, 6) @ R1[i].cpu().numpy().reshape(6, -1)
+        assert np.max(np.abs(got - ref)) <= 1e-12 * float(s0[i, 0])
