@@ -231,8 +231,9 @@ __device__ __forceinline__ void tile_pos(int e, int& row, int& kk) {
   kk = (rest / (R / 16)) * 4 + grp;
 }
 
+// One work item w (tile, K-split part, instance) of the product.
 template <class TC, bool CPLX, class TIn, class TOut, int WM, int WN, int TM, int TN, int KS>
-__global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
+__device__ __forceinline__ void gemm_item(const GemmArgs& g, int w, unsigned char* smem_raw) {
   constexpr int BM = WM * TM * 16, BN = WN * TN * 16, BK = 16 * KS;
   constexpr int LDK = BK + 16 / (int)sizeof(TC);  // row pitch (elements), odd multiple of 16 B
   constexpr int NA = BM * BK / 256, NB = BN * BK / 256;  // elements each thread loads per K-step
@@ -242,14 +243,10 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
   constexpr int STAGE = NP * (SA + SB);
   using acc_t = typename Mfma<TC>::acc_t;
 
-  extern __shared__ __align__(16) unsigned char smem_raw[];
   TC* sbuf = reinterpret_cast<TC*>(smem_raw);
   int* sKA = reinterpret_cast<int*>(sbuf + 2 * STAGE);
   int* sKB = sKA + (g.tabA ? g.kchunk : 0);
 
-  // work item of this block (see header comment)
-  const int w = (int)(blockIdx.x & 7) * g.per_xcd + (int)(blockIdx.x >> 3);
-  if (w >= g.nwork) return;
   const int tile = w % g.ntotal;
   const int rest = w / g.ntotal;
   const int ks = rest % g.ksplit, b = rest / g.ksplit;
@@ -298,10 +295,10 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
 
   // (row, k) position of element i of this thread in a K-step tile; the
   // mapping follows the contiguous direction of each operand so that global
-  // loads coalesce.  Kept per element: LDS slot, k within the step, and the
-  // row offset (-1 past the last row).
-  int a_lds[NA], a_kk[NA], a_roff[NA];
-  int b_lds[NB], b_kk[NB], b_coff[NB];
+  // loads coalesce.  Kept per element: the LDS slot row * LDK + kk (row and
+  // kk are recovered from it on the slow paths) and the byte offset of
+  // (row, kk) at k = 0.
+  int a_lds[NA], b_lds[NB];
   unsigned a_base[NA], b_base[NB];
 #pragma unroll
   for (int i = 0; i < NA; ++i) {
@@ -314,12 +311,11 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
       tile_pos<BM>(e, row, kk);
     }
     a_lds[i] = row * LDK + kk;
-    a_kk[i] = kk;
     const int m = m0 + row;
-    a_roff[i] = (m < g.M) ? (g.rA_step >= 0 ? m * g.rA_step : g.rA[m]) : -1;
-    // byte offset of (row, kk) at k = 0 on the affine path; rows past M read
-    // row 0 instead (those accumulator rows are never stored)
-    a_base[i] = (unsigned)(max(a_roff[i], 0) + kk * g.a_kstep) * ELT;
+    const int roff = (m < g.M) ? (g.rA_step >= 0 ? m * g.rA_step : g.rA[m]) : 0;
+    // rows past M read row 0 instead (those accumulator rows are never
+    // stored); with K offset tables a_kstep is 0 and this is the row offset
+    a_base[i] = (unsigned)(roff + kk * g.a_kstep) * ELT;
   }
 #pragma unroll
   for (int i = 0; i < NB; ++i) {
@@ -332,11 +328,15 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
       tile_pos<BN>(e, col, kk);
     }
     b_lds[i] = col * LDK + kk;
-    b_kk[i] = kk;
     const int n = n0 + col;
-    b_coff[i] = (n < g.N) ? (g.cB_step >= 0 ? n * g.cB_step : g.cB[n]) : -1;
-    b_base[i] = (unsigned)(max(b_coff[i], 0) + kk * g.b_kstep) * ELT;
+    const int coff = (n < g.N) ? (g.cB_step >= 0 ? n * g.cB_step : g.cB[n]) : 0;
+    b_base[i] = (unsigned)(coff + kk * g.b_kstep) * ELT;
   }
+  // row (or column) of a tile and k within the step, from an LDS slot
+  auto slot_rk = [](int slot, int& r, int& kk) {
+    r = slot / LDK;
+    kk = slot - r * LDK;
+  };
 
   Elem<TC, CPLX> ra[NA], rb[NB];
   // K-step starting at k0.  A full step of an affine operand needs no
@@ -351,17 +351,20 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
     } else if (g.tabA) {
 #pragma unroll
       for (int i = 0; i < NA; ++i) {
-        const int k = k0 + a_kk[i];
+        int row, kk;
+        slot_rk(a_lds[i], row, kk);
+        const int k = k0 + kk;
         const int ko = sKA[k - kbeg];
-        const bool ok = (a_roff[i] >= 0) & (k < kend);
-        ra[i] = buf_load<TC, CPLX, TIn>(rsA, ok ? (unsigned)(a_roff[i] + ko) * ELT : kOut);
+        const bool ok = (m0 + row < g.M) & (k < kend);
+        ra[i] = buf_load<TC, CPLX, TIn>(rsA, ok ? a_base[i] + (unsigned)ko * ELT : kOut);
       }
     } else {
 #pragma unroll
       for (int i = 0; i < NA; ++i) {
-        const int k = k0 + a_kk[i];
-        const bool ok = (a_roff[i] >= 0) & (k < kend);
-        ra[i] = buf_load<TC, CPLX, TIn>(rsA, ok ? (unsigned)(a_roff[i] + k * g.a_kstep) * ELT : kOut);
+        int row, kk;
+        slot_rk(a_lds[i], row, kk);
+        const bool ok = (m0 + row < g.M) & (k0 + kk < kend);
+        ra[i] = buf_load<TC, CPLX, TIn>(rsA, ok ? a_base[i] + (unsigned)(k0 * g.a_kstep) * ELT : kOut);
       }
     }
     if (!g.tabB && full) {
@@ -371,17 +374,20 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
     } else if (g.tabB) {
 #pragma unroll
       for (int i = 0; i < NB; ++i) {
-        const int k = k0 + b_kk[i];
+        int col, kk;
+        slot_rk(b_lds[i], col, kk);
+        const int k = k0 + kk;
         const int ko = sKB[k - kbeg];
-        const bool ok = (b_coff[i] >= 0) & (k < kend);
-        rb[i] = buf_load<TC, CPLX, TIn>(rsB, ok ? (unsigned)(b_coff[i] + ko) * ELT : kOut);
+        const bool ok = (n0 + col < g.N) & (k < kend);
+        rb[i] = buf_load<TC, CPLX, TIn>(rsB, ok ? b_base[i] + (unsigned)ko * ELT : kOut);
       }
     } else {
 #pragma unroll
       for (int i = 0; i < NB; ++i) {
-        const int k = k0 + b_kk[i];
-        const bool ok = (b_coff[i] >= 0) & (k < kend);
-        rb[i] = buf_load<TC, CPLX, TIn>(rsB, ok ? (unsigned)(b_coff[i] + k * g.b_kstep) * ELT : kOut);
+        int col, kk;
+        slot_rk(b_lds[i], col, kk);
+        const bool ok = (n0 + col < g.N) & (k0 + kk < kend);
+        rb[i] = buf_load<TC, CPLX, TIn>(rsB, ok ? b_base[i] + (unsigned)(k0 * g.b_kstep) * ELT : kOut);
       }
     }
   };
@@ -555,6 +561,29 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
         store_out<CPLX, TOut>(Cb, cbase + roff + coff[j], re, im, g.accumulate != 0);
       }
     }
+}
+
+// Occupancy hint (waves per SIMD) for the register allocator: the real FP64
+// shapes below fit that many waves without spilling, which the allocator
+// does not find by itself (128 x 48: 3 instead of 2 waves; 64 x 64: 4
+// instead of 3).  Everything else keeps the default.
+template <class TC, bool CPLX, int WM, int WN, int TM, int TN, int KS>
+constexpr int gemm_waves() {
+  if (!std::is_same<TC, double>::value || CPLX || KS != 1) return 1;
+  if (TM * TN == 6) return 3;
+  if (WM == 2 && WN == 2 && TM == 2 && TN == 2) return 4;
+  return 1;
+}
+
+// Work items are dealt to the XCDs in contiguous ranges: XCD x = blockIdx % 8
+// (consecutive hardware block ids go round-robin over the XCDs) owns items
+// [x per_xcd, (x + 1) per_xcd), one per block.
+template <class TC, bool CPLX, class TIn, class TOut, int WM, int WN, int TM, int TN, int KS>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(gemm_waves<TC, CPLX, WM, WN, TM, TN, KS>())))
+void gemm_kernel(GemmArgs g) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int w = (int)(blockIdx.x & 7) * g.per_xcd + (int)(blockIdx.x >> 3);
+  if (w < g.nwork) gemm_item<TC, CPLX, TIn, TOut, WM, WN, TM, TN, KS>(g, w, smem_raw);
 }
 
 // Sum of split-K partials followed by the epilogue (fixed order: deterministic).

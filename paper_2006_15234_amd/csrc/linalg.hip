@@ -103,30 +103,40 @@ __global__ void sketch_kernel(TO* out, long long nk, uint64_t seed, uint64_t str
 // triangular M with M G = U, i.e. M = D R^-H; M is kept in the strict lower
 // triangle of the same array.  Hence R = D^-1 U and R^-1 = M^H D^-1 without
 // a separate triangular inversion.  Step j reads row j and writes rows > j
-// only: one barrier per step.  Rows are dealt to the wavefronts, columns to
-// the lanes (no integer division in the loop).
+// only: one barrier per step.  The step is latency-bound (k sequential
+// steps of a few LDS round trips), so it is kept short: four wavefronts,
+// lane = column (and column + 64), rows i > j dealt round-robin to the
+// wavefronts, and all the rows of a wavefront loaded in one batch with
+// clamped (always in-range) addresses, updated, and stored under a mask.
 constexpr int kCholThreads = 512;
-constexpr int kCholRows = 4;  // rows per wavefront batch
+constexpr int kCholWaves = kCholThreads / 64;
+// LDS of one instance: the k x k array and one spare slot per lane
+size_t chol_lds_bytes(int k, bool cplx) { return (size_t)(k * k + 64) * (cplx ? 16 : 8); }
 
-template <bool CPLX>
+template <bool CPLX, bool TWO>
 __global__ __launch_bounds__(kCholThreads) void chol_inv_kernel(const double* Gall, long long n_rows,
                                                                  int k, int pass, double* Rinv_all,
                                                                  double* Racc_all, int* flags) {
   using T = typename S<CPLX>::T;
+  constexpr int kB = TWO ? 8 : 6;  // rows per wavefront and LDS round trip (k <= 49 or 113: one)
   extern __shared__ double smem[];
   T* A = reinterpret_cast<T*>(smem);
-  __shared__ double dg[128];
-  __shared__ double red[kCholThreads / 64];
-  const int b = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
-  const int wave = tid >> 6, lane = tid & 63, nw = nt >> 6;
-  const long long kk = (long long)k * k;
-  const T* G = reinterpret_cast<const T*>(Gall) + b * kk;
-  T* Rinv = reinterpret_cast<T*>(Rinv_all) + b * kk;
-  T* Racc = Racc_all ? reinterpret_cast<T*>(Racc_all) + b * kk : nullptr;
+  __shared__ double dg[128], sq[128], rs[128];
+  __shared__ double red[kCholWaves];
+  const int b = blockIdx.x, tid = threadIdx.x;
+  const int wave = tid >> 6, lane = tid & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(wave);  // as a scalar
+  const int kk = k * k;
+  const T* G = reinterpret_cast<const T*>(Gall) + (long long)b * kk;
+  T* Rinv = reinterpret_cast<T*>(Rinv_all) + (long long)b * kk;
+  T* Racc = Racc_all ? reinterpret_cast<T*>(Racc_all) + (long long)b * kk : nullptr;
   int f = flags[b];
 
   auto write_identity = [&]() {
-    for (long long e = tid; e < kk; e += nt) Rinv[e] = (e / k == e % k) ? S<CPLX>::one() : S<CPLX>::zero();
+    for (int e = tid; e < kk; e += kCholThreads) {
+      const int r = e / k;
+      Rinv[e] = (e - r * k == r) ? S<CPLX>::one() : S<CPLX>::zero();
+    }
   };
   if (pass == 3 && !(f & FLAG_THIRD_PASS)) {
     write_identity();
@@ -136,69 +146,77 @@ __global__ __launch_bounds__(kCholThreads) void chol_inv_kernel(const double* Ga
 
   // trace of G for the shift
   double tr = 0.0;
-  for (int i = tid; i < k; i += nt) tr += S<CPLX>::re(G[(long long)i * k + i]);
+  for (int i = tid; i < k; i += kCholThreads) tr += S<CPLX>::re(G[i * k + i]);
   tr = wave_sum(tr);
   if (lane == 0) red[wave] = tr;
   __syncthreads();
   tr = 0.0;
-  for (int w = 0; w < nw; ++w) tr += red[w];
+  for (int w = 0; w < kCholWaves; ++w) tr += red[w];
   // shifted CholeskyQR: s = 11 (n k + k (k + 1)) u ||Y||^2, with ||Y||_2^2 <= trace(G)
   const double shift = 11.0 * ((double)n_rows * k + (double)k * (k + 1)) * 0x1p-53 * tr;
 
+  // the lane's columns (the second one when k > 64: TWO), clamped for reads
+  const int c0 = lane, c1 = lane + 64;
+  const int c0r = min(c0, k - 1), c1r = min(c1, k - 1);
   bool ok = false;
   for (int attempt = 0; attempt < 2; ++attempt) {
     // upper triangle of G (+ shift), zero strict lower triangle (M = I)
-    for (int i = wave; i < k; i += nw)
-      for (int c = lane; c < k; c += 64) {
-        T v = c >= i ? G[(long long)i * k + c] : S<CPLX>::zero();
-        if (attempt == 1 && c == i) {
-          if constexpr (CPLX) v.re += shift; else v += shift;
-        }
-        A[(long long)i * k + c] = v;
+    for (int e = tid; e < kk; e += kCholThreads) {
+      const int i = e / k, c = e - i * k;
+      T v = c >= i ? G[e] : S<CPLX>::zero();
+      if (attempt == 1 && c == i) {
+        if constexpr (CPLX) v.re += shift; else v += shift;
       }
+      A[e] = v;
+    }
     __syncthreads();
     ok = true;
     for (int j = 0; j < k; ++j) {
-      const double d = S<CPLX>::re(A[(long long)j * k + j]);  // same value in every thread
+      const T* Aj = A + j * k;
+      // Every load of the step is issued before the first use (one LDS round
+      // trip): the pivot, row j at the lane's columns, and the first batch of
+      // this wavefront's rows i > j, i % kCholWaves == wave.  A batch has a
+      // fixed length: rows past the end are clamped for reads and their
+      // results go to the lane's spare slot, so the only branch is the
+      // wavefront-uniform one that skips an empty batch.
+      const int r0 = j + 1 + ((wv - (j + 1)) & (kCholWaves - 1));
+      T aji[kB], a0[kB], a1[kB];
+      auto load_batch = [&](int i0) {
+#pragma unroll
+        for (int q = 0; q < kB; ++q) {
+          const int i = min(i0 + kCholWaves * q, k - 1);
+          aji[q] = Aj[i];
+          a0[q] = A[i * k + c0r];
+          if constexpr (TWO) a1[q] = A[i * k + c1r];
+        }
+      };
+      const double d = S<CPLX>::re(Aj[j]);  // same value in every thread
+      T ajc0 = Aj[c0r], ajc1 = TWO ? Aj[c1r] : S<CPLX>::zero();
+      if (r0 < k) load_batch(r0);
+      // row j at the lane's columns; M[j, j] = 1
+      if (c0 == j) ajc0 = S<CPLX>::one();
+      if (c1 == j) ajc1 = S<CPLX>::one();
       if (!(d > 0.0) || !isfinite(d)) {
         ok = false;
         break;
       }
       if (tid == 0) dg[j] = d;
       const double invd = 1.0 / d;
-      const T* Aj = A + (long long)j * k;
-      // row j once per step (the lane's columns c = lane, lane + 64); M[j, j] = 1
-      T ajc[2];
+      // last row that updates column c: every row for an M column (c <= j),
+      // rows up to c for a U column (c >= i), none past the end
+      const int hi0 = c0 >= k ? -1 : (c0 <= j ? k - 1 : c0);
+      const int hi1 = c1 >= k ? -1 : (c1 <= j ? k - 1 : c1);
+      for (int i0 = r0; i0 < k;) {
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const int c = lane + 64 * h;
-        ajc[h] = c < k ? (c == j ? S<CPLX>::one() : Aj[c]) : S<CPLX>::zero();
-      }
-      // rows i > j in batches of kCholRows per wavefront, loads issued together
-      for (int i0 = j + 1 + wave; i0 < k; i0 += nw * kCholRows) {
-        T mu[kCholRows], aic[kCholRows][2];
-#pragma unroll
-        for (int q = 0; q < kCholRows; ++q) {
-          const int i = i0 + q * nw;
+        for (int q = 0; q < kB; ++q) {
+          const int i = i0 + kCholWaves * q;
           // multiplier of row i: conj(A[j, i]) / d_j
-          mu[q] = i < k ? S<CPLX>::scale(S<CPLX>::conj(Aj[i]), invd) : S<CPLX>::zero();
-#pragma unroll
-          for (int h = 0; h < 2; ++h) {
-            const int c = lane + 64 * h;
-            aic[q][h] = (i < k && c < k) ? A[(long long)i * k + c] : S<CPLX>::zero();
-          }
+          const T mu = S<CPLX>::scale(S<CPLX>::conj(aji[q]), invd);
+          A[i <= hi0 ? i * k + c0 : kk + lane] = S<CPLX>::sub(a0[q], S<CPLX>::mul(mu, ajc0));
+          if constexpr (TWO) A[i <= hi1 ? i * k + c1 : kk + lane] = S<CPLX>::sub(a1[q], S<CPLX>::mul(mu, ajc1));
         }
-#pragma unroll
-        for (int q = 0; q < kCholRows; ++q) {
-          const int i = i0 + q * nw;
-#pragma unroll
-          for (int h = 0; h < 2; ++h) {
-            const int c = lane + 64 * h;
-            // upper (c >= i): U; strict lower (c <= j): M; between: untouched
-            if (i < k && c < k && (c >= i || c <= j))
-              A[(long long)i * k + c] = S<CPLX>::sub(aic[q][h], S<CPLX>::mul(mu[q], ajc[h]));
-          }
-        }
+        i0 += kCholWaves * kB;
+        if (i0 < k) load_batch(i0);
       }
       __syncthreads();
     }
@@ -226,38 +244,40 @@ __global__ __launch_bounds__(kCholThreads) void chol_inv_kernel(const double* Ga
     if (tid == 0) flags[b] = f;
     return;
   }
+  for (int i = tid; i < k; i += kCholThreads) {
+    sq[i] = sqrt(dg[i]);
+    rs[i] = 1.0 / sqrt(dg[i]);
+  }
+  __syncthreads();
   // R[i, l] = U[i, l] / sqrt(d_i) (l >= i), R^-1[a, c] = conj(M[c, a]) / sqrt(d_c) (a <= c)
   auto R_at = [&](int i, int l) -> T {
     if (l < i) return S<CPLX>::zero();
-    return l == i ? S<CPLX>::scale(S<CPLX>::one(), sqrt(dg[i]))
-                  : S<CPLX>::scale(A[(long long)i * k + l], 1.0 / sqrt(dg[i]));
+    return l == i ? S<CPLX>::scale(S<CPLX>::one(), sq[i]) : S<CPLX>::scale(A[i * k + l], rs[i]);
   };
   // Racc <- R (pass 1) or R * Racc (later passes; staged through Rinv)
   if (Racc) {
     if (pass == 1) {
-      for (long long e = tid; e < kk; e += nt) Racc[e] = R_at((int)(e / k), (int)(e % k));
+      for (int e = tid; e < kk; e += kCholThreads) {
+        const int i = e / k;
+        Racc[e] = R_at(i, e - i * k);
+      }
     } else {
-      for (long long e = tid; e < kk; e += nt) {
-        const int i = (int)(e / k), l = (int)(e % k);
+      for (int e = tid; e < kk; e += kCholThreads) {
+        const int i = e / k, l = e - i * k;
         T sacc = S<CPLX>::zero();
-        const double inv_ri = 1.0 / sqrt(dg[i]);
-        for (int t = i; t <= l; ++t) {
-          const T rit = t == i ? S<CPLX>::scale(S<CPLX>::one(), sqrt(dg[i]))
-                               : S<CPLX>::scale(A[(long long)i * k + t], inv_ri);
-          sacc = S<CPLX>::add(sacc, S<CPLX>::mul(rit, Racc[(long long)t * k + l]));
-        }
+        for (int t = i; t <= l; ++t) sacc = S<CPLX>::add(sacc, S<CPLX>::mul(R_at(i, t), Racc[t * k + l]));
         Rinv[e] = sacc;
       }
       __syncthreads();
-      for (long long e = tid; e < kk; e += nt) Racc[e] = Rinv[e];
+      for (int e = tid; e < kk; e += kCholThreads) Racc[e] = Rinv[e];
       __syncthreads();
     }
   }
-  for (long long e = tid; e < kk; e += nt) {
-    const int a = (int)(e / k), c = (int)(e % k);
+  for (int e = tid; e < kk; e += kCholThreads) {
+    const int a = e / k, c = e - a * k;
     T v = S<CPLX>::zero();
-    if (c == a) v = S<CPLX>::scale(S<CPLX>::one(), 1.0 / sqrt(dg[a]));
-    else if (c > a) v = S<CPLX>::scale(S<CPLX>::conj(A[(long long)c * k + a]), 1.0 / sqrt(dg[c]));
+    if (c == a) v = S<CPLX>::scale(S<CPLX>::one(), rs[a]);
+    else if (c > a) v = S<CPLX>::scale(S<CPLX>::conj(A[c * k + a]), rs[c]);
     Rinv[e] = v;
   }
   if (tid == 0) flags[b] = f;
@@ -863,19 +883,18 @@ void gram(Ctx& ctx, bool cplx, const void* Y, int64_t n, int64_t k, int batch, d
 
 void chol_inv(Ctx& ctx, bool cplx, const double* G, int64_t n_rows, int64_t k, int batch, int pass,
               double* Rinv, double* Racc, int* flags) {
-  const size_t lds = small_lds_bytes((int)k, cplx);
+  const size_t lds = chol_lds_bytes((int)k, cplx);
   HP_REQUIRE(k <= 128 && lds <= 160 * 1024 - 2048, HPEPS_ERR_UNSUPPORTED,
              "sketch width too large for the small factorizations (k <= 128, complex k <= 88)");
   const int rec = ctx.prof_begin("chol_inv");
-  if (cplx) {
-    HP_CHECK_HIP(hipFuncSetAttribute((const void*)chol_inv_kernel<true>,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    chol_inv_kernel<true><<<batch, kCholThreads, lds, ctx.stream>>>(G, n_rows, (int)k, pass, Rinv, Racc, flags);
-  } else {
-    HP_CHECK_HIP(hipFuncSetAttribute((const void*)chol_inv_kernel<false>,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    chol_inv_kernel<false><<<batch, kCholThreads, lds, ctx.stream>>>(G, n_rows, (int)k, pass, Rinv, Racc, flags);
-  }
+  auto launch = [&](auto kern) {
+    HP_CHECK_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    kern<<<batch, kCholThreads, lds, ctx.stream>>>(G, n_rows, (int)k, pass, Rinv, Racc, flags);
+  };
+  if (cplx)
+    k > 64 ? launch(chol_inv_kernel<true, true>) : launch(chol_inv_kernel<true, false>);
+  else
+    k > 64 ? launch(chol_inv_kernel<false, true>) : launch(chol_inv_kernel<false, false>);
   HP_CHECK_HIP(hipGetLastError());
   ctx.prof_end(rec, (double)batch * k * k * k / 3.0 * (cplx ? 4 : 1), 0.0);
 }
