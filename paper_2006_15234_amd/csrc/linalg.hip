@@ -292,11 +292,10 @@ __global__ __launch_bounds__(kCholThreads) void chol_inv_kernel(const double* Ga
 // per four pairs and one barrier per round.  (Every wavefront instruction
 // occupies its SIMD for four cycles: the rotation arithmetic, identical in
 // all lanes of a group, is shared by four pairs instead of repeated per pair.)
+// ROWS = ceil(k / 16) rows per lane (k <= 16 ROWS).
 constexpr int kJacMaxThreads = 1024;  // 64 pairs (k <= 128) / 4 per wavefront
-constexpr int kJacRows = 8;           // rows per lane: k <= 16 * 8
 
-
-template <bool CPLX>
+template <bool CPLX, int ROWS>
 __global__ __launch_bounds__(kJacMaxThreads) void jacobi_kernel(const double* Racc_all, int k, int max_sweeps,
                                                                 double* Z_all, double* sigma_all,
                                                                 double* inv_sigma_all, double* inv_sigma1,
@@ -309,12 +308,12 @@ __global__ __launch_bounds__(kJacMaxThreads) void jacobi_kernel(const double* Ra
   __shared__ int perm[128];
   __shared__ double nrm[128];
   const int b = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
-  const long long kk = (long long)k * k;
-  const T* R = reinterpret_cast<const T*>(Racc_all) + b * kk;
+  const int kk = k * k;
+  const T* R = reinterpret_cast<const T*>(Racc_all) + (long long)b * kk;
   // column c of K = R^H is the conjugated row c of R
-  for (long long e = tid; e < (long long)n * k; e += nt) {
-    const int c = (int)(e / k), r = (int)(e % k);
-    Kc[e] = (c < k) ? S<CPLX>::conj(R[(long long)c * k + r]) : S<CPLX>::zero();
+  for (int e = tid; e < n * k; e += nt) {
+    const int c = e / k, r = e - c * k;
+    Kc[e] = (c < k) ? S<CPLX>::conj(R[c * k + r]) : S<CPLX>::zero();
   }
   __syncthreads();
   const int wave = tid >> 6, lane = tid & 63, nw = nt >> 6;
@@ -330,15 +329,20 @@ __global__ __launch_bounds__(kJacMaxThreads) void jacobi_kernel(const double* Ra
     if (tid == 0) rotated = 0;
     __syncthreads();
     for (int round = 0; round < n - 1; ++round) {
-      // circle method: position 0 fixed, the others rotate
-      auto at = [&](int pos) { return pos == 0 ? 0 : 1 + (pos - 1 + round) % (n - 1); };
+      // circle method: position 0 fixed, the others rotate ((pos - 1 + round)
+      // mod (n - 1) by one conditional subtraction: both terms are < n - 1)
+      auto at = [&](int pos) {
+        int t = pos - 1 + round;
+        t -= t >= n - 1 ? n - 1 : 0;
+        return pos == 0 ? 0 : 1 + t;
+      };
       const int ca = active ? at(pair) : 0, cb = active ? at(n - 1 - pair) : 0;
-      T* xc = Kc + (long long)ca * k;
-      T* yc = Kc + (long long)cb * k;
-      T x[kJacRows], y[kJacRows];
+      T* xc = Kc + ca * k;
+      T* yc = Kc + cb * k;
+      T x[ROWS], y[ROWS];
       double a2 = 0, b2 = 0, gr = 0, gi = 0;
 #pragma unroll
-      for (int h = 0; h < kJacRows; ++h) {
+      for (int h = 0; h < ROWS; ++h) {
         const int r = li + 16 * h;
         const bool in = active && r < k;
         x[h] = in ? xc[r] : S<CPLX>::zero();
@@ -367,7 +371,7 @@ __global__ __launch_bounds__(kJacMaxThreads) void jacobi_kernel(const double* Ra
         // y~ = conj(e) y with e = gamma / |gamma|, then a real rotation of (x, y~)
         const double er = gr * inv_ga, ei = gi * inv_ga;
 #pragma unroll
-        for (int h = 0; h < kJacRows; ++h) {
+        for (int h = 0; h < ROWS; ++h) {
           const int r = li + 16 * h;
           if (r < k) {
             const T xv = x[h];
@@ -397,7 +401,7 @@ __global__ __launch_bounds__(kJacMaxThreads) void jacobi_kernel(const double* Ra
   // singular values = column norms; sort descending (stable in column index)
   for (int c = wave; c < k; c += nw) {
     double a2 = 0;
-    for (int r = lane; r < k; r += 64) a2 += S<CPLX>::abs2(Kc[(long long)c * k + r]);
+    for (int r = lane; r < k; r += 64) a2 += S<CPLX>::abs2(Kc[c * k + r]);
     a2 = wave_sum(a2);
     if (lane == 0) nrm[c] = sqrt(a2);
   }
@@ -415,12 +419,12 @@ __global__ __launch_bounds__(kJacMaxThreads) void jacobi_kernel(const double* Ra
     }
   }
   __syncthreads();
-  T* Z = reinterpret_cast<T*>(Z_all) + b * kk;
-  for (long long e = tid; e < kk; e += nt) {
-    const int r = (int)(e / k), i = (int)(e % k);
+  T* Z = reinterpret_cast<T*>(Z_all) + (long long)b * kk;
+  for (int e = tid; e < kk; e += nt) {
+    const int r = e / k, i = e - r * k;
     const int c = perm[i];
     const double s = nrm[c];
-    Z[e] = s > 0 ? S<CPLX>::scale(Kc[(long long)c * k + r], 1.0 / s) : S<CPLX>::zero();
+    Z[e] = s > 0 ? S<CPLX>::scale(Kc[c * k + r], 1.0 / s) : S<CPLX>::zero();
   }
   for (int i = tid; i < k; i += nt) {
     const double s = nrm[perm[i]];
@@ -919,17 +923,28 @@ void jacobi_svd(Ctx& ctx, bool cplx, const double* Racc, int64_t k, int batch, i
       }
     }
   } end_rec{ctx, rec};
-  if (cplx) {
-    HP_CHECK_HIP(hipFuncSetAttribute((const void*)jacobi_kernel<true>,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    jacobi_kernel<true><<<batch, threads, lds, ctx.stream>>>(Racc, (int)k, max_sweeps, Z, sigma, inv_sigma,
-                                                                   inv_sigma1, log_scale, stats);
-  } else {
-    HP_CHECK_HIP(hipFuncSetAttribute((const void*)jacobi_kernel<false>,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    jacobi_kernel<false><<<batch, threads, lds, ctx.stream>>>(Racc, (int)k, max_sweeps, Z, sigma, inv_sigma,
-                                                                    inv_sigma1, log_scale, stats);
-  }
+  auto launch = [&](auto kern) {
+    HP_CHECK_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    kern<<<batch, threads, lds, ctx.stream>>>(Racc, (int)k, max_sweeps, Z, sigma, inv_sigma, inv_sigma1, log_scale,
+                                              stats);
+  };
+  auto by_rows = [&](auto cplx_c) {
+    constexpr bool C = decltype(cplx_c)::value;
+    switch ((k + 15) / 16) {
+      case 1: launch(jacobi_kernel<C, 1>); break;
+      case 2: launch(jacobi_kernel<C, 2>); break;
+      case 3: launch(jacobi_kernel<C, 3>); break;
+      case 4: launch(jacobi_kernel<C, 4>); break;
+      case 5: launch(jacobi_kernel<C, 5>); break;
+      case 6: launch(jacobi_kernel<C, 6>); break;
+      case 7: launch(jacobi_kernel<C, 7>); break;
+      default: launch(jacobi_kernel<C, 8>); break;
+    }
+  };
+  if (cplx)
+    by_rows(std::true_type{});
+  else
+    by_rows(std::false_type{});
   HP_CHECK_HIP(hipGetLastError());
 }
 
