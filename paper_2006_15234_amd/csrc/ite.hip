@@ -270,22 +270,25 @@ __global__ __launch_bounds__(kT) void qrsvd_bond_kernel(IteArgs a) {
     if (tid == 0) rot = 0;
     __syncthreads();
     for (int round = 0; round < n - 1; ++round) {
+      // circle positions; (pos - 1 + round) mod (n - 1) by one conditional
+      // subtraction (both terms are below n - 1)
       int ca = nc, cb = nc;
       if (grp < n / 2) {
-        ca = grp == 0 ? 0 : 1 + (grp - 1 + round) % (n - 1);
-        const int pb = n - 1 - grp;
-        cb = 1 + (pb - 1 + round) % (n - 1);
+        int ta = grp - 1 + round;
+        ta -= ta >= n - 1 ? n - 1 : 0;
+        ca = grp == 0 ? 0 : 1 + ta;
+        int tb = n - 2 - grp + round;
+        tb -= tb >= n - 1 ? n - 1 : 0;
+        cb = 1 + tb;
       }
       const bool act = ca < nc && cb < nc;
-      double* x = Th + (long long)(act ? ca : 0) * nr;
-      double* y = Th + (long long)(act ? cb : 0) * nr;
-      double a2 = 0, b2 = 0, gm = 0;
-      if (act)
-        for (int r = gl; r < nr; r += 16) {
-          a2 += x[r] * x[r];
-          b2 += y[r] * y[r];
-          gm += x[r] * y[r];
-        }
+      double* x = Th + (act ? ca : 0) * nr;
+      double* y = Th + (act ? cb : 0) * nr;
+      // rows gl and gl + 16 of the pair (nr, nc <= 32)
+      const bool in0 = act && gl < nr, in1 = act && gl + 16 < nr;
+      const double x0 = in0 ? x[gl] : 0.0, y0 = in0 ? y[gl] : 0.0;
+      const double x1 = in1 ? x[gl + 16] : 0.0, y1 = in1 ? y[gl + 16] : 0.0;
+      double a2 = x0 * x0 + x1 * x1, b2 = y0 * y0 + y1 * y1, gm = x0 * y0 + x1 * y1;
       a2 = row_sum16(a2);
       b2 = row_sum16(b2);
       gm = row_sum16(gm);
@@ -293,17 +296,26 @@ __global__ __launch_bounds__(kT) void qrsvd_bond_kernel(IteArgs a) {
         const double zeta = (b2 - a2) / (2.0 * gm);
         const double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
         const double c = 1.0 / sqrt(1.0 + t * t), sn = c * t;
-        for (int r = gl; r < nr; r += 16) {
-          const double xv = x[r], yv = y[r];
-          x[r] = c * xv - sn * yv;
-          y[r] = sn * xv + c * yv;
+        if (in0) {
+          x[gl] = c * x0 - sn * y0;
+          y[gl] = sn * x0 + c * y0;
         }
-        double* jx = J + (long long)ca * nc;
-        double* jy = J + (long long)cb * nc;
-        for (int r = gl; r < nc; r += 16) {
-          const double xv = jx[r], yv = jy[r];
-          jx[r] = c * xv - sn * yv;
-          jy[r] = sn * xv + c * yv;
+        if (in1) {
+          x[gl + 16] = c * x1 - sn * y1;
+          y[gl + 16] = sn * x1 + c * y1;
+        }
+        double* jx = J + ca * nc;
+        double* jy = J + cb * nc;
+        const bool j0 = gl < nc, j1 = gl + 16 < nc;
+        const double jx0 = j0 ? jx[gl] : 0.0, jy0 = j0 ? jy[gl] : 0.0;
+        const double jx1 = j1 ? jx[gl + 16] : 0.0, jy1 = j1 ? jy[gl + 16] : 0.0;
+        if (j0) {
+          jx[gl] = c * jx0 - sn * jy0;
+          jy[gl] = sn * jx0 + c * jy0;
+        }
+        if (j1) {
+          jx[gl + 16] = c * jx1 - sn * jy1;
+          jy[gl + 16] = sn * jx1 + c * jy1;
         }
         if (gl == 0) rot = 1;
       }
