@@ -107,6 +107,22 @@ def dominant_roofline(kernel, prof):
                 frac=round(a / MFMA_F64_PEAK_TFLOPS, 4))
 
 
+def class_entry(a):
+    """Time of a kernel class in the profiled step, and for GEMM classes the bound and the
+    fraction of it reached (algorithmic flops and bytes of the class, FP64 peaks)."""
+    e = {"ms_per_step": round(a["ms"], 4), "launches": a["launches"]}
+    if a["flops"] > 0 and a["bytes"] > 0 and a["ms"] > 0:
+        t = a["ms"] * 1e-3
+        ridge = MFMA_F64_PEAK_TFLOPS * 1e12 / (HBM_PEAK_GBS * 1e9)
+        if a["flops"] / a["bytes"] < ridge:
+            e.update(bound="hbm", achieved_gbs=round(a["bytes"] / t / 1e9, 1),
+                     frac=round(a["bytes"] / t / 1e9 / HBM_PEAK_GBS, 4))
+        else:
+            e.update(bound="mfma", achieved_tflops=round(a["flops"] / t / 1e12, 2),
+                     frac=round(a["flops"] / t / 1e12 / MFMA_F64_PEAK_TFLOPS, 4))
+    return e
+
+
 def d8_variant(hp, ctx, steps, m=64, D=8, d=2, rank=64, p=8, q=2, batch=16):
     """The same pair einsumsvd at bond 8 and boundary bond 64 (rows = cols = 4096, k = 72),
     FP64, 16 instances: the size class the FP64 MFMA roofline target is stated for."""
@@ -124,6 +140,7 @@ def d8_variant(hp, ctx, steps, m=64, D=8, d=2, rank=64, p=8, q=2, batch=16):
 
     step()
     torch.cuda.synchronize()
+    hp.profile_by_shape(ctx, True)
     hp.profile_start(ctx)
     step()
     agg = hp.profile_read(ctx)
@@ -138,6 +155,7 @@ def d8_variant(hp, ctx, steps, m=64, D=8, d=2, rank=64, p=8, q=2, batch=16):
     ms = (time.perf_counter() - t0) * 1e3 / steps
     prof = hp.profile_read(ctx).get(dominant)
     hp.profile_stop(ctx)
+    hp.profile_by_shape(ctx, False)
     flops = step_flops(m, D, d, rank, p, q) * batch
     achieved = prof["flops"] / (prof["ms"] * 1e-3) / 1e12
     return {"workload": f"pair einsumsvd m={m} D={D} d={d} rank={rank} p={p} q={q}, {batch} instances",
@@ -145,7 +163,7 @@ def d8_variant(hp, ctx, steps, m=64, D=8, d=2, rank=64, p=8, q=2, batch=16):
             "frac_of_fp64_peak": round(flops / (ms * 1e-3) / 1e12 / MFMA_F64_PEAK_TFLOPS, 4),
             "dominant_kernel": dominant, "dominant_achieved_tflops": round(achieved, 3),
             "dominant_frac": round(achieved / MFMA_F64_PEAK_TFLOPS, 4),
-            "kernel_classes": {n: round(a["ms"], 4) for n, a in sorted(agg.items(), key=lambda x: -x[1]["ms"])}}
+            "kernel_classes": {n: class_entry(a) for n, a in sorted(agg.items(), key=lambda x: -x[1]["ms"])}}
 
 
 def c3_flops(n=12, D=10, d=2, m=100, p=8, q=1):
@@ -181,10 +199,12 @@ def c3_norm(hp, n=12, D=10, d=2, m=100, p=8):
         dt = time.perf_counter() - t0
         if ref is None:
             ref = ln
+            hp.profile_by_shape(ctx, True)
             hp.profile_start(ctx)
             hp.peps_norm(ctx, dev, rank=m, oversample=p, power_iters=q, precision=prec)
             agg = hp.profile_read(ctx)
             hp.profile_stop(ctx)
+            hp.profile_by_shape(ctx, False)
             out["f64_kernel_classes"] = {
                 k: {"ms": round(a["ms"], 2), "launches": a["launches"],
                     "tflops": round(a["flops"] / max(a["ms"], 1e-9) / 1e9, 2)}
@@ -340,7 +360,10 @@ def main():
     for _ in range(max(args.warmup, 1)):
         step("f64")
     torch.cuda.synchronize()
-    # find the dominant kernel class with one profiled step
+    # find the dominant kernel class with one profiled step; GEMM classes are
+    # kept apart by product shape (one kernel variant can serve an MFMA-bound
+    # and an HBM-bound product of the same step)
+    hp.profile_by_shape(ctx, True)
     hp.profile_start(ctx)
     step("f64")
     agg = hp.profile_read(ctx)
@@ -357,6 +380,7 @@ def main():
     t1 = time.perf_counter()
     prof = hp.profile_read(ctx).get(dominant)
     hp.profile_stop(ctx)
+    hp.profile_by_shape(ctx, False)
     ms = (t1 - t0) * 1e3 / args.steps
     flops = step_flops() * BATCH
     value = flops / (ms * 1e-3) / 1e9
@@ -415,8 +439,7 @@ def main():
                        "frac_of_bf16_peak": round(flops / (ms16 * 1e-3) / 1e12 / MFMA_BF16_PEAK_TFLOPS, 5),
                        "eps_sigma_vs_f64": eps16},
         "autotune": not args.no_autotune,
-        "kernel_classes": {n: {"ms_per_step": round(a["ms"], 4), "launches": a["launches"]}
-                           for n, a in sorted(agg.items(), key=lambda x: -x[1]["ms"])},
+        "kernel_classes": {n: class_entry(a) for n, a in sorted(agg.items(), key=lambda x: -x[1]["ms"])},
     }
     if args.c4 > 0:
         res["c4_ite"] = c4_ite(hp, args.c4)

@@ -164,6 +164,11 @@ typedef struct {
 } hpeps_profile_entry;
 hpeps_status hpeps_profile_start(hpeps_ctx* ctx, const char* filter);
 hpeps_status hpeps_profile_stop(hpeps_ctx* ctx);
+/* on != 0: the GEMM class names of later launches carry the product's shape,
+ * "gemm_<prec>_<BM>x<BN>k<BK>_M<M>_N<N>_K<K>_b<batch>", so that products of
+ * one kernel variant with different shapes (and bounds) are timed apart;
+ * on = 0 returns to the variant names. */
+hpeps_status hpeps_profile_by_shape(hpeps_ctx* ctx, int32_t on);
 hpeps_status hpeps_profile_read(hpeps_ctx* ctx, int32_t max_entries, hpeps_profile_entry* out,
                                 int32_t* n_out);
 

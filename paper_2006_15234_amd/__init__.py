@@ -15,6 +15,6 @@ from .api import (  # noqa: F401
     peps_norm, boundary_contract_row, peps_energy, peps_norm_backward, peps_energy_backward,
     peps_energy_autograd,
     apply_two_site_gate, ItePlan, get_info, sketch, make_opts, profile_start, profile_stop,
-    profile_read, autotune_enable, autotune_export, autotune_import, autotune_save,
+    profile_read, profile_by_shape, autotune_enable, autotune_export, autotune_import, autotune_save,
     autotune_load,
 )

@@ -70,6 +70,7 @@ _SIGS = {
     "hpeps_autotune_import": (C.c_int, [_P, C.c_char_p]),
     "hpeps_profile_start": (C.c_int, [_P, C.c_char_p]),
     "hpeps_profile_stop": (C.c_int, [_P]),
+    "hpeps_profile_by_shape": (C.c_int, [_P, C.c_int32]),
     "hpeps_profile_read": (C.c_int, [_P, C.c_int32, C.c_void_p, C.POINTER(C.c_int32)]),
     "hpeps_sketch": (C.c_int, [_P, C.c_int, C.c_int64, C.c_int64, C.c_int64, C.c_uint64,
                                C.c_uint64, _P]),

@@ -239,6 +239,11 @@ def profile_stop(ctx):
     ctx.check(ctx.lib.hpeps_profile_stop(ctx.h))
 
 
+def profile_by_shape(ctx, on=True):
+    """GEMM class names with the product's M, N, K and batch (see hpeps_profile_by_shape)."""
+    ctx.check(ctx.lib.hpeps_profile_by_shape(ctx.h, 1 if on else 0))
+
+
 def profile_read(ctx):
     """Synchronises and returns {class: dict(launches, ms, flops, bytes)}; clears."""
     buf = (ProfileEntry * 128)()

@@ -139,6 +139,12 @@ hpeps_status hpeps_profile_start(hpeps_ctx* ctx, const char* filter) {
   return HPEPS_OK;
 }
 
+hpeps_status hpeps_profile_by_shape(hpeps_ctx* ctx, int32_t on) {
+  if (!ctx) return HPEPS_ERR_INVALID_ARG;
+  ctx->impl->prof_shapes = on != 0;
+  return HPEPS_OK;
+}
+
 hpeps_status hpeps_profile_stop(hpeps_ctx* ctx) {
   if (!ctx) return HPEPS_ERR_INVALID_ARG;
   ctx->impl->prof_on = false;

@@ -1026,7 +1026,10 @@ void gemm(Ctx& ctx, Prec prec, const GemmDesc& d, const GemmCall& c) {
                              (prec == Prec::F32 && !c.out_f64 ? "o32" : "") +
                              (prec == Prec::BF16 && !c.out_f64 ? "o16" : "") + "_" +
                              std::to_string(cf.BM()) + "x" + std::to_string(cf.BN()) + "k" +
-                             std::to_string(16 * p.ks);
+                             std::to_string(16 * p.ks) +
+                             (ctx.prof_shapes ? "_M" + std::to_string(d.M) + "_N" + std::to_string(d.N) + "_K" +
+                                                    std::to_string(d.K) + "_b" + std::to_string(c.batch)
+                                              : std::string());
     rec = ctx.prof_begin(name);
   }
   run_plan(ctx, prec, d, c, a, p);

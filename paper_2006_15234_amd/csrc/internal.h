@@ -219,6 +219,7 @@ class Ctx {
   // profiling is on, launches whose class name contains `prof_filter` (all
   // when empty) are bracketed by two events; prof_read aggregates per class.
   bool prof_on = false;
+  bool prof_shapes = false;  // GEMM class names carry the product's M, N, K and batch
   std::string prof_filter;
   int prof_begin(const std::string& cls);            // -1 when not recorded
   void prof_end(int rec, double flops, double bytes);

@@ -55,6 +55,37 @@ def test_gemm(ctx, cplx, shape, trans):
         assert np.max(np.abs(out[b] - ref)) <= 1e-13 * max(1.0, np.abs(ref).max()) * np.sqrt(K)
 
 
+def test_profile_by_shape(ctx):
+    """Live timing keeps GEMM classes apart by product shape when asked to, and counts the
+    algorithmic work of each product (2 M N K flops per instance)."""
+    rng = np.random.default_rng(5)
+    B = 3
+    shapes = [(40, 70, 9), (33, 20, 50)]
+    bufs = []
+    for M, N, K in shapes:
+        bufs.append((_dev(rng.standard_normal((B, M, K))), _dev(rng.standard_normal((B, K, N))),
+                     torch.zeros((B, M, N), dtype=torch.float64, device="cuda")))
+    ctx.sync_stream()
+    for by_shape in (True, False):
+        hp.profile_by_shape(ctx, by_shape)
+        hp.profile_start(ctx, "gemm_f64")
+        for (M, N, K), (dA, dB, dC) in zip(shapes, bufs):
+            ctx.check(ctx.lib.hpeps_test_gemm(ctx.h, hp.F64, B, M, N, K, 0, _p(dA), _p(dB), _p(dC)))
+        agg = hp.profile_read(ctx)
+        hp.profile_stop(ctx)
+        if by_shape:
+            for M, N, K in shapes:
+                names = [n for n in agg if n.endswith(f"_M{M}_N{N}_K{K}_b{B}")]
+                assert len(names) == 1, agg.keys()
+                a = agg[names[0]]
+                assert a["launches"] == 1 and a["ms"] > 0
+                assert a["flops"] == pytest.approx(2.0 * M * N * K * B)
+        else:
+            assert all("_M" not in n for n in agg)
+            assert sum(a["launches"] for a in agg.values()) == len(shapes)
+    hp.profile_by_shape(ctx, False)
+
+
 @pytest.mark.parametrize("cplx", [False, True])
 @pytest.mark.parametrize("nk", [(8, 8), (100, 7), (1296, 44), (5000, 108), (300, 128)])
 def test_orthogonalize(ctx, cplx, nk):
