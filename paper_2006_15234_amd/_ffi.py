@@ -106,6 +106,7 @@ _SIGS = {
     # include/hpeps_testing.h
     "hpeps_test_gemm_variant": (C.c_int, [_P, C.c_int32, C.c_int32, C.c_int32]),
     "hpeps_test_zip_order": (C.c_int, [_P, C.c_int32]),
+    "hpeps_test_gemm_smallk": (C.c_int, [_P, C.c_int32]),
     "hpeps_test_gemm": (C.c_int, [_P, C.c_int, C.c_int64, C.c_int64, C.c_int64, C.c_int64,
                                   C.c_int32, _P, _P, _P]),
     "hpeps_test_orthogonalize": (C.c_int, [_P, C.c_int, C.c_int64, C.c_int64, C.c_int64, _P, _P]),

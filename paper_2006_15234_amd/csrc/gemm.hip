@@ -586,6 +586,113 @@ void gemm_kernel(GemmArgs g) {
   if (w < g.nwork) gemm_item<TC, CPLX, TIn, TOut, WM, WN, TM, TN, KS>(g, w, smem_raw);
 }
 
+// Products with a short reduction (K <= 16) and wide output rows (real,
+// N >= 256, C columns in contiguous runs of 16 bytes) are bound by writing C: a
+// K-deep MFMA step would be mostly padding, and the tile epilogue stores
+// 8-byte pieces.  Here each thread owns VN consecutive columns (8 or 16
+// bytes of C), holds their K values of B in registers, and sweeps kSkRows
+// rows whose K values of A sit in LDS, so every row is one vector store per
+// thread.  Work items (row group, column chunk,
+// instance) are dealt to the XCDs as in gemm_kernel.
+constexpr int kSkRows = 8;  // rows per work item
+
+// columns per thread: 16 bytes of FP64 or FP32 output, 8 bytes of BF16 output
+// (the sketch width k, the fastest output leg, is then a multiple of 4)
+template <class T>
+struct SkCols;
+template <>
+struct SkCols<double> {
+  static constexpr int n = 2;
+};
+template <>
+struct SkCols<float> {
+  static constexpr int n = 4;
+};
+template <>
+struct SkCols<__bf16> {
+  static constexpr int n = 4;
+};
+
+template <class TIn, class TC, class TOut, int KMAX>
+__global__ __launch_bounds__(256) void smallk_kernel(GemmArgs g, int nchunks, int mgroups) {
+  constexpr int VN = SkCols<TOut>::n;
+  constexpr int VB = VN * (int)sizeof(TOut);  // bytes per store
+  __shared__ TC sA[kSkRows * KMAX];
+  const int w = (int)(blockIdx.x & 7) * g.per_xcd + (int)(blockIdx.x >> 3);
+  if (w >= g.nwork) return;
+  const int chunk = w % nchunks, rest = w / nchunks;
+  const int mg = rest % mgroups, b = rest / mgroups;
+  const int m0 = mg * kSkRows, tid = threadIdx.x;
+  const TIn* A = reinterpret_cast<const TIn*>(g.A) + (long long)b * g.sA;
+  const TIn* B = reinterpret_cast<const TIn*>(g.B) + (long long)b * g.sB;
+  // A[m0 .. m0 + kSkRows) x K (zero past the ends)
+  for (int e = tid; e < kSkRows * KMAX; e += 256) {
+    const int r = e / KMAX, k = e - r * KMAX, m = m0 + r;
+    TC v = (TC)0;
+    if (m < g.M && k < g.K) {
+      const int ro = g.rA_step >= 0 ? m * g.rA_step : g.rA[m];
+      const int ko = g.tabA ? g.cA[k] : k * g.a_kstep;
+      v = (TC)A[ro + ko];
+    }
+    sA[e] = v;
+  }
+  // B at this thread's columns, all k
+  const int n0 = (chunk * 256 + tid) * VN;
+  TC bv[KMAX][VN];
+  double cs[VN];
+  const double sb = g.alpha * (g.scale ? g.scale[b] : 1.0);
+#pragma unroll
+  for (int v = 0; v < VN; ++v) {
+    const int n = n0 + v;
+    const bool in = n < g.N;
+    const int co = in ? (g.cB_step >= 0 ? n * g.cB_step : g.cB[n]) : 0;
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k) {
+      const int ko = k < g.K ? (g.tabB ? g.rB[k] : k * g.b_kstep) : 0;
+      bv[k][v] = (in && k < g.K) ? (TC)B[ko + co] : (TC)0;
+    }
+    cs[v] = (g.nscale && in) ? sb * g.nscale[(long long)b * g.nscale_ld + n] : sb;
+  }
+  __syncthreads();
+  TOut* C = reinterpret_cast<TOut*>(g.C) + (long long)b * g.sC;
+  if (n0 >= g.N) return;
+  // the VN columns are contiguous in C (checked on the host): one offset
+  const bool full = n0 + VN <= g.N;
+  const int co = g.cC_step >= 0 ? n0 * g.cC_step : g.cC[n0];
+  for (int r = 0; r < kSkRows; ++r) {
+    const int m = m0 + r;
+    if (m >= g.M) break;
+    TC acc[VN];
+#pragma unroll
+    for (int v = 0; v < VN; ++v) acc[v] = (TC)0;
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k) {
+      const TC a = sA[r * KMAX + k];
+#pragma unroll
+      for (int v = 0; v < VN; ++v) acc[v] += a * bv[k][v];
+    }
+    const long long off = (long long)(g.rC_step >= 0 ? m * g.rC_step : g.rC[m]) + co;
+    TOut o[VN];
+    if (full && (((long long)b * g.sC + off) % VN) == 0) {
+      if (g.accumulate) __builtin_memcpy(o, C + off, VB);
+#pragma unroll
+      for (int v = 0; v < VN; ++v) {
+        const double x = (double)acc[v] * cs[v] + (g.accumulate ? (double)o[v] : 0.0);
+        o[v] = sizeof(TOut) == 8 ? (TOut)x : (TOut)(float)x;
+      }
+      __builtin_memcpy(C + off, o, VB);
+    } else {
+#pragma unroll
+      for (int v = 0; v < VN; ++v) {
+        if (n0 + v >= g.N) break;
+        double x = (double)acc[v] * cs[v];
+        if (g.accumulate) x += (double)C[off + v];
+        C[off + v] = sizeof(TOut) == 8 ? (TOut)x : (TOut)(float)x;
+      }
+    }
+  }
+}
+
 // Sum of split-K partials followed by the epilogue (fixed order: deterministic).
 template <bool CPLX, class TOut>
 __global__ void splitk_reduce_kernel(GemmArgs g, int batch) {
@@ -857,6 +964,66 @@ void run_plan(Ctx& ctx, Prec prec, const GemmDesc& d, const GemmCall& c, GemmArg
   HP_CHECK_HIP(hipGetLastError());
 }
 
+// True when the column index map of C runs through memory in contiguous
+// groups of vn: its fastest mode has unit stride and a multiple of vn values.
+bool contiguous_runs(const IndexMap& m, int vn) {
+  for (int i = m.n - 1; i >= 0; --i)
+    if (m.dim[i] > 1) return m.stride[i] == 1 && m.dim[i] % vn == 0;
+  return false;
+}
+
+// Enqueues the short-reduction kernel (see smallk_kernel).
+void run_smallk(Ctx& ctx, Prec prec, const GemmDesc& d, const GemmCall& c, GemmArgs a) {
+  const int vn = prec == Prec::F64 || c.out_f64 ? 2 : 4;
+  const int64_t nchunks = cdiv(d.N, 256 * vn), mgroups = cdiv(d.M, kSkRows);
+  const int64_t nwork = nchunks * mgroups * c.batch;
+  HP_REQUIRE(nwork < (1LL << 30), HPEPS_ERR_UNSUPPORTED, "gemm launch too large");
+  a.nwork = (int)nwork;
+  const unsigned grid = (unsigned)((nwork + 7) / 8) * 8u;
+  a.per_xcd = (int)(grid / 8);
+  a.ksplit = 1;
+  int rec = -1;
+  if (ctx.prof_on) {
+    static const char* pn[] = {"f64", "c128", "f32", "bf16"};
+    std::string name = std::string("gemm_") + pn[(int)prec] + (prec == Prec::F32 && !c.out_f64 ? "o32" : "") +
+                       (prec == Prec::BF16 && !c.out_f64 ? "o16" : "") + "_smallk";
+    if (ctx.prof_shapes)
+      name += "_M" + std::to_string(d.M) + "_N" + std::to_string(d.N) + "_K" + std::to_string(d.K) + "_b" +
+              std::to_string(c.batch);
+    rec = ctx.prof_begin(name);
+  }
+  hipStream_t st = ctx.stream;
+  const int nc = (int)nchunks, mgr = (int)mgroups;
+  auto go = [&](auto kern) { kern<<<grid, 256, 0, st>>>(a, nc, mgr); };
+  const bool k8 = d.K <= 8;
+  switch (prec) {
+    case Prec::F64:
+      k8 ? go(smallk_kernel<double, double, double, 8>) : go(smallk_kernel<double, double, double, 16>);
+      break;
+    case Prec::F32:
+      if (c.out_f64)
+        k8 ? go(smallk_kernel<float, float, double, 8>) : go(smallk_kernel<float, float, double, 16>);
+      else
+        k8 ? go(smallk_kernel<float, float, float, 8>) : go(smallk_kernel<float, float, float, 16>);
+      break;
+    case Prec::BF16:
+      if (c.out_f64)
+        k8 ? go(smallk_kernel<__bf16, float, double, 8>) : go(smallk_kernel<__bf16, float, double, 16>);
+      else
+        k8 ? go(smallk_kernel<__bf16, float, __bf16, 8>) : go(smallk_kernel<__bf16, float, __bf16, 16>);
+      break;
+    default:
+      throw Error{HPEPS_ERR_UNSUPPORTED, "short-reduction kernel: real products only"};
+  }
+  HP_CHECK_HIP(hipGetLastError());
+  if (rec >= 0) {
+    const double elt = prec == Prec::F32 ? 4 : prec == Prec::BF16 ? 2 : 8;
+    const double eout = c.out_f64 || prec == Prec::F64 ? 8 : elt;
+    ctx.prof_end(rec, 2.0 * (double)d.M * d.N * d.K * c.batch,
+                 ((double)d.M * d.K * elt + (double)d.K * d.N * elt + (double)d.M * d.N * eout) * c.batch);
+  }
+}
+
 std::string tune_key(Prec prec, const GemmDesc& d, const GemmCall& c, const GemmArgs& a) {
   char buf[160];
   snprintf(buf, sizeof(buf), "%s_M%lld_N%lld_K%lld_b%d_a%d%d_b%d%d",
@@ -1004,6 +1171,14 @@ void gemm(Ctx& ctx, Prec prec, const GemmDesc& d, const GemmCall& c) {
   a.tabB = affB ? 0 : 1;
   a.a_kstep = affA ? (int)stepA : 0;
   a.b_kstep = affB ? (int)stepB : 0;
+
+  // short reductions with wide contiguous output rows: the store-bound kernel
+  if (!cplx && !c.copy_if_zero && ctx.smallk && ctx.gemm_force.cfg < 0 && d.K <= 16 && d.N >= 256 &&
+      reinterpret_cast<uintptr_t>(c.C) % 16 == 0 &&
+      contiguous_runs(d.Cn, prec == Prec::F64 || c.out_f64 ? 2 : 4)) {
+    run_smallk(ctx, prec, d, c, a);
+    return;
+  }
 
   // launch variant: forced, tuned, tuned now, or the heuristic
   GemmVariant v = ctx.gemm_force;

@@ -235,6 +235,7 @@ class Ctx {
   // (when on, the first product of a new key times every variant and keeps
   // the fastest; that call synchronises the stream)
   GemmVariant gemm_force;
+  bool smallk = true;  // short reductions (K <= 16, N >= 256) on the store-bound kernel
   bool autotune = false;
   std::map<std::string, GemmVariant> gemm_tuned;
 

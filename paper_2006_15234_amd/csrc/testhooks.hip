@@ -111,6 +111,12 @@ hpeps_status hpeps_test_zip_order(hpeps_ctx* ctx, int32_t order) {
   return HPEPS_OK;
 }
 
+hpeps_status hpeps_test_gemm_smallk(hpeps_ctx* ctx, int32_t on) {
+  if (!ctx) return HPEPS_ERR_INVALID_ARG;
+  ctx->impl->smallk = on != 0;
+  return HPEPS_OK;
+}
+
 hpeps_status hpeps_test_gemm_variant(hpeps_ctx* ctx, int32_t tile, int32_t kstep, int32_t split) {
   if (!ctx || split < 0) return HPEPS_ERR_INVALID_ARG;
   ctx->impl->gemm_force = hp::GemmVariant{tile < 0 ? -1 : tile, kstep, split};

@@ -55,6 +55,31 @@ def test_gemm(ctx, cplx, shape, trans):
         assert np.max(np.abs(out[b] - ref)) <= 1e-13 * max(1.0, np.abs(ref).max()) * np.sqrt(K)
 
 
+@pytest.mark.parametrize("smallk", [1, 0])
+@pytest.mark.parametrize("shape", [(17, 300, 5), (8, 1030, 16), (40, 513, 1), (72, 9504, 6), (9, 777, 12)])
+@pytest.mark.parametrize("trans", [0, 1])
+def test_gemm_short_reduction(ctx, smallk, shape, trans):
+    """Real products with K <= 16 and N >= 256 (the store-bound kernel, and with it switched
+    off the MFMA tile kernel): ragged rows and column chunks, K = 1 and K past 8."""
+    M, N, K = shape
+    rng = np.random.default_rng(M * 7 + N + K)
+    B = 3
+    A = rng.standard_normal((B, K, M) if trans else (B, M, K))
+    Bm = rng.standard_normal((B, K, N))
+    dA, dB = _dev(A), _dev(Bm)
+    dC = torch.full((B, M, N), np.nan, dtype=torch.float64, device="cuda")
+    ctx.sync_stream()
+    ctx.check(ctx.lib.hpeps_test_gemm_smallk(ctx.h, smallk))
+    try:
+        ctx.check(ctx.lib.hpeps_test_gemm(ctx.h, hp.F64, B, M, N, K, trans, _p(dA), _p(dB), _p(dC)))
+    finally:
+        ctx.check(ctx.lib.hpeps_test_gemm_smallk(ctx.h, 1))
+    out = dC.cpu().numpy()
+    for b in range(B):
+        ref = (A[b].T if trans else A[b]) @ Bm[b]
+        assert np.max(np.abs(out[b] - ref)) <= 1e-14 * max(1.0, np.abs(ref).max()) * K
+
+
 def test_profile_by_shape(ctx):
     """Live timing keeps GEMM classes apart by product shape when asked to, and counts the
     algorithmic work of each product (2 M N K flops per instance)."""
