@@ -39,6 +39,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <initializer_list>
 #include <tuple>
 #include <type_traits>
 
@@ -693,6 +694,90 @@ __global__ __launch_bounds__(256) void smallk_kernel(GemmArgs g, int nchunks, in
   }
 }
 
+// Products with few rows (M <= 8) and a moderate reduction (K <= 256) over
+// wide operands (real, N >= 256) are bound by reading B: a 16-row MFMA tile
+// would idle at least half of its rows while the tile loads wait.  Here each thread
+// owns VN consecutive columns, streams their K values of B with one vector
+// load per k (8 k in flight), and keeps all M rows of the result in
+// registers; A (M x K) sits in LDS.  The host checks that every vector load
+// and store is aligned (unit-stride fastest leg with a multiple of VN
+// values, all other strides multiples of VN).
+constexpr int kSmMaxK = 256;
+
+template <class TIn, class TC, class TOut, int MMAX>
+__global__ __launch_bounds__(256) void smallm_kernel(GemmArgs g, int nchunks) {
+  constexpr int VN = 16 / (int)sizeof(TIn) < 4 ? 16 / (int)sizeof(TIn) : 4;  // 2 doubles, 4 floats or bf16
+  __shared__ TC sA[MMAX * kSmMaxK];
+  const int w = (int)(blockIdx.x & 7) * g.per_xcd + (int)(blockIdx.x >> 3);
+  if (w >= g.nwork) return;
+  const int chunk = w % nchunks, b = w / nchunks, tid = threadIdx.x;
+  const TIn* A = reinterpret_cast<const TIn*>(g.A) + (long long)b * g.sA;
+  const TIn* B = reinterpret_cast<const TIn*>(g.B) + (long long)b * g.sB;
+  for (int e = tid; e < MMAX * g.K; e += 256) {
+    const int m = e / g.K, k = e - m * g.K;
+    TC v = (TC)0;
+    if (m < g.M) {
+      const int ro = g.rA_step >= 0 ? m * g.rA_step : g.rA[m];
+      const int ko = g.tabA ? g.cA[k] : k * g.a_kstep;
+      v = (TC)A[ro + ko];
+    }
+    sA[e] = v;
+  }
+  __syncthreads();
+  const int n0 = (chunk * 256 + tid) * VN;
+  if (n0 >= g.N) return;
+  const int co = g.cB_step >= 0 ? n0 * g.cB_step : g.cB[n0];
+  TC acc[MMAX][VN];
+#pragma unroll
+  for (int m = 0; m < MMAX; ++m)
+#pragma unroll
+    for (int v = 0; v < VN; ++v) acc[m][v] = (TC)0;
+  auto load = [&](int k, TIn* x) {
+    const int ko = g.tabB ? g.rB[k] : k * g.b_kstep;
+    __builtin_memcpy(x, B + ko + co, VN * sizeof(TIn));
+  };
+  auto fma_k = [&](int k, const TIn* x) {
+#pragma unroll
+    for (int m = 0; m < MMAX; ++m) {
+      const TC a = sA[m * g.K + k];
+#pragma unroll
+      for (int v = 0; v < VN; ++v) acc[m][v] += a * (TC)x[v];
+    }
+  };
+  int k = 0;
+  for (; k + 8 <= g.K; k += 8) {
+    TIn x[8][VN];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) load(k + u, x[u]);
+#pragma unroll
+    for (int u = 0; u < 8; ++u) fma_k(k + u, x[u]);
+  }
+  for (; k < g.K; ++k) {
+    TIn x[VN];
+    load(k, x);
+    fma_k(k, x);
+  }
+  const double sb = g.alpha * (g.scale ? g.scale[b] : 1.0);
+  double cs[VN];
+#pragma unroll
+  for (int v = 0; v < VN; ++v) cs[v] = g.nscale ? sb * g.nscale[(long long)b * g.nscale_ld + n0 + v] : sb;
+  TOut* C = reinterpret_cast<TOut*>(g.C) + (long long)b * g.sC;
+  const int cco = g.cC_step >= 0 ? n0 * g.cC_step : g.cC[n0];
+#pragma unroll
+  for (int m = 0; m < MMAX; ++m) {
+    if (m >= g.M) continue;
+    TOut* c = C + (g.rC_step >= 0 ? m * g.rC_step : g.rC[m]) + cco;
+    TOut o[VN];
+    if (g.accumulate) __builtin_memcpy(o, c, VN * sizeof(TOut));
+#pragma unroll
+    for (int v = 0; v < VN; ++v) {
+      const double x = (double)acc[m][v] * cs[v] + (g.accumulate ? (double)o[v] : 0.0);
+      o[v] = sizeof(TOut) == 8 ? (TOut)x : (TOut)(float)x;
+    }
+    __builtin_memcpy(c, o, VN * sizeof(TOut));
+  }
+}
+
 // Sum of split-K partials followed by the epilogue (fixed order: deterministic).
 template <bool CPLX, class TOut>
 __global__ void splitk_reduce_kernel(GemmArgs g, int batch) {
@@ -1024,6 +1109,69 @@ void run_smallk(Ctx& ctx, Prec prec, const GemmDesc& d, const GemmCall& c, GemmA
   }
 }
 
+// True when every vn-group of consecutive columns of the map is contiguous
+// and starts at a multiple of vn elements: the fastest mode has unit stride
+// and a multiple of vn values, every other stride of the maps in `others`
+// (and of this map) is a multiple of vn.
+bool vec_aligned(const IndexMap& cols, std::initializer_list<const IndexMap*> others, int64_t inst_stride,
+                 const void* base, int vn, int64_t elt) {
+  if (!contiguous_runs(cols, vn) || inst_stride % vn != 0 || reinterpret_cast<uintptr_t>(base) % (vn * elt) != 0)
+    return false;
+  int last = cols.n - 1;
+  while (last >= 0 && cols.dim[last] == 1) --last;
+  for (int i = 0; i < last; ++i)
+    if (cols.dim[i] > 1 && cols.stride[i] % vn != 0) return false;
+  for (const IndexMap* m : others)
+    for (int i = 0; i < m->n; ++i)
+      if (m->dim[i] > 1 && m->stride[i] % vn != 0) return false;
+  return true;
+}
+
+// Enqueues the few-rows kernel (see smallm_kernel).
+void run_smallm(Ctx& ctx, Prec prec, const GemmDesc& d, const GemmCall& c, GemmArgs a) {
+  const int vn = prec == Prec::F64 ? 2 : 4;
+  const int64_t nchunks = cdiv(d.N, 256 * vn);
+  const int64_t nwork = nchunks * c.batch;
+  HP_REQUIRE(nwork < (1LL << 30), HPEPS_ERR_UNSUPPORTED, "gemm launch too large");
+  a.nwork = (int)nwork;
+  const unsigned grid = (unsigned)((nwork + 7) / 8) * 8u;
+  a.per_xcd = (int)(grid / 8);
+  a.ksplit = 1;
+  int rec = -1;
+  if (ctx.prof_on) {
+    static const char* pn[] = {"f64", "c128", "f32", "bf16"};
+    std::string name = std::string("gemm_") + pn[(int)prec] + (prec == Prec::F32 && !c.out_f64 ? "o32" : "") +
+                       (prec == Prec::BF16 && !c.out_f64 ? "o16" : "") + "_smallm";
+    if (ctx.prof_shapes)
+      name += "_M" + std::to_string(d.M) + "_N" + std::to_string(d.N) + "_K" + std::to_string(d.K) + "_b" +
+              std::to_string(c.batch);
+    rec = ctx.prof_begin(name);
+  }
+  hipStream_t st = ctx.stream;
+  const int nc = (int)nchunks;
+  auto go = [&](auto kern) { kern<<<grid, 256, 0, st>>>(a, nc); };
+  switch (prec) {
+    case Prec::F64:
+      go(smallm_kernel<double, double, double, 8>);
+      break;
+    case Prec::F32:
+      c.out_f64 ? go(smallm_kernel<float, float, double, 8>) : go(smallm_kernel<float, float, float, 8>);
+      break;
+    case Prec::BF16:
+      c.out_f64 ? go(smallm_kernel<__bf16, float, double, 8>) : go(smallm_kernel<__bf16, float, __bf16, 8>);
+      break;
+    default:
+      throw Error{HPEPS_ERR_UNSUPPORTED, "few-rows kernel: real products only"};
+  }
+  HP_CHECK_HIP(hipGetLastError());
+  if (rec >= 0) {
+    const double elt = prec == Prec::F32 ? 4 : prec == Prec::BF16 ? 2 : 8;
+    const double eout = c.out_f64 || prec == Prec::F64 ? 8 : elt;
+    ctx.prof_end(rec, 2.0 * (double)d.M * d.N * d.K * c.batch,
+                 ((double)d.M * d.K * elt + (double)d.K * d.N * elt + (double)d.M * d.N * eout) * c.batch);
+  }
+}
+
 std::string tune_key(Prec prec, const GemmDesc& d, const GemmCall& c, const GemmArgs& a) {
   char buf[160];
   snprintf(buf, sizeof(buf), "%s_M%lld_N%lld_K%lld_b%d_a%d%d_b%d%d",
@@ -1178,6 +1326,17 @@ void gemm(Ctx& ctx, Prec prec, const GemmDesc& d, const GemmCall& c) {
       contiguous_runs(d.Cn, prec == Prec::F64 || c.out_f64 ? 2 : 4)) {
     run_smallk(ctx, prec, d, c, a);
     return;
+  }
+  // few rows over wide operands: the read-bound kernel
+  if (!cplx && !c.copy_if_zero && ctx.smallk && ctx.gemm_force.cfg < 0 && d.M <= 8 && d.N >= 256 &&
+      d.K <= kSmMaxK) {
+    const int vn = prec == Prec::F64 ? 2 : 4;
+    const int64_t ein = prec == Prec::F64 ? 8 : prec == Prec::F32 ? 4 : 2;
+    const int64_t eout = prec == Prec::F64 || c.out_f64 ? 8 : ein;
+    if (vec_aligned(d.Bn, {&d.Bk}, c.sB, c.B, vn, ein) && vec_aligned(d.Cn, {&d.Cm}, c.sC, c.C, vn, eout)) {
+      run_smallm(ctx, prec, d, c, a);
+      return;
+    }
   }
 
   // launch variant: forced, tuned, tuned now, or the heuristic

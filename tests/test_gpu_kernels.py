@@ -56,11 +56,13 @@ def test_gemm(ctx, cplx, shape, trans):
 
 
 @pytest.mark.parametrize("smallk", [1, 0])
-@pytest.mark.parametrize("shape", [(17, 300, 5), (8, 1030, 16), (40, 513, 1), (72, 9504, 6), (9, 777, 12)])
+@pytest.mark.parametrize("shape", [(17, 300, 5), (8, 1030, 16), (40, 513, 1), (72, 9504, 6), (9, 777, 12),
+                                   (6, 9504, 72), (3, 1030, 200), (8, 512, 17), (1, 2050, 9)])
 @pytest.mark.parametrize("trans", [0, 1])
-def test_gemm_short_reduction(ctx, smallk, shape, trans):
-    """Real products with K <= 16 and N >= 256 (the store-bound kernel, and with it switched
-    off the MFMA tile kernel): ragged rows and column chunks, K = 1 and K past 8."""
+def test_gemm_skinny(ctx, smallk, shape, trans):
+    """Real products with K <= 16 or M <= 8 and N >= 256 (the store-bound and the read-bound
+    kernels, and with them switched off the MFMA tile kernel): ragged rows and column chunks,
+    K = 1, K past 8, K not a multiple of the 8-deep load batch, M = 1."""
     M, N, K = shape
     rng = np.random.default_rng(M * 7 + N + K)
     B = 3
