@@ -591,11 +591,11 @@ void gemm_kernel(GemmArgs g) {
 // N >= 256, C columns in contiguous runs of 16 bytes) are bound by writing C: a
 // K-deep MFMA step would be mostly padding, and the tile epilogue stores
 // 8-byte pieces.  Here each thread owns VN consecutive columns (8 or 16
-// bytes of C), holds their K values of B in registers, and sweeps kSkRows
-// rows whose K values of A sit in LDS, so every row is one vector store per
-// thread.  Work items (row group, column chunk,
+// bytes of C), holds their K values of B in registers, and sweeps up to
+// kSkRows rows whose K values of A sit in LDS (B is read once per row group),
+// so every row is one vector store per thread.  Work items (row group, column chunk,
 // instance) are dealt to the XCDs as in gemm_kernel.
-constexpr int kSkRows = 8;  // rows per work item
+constexpr int kSkRows = 128;  // rows per work item (all rows of most products: B is read once)
 
 // columns per thread: 16 bytes of FP64 or FP32 output, 8 bytes of BF16 output
 // (the sketch width k, the fastest output leg, is then a multiple of 4)
