@@ -57,11 +57,11 @@ hpeps_status hpeps_test_gemm_variant(hpeps_ctx* ctx, int32_t tile, int32_t kstep
  * network, two contraction sequences). */
 hpeps_status hpeps_test_zip_order(hpeps_ctx* ctx, int32_t order);
 
-/* on = 0 sends every later real product with wide contiguous rows
- * (N >= 256) and a short reduction (K <= 16) or few rows (M <= 8) to the
- * MFMA tile kernel instead of the store-bound short-reduction kernel or the
- * read-bound few-rows kernel; on != 0 restores the default.  All compute the
- * same product (different summation order). */
+/* on = 0 sends every later real product with a short reduction (K <= 16,
+ * N >= 72) or few rows (M <= 8, N >= 256) and suitably contiguous output
+ * columns to the MFMA tile kernel instead of the store-bound short-reduction
+ * kernel or the read-bound few-rows kernel; on != 0 restores the default.
+ * All compute the same product (different summation order). */
 hpeps_status hpeps_test_gemm_smallk(hpeps_ctx* ctx, int32_t on);
 
 #ifdef __cplusplus

@@ -587,8 +587,8 @@ void gemm_kernel(GemmArgs g) {
   if (w < g.nwork) gemm_item<TC, CPLX, TIn, TOut, WM, WN, TM, TN, KS>(g, w, smem_raw);
 }
 
-// Products with a short reduction (K <= 16) and wide output rows (real,
-// N >= 256, C columns in contiguous runs of 16 bytes) are bound by writing C: a
+// Products with a short reduction (K <= 16; real, N >= 72, C columns in
+// contiguous runs of VN) are bound by writing C: a
 // K-deep MFMA step would be mostly padding, and the tile epilogue stores
 // 8-byte pieces.  Here each thread owns VN consecutive columns (8 or 16
 // bytes of C), holds their K values of B in registers, and sweeps up to
@@ -615,7 +615,7 @@ struct SkCols<__bf16> {
 };
 
 template <class TIn, class TC, class TOut, int KMAX>
-__global__ __launch_bounds__(256) void smallk_kernel(GemmArgs g, int nchunks, int mgroups) {
+__global__ __launch_bounds__(256) void smallk_kernel(GemmArgs g, int nchunks, int mgroups, int gpr) {
   constexpr int VN = SkCols<TOut>::n;
   constexpr int VB = VN * (int)sizeof(TOut);  // bytes per store
   __shared__ TC sA[kSkRows * KMAX];
@@ -626,19 +626,34 @@ __global__ __launch_bounds__(256) void smallk_kernel(GemmArgs g, int nchunks, in
   const int m0 = mg * kSkRows, tid = threadIdx.x;
   const TIn* A = reinterpret_cast<const TIn*>(g.A) + (long long)b * g.sA;
   const TIn* B = reinterpret_cast<const TIn*>(g.B) + (long long)b * g.sB;
-  // A[m0 .. m0 + kSkRows) x K (zero past the ends)
-  for (int e = tid; e < kSkRows * KMAX; e += 256) {
-    const int r = e / KMAX, k = e - r * KMAX, m = m0 + r;
+  // A[m0 .. m0 + kSkRows) x K (zero past the ends); every load is issued
+  // before the first LDS store
+  constexpr int IA = kSkRows * KMAX / 256;
+  TC av[IA];
+#pragma unroll
+  for (int it = 0; it < IA; ++it) {
+    const int e = tid + 256 * it, r = e / KMAX, k = e - r * KMAX, m = m0 + r;
     TC v = (TC)0;
     if (m < g.M && k < g.K) {
       const int ro = g.rA_step >= 0 ? m * g.rA_step : g.rA[m];
       const int ko = g.tabA ? g.cA[k] : k * g.a_kstep;
       v = (TC)A[ro + ko];
     }
-    sA[e] = v;
+    av[it] = v;
   }
+#pragma unroll
+  for (int it = 0; it < IA; ++it) sA[tid + 256 * it] = av[it];
+  // C row offsets of the work item's rows (a gathered map costs one load each)
+  __shared__ int sRC[kSkRows];
+  if (tid < kSkRows) {
+    const int m = m0 + tid;
+    sRC[tid] = m < g.M ? (g.rC_step >= 0 ? m * g.rC_step : g.rC[m]) : 0;
+  }
+  // the thread's column group (gpr groups of VN columns per pass over the
+  // rows; 256 / gpr rows per pass when the rows are narrower than 256 groups)
+  const int rpp = 256 / gpr, grp = tid % gpr, rsub = tid / gpr;
   // B at this thread's columns, all k
-  const int n0 = (chunk * 256 + tid) * VN;
+  const int n0 = (chunk * gpr + grp) * VN;
   TC bv[KMAX][VN];
   double cs[VN];
   const double sb = g.alpha * (g.scale ? g.scale[b] : 1.0);
@@ -656,11 +671,11 @@ __global__ __launch_bounds__(256) void smallk_kernel(GemmArgs g, int nchunks, in
   }
   __syncthreads();
   TOut* C = reinterpret_cast<TOut*>(g.C) + (long long)b * g.sC;
-  if (n0 >= g.N) return;
+  if (n0 >= g.N || rsub >= rpp) return;
   // the VN columns are contiguous in C (checked on the host): one offset
   const bool full = n0 + VN <= g.N;
   const int co = g.cC_step >= 0 ? n0 * g.cC_step : g.cC[n0];
-  for (int r = 0; r < kSkRows; ++r) {
+  for (int r = rsub; r < kSkRows; r += rpp) {
     const int m = m0 + r;
     if (m >= g.M) break;
     TC acc[VN];
@@ -672,7 +687,7 @@ __global__ __launch_bounds__(256) void smallk_kernel(GemmArgs g, int nchunks, in
 #pragma unroll
       for (int v = 0; v < VN; ++v) acc[v] += a * bv[k][v];
     }
-    const long long off = (long long)(g.rC_step >= 0 ? m * g.rC_step : g.rC[m]) + co;
+    const long long off = (long long)sRC[r] + co;
     TOut o[VN];
     if (full && (((long long)b * g.sC + off) % VN) == 0) {
       if (g.accumulate) __builtin_memcpy(o, C + off, VB);
@@ -713,16 +728,23 @@ __global__ __launch_bounds__(256) void smallm_kernel(GemmArgs g, int nchunks) {
   const int chunk = w % nchunks, b = w / nchunks, tid = threadIdx.x;
   const TIn* A = reinterpret_cast<const TIn*>(g.A) + (long long)b * g.sA;
   const TIn* B = reinterpret_cast<const TIn*>(g.B) + (long long)b * g.sB;
-  for (int e = tid; e < MMAX * g.K; e += 256) {
-    const int m = e / g.K, k = e - m * g.K;
+  // A (MMAX x K, zero past M); every load is issued before the first LDS store
+  constexpr int IA = MMAX * kSmMaxK / 256;
+  TC av[IA];
+#pragma unroll
+  for (int it = 0; it < IA; ++it) {
+    const int e = tid + 256 * it, m = e / g.K, k = e - m * g.K;
     TC v = (TC)0;
-    if (m < g.M) {
+    if (e < MMAX * g.K && m < g.M) {
       const int ro = g.rA_step >= 0 ? m * g.rA_step : g.rA[m];
       const int ko = g.tabA ? g.cA[k] : k * g.a_kstep;
       v = (TC)A[ro + ko];
     }
-    sA[e] = v;
+    av[it] = v;
   }
+#pragma unroll
+  for (int it = 0; it < IA; ++it)
+    if (tid + 256 * it < MMAX * g.K) sA[tid + 256 * it] = av[it];
   __syncthreads();
   const int n0 = (chunk * 256 + tid) * VN;
   if (n0 >= g.N) return;
@@ -1060,7 +1082,8 @@ bool contiguous_runs(const IndexMap& m, int vn) {
 // Enqueues the short-reduction kernel (see smallk_kernel).
 void run_smallk(Ctx& ctx, Prec prec, const GemmDesc& d, const GemmCall& c, GemmArgs a) {
   const int vn = prec == Prec::F64 || c.out_f64 ? 2 : 4;
-  const int64_t nchunks = cdiv(d.N, 256 * vn), mgroups = cdiv(d.M, kSkRows);
+  const int gpr = (int)std::min<int64_t>(cdiv(d.N, vn), 256);
+  const int64_t nchunks = cdiv(cdiv(d.N, vn), gpr), mgroups = cdiv(d.M, kSkRows);
   const int64_t nwork = nchunks * mgroups * c.batch;
   HP_REQUIRE(nwork < (1LL << 30), HPEPS_ERR_UNSUPPORTED, "gemm launch too large");
   a.nwork = (int)nwork;
@@ -1079,7 +1102,7 @@ void run_smallk(Ctx& ctx, Prec prec, const GemmDesc& d, const GemmCall& c, GemmA
   }
   hipStream_t st = ctx.stream;
   const int nc = (int)nchunks, mgr = (int)mgroups;
-  auto go = [&](auto kern) { kern<<<grid, 256, 0, st>>>(a, nc, mgr); };
+  auto go = [&](auto kern) { kern<<<grid, 256, 0, st>>>(a, nc, mgr, gpr); };
   const bool k8 = d.K <= 8;
   switch (prec) {
     case Prec::F64:
@@ -1320,8 +1343,9 @@ void gemm(Ctx& ctx, Prec prec, const GemmDesc& d, const GemmCall& c) {
   a.a_kstep = affA ? (int)stepA : 0;
   a.b_kstep = affB ? (int)stepB : 0;
 
-  // short reductions with wide contiguous output rows: the store-bound kernel
-  if (!cplx && !c.copy_if_zero && ctx.smallk && ctx.gemm_force.cfg < 0 && d.K <= 16 && d.N >= 256 &&
+  // short reductions (output columns in contiguous runs): the store-bound
+  // kernel; below ~70 columns the MFMA tiles were measured as fast or faster
+  if (!cplx && !c.copy_if_zero && ctx.smallk && ctx.gemm_force.cfg < 0 && d.K <= 16 && d.N >= 72 &&
       reinterpret_cast<uintptr_t>(c.C) % 16 == 0 &&
       contiguous_runs(d.Cn, prec == Prec::F64 || c.out_f64 ? 2 : 4)) {
     run_smallk(ctx, prec, d, c, a);

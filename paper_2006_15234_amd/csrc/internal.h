@@ -235,7 +235,7 @@ class Ctx {
   // (when on, the first product of a new key times every variant and keeps
   // the fastest; that call synchronises the stream)
   GemmVariant gemm_force;
-  bool smallk = true;  // skinny real products (N >= 256; K <= 16 or M <= 8) on their own kernels
+  bool smallk = true;  // skinny real products (K <= 16, or M <= 8 with N >= 256) on their own kernels
   bool autotune = false;
   std::map<std::string, GemmVariant> gemm_tuned;
 

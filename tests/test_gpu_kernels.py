@@ -57,12 +57,14 @@ def test_gemm(ctx, cplx, shape, trans):
 
 @pytest.mark.parametrize("smallk", [1, 0])
 @pytest.mark.parametrize("shape", [(17, 300, 5), (8, 1030, 16), (40, 513, 1), (72, 9504, 6), (9, 777, 12),
-                                   (6, 9504, 72), (3, 1030, 200), (8, 512, 17), (1, 2050, 9)])
+                                   (6, 9504, 72), (3, 1030, 200), (8, 512, 17), (1, 2050, 9),
+                                   (300, 36, 12), (130, 96, 16), (40, 72, 6), (5, 20, 3), (260, 80, 2)])
 @pytest.mark.parametrize("trans", [0, 1])
 def test_gemm_skinny(ctx, smallk, shape, trans):
-    """Real products with K <= 16 or M <= 8 and N >= 256 (the store-bound and the read-bound
-    kernels, and with them switched off the MFMA tile kernel): ragged rows and column chunks,
-    K = 1, K past 8, K not a multiple of the 8-deep load batch, M = 1."""
+    """Real skinny products: K <= 16 (the store-bound kernel, wide rows and rows narrower than
+    one pass of column groups) and M <= 8 with N >= 256 (the read-bound kernel), and with them
+    switched off the MFMA tile kernel: ragged rows and column chunks, K = 1, K past 8, K not a
+    multiple of the 8-deep load batch, M = 1, more rows than one work item holds."""
     M, N, K = shape
     rng = np.random.default_rng(M * 7 + N + K)
     B = 3
