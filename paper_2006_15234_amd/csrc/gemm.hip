@@ -1198,7 +1198,10 @@ void run_smallm(Ctx& ctx, Prec prec, const GemmDesc& d, const GemmCall& c, GemmA
 std::string tune_key(Prec prec, const GemmDesc& d, const GemmCall& c, const GemmArgs& a) {
   char buf[160];
   snprintf(buf, sizeof(buf), "%s_M%lld_N%lld_K%lld_b%d_a%d%d_b%d%d",
-           prec == Prec::F64 ? "f64" : prec == Prec::C128 ? "c128" : (c.out_f64 ? "f32" : "f32o32"),
+           prec == Prec::F64    ? "f64"
+           : prec == Prec::C128 ? "c128"
+           : prec == Prec::F32  ? (c.out_f64 ? "f32" : "f32o32")
+                                : (c.out_f64 ? "bf16" : "bf16o16"),
            (long long)d.M, (long long)d.N, (long long)d.K, c.batch, a.a_kfast, a.tabA, a.b_kfast,
            a.tabB);
   return buf;
@@ -1225,6 +1228,8 @@ bool tunable(Ctx& ctx, Prec prec, const GemmCall& c, int64_t nA, int64_t nB, int
   };
   return !overlap(rc, ra) && !overlap(rc, rb);
 }
+
+constexpr int kTuneReps = 8;  // timed launches per variant (after one warm-up launch)
 
 GemmVariant tune(Ctx& ctx, Prec prec, const GemmDesc& d, const GemmCall& c, const GemmArgs& a) {
   const bool cplx = prec == Prec::C128;
@@ -1254,7 +1259,7 @@ GemmVariant tune(Ctx& ctx, Prec prec, const GemmDesc& d, const GemmCall& c, cons
         const int64_t off = ctx.ws_offset();
         run_plan(ctx, prec, d, c, a, p);  // warm-up (also first-launch setup)
         HP_CHECK_HIP(hipEventRecord(e0, ctx.stream));
-        for (int r = 0; r < 3; ++r) run_plan(ctx, prec, d, c, a, p);
+        for (int r = 0; r < kTuneReps; ++r) run_plan(ctx, prec, d, c, a, p);
         HP_CHECK_HIP(hipEventRecord(e1, ctx.stream));
         HP_CHECK_HIP(hipEventSynchronize(e1));
         float ms = 0;
