@@ -178,9 +178,11 @@ def c3_flops(n=12, D=10, d=2, m=100, p=8, q=1):
     return step * (n - 2) * (n - 1)
 
 
-def c3_norm(hp, n=12, D=10, d=2, m=100, p=8):
+def c3_norm(hp, args, n=12, D=10, d=2, m=100, p=8):
     """peps_norm of a 12 x 12 lattice, bond 10, boundary bond 100 (FP64 q=1; FP32 and BF16
-    q=2), iid N(0,1) sites normalised: time per norm and log-norm deviation from FP64."""
+    q=2), iid N(0,1) sites normalised: time per norm and log-norm deviation from FP64.
+    GEMM variants as in the main measurement: the shipped choices, and products not in
+    them tuned during the untimed first norm of each precision."""
     import numpy as np
     import torch
 
@@ -188,6 +190,9 @@ def c3_norm(hp, n=12, D=10, d=2, m=100, p=8):
     peps = synth.random_peps(n, n, D=D, seed=0)
     dev = [[torch.from_numpy(np.ascontiguousarray(t)).cuda() for t in row] for row in peps]
     ctx = hp.Context(0)
+    if not args.no_autotune and args.tune_cache and os.path.exists(args.tune_cache):
+        hp.autotune_load(ctx, args.tune_cache)
+    hp.autotune_enable(ctx, not args.no_autotune)
     out = {"workload": f"peps_norm {n}x{n} D={D} d={d} m={m} p={p}"}
     ref = None
     for prec, q in (("f64", 1), ("f32", 2), ("bf16", 2)):
@@ -213,7 +218,7 @@ def c3_norm(hp, n=12, D=10, d=2, m=100, p=8):
         out[prec] = {"q": q, "s_per_norm": round(dt, 4), "log_norm": ln,
                      "dlog_vs_f64": abs(ln - ref), "alg_tflops": round(fl / dt / 1e12, 3),
                      "frac_of_fp64_peak": round(fl / dt / 1e12 / MFMA_F64_PEAK_TFLOPS, 4)}
-    return out
+    return out, ctx
 
 
 def c5_gradient(hp, reps, n=8, D=4, d=2, m=16, p=8, q=1):
@@ -342,7 +347,10 @@ def main():
     import synth
 
     if args.c3:
-        print(json.dumps(c3_norm(hp)))
+        out, ctx3 = c3_norm(hp, args)
+        if args.save_tune_cache:
+            hp.autotune_save(ctx3, args.save_tune_cache)
+        print(json.dumps(out))
         return
 
     inst = [synth.pair_instance(M, DB, DP, seed=0, instance=i) for i in range(BATCH)]
