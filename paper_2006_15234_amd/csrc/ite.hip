@@ -295,7 +295,7 @@ __global__ __launch_bounds__(kT) void qrsvd_bond_kernel(IteArgs a) {
       if (act && a2 > 0 && b2 > 0 && fabs(gm) > tol * sqrt(a2) * sqrt(b2) && fabs(gm) > floor_abs) {
         const double zeta = (b2 - a2) / (2.0 * gm);
         const double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-        const double c = 1.0 / sqrt(1.0 + t * t), sn = c * t;
+        const double c = rsqrt(1.0 + t * t), sn = c * t;  // 1 + t^2 in [1, 2]
         if (in0) {
           x[gl] = c * x0 - sn * y0;
           y[gl] = sn * x0 + c * y0;

@@ -367,7 +367,7 @@ __global__ __launch_bounds__(kJacMaxThreads) void jacobi_kernel(const double* Ra
         const double inv_ga = 1.0 / ga;
         const double zeta = 0.5 * (b2 - a2) * inv_ga;
         const double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-        const double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
+        const double c = rsqrt(1.0 + t * t), s = c * t;  // 1 + t^2 in [1, 2]
         // y~ = conj(e) y with e = gamma / |gamma|, then a real rotation of (x, y~)
         const double er = gr * inv_ga, ei = gi * inv_ga;
 #pragma unroll
