@@ -55,6 +55,36 @@ def test_gemm(ctx, cplx, shape, trans):
         assert np.max(np.abs(out[b] - ref)) <= 1e-13 * max(1.0, np.abs(ref).max()) * np.sqrt(K)
 
 
+N_TILES = 10  # tile shapes of the GEMM (0..9; complex products use those of <= 4 tiles per wave)
+
+
+@pytest.mark.parametrize("tile", range(N_TILES))
+@pytest.mark.parametrize("kstep,split", [(1, 1), (2, 1), (1, 3), (2, 0)])
+def test_gemm_every_variant(ctx, tile, kstep, split):
+    """Each kernel instantiation (tile shape x K-step x split-K), forced through the
+    variant hook on a ragged batched product (several tiles, partial edge tiles,
+    a K tail), real and complex, both operand layouts."""
+    rng = np.random.default_rng(tile * 10 + kstep + split)
+    B, M, N, K = 2, 230, 150, 77
+    try:
+        ctx.check(ctx.lib.hpeps_test_gemm_variant(ctx.h, tile, kstep, split))
+        for cplx in (False, True):
+            for trans in (0, 1):
+                A = _rand(rng, (B, K, M) if trans else (B, M, K), cplx)
+                Bm = _rand(rng, (B, K, N), cplx)
+                dA, dB = _dev(A), _dev(Bm)
+                dC = torch.zeros((B, M, N), dtype=dA.dtype, device="cuda")
+                ctx.sync_stream()
+                ctx.check(ctx.lib.hpeps_test_gemm(ctx.h, hp.C128 if cplx else hp.F64, B, M, N, K, trans,
+                                                  _p(dA), _p(dB), _p(dC)))
+                out = dC.cpu().numpy()
+                for b in range(B):
+                    ref = (A[b].conj().T if trans else A[b]) @ Bm[b]
+                    assert np.max(np.abs(out[b] - ref)) <= 1e-13 * np.abs(ref).max() * np.sqrt(K)
+    finally:
+        ctx.check(ctx.lib.hpeps_test_gemm_variant(ctx.h, -1, 1, 0))
+
+
 @pytest.mark.parametrize("smallk", [1, 0])
 @pytest.mark.parametrize("shape", [(17, 300, 5), (8, 1030, 16), (40, 513, 1), (72, 9504, 6), (9, 777, 12),
                                    (6, 9504, 72), (3, 1030, 200), (8, 512, 17), (1, 2050, 9),
