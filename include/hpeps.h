@@ -352,6 +352,26 @@ hpeps_status hpeps_boundary_contract_row(hpeps_ctx* ctx, const hpeps_bmps* bnd,
 hpeps_status hpeps_peps_norm(hpeps_ctx* ctx, const hpeps_peps* ket, const hpeps_peps* bra,
                              const hpeps_esvd_opts* opts, double* log_norm, double* phase);
 
+/* ---- peps_amplitude (one-layer boundary MPS, Sec. III with Algs. 2-4) ----
+ * <bits|psi>: every physical leg of the ket is fixed to bits[i*ncol + j]
+ * (host, row-major over the sites, 0 <= bit < p), which leaves a one-layer
+ * network of [u,d,l,r] slices (strided views of the sites, not copied).
+ * Row 1 is the exact boundary [l, d, r] (each tensor normalised), rows
+ * 2..n-1 are absorbed by zip-ups whose direction alternates (L2R on the
+ * 1st, 3rd, ... absorbed row): the first column's carry is exact, every
+ * later column is one randomized einsumsvd of the network
+ * "axbh,buc,uyhg->ax|ycg" (carry, boundary tensor, slice; rows (a,x),
+ * columns (y,c,g)) with the options of opts (sketch_precision HPEPS_F64;
+ * stream_id 1 + (i*ncol + j) for lattice row i, column j), row n is
+ * contracted exactly.  Result (host): <bits|psi> = phase * exp(*log_abs),
+ * phase = {re, im} of unit modulus; an exactly zero slice gives
+ * *log_abs = -inf and phase = {0, 0}.  Errors: INVALID_ARG (bit out of
+ * range, null pointers, bad options), SHAPE (inconsistent bonds), DTYPE
+ * (sketch precision other than FP64), NUMERIC (a non-finite result, e.g. an
+ * exactly zero boundary from nonzero slices).  Synchronises. */
+hpeps_status hpeps_peps_amplitude(hpeps_ctx* ctx, const hpeps_peps* ket, const int32_t* bits,
+                                  const hpeps_esvd_opts* opts, double* log_abs, double* phase);
+
 /* ---- peps_energy (Eq. 5 with cached environments, Sec. IV-B) ------------
  * Terms: n_terms entries; term t acts on nsites[t] (1 or 2) sites given by
  * sites[4t .. 4t+3] = {i1, j1, i2, j2} (nearest neighbours, site 1 left of or

@@ -89,6 +89,7 @@ _SIGS = {
                                               C.c_int32, C.c_int, C.POINTER(EsvdOpts),
                                               C.POINTER(Bmps), _DP]),
     "hpeps_peps_norm": (C.c_int, [_P, C.POINTER(Peps), C.POINTER(Peps), C.POINTER(EsvdOpts), _DP, _DP]),
+    "hpeps_peps_amplitude": (C.c_int, [_P, C.POINTER(Peps), C.POINTER(C.c_int32), C.POINTER(EsvdOpts), _DP, _DP]),
     "hpeps_peps_energy": (C.c_int, [_P, C.POINTER(Peps), C.c_int32, C.POINTER(C.c_int32),
                                     C.POINTER(C.c_int32), _DP, _I64P, C.POINTER(EsvdOpts), _DP, _DP]),
     "hpeps_peps_norm_backward": (C.c_int, [_P, C.POINTER(Peps), C.POINTER(EsvdOpts), C.c_double,

@@ -324,6 +324,24 @@ def peps_norm(ctx, ket, bra=None, *, rank, oversample=0, power_iters=0, seed=0, 
     return ln.value, complex(ph[0], ph[1])
 
 
+def peps_amplitude(ctx, ket, bits, *, rank, oversample=0, power_iters=0, seed=0, jacobi_max_sweeps=0):
+    """<bits|psi> by the one-layer boundary MPS (bits: one int per site, row-major).
+    Returns (log|a|, phase as complex); (-inf, 0) for an exactly zero slice."""
+    keep = []
+    dt = _dtype_code(ket[0][0])
+    pk = _peps_struct(ket, dt, keep)
+    nsites = len(ket) * len(ket[0])
+    if len(bits) != nsites:
+        raise ValueError("bits needs one entry per site")
+    b = (C.c_int32 * nsites)(*[int(v) for v in bits])
+    o = make_opts(rank, oversample, power_iters, "f64", seed, 0, jacobi_max_sweeps)
+    la = C.c_double()
+    ph = (C.c_double * 2)()
+    ctx.sync_stream()
+    ctx.check(ctx.lib.hpeps_peps_amplitude(ctx.h, C.byref(pk), b, C.byref(o), C.byref(la), ph))
+    return la.value, complex(ph[0], ph[1])
+
+
 def boundary_contract_row(ctx, bnd, ket, bra=None, *, row, direction, rank, oversample=0,
                           power_iters=0, seed=0, stream_id=0, precision="f64", out_capacity=None):
     """Absorbs row ``row`` of the lattice ``ket`` (list of rows of device site
