@@ -355,7 +355,7 @@ hpeps_status hpeps_peps_norm(hpeps_ctx* ctx, const hpeps_peps* ket, const hpeps_
 /* ---- peps_amplitude (one-layer boundary MPS, Sec. III with Algs. 2-4) ----
  * <bits|psi>: every physical leg of the ket is fixed to bits[i*ncol + j]
  * (host, row-major over the sites, 0 <= bit < p), which leaves a one-layer
- * network of [u,d,l,r] slices (strided views of the sites, not copied).
+ * network of [u,d,l,r] slices (gathered into the workspace).
  * Row 1 is the exact boundary [l, d, r] (each tensor normalised), rows
  * 2..n-1 are absorbed by zip-ups whose direction alternates (L2R on the
  * 1st, 3rd, ... absorbed row): the first column's carry is exact, every
@@ -371,6 +371,18 @@ hpeps_status hpeps_peps_norm(hpeps_ctx* ctx, const hpeps_peps* ket, const hpeps_
  * exactly zero boundary from nonzero slices).  Synchronises. */
 hpeps_status hpeps_peps_amplitude(hpeps_ctx* ctx, const hpeps_peps* ket, const int32_t* bits,
                                   const hpeps_esvd_opts* opts, double* log_abs, double* phase);
+
+/* ---- peps_amplitudes (the same for a batch of basis states) --------------
+ * n_states basis states (1..65535), bits[t*nsites + i*ncol + j] (host); every
+ * state's amplitude is computed exactly as by hpeps_peps_amplitude (same
+ * sketch streams), all states in lockstep: their slices are gathered into
+ * one batch and every kernel launch of the contraction carries the whole
+ * batch.  Outputs (host): log_abs[n_states], phase[2*n_states].  A bit out of
+ * range fails the whole call (INVALID_ARG) before any launch; a non-finite
+ * amplitude of any state fails it with NUMERIC.  Synchronises. */
+hpeps_status hpeps_peps_amplitudes(hpeps_ctx* ctx, const hpeps_peps* ket, int64_t n_states,
+                                   const int32_t* bits, const hpeps_esvd_opts* opts, double* log_abs,
+                                   double* phase);
 
 /* ---- peps_energy (Eq. 5 with cached environments, Sec. IV-B) ------------
  * Terms: n_terms entries; term t acts on nsites[t] (1 or 2) sites given by

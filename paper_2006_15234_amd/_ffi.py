@@ -90,6 +90,8 @@ _SIGS = {
                                               C.POINTER(Bmps), _DP]),
     "hpeps_peps_norm": (C.c_int, [_P, C.POINTER(Peps), C.POINTER(Peps), C.POINTER(EsvdOpts), _DP, _DP]),
     "hpeps_peps_amplitude": (C.c_int, [_P, C.POINTER(Peps), C.POINTER(C.c_int32), C.POINTER(EsvdOpts), _DP, _DP]),
+    "hpeps_peps_amplitudes": (C.c_int, [_P, C.POINTER(Peps), C.c_int64, C.POINTER(C.c_int32), C.POINTER(EsvdOpts),
+                                        _DP, _DP]),
     "hpeps_peps_energy": (C.c_int, [_P, C.POINTER(Peps), C.c_int32, C.POINTER(C.c_int32),
                                     C.POINTER(C.c_int32), _DP, _I64P, C.POINTER(EsvdOpts), _DP, _DP]),
     "hpeps_peps_norm_backward": (C.c_int, [_P, C.POINTER(Peps), C.POINTER(EsvdOpts), C.c_double,

@@ -342,6 +342,26 @@ def peps_amplitude(ctx, ket, bits, *, rank, oversample=0, power_iters=0, seed=0,
     return la.value, complex(ph[0], ph[1])
 
 
+def peps_amplitudes(ctx, ket, states, *, rank, oversample=0, power_iters=0, seed=0, jacobi_max_sweeps=0):
+    """<bits|psi> for a batch of basis states (``states``: sequences of one int per
+    site, row-major), computed in lockstep.  Returns (log|a| list, phase list)."""
+    keep = []
+    dt = _dtype_code(ket[0][0])
+    pk = _peps_struct(ket, dt, keep)
+    nsites = len(ket) * len(ket[0])
+    flat = [int(v) for b in states for v in b]
+    n = len(states)
+    if n < 1 or len(flat) != n * nsites:
+        raise ValueError("states needs one entry per site for every state")
+    b = (C.c_int32 * len(flat))(*flat)
+    o = make_opts(rank, oversample, power_iters, "f64", seed, 0, jacobi_max_sweeps)
+    la = (C.c_double * n)()
+    ph = (C.c_double * (2 * n))()
+    ctx.sync_stream()
+    ctx.check(ctx.lib.hpeps_peps_amplitudes(ctx.h, C.byref(pk), n, b, C.byref(o), la, ph))
+    return list(la), [complex(ph[2 * t], ph[2 * t + 1]) for t in range(n)]
+
+
 def boundary_contract_row(ctx, bnd, ket, bra=None, *, row, direction, rank, oversample=0,
                           power_iters=0, seed=0, stream_id=0, precision="f64", out_capacity=None):
     """Absorbs row ``row`` of the lattice ``ket`` (list of rows of device site

@@ -2,7 +2,7 @@
 // one-layer network (Sec. III: the amplitude network has one layer fewer
 // than the <psi|psi> network of the IBMPS; Algs. 2-3 with Alg. 4).
 // * Fixing every physical leg to its bit leaves the slices A[u,d,l,r] =
-//   T[u,d,l,r,bit]: strided views of the sites, nothing is copied.
+//   T[u,d,l,r,bit], gathered per basis state into [state, u, d, l, r].
 // * Row 1 is the exact boundary ([l, d, r] per column, normalised).
 // * Rows 2..n-1 are absorbed by the zip-up, left to right on the 1st, 3rd,
 //   ... absorbed row and right to left on the others: the first column's
@@ -14,6 +14,9 @@
 //   reads every tensor through mirrored strides.
 // * Row n is contracted exactly column by column.
 // Every normalisation factor and sigma_1 enters a device-side log.
+// Basis states share every shape, so a call takes a batch of them and runs
+// the zip-ups in lockstep: every launch carries all states (the slices are
+// gathered per state; the sketch of a column is shared, as its stream id is).
 #include <cmath>
 #include <initializer_list>
 #include <string>
@@ -26,13 +29,14 @@
 namespace hp {
 namespace {
 
-// A one-layer tensor: leg dims and element strides in lattice orientation
-// (boundary tensors [left, x, right]; slices [u, d, l, r]).
+// A batch of one-layer tensors: instance i at p + i * zs (elements), leg dims
+// and strides in lattice orientation (boundary tensors [left, x, right],
+// slices [u, d, l, r]).
 template <int N>
 struct View {
   const void* p = nullptr;
   int64_t n[N], s[N];
-  int64_t extent = 0;
+  int64_t zs = 0;
 };
 using Bnd = View<3>;
 using Slc = View<4>;
@@ -54,20 +58,15 @@ Slc orient(const Slc& t, Dir dir) {
   return o;
 }
 
+// The view with the state leg Z in front.
 template <int N>
-TView tv(const View<N>& v, const char* legs) {
-  return tview(v.p, legs, std::vector<int64_t>(v.n, v.n + N), std::vector<int64_t>(v.s, v.s + N), v.extent);
-}
-template <int N>
-hpeps_tensor ht(const View<N>& v) {
-  hpeps_tensor t{};
-  t.data = v.p;
-  t.ndim = N;
+TView tvz(const View<N>& v, const char* legs, int nb, bool conj = false) {
+  std::vector<int64_t> d{nb}, st{v.zs};
   for (int i = 0; i < N; ++i) {
-    t.shape[i] = v.n[i];
-    t.strides[i] = v.s[i];
+    d.push_back(v.n[i]);
+    st.push_back(v.s[i]);
   }
-  return t;
+  return tview(v.p, std::string("Z") + legs, d, st, (int64_t)nb * v.zs, conj);
 }
 template <int N>
 View<N> contiguous(void* p, std::initializer_list<int64_t> dims) {
@@ -80,16 +79,14 @@ View<N> contiguous(void* p, std::initializer_list<int64_t> dims) {
     v.s[q] = st;
     st *= v.n[q];
   }
-  v.extent = st;
+  v.zs = st;
   return v;
 }
 
-constexpr const char* kZip1 = "axbh,buc,uyhg->ax|ycg";
-
 // One zip-up (Alg. 3) of the slices `row` into the boundary `bnd` (both by
-// lattice column); out receives the new boundary by lattice column.
-void absorb_row1(Ctx& ctx, bool cplx, const std::vector<Bnd>& bnd, const std::vector<Slc>& row, Dir dir,
-                 const hpeps_esvd_opts& o, int lattice_row, std::vector<Bnd>& out, double* log_dev) {
+// lattice column), all states at once; out receives the new boundary.
+void absorb_row(Ctx& ctx, bool cplx, int nb, const std::vector<Bnd>& bnd, const std::vector<Slc>& row, Dir dir,
+                const hpeps_esvd_opts& o, int lattice_row, std::vector<Bnd>& out, double* logs) {
   const int n = (int)row.size();
   const int es = cplx ? 2 : 1;
   auto col = [&](int q) { return dir == kL2R ? q : n - 1 - q; };
@@ -97,10 +94,11 @@ void absorb_row1(Ctx& ctx, bool cplx, const std::vector<Bnd>& bnd, const std::ve
   const Bnd S0 = orient(bnd[col(0)], dir);
   const Slc A0 = orient(row[col(0)], dir);
   HP_REQUIRE(S0.n[0] == 1 && A0.n[2] == 1, HPEPS_ERR_SHAPE, "open boundary legs must have dim 1");
+  HP_REQUIRE(S0.n[1] == A0.n[0], HPEPS_ERR_SHAPE, "row and boundary legs do not chain");
   int64_t a = 1, x = A0.n[1], b = S0.n[2], h = A0.n[3];
-  double* carry = ctx.ws<double>(x * b * h * es);
-  contract2(ctx, cplx, tv(S0, "auc"), tv(A0, "uyhg"), "ayhcg", carry, x * b * h);
-  normalize(ctx, cplx, carry, x * b * h, 1, log_dev);
+  double* carry = ctx.ws<double>(nb * x * b * h * es);
+  contract2(ctx, cplx, tvz(S0, "auc", nb), tvz(A0, "uyhg", nb), "Zayhcg", carry, nb * x * b * h);
+  normalize(ctx, cplx, carry, x * b * h, nb, logs);
   if (n == 1) {
     out[0] = contiguous<3>(carry, {1, x, b * h});
     return;
@@ -109,28 +107,64 @@ void absorb_row1(Ctx& ctx, bool cplx, const std::vector<Bnd>& bnd, const std::ve
     const Bnd S = orient(bnd[col(q)], dir);
     const Slc A = orient(row[col(q)], dir);
     HP_REQUIRE(S.n[0] == b && A.n[2] == h && S.n[1] == A.n[0], HPEPS_ERR_SHAPE, "row and boundary legs do not chain");
-    const int64_t y = A.n[1], c = S.n[2], g = A.n[3];
-    View<4> Cview = contiguous<4>(carry, {a, x, b, h});
-    const hpeps_tensor ops[3] = {ht(Cview), ht(S), ht(A)};
-    hpeps_esvd_opts oq = o;
-    oq.stream_id = 1 + ((uint64_t)lattice_row * n + col(q));
-    int64_t rows = 0, cols = 0, mp = 0;
-    einsumsvd_query(kZip1, 3, ops, oq, &rows, &cols, &mp);
-    double* U = ctx.ws<double>(rows * mp * es);
-    double* R = ctx.ws<double>(mp * cols * es);
-    einsumsvd_network(ctx, cplx, kZip1, 3, ops, oq, HPEPS_ABSORB_CARRY, U, nullptr, R, log_dev);
+    const int64_t u = A.n[0], y = A.n[1], c = S.n[2], g = A.n[3];
+    const int64_t rows = a * x, cols = y * c * g;
+    const int64_t k = sketch_width(o.rank, o.oversample, rows, cols);
+    const int64_t mp = std::min<int64_t>(o.rank, k);
+    HP_REQUIRE(k >= 1 && k <= (cplx ? 88 : 128), HPEPS_ERR_SHAPE, "sketch width k out of range");
+    ctx.last_rank = mp;
+    ctx.last_k = k;
+    const View<4> Cv = contiguous<4>(carry, {a, x, b, h});
+    const int64_t w1 = nb * u * h * c * k, w2 = nb * b * h * k;
+    double* W1 = ctx.ws<double>(w1 * es);
+    double* W2 = ctx.ws<double>(w2 * es);
+    // A X: slice over (y, g), boundary tensor over (u, c), carry over (b, h);
+    // X is the shared sketch (no state leg) or a panel [Z, y, c, g, k]
+    auto fwd = [&](const double* X, bool per_state, double* Y) {
+      const TView Xv = per_state ? tview_rm(X, "Zycgk", {nb, y, c, g, k}) : tview_rm(X, "ycgk", {y, c, g, k});
+      contract2(ctx, cplx, tvz(A, "uyhg", nb), Xv, "Zuhck", W1, w1);
+      contract2(ctx, cplx, tvz(S, "buc", nb), tview_rm(W1, "Zuhck", {nb, u, h, c, k}), "Zbhk", W2, w2);
+      contract2(ctx, cplx, tvz(Cv, "axbh", nb), tview_rm(W2, "Zbhk", {nb, b, h, k}), "Zaxk", Y, nb * rows * k);
+    };
+    // A^* Y: the mirror stages on the conjugated operands
+    auto adj = [&](const double* X, double* Y) {
+      contract2(ctx, cplx, tvz(Cv, "axbh", nb, true), tview_rm(X, "Zaxk", {nb, a, x, k}), "Zbhk", W2, w2);
+      contract2(ctx, cplx, tvz(S, "buc", nb, true), tview_rm(W2, "Zbhk", {nb, b, h, k}), "Zuchk", W1, w1);
+      contract2(ctx, cplx, tvz(A, "uyhg", nb, true), tview_rm(W1, "Zuchk", {nb, u, c, h, k}), "Zycgk", Y,
+                nb * cols * k);
+    };
+    double* Om = ctx.ws<double>(cols * k * es);
+    sketch(ctx, Om, false, cols, k, 1, o.seed, 1 + ((uint64_t)lattice_row * n + col(q)), cplx);
+    double* Y0 = ctx.ws<double>(nb * rows * k * es);
+    fwd(Om, false, Y0);
+    ZipOut zo;
+    zo.Urows.add(rows, mp);
+    zo.Ucol.add(mp, 1);
+    zo.Rrow.add(mp, cols);
+    zo.Rcols.add(cols, 1);
+    zo.nU = rows * mp;
+    zo.nR = mp * cols;
+    double* U = ctx.ws<double>(nb * rows * mp * es);
+    double* R = ctx.ws<double>(nb * mp * cols * es);
+    rsvd_finish(ctx, cplx, rows, cols, k, mp, nb, o, HPEPS_ABSORB_CARRY, zo, U, nullptr, R, logs, Y0,
+                [&](bool adjoint, const double* X, double* Y) {
+                  if (adjoint)
+                    adj(X, Y);
+                  else
+                    fwd(X, true, Y);
+                });
     // U [a, x, mp] in the sweep frame: lattice [left, x, right]
-    Bnd u;
-    u.p = U;
-    u.extent = rows * mp;
+    Bnd uv;
+    uv.p = U;
+    uv.zs = rows * mp;
     if (dir == kL2R) {
-      u.n[0] = a; u.n[1] = x; u.n[2] = mp;
-      u.s[0] = x * mp; u.s[1] = mp; u.s[2] = 1;
+      uv.n[0] = a; uv.n[1] = x; uv.n[2] = mp;
+      uv.s[0] = x * mp; uv.s[1] = mp; uv.s[2] = 1;
     } else {
-      u.n[0] = mp; u.n[1] = x; u.n[2] = a;
-      u.s[0] = 1; u.s[1] = mp; u.s[2] = x * mp;
+      uv.n[0] = mp; uv.n[1] = x; uv.n[2] = a;
+      uv.s[0] = 1; uv.s[1] = mp; uv.s[2] = x * mp;
     }
-    out[col(q - 1)] = u;
+    out[col(q - 1)] = uv;
     if (q + 1 < n) {
       carry = R;
       a = mp; x = y; b = c; h = g;
@@ -138,7 +172,7 @@ void absorb_row1(Ctx& ctx, bool cplx, const std::vector<Bnd>& bnd, const std::ve
       // the last carry [mp, y, c*g = 1] is the last boundary tensor
       Bnd l;
       l.p = R;
-      l.extent = mp * y;
+      l.zs = mp * cols;
       if (dir == kL2R) {
         l.n[0] = mp; l.n[1] = y; l.n[2] = c * g;
         l.s[0] = y; l.s[1] = 1; l.s[2] = 1;
@@ -152,12 +186,12 @@ void absorb_row1(Ctx& ctx, bool cplx, const std::vector<Bnd>& bnd, const std::ve
 }
 
 // Exact contraction of the boundary with the last row (down legs 1): the
-// unit-modulus mantissa goes to result_dev, the logs to log_dev.
-void last_row1(Ctx& ctx, bool cplx, const std::vector<Bnd>& bnd, const std::vector<Slc>& row, double* result_dev,
-               double* log_dev) {
+// unit-modulus mantissas (one per state) are returned, the logs go to logs.
+double* last_row(Ctx& ctx, bool cplx, int nb, const std::vector<Bnd>& bnd, const std::vector<Slc>& row,
+                 double* logs) {
   const int es = cplx ? 2 : 1;
-  double* E = ctx.ws<double>(es);
-  fill_value(ctx, E, 1, 1.0, cplx);
+  double* E = ctx.ws<double>(nb * es);
+  fill_value(ctx, E, nb, 1.0, cplx);
   int64_t b = 1, h = 1;
   for (size_t j = 0; j < row.size(); ++j) {
     const Bnd& S = bnd[j];
@@ -165,34 +199,35 @@ void last_row1(Ctx& ctx, bool cplx, const std::vector<Bnd>& bnd, const std::vect
     HP_REQUIRE(A.n[1] == 1, HPEPS_ERR_SHAPE, "last-row sites must have down legs of dim 1");
     HP_REQUIRE(S.n[0] == b && A.n[2] == h && S.n[1] == A.n[0], HPEPS_ERR_SHAPE, "row and boundary legs do not chain");
     const int64_t u = S.n[1], c = S.n[2], g = A.n[3];
-    View<2> Ev = contiguous<2>(E, {b, h});
-    double* X1 = ctx.ws<double>(h * u * c * es);
-    contract2(ctx, cplx, tv(Ev, "bh"), tv(S, "buc"), "huc", X1, h * u * c);
-    View<3> Xv = contiguous<3>(X1, {h, u, c});
-    double* En = ctx.ws<double>(c * g * es);
-    contract2(ctx, cplx, tv(Xv, "huc"), tv(A, "udhg"), "cdg", En, c * g);
-    normalize(ctx, cplx, En, c * g, 1, log_dev);
+    const View<2> Ev = contiguous<2>(E, {b, h});
+    double* X1 = ctx.ws<double>(nb * h * u * c * es);
+    contract2(ctx, cplx, tvz(Ev, "bh", nb), tvz(S, "buc", nb), "Zhuc", X1, nb * h * u * c);
+    double* En = ctx.ws<double>(nb * c * g * es);
+    contract2(ctx, cplx, tview_rm(X1, "Zhuc", {nb, h, u, c}), tvz(A, "udhg", nb), "Zcdg", En, nb * c * g);
+    normalize(ctx, cplx, En, c * g, nb, logs);
     E = En;
     b = c;
     h = g;
   }
-  copy_scalar(ctx, E, cplx, result_dev);
+  return E;
 }
 
-// flags[q] = 1 when slice q has a nonzero element (element e of slice q at
-// (e * P + bit) in the site's storage, es doubles per element).
-struct SliceRef {
-  const double* p;
-  long long n;
-  int P, bit;
-};
-__global__ void slice_nonzero_kernel(const SliceRef* refs, int es, int* flags) {
-  const SliceRef r = refs[blockIdx.x];
+// out[t, e] = T[e * P + bit_t] (es doubles per element) for state t (one
+// block per state); flags[t * nsites + site] = the slice has a nonzero.
+__global__ void gather_slices_kernel(const double* T, long long vol, int P, const int* bits, int nsites, int site,
+                                     int es, double* out, int* flags) {
+  const int t = blockIdx.x;
+  const int bit = bits[(long long)t * nsites + site];
+  double* o = out + (long long)t * vol * es;
   int any = 0;
-  for (long long e = threadIdx.x; e < r.n; e += blockDim.x)
-    for (int c = 0; c < es; ++c) any |= r.p[(e * r.P + r.bit) * es + c] != 0.0;
+  for (long long e = threadIdx.x; e < vol; e += blockDim.x)
+    for (int q = 0; q < es; ++q) {
+      const double v = T[(e * P + bit) * es + q];
+      o[e * es + q] = v;
+      any |= v != 0.0;
+    }
   any = __syncthreads_or(any);
-  if (threadIdx.x == 0) flags[blockIdx.x] = any;
+  if (threadIdx.x == 0) flags[(long long)t * nsites + site] = any;
 }
 
 template <class F>
@@ -214,92 +249,103 @@ hpeps_status guard_a(hpeps_ctx* ctx, F&& f) {
   }
 }
 
+void amplitudes(Ctx& c, const hpeps_peps* ket, int64_t n_states, const int32_t* bits, const hpeps_esvd_opts* opts,
+                double* log_abs, double* phase) {
+  HP_REQUIRE(opts && bits && log_abs && phase, HPEPS_ERR_INVALID_ARG, "null argument");
+  HP_REQUIRE(n_states >= 1 && n_states <= 65535, HPEPS_ERR_INVALID_ARG, "n_states must be in 1..65535");
+  HP_REQUIRE(opts->rank >= 1 && opts->oversample >= 0 && opts->power_iters >= 0 && opts->jacobi_max_sweeps >= 0,
+             HPEPS_ERR_INVALID_ARG, "bad einsumsvd options");
+  HP_REQUIRE(opts->sketch_precision == HPEPS_F64, HPEPS_ERR_DTYPE, "amplitudes run in FP64 / complex128");
+  const Lattice K = lattice_from_abi(ket);
+  const bool cplx = K.cplx;
+  const int es = cplx ? 2 : 1;
+  const int nrow = K.nrow, ncol = K.ncol, nsites = nrow * ncol;
+  const int nb = (int)n_states;
+  for (int64_t t = 0; t < n_states; ++t)
+    for (int q = 0; q < nsites; ++q) {
+      const int32_t bit = bits[t * nsites + q];
+      HP_REQUIRE(bit >= 0 && bit < K.sites[q].dims[4], HPEPS_ERR_INVALID_ARG,
+                 "bit out of range of the physical dimension");
+    }
+  int* dbits = c.ws<int>(n_states * nsites);
+  int* flags = c.ws<int>(n_states * nsites);
+  HP_CHECK_HIP(hipMemcpyAsync(dbits, bits, (size_t)n_states * nsites * sizeof(int32_t), hipMemcpyHostToDevice,
+                              c.stream));
+  // slices gathered per state: [Z, u, d, l, r]
+  std::vector<std::vector<Slc>> layer(nrow, std::vector<Slc>(ncol));
+  for (int i = 0; i < nrow; ++i)
+    for (int j = 0; j < ncol; ++j) {
+      const DevTensor& T = K.at(i, j);
+      const int P = (int)T.dims[4];
+      const int64_t vol = T.size() / P;
+      double* g = c.ws<double>(n_states * vol * es);
+      gather_slices_kernel<<<nb, 256, 0, c.stream>>>((const double*)T.p, vol, P, dbits, nsites, i * ncol + j, es,
+                                                     g, flags);
+      HP_CHECK_HIP(hipGetLastError());
+      layer[i][j] = contiguous<4>(g, {T.dims[0], T.dims[1], T.dims[2], T.dims[3]});
+    }
+  double* logs = c.ws<double>(n_states);
+  fill_value(c, logs, n_states, 0.0, false);
+  std::vector<Bnd> bnd(ncol);
+  if (nrow == 1) {
+    double* one = c.ws<double>(n_states * es);
+    fill_value(c, one, n_states, 1.0, cplx);
+    for (int j = 0; j < ncol; ++j) bnd[j] = contiguous<3>(one, {1, 1, 1});
+  } else {
+    // row 1: each slice [1, d, l, r] read as [l, d, r], normalised in place
+    for (int j = 0; j < ncol; ++j) {
+      const Slc& A = layer[0][j];
+      HP_REQUIRE(A.n[0] == 1, HPEPS_ERR_SHAPE, "top legs must have dim 1");
+      normalize(c, cplx, const_cast<void*>(A.p), A.zs, nb, logs);
+      Bnd v;
+      v.p = A.p;
+      v.zs = A.zs;
+      v.n[0] = A.n[2]; v.s[0] = A.s[2];
+      v.n[1] = A.n[1]; v.s[1] = A.s[1];
+      v.n[2] = A.n[3]; v.s[2] = A.s[3];
+      bnd[j] = v;
+    }
+    for (int t = 1; t < nrow - 1; ++t) {
+      std::vector<Bnd> nbnd(ncol);
+      absorb_row(c, cplx, nb, bnd, layer[t], t % 2 == 1 ? kL2R : kR2L, *opts, t, nbnd, logs);
+      bnd = nbnd;
+    }
+  }
+  const double* E = last_row(c, cplx, nb, bnd, layer[nrow - 1], logs);
+  std::vector<double> hl(n_states), he(n_states * es);
+  std::vector<int> hf(n_states * nsites);
+  HP_CHECK_HIP(hipMemcpyAsync(hl.data(), logs, hl.size() * sizeof(double), hipMemcpyDeviceToHost, c.stream));
+  HP_CHECK_HIP(hipMemcpyAsync(he.data(), E, he.size() * sizeof(double), hipMemcpyDeviceToHost, c.stream));
+  HP_CHECK_HIP(hipMemcpyAsync(hf.data(), flags, hf.size() * sizeof(int), hipMemcpyDeviceToHost, c.stream));
+  HP_CHECK_HIP(hipStreamSynchronize(c.stream));
+  for (int64_t t = 0; t < n_states; ++t) {
+    bool zero = false;
+    for (int q = 0; q < nsites; ++q) zero = zero || !hf[t * nsites + q];
+    if (zero) {
+      // an exactly zero slice makes the amplitude exactly zero
+      log_abs[t] = -INFINITY;
+      phase[2 * t] = phase[2 * t + 1] = 0.0;
+      continue;
+    }
+    const double re = he[t * es], im = cplx ? he[t * es + 1] : 0.0;
+    HP_REQUIRE(std::isfinite(hl[t]) && std::isfinite(re) && std::isfinite(im), HPEPS_ERR_NUMERIC,
+               "non-finite amplitude");
+    log_abs[t] = hl[t];
+    phase[2 * t] = re;
+    phase[2 * t + 1] = im;
+  }
+}
+
 }  // namespace
 }  // namespace hp
 
+extern "C" hpeps_status hpeps_peps_amplitudes(hpeps_ctx* ctx, const hpeps_peps* ket, int64_t n_states,
+                                              const int32_t* bits, const hpeps_esvd_opts* opts, double* log_abs,
+                                              double* phase) {
+  return hp::guard_a(ctx, [&](hp::Ctx& c) { hp::amplitudes(c, ket, n_states, bits, opts, log_abs, phase); });
+}
+
 extern "C" hpeps_status hpeps_peps_amplitude(hpeps_ctx* ctx, const hpeps_peps* ket, const int32_t* bits,
                                              const hpeps_esvd_opts* opts, double* log_abs, double* phase) {
-  using namespace hp;
-  return guard_a(ctx, [&](Ctx& c) {
-    HP_REQUIRE(opts && bits && log_abs && phase, HPEPS_ERR_INVALID_ARG, "null argument");
-    HP_REQUIRE(opts->rank >= 1 && opts->oversample >= 0 && opts->power_iters >= 0 && opts->jacobi_max_sweeps >= 0,
-               HPEPS_ERR_INVALID_ARG, "bad einsumsvd options");
-    HP_REQUIRE(opts->sketch_precision == HPEPS_F64, HPEPS_ERR_DTYPE, "amplitudes run in FP64 / complex128");
-    const Lattice K = lattice_from_abi(ket);
-    const bool cplx = K.cplx;
-    const int es = cplx ? 2 : 1;
-    const int nrow = K.nrow, ncol = K.ncol;
-    // slices as strided views of the sites
-    std::vector<std::vector<Slc>> layer(nrow, std::vector<Slc>(ncol));
-    std::vector<SliceRef> refs;
-    for (int i = 0; i < nrow; ++i)
-      for (int j = 0; j < ncol; ++j) {
-        const DevTensor& T = K.at(i, j);
-        const int P = (int)T.dims[4], bit = bits[i * ncol + j];
-        HP_REQUIRE(bit >= 0 && bit < P, HPEPS_ERR_INVALID_ARG, "bit out of range of the physical dimension");
-        const auto st = rm_strides(T.dims);
-        Slc& v = layer[i][j];
-        v.p = (const double*)T.p + (int64_t)bit * es;
-        for (int q = 0; q < 4; ++q) {
-          v.n[q] = T.dims[q];
-          v.s[q] = st[q];
-        }
-        v.extent = T.size() - bit;
-        refs.push_back(SliceRef{(const double*)T.p, T.size() / P, P, bit});
-      }
-    // an exactly zero slice makes the amplitude exactly zero
-    {
-      SliceRef* d_refs = c.ws<SliceRef>((int64_t)refs.size());
-      int* flags = c.ws<int>((int64_t)refs.size());
-      HP_CHECK_HIP(hipMemcpyAsync(d_refs, refs.data(), refs.size() * sizeof(SliceRef), hipMemcpyHostToDevice,
-                                  c.stream));
-      slice_nonzero_kernel<<<(unsigned)refs.size(), 256, 0, c.stream>>>(d_refs, es, flags);
-      HP_CHECK_HIP(hipGetLastError());
-      std::vector<int> h(refs.size());
-      HP_CHECK_HIP(hipMemcpyAsync(h.data(), flags, h.size() * sizeof(int), hipMemcpyDeviceToHost, c.stream));
-      HP_CHECK_HIP(hipStreamSynchronize(c.stream));
-      for (int f : h)
-        if (!f) {
-          *log_abs = -INFINITY;
-          phase[0] = phase[1] = 0.0;
-          return;
-        }
-    }
-    double* dev = c.ws<double>(4);  // log, mantissa re/im
-    fill_value(c, dev, 1, 0.0, false);
-    std::vector<Bnd> bnd(ncol);
-    if (nrow == 1) {
-      double* one = c.ws<double>(es);
-      fill_value(c, one, 1, 1.0, cplx);
-      for (int j = 0; j < ncol; ++j) bnd[j] = contiguous<3>(one, {1, 1, 1});
-    } else {
-      // row 1: [l, d, r] copies of the slices (u = 1), normalised
-      double* one = c.ws<double>(es);
-      fill_value(c, one, 1, 1.0, cplx);
-      const View<1> onev = contiguous<1>(one, {1});
-      for (int j = 0; j < ncol; ++j) {
-        const Slc& A = layer[0][j];
-        HP_REQUIRE(A.n[0] == 1, HPEPS_ERR_SHAPE, "top legs must have dim 1");
-        const int64_t l = A.n[2], d = A.n[1], r = A.n[3];
-        double* B = c.ws<double>(l * d * r * es);
-        contract2(c, cplx, tv(A, "udlr"), tv(onev, "u"), "ldr", B, l * d * r);
-        normalize(c, cplx, B, l * d * r, 1, dev);
-        bnd[j] = contiguous<3>(B, {l, d, r});
-      }
-      for (int t = 1; t < nrow - 1; ++t) {
-        std::vector<Bnd> nb(ncol);
-        absorb_row1(c, cplx, bnd, layer[t], t % 2 == 1 ? kL2R : kR2L, *opts, t, nb, dev);
-        bnd = nb;
-      }
-    }
-    last_row1(c, cplx, bnd, layer[nrow - 1], dev + 1, dev);
-    double hres[3];
-    HP_CHECK_HIP(hipMemcpyAsync(hres, dev, sizeof(hres), hipMemcpyDeviceToHost, c.stream));
-    HP_CHECK_HIP(hipStreamSynchronize(c.stream));
-    HP_REQUIRE(std::isfinite(hres[0]) && std::isfinite(hres[1]) && std::isfinite(hres[2]), HPEPS_ERR_NUMERIC,
-               "non-finite amplitude");
-    *log_abs = hres[0];
-    phase[0] = hres[1];
-    phase[1] = hres[2];
-  });
+  return hp::guard_a(ctx, [&](hp::Ctx& c) { hp::amplitudes(c, ket, 1, bits, opts, log_abs, phase); });
 }

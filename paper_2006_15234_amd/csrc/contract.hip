@@ -2,7 +2,12 @@
 // GEMM: legs present in both operands and absent from the output are summed
 // (K), legs of only one operand become the rows (M, from A) or columns
 // (N, from B) of the product, the output is written in the row-major order
-// of its leg string.  Used for the strip contractions of expectation values.
+// of its leg string.  A leg present in both operands and in the output (at
+// most one) is a batch leg: instance i of the product reads A and B at i
+// times their strides of that leg and writes the output at i times its
+// stride there; within an instance every access must stay below those
+// strides.  Used for the strip contractions of expectation values and the
+// batched amplitudes.
 #include "contract.h"
 
 namespace hp {
@@ -40,11 +45,14 @@ std::vector<int64_t> contract2(Ctx& ctx, bool cplx, const TView& A, const TView&
     return a >= 0 ? a : b;
   };
   std::vector<int64_t> odims;
+  char bleg = 0;
   for (char c : out) {
     const int64_t d = dim_of(c);
     HP_REQUIRE(d >= 1, HPEPS_ERR_SHAPE, std::string("output leg not in the operands: ") + c);
-    HP_REQUIRE(!(leg_dim(A, c) >= 0 && leg_dim(B, c) >= 0), HPEPS_ERR_SHAPE,
-               std::string("leg in both operands and the output: ") + c);
+    if (leg_dim(A, c) >= 0 && leg_dim(B, c) >= 0) {
+      HP_REQUIRE(!bleg, HPEPS_ERR_SHAPE, "at most one batch leg");
+      bleg = c;
+    }
     odims.push_back(d);
   }
   const auto ost = rm_strides(odims);
@@ -56,6 +64,7 @@ std::vector<int64_t> contract2(Ctx& ctx, bool cplx, const TView& A, const TView&
   // M: legs of A kept in the output (output order), N: legs of B kept
   for (size_t i = 0; i < out.size(); ++i) {
     const char c = out[i];
+    if (c == bleg) continue;
     const auto pa = A.legs.find(c);
     if (pa != std::string::npos) {
       D.Am.add(A.dims[pa], A.strides[pa]);
@@ -99,6 +108,16 @@ std::vector<int64_t> contract2(Ctx& ctx, bool cplx, const TView& A, const TView&
   g.sA = A.extent;
   g.sB = B.extent;
   g.sC = osize;
+  if (bleg) {
+    const auto pa = A.legs.find(bleg), pb = B.legs.find(bleg), po = out.find(bleg);
+    const int64_t nb = odims[po];
+    g.batch = (int)nb;
+    g.sA = A.strides[pa];
+    g.sB = B.strides[pb];
+    g.sC = ost[po];
+    HP_REQUIRE(nb < (1LL << 31) && g.sA >= 1 && g.sB >= 1 && nb * g.sA <= A.extent && nb * g.sB <= B.extent,
+               HPEPS_ERR_SHAPE, "batch leg strides exceed the operands");
+  }
   g.conjA = cplx && A.conj;
   g.conjB = cplx && B.conj;
   gemm(ctx, cplx ? Prec::C128 : Prec::F64, D, g);

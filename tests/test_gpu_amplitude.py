@@ -47,6 +47,29 @@ def test_amplitude_matches_oracle(ctx, case):
         assert abs(ph - ph_ref) <= 1e-10
 
 
+@pytest.mark.parametrize("case", [CASES[1], CASES[4], CASES[5], CASES[7]],
+                         ids=lambda c: "x".join(map(str, c[:3])) + ("c" if c[6] else ""))
+def test_batched_amplitudes_match_oracle(ctx, case):
+    """A batch of basis states in lockstep, including a state with an exactly zero
+    slice: every state equals the oracle's single amplitude."""
+    nrow, ncol, D, m, p, q, cplx = case
+    ket = synth.random_peps(nrow, ncol, D, seed=nrow * 100 + ncol * 10 + D, complex_=cplx)
+    ket[0][0] = ket[0][0].copy()
+    ket[0][0][..., 1] = 0.0           # states with bit 1 at site (0, 0) have amplitude 0
+    states = [_bits(nrow * ncol, t) for t in range(7)]
+    states[3][0] = 1
+    for st in states[:3] + states[4:]:
+        st[0] = 0
+    la, ph = hp.peps_amplitudes(ctx, dev_lattice(ket), states, rank=m, oversample=p, power_iters=q, seed=7)
+    for t, st in enumerate(states):
+        la_ref, ph_ref = amp.amplitude(ket, st, m, p, q, seed=7)
+        if t == 3:
+            assert la[t] == -np.inf and ph[t] == 0 and la_ref == -np.inf
+            continue
+        assert abs(la[t] - la_ref) <= 1e-10 * max(1.0, abs(la_ref))
+        assert abs(ph[t] - ph_ref) <= 1e-10
+
+
 def test_exact_regime_equals_state_vector(ctx):
     ket = synth.random_peps(4, 4, 2, seed=21, complex_=True)
     psi = sv.peps_to_statevector(ket)
@@ -75,18 +98,19 @@ def test_zero_slice_and_errors(ctx):
 
 def test_bench_workload_sample(ctx):
     """The timed workload (16 x 16, D = 8, m = 56, p = 8, q = 1: 210 einsumsvds of
-    up to 448 x 3584, nonnegative sites) on one of its basis states, against the
-    oracle.  With random-sign sites this size is ill-conditioned (in the oracle
+    up to 448 x 3584, nonnegative sites), a batch of 4 of its basis states, against
+    the oracle.  With random-sign sites this size is ill-conditioned (in the oracle
     alone a 1e-14 relative perturbation of the sites moves log|a| by about 1.5),
     so no rounding-level comparison exists there; nonnegative sites have no
     cancellation, and at k = 64 every sketch panel keeps full numerical rank
     (smallest singular value above 1e-12 of the largest)."""
     ket = [[np.abs(t) for t in row] for row in synth.random_peps(16, 16, 8, seed=0)]
-    bits = _bits(256, 0)
-    la_ref, ph_ref = amp.amplitude(ket, bits, 56, 8, 1, seed=0)
-    la, ph = hp.peps_amplitude(ctx, dev_lattice(ket), bits, rank=56, oversample=8, power_iters=1, seed=0)
-    assert abs(la - la_ref) <= 1e-10 * max(1.0, abs(la_ref))
-    assert abs(ph - ph_ref) <= 1e-10
+    states = [_bits(256, t) for t in range(4)]
+    la, ph = hp.peps_amplitudes(ctx, dev_lattice(ket), states, rank=56, oversample=8, power_iters=1, seed=0)
+    for t in (0, 3):
+        la_ref, ph_ref = amp.amplitude(ket, states[t], 56, 8, 1, seed=0)
+        assert abs(la[t] - la_ref) <= 1e-10 * max(1.0, abs(la_ref))
+        assert abs(ph[t] - ph_ref) <= 1e-10
 
 
 def test_rank_deficient_sketches_bound(ctx):
