@@ -755,19 +755,47 @@ __global__ void copy_sigma_kernel(const double* sk, int k, int mp, int batch, do
   }
 }
 
-__global__ void stats_kernel(const int* flags, const int* sweeps, int batch, int* acc) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    for (int b = 0; b < batch; ++b) {
-      if (flags) {
-        if (flags[b] & FLAG_THIRD_PASS) acc[0] += 1;
-        if (flags[b] & FLAG_NUMERIC) acc[2] += 1;
-      }
-      if (sweeps) {
-        const int s = sweeps[b];
-        acc[1] = max(acc[1], s < 0 ? -s : s);
-        if (s < 0) acc[3] += 1;
-      }
+// Diagnostics of a batch (third CholeskyQR passes, non-finite factors, the
+// largest Jacobi sweep count, capped sweeps): per-thread partials over the
+// instances, one block reduction, one update of acc (integers: exact and
+// independent of the order).
+constexpr int kStatsThreads = 256;
+__global__ __launch_bounds__(kStatsThreads) void stats_kernel(const int* flags, const int* sweeps, int batch,
+                                                              int* acc) {
+  __shared__ int part[4][kStatsThreads];
+  const int tid = threadIdx.x;
+  int third = 0, numeric = 0, smax = 0, capped = 0;
+  for (int b = tid; b < batch; b += kStatsThreads) {
+    if (flags) {
+      const int f = flags[b];
+      third += (f & FLAG_THIRD_PASS) != 0;
+      numeric += (f & FLAG_NUMERIC) != 0;
     }
+    if (sweeps) {
+      const int sw = sweeps[b];
+      smax = max(smax, sw < 0 ? -sw : sw);
+      capped += sw < 0;
+    }
+  }
+  part[0][tid] = third;
+  part[1][tid] = numeric;
+  part[2][tid] = smax;
+  part[3][tid] = capped;
+  __syncthreads();
+  for (int st = kStatsThreads / 2; st > 0; st >>= 1) {
+    if (tid < st) {
+      part[0][tid] += part[0][tid + st];
+      part[1][tid] += part[1][tid + st];
+      part[2][tid] = max(part[2][tid], part[2][tid + st]);
+      part[3][tid] += part[3][tid + st];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    acc[0] += part[0][0];
+    acc[2] += part[1][0];
+    acc[1] = max(acc[1], part[2][0]);
+    acc[3] += part[3][0];
   }
 }
 
@@ -1107,7 +1135,7 @@ void copy_sigma(Ctx& ctx, const double* sigma_k, int64_t k, int64_t mp, int batc
 }
 
 void stats_reduce(Ctx& ctx, const int* flags, const int* sweeps, int batch, int* acc) {
-  stats_kernel<<<1, 64, 0, ctx.stream>>>(flags, sweeps, batch, acc);
+  stats_kernel<<<1, kStatsThreads, 0, ctx.stream>>>(flags, sweeps, batch, acc);
   HP_CHECK_HIP(hipGetLastError());
 }
 
