@@ -261,12 +261,14 @@ def c5_gradient(hp, reps, n=8, D=4, d=2, m=16, p=8, q=1):
                                         for k, a in sorted(agg.items(), key=lambda x: -x[1]["ms"])[:8]}}
 
 
-def amplitudes(hp, count, n=16, D=8, m=56, p=8, q=1):
+def amplitudes(hp, args, count, n=16, D=8, m=56, p=8, q=1):
     """Amplitudes <i|psi> of an n x n PEPS with nonnegative random sites (|N(0,1)|,
     bond D, d = 2) by the one-layer boundary MPS: (n - 2) * (n - 1) randomized
     einsumsvds per amplitude, each on the network carry x boundary tensor x slice
     (up to m D x m D^2 rows x columns).  ``count`` basis states in one batched call
-    after two untimed calls, and one state alone for the latency."""
+    after two untimed calls (the first tunes the products missing from the shipped
+    GEMM choices and grows the workspace, the second runs with the workspace merged
+    into one chunk), then one state alone for the latency.  Returns (result, context)."""
     import numpy as np
     import torch
 
@@ -274,11 +276,14 @@ def amplitudes(hp, count, n=16, D=8, m=56, p=8, q=1):
     ket = [[np.abs(t) for t in row] for row in synth.random_peps(n, n, D, seed=0)]
     dev = [[torch.from_numpy(np.ascontiguousarray(t)).cuda() for t in row] for row in ket]
     ctx = hp.Context(0)
+    if not args.no_autotune and args.tune_cache and os.path.exists(args.tune_cache):
+        hp.autotune_load(ctx, args.tune_cache)
     rng = np.random.default_rng(0)
     states = [[int(v) for v in rng.integers(0, 2, n * n)] for _ in range(count + 1)]
-    # two untimed calls: the first grows the workspace, the second merges it into one chunk
-    for _ in range(2):
+    for it in range(2):
+        hp.autotune_enable(ctx, it == 0 and not args.no_autotune)
         hp.peps_amplitudes(ctx, dev, states[:count], rank=m, oversample=p, power_iters=q)
+    hp.autotune_enable(ctx, False)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     hp.peps_amplitudes(ctx, dev, states[1:], rank=m, oversample=p, power_iters=q)
@@ -291,7 +296,7 @@ def amplitudes(hp, count, n=16, D=8, m=56, p=8, q=1):
     return {"workload": f"amplitudes of a {n}x{n} PEPS (nonnegative sites), D={D}, d=2, m={m}, p={p}, q={q}, "
                         f"{(n - 2) * (n - 1)} einsumsvds each", "batch": count,
             "ms_per_batch": round(dt * 1e3, 2), "amplitudes_per_s": round(count / dt, 2),
-            "ms_single_amplitude": round(single * 1e3, 2)}
+            "ms_single_amplitude": round(single * 1e3, 2)}, ctx
 
 
 def c4_ite(hp, sweeps, n=16, D=8, d=2, tau=0.01, J=1.0, hfield=3.0):
@@ -353,6 +358,8 @@ def main():
                     help="time this many ITE sweeps of the 16x16 D=8 TFI PEPS (0 skips)")
     ap.add_argument("--amp", type=int, default=256, metavar="COUNT",
                     help="basis states per batched call in the one-layer amplitude block (0 disables it)")
+    ap.add_argument("--amp-only", type=int, default=0, metavar="COUNT",
+                    help="run only the amplitude block with COUNT basis states per call and print its JSON")
     ap.add_argument("--c5", type=int, default=2, metavar="REPS",
                     help="time the 8x8 D=4 complex energy gradient this many times (0 skips)")
     ap.add_argument("--c3", action="store_true",
@@ -380,6 +387,13 @@ def main():
 
     import paper_2006_15234_amd as hp
     import synth
+
+    if args.amp_only > 0:
+        out, actx = amplitudes(hp, args, args.amp_only)
+        if args.save_tune_cache:
+            hp.autotune_save(actx, args.save_tune_cache)
+        print(json.dumps(out))
+        return
 
     if args.c3:
         out, ctx3 = c3_norm(hp, args)
@@ -487,7 +501,8 @@ def main():
     if args.c4 > 0:
         res["c4_ite"] = c4_ite(hp, args.c4)
     if args.amp > 0:
-        res["amplitude"] = amplitudes(hp, args.amp)
+        res["amplitude"], actx = amplitudes(hp, args, args.amp)
+        hp.autotune_import(ctx, hp.autotune_export(actx))   # its tuned products join the saved set
     if args.c5 > 0:
         res["c5_gradient"] = c5_gradient(hp, args.c5)
     if args.d8 > 0:
