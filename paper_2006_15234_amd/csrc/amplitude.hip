@@ -83,20 +83,37 @@ View<N> contiguous(void* p, std::initializer_list<int64_t> dims) {
   return v;
 }
 
+// Storage of one zip-up: the new boundary tensors go to `store` (slot j of
+// lattice column j holds nb * cap_u elements), the carries alternate between
+// carries[0] and carries[1] (nb * cap_c elements each); every other buffer
+// of a column lives in a workspace scope, so the footprint does not grow
+// with the lattice.
+struct RowBuffers {
+  double* store;
+  int64_t cap_u;
+  double* carries[2];
+  int64_t cap_c;
+};
+
 // One zip-up (Alg. 3) of the slices `row` into the boundary `bnd` (both by
 // lattice column), all states at once; out receives the new boundary.
 void absorb_row(Ctx& ctx, bool cplx, int nb, const std::vector<Bnd>& bnd, const std::vector<Slc>& row, Dir dir,
-                const hpeps_esvd_opts& o, int lattice_row, std::vector<Bnd>& out, double* logs) {
+                const hpeps_esvd_opts& o, int lattice_row, const RowBuffers& rb, std::vector<Bnd>& out,
+                double* logs) {
   const int n = (int)row.size();
   const int es = cplx ? 2 : 1;
   auto col = [&](int q) { return dir == kL2R ? q : n - 1 - q; };
+  auto slot = [&](int j) { return rb.store + (int64_t)j * nb * rb.cap_u * es; };
   // first column: exact carry [a, x, b, h] (a = h_left = 1)
   const Bnd S0 = orient(bnd[col(0)], dir);
   const Slc A0 = orient(row[col(0)], dir);
   HP_REQUIRE(S0.n[0] == 1 && A0.n[2] == 1, HPEPS_ERR_SHAPE, "open boundary legs must have dim 1");
   HP_REQUIRE(S0.n[1] == A0.n[0], HPEPS_ERR_SHAPE, "row and boundary legs do not chain");
   int64_t a = 1, x = A0.n[1], b = S0.n[2], h = A0.n[3];
-  double* carry = ctx.ws<double>(nb * x * b * h * es);
+  HP_REQUIRE(x * b * h <= (n == 1 ? rb.cap_u : rb.cap_c), HPEPS_ERR_SHAPE, "carry exceeds its buffer");
+  // a one-column row has no einsumsvd: the exact carry is the boundary
+  double* carry = n == 1 ? slot(0) : rb.carries[0];
+  int cur = 0;
   contract2(ctx, cplx, tvz(S0, "auc", nb), tvz(A0, "uyhg", nb), "Zayhcg", carry, nb * x * b * h);
   normalize(ctx, cplx, carry, x * b * h, nb, logs);
   if (n == 1) {
@@ -104,6 +121,7 @@ void absorb_row(Ctx& ctx, bool cplx, int nb, const std::vector<Bnd>& bnd, const 
     return;
   }
   for (int q = 1; q < n; ++q) {
+    WsScope scope(ctx);
     const Bnd S = orient(bnd[col(q)], dir);
     const Slc A = orient(row[col(q)], dir);
     HP_REQUIRE(S.n[0] == b && A.n[2] == h && S.n[1] == A.n[0], HPEPS_ERR_SHAPE, "row and boundary legs do not chain");
@@ -112,6 +130,8 @@ void absorb_row(Ctx& ctx, bool cplx, int nb, const std::vector<Bnd>& bnd, const 
     const int64_t k = sketch_width(o.rank, o.oversample, rows, cols);
     const int64_t mp = std::min<int64_t>(o.rank, k);
     HP_REQUIRE(k >= 1 && k <= (cplx ? 88 : 128), HPEPS_ERR_SHAPE, "sketch width k out of range");
+    HP_REQUIRE(rows * mp <= rb.cap_u && mp * cols <= (q + 1 < n ? rb.cap_c : rb.cap_u), HPEPS_ERR_SHAPE,
+               "einsumsvd factors exceed their buffers");
     ctx.last_rank = mp;
     ctx.last_k = k;
     const View<4> Cv = contiguous<4>(carry, {a, x, b, h});
@@ -144,8 +164,8 @@ void absorb_row(Ctx& ctx, bool cplx, int nb, const std::vector<Bnd>& bnd, const 
     zo.Rcols.add(cols, 1);
     zo.nU = rows * mp;
     zo.nR = mp * cols;
-    double* U = ctx.ws<double>(nb * rows * mp * es);
-    double* R = ctx.ws<double>(nb * mp * cols * es);
+    double* U = slot(col(q - 1));
+    double* R = q + 1 < n ? rb.carries[1 - cur] : slot(col(q));
     rsvd_finish(ctx, cplx, rows, cols, k, mp, nb, o, HPEPS_ABSORB_CARRY, zo, U, nullptr, R, logs, Y0,
                 [&](bool adjoint, const double* X, double* Y) {
                   if (adjoint)
@@ -167,6 +187,7 @@ void absorb_row(Ctx& ctx, bool cplx, int nb, const std::vector<Bnd>& bnd, const 
     out[col(q - 1)] = uv;
     if (q + 1 < n) {
       carry = R;
+      cur = 1 - cur;
       a = mp; x = y; b = c; h = g;
     } else {
       // the last carry [mp, y, c*g = 1] is the last boundary tensor
@@ -286,6 +307,24 @@ void amplitudes(Ctx& c, const hpeps_peps* ket, int64_t n_states, const int32_t* 
     }
   double* logs = c.ws<double>(n_states);
   fill_value(c, logs, n_states, 0.0, false);
+  // zip-up storage: boundary tensors [left, x, right] of at most M x Dm x M
+  // elements and carries [a, x, b, h] of at most M x Dm x M x Dm, with Dm
+  // the largest site dimension and M = max(rank, Dm) (the first boundary's
+  // bonds are site bonds); two boundary rows and two carries are live at once
+  int64_t Dm = 1;
+  for (const auto& t : K.sites)
+    for (int q = 0; q < 4; ++q) Dm = std::max<int64_t>(Dm, t.dims[q]);
+  const int64_t M = std::max<int64_t>(opts->rank, Dm);
+  RowBuffers rbuf[2];
+  for (auto& r : rbuf) {
+    r.cap_u = M * Dm * M;
+    r.cap_c = M * Dm * M * Dm;
+    r.store = nrow > 2 ? c.ws<double>((int64_t)ncol * n_states * r.cap_u * es) : nullptr;
+  }
+  if (nrow > 2) {
+    rbuf[0].carries[0] = rbuf[1].carries[0] = c.ws<double>(n_states * rbuf[0].cap_c * es);
+    rbuf[0].carries[1] = rbuf[1].carries[1] = c.ws<double>(n_states * rbuf[0].cap_c * es);
+  }
   std::vector<Bnd> bnd(ncol);
   if (nrow == 1) {
     double* one = c.ws<double>(n_states * es);
@@ -307,7 +346,7 @@ void amplitudes(Ctx& c, const hpeps_peps* ket, int64_t n_states, const int32_t* 
     }
     for (int t = 1; t < nrow - 1; ++t) {
       std::vector<Bnd> nbnd(ncol);
-      absorb_row(c, cplx, nb, bnd, layer[t], t % 2 == 1 ? kL2R : kR2L, *opts, t, nbnd, logs);
+      absorb_row(c, cplx, nb, bnd, layer[t], t % 2 == 1 ? kL2R : kR2L, *opts, t, rbuf[t % 2], nbnd, logs);
       bnd = nbnd;
     }
   }
