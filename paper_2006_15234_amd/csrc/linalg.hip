@@ -823,15 +823,16 @@ template <bool CPLX>
 __global__ __launch_bounds__(256) void gauge_fix_kernel(const double* Uall, long long rows, int mp, double* Zall,
                                                         int k) {
   using T = typename S<CPLX>::T;
-  const int b = blockIdx.x, tid = threadIdx.x;
+  const int b = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const T* U = reinterpret_cast<const T*>(Uall) + (long long)b * rows * mp;
   T* Z = reinterpret_cast<T*>(Zall) + (long long)b * k * k;
-  __shared__ double sr[256], si[256];
-  __shared__ T phase;
+  __shared__ T phase[128];  // mp <= k <= 128
   const uint64_t base = mix64(mix64(0ull) + 0ull);
-  for (int i = 0; i < mp; ++i) {
+  // one wavefront per column (wave-uniform loop): lanes stride the rows, the
+  // projection is one wavefront sum
+  for (int i = wave; i < mp; i += 4) {
     double zr = 0.0, zi = 0.0;
-    for (long long r = tid; r < rows; r += blockDim.x) {
+    for (long long r = lane; r < rows; r += 64) {
       const uint64_t h = mix64(base + (uint64_t)(r + 1) * 0x9E3779B97F4A7C15ull);
       const double w = 2.0 * (double)(h >> 11) * 0x1p-53 - 1.0;
       const T u = U[r * mp + i];
@@ -842,27 +843,21 @@ __global__ __launch_bounds__(256) void gauge_fix_kernel(const double* Uall, long
         zr += w * u;
       }
     }
-    sr[tid] = zr;
-    si[tid] = zi;
-    __syncthreads();
-    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-      if (tid < s) {
-        sr[tid] += sr[tid + s];
-        si[tid] += si[tid + s];
-      }
-      __syncthreads();
-    }
-    if (tid == 0) {
-      const double m = sqrt(sr[0] * sr[0] + si[0] * si[0]);
+    zr = wave_sum(zr);
+    if constexpr (CPLX) zi = wave_sum(zi);
+    if (lane == 0) {
       if constexpr (CPLX) {
-        phase = m > 0 ? T{sr[0] / m, -si[0] / m} : T{1.0, 0.0};  // conj(z)/|z|
+        const double m = sqrt(zr * zr + zi * zi);
+        phase[i] = m > 0 ? T{zr / m, -zi / m} : T{1.0, 0.0};  // conj(z)/|z|
       } else {
-        phase = (sr[0] < 0) ? -1.0 : 1.0;
+        phase[i] = zr < 0 ? -1.0 : 1.0;
       }
     }
-    __syncthreads();
-    for (int r = tid; r < k; r += blockDim.x) Z[(long long)r * k + i] = S<CPLX>::mul(Z[(long long)r * k + i], phase);
-    __syncthreads();
+  }
+  __syncthreads();
+  for (int e = tid; e < k * mp; e += 256) {
+    const int r = e / mp, i = e - r * mp;
+    Z[(long long)r * k + i] = S<CPLX>::mul(Z[(long long)r * k + i], phase[i]);
   }
 }
 
@@ -1095,6 +1090,7 @@ void fill_value(Ctx& ctx, double* p, int64_t n, double v, bool cplx) {
 
 void gauge_fix(Ctx& ctx, bool cplx, const double* U, int64_t rows, int64_t mp, double* Z, int64_t k,
                int batch) {
+  HP_REQUIRE(mp >= 1 && mp <= k && k <= 128, HPEPS_ERR_SHAPE, "canonical phase: k above 128");
   if (cplx)
     gauge_fix_kernel<true><<<batch, 256, 0, ctx.stream>>>(U, rows, (int)mp, Z, (int)k);
   else
