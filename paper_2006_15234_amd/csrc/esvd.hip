@@ -376,7 +376,10 @@ void orthogonalize(Ctx& ctx, bool cplx, double* Y, double* P, int64_t n, int64_t
   chol_inv(ctx, cplx, w.G, n, k, batch, 2, w.Rinv, nullptr, w.flags);
   apply_rinv(ctx, cplx, P, n, k, batch, w.Rinv, Y, nullptr);
   if (Rt_inv) chain_rinv(ctx, cplx, Rt_inv, w.Rinv, S, k, batch);
-  gram(ctx, cplx, Y, n, k, batch, w.G, nullptr);
+  // third pass: the Gram only of flagged instances (the factor step writes
+  // the identity for the others without reading G); a recording tape keeps
+  // every Gram
+  gram(ctx, cplx, Y, n, k, batch, w.G, taping(ctx) ? nullptr : w.flags);
   chol_inv(ctx, cplx, w.G, n, k, batch, 3, w.Rinv, nullptr, w.flags);
   apply_rinv(ctx, cplx, Y, n, k, batch, w.Rinv, P, w.flags);
   if (Rt_inv) chain_rinv(ctx, cplx, Rt_inv, w.Rinv, S, k, batch);
@@ -392,7 +395,7 @@ void cholqr_r(Ctx& ctx, bool cplx, const double* Y, double* S1, double* S2, int6
   gram(ctx, cplx, S1, n, k, batch, w.G, nullptr);
   chol_inv(ctx, cplx, w.G, n, k, batch, 2, w.Rinv, w.Racc, w.flags);
   apply_rinv(ctx, cplx, S1, n, k, batch, w.Rinv, S2, w.flags);
-  gram(ctx, cplx, S2, n, k, batch, w.G, nullptr);
+  gram(ctx, cplx, S2, n, k, batch, w.G, taping(ctx) ? nullptr : w.flags);
   chol_inv(ctx, cplx, w.G, n, k, batch, 3, w.Rinv, w.Racc, w.flags);
   stats_reduce(ctx, w.flags, nullptr, batch, ctx.stats_dev);
 }

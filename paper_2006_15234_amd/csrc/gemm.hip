@@ -77,6 +77,7 @@ struct GemmArgs {
   const double* nscale;
   long long nscale_ld;
   const int* copy_if_zero;
+  const int* skip_if_zero;
   void* partial;
   unsigned nA_bytes, nB_bytes;  // per-instance operand extents (buffer ranges)
 };
@@ -271,6 +272,7 @@ __device__ __forceinline__ void gemm_item(const GemmArgs& g, int w, unsigned cha
     }
     return;
   }
+  if (g.skip_if_zero && g.skip_if_zero[b] == 0) return;  // whole block: b is per work item
 
   const int kbeg = ks * g.kchunk;
   const int kend = min(g.K, kbeg + g.kchunk);
@@ -808,6 +810,7 @@ __global__ void splitk_reduce_kernel(GemmArgs g, int batch) {
   for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < total;
        t += (long long)gridDim.x * blockDim.x) {
     const int b = (int)(t / MN);
+    if (g.skip_if_zero && g.skip_if_zero[b] == 0) continue;
     const long long mn = t % MN;
     const int m = (int)(mn / g.N), n = (int)(mn % g.N);
     const double* P = reinterpret_cast<const double*>(g.partial);
@@ -1333,6 +1336,7 @@ void gemm(Ctx& ctx, Prec prec, const GemmDesc& d, const GemmCall& c) {
   a.nscale = c.nscale;
   a.nscale_ld = c.nscale_ld;
   a.copy_if_zero = c.copy_if_zero;
+  a.skip_if_zero = c.skip_if_zero;
   // per-instance extents for the buffer resources (byte offsets are 32-bit)
   const int64_t elt_in = prec == Prec::F32 ? 4 : prec == Prec::BF16 ? 2 : (cplx ? 16 : 8);
   HP_REQUIRE(nA * elt_in < (1LL << 32) - 16 && nB * elt_in < (1LL << 32) - 16, HPEPS_ERR_UNSUPPORTED,
@@ -1350,14 +1354,16 @@ void gemm(Ctx& ctx, Prec prec, const GemmDesc& d, const GemmCall& c) {
 
   // short reductions (output columns in contiguous runs): the store-bound
   // kernel; below ~70 columns the MFMA tiles were measured as fast or faster
-  if (!cplx && !c.copy_if_zero && ctx.smallk && ctx.gemm_force.cfg < 0 && d.K <= 16 && d.N >= 72 &&
+  if (!cplx && !c.copy_if_zero && !c.skip_if_zero && ctx.smallk && ctx.gemm_force.cfg < 0 && d.K <= 16 &&
+      d.N >= 72 &&
       reinterpret_cast<uintptr_t>(c.C) % 16 == 0 &&
       contiguous_runs(d.Cn, prec == Prec::F64 || c.out_f64 ? 2 : 4)) {
     run_smallk(ctx, prec, d, c, a);
     return;
   }
   // few rows over wide operands: the read-bound kernel
-  if (!cplx && !c.copy_if_zero && ctx.smallk && ctx.gemm_force.cfg < 0 && d.M <= 8 && d.N >= 256 &&
+  if (!cplx && !c.copy_if_zero && !c.skip_if_zero && ctx.smallk && ctx.gemm_force.cfg < 0 && d.M <= 8 &&
+      d.N >= 256 &&
       d.K <= kSmMaxK) {
     const int vn = prec == Prec::F64 ? 2 : 4;
     const int64_t ein = prec == Prec::F64 ? 8 : prec == Prec::F32 ? 4 : 2;

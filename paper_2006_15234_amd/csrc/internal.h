@@ -82,6 +82,7 @@ struct GemmCall {
   int64_t nscale_ld = 0;
   bool accumulate = false;         // C += result
   const int* copy_if_zero = nullptr; // per batch flag: when 0, C := A (no product)
+  const int* skip_if_zero = nullptr; // per batch flag: when 0, the instance is skipped (C untouched)
   // storage types (F32 / BF16 compute only): inputs float / bf16; output that
   // type, or double when out_f64
   bool out_f64 = true;
@@ -108,6 +109,7 @@ void autotune_import(Ctx& ctx, const std::string& json);
 // ---------------------------------------------------------------------------
 // small dense linear algebra kernels (launchers)
 // Gram: G[b] = Y[b]^H Y[b] (Y: n x k row-major, batch stride n*k); G k x k.
+// With `active`, instances whose flag is 0 are skipped (G[b] left as it was).
 void gram(Ctx& ctx, bool cplx, const void* Y, int64_t n, int64_t k, int batch, double* G,
           const int* active);
 // CholeskyQR step on G (k x k, Hermitian): writes Rinv (k x k upper).  pass 1

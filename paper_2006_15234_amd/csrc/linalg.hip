@@ -886,7 +886,7 @@ void sketch(Ctx& ctx, void* out, bool f32, int64_t n, int64_t k, int batch, uint
 }
 
 void gram(Ctx& ctx, bool cplx, const void* Y, int64_t n, int64_t k, int batch, double* G,
-          const int* /*active*/) {
+          const int* active) {
   GemmDesc d;
   d.M = k;
   d.N = k;
@@ -905,6 +905,7 @@ void gram(Ctx& ctx, bool cplx, const void* Y, int64_t n, int64_t k, int batch, d
   c.sC = k * k;
   c.batch = batch;
   c.conjA = cplx;
+  c.skip_if_zero = active;
   gemm(ctx, cplx ? Prec::C128 : Prec::F64, d, c);
 }
 
