@@ -185,3 +185,70 @@ def test_fix_gauge_canonical_and_product_invariant():
     # idempotent, and any column phase change is undone
     U3, _, V3 = rsvd.fix_gauge(U2 * np.exp(1j * np.arange(4)), s2, V2 * np.exp(-1j * np.arange(4))[:, None])
     assert np.allclose(U3, U2, atol=1e-14) and np.allclose(V3, V2, atol=1e-14)
+
+
+def _explicit_power_reference(A, omega, m, q):
+    """Alg. 4 (Sec. IV-A) by its definition rather than its steps: after q
+    power iterations the sketch spans range((A A^*)^q A Omega), and the result
+    is the best rank-m' approximation of A within that subspace, P (P^* A)_m'.
+    The power is applied to the raw sketch without intermediate
+    orthogonalization, the basis comes from an SVD instead of a QR, and the
+    projected matrix P^* A is formed explicitly."""
+    Y = A @ omega
+    for _ in range(q):
+        Y = A @ (A.conj().T @ Y)
+    P = np.linalg.svd(Y, full_matrices=False)[0]
+    W, s, Vh = np.linalg.svd(P.conj().T @ A, full_matrices=False)
+    mp = min(m, omega.shape[1])
+    return P @ W[:, :mp], s[:mp], Vh[:mp]
+
+
+@pytest.mark.parametrize("complex_", [False, True])
+def test_rsvd_power_iterations_match_explicit_krylov_power(complex_):
+    """Pins the power loop: for q = 0..3 the randomized SVD equals the best
+    rank-m' approximation of A inside range((A A^*)^q A Omega), computed from
+    the explicit matrix power.  A gently decaying spectrum keeps the explicit
+    power well conditioned (its columns span 0.9^(2q+1) decades at most) while
+    the tail beyond k is large enough that every q gives a different answer,
+    so a dropped or miscounted iteration fails."""
+    rng = np.random.default_rng(21)
+    n_rows, n_cols, k, m = 60, 50, 8, 5
+    Ul = np.linalg.qr(_rand((n_rows, n_cols), rng, complex_))[0]
+    Vr = np.linalg.qr(_rand((n_cols, n_cols), rng, complex_))[0]
+    sv = 0.9 ** np.arange(n_cols)
+    A = (Ul * sv) @ Vr.conj().T
+    om = sketch(4, 2, n_cols, k)
+    prods = []
+    for q in range(4):
+        U, s, Vh = rsvd.randomized_svd(lambda X: A @ X, lambda Y: A.conj().T @ Y,
+                                       n_rows, n_cols, m, q, om)
+        Ur, sr, Vhr = _explicit_power_reference(A, om, m, q)
+        assert np.allclose(s, sr, rtol=0, atol=1e-11 * sv[0])
+        prod = (U * s) @ Vh
+        assert np.allclose(prod, (Ur * sr) @ Vhr, rtol=0, atol=1e-11 * sv[0])
+        prods.append(prod)
+    # each extra iteration changes the result far above the 1e-11 tolerance
+    for q in range(3):
+        assert np.abs(prods[q + 1] - prods[q]).max() > 1e-6 * sv[0]
+
+
+def test_rsvd_error_ratio_per_power_iteration():
+    """Halko et al.'s bound (cited in Sec. IV-A) tightens geometrically with q:
+    on a pair network whose spectrum decays slowly the ratio of the error to
+    the optimal rank-m error must fall into a distinct band for each q
+    (q = 0 about 1.2, then within 1e-3, 1e-5, 1e-7 of the optimum)."""
+    Bl, Br, T1, T2 = synth.pair_instance(m=6, D=2, d=2, seed=0, instance=0)
+    op = pair_operator(Bl, Br, T1, T2)
+    A = op.explicit()
+    m, k = 6, 10
+    om = sketch(0, 1, op.n_cols, k)
+    s_ref = np.linalg.svd(A, compute_uv=False)
+    opt = np.sqrt(np.sum(s_ref[m:] ** 2))
+    ratio = []
+    for q in range(4):
+        U, s, Vh = rsvd.randomized_svd(op.apply, op.apply_adj, op.n_rows, op.n_cols, m, q, om)
+        ratio.append(np.linalg.norm(A - (U * s) @ Vh) / opt)
+    assert ratio[0] > 1.1
+    assert 1 + 1e-5 < ratio[1] <= 1.001
+    assert 1 + 1e-8 < ratio[2] <= 1 + 1e-5
+    assert 1 <= ratio[3] <= 1 + 1e-7
