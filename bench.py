@@ -19,13 +19,22 @@ independent of how the kernels actually evaluate it.  The same step with
 FP32 and with BF16 operator applications (FP32 accumulation; FP64
 orthogonalization and SVD) is reported beside it with its singular-value
 deviation from the FP64 result.  Side blocks: the D=8 boundary-bond-64
-variant of the step, batched ITE sweeps of a 16x16 D=8 Ising PEPS, and the
-reverse-mode gradient of the 8x8 D=4 complex Heisenberg energy (time of the
-energy and of energy plus gradient).
+variant of the step; the latency of the 4x4 D=2 m=4 norm; the 12x12 D=10
+m=100 boundary-contraction norm in FP64 (1 and 2 power iterations), FP32 and
+BF16 (2 power iterations, compared with FP64 at the same iteration count);
+batched ITE sweeps of a 16x16 D=8 Ising PEPS; amplitudes by the one-layer
+boundary MPS; and the reverse-mode gradient of the 8x8 D=4 complex Heisenberg
+energy (time of the energy and of energy plus gradient).
+
+The roofline object's `achieved` counts the algorithmic flops of the stage the
+dominant GEMM class performs (the boundary-first middle product executes d
+times the boundary stage's work; only that stage's count is credited), with
+the executed rate beside it.
 """
 import argparse
 import json
 import os
+import re
 import sys
 import time
 
@@ -87,15 +96,41 @@ def measured_traffic(kernel):
     return t["bytes_per_launch"]
 
 
-def dominant_roofline(kernel, prof):
-    """Roofline entry of the dominant kernel class from its live HIP-event timing: the bound is
-    the HBM roof when the class's algorithmic intensity is below the FP64 ridge point."""
+def product_shape(kernel):
+    """(M, N, K, batch) of a GEMM class name such as gemm_f64_48x128k16_M216_N3168_K216_b64."""
+    m = re.search(r"_M(\d+)_N(\d+)_K(\d+)_b(\d+)", kernel)
+    return tuple(int(v) for v in m.groups()) if m else None
+
+
+def pair_alg_ratio(kernel, m=M, D=DB, d=DP, k=RANK + OVERS):
+    """Algorithmic over executed flops of a GEMM class of the pair einsumsvd.  The operator's
+    algorithmic count is fixed by the classic contraction order (ket s1, bra s2, boundary s3,
+    carry s4).  The boundary-first order runs the boundary tensor before the bra and then
+    contracts the bra with the physical leg still open: that product executes d times the
+    boundary stage's 2 D^4 m^2 k, so only 1/d of its flops are algorithmic.  Every other
+    product executes exactly the work the formula counts for it."""
+    shp = product_shape(kernel)
+    if shp is None:
+        return 1.0
+    Mq, Nq, Kq, _ = shp
+    if 2 * Mq * Nq * Kq == 2 * d * D ** 4 * m * m * k:
+        return 1.0 / d
+    return 1.0
+
+
+def dominant_roofline(kernel, prof, alg_ratio=1.0):
+    """Roofline entry of the dominant kernel class from its live HIP-event timing.  `achieved`
+    uses the algorithmic flops of the stage the class performs (executed flops times
+    alg_ratio); the executed rate is reported beside it.  The bound is the HBM roof when the
+    class's algorithmic intensity is below the FP64 ridge point."""
     n = prof["launches"]
     t = prof["ms"] / n * 1e-3
-    flops, byts = prof["flops"] / n, prof["bytes"] / n
+    exe, byts = prof["flops"] / n, prof["bytes"] / n
+    flops = exe * alg_ratio
     ridge = MFMA_F64_PEAK_TFLOPS * 1e12 / (HBM_PEAK_GBS * 1e9)
     base = {"kernel": kernel, "launches": n, "avg_launch_us": round(t * 1e6, 3),
-            "flops_per_launch": flops, "alg_bytes_per_launch": byts,
+            "flops_per_launch": flops, "executed_flops_per_launch": exe,
+            "executed_tflops": round(exe / t / 1e12, 3), "alg_bytes_per_launch": byts,
             "intensity_flop_per_byte": round(flops / byts, 3), "traffic": measured_traffic(kernel)}
     if flops / byts < ridge:
         a = byts / t / 1e9
@@ -107,19 +142,23 @@ def dominant_roofline(kernel, prof):
                 frac=round(a / MFMA_F64_PEAK_TFLOPS, 4))
 
 
-def class_entry(a):
+def class_entry(a, alg_ratio=1.0):
     """Time of a kernel class in the profiled step, and for GEMM classes the bound and the
-    fraction of it reached (algorithmic flops and bytes of the class, FP64 peaks)."""
+    fraction of it reached (algorithmic flops -- executed flops times alg_ratio -- and bytes
+    of the class, FP64 peaks)."""
     e = {"ms_per_step": round(a["ms"], 4), "launches": a["launches"]}
     if a["flops"] > 0 and a["bytes"] > 0 and a["ms"] > 0:
         t = a["ms"] * 1e-3
+        fl = a["flops"] * alg_ratio
         ridge = MFMA_F64_PEAK_TFLOPS * 1e12 / (HBM_PEAK_GBS * 1e9)
-        if a["flops"] / a["bytes"] < ridge:
+        if fl / a["bytes"] < ridge:
             e.update(bound="hbm", achieved_gbs=round(a["bytes"] / t / 1e9, 1),
                      frac=round(a["bytes"] / t / 1e9 / HBM_PEAK_GBS, 4))
         else:
-            e.update(bound="mfma", achieved_tflops=round(a["flops"] / t / 1e12, 2),
-                     frac=round(a["flops"] / t / 1e12 / MFMA_F64_PEAK_TFLOPS, 4))
+            e.update(bound="mfma", achieved_tflops=round(fl / t / 1e12, 2),
+                     frac=round(fl / t / 1e12 / MFMA_F64_PEAK_TFLOPS, 4))
+        if alg_ratio != 1.0:
+            e["executed_tflops"] = round(a["flops"] / t / 1e12, 2)
     return e
 
 
@@ -157,32 +196,57 @@ def d8_variant(hp, ctx, steps, m=64, D=8, d=2, rank=64, p=8, q=2, batch=16):
     hp.profile_stop(ctx)
     hp.profile_by_shape(ctx, False)
     flops = step_flops(m, D, d, rank, p, q) * batch
-    achieved = prof["flops"] / (prof["ms"] * 1e-3) / 1e12
+    ratio = lambda n: pair_alg_ratio(n, m, D, d, min(rank + p, m * D * D))
+    achieved = prof["flops"] * ratio(dominant) / (prof["ms"] * 1e-3) / 1e12
     return {"workload": f"pair einsumsvd m={m} D={D} d={d} rank={rank} p={p} q={q}, {batch} instances",
             "value": round(flops / (ms * 1e-3) / 1e9, 2), "unit": "GFLOP/s", "ms_per_step": round(ms, 3),
             "frac_of_fp64_peak": round(flops / (ms * 1e-3) / 1e12 / MFMA_F64_PEAK_TFLOPS, 4),
             "dominant_kernel": dominant, "dominant_achieved_tflops": round(achieved, 3),
             "dominant_frac": round(achieved / MFMA_F64_PEAK_TFLOPS, 4),
-            "kernel_classes": {n: class_entry(a) for n, a in sorted(agg.items(), key=lambda x: -x[1]["ms"])}}
+            "kernel_classes": {n: class_entry(a, ratio(n)) for n, a in sorted(agg.items(), key=lambda x: -x[1]["ms"])}}
+
+
+def zipup_einsumsvd_flops(a, x, b, h, u, c, y, g, p_, m, k, q):
+    """Algorithmic flops of one zip-up einsumsvd (Alg. 4 on the operator with rows (a,x,X)
+    and columns (y,Y,c,g,G); X = x, H = h, U = u, Y = y, G = g for a ket/bra pair):
+    2(q+1) operator applications of the four stages s1 = 2 (u h p)(y g)(y c g k),
+    s2 = 2 (u h)(y g p)(u h c k), s3 = 2 b (u u c)(h h k), s4 = 2 (a x x)(b h h) k, (q+1)
+    Householder-equivalent QRs of each panel and the two factor products."""
+    rows, cols = a * x * x, y * y * c * g * g
+    fa = (2 * (u * h * p_) * (y * g) * (y * c * g * k) + 2 * (u * h) * (y * g * p_) * (u * h * c * k)
+          + 2 * b * (u * u * c) * (h * h * k) + 2 * (a * x * x) * (b * h * h) * k)
+    fqr = lambda nn: 2 * nn * k * k - 2 * k ** 3 / 3
+    return 2 * (q + 1) * fa + (q + 1) * (fqr(rows) + fqr(cols)) + 2 * min(m, k) * k * (rows + cols)
 
 
 def c3_flops(n=12, D=10, d=2, m=100, p=8, q=1):
-    """Algorithmic flops of one peps_norm of an n x n lattice: the bulk einsumsvd count of
-    the zip-up operator (s1, s2: 2 d D^6 m k each; s3, s4: 2 D^4 m^2 k each) times the
-    (n-2)(n-1) truncating steps, plus the orthogonalizations and factor products."""
-    k = m + p
-    fa = 4 * d * D ** 6 * m * k + 4 * D ** 4 * m * m * k
-    rows, cols = m * D * D, m * D ** 4
-    fqr = lambda nn: 2 * nn * k * k - 2 * k ** 3 / 3
-    step = 2 * (q + 1) * fa + (q + 1) * (fqr(rows) + fqr(cols)) + 2 * m * k * (rows + cols)
-    return step * (n - 2) * (n - 1)
+    """Algorithmic flops of one peps_norm of an n x n lattice with bond D: the einsumsvds of
+    the (n-2) zip-up rows, each column at its own size.  Row 1 is exact (boundary bonds D^2),
+    the first column of a row starts from a carry with a = 1, the last has c = g = 1, and every
+    kept rank is min(m, k, rows, cols) with k = min(m + p, rows, cols).  The exact first and
+    last rows and the exact first-column carries are not counted."""
+    bonds = [1] + [D * D] * (n - 1) + [1]          # boundary bonds after row 1
+    total = 0.0
+    for _ in range(n - 2):
+        new = [1] * (n + 1)
+        for jj in range(1, n):
+            a, b, c = new[jj - 1], bonds[jj], bonds[jj + 1]
+            g = 1 if jj == n - 1 else D
+            rows, cols = a * D * D, D * D * c * g * g
+            k = min(m + p, rows, cols)
+            total += zipup_einsumsvd_flops(a, D, b, D, D, c, D, g, d, m, k, q)
+            new[jj] = min(m, k)
+        bonds = new
+    return total
 
 
 def c3_norm(hp, args, n=12, D=10, d=2, m=100, p=8):
-    """peps_norm of a 12 x 12 lattice, bond 10, boundary bond 100 (FP64 q=1; FP32 and BF16
-    q=2), iid N(0,1) sites normalised: time per norm and log-norm deviation from FP64.
-    GEMM variants as in the main measurement: the shipped choices, and products not in
-    them tuned during the untimed first norm of each precision."""
+    """peps_norm of a 12 x 12 lattice, bond 10, boundary bond 100, iid N(0,1) sites normalised:
+    FP64 with 1 and with 2 power iterations, FP32 and BF16 operator applications with 2.  Each
+    mixed form is compared with FP64 at the same q (|dlog N| against the FP32 / BF16 bounds
+    1e-4 / 3e-2) and its speedup is per norm at that accuracy.  GEMM variants as in the main
+    measurement: the shipped choices, and products not in them tuned during the untimed first
+    norm of each precision."""
     import numpy as np
     import torch
 
@@ -193,32 +257,68 @@ def c3_norm(hp, args, n=12, D=10, d=2, m=100, p=8):
     if not args.no_autotune and args.tune_cache and os.path.exists(args.tune_cache):
         hp.autotune_load(ctx, args.tune_cache)
     hp.autotune_enable(ctx, not args.no_autotune)
-    out = {"workload": f"peps_norm {n}x{n} D={D} d={d} m={m} p={p}"}
-    ref = None
-    for prec, q in (("f64", 1), ("f32", 2), ("bf16", 2)):
+    out = {"workload": f"peps_norm {n}x{n} D={D} d={d} m={m} p={p}",
+           "einsumsvds_per_norm": (n - 2) * (n - 1)}
+    ref = {}
+    tol = {"f32": 1e-4, "bf16": 3e-2}
+    for prec, q in (("f64", 1), ("f64", 2), ("f32", 2), ("bf16", 2)):
         hp.peps_norm(ctx, dev, rank=m, oversample=p, power_iters=q, precision=prec)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         ln, ph = hp.peps_norm(ctx, dev, rank=m, oversample=p, power_iters=q, precision=prec)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
-        if ref is None:
-            ref = ln
-            hp.profile_by_shape(ctx, True)
-            hp.profile_start(ctx)
-            hp.peps_norm(ctx, dev, rank=m, oversample=p, power_iters=q, precision=prec)
-            agg = hp.profile_read(ctx)
-            hp.profile_stop(ctx)
-            hp.profile_by_shape(ctx, False)
-            out["f64_kernel_classes"] = {
-                k: {"ms": round(a["ms"], 2), "launches": a["launches"],
-                    "tflops": round(a["flops"] / max(a["ms"], 1e-9) / 1e9, 2)}
-                for k, a in sorted(agg.items(), key=lambda x: -x[1]["ms"])[:12]}
         fl = c3_flops(n, D, d, m, p, q)
-        out[prec] = {"q": q, "s_per_norm": round(dt, 4), "log_norm": ln,
-                     "dlog_vs_f64": abs(ln - ref), "alg_tflops": round(fl / dt / 1e12, 3),
-                     "frac_of_fp64_peak": round(fl / dt / 1e12 / MFMA_F64_PEAK_TFLOPS, 4)}
+        e = {"q": q, "s_per_norm": round(dt, 4), "log_norm": ln, "alg_flops": fl,
+             "alg_tflops": round(fl / dt / 1e12, 3),
+             "frac_of_fp64_peak": round(fl / dt / 1e12 / MFMA_F64_PEAK_TFLOPS, 4)}
+        if prec == "f64":
+            ref[q] = (ln, dt)
+            if q == 1:
+                hp.profile_by_shape(ctx, True)
+                hp.profile_start(ctx)
+                hp.peps_norm(ctx, dev, rank=m, oversample=p, power_iters=q, precision=prec)
+                agg = hp.profile_read(ctx)
+                hp.profile_stop(ctx)
+                hp.profile_by_shape(ctx, False)
+                out["f64_kernel_classes"] = {
+                    k: {"ms": round(a["ms"], 2), "launches": a["launches"],
+                        "executed_tflops": round(a["flops"] / max(a["ms"], 1e-9) / 1e9, 2)}
+                    for k, a in sorted(agg.items(), key=lambda x: -x[1]["ms"])[:12]}
+            else:
+                e["dlog_vs_f64_q1"] = abs(ln - ref[1][0])
+            out[f"f64_q{q}"] = e
+        else:
+            dl = abs(ln - ref[q][0])
+            e.update(dlog_vs_f64_same_q=dl, tol=tol[prec], within_tol=bool(dl <= tol[prec]),
+                     speedup_vs_f64_same_q=round(ref[q][1] / dt, 3),
+                     speedup_vs_f64_q1=round(ref[1][1] / dt, 3))
+            out[prec] = e
     return out, ctx
+
+
+def c1_latency(hp, reps=10, n=4, D=2, m=4, p=4, q=1):
+    """Latency of one plain FP64 peps_norm of the 4 x 4, bond-2 lattice (boundary bond 4,
+    oversampling 4, 1 power iteration): median over `reps` calls, each ending with the host
+    read of the result."""
+    import numpy as np
+    import torch
+
+    import synth
+    peps = synth.random_peps(n, n, D=D, seed=0)
+    dev = [[torch.from_numpy(np.ascontiguousarray(t)).cuda() for t in row] for row in peps]
+    ctx = hp.Context(0)
+    for _ in range(3):
+        hp.peps_norm(ctx, dev, rank=m, oversample=p, power_iters=q)
+    ts = []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ln, _ = hp.peps_norm(ctx, dev, rank=m, oversample=p, power_iters=q)
+        ts.append(time.perf_counter() - t0)
+    return {"workload": f"peps_norm {n}x{n} D={D} d=2 m={m} p={p} q={q}, FP64", "log_norm": ln,
+            "us_median": round(float(np.median(ts)) * 1e6, 1), "us_min": round(min(ts) * 1e6, 1),
+            "reps": reps}
 
 
 def c5_gradient(hp, reps, n=8, D=4, d=2, m=16, p=8, q=1):
@@ -364,6 +464,8 @@ def main():
                     help="time the 8x8 D=4 complex energy gradient this many times (0 skips)")
     ap.add_argument("--c3", action="store_true",
                     help="only time peps_norm of the 12x12, D=10, m=100 lattice in FP64, FP32 and BF16")
+    ap.add_argument("--no-c3", action="store_true",
+                    help="leave the 12x12, D=10, m=100 norm block out of the full run")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a device-to-device copy of MIB MiB (reference for the HBM byte counters)")
     args = ap.parse_args()
@@ -467,7 +569,7 @@ def main():
     s16 = out16[1].cpu().numpy()
     eps16 = float(np.max(np.abs(s16 - s64) / s64[:, :1]))
 
-    roofline = dominant_roofline(dominant, prof)
+    roofline = dominant_roofline(dominant, prof, pair_alg_ratio(dominant))
     res = {
         "metric": "einsumsvd GFLOP/s & boundary-contraction sweep time vs plain FP64, same GPU, at fixed eps",
         "value": round(value, 2),
@@ -496,8 +598,14 @@ def main():
                        "frac_of_bf16_peak": round(flops / (ms16 * 1e-3) / 1e12 / MFMA_BF16_PEAK_TFLOPS, 5),
                        "eps_sigma_vs_f64": eps16},
         "autotune": not args.no_autotune,
-        "kernel_classes": {n: class_entry(a) for n, a in sorted(agg.items(), key=lambda x: -x[1]["ms"])},
+        "kernel_classes": {n: class_entry(a, pair_alg_ratio(n))
+                           for n, a in sorted(agg.items(), key=lambda x: -x[1]["ms"])},
     }
+    res["c1_norm_latency"] = c1_latency(hp)
+    if not args.no_c3:
+        res["c3_norm"], ctx3 = c3_norm(hp, args)
+        hp.autotune_import(ctx, hp.autotune_export(ctx3))
+        del ctx3
     if args.c4 > 0:
         res["c4_ite"] = c4_ite(hp, args.c4)
     if args.amp > 0:
