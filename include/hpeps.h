@@ -128,6 +128,10 @@ typedef struct {
   int32_t jacobi_sweeps;    /* largest sweep count of any small SVD          */
   int32_t numeric_errors;   /* factorizations that met non-finite values     */
   int32_t not_converged;    /* small SVDs that hit the sweep cap             */
+  int32_t orth_householder; /* flagged sketches whose orthogonalization (or  */
+                            /* projected factor) was redone by Householder   */
+                            /* QR (the fallback of Alg. 4's orthogonalize)   */
+  int32_t reserved;
 } hpeps_esvd_info;
 
 /* ---- context ---------------------------------------------------------- */

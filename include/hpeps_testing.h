@@ -28,6 +28,15 @@ hpeps_status hpeps_test_gemm(hpeps_ctx* ctx, hpeps_dtype dtype, int64_t batch, i
 hpeps_status hpeps_test_orthogonalize(hpeps_ctx* ctx, hpeps_dtype dtype, int64_t batch, int64_t n,
                                       int64_t k, void* Y, void* P);
 
+/* Householder QR (the orthogonalization fallback for sketches flagged as
+ * rank-deficient or very ill-conditioned; tall-skinny, one reduction level)
+ * of every instance of Y [n,k] (unchanged): the orthonormal Q [n,k] to P and
+ * the upper-triangular R [k,k] (zero below the diagonal) to R, each when
+ * non-NULL, Y = Q R.  LAPACK's reflector convention (R's diagonal may be
+ * negative; an exactly zero column gives tau = 0).  k <= 128, n >= k. */
+hpeps_status hpeps_test_householder(hpeps_ctx* ctx, hpeps_dtype dtype, int64_t batch, int64_t n,
+                                    int64_t k, const void* Y, void* P, void* R);
+
 /* Small SVD stage: for the upper-triangular R [k,k] writes Z [k,k] (left
  * singular vectors of R^H, columns sorted by descending singular value) and
  * sigma [k] (double).  One-sided Jacobi. */

@@ -28,7 +28,8 @@ class EsvdOpts(C.Structure):
 class EsvdInfo(C.Structure):
     _fields_ = [("rank_kept", C.c_int64), ("sketch_width", C.c_int64),
                 ("orth_extra_passes", C.c_int32), ("jacobi_sweeps", C.c_int32),
-                ("numeric_errors", C.c_int32), ("not_converged", C.c_int32)]
+                ("numeric_errors", C.c_int32), ("not_converged", C.c_int32),
+                ("orth_householder", C.c_int32), ("reserved", C.c_int32)]
 
 
 class Peps(C.Structure):
@@ -113,6 +114,7 @@ _SIGS = {
     "hpeps_test_gemm": (C.c_int, [_P, C.c_int, C.c_int64, C.c_int64, C.c_int64, C.c_int64,
                                   C.c_int32, _P, _P, _P]),
     "hpeps_test_orthogonalize": (C.c_int, [_P, C.c_int, C.c_int64, C.c_int64, C.c_int64, _P, _P]),
+    "hpeps_test_householder": (C.c_int, [_P, C.c_int, C.c_int64, C.c_int64, C.c_int64, _P, _P, _P]),
     "hpeps_test_small_svd": (C.c_int, [_P, C.c_int, C.c_int64, C.c_int64, _P, _P, _P]),
     "hpeps_test_zip_apply": (C.c_int, [_P, C.c_int, C.c_int64, _I64P, _P, _P, _P, _P, C.c_int64,
                                        C.c_int32, _P, _P]),

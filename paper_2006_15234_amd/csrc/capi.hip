@@ -105,6 +105,8 @@ hpeps_status hpeps_get_info(hpeps_ctx* ctx, hpeps_esvd_info* info) {
     info->jacobi_sweeps = h[1];
     info->numeric_errors = h[2];
     info->not_converged = h[3];
+    info->orth_householder = h[4];
+    info->reserved = 0;
   });
 }
 

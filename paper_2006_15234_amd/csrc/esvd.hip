@@ -372,6 +372,11 @@ void orthogonalize(Ctx& ctx, bool cplx, double* Y, double* P, int64_t n, int64_t
   if (Rt_inv)
     HP_CHECK_HIP(hipMemcpyAsync(Rt_inv, w.Rinv, (size_t)batch * k * k * (cplx ? 16 : 8),
                                 hipMemcpyDeviceToDevice, ctx.stream));
+  // panels flagged in pass 1 (rank-deficient or very ill-conditioned): the
+  // Householder QR of Y replaces P before the next passes (which then leave
+  // it unchanged to rounding).  Not while differentiating: the adjoint of
+  // the orthogonalization is the CholeskyQR one.
+  if (!Rt_inv && !taping(ctx)) householder_qr(ctx, cplx, Y, n, k, batch, w.flags, FLAG_THIRD_PASS, P, nullptr);
   gram(ctx, cplx, P, n, k, batch, w.G, nullptr);
   chol_inv(ctx, cplx, w.G, n, k, batch, 2, w.Rinv, nullptr, w.flags);
   apply_rinv(ctx, cplx, P, n, k, batch, w.Rinv, Y, nullptr);
@@ -397,6 +402,8 @@ void cholqr_r(Ctx& ctx, bool cplx, const double* Y, double* S1, double* S2, int6
   apply_rinv(ctx, cplx, S1, n, k, batch, w.Rinv, S2, w.flags);
   gram(ctx, cplx, S2, n, k, batch, w.G, taping(ctx) ? nullptr : w.flags);
   chol_inv(ctx, cplx, w.G, n, k, batch, 3, w.Rinv, w.Racc, w.flags);
+  // flagged panels: R of the Householder QR of Y (kept unchanged above)
+  if (!taping(ctx)) householder_qr(ctx, cplx, Y, n, k, batch, w.flags, FLAG_THIRD_PASS, nullptr, w.Racc);
   stats_reduce(ctx, w.flags, nullptr, batch, ctx.stats_dev);
 }
 

@@ -112,6 +112,11 @@ void autotune_import(Ctx& ctx, const std::string& json);
 // With `active`, instances whose flag is 0 are skipped (G[b] left as it was).
 void gram(Ctx& ctx, bool cplx, const void* Y, int64_t n, int64_t k, int batch, double* G,
           const int* active);
+// Per-instance flag bits of the orthogonalization (set by the factor step,
+// read by the later passes, the Householder fallback and the diagnostics).
+constexpr int FLAG_THIRD_PASS = 2;   // ill-conditioned or rank-deficient: third pass / fallback
+constexpr int FLAG_NUMERIC = 4;      // non-finite values met
+constexpr int FLAG_HOUSEHOLDER = 8;  // the Householder fallback replaced the factor
 // CholeskyQR step on G (k x k, Hermitian): writes Rinv (k x k upper).  pass 1
 // may shift; flags[b] bit 1 is set when a third pass is needed, bit 2 on
 // non-finite values.  pass 3 is skipped (Rinv = I) unless bit 1 is set.
@@ -160,6 +165,15 @@ bool tape_keeps_workspace(const Ctx& ctx);
 // diag(out)[..] helpers for tests of the gemm itself are not exported.
 void copy_sigma(Ctx& ctx, const double* sigma_k, int64_t k, int64_t mp, int batch, double* out);
 void stats_reduce(Ctx& ctx, const int* flags, const int* sweeps, int batch, int* acc);
+// Householder QR (tall-skinny, one reduction level) of the row-major n x k
+// panels Y (batch stride n k, unchanged) of the instances whose flag has a
+// bit of `mask` (all instances when flags is null): the orthonormal Q to P
+// (row-major n x k) and / or R to R (row-major k x k, zero below the
+// diagonal), each when non-null; sets FLAG_HOUSEHOLDER on those instances.
+// Other instances' P and R are left untouched.  k <= 128.
+void householder_qr(Ctx& ctx, bool cplx, const double* Y, int64_t n, int64_t k, int batch, int* flags, int mask,
+                    double* P, double* R);
+int householder_blocks(int64_t n, int64_t k);
 // einsumsvd adjoint helpers (k x k / panel elementwise work, one workgroup per instance)
 void svd_bwd_core(Ctx& ctx, bool cplx, const double* ZZ, const double* VV, const double* s,
                   const double* sbar, int64_t k, int batch, double eps, double* G1H);

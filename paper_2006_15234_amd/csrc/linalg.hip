@@ -63,8 +63,6 @@ struct S<true> {
 };
 
 constexpr int kSmallThreads = 1024;
-constexpr int FLAG_THIRD_PASS = 2;
-constexpr int FLAG_NUMERIC = 4;
 
 // ---------------------------------------------------------------------------
 // sketch generator (SplitMix64 output function, counter based)
@@ -756,20 +754,21 @@ __global__ void copy_sigma_kernel(const double* sk, int k, int mp, int batch, do
 }
 
 // Diagnostics of a batch (third CholeskyQR passes, non-finite factors, the
-// largest Jacobi sweep count, capped sweeps): per-thread partials over the
+// largest Jacobi sweep count, capped sweeps, Householder fallbacks): per-thread partials over the
 // instances, one block reduction, one update of acc (integers: exact and
 // independent of the order).
 constexpr int kStatsThreads = 256;
 __global__ __launch_bounds__(kStatsThreads) void stats_kernel(const int* flags, const int* sweeps, int batch,
                                                               int* acc) {
-  __shared__ int part[4][kStatsThreads];
+  __shared__ int part[5][kStatsThreads];
   const int tid = threadIdx.x;
-  int third = 0, numeric = 0, smax = 0, capped = 0;
+  int third = 0, numeric = 0, smax = 0, capped = 0, house = 0;
   for (int b = tid; b < batch; b += kStatsThreads) {
     if (flags) {
       const int f = flags[b];
       third += (f & FLAG_THIRD_PASS) != 0;
       numeric += (f & FLAG_NUMERIC) != 0;
+      house += (f & FLAG_HOUSEHOLDER) != 0;
     }
     if (sweeps) {
       const int sw = sweeps[b];
@@ -781,6 +780,7 @@ __global__ __launch_bounds__(kStatsThreads) void stats_kernel(const int* flags, 
   part[1][tid] = numeric;
   part[2][tid] = smax;
   part[3][tid] = capped;
+  part[4][tid] = house;
   __syncthreads();
   for (int st = kStatsThreads / 2; st > 0; st >>= 1) {
     if (tid < st) {
@@ -788,6 +788,7 @@ __global__ __launch_bounds__(kStatsThreads) void stats_kernel(const int* flags, 
       part[1][tid] += part[1][tid + st];
       part[2][tid] = max(part[2][tid], part[2][tid + st]);
       part[3][tid] += part[3][tid + st];
+      part[4][tid] += part[4][tid + st];
     }
     __syncthreads();
   }
@@ -796,6 +797,7 @@ __global__ __launch_bounds__(kStatsThreads) void stats_kernel(const int* flags, 
     acc[2] += part[1][0];
     acc[1] = max(acc[1], part[2][0]);
     acc[3] += part[3][0];
+    acc[4] += part[4][0];
   }
 }
 

@@ -70,6 +70,16 @@ hpeps_status hpeps_test_orthogonalize(hpeps_ctx* ctx, hpeps_dtype dtype, int64_t
   });
 }
 
+hpeps_status hpeps_test_householder(hpeps_ctx* ctx, hpeps_dtype dtype, int64_t batch, int64_t n, int64_t k,
+                                    const void* Y, void* P, void* R) {
+  return guard_t(ctx, [&](hp::Ctx& c) {
+    const bool cplx = cplx_of(dtype);
+    HP_REQUIRE(Y && (P || R) && batch >= 1 && n >= k && k >= 1 && k <= 128, HPEPS_ERR_INVALID_ARG,
+               "bad Householder arguments");
+    hp::householder_qr(c, cplx, (const double*)Y, n, k, (int)batch, nullptr, 0, (double*)P, (double*)R);
+  });
+}
+
 hpeps_status hpeps_test_small_svd(hpeps_ctx* ctx, hpeps_dtype dtype, int64_t batch, int64_t k,
                                   const void* R, void* Z, double* sigma) {
   return guard_t(ctx, [&](hp::Ctx& c) {

@@ -162,3 +162,40 @@ def test_zipup_left_and_sqrt_absorb(ctx, absorb):
         ref = _product(U0[i].cpu().numpy(), s0[i].cpu().numpy(), R0[i].cpu().numpy(), hp.ABSORB_NONE)
         got = U1[i].cpu().numpy().reshape(-1, 6) @ R1[i].cpu().numpy().reshape(6, -1)
         assert np.max(np.abs(got - ref)) <= 1e-12 * float(s0[i, 0])
+
+
+@pytest.mark.parametrize("cplx,rows,cols,r,rank,p,q", [
+    (False, 300, 400, 10, 16, 8, 1),
+    (True, 200, 150, 7, 12, 6, 2),
+    (False, 64, 900, 5, 12, 4, 1),
+])
+def test_low_rank_operator_householder_fallback(ctx, cplx, rows, cols, r, rank, p, q):
+    """Forced breakdown of the Cholesky orthogonalization: the operator X Y has exact rank
+    r < k, so every sketch panel is rank-deficient (k - r null directions).  The flagged
+    panels are orthogonalized by the Householder fallback (counted in the diagnostics), and
+    the result matches the oracle's Alg. 4 (Householder QR, same sketch) at 1e-10: all kept
+    singular values (the k - r beyond the rank at rounding level on both sides), the
+    leading r singular pairs, and U Sigma V^*."""
+    rng = np.random.default_rng(5)
+    X = _rand(rng, (rows, r), cplx)
+    Y = _rand(rng, (r, cols), cplx)
+    seed, sid = 2, 7
+    hp.get_info(ctx)                                   # clear the diagnostics
+    U, s, R = hp.einsumsvd(ctx, "ab,bc->a|c", _dev(X), _dev(Y), rank=rank, oversample=p,
+                           power_iters=q, seed=seed, stream_id=sid, absorb=hp.ABSORB_NONE)
+    info = hp.get_info(ctx)
+    assert info["orth_householder"] >= 1
+    M = X @ Y
+    k = rsvd.sketch_width(rank, p, rows, cols)
+    Uo, so, Vho = rsvd.randomized_svd(lambda Z: M @ Z, lambda Z: M.conj().T @ Z, rows, cols, rank, q,
+                                      oracle_sketch(seed, sid, cols, k))
+    s = s.cpu().numpy()
+    assert np.max(np.abs(s - so)) <= 1e-10 * so[0]
+    assert np.max(s[r:]) <= 1e-13 * so[0]
+    Um = U.cpu().numpy().reshape(rows, rank)
+    Rm = R.cpu().numpy().reshape(rank, cols)
+    # leading pairs: same canonical phase on both sides
+    assert np.max(np.abs(Um[:, :r] - Uo[:, :r])) <= 1e-10
+    assert np.max(np.abs(Rm[:r] - Vho[:r])) <= 1e-10
+    assert np.max(np.abs((Um * s) @ Rm - (Uo * so) @ Vho)) <= 1e-10 * so[0]
+    assert np.max(np.abs(Um.conj().T @ Um - np.eye(rank))) <= 1e-12

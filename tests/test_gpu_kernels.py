@@ -252,3 +252,77 @@ def _zip_apply_case(ctx, cplx, dims):
     ry, rz = op.apply(X), op.apply_adj(P)
     assert np.max(np.abs(Y - ry)) < 1e-12 * np.abs(ry).max()
     assert np.max(np.abs(Z - rz)) < 1e-12 * np.abs(rz).max()
+
+
+def _householder(ctx, Y, cplx):
+    B, n, k = Y.shape
+    dY = _dev(Y)
+    dP = torch.zeros_like(dY)
+    dR = torch.full((B, k, k), 7.0, dtype=dY.dtype, device="cuda")
+    ctx.sync_stream()
+    ctx.check(ctx.lib.hpeps_test_householder(ctx.h, hp.C128 if cplx else hp.F64, B, n, k,
+                                             _p(dY), _p(dP), _p(dR)))
+    assert np.array_equal(dY.cpu().numpy(), Y)
+    return dP.cpu().numpy(), dR.cpu().numpy()
+
+
+@pytest.mark.parametrize("n,k,cplx,B", [(50, 7, False, 2), (300, 9, True, 1), (37, 37, True, 1),
+                                        (4000, 44, False, 3), (20000, 108, False, 1), (3000, 88, True, 1),
+                                        (129, 64, False, 2)])
+def test_householder_qr(ctx, n, k, cplx, B):
+    """Householder TSQR (the orthogonalization fallback).  Full-rank panels: Q orthonormal,
+    Q R = Y, R upper triangular and equal to LAPACK's R up to the signs of its rows (Q to
+    LAPACK's Q up to the same column signs).  Rank-deficient panels (an exactly zero and a
+    duplicated column): Q orthonormal, Q R = Y; with one row block (n < 4k) and only the zero
+    column, Q and R equal LAPACK's, reflector convention included (tau = 0 on the zero
+    column)."""
+    rng = np.random.default_rng(n + k)
+    Y = rng.standard_normal((B, n, k))
+    if cplx:
+        Y = Y + 1j * rng.standard_normal((B, n, k))
+    P, R = _householder(ctx, Y, cplx)
+    for b in range(B):
+        nrm = np.linalg.norm(Y[b], 2)
+        assert np.max(np.abs(P[b].conj().T @ P[b] - np.eye(k))) < 1e-13
+        assert np.max(np.abs(P[b] @ R[b] - Y[b])) < 1e-13 * nrm
+        assert np.all(np.tril(R[b], -1) == 0)
+        Q0, R0 = np.linalg.qr(Y[b])
+        ph = np.diag(R[b]) / np.diag(R0)             # unit-modulus row factors
+        assert np.max(np.abs(np.abs(ph) - 1)) < 1e-12
+        assert np.max(np.abs(R[b] - ph[:, None] * R0)) < 1e-12 * nrm
+        assert np.max(np.abs(P[b] - Q0 * ph.conj()[None, :])) < 1e-11
+    Yz = Y.copy()
+    Yz[:, :, 3] = 0
+    P, R = _householder(ctx, Yz, cplx)
+    for b in range(B):
+        assert np.max(np.abs(P[b].conj().T @ P[b] - np.eye(k))) < 1e-13
+        assert np.max(np.abs(P[b] @ R[b] - Yz[b])) < 1e-13 * np.linalg.norm(Yz[b], 2)
+        if n < 4 * k:
+            Q0, R0 = np.linalg.qr(Yz[b])
+            assert np.max(np.abs(P[b] - Q0)) < 1e-12
+            assert np.max(np.abs(R[b] - R0)) < 1e-12 * np.linalg.norm(Yz[b], 2)
+    Yd = Yz.copy()
+    Yd[:, :, 5] = Yd[:, :, 1]
+    P, R = _householder(ctx, Yd, cplx)
+    for b in range(B):
+        assert np.max(np.abs(P[b].conj().T @ P[b] - np.eye(k))) < 1e-13
+        assert np.max(np.abs(P[b] @ R[b] - Yd[b])) < 1e-13 * np.linalg.norm(Yd[b], 2)
+        assert np.all(np.tril(R[b], -1) == 0)
+
+
+def test_orthogonalize_rank_deficient_uses_householder(ctx):
+    """A panel of exact rank 10 < k = 24: the first Cholesky pass flags it, the Householder
+    fallback produces P, and P is orthonormal with range(P) containing range(Y) to rounding."""
+    rng = np.random.default_rng(3)
+    n, k, r = 3000, 24, 10
+    Y = rng.standard_normal((n, r)) @ rng.standard_normal((r, k))
+    dY = _dev(Y[None])
+    dP = torch.zeros_like(dY)
+    hp.get_info(ctx)
+    ctx.sync_stream()
+    ctx.check(ctx.lib.hpeps_test_orthogonalize(ctx.h, hp.F64, 1, n, k, _p(dY), _p(dP)))
+    info = hp.get_info(ctx)
+    assert info["orth_householder"] == 1
+    P = dP.cpu().numpy()[0]
+    assert np.max(np.abs(P.T @ P - np.eye(k))) < 1e-13
+    assert np.linalg.norm(Y - P @ (P.T @ Y)) < 1e-14 * np.linalg.norm(Y)
