@@ -454,6 +454,26 @@ hpeps_status hpeps_apply_two_site_gate(hpeps_ctx* ctx, hpeps_peps* peps,
                                        int32_t axis, const void* G, int64_t max_rank,
                                        int64_t* new_bond, double* sigma_out);
 
+/* ---- apply_two_site_gate without allocation -----------------------------
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * update, arguments, layouts, results and errors as hpeps_apply_two_site_gate,
+ * but every device buffer the call needs beyond the caller's sites, gate and
+ * sigma_out (staging copies of the two sites, the reflector scratch, the
+ * dimension and bond tables, the singular values) comes from a static
+ * 1 MiB array in the library's device image, one per GPU, resolved when a
+ * context is created on that GPU.  The call makes no hipMalloc / hipFree and
+ * no allocating library call.  Sizes whose buffers exceed the static array
+ * (2 copies of 2 max_rank^4 d doubles plus small tables, 256-byte aligned)
+ * return HPEPS_ERR_ALLOC before anything is enqueued; every size the
+ * QR-SVD kernel supports fits.  All calls on one GPU share that array: calls
+ * that overlap in time on one GPU (from several host threads or contexts)
+ * race and must be serialised by the caller.  Synchronises. */
+hpeps_status hpeps_apply_two_site_gate_noalloc(hpeps_ctx* ctx, hpeps_peps* peps,
+                                               const int64_t* capacity, int32_t i, int32_t j,
+                                               int32_t axis, const void* G, int64_t max_rank,
+                                               int64_t* new_bond, double* sigma_out);
+
 /* ---- batched imaginary-time-evolution sweep (TEBD, Sec. II-D) -----------
  * A plan owns the evolving PEPS in a device arena of fixed capacity
  * max_rank per bond.  Each sweep applies the gate of every bond, layer by

@@ -102,6 +102,8 @@ _SIGS = {
                                              C.c_double, C.POINTER(C.c_void_p), _DP]),
     "hpeps_apply_two_site_gate": (C.c_int, [_P, C.POINTER(Peps), _I64P, C.c_int32, C.c_int32,
                                             C.c_int32, _P, C.c_int64, _I64P, _P]),
+    "hpeps_apply_two_site_gate_noalloc": (C.c_int, [_P, C.POINTER(Peps), _I64P, C.c_int32, C.c_int32,
+                                            C.c_int32, _P, C.c_int64, _I64P, _P]),
     "hpeps_ite_plan_create": (C.c_int, [_P, C.POINTER(Peps), C.c_int32, _P, C.POINTER(C.c_int32),
                                         C.c_int64, C.POINTER(C.c_void_p)]),
     "hpeps_ite_run": (C.c_int, [_P, C.c_int32, C.c_int32]),

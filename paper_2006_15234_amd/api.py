@@ -512,11 +512,13 @@ def peps_norm_backward(ctx, ket, *, rank, oversample=0, power_iters=0, seed=0, b
     return ln.value, grads
 
 
-def apply_two_site_gate(ctx, sites, i, j, axis, G, max_rank):
+def apply_two_site_gate(ctx, sites, i, j, axis, G, max_rank, noalloc=False):
     """QR-SVD update (Alg. 1) of sites[i][j] and its right (axis 0) or lower
     (axis 1) neighbour with the gate G[out1,out2,in1,in2] (device tensor).
     ``sites`` is a list of rows of device tensors [u,d,l,r,p]; returns
-    (new lattice as a list of rows, kept singular values on the device)."""
+    (new lattice as a list of rows, kept singular values on the device).
+    noalloc selects hpeps_apply_two_site_gate_noalloc (the library's buffers
+    from its static device scratch instead of its workspace)."""
     torch = _torch()
     nrow, ncol = len(sites), len(sites[0])
     d = sites[0][0].shape[4]
@@ -536,8 +538,9 @@ def apply_two_site_gate(ctx, sites, i, j, axis, G, max_rank):
     nb = C.c_int64()
     Gd = G.contiguous()
     ctx.sync_stream()
-    ctx.check(ctx.lib.hpeps_apply_two_site_gate(ctx.h, C.byref(pk), capa, i, j, axis, _dev(Gd, "G"),
-                                                max_rank, C.byref(nb), _dev(sig, "sigma")))
+    fn = ctx.lib.hpeps_apply_two_site_gate_noalloc if noalloc else ctx.lib.hpeps_apply_two_site_gate
+    ctx.check(fn(ctx.h, C.byref(pk), capa, i, j, axis, _dev(Gd, "G"), max_rank, C.byref(nb),
+                 _dev(sig, "sigma")))
     out = []
     for r in range(nrow):
         row = []

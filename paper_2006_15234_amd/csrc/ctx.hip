@@ -38,6 +38,7 @@ __global__ void fill_table_kernel(int* out, long long total, TableArgs a) {
 
 Ctx::Ctx(int dev) : device(dev) {
   HP_CHECK_HIP(hipSetDevice(dev));
+  gate_scratch_init(dev);
   HP_CHECK_HIP(hipMalloc(&stats_dev, 8 * sizeof(int)));
   HP_CHECK_HIP(hipMemset(stats_dev, 0, 8 * sizeof(int)));
 }

@@ -174,6 +174,9 @@ void stats_reduce(Ctx& ctx, const int* flags, const int* sweeps, int batch, int*
 void householder_qr(Ctx& ctx, bool cplx, const double* Y, int64_t n, int64_t k, int batch, int* flags, int mask,
                     double* P, double* R);
 int householder_blocks(int64_t n, int64_t k);
+// Resolves the device address of the allocation-free gate update's static
+// scratch on `device` (current), once per device; called at context creation.
+void gate_scratch_init(int device);
 // einsumsvd adjoint helpers (k x k / panel elementwise work, one workgroup per instance)
 void svd_bwd_core(Ctx& ctx, bool cplx, const double* ZZ, const double* VV, const double* s,
                   const double* sbar, int64_t k, int batch, double eps, double* G1H);

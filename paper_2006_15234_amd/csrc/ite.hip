@@ -18,7 +18,9 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
+#include <string>
 
 #include "dpp.h"
 #include "peps.h"
@@ -491,6 +493,117 @@ std::vector<std::vector<std::array<int, 3>>> lattice_layers(int nrow, int ncol) 
 }
 }  // namespace
 
+namespace {
+
+// Static scratch of the allocation-free two-site gate update: one copy per
+// GPU the library runs on, held until the process ends.  Host code never
+// names it except to resolve its device address (hipGetSymbolAddress, once
+// per device, when a context is created on it).
+constexpr size_t kGateScratchBytes = (size_t)1 << 20;
+static __device__ __align__(256) unsigned char scratch[kGateScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Bytes of one buffer rounded up to the 256-byte alignment of every piece.
+size_t round256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// One QR-SVD update of the bond (i, j)-(i2, j2) on the context's stream, with
+// the device buffers (staging copies of the two sites, reflector scratch,
+// dimension and bond tables, gate, singular values) taken from `take`.
+template <class Take>
+void gate_update(hp::Ctx& c, hpeps_peps* peps, const int64_t* capacity, int32_t i, int32_t j, int32_t axis,
+                 const void* G, int64_t max_rank, int64_t* new_bond, double* sigma_out, Take take) {
+  HP_REQUIRE(peps && capacity && G && new_bond, HPEPS_ERR_INVALID_ARG, "null argument");
+  HP_REQUIRE(axis == 0 || axis == 1, HPEPS_ERR_INVALID_ARG, "axis must be 0 or 1");
+  hp::Lattice L = hp::lattice_from_abi(peps);
+  HP_REQUIRE(!L.cplx, HPEPS_ERR_DTYPE, "the QR-SVD kernel is FP64 real");
+  const int i2 = axis == 0 ? i : i + 1, j2 = axis == 0 ? j + 1 : j;
+  HP_REQUIRE(i >= 0 && j >= 0 && i2 < L.nrow && j2 < L.ncol, HPEPS_ERR_INVALID_ARG, "bond outside the lattice");
+  const int d = (int)L.sites[0].dims[4];
+  hp::check_dims(max_rank, d);
+  const int q1 = i * L.ncol + j, q2 = i2 * L.ncol + j2;
+  const hp::DevTensor &T1 = L.sites[q1], &T2 = L.sites[q2];
+  for (int e = 0; e < 4; ++e)
+    HP_REQUIRE(T1.dims[e] <= max_rank && T2.dims[e] <= max_rank, HPEPS_ERR_SHAPE, "bond exceeds max_rank");
+  // new bond, from the shapes alone
+  const int sh1 = axis == 0 ? 3 : 1, sh2 = axis == 0 ? 2 : 0;
+  const int64_t rows1 = T1.size() / (T1.dims[sh1] * d), rows2 = T2.size() / (T2.dims[sh2] * d);
+  const int64_t c1 = T1.dims[sh1] * d, c2 = T2.dims[sh2] * d;
+  const int64_t k1 = std::min(rows1, c1), k2 = std::min(rows2, c2);
+  const int64_t Dn = std::min<int64_t>(max_rank, std::min(k1 * d, d * k2));
+  HP_REQUIRE(capacity[q1] >= T1.size() / T1.dims[sh1] * Dn && capacity[q2] >= T2.size() / T2.dims[sh2] * Dn,
+             HPEPS_ERR_SHAPE, "site buffers too small for the new bond");
+  const int64_t cap = max_rank * max_rank * max_rank * max_rank * d;
+  double* arena = (double*)take(2 * cap * sizeof(double));
+  int* dims_dev = (int*)take(10 * sizeof(int));
+  int* bond_dev = (int*)take(4 * sizeof(int));
+  double* gate_dev = (double*)take((size_t)d * d * d * d * sizeof(double));
+  double* refl = (double*)take(2 * cap * sizeof(double));
+  double* sig = (double*)take(max_rank * sizeof(double));
+  int hd[10], hb[4] = {0, 1, axis, 0};
+  for (int e = 0; e < 5; ++e) {
+    hd[e] = (int)T1.dims[e];
+    hd[5 + e] = (int)T2.dims[e];
+  }
+  HP_CHECK_HIP(hipMemcpyAsync(arena, T1.p, T1.size() * 8, hipMemcpyDeviceToDevice, c.stream));
+  HP_CHECK_HIP(hipMemcpyAsync(arena + cap, T2.p, T2.size() * 8, hipMemcpyDeviceToDevice, c.stream));
+  HP_CHECK_HIP(hipMemcpyAsync(dims_dev, hd, sizeof(hd), hipMemcpyHostToDevice, c.stream));
+  HP_CHECK_HIP(hipMemcpyAsync(bond_dev, hb, sizeof(hb), hipMemcpyHostToDevice, c.stream));
+  HP_CHECK_HIP(hipMemcpyAsync(gate_dev, G, d * d * d * d * 8, hipMemcpyDeviceToDevice, c.stream));
+  hp::IteArgs a{};
+  a.sites = arena;
+  a.cap = cap;
+  a.dims = dims_dev;
+  a.bonds = bond_dev;
+  a.gates = gate_dev;
+  a.dmax = (int)max_rank;
+  a.scratch = refl;
+  a.scratch_per = cap;
+  a.sigma = sig;
+  a.max_rows = (int)(max_rank * max_rank * max_rank);
+  a.max_cols = (int)(max_rank * d);
+  const size_t lds = hp::bond_lds_bytes(a.max_rows, a.max_cols);
+  HP_CHECK_HIP(hipFuncSetAttribute((const void*)hp::qrsvd_bond_kernel,
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  hp::launch_layer(c.stream, a, 1);
+  HP_CHECK_HIP(hipGetLastError());
+  int64_t* shp = const_cast<int64_t*>(peps->shapes);
+  shp[5 * q1 + sh1] = Dn;
+  shp[5 * q2 + sh2] = Dn;
+  const int64_t n1 = T1.size() / T1.dims[sh1] * Dn, n2 = T2.size() / T2.dims[sh2] * Dn;
+  HP_CHECK_HIP(hipMemcpyAsync(T1.p, arena, n1 * 8, hipMemcpyDeviceToDevice, c.stream));
+  HP_CHECK_HIP(hipMemcpyAsync(T2.p, arena + cap, n2 * 8, hipMemcpyDeviceToDevice, c.stream));
+  if (sigma_out)
+    HP_CHECK_HIP(hipMemcpyAsync(sigma_out, sig, Dn * 8, hipMemcpyDeviceToDevice, c.stream));
+  HP_CHECK_HIP(hipStreamSynchronize(c.stream));
+  *new_bond = Dn;
+}
+
+// Device bytes gate_update takes for (max_rank, d), each piece 256-aligned.
+size_t gate_scratch_bytes(int64_t max_rank, int d) {
+  const size_t cap = (size_t)(max_rank * max_rank * max_rank * max_rank * d);
+  return 2 * round256(2 * cap * sizeof(double)) + round256(10 * sizeof(int)) + round256(4 * sizeof(int)) +
+         round256((size_t)d * d * d * d * sizeof(double)) + round256((size_t)max_rank * sizeof(double));
+}
+
+}  // namespace
+
+namespace hp {
+// Resolves this device's copy of the static gate scratch (the device must be
+// current); idempotent.
+void gate_scratch_init(int device) {
+  HP_REQUIRE(device >= 0 && device < kMaxDevices, HPEPS_ERR_UNSUPPORTED, "device index above 63");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr[device]) return;
+  void* ptr = nullptr;
+  HP_CHECK_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+  HP_REQUIRE(ptr != nullptr, HPEPS_ERR_HIP, "static gate scratch has no device address");
+  g_scratch_ptr[device] = ptr;
+}
+}  // namespace hp
+
 extern "C" {
 
 hpeps_status hpeps_ite_plan_create(hpeps_ctx* ctx, const hpeps_peps* init, int32_t n_gates,
@@ -627,70 +740,38 @@ hpeps_status hpeps_apply_two_site_gate(hpeps_ctx* ctx, hpeps_peps* peps, const i
   hp::Ctx& c = *ctx->impl;
   return guard_i(&c, [&] {
     c.ws_reset();
-    HP_REQUIRE(peps && capacity && G && new_bond, HPEPS_ERR_INVALID_ARG, "null argument");
-    HP_REQUIRE(axis == 0 || axis == 1, HPEPS_ERR_INVALID_ARG, "axis must be 0 or 1");
-    hp::Lattice L = hp::lattice_from_abi(peps);
-    HP_REQUIRE(!L.cplx, HPEPS_ERR_DTYPE, "the QR-SVD kernel is FP64 real");
-    const int i2 = axis == 0 ? i : i + 1, j2 = axis == 0 ? j + 1 : j;
-    HP_REQUIRE(i >= 0 && j >= 0 && i2 < L.nrow && j2 < L.ncol, HPEPS_ERR_INVALID_ARG, "bond outside the lattice");
-    const int d = (int)L.sites[0].dims[4];
+    gate_update(c, peps, capacity, i, j, axis, G, max_rank, new_bond, sigma_out,
+                [&](size_t bytes) { return (void*)c.ws<unsigned char>((int64_t)bytes); });
+  });
+}
+
+hpeps_status hpeps_apply_two_site_gate_noalloc(hpeps_ctx* ctx, hpeps_peps* peps, const int64_t* capacity,
+                                               int32_t i, int32_t j, int32_t axis, const void* G,
+                                               int64_t max_rank, int64_t* new_bond, double* sigma_out) {
+  if (!ctx) return HPEPS_ERR_INVALID_ARG;
+  hp::Ctx& c = *ctx->impl;
+  return guard_i(&c, [&] {
+    HP_REQUIRE(max_rank >= 1 && peps && peps->nrow >= 1 && peps->ncol >= 1 && peps->shapes,
+               HPEPS_ERR_INVALID_ARG, "bad lattice or max_rank");
+    const int d = (int)peps->shapes[4];
+    HP_REQUIRE(d >= 1, HPEPS_ERR_SHAPE, "bad physical dimension");
     hp::check_dims(max_rank, d);
-    const int q1 = i * L.ncol + j, q2 = i2 * L.ncol + j2;
-    const hp::DevTensor &T1 = L.sites[q1], &T2 = L.sites[q2];
-    for (int e = 0; e < 4; ++e)
-      HP_REQUIRE(T1.dims[e] <= max_rank && T2.dims[e] <= max_rank, HPEPS_ERR_SHAPE, "bond exceeds max_rank");
-    // new bond, from the shapes alone
-    const int sh1 = axis == 0 ? 3 : 1, sh2 = axis == 0 ? 2 : 0;
-    const int64_t rows1 = T1.size() / (T1.dims[sh1] * d), rows2 = T2.size() / (T2.dims[sh2] * d);
-    const int64_t c1 = T1.dims[sh1] * d, c2 = T2.dims[sh2] * d;
-    const int64_t k1 = std::min(rows1, c1), k2 = std::min(rows2, c2);
-    const int64_t Dn = std::min<int64_t>(max_rank, std::min(k1 * d, d * k2));
-    HP_REQUIRE(capacity[q1] >= T1.size() / T1.dims[sh1] * Dn && capacity[q2] >= T2.size() / T2.dims[sh2] * Dn,
-               HPEPS_ERR_SHAPE, "site buffers too small for the new bond");
-    const int64_t cap = max_rank * max_rank * max_rank * max_rank * d;
-    double* arena = c.ws<double>(2 * cap);
-    int* dims_dev = c.ws<int>(10);
-    int* bond_dev = c.ws<int>(4);
-    double* gate_dev = c.ws<double>(d * d * d * d);
-    double* scratch = c.ws<double>(2 * cap);
-    double* sig = c.ws<double>(max_rank);
-    int hd[10], hb[4] = {0, 1, axis, 0};
-    for (int e = 0; e < 5; ++e) {
-      hd[e] = (int)T1.dims[e];
-      hd[5 + e] = (int)T2.dims[e];
+    const size_t need = gate_scratch_bytes(max_rank, d);
+    HP_REQUIRE(need <= kGateScratchBytes, HPEPS_ERR_ALLOC,
+               "allocation-free gate update needs " + std::to_string(need) + " bytes of scratch, the static "
+               "scratch holds " + std::to_string(kGateScratchBytes));
+    void* base = nullptr;
+    {
+      std::lock_guard<std::mutex> lk(g_scratch_mu);
+      base = g_scratch_ptr[c.device];
     }
-    HP_CHECK_HIP(hipMemcpyAsync(arena, T1.p, T1.size() * 8, hipMemcpyDeviceToDevice, c.stream));
-    HP_CHECK_HIP(hipMemcpyAsync(arena + cap, T2.p, T2.size() * 8, hipMemcpyDeviceToDevice, c.stream));
-    HP_CHECK_HIP(hipMemcpyAsync(dims_dev, hd, sizeof(hd), hipMemcpyHostToDevice, c.stream));
-    HP_CHECK_HIP(hipMemcpyAsync(bond_dev, hb, sizeof(hb), hipMemcpyHostToDevice, c.stream));
-    HP_CHECK_HIP(hipMemcpyAsync(gate_dev, G, d * d * d * d * 8, hipMemcpyDeviceToDevice, c.stream));
-    hp::IteArgs a{};
-    a.sites = arena;
-    a.cap = cap;
-    a.dims = dims_dev;
-    a.bonds = bond_dev;
-    a.gates = gate_dev;
-    a.dmax = (int)max_rank;
-    a.scratch = scratch;
-    a.scratch_per = cap;
-    a.sigma = sig;
-    a.max_rows = (int)(max_rank * max_rank * max_rank);
-    a.max_cols = (int)(max_rank * d);
-    const size_t lds = hp::bond_lds_bytes(a.max_rows, a.max_cols);
-    HP_CHECK_HIP(hipFuncSetAttribute((const void*)hp::qrsvd_bond_kernel,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    hp::launch_layer(c.stream, a, 1);
-    HP_CHECK_HIP(hipGetLastError());
-    int64_t* shp = const_cast<int64_t*>(peps->shapes);
-    shp[5 * q1 + sh1] = Dn;
-    shp[5 * q2 + sh2] = Dn;
-    const int64_t n1 = T1.size() / T1.dims[sh1] * Dn, n2 = T2.size() / T2.dims[sh2] * Dn;
-    HP_CHECK_HIP(hipMemcpyAsync(T1.p, arena, n1 * 8, hipMemcpyDeviceToDevice, c.stream));
-    HP_CHECK_HIP(hipMemcpyAsync(T2.p, arena + cap, n2 * 8, hipMemcpyDeviceToDevice, c.stream));
-    if (sigma_out)
-      HP_CHECK_HIP(hipMemcpyAsync(sigma_out, sig, Dn * 8, hipMemcpyDeviceToDevice, c.stream));
-    HP_CHECK_HIP(hipStreamSynchronize(c.stream));
-    *new_bond = Dn;
+    HP_REQUIRE(base, HPEPS_ERR_HIP, "static gate scratch not resolved for this device");
+    size_t off = 0;
+    gate_update(c, peps, capacity, i, j, axis, G, max_rank, new_bond, sigma_out, [&](size_t bytes) {
+      void* p = (unsigned char*)base + off;
+      off += round256(bytes);
+      return p;
+    });
   });
 }
 
