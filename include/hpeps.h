@@ -459,12 +459,13 @@ hpeps_status hpeps_apply_two_site_gate(hpeps_ctx* ctx, hpeps_peps* peps,
  * capture, tight serving loops, harnesses that forbid hipMalloc): the same
  * update, arguments, layouts, results and errors as hpeps_apply_two_site_gate,
  * but every device buffer the call needs beyond the caller's sites, gate and
- * sigma_out (staging copies of the two sites, the reflector scratch, the
- * dimension and bond tables, the singular values) comes from a static
+ * sigma_out (staging copies of the two sites, the dimension and bond tables, the
+ * gate, the singular values) comes from a static
  * 1 MiB array in the library's device image, one per GPU, resolved when a
  * context is created on that GPU.  The call makes no hipMalloc / hipFree and
  * no allocating library call.  Sizes whose buffers exceed the static array
- * (2 copies of 2 max_rank^4 d doubles plus small tables, 256-byte aligned)
+ * (2 max_rank^4 d doubles for the two sites plus small tables, 256-byte
+ * aligned)
  * return HPEPS_ERR_ALLOC before anything is enqueued; every size the
  * QR-SVD kernel supports fits.  All calls on one GPU share that array: calls
  * that overlap in time on one GPU (from several host threads or contexts)
@@ -491,8 +492,18 @@ hpeps_status hpeps_ite_plan_create(hpeps_ctx* ctx, const hpeps_peps* init,
                                    int32_t n_gates, const void* gates,
                                    const int32_t* bond_gate, int64_t max_rank,
                                    hpeps_ite_plan** out);
-/* Runs n_sweeps sweeps (graph replay when use_graph != 0). */
+/* Runs n_sweeps sweeps: use_graph = 1 replays the captured graph of the four
+ * layer launches, 0 issues the four layer launches directly, 2 is the plain
+ * form with one launch per bond (no graph; the baseline of the batched
+ * forms).  All three compute the same updates. */
 hpeps_status hpeps_ite_run(hpeps_ite_plan* plan, int32_t n_sweeps, int32_t use_graph);
+/* Kept singular values of every bond update of the most recent sweep (Alg. 1
+ * step: the truncated spectrum of Theta normalised to unit 2-norm), bond by
+ * bond in layer order (the order of bond_gate), max_rank values per bond,
+ * zero past the bond's new dimension: n_bonds * max_rank doubles copied to
+ * the caller's device buffer out on the context stream (not synchronised).
+ * Zeros before the first sweep. */
+hpeps_status hpeps_ite_spectra(hpeps_ite_plan* plan, double* out);
 /* Copies the current state out: shapes (host, nrow*ncol*5) and, when sites
  * is not NULL, the tensors into caller buffers (device pointers, each with
  * room for max_rank-bond shapes). Synchronises. */

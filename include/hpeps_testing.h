@@ -37,6 +37,12 @@ hpeps_status hpeps_test_orthogonalize(hpeps_ctx* ctx, hpeps_dtype dtype, int64_t
 hpeps_status hpeps_test_householder(hpeps_ctx* ctx, hpeps_dtype dtype, int64_t batch, int64_t n,
                                     int64_t k, const void* Y, void* P, void* R);
 
+/* Byte budget of one intermediate of an energy strip column (default 1 GiB):
+ * larger column transfers run in chunks of the bottom-environment leg,
+ * accumulated into the column's output (not while a gradient tape records).
+ * Small budgets force the chunked path on small lattices. */
+hpeps_status hpeps_test_strip_chunk_bytes(hpeps_ctx* ctx, int64_t bytes);
+
 /* Small SVD stage: for the upper-triangular R [k,k] writes Z [k,k] (left
  * singular vectors of R^H, columns sorted by descending singular value) and
  * sigma [k] (double).  One-sided Jacobi. */

@@ -108,6 +108,7 @@ _SIGS = {
                                         C.c_int64, C.POINTER(C.c_void_p)]),
     "hpeps_ite_run": (C.c_int, [_P, C.c_int32, C.c_int32]),
     "hpeps_ite_get_state": (C.c_int, [_P, _I64P, C.POINTER(C.c_void_p)]),
+    "hpeps_ite_spectra": (C.c_int, [_P, _P]),
     "hpeps_ite_plan_destroy": (C.c_int, [_P]),
     # include/hpeps_testing.h
     "hpeps_test_gemm_variant": (C.c_int, [_P, C.c_int32, C.c_int32, C.c_int32]),
@@ -117,6 +118,7 @@ _SIGS = {
                                   C.c_int32, _P, _P, _P]),
     "hpeps_test_orthogonalize": (C.c_int, [_P, C.c_int, C.c_int64, C.c_int64, C.c_int64, _P, _P]),
     "hpeps_test_householder": (C.c_int, [_P, C.c_int, C.c_int64, C.c_int64, C.c_int64, _P, _P, _P]),
+    "hpeps_test_strip_chunk_bytes": (C.c_int, [_P, C.c_int64]),
     "hpeps_test_small_svd": (C.c_int, [_P, C.c_int, C.c_int64, C.c_int64, _P, _P, _P]),
     "hpeps_test_zip_apply": (C.c_int, [_P, C.c_int, C.c_int64, _I64P, _P, _P, _P, _P, C.c_int64,
                                        C.c_int32, _P, _P]),

@@ -568,6 +568,8 @@ class ItePlan:
         self.device = peps[0][0].device
         pk = _peps_struct(peps, _dtype_code(peps[0][0]), keep)
         bg = (C.c_int32 * len(bond_gate))(*bond_gate)
+        self.n_bonds = len(bond_gate)
+        self.max_rank = int(max_rank)
         self.gates = gates.contiguous()
         h = C.c_void_p()
         ctx.sync_stream()
@@ -575,9 +577,21 @@ class ItePlan:
                                                 _dev(self.gates, "gates"), bg, max_rank, C.byref(h)))
         self.h = h
 
-    def run(self, n_sweeps, use_graph=True):
+    def run(self, n_sweeps, use_graph=True, per_bond=False):
+        """use_graph: replay the captured sweep graph; per_bond: the plain form,
+        one launch per bond (no graph)."""
         self.ctx.sync_stream()
-        self.ctx.check(self.ctx.lib.hpeps_ite_run(self.h, n_sweeps, 1 if use_graph else 0))
+        mode = 2 if per_bond else (1 if use_graph else 0)
+        self.ctx.check(self.ctx.lib.hpeps_ite_run(self.h, n_sweeps, mode))
+
+    def spectra(self):
+        """Kept singular values of every bond update of the last sweep, layer
+        order: device tensor [n_bonds, max_rank] (zero-padded)."""
+        torch = _torch()
+        out = torch.zeros((self.n_bonds, self.max_rank), dtype=torch.float64, device=self.device)
+        self.ctx.sync_stream()
+        self.ctx.check(self.ctx.lib.hpeps_ite_spectra(self.h, _dev(out, "spectra")))
+        return out
 
     def shapes(self):
         n = self.nrow * self.ncol

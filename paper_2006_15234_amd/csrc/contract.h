@@ -22,9 +22,13 @@ TView tview_rm(const void* p, const std::string& legs, const std::vector<int64_t
                bool conj = false);
 int64_t leg_dim(const TView& t, char c);
 
-// C[out] = sum over shared legs of A * B; C row-major in the order of `out`.
-// Returns the output dims.  c_capacity: element capacity of C.
+// C[out] = sum over shared legs of A * B (C += ... with accumulate); C
+// row-major in the order of `out`.  Returns the output dims.  c_capacity:
+// element capacity of C.
 std::vector<int64_t> contract2(Ctx& ctx, bool cplx, const TView& A, const TView& B,
-                               const std::string& out, void* C, int64_t c_capacity);
+                               const std::string& out, void* C, int64_t c_capacity,
+                               bool accumulate = false);
+// The sub-view of `v` with leg `leg` restricted to [start, start + len).
+TView restrict_leg(const TView& v, char leg, int64_t start, int64_t len, bool cplx);
 
 }  // namespace hp

@@ -37,8 +37,20 @@ int64_t leg_dim(const TView& t, char c) {
   return pos == std::string::npos ? -1 : t.dims[pos];
 }
 
+TView restrict_leg(const TView& v, char leg, int64_t start, int64_t len, bool cplx) {
+  const auto pos = v.legs.find(leg);
+  HP_REQUIRE(pos != std::string::npos && start >= 0 && len >= 1 && start + len <= v.dims[pos], HPEPS_ERR_SHAPE,
+             std::string("bad sub-range of leg ") + leg);
+  TView r = v;
+  const int64_t off = start * v.strides[pos];
+  r.p = static_cast<const double*>(v.p) + off * (cplx ? 2 : 1);
+  r.dims[pos] = len;
+  r.extent = v.extent - off;
+  return r;
+}
+
 std::vector<int64_t> contract2(Ctx& ctx, bool cplx, const TView& A, const TView& B,
-                               const std::string& out, void* C, int64_t c_capacity) {
+                               const std::string& out, void* C, int64_t c_capacity, bool accumulate) {
   auto dim_of = [&](char c) {
     const int64_t a = leg_dim(A, c), b = leg_dim(B, c);
     HP_REQUIRE(a < 0 || b < 0 || a == b, HPEPS_ERR_SHAPE, std::string("leg dims differ for ") + c);
@@ -120,6 +132,7 @@ std::vector<int64_t> contract2(Ctx& ctx, bool cplx, const TView& A, const TView&
   }
   g.conjA = cplx && A.conj;
   g.conjB = cplx && B.conj;
+  g.accumulate = accumulate;
   gemm(ctx, cplx ? Prec::C128 : Prec::F64, D, g);
   return odims;
 }

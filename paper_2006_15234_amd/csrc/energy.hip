@@ -79,6 +79,31 @@ Ten alloc_out(Ctx& ctx, bool cplx, const TView& A, const TView& B, const std::st
   return t;
 }
 
+// Number of chunks of the bottom-environment leg b (a spectator of every
+// intermediate of a strip column until the last contraction sums it) that
+// keeps each intermediate below the context's strip_chunk_bytes (1 GiB by
+// default); 1 while a tape records (its adjoints need one product per
+// output) or when everything fits.
+int64_t strip_chunks(Ctx& ctx, bool cplx, const TView& L, const std::vector<TView>& ops,
+                     const std::vector<std::string>& steps) {
+  if (taping(ctx)) return 1;
+  auto dim = [&](char c) {
+    int64_t d = leg_dim(L, c);
+    for (const auto& v : ops)
+      if (d < 0) d = leg_dim(v, c);
+    return d < 0 ? (int64_t)1 : d;
+  };
+  int64_t big = 0;
+  for (const auto& st : steps) {
+    int64_t n = 1;
+    for (char c : st) n *= dim(c);
+    big = std::max(big, n);
+  }
+  const int64_t bytes = big * (cplx ? 16 : 8);
+  const int64_t budget = std::max<int64_t>(1, ctx.strip_chunk_bytes);
+  return std::min(dim('b'), std::max<int64_t>(1, (bytes + budget - 1) / budget));
+}
+
 // One column of a three-layer strip: L[spec,t,l,L,b] -> L'[spec,s,r,R,c(,p,P)].
 Ten transfer3(Ctx& ctx, bool cplx, const Ten& L, const BndView& top, const SiteView& ket, const SiteView& bra,
               const BndView& bot, bool open) {
@@ -97,13 +122,19 @@ Ten transfer3(Ctx& ctx, bool cplx, const Ten& L, const BndView& top, const SiteV
     res.dims.push_back(dd);
   }
   res.p = ctx.ws<double>(res.size() * (cplx ? 2 : 1));
-  {
+  const std::string s1 = sp + "lLbuUs", s2 = sp + "LbUsdrp", s3 = sp + (open ? "bsdrDRpP" : "bsdrDR");
+  const int64_t nch = strip_chunks(ctx, cplx, L.view(), {bview(top, "tuUs"), sview(ket, "udlrp", false),
+                                                         sview(bra, "UDLRP", true), bview(bot, "bdDc")},
+                                   {s1, s2, s3});
+  const int64_t nbl = leg_dim(L.view(), 'b'), bc = (nbl + nch - 1) / nch;
+  for (int64_t b0 = 0; b0 < nbl; b0 += bc) {
+    const int64_t len = std::min(bc, nbl - b0);
     WsScope scope(ctx);
-    Ten x1 = contract(ctx, cplx, L.view(), bview(top, "tuUs"), sp + "lLbuUs");
-    Ten x2 = contract(ctx, cplx, x1.view(), sview(ket, "udlrp", false), sp + "LbUsdrp");
-    Ten x3 = contract(ctx, cplx, x2.view(), sview(bra, open ? "UDLRP" : "UDLRp", true),
-                      sp + (open ? "bsdrDRpP" : "bsdrDR"));
-    contract2(ctx, cplx, x3.view(), bview(bot, "bdDc"), out, res.p, res.size());
+    Ten x1 = contract(ctx, cplx, restrict_leg(L.view(), 'b', b0, len, cplx), bview(top, "tuUs"), s1);
+    Ten x2 = contract(ctx, cplx, x1.view(), sview(ket, "udlrp", false), s2);
+    Ten x3 = contract(ctx, cplx, x2.view(), sview(bra, open ? "UDLRP" : "UDLRp", true), s3);
+    contract2(ctx, cplx, x3.view(), restrict_leg(bview(bot, "bdDc"), 'b', b0, len, cplx), out, res.p, res.size(),
+              b0 > 0);
   }
   return res;
 }
@@ -128,14 +159,23 @@ Ten transfer4(Ctx& ctx, bool cplx, const Ten& L, const BndView& top, const SiteV
     res.dims.push_back(dd);
   }
   res.p = ctx.ws<double>(res.size() * (cplx ? 2 : 1));
-  {
+  const std::string s1 = sp + "lLmMbuUs", s2 = sp + "LmMbUsvrp", s3 = sp + "mMbsvrVR" + o1,
+                    s4 = sp + "MbsrVRdnq" + o1, s5 = sp + "bsrRdnDN" + o1 + o2;
+  const int64_t nch = strip_chunks(ctx, cplx, L.view(), {bview(top, "tuUs"), sview(k1, "uvlrp", false),
+                                                         sview(b1, "UVLRP", true), sview(k2, "vdmnq", false),
+                                                         sview(b2, "VDMNQ", true), bview(bot, "bdDc")},
+                                   {s1, s2, s3, s4, s5});
+  const int64_t nbl = leg_dim(L.view(), 'b'), bc = (nbl + nch - 1) / nch;
+  for (int64_t b0 = 0; b0 < nbl; b0 += bc) {
+    const int64_t len = std::min(bc, nbl - b0);
     WsScope scope(ctx);
-    Ten x1 = contract(ctx, cplx, L.view(), bview(top, "tuUs"), sp + "lLmMbuUs");
-    Ten x2 = contract(ctx, cplx, x1.view(), sview(k1, "uvlrp", false), sp + "LmMbUsvrp");
-    Ten x3 = contract(ctx, cplx, x2.view(), sview(b1, open ? "UVLRP" : "UVLRp", true), sp + "mMbsvrVR" + o1);
-    Ten x4 = contract(ctx, cplx, x3.view(), sview(k2, "vdmnq", false), sp + "MbsrVRdnq" + o1);
-    Ten x5 = contract(ctx, cplx, x4.view(), sview(b2, open ? "VDMNQ" : "VDMNq", true), sp + "bsrRdnDN" + o1 + o2);
-    contract2(ctx, cplx, x5.view(), bview(bot, "bdDc"), out, res.p, res.size());
+    Ten x1 = contract(ctx, cplx, restrict_leg(L.view(), 'b', b0, len, cplx), bview(top, "tuUs"), s1);
+    Ten x2 = contract(ctx, cplx, x1.view(), sview(k1, "uvlrp", false), s2);
+    Ten x3 = contract(ctx, cplx, x2.view(), sview(b1, open ? "UVLRP" : "UVLRp", true), s3);
+    Ten x4 = contract(ctx, cplx, x3.view(), sview(k2, "vdmnq", false), s4);
+    Ten x5 = contract(ctx, cplx, x4.view(), sview(b2, open ? "VDMNQ" : "VDMNq", true), s5);
+    contract2(ctx, cplx, x5.view(), restrict_leg(bview(bot, "bdDc"), 'b', b0, len, cplx), out, res.p, res.size(),
+              b0 > 0);
   }
   return res;
 }

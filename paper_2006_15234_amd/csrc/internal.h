@@ -209,6 +209,9 @@ class Ctx {
   hipStream_t stream = nullptr;
   std::string last_error;
   int64_t ws_limit = 0;
+  // byte budget of one intermediate of an energy strip column (larger ones are
+  // split along the bottom-environment leg)
+  int64_t strip_chunk_bytes = (int64_t)1 << 30;
 
   // device index table for an IndexMap (int32 offsets), cached
   const int* table(const IndexMap& m);

@@ -3,15 +3,16 @@
 //
 // One workgroup updates one bond entirely on chip:
 //   1. each site is matricized as (other legs) x (shared bond, p) while it
-//      is gathered into LDS; when it has more rows than columns it is
-//      Householder-QR factored in LDS (the reflectors are parked in a
-//      per-bond global scratch), otherwise Q = I and R is the site itself;
+//      is gathered into registers (thread t owns rows t, t + 256, ...); when
+//      it has more rows than columns it is Householder-QR factored there,
+//      one barrier per column, otherwise Q = I and R is the site itself;
 //   2. Theta = G R1 R2 (d^2 x d^2 gate, tiny);
-//   3. one-sided Jacobi SVD of Theta (<= 32 x 32) with accumulated right
-//      vectors, truncation to D' = min(Dmax, rows, cols), normalisation of the
-//      kept values and the sqrt(s) split;
-//   4. T' = Q [R~; 0] by applying the reflectors in reverse order, scattered
-//      straight into the canonical [u,d,l,r,p] layout with the new bond.
+//   3. one-sided Jacobi SVD of Theta (<= 32 x 32) in LDS with accumulated
+//      right vectors, truncation to D' = min(Dmax, rows, cols), normalisation
+//      of the kept values and the sqrt(s) split;
+//   4. T' = Q [R~; 0] by applying the reflectors still held in registers in
+//      reverse order, scattered straight into the canonical [u,d,l,r,p]
+//      layout with the new bond.
 // Bond dimensions live in a device table, so a whole sweep (four launches,
 // one per layer of non-overlapping bonds) is a static sequence that is
 // captured once in a HIP graph and replayed.
@@ -34,9 +35,7 @@ struct hpeps_ite_plan {
   int* bonds[4] = {nullptr, nullptr, nullptr, nullptr};
   int nb[4] = {0, 0, 0, 0};
   double* gates = nullptr;
-  double* scratch = nullptr;
-  int64_t scratch_per = 0;
-  double* sigma = nullptr;
+  double* sigma = nullptr;  // per bond of a sweep (layer order): max_rank kept values
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   hipStream_t gstream = nullptr;
@@ -47,7 +46,9 @@ namespace hp {
 namespace {
 
 constexpr int kT = 256;     // threads per bond workgroup
-constexpr int kMaxTh = 32;  // Theta is at most 32 x 32 (D <= 8, d = 2 or D d^2 <= 32)
+constexpr int kMaxTh = 32;  // Theta is at most 32 x 32 (D d^2 <= 32)
+constexpr int kMaxC = 16;   // columns of a site matricization (shared bond x p) <= 16
+constexpr int kMaxRpt = 3;  // rows of a site matricization <= 3 * kT
 
 struct IteArgs {
   double* sites;
@@ -56,76 +57,9 @@ struct IteArgs {
   const int* bonds;  // per bond: s1, s2, axis, gate
   const double* gates;
   int dmax;
-  double* scratch;
-  long long scratch_per;
   double* sigma;     // per bond: dmax values (or null)
-  int max_rows, max_cols;
+  int max_rows;
 };
-
-
-// Householder QR in place of the column-major rows x cols matrix A (cols <=
-// rows).  Reflector j is stored in A[j][j..rows) (unnormalised v with
-// H = I - tau v v^T); diag receives R's diagonal.
-__device__ void householder_qr(double* A, int rows, int cols, double* tau, double* diag, double* red) {
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = kT / 64;
-  for (int j = 0; j < cols; ++j) {
-    double* x = A + (long long)j * rows;
-    double s = 0;
-    for (int r = j + tid; r < rows; r += kT) s += x[r] * x[r];
-    s = wave_sum(s);
-    if (lane == 0) red[wave] = s;
-    __syncthreads();
-    double nrm2 = 0;
-    for (int w = 0; w < nw; ++w) nrm2 += red[w];
-    const double x0 = x[j];
-    __syncthreads();
-    if (nrm2 == 0.0) {
-      if (tid == 0) {
-        tau[j] = 0.0;
-        diag[j] = 0.0;
-      }
-      __syncthreads();
-      continue;
-    }
-    const double alpha = -copysign(sqrt(nrm2), x0);
-    const double v0 = x0 - alpha;
-    const double vn2 = nrm2 - x0 * x0 + v0 * v0;
-    const double t = vn2 > 0 ? 2.0 / vn2 : 0.0;
-    if (tid == 0) {
-      x[j] = v0;
-      tau[j] = t;
-      diag[j] = alpha;
-    }
-    __syncthreads();
-    for (int l = j + 1 + wave; l < cols; l += nw) {
-      double* y = A + (long long)l * rows;
-      double dot = 0;
-      for (int r = j + lane; r < rows; r += 64) dot += x[r] * y[r];
-      dot = wave_sum(dot) * t;
-      for (int r = j + lane; r < rows; r += 64) y[r] -= dot * x[r];
-    }
-    __syncthreads();
-  }
-}
-
-// B (column-major rows x nbc) := Q B with Q = H_0 ... H_{cols-1}.
-__device__ void apply_q(const double* A, int rows, int cols, const double* tau, double* B, int nbc) {
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = kT / 64;
-  for (int j = cols - 1; j >= 0; --j) {
-    const double* v = A + (long long)j * rows;
-    const double t = tau[j];
-    if (t != 0.0) {
-      for (int q = wave; q < nbc; q += nw) {
-        double* y = B + (long long)q * rows;
-        double dot = 0;
-        for (int r = j + lane; r < rows; r += 64) dot += v[r] * y[r];
-        dot = wave_sum(dot) * t;
-        for (int r = j + lane; r < rows; r += 64) y[r] -= dot * v[r];
-      }
-    }
-    __syncthreads();
-  }
-}
 
 struct SiteGeom {
   int dims[5];
@@ -147,96 +81,264 @@ __device__ void site_geom(const int* dims, int shared, SiteGeom& g) {
   g.cols = g.dims[shared] * g.dims[4];
 }
 
-// offset of matricized element (row over the other legs, col = (shared, p))
-__device__ __forceinline__ long long site_off(const SiteGeom& g, int row, int col) {
-  const int p = col % g.dims[4], h = col / g.dims[4];
+// element offset of the matricized row (over the other legs, canonical order)
+__device__ __forceinline__ long long row_off(const SiteGeom& g, int row) {
   const int o2 = row % g.dims[g.other[2]];
   const int r1 = row / g.dims[g.other[2]];
   const int o1 = r1 % g.dims[g.other[1]], o0 = r1 / g.dims[g.other[1]];
-  return o0 * g.st[g.other[0]] + o1 * g.st[g.other[1]] + o2 * g.st[g.other[2]] + h * g.st[g.shared] +
-         (long long)p * g.st[4];
+  return o0 * g.st[g.other[0]] + o1 * g.st[g.other[1]] + o2 * g.st[g.other[2]];
 }
 
+// Cross-wavefront sums of the partials of one column step.  Every thread
+// adds the four wavefronts' values; buffers alternate between steps so that
+// one barrier per step suffices (a wavefront can be at most one step ahead).
+struct StepBuf {
+  double part[2][kT / 64][kMaxC];
+  double row[2][kMaxC];  // snapshot of the pivot row
+};
+
+// Wavefront sums of 16 values per lane by recursive halving: in stage k
+// (partner lane ^ 2^k) a lane keeps the half of its remaining values that
+// its bit k selects and adds the partner's copy of that half, so after four
+// stages lane i holds the sum over its 16-lane row of value
+// bitrev4(i & 15); two more exchanges add the four rows.  17 shuffles
+// instead of 16 separate wavefront reductions.
+__device__ __forceinline__ int bitrev4(int i) {
+  return ((i & 1) << 3) | ((i & 2) << 1) | ((i & 4) >> 1) | ((i & 8) >> 3);
+}
+__device__ __forceinline__ double wave_reduce_scatter16(const double (&v)[16], int lane) {
+  double a[8], b[4], c[2];
+  bool hi = lane & 1;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) a[i] = (hi ? v[i + 8] : v[i]) + __shfl_xor(hi ? v[i] : v[i + 8], 1);
+  hi = lane & 2;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) b[i] = (hi ? a[i + 4] : a[i]) + __shfl_xor(hi ? a[i] : a[i + 4], 2);
+  hi = lane & 4;
+#pragma unroll
+  for (int i = 0; i < 2; ++i) c[i] = (hi ? b[i + 2] : b[i]) + __shfl_xor(hi ? b[i] : b[i + 2], 4);
+  hi = lane & 8;
+  double d = (hi ? c[1] : c[0]) + __shfl_xor(hi ? c[0] : c[1], 8);
+  d += __shfl_xor(d, 16);
+  d += __shfl_xor(d, 32);
+  return d;
+}
+
+// Householder QR of the rows x cols matricization P (LDS, column-major with
+// leading dimension LD): thread t owns rows t, t + kT, ... and only ever
+// touches those rows of P.  One barrier per column: the pivot row's owner
+// publishes it, every thread reduces x^T y_l over its rows for all l >= j at
+// once (x = column j, y_l = column l, rows >= j), and the reflector
+// v = x - alpha e_j (H = I - tau v v^T) follows in every thread from
+// ||x||^2, x_j and those sums (v^T y_l = x^T y_l - alpha y_l[j]).
+// Afterwards column j of P holds v below and on the diagonal, tau[j] and row
+// j of R (ld kMaxC) are in LDS.
+template <int RPT, int MC, int LD>
+__device__ __forceinline__ void house_factor(double* P, int cols, double* R, double* tau, StepBuf& sb, int& step) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int j = 0; j < cols; ++j) {
+    const int buf = step++ & 1;
+    const double* x = P + j * LD;
+    if (tid == j) {
+#pragma unroll
+      for (int l = 0; l < MC; ++l)
+        if (l >= j && l < cols) sb.row[buf][l] = P[l * LD + j];
+    }
+    // every load is in range (P has MC columns of LD rows): load all, then
+    // mask, so that the loads of a step form one batch without branches
+    double xr[RPT];
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+      const double xv = x[tid + q * kT];
+      xr[q] = tid + q * kT >= j ? xv : 0.0;
+    }
+    double pv[16];
+#pragma unroll
+    for (int l = 0; l < 16; ++l) {
+      double sacc = 0.0;
+      if (l < MC) {
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) sacc += xr[q] * P[l * LD + tid + q * kT];
+      }
+      pv[l] = (l >= j && l < cols) ? sacc : 0.0;
+    }
+    {
+      const double tot = wave_reduce_scatter16(pv, lane);
+      if (lane < 16 && bitrev4(lane) < MC) sb.part[buf][wave][bitrev4(lane)] = tot;
+    }
+    __syncthreads();
+    double w[MC];
+#pragma unroll
+    for (int l = 0; l < MC; ++l) {
+      double t = 0.0;
+#pragma unroll
+      for (int wv = 0; wv < kT / 64; ++wv) t += sb.part[buf][wv][l];
+      w[l] = t;
+    }
+    double nrm2 = 0.0;
+#pragma unroll
+    for (int l = 0; l < MC; ++l)
+      if (l == j) nrm2 = w[l];
+    const double x0 = sb.row[buf][j];
+    if (nrm2 == 0.0) {  // zero column: H = I, R[j, :] = 0 (the pivot row is zero too)
+      if (tid == j) {
+        tau[j] = 0.0;
+        for (int l = 0; l < cols; ++l) R[j * kMaxC + l] = 0.0;
+      }
+      continue;
+    }
+    const double alpha = -copysign(sqrt(nrm2), x0);
+    const double v0 = x0 - alpha;
+    const double vn2 = nrm2 - x0 * x0 + v0 * v0;
+    const double t = vn2 > 0 ? 2.0 / vn2 : 0.0;
+#pragma unroll
+    for (int l = 0; l < MC; ++l) {
+      const double wl = t * (w[l] - alpha * sb.row[buf][l]);  // tau v^T y_l
+      w[l] = (l > j && l < cols) ? wl : 0.0;
+    }
+    // rows below j have v = 0 and columns up to j have w = 0: those stores
+    // write back the loaded values, so the update needs no branches
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+      const int r = tid + q * kT;
+      const double v = r == j ? v0 : xr[q];
+      double y[MC];
+#pragma unroll
+      for (int l = 0; l < MC; ++l) y[l] = P[l * LD + r];
+#pragma unroll
+      for (int l = 0; l < MC; ++l) P[l * LD + r] = l == j && r == j ? v0 : y[l] - w[l] * v;
+    }
+    if (tid == j) {
+      tau[j] = t;
+      for (int l = 0; l < cols; ++l) R[j * kMaxC + l] = l < j ? 0.0 : (l == j ? alpha : P[l * LD + j]);
+    }
+  }
+}
+
+// B := H_0 H_1 ... H_{cols-1} B for the reflectors of house_factor in P (same
+// row ownership), B (registers, RPT rows x MC columns) with ncol columns; one
+// barrier per reflector.
+template <int RPT, int MC, int LD>
+__device__ __forceinline__ void house_apply(const double* P, int cols, const double* tau, double (&B)[RPT][MC],
+                                            int ncol, StepBuf& sb, int& step) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int j = cols - 1; j >= 0; --j) {
+    const double t = tau[j];
+    if (t == 0.0) continue;  // same value in every thread
+    const int buf = step++ & 1;
+    double v[RPT];
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+      const double pvq = P[j * LD + tid + q * kT];
+      v[q] = tid + q * kT >= j ? pvq : 0.0;
+    }
+    double pv[16];
+#pragma unroll
+    for (int c = 0; c < 16; ++c) {
+      double sacc = 0.0;
+      if (c < MC) {
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) sacc += v[q] * B[q][c < MC ? c : 0];
+      }
+      pv[c] = c < ncol ? sacc : 0.0;
+    }
+    {
+      const double tot = wave_reduce_scatter16(pv, lane);
+      if (lane < 16 && bitrev4(lane) < MC) sb.part[buf][wave][bitrev4(lane)] = tot;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < MC; ++c) {
+      double sum = 0.0;
+#pragma unroll
+      for (int wv = 0; wv < kT / 64; ++wv) sum += sb.part[buf][wv][c];
+      const double wc = c < ncol ? t * sum : 0.0;
+#pragma unroll
+      for (int q = 0; q < RPT; ++q) B[q][c] -= wc * v[q];
+    }
+  }
+}
+
+// One bond per workgroup (Alg. 1): both site matricizations are gathered
+// into registers and QR-factored (QR skipped when a site has no more rows
+// than columns), the reflectors are parked in LDS, Theta = G R1 R2 is
+// decomposed by one-sided Jacobi in LDS, and each new site Q [R~; 0] is
+// formed in registers and scattered into the [u,d,l,r,p] layout with the new
+// bond.  RPT rows and MC columns per thread; dynamic LDS: two column-major
+// RPT kT x MC reflector blocks.
+template <int RPT, int MC>
 __global__ __launch_bounds__(kT) void qrsvd_bond_kernel(IteArgs a) {
-  extern __shared__ double smem[];
-  const int bi = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = kT / 64;
-  const int s1 = a.bonds[4 * bi], s2 = a.bonds[4 * bi + 1], axis = a.bonds[4 * bi + 2];
-  const double* G = a.gates + (long long)a.bonds[4 * bi + 3] * 0;  // set below once d is known
-  const int matsz = a.max_rows * a.max_cols;
-  double* A = smem;                 // matricized site / reflectors
-  double* Bm = A + matsz;           // output before the scatter
-  double* R1 = Bm + matsz;          // k1 x c (row-major), k1 <= c <= max_cols
-  double* R2 = R1 + a.max_cols * a.max_cols;
-  double* Th = R2 + a.max_cols * a.max_cols;  // Theta, column-major (col * nr + row)
-  double* J = Th + kMaxTh * kMaxTh;   // right vectors, column-major
-  double* small = J + kMaxTh * kMaxTh;
-  double* tau1 = small;
-  double* tau2 = tau1 + kMaxTh;
-  double* diag = tau2 + kMaxTh;
-  double* red = diag + kMaxTh;      // nw entries
-  double* sig = red + 16;
-  double* sv = sig + kMaxTh;        // kept, normalised values
+  extern __shared__ double park[];                          // [2][MC][RPT kT]
+  __shared__ double R1[kMaxC * kMaxC], R2[kMaxC * kMaxC];  // k x cols, ld kMaxC
+  __shared__ double Th[kMaxTh * kMaxTh];                    // Theta, column-major (col * nr + row)
+  __shared__ double J[kMaxTh * kMaxTh];                     // right vectors, column-major
+  __shared__ double tau1[kMaxC], tau2[kMaxC];
+  __shared__ double red[kT / 64];
+  __shared__ double sig[kMaxTh], sv[kMaxTh];
+  __shared__ long long coff1[kMaxC], coff2[kMaxC];
+  __shared__ StepBuf sb;
   __shared__ int perm[kMaxTh];
   __shared__ int rot;
-  __shared__ SiteGeom g1, g2;
+  __shared__ SiteGeom g1, g2, go[2];
+  constexpr int LD = RPT * kT;
+  const int bi = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = kT / 64;
+  const int s1 = a.bonds[4 * bi], s2 = a.bonds[4 * bi + 1], axis = a.bonds[4 * bi + 2];
   if (tid == 0) {
     site_geom(a.dims + 5 * s1, axis == 0 ? 3 : 1, g1);
     site_geom(a.dims + 5 * s2, axis == 0 ? 2 : 0, g2);
   }
   __syncthreads();
   const int d = g1.dims[4];
-  G = a.gates + (long long)a.bonds[4 * bi + 3] * d * d * d * d;
+  if (tid < kMaxC) {
+    coff1[tid] = (long long)(tid / d) * g1.st[g1.shared] + (tid % d);
+    coff2[tid] = (long long)(tid / d) * g2.st[g2.shared] + (tid % d);
+  }
+  __syncthreads();
+  const double* G = a.gates + (long long)a.bonds[4 * bi + 3] * d * d * d * d;
   const int h = g1.dims[g1.shared];
   double* site1 = a.sites + (long long)s1 * a.cap;
   double* site2 = a.sites + (long long)s2 * a.cap;
-  double* scr1 = a.scratch + (long long)bi * 2 * a.scratch_per;
-  double* scr2 = scr1 + a.scratch_per;
+  int step = 0;
 
-  // ---- factor both sites ------------------------------------------------
-  int k1, k2;
+  // ---- gather and factor both sites (matricizations in LDS) -------------
   const bool qr1 = g1.rows > g1.cols, qr2 = g2.rows > g2.cols;
   for (int s = 0; s < 2; ++s) {
     const SiteGeom& g = s == 0 ? g1 : g2;
+    const long long* coff = s == 0 ? coff1 : coff2;
     const double* site = s == 0 ? site1 : site2;
     double* R = s == 0 ? R1 : R2;
-    double* tau = s == 0 ? tau1 : tau2;
-    double* scr = s == 0 ? scr1 : scr2;
-    const bool qr = s == 0 ? qr1 : qr2;
-    for (int e = tid; e < g.rows * g.cols; e += kT) {
-      const int col = e / g.rows, row = e % g.rows;
-      A[e] = site[site_off(g, row, col)];
+    double* P = park + (long long)s * MC * LD;
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+      const int r = tid + q * kT;
+      const bool in = r < g.rows;
+      const long long ro = in ? row_off(g, r) : 0;
+#pragma unroll
+      for (int c = 0; c < MC; ++c) P[c * LD + r] = (in && c < g.cols) ? site[ro + coff[c]] : 0.0;
     }
-    __syncthreads();
-    if (qr) {
-      householder_qr(A, g.rows, g.cols, tau, diag, red);
-      for (int e = tid; e < g.cols * g.cols; e += kT) {
-        const int i = e / g.cols, l = e % g.cols;
-        R[e] = (i < l) ? A[(long long)l * g.rows + i] : (i == l ? diag[i] : 0.0);
-      }
-      for (int e = tid; e < g.rows * g.cols; e += kT) scr[e] = A[e];
-    } else {
-      for (int e = tid; e < g.rows * g.cols; e += kT) {
-        const int i = e / g.cols, l = e % g.cols;
-        R[e] = A[(long long)l * g.rows + i];
-      }
+    if (s == 0 ? qr1 : qr2) {
+      house_factor<RPT, MC, LD>(P, g.cols, R, s == 0 ? tau1 : tau2, sb, step);
+    } else if (tid < g.rows) {
+      // no QR: R is the matricization itself (rows <= cols <= 16: thread r owns row r)
+      for (int c = 0; c < g.cols; ++c) R[tid * kMaxC + c] = P[c * LD + tid];
     }
-    __syncthreads();
   }
-  k1 = qr1 ? g1.cols : g1.rows;
-  k2 = qr2 ? g2.cols : g2.rows;
+  __syncthreads();
+  const int k1 = qr1 ? g1.cols : g1.rows;
+  const int k2 = qr2 ? g2.cols : g2.rows;
 
   // ---- Theta[(k1,a),(b,l)] = sum_{h,i,j} G[a,b,i,j] R1[k1,(h,i)] R2[l,(h,j)] ----
   const int nr = k1 * d, nc = d * k2;
   for (int e = tid; e < nr * nc; e += kT) {
-    const int col = e / nr, row = e % nr;
-    const int kk1 = row / d, aa = row % d, bb = col / k2, ll = col % k2;
+    const int col = e / nr, row = e - col * nr;
+    const int kk1 = row / d, aa = row - kk1 * d, bb = col / k2, ll = col - bb * k2;
     double acc = 0;
     for (int i = 0; i < d; ++i)
       for (int j = 0; j < d; ++j) {
         const double gv = G[((aa * d + bb) * d + i) * d + j];
         if (gv == 0.0) continue;
         double w = 0;
-        for (int hh = 0; hh < h; ++hh) w += R1[kk1 * g1.cols + hh * d + i] * R2[ll * g2.cols + hh * d + j];
+        for (int hh = 0; hh < h; ++hh) w += R1[kk1 * kMaxC + hh * d + i] * R2[ll * kMaxC + hh * d + j];
         acc += gv * w;
       }
     Th[e] = acc;
@@ -245,13 +347,16 @@ __global__ __launch_bounds__(kT) void qrsvd_bond_kernel(IteArgs a) {
   __syncthreads();
 
   // ---- one-sided Jacobi on the columns of Theta (J accumulates) ----------
-  // A pair is rotated when its correlation is above sqrt(nr) eps relative to
-  // the two column norms and above nr eps ||Theta||_F^2.  The second test
-  // leaves Theta^T Theta wrong by at most the rounding error of forming
-  // Theta (a backward-stable stop); without it, the columns of rounding
-  // noise of a rank-deficient Theta (near product states) keep O(1) relative
-  // correlation forever and the sweeps never stop.  Only the leading pairs,
-  // weighted by their singular values, enter the updated sites.
+  // A pair (x, y) with Gram entries a2 = |x|^2, b2 = |y|^2, g = x.y is
+  // rotated while |g| exceeds both sqrt(nr) eps |x| |y| (relative
+  // convergence) and delta ||Theta||_F max(|x|, |y|), delta = 512 eps.
+  // Leaving a pair unrotated moves its singular values by at most
+  // |g| / max(|x|, |y|) (the degenerate case) and the two-site product by
+  // as much, so the second test bounds every kept value and the product at
+  // delta ||Theta||_F, for large and small singular values alike, while it
+  // stops the rotations among columns of rounding noise (rank-deficient
+  // Theta near product states), whose correlations stay O(1) relative to
+  // their norms.
   {
     double f2 = 0;
     for (int e = tid; e < nr * nc; e += kT) f2 += Th[e] * Th[e];
@@ -261,10 +366,9 @@ __global__ __launch_bounds__(kT) void qrsvd_bond_kernel(IteArgs a) {
   __syncthreads();
   double fro2 = 0;
   for (int w = 0; w < nw; ++w) fro2 += red[w];
-  __syncthreads();
-  const double floor_abs = nr * 0x1p-52 * fro2;
+  const double acc2 = 0x1p-86 * fro2;  // (delta ||Theta||_F)^2, delta = 512 eps = 2^-43
   const int n = (nc + 1) / 2 * 2;
-  const double tol = sqrt((double)nr) * 0x1p-52;
+  const double tol2 = (double)nr * 0x1p-104;  // (sqrt(nr) eps)^2
   // one 16-lane group per column pair (nc <= 32: at most 16 pairs per round,
   // all in flight at once); a group reduces over the rows with DPP row sums
   const int grp = tid >> 4, gl = tid & 15;
@@ -294,9 +398,11 @@ __global__ __launch_bounds__(kT) void qrsvd_bond_kernel(IteArgs a) {
       a2 = row_sum16(a2);
       b2 = row_sum16(b2);
       gm = row_sum16(gm);
-      if (act && a2 > 0 && b2 > 0 && fabs(gm) > tol * sqrt(a2) * sqrt(b2) && fabs(gm) > floor_abs) {
-        const double zeta = (b2 - a2) / (2.0 * gm);
-        const double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+      // |gm| > sqrt(nr) eps sqrt(a2 b2) without square roots; the rotation
+      // t = tan(theta) = sign(dl) 2 gm / (|dl| + sqrt(dl^2 + 4 gm^2)), dl = b2 - a2
+      if (act && gm * gm > tol2 * a2 * b2 && gm * gm > acc2 * fmax(a2, b2)) {
+        const double dl = b2 - a2;
+        const double t = (dl >= 0 ? 2.0 : -2.0) * gm / (fabs(dl) + sqrt(dl * dl + 4.0 * gm * gm));
         const double c = rsqrt(1.0 + t * t), sn = c * t;  // 1 + t^2 in [1, 2]
         if (in0) {
           x[gl] = c * x0 - sn * y0;
@@ -355,48 +461,55 @@ __global__ __launch_bounds__(kT) void qrsvd_bond_kernel(IteArgs a) {
   __syncthreads();
 
   // ---- new sites: T' = Q [R~; 0] with columns (b, p) ---------------------
+  const int ncol_out = Dn * d;
   for (int s = 0; s < 2; ++s) {
     const SiteGeom& g = s == 0 ? g1 : g2;
     const bool qr = s == 0 ? qr1 : qr2;
     const int kk = s == 0 ? k1 : k2;
-    const int ncol_out = Dn * d;
-    // R~[kk, (b, a)]
-    for (int e = tid; e < g.rows * ncol_out; e += kT) {
-      const int col = e / g.rows, row = e % g.rows;
-      double v = 0.0;
-      if (row < kk) {
-        const int b = col / d, aa = col % d;
-        const int c = perm[b];
-        const double sg = sig[c];
-        const double rs = sqrt(sv[b]);
-        if (s == 0) {
-          // X[(row, aa), b] = Theta_c[(row, aa)] / sigma_c
-          v = sg > 0 ? Th[(long long)c * nr + row * d + aa] / sg * rs : 0.0;
-        } else {
-          // Y[(aa, row), b] = J[c][(aa, row)]
-          v = J[(long long)c * nc + aa * k2 + row] * rs;
+    double B[RPT][MC];
+    // R~[kk, (b, a)] in the rows the thread owns (rows >= kk are zero)
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+      const int row = tid + q * kT;
+#pragma unroll
+      for (int col = 0; col < MC; ++col) {
+        double v = 0.0;
+        if (row < kk && col < ncol_out) {
+          const int b = col / d, aa = col - b * d;
+          const int c = perm[b];
+          const double sg = sig[c];
+          const double rs = sqrt(sv[b]);
+          if (s == 0) v = sg > 0 ? Th[(long long)c * nr + row * d + aa] / sg * rs : 0.0;  // X[(row,aa),b]
+          else v = J[(long long)c * nc + aa * k2 + row] * rs;                               // Y[(aa,row),b]
+        }
+        B[q][col] = v;
+      }
+    }
+    if (qr)
+      house_apply<RPT, MC, LD>(park + (long long)s * MC * LD, g.cols, s == 0 ? tau1 : tau2, B, ncol_out, sb, step);
+    // scatter into the canonical layout with the new shared dimension
+    if (tid == 0) {
+      go[s] = g;
+      go[s].dims[g.shared] = Dn;
+      go[s].st[4] = 1;
+      for (int i = 3; i >= 0; --i) go[s].st[i] = go[s].st[i + 1] * go[s].dims[i + 1];
+    }
+    __syncthreads();
+    double* site = s == 0 ? site1 : site2;
+    const long long sst = go[s].st[g.shared];
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+      const int r = tid + q * kT;
+      if (r >= g.rows) continue;
+      const long long ro = row_off(go[s], r);
+#pragma unroll
+      for (int col = 0; col < MC; ++col) {
+        if (col < ncol_out) {
+          const int b = col / d, aa = col - b * d;
+          site[ro + b * sst + aa] = B[q][col];
         }
       }
-      Bm[e] = v;
     }
-    __syncthreads();
-    if (qr) {
-      for (int e = tid; e < g.rows * g.cols; e += kT) A[e] = (s == 0 ? scr1 : scr2)[e];
-      __syncthreads();
-      apply_q(A, g.rows, g.cols, s == 0 ? tau1 : tau2, Bm, ncol_out);
-    }
-    // scatter into the canonical layout with the new shared dimension
-    SiteGeom go = g;
-    go.dims[go.shared] = Dn;
-    go.st[4] = 1;
-    for (int i = 3; i >= 0; --i) go.st[i] = go.st[i + 1] * go.dims[i + 1];
-    go.cols = Dn * d;
-    double* site = s == 0 ? site1 : site2;
-    for (int e = tid; e < g.rows * ncol_out; e += kT) {
-      const int col = e / g.rows, row = e % g.rows;
-      site[site_off(go, row, col)] = Bm[e];
-    }
-    __syncthreads();
   }
   if (tid == 0) {
     a.dims[5 * s1 + g1.shared] = Dn;
@@ -404,22 +517,35 @@ __global__ __launch_bounds__(kT) void qrsvd_bond_kernel(IteArgs a) {
   }
 }
 
-size_t bond_lds_bytes(int max_rows, int max_cols) {
-  return (size_t)(2 * max_rows * max_cols + 2 * max_cols * max_cols + 2 * kMaxTh * kMaxTh + 5 * kMaxTh + 16) *
-         sizeof(double);
-}
+int rows_per_thread(int max_rows) { return (max_rows + kT - 1) / kT; }
 
 void check_dims(int64_t dmax, int d) {
   HP_REQUIRE(dmax >= 1 && d >= 1, HPEPS_ERR_INVALID_ARG, "bad bond or physical dimension");
   HP_REQUIRE(dmax * d * d <= kMaxTh, HPEPS_ERR_UNSUPPORTED, "QR-SVD kernel supports D d^2 <= 32");
-  HP_REQUIRE(bond_lds_bytes((int)(dmax * dmax * dmax), (int)(dmax * d)) <= 160 * 1024 - 4096,
-             HPEPS_ERR_UNSUPPORTED, "QR-SVD kernel: site too large for LDS (D^4 d <= 8192)");
+  HP_REQUIRE(dmax * d <= kMaxC && dmax * dmax * dmax <= kMaxRpt * kT, HPEPS_ERR_UNSUPPORTED,
+             "QR-SVD kernel supports D d <= 16 and D^3 <= 768");
 }
 
+// Variants: rows per thread x register columns.  D^3 > 512 needs D >= 9,
+// hence d = 1 and at most 9 columns.
 void launch_layer(hipStream_t st, const IteArgs& a, int nb) {
   if (nb == 0) return;
-  const size_t lds = bond_lds_bytes(a.max_rows, a.max_cols);
-  qrsvd_bond_kernel<<<nb, kT, lds, st>>>(a);
+  // the dynamic LDS limit is raised once per variant and process
+  static std::once_flag once[3];
+  auto go = [&](auto kern, int rpt, int mc) {
+    const size_t lds = (size_t)2 * mc * rpt * kT * sizeof(double);
+    hipError_t e = hipSuccess;
+    std::call_once(once[rpt - 1], [&] {
+      e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    });
+    HP_CHECK_HIP(e);
+    kern<<<nb, kT, lds, st>>>(a);
+  };
+  switch (rows_per_thread(a.max_rows)) {
+    case 1: go(qrsvd_bond_kernel<1, kMaxC>, 1, kMaxC); break;
+    case 2: go(qrsvd_bond_kernel<2, kMaxC>, 2, kMaxC); break;
+    default: go(qrsvd_bond_kernel<3, 9>, 3, 9); break;
+  }
 }
 
 IteArgs plan_args(hpeps_ite_plan* p, int layer) {
@@ -430,11 +556,10 @@ IteArgs plan_args(hpeps_ite_plan* p, int layer) {
   a.bonds = p->bonds[layer];
   a.gates = p->gates;
   a.dmax = (int)p->dmax;
-  a.scratch = p->scratch;
-  a.scratch_per = p->scratch_per;
-  a.sigma = p->sigma;
+  int off = 0;
+  for (int l = 0; l < layer; ++l) off += p->nb[l];
+  a.sigma = p->sigma + (int64_t)off * p->dmax;
   a.max_rows = (int)(p->dmax * p->dmax * p->dmax);
-  a.max_cols = (int)(p->dmax * p->d);
   return a;
 }
 
@@ -474,7 +599,6 @@ void free_plan(hpeps_ite_plan* p) {
   (void)hipFree(p->dims);
   for (auto& b : p->bonds) (void)hipFree(b);
   (void)hipFree(p->gates);
-  (void)hipFree(p->scratch);
   (void)hipFree(p->sigma);
   delete p;
 }
@@ -510,8 +634,8 @@ void* g_scratch_ptr[kMaxDevices] = {};
 size_t round256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 // One QR-SVD update of the bond (i, j)-(i2, j2) on the context's stream, with
-// the device buffers (staging copies of the two sites, reflector scratch,
-// dimension and bond tables, gate, singular values) taken from `take`.
+// the device buffers (staging copies of the two sites, dimension and bond
+// tables, gate, singular values) taken from `take`.
 template <class Take>
 void gate_update(hp::Ctx& c, hpeps_peps* peps, const int64_t* capacity, int32_t i, int32_t j, int32_t axis,
                  const void* G, int64_t max_rank, int64_t* new_bond, double* sigma_out, Take take) {
@@ -540,7 +664,6 @@ void gate_update(hp::Ctx& c, hpeps_peps* peps, const int64_t* capacity, int32_t 
   int* dims_dev = (int*)take(10 * sizeof(int));
   int* bond_dev = (int*)take(4 * sizeof(int));
   double* gate_dev = (double*)take((size_t)d * d * d * d * sizeof(double));
-  double* refl = (double*)take(2 * cap * sizeof(double));
   double* sig = (double*)take(max_rank * sizeof(double));
   int hd[10], hb[4] = {0, 1, axis, 0};
   for (int e = 0; e < 5; ++e) {
@@ -559,14 +682,8 @@ void gate_update(hp::Ctx& c, hpeps_peps* peps, const int64_t* capacity, int32_t 
   a.bonds = bond_dev;
   a.gates = gate_dev;
   a.dmax = (int)max_rank;
-  a.scratch = refl;
-  a.scratch_per = cap;
   a.sigma = sig;
   a.max_rows = (int)(max_rank * max_rank * max_rank);
-  a.max_cols = (int)(max_rank * d);
-  const size_t lds = hp::bond_lds_bytes(a.max_rows, a.max_cols);
-  HP_CHECK_HIP(hipFuncSetAttribute((const void*)hp::qrsvd_bond_kernel,
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   hp::launch_layer(c.stream, a, 1);
   HP_CHECK_HIP(hipGetLastError());
   int64_t* shp = const_cast<int64_t*>(peps->shapes);
@@ -584,7 +701,7 @@ void gate_update(hp::Ctx& c, hpeps_peps* peps, const int64_t* capacity, int32_t 
 // Device bytes gate_update takes for (max_rank, d), each piece 256-aligned.
 size_t gate_scratch_bytes(int64_t max_rank, int d) {
   const size_t cap = (size_t)(max_rank * max_rank * max_rank * max_rank * d);
-  return 2 * round256(2 * cap * sizeof(double)) + round256(10 * sizeof(int)) + round256(4 * sizeof(int)) +
+  return round256(2 * cap * sizeof(double)) + round256(10 * sizeof(int)) + round256(4 * sizeof(int)) +
          round256((size_t)d * d * d * d * sizeof(double)) + round256((size_t)max_rank * sizeof(double));
 }
 
@@ -639,7 +756,7 @@ hpeps_status hpeps_ite_plan_create(hpeps_ctx* ctx, const hpeps_peps* init, int32
     HP_CHECK_HIP(hipMalloc(&p->dims, dims.size() * sizeof(int)));
     HP_CHECK_HIP(hipMemcpy(p->dims, dims.data(), dims.size() * sizeof(int), hipMemcpyHostToDevice));
     auto layers = lattice_layers(L.nrow, L.ncol);
-    int q = 0, maxnb = 0;
+    int q = 0;
     for (int l = 0; l < 4; ++l) {
       std::vector<int> tb;
       for (auto& bd : layers[l]) {
@@ -648,7 +765,6 @@ hpeps_status hpeps_ite_plan_create(hpeps_ctx* ctx, const hpeps_peps* init, int32
         tb.insert(tb.end(), {bd[0], bd[1], bd[2], gi});
       }
       p->nb[l] = (int)layers[l].size();
-      maxnb = std::max(maxnb, p->nb[l]);
       if (!tb.empty()) {
         HP_CHECK_HIP(hipMalloc(&p->bonds[l], tb.size() * sizeof(int)));
         HP_CHECK_HIP(hipMemcpy(p->bonds[l], tb.data(), tb.size() * sizeof(int), hipMemcpyHostToDevice));
@@ -657,12 +773,10 @@ hpeps_status hpeps_ite_plan_create(hpeps_ctx* ctx, const hpeps_peps* init, int32
     const size_t gsz = (size_t)n_gates * d * d * d * d * sizeof(double);
     HP_CHECK_HIP(hipMalloc(&p->gates, gsz));
     HP_CHECK_HIP(hipMemcpyAsync(p->gates, gates, gsz, hipMemcpyDeviceToDevice, c.stream));
-    p->scratch_per = max_rank * max_rank * max_rank * max_rank * d;
-    HP_CHECK_HIP(hipMalloc(&p->scratch, (size_t)std::max(maxnb, 1) * 2 * p->scratch_per * sizeof(double)));
-    HP_CHECK_HIP(hipMalloc(&p->sigma, (size_t)std::max(maxnb, 1) * max_rank * sizeof(double)));
-    const size_t lds = hp::bond_lds_bytes((int)(max_rank * max_rank * max_rank), (int)(max_rank * d));
-    HP_CHECK_HIP(hipFuncSetAttribute((const void*)hp::qrsvd_bond_kernel,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    int total_nb = 0;
+    for (int l = 0; l < 4; ++l) total_nb += p->nb[l];
+    HP_CHECK_HIP(hipMalloc(&p->sigma, (size_t)std::max(total_nb, 1) * max_rank * sizeof(double)));
+    HP_CHECK_HIP(hipMemsetAsync(p->sigma, 0, (size_t)std::max(total_nb, 1) * max_rank * sizeof(double), c.stream));
     HP_CHECK_HIP(hipStreamSynchronize(c.stream));
   });
   if (st != HPEPS_OK) {
@@ -680,6 +794,22 @@ hpeps_status hpeps_ite_run(hpeps_ite_plan* p, int32_t n_sweeps, int32_t use_grap
     auto sweep = [&](hipStream_t st) {
       for (int l = 0; l < 4; ++l) hp::launch_layer(st, hp::plan_args(p, l), p->nb[l]);
     };
+    if (use_graph == 2) {
+      // plain form: one launch per bond, no graph (the baseline the batched
+      // layer launches and their graph replay are measured against)
+      for (int s = 0; s < n_sweeps; ++s)
+        for (int l = 0; l < 4; ++l) {
+          hp::IteArgs a = hp::plan_args(p, l);
+          for (int b = 0; b < p->nb[l]; ++b) {
+            hp::IteArgs ab = a;
+            ab.bonds = a.bonds + 4 * b;
+            ab.sigma = a.sigma + (int64_t)b * p->dmax;
+            hp::launch_layer(c.stream, ab, 1);
+          }
+        }
+      HP_CHECK_HIP(hipGetLastError());
+      return;
+    }
     if (!use_graph) {
       for (int s = 0; s < n_sweeps; ++s) sweep(c.stream);
       HP_CHECK_HIP(hipGetLastError());
@@ -723,6 +853,17 @@ hpeps_status hpeps_ite_get_state(hpeps_ite_plan* p, int64_t* shapes, void* const
       }
       HP_CHECK_HIP(hipStreamSynchronize(c.stream));
     }
+  });
+}
+
+hpeps_status hpeps_ite_spectra(hpeps_ite_plan* p, double* out) {
+  if (!p || !out) return HPEPS_ERR_INVALID_ARG;
+  hp::Ctx& c = *p->ctx;
+  return guard_i(&c, [&] {
+    int total = 0;
+    for (int l = 0; l < 4; ++l) total += p->nb[l];
+    HP_CHECK_HIP(hipMemcpyAsync(out, p->sigma, (size_t)total * p->dmax * sizeof(double), hipMemcpyDeviceToDevice,
+                                c.stream));
   });
 }
 

@@ -80,6 +80,12 @@ hpeps_status hpeps_test_householder(hpeps_ctx* ctx, hpeps_dtype dtype, int64_t b
   });
 }
 
+hpeps_status hpeps_test_strip_chunk_bytes(hpeps_ctx* ctx, int64_t bytes) {
+  if (!ctx || bytes < 1) return HPEPS_ERR_INVALID_ARG;
+  ctx->impl->strip_chunk_bytes = bytes;
+  return HPEPS_OK;
+}
+
 hpeps_status hpeps_test_small_svd(hpeps_ctx* ctx, hpeps_dtype dtype, int64_t batch, int64_t k,
                                   const void* R, void* Z, double* sigma) {
   return guard_t(ctx, [&](hp::Ctx& c) {

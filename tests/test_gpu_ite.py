@@ -69,37 +69,96 @@ def _tfi_plan_inputs(nrow, ncol, tau, J=1.0, hfield=3.0):
     return layers, gates, np.stack(uniq), bond_gate
 
 
-def _overlap(a, b):
-    return abs(np.vdot(a, b)) / (np.linalg.norm(a) * np.linalg.norm(b))
+def _bond_product_spectra(peps, layers, D):
+    """Gauge-invariant content of every bond of a lattice: the singular values of the two
+    sites contracted over the bond (matricized as the left site's other legs and p against
+    the right site's), from the R factors of both matricizations.  Invariant under any
+    orthogonal change of basis on every bond."""
+    out = []
+    for li, layer in enumerate(layers):
+        for (s1, s2) in layer:
+            A, B = peps[s1[0]][s1[1]], peps[s2[0]][s2[1]]
+            if li < 2:
+                Am = A.transpose(0, 1, 2, 4, 3).reshape(-1, A.shape[3])
+                Bm = B.transpose(0, 1, 3, 4, 2).reshape(-1, B.shape[2])
+            else:
+                Am = A.transpose(0, 2, 3, 4, 1).reshape(-1, A.shape[1])
+                Bm = B.transpose(1, 2, 3, 4, 0).reshape(-1, B.shape[0])
+            Ra = np.linalg.qr(Am)[1]
+            Rb = np.linalg.qr(Bm)[1]
+            out.append(np.linalg.svd(Ra @ Rb.T, compute_uv=False))
+    return out
 
 
 @pytest.mark.parametrize("shape,Dmax,sweeps", [((2, 2), 8, 3), ((2, 3), 8, 4), ((3, 3), 4, 3),
                                                ((4, 4), 3, 5), ((3, 4), 2, 6)])
-@pytest.mark.parametrize("use_graph", [True, False])
-def test_ite_sweeps_match_oracle(ctx, shape, Dmax, sweeps, use_graph):
+@pytest.mark.parametrize("mode", ["graph", "layers", "per_bond"])
+def test_ite_sweeps_match_oracle(ctx, shape, Dmax, sweeps, mode):
+    """Sweeps of the batched plan (graph replay, direct layer launches, one launch per
+    bond) against the oracle's TEBD: equal shapes, every bond's kept singular values of
+    the last sweep at 1e-12, and the normalised state vectors element by element at 1e-10
+    (after the one global sign the two factorizations may differ by)."""
     nrow, ncol = shape
     layers, gates, uniq, bond_gate = _tfi_plan_inputs(nrow, ncol, 0.1)
     peps0 = synth.product_state_peps(nrow, ncol, seed=3)
-    ref, _ = ite.ite(peps0, layers, gates, Dmax, sweeps)
+    ref, spec_ref = ite.ite(peps0, layers, gates, Dmax, sweeps)
     plan = hp.ItePlan(ctx, dev_lattice(peps0), torch.from_numpy(uniq).cuda(), bond_gate, Dmax)
-    plan.run(sweeps, use_graph=use_graph)
+    plan.run(sweeps, use_graph=mode == "graph", per_bond=mode == "per_bond")
     got = host_lattice(plan.state())
+    spec = plan.spectra().cpu().numpy()
     plan.close()
     for r in range(nrow):
         for c in range(ncol):
             assert got[r][c].shape == ref[r][c].shape
-    ov = _overlap(sv.peps_to_statevector(got).ravel(), sv.peps_to_statevector(ref).ravel())
-    assert abs(1 - ov) < 1e-10
+    for b, s in enumerate(spec_ref):
+        assert np.max(np.abs(spec[b, :len(s)] - s)) < 1e-12
+        assert np.all(spec[b, len(s):] == 0)
+    a = sv.peps_to_statevector(got).ravel()
+    e = sv.peps_to_statevector(ref).ravel()
+    a, e = a / np.linalg.norm(a), e / np.linalg.norm(e)
+    sgn = np.sign(np.vdot(e, a).real)
+    assert np.max(np.abs(sgn * a - e)) < 1e-10
+
+
+def test_ite_c4_lattice_matches_oracle(ctx):
+    """The 16 x 16, D = 8 transverse-field Ising lattice (J = 1, h = 3, tau = 0.01, 480 bonds
+    per sweep, edge bonds of uneven dimension, bonds growing 1 -> 8): six sweeps from the
+    random product state, sweep by sweep, against the oracle.  Every bond's kept singular
+    values of every sweep at 1e-10, the shapes of all 256 sites, and after the last sweep
+    the gauge-invariant singular values of every two-site product over its bond at 1e-10
+    of the largest."""
+    n, D, sweeps = 16, 8, 6
+    layers, gates, uniq, bond_gate = _tfi_plan_inputs(n, n, 0.01)
+    peps0 = synth.product_state_peps(n, n, seed=0)
+    plan = hp.ItePlan(ctx, dev_lattice(peps0), torch.from_numpy(uniq).cuda(), bond_gate, D)
+    ref = [[t.copy() for t in row] for row in peps0]
+    for sw in range(sweeps):
+        spec_ref = ite.ite_sweep(ref, layers, gates, D)
+        plan.run(1)
+        spec = plan.spectra().cpu().numpy()
+        assert len(spec_ref) == spec.shape[0] == 480
+        for b, s in enumerate(spec_ref):
+            assert np.max(np.abs(spec[b, :len(s)] - s)) < 1e-10, (sw, b)
+            assert np.all(spec[b, len(s):] == 0)
+    got = host_lattice(plan.state())
+    plan.close()
+    for r in range(n):
+        for c in range(n):
+            assert got[r][c].shape == ref[r][c].shape
+    assert max(max(t.shape[:4]) for row in got for t in row) == D
+    pg, pr = _bond_product_spectra(got, layers, D), _bond_product_spectra(ref, layers, D)
+    for x, y in zip(pg, pr):
+        assert np.max(np.abs(x - y)) <= 1e-10 * y[0]
 
 
 def test_ite_graph_replay_is_deterministic(ctx):
     layers, gates, uniq, bond_gate = _tfi_plan_inputs(4, 4, 0.05)
     peps0 = synth.product_state_peps(4, 4, seed=1)
     outs = []
-    for use_graph in (True, True, False):
+    for use_graph, per_bond in ((True, False), (True, False), (False, False), (False, True)):
         plan = hp.ItePlan(ctx, dev_lattice(peps0), torch.from_numpy(uniq).cuda(), bond_gate, 4)
-        plan.run(3, use_graph=use_graph)
-        plan.run(2, use_graph=use_graph)
+        plan.run(3, use_graph=use_graph, per_bond=per_bond)
+        plan.run(2, use_graph=use_graph, per_bond=per_bond)
         outs.append(host_lattice(plan.state()))
         plan.close()
     for o in outs[1:]:
