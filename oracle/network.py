@@ -47,19 +47,21 @@ def zipup_operator(V, S, T, B):
     _, Y, _, G, _ = B.shape
     Bc = B.conj()
 
-    # one pairwise contraction per tensor of the network (multi-operand
-    # einsum path searches can pick orders that are orders of magnitude slower)
+    # one pairwise contraction per tensor of the network, in the order of the
+    # stages (multi-operand einsum path searches can pick orders that are
+    # orders of magnitude slower); each pairwise contraction is one matrix
+    # product (BLAS), the library primitive a step may use
     def fwd(Om):
-        W = np.einsum("uyhgp,yYcgGj->uhpYcGj", T, Om)
-        W = np.einsum("UYHGp,uhpYcGj->uhUHcj", Bc, W)
-        W = np.einsum("buUc,uhUHcj->bhHj", S, W)
-        return np.einsum("axXbhH,bhHj->axXj", V, W)
+        W = np.einsum("uyhgp,yYcgGj->uhpYcGj", T, Om, optimize=True)
+        W = np.einsum("UYHGp,uhpYcGj->uhUHcj", Bc, W, optimize=True)
+        W = np.einsum("buUc,uhUHcj->bhHj", S, W, optimize=True)
+        return np.einsum("axXbhH,bhHj->axXj", V, W, optimize=True)
 
     def adj(P):
-        W = np.einsum("axXbhH,axXj->bhHj", V.conj(), P)
-        W = np.einsum("buUc,bhHj->uhUHcj", S.conj(), W)
-        W = np.einsum("UYHGp,uhUHcj->uhpYcGj", B, W)
-        return np.einsum("uyhgp,uhpYcGj->yYcgGj", T.conj(), W)
+        W = np.einsum("axXbhH,axXj->bhHj", V.conj(), P, optimize=True)
+        W = np.einsum("buUc,bhHj->uhUHcj", S.conj(), W, optimize=True)
+        W = np.einsum("UYHGp,uhUHcj->uhpYcGj", B, W, optimize=True)
+        return np.einsum("uyhgp,uhpYcGj->yYcgGj", T.conj(), W, optimize=True)
 
     def explicit():
         return np.einsum("axXbhH,buUc,uyhgp,UYHGp->axXyYcgG", V, S, T, Bc, optimize=True)
@@ -79,20 +81,20 @@ def pair_operator(Bl, Br, T1, T2, T1b=None, T2b=None):
     sub = "auUb,bvVc,uxhp,UXHp,vyhq,VYHq"
 
     def fwd(Om):
-        W = np.einsum("vyhq,yYcj->vhqYcj", t2, Om)
-        W = np.einsum("VYHq,vhqYcj->vhVHcj", t2b, W)
-        W = np.einsum("bvVc,vhVHcj->bhHj", Br, W)
-        W = np.einsum("auUb,bhHj->auUhHj", Bl, W)
-        W = np.einsum("uxhp,auUhHj->axpUHj", t1, W)
-        return np.einsum("UXHp,axpUHj->axXj", t1b, W)
+        W = np.einsum("vyhq,yYcj->vhqYcj", t2, Om, optimize=True)
+        W = np.einsum("VYHq,vhqYcj->vhVHcj", t2b, W, optimize=True)
+        W = np.einsum("bvVc,vhVHcj->bhHj", Br, W, optimize=True)
+        W = np.einsum("auUb,bhHj->auUhHj", Bl, W, optimize=True)
+        W = np.einsum("uxhp,auUhHj->axpUHj", t1, W, optimize=True)
+        return np.einsum("UXHp,axpUHj->axXj", t1b, W, optimize=True)
 
     def adj(P):
-        W = np.einsum("UXHp,axXj->axpUHj", t1b.conj(), P)
-        W = np.einsum("uxhp,axpUHj->auUhHj", t1.conj(), W)
-        W = np.einsum("auUb,auUhHj->bhHj", Bl.conj(), W)
-        W = np.einsum("bvVc,bhHj->vhVHcj", Br.conj(), W)
-        W = np.einsum("VYHq,vhVHcj->vhqYcj", t2b.conj(), W)
-        return np.einsum("vyhq,vhqYcj->yYcj", t2.conj(), W)
+        W = np.einsum("UXHp,axXj->axpUHj", t1b.conj(), P, optimize=True)
+        W = np.einsum("uxhp,axpUHj->auUhHj", t1.conj(), W, optimize=True)
+        W = np.einsum("auUb,auUhHj->bhHj", Bl.conj(), W, optimize=True)
+        W = np.einsum("bvVc,bhHj->vhVHcj", Br.conj(), W, optimize=True)
+        W = np.einsum("VYHq,vhVHcj->vhqYcj", t2b.conj(), W, optimize=True)
+        return np.einsum("vyhq,vhqYcj->yYcj", t2.conj(), W, optimize=True)
 
     def explicit():
         return np.einsum(sub + "->axXyYc", Bl, Br, t1, t1b, t2, t2b, optimize=True)
