@@ -359,34 +359,40 @@ static void chain_rinv(Ctx& ctx, bool cplx, double* Rt, const double* Rinv, doub
                               ctx.stream));
 }
 
-// Orthonormal basis of range(Y): result in P; Y is overwritten.  Rt_inv
-// (optional, k x k per instance) receives the inverse of the total factor R
-// with Y = P R (the product of the passes' inverses).
+// Orthonormal basis of range(Y): result in P; Y is overwritten unless the
+// Householder fallback may run.  Rt_inv (optional, k x k per instance)
+// receives the inverse of the total factor R with Y = P R (the product of
+// the passes' inverses).
 void orthogonalize(Ctx& ctx, bool cplx, double* Y, double* P, int64_t n, int64_t k, int batch,
                    const OrthWork& w, double* Rt_inv) {
   WsScope scope(ctx);
+  const bool fallback = !Rt_inv && !taping(ctx);
   double* S = Rt_inv ? ctx.ws<double>((int64_t)batch * k * k * (cplx ? 2 : 1)) : nullptr;
+  // second-pass output: a scratch panel when the fallback may need Y intact
+  double* Y2 = fallback ? ctx.ws<double>((int64_t)batch * n * k * (cplx ? 2 : 1)) : Y;
   gram(ctx, cplx, Y, n, k, batch, w.G, nullptr);
   chol_inv(ctx, cplx, w.G, n, k, batch, 1, w.Rinv, nullptr, w.flags);
   apply_rinv(ctx, cplx, Y, n, k, batch, w.Rinv, P, nullptr);
   if (Rt_inv)
     HP_CHECK_HIP(hipMemcpyAsync(Rt_inv, w.Rinv, (size_t)batch * k * k * (cplx ? 16 : 8),
                                 hipMemcpyDeviceToDevice, ctx.stream));
-  // panels flagged in pass 1 (rank-deficient or very ill-conditioned): the
-  // Householder QR of Y replaces P before the next passes (which then leave
-  // it unchanged to rounding).  Not while differentiating: the adjoint of
-  // the orthogonalization is the CholeskyQR one.
-  if (!Rt_inv && !taping(ctx)) householder_qr(ctx, cplx, Y, n, k, batch, w.flags, FLAG_THIRD_PASS, P, nullptr);
   gram(ctx, cplx, P, n, k, batch, w.G, nullptr);
   chol_inv(ctx, cplx, w.G, n, k, batch, 2, w.Rinv, nullptr, w.flags);
-  apply_rinv(ctx, cplx, P, n, k, batch, w.Rinv, Y, nullptr);
+  apply_rinv(ctx, cplx, P, n, k, batch, w.Rinv, Y2, nullptr);
   if (Rt_inv) chain_rinv(ctx, cplx, Rt_inv, w.Rinv, S, k, batch);
+  // sketches whose second-pass Gram breaks down are numerically
+  // rank-deficient: a Gram-based factorization cannot resolve their weak and
+  // null directions, so the Householder QR of the original Y replaces the
+  // second pass's output (the third pass then leaves it unchanged to
+  // rounding).  Not while differentiating: the adjoint of the
+  // orthogonalization is the CholeskyQR one.
+  if (fallback) householder_qr(ctx, cplx, Y, n, k, batch, w.flags, FLAG_RANK_DEFICIENT, Y2, nullptr);
   // third pass: the Gram only of flagged instances (the factor step writes
   // the identity for the others without reading G); a recording tape keeps
   // every Gram
-  gram(ctx, cplx, Y, n, k, batch, w.G, taping(ctx) ? nullptr : w.flags);
+  gram(ctx, cplx, Y2, n, k, batch, w.G, taping(ctx) ? nullptr : w.flags);
   chol_inv(ctx, cplx, w.G, n, k, batch, 3, w.Rinv, nullptr, w.flags);
-  apply_rinv(ctx, cplx, Y, n, k, batch, w.Rinv, P, w.flags);
+  apply_rinv(ctx, cplx, Y2, n, k, batch, w.Rinv, P, w.flags);
   if (Rt_inv) chain_rinv(ctx, cplx, Rt_inv, w.Rinv, S, k, batch);
   stats_reduce(ctx, w.flags, nullptr, batch, ctx.stats_dev);
 }
@@ -402,8 +408,8 @@ void cholqr_r(Ctx& ctx, bool cplx, const double* Y, double* S1, double* S2, int6
   apply_rinv(ctx, cplx, S1, n, k, batch, w.Rinv, S2, w.flags);
   gram(ctx, cplx, S2, n, k, batch, w.G, taping(ctx) ? nullptr : w.flags);
   chol_inv(ctx, cplx, w.G, n, k, batch, 3, w.Rinv, w.Racc, w.flags);
-  // flagged panels: R of the Householder QR of Y (kept unchanged above)
-  if (!taping(ctx)) householder_qr(ctx, cplx, Y, n, k, batch, w.flags, FLAG_THIRD_PASS, nullptr, w.Racc);
+  // rank-deficient panels: R of the Householder QR of Y (kept unchanged above)
+  if (!taping(ctx)) householder_qr(ctx, cplx, Y, n, k, batch, w.flags, FLAG_RANK_DEFICIENT, nullptr, w.Racc);
   stats_reduce(ctx, w.flags, nullptr, batch, ctx.stats_dev);
 }
 

@@ -117,6 +117,7 @@ void gram(Ctx& ctx, bool cplx, const void* Y, int64_t n, int64_t k, int batch, d
 constexpr int FLAG_THIRD_PASS = 2;   // ill-conditioned or rank-deficient: third pass / fallback
 constexpr int FLAG_NUMERIC = 4;      // non-finite values met
 constexpr int FLAG_HOUSEHOLDER = 8;  // the Householder fallback replaced the factor
+constexpr int FLAG_RANK_DEFICIENT = 16;  // pass 2's unshifted Cholesky broke down or spans 1e7 (kappa above ~1e13)
 // CholeskyQR step on G (k x k, Hermitian): writes Rinv (k x k upper).  pass 1
 // may shift; flags[b] bit 1 is set when a third pass is needed, bit 2 on
 // non-finite values.  pass 3 is skipped (Rinv = I) unless bit 1 is set.

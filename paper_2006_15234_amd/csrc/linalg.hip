@@ -231,9 +231,14 @@ __global__ __launch_bounds__(kCholThreads) void chol_inv_kernel(const double* Ga
         __syncthreads();
         continue;  // redo with the shift
       }
+      // the first pass's output is still this ill-conditioned: the sketch is
+      // numerically rank-deficient (condition number beyond about 1e13)
+      if (attempt == 0 && illcond && pass == 2) f |= FLAG_RANK_DEFICIENT;
       break;
     }
     f |= FLAG_THIRD_PASS;
+    // or the Gram of the first pass's output breaks down
+    if (attempt == 0 && pass == 2) f |= FLAG_RANK_DEFICIENT;
     __syncthreads();
   }
   if (!ok) {
