@@ -353,10 +353,26 @@ def c5_gradient(hp, reps, n=8, D=4, d=2, m=16, p=8, q=1):
     hp.peps_energy_backward(ctx, dev, terms, **kw)
     agg = hp.profile_read(ctx)
     hp.profile_stop(ctx)
+
+    def peak_mib(lattice, on, tms):
+        c = hp.Context(0)
+        c.check(c.lib.hpeps_test_checkpoint_rows(c.h, on))
+        hp.workspace_peak(c, reset=True)
+        hp.peps_energy_backward(c, lattice, tms, **kw)
+        return round(hp.workspace_peak(c) / 2 ** 20, 1)
+
+    big = 12
+    peps_b = synth.random_peps(big, big, D=D, seed=0, complex_=True)
+    dev_b = [[torch.from_numpy(np.ascontiguousarray(t)).cuda() for t in row] for row in peps_b]
+    terms_b = [((s1, s2), Hb) for layer in synth.lattice_bonds(big, big) for (s1, s2) in layer]
+    memory = {f"{n}x{n}": {"row_checkpoints": peak_mib(dev, 1, terms), "full_tape": peak_mib(dev, 0, terms)},
+              f"{big}x{big}": {"row_checkpoints": peak_mib(dev_b, 1, terms_b),
+                               "full_tape": peak_mib(dev_b, 0, terms_b)}}
     return {"workload": f"energy gradient {n}x{n} D={D} d={d} complex128 Heisenberg, m={m} p={p} q={q}",
             "sites": n * n, "terms": len(terms), "energy": [e.real, e.imag],
             "energy_ms": round(fwd * 1e3, 2), "energy_and_gradient_ms": round(bwd * 1e3, 2),
             "gradient_over_energy": round(bwd / fwd, 2),
+            "peak_workspace_mib": memory,
             "gradient_kernel_classes": {k: {"ms": round(a["ms"], 2), "launches": a["launches"]}
                                         for k, a in sorted(agg.items(), key=lambda x: -x[1]["ms"])[:8]}}
 

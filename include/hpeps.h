@@ -144,6 +144,10 @@ const char* hpeps_last_error(hpeps_ctx* ctx);
 /* Caps the workspace arena (bytes; 0 = no cap).  Calls that would need more
  * return HPEPS_ERR_ALLOC before launching anything. */
 hpeps_status hpeps_set_workspace_limit(hpeps_ctx* ctx, int64_t bytes);
+/* High-water mark of the workspace arena in bytes (device memory the
+ * library's calls on this context had in use at once) since creation or the
+ * last reset; reset != 0 restarts it from zero afterwards. */
+hpeps_status hpeps_workspace_peak(hpeps_ctx* ctx, int64_t* bytes, int32_t reset);
 /* Synchronises the stream and copies the diagnostics accumulated since the
  * last call of hpeps_get_info (or creation) to *info, then clears them. */
 hpeps_status hpeps_get_info(hpeps_ctx* ctx, hpeps_esvd_info* info);

@@ -43,6 +43,12 @@ hpeps_status hpeps_test_householder(hpeps_ctx* ctx, hpeps_dtype dtype, int64_t b
  * Small budgets force the chunked path on small lattices. */
 hpeps_status hpeps_test_strip_chunk_bytes(hpeps_ctx* ctx, int64_t bytes);
 
+/* Reverse mode of the norm and energy gradients: on != 0 (the default)
+ * checkpoints every zip-up row of the boundary passes (only its input
+ * boundary is kept, the row is recomputed in the reverse walk); 0 records
+ * every intermediate of every row instead.  Both give the same gradients. */
+hpeps_status hpeps_test_checkpoint_rows(hpeps_ctx* ctx, int32_t on);
+
 /* Small SVD stage: for the upper-triangular R [k,k] writes Z [k,k] (left
  * singular vectors of R^H, columns sorted by descending singular value) and
  * sigma [k] (double).  One-sided Jacobi. */

@@ -14,7 +14,7 @@ from .api import (  # noqa: F401
     einsumsvd, einsumsvd_zipup, einsumsvd_pair, einsumsvd_pair_backward, einsumsvd_pair_autograd,
     peps_norm, peps_amplitude, peps_amplitudes, boundary_contract_row, peps_energy, peps_norm_backward, peps_energy_backward,
     peps_energy_autograd,
-    apply_two_site_gate, ItePlan, get_info, sketch, make_opts, profile_start, profile_stop,
+    apply_two_site_gate, ItePlan, get_info, workspace_peak, sketch, make_opts, profile_start, profile_stop,
     profile_read, profile_by_shape, autotune_enable, autotune_export, autotune_import, autotune_save,
     autotune_load,
 )

@@ -65,6 +65,7 @@ _SIGS = {
     "hpeps_status_string": (C.c_char_p, [C.c_int]),
     "hpeps_last_error": (C.c_char_p, [_P]),
     "hpeps_set_workspace_limit": (C.c_int, [_P, C.c_int64]),
+    "hpeps_workspace_peak": (C.c_int, [_P, _I64P, C.c_int32]),
     "hpeps_get_info": (C.c_int, [_P, C.POINTER(EsvdInfo)]),
     "hpeps_autotune_enable": (C.c_int, [_P, C.c_int32]),
     "hpeps_autotune_export": (C.c_int, [_P, C.c_char_p, C.c_int64, _I64P]),
@@ -119,6 +120,7 @@ _SIGS = {
     "hpeps_test_orthogonalize": (C.c_int, [_P, C.c_int, C.c_int64, C.c_int64, C.c_int64, _P, _P]),
     "hpeps_test_householder": (C.c_int, [_P, C.c_int, C.c_int64, C.c_int64, C.c_int64, _P, _P, _P]),
     "hpeps_test_strip_chunk_bytes": (C.c_int, [_P, C.c_int64]),
+    "hpeps_test_checkpoint_rows": (C.c_int, [_P, C.c_int32]),
     "hpeps_test_small_svd": (C.c_int, [_P, C.c_int, C.c_int64, C.c_int64, _P, _P, _P]),
     "hpeps_test_zip_apply": (C.c_int, [_P, C.c_int, C.c_int64, _I64P, _P, _P, _P, _P, C.c_int64,
                                        C.c_int32, _P, _P]),

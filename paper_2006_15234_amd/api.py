@@ -283,6 +283,13 @@ def autotune_load(ctx, path):
         autotune_import(ctx, f.read())
 
 
+def workspace_peak(ctx, reset=False):
+    """High-water mark of the library's workspace (bytes) on this context."""
+    b = C.c_int64()
+    ctx.check(ctx.lib.hpeps_workspace_peak(ctx.h, C.byref(b), 1 if reset else 0))
+    return b.value
+
+
 def get_info(ctx):
     info = EsvdInfo()
     ctx.check(ctx.lib.hpeps_get_info(ctx.h, C.byref(info)))

@@ -91,6 +91,13 @@ hpeps_status hpeps_set_workspace_limit(hpeps_ctx* ctx, int64_t bytes) {
   return HPEPS_OK;
 }
 
+hpeps_status hpeps_workspace_peak(hpeps_ctx* ctx, int64_t* bytes, int32_t reset) {
+  if (!ctx || !bytes) return HPEPS_ERR_INVALID_ARG;
+  *bytes = ctx->impl->ws_peak;
+  if (reset) ctx->impl->ws_peak = 0;
+  return HPEPS_OK;
+}
+
 hpeps_status hpeps_get_info(hpeps_ctx* ctx, hpeps_esvd_info* info) {
   if (!ctx || !info) return HPEPS_ERR_INVALID_ARG;
   return guard(ctx, [&] {

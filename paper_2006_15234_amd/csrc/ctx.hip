@@ -1,4 +1,5 @@
 // Context: stream, workspace arena and the cache of gather tables.
+#include <algorithm>
 #include <sstream>
 
 #include "internal.h"
@@ -188,6 +189,9 @@ void* Ctx::ws_alloc(int64_t bytes) {
   }
   void* p = chunks_[cur_].base + ws_off_;
   ws_off_ += bytes;
+  int64_t in_use = ws_off_;
+  for (int i = 0; i < cur_; ++i) in_use += chunks_[i].cap;
+  ws_peak = std::max(ws_peak, in_use);
   return p;
 }
 

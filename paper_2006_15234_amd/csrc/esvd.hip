@@ -366,7 +366,9 @@ static void chain_rinv(Ctx& ctx, bool cplx, double* Rt, const double* Rinv, doub
 void orthogonalize(Ctx& ctx, bool cplx, double* Y, double* P, int64_t n, int64_t k, int batch,
                    const OrthWork& w, double* Rt_inv) {
   WsScope scope(ctx);
-  const bool fallback = !Rt_inv && !taping(ctx);
+  // (no fallback under a tape, recording or suspended: the reverse walk
+  // differentiates, and a checkpointed row recomputes, the CholeskyQR path)
+  const bool fallback = !Rt_inv && !ctx.tape;
   double* S = Rt_inv ? ctx.ws<double>((int64_t)batch * k * k * (cplx ? 2 : 1)) : nullptr;
   // second-pass output: a scratch panel when the fallback may need Y intact
   double* Y2 = fallback ? ctx.ws<double>((int64_t)batch * n * k * (cplx ? 2 : 1)) : Y;
@@ -409,7 +411,7 @@ void cholqr_r(Ctx& ctx, bool cplx, const double* Y, double* S1, double* S2, int6
   gram(ctx, cplx, S2, n, k, batch, w.G, taping(ctx) ? nullptr : w.flags);
   chol_inv(ctx, cplx, w.G, n, k, batch, 3, w.Rinv, w.Racc, w.flags);
   // rank-deficient panels: R of the Householder QR of Y (kept unchanged above)
-  if (!taping(ctx)) householder_qr(ctx, cplx, Y, n, k, batch, w.flags, FLAG_RANK_DEFICIENT, nullptr, w.Racc);
+  if (!ctx.tape) householder_qr(ctx, cplx, Y, n, k, batch, w.flags, FLAG_RANK_DEFICIENT, nullptr, w.Racc);
   stats_reduce(ctx, w.flags, nullptr, batch, ctx.stats_dev);
 }
 

@@ -213,6 +213,13 @@ class Ctx {
   // byte budget of one intermediate of an energy strip column (larger ones are
   // split along the bottom-environment leg)
   int64_t strip_chunk_bytes = (int64_t)1 << 30;
+  // reverse mode: checkpoint each zip-up row of a boundary pass (store its
+  // input boundary, recompute the row in the reverse walk) instead of
+  // recording every intermediate of the row
+  bool checkpoint_rows = true;
+  // high-water mark of the workspace arena (bytes in use), since creation or
+  // the last hpeps_workspace_peak reset
+  int64_t ws_peak = 0;
 
   // device index table for an IndexMap (int32 offsets), cached
   const int* table(const IndexMap& m);

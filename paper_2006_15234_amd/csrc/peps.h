@@ -59,6 +59,27 @@ void absorb_row(Ctx& ctx, bool cplx, const std::vector<BndView>& bnd,
                 const hpeps_esvd_opts& o, const std::vector<uint64_t>& stream_ids,
                 std::vector<DevTensor>& out, double* log_dev);
 
+// Everything a checkpointed zip-up row needs to be rerun in the reverse walk
+// (views of its input boundary and sites, its direction, options and sketch
+// streams, and its output tensors).
+struct RowCheckpoint {
+  bool cplx = false;
+  std::vector<BndView> bnd;
+  std::vector<SiteView> ket, bra;
+  Dir dir = kL2R;
+  hpeps_esvd_opts o{};
+  std::vector<uint64_t> sids;
+  std::vector<DevTensor> out;
+};
+
+// absorb_row under a recording tape: with Ctx::checkpoint_rows the row runs
+// unrecorded and one checkpoint op is recorded in its place; otherwise every
+// operation of the row is recorded.  Without a tape it is absorb_row.
+void absorb_row_recorded(Ctx& ctx, bool cplx, const std::vector<BndView>& bnd,
+                         const std::vector<SiteView>& ket, const std::vector<SiteView>& bra, Dir dir,
+                         const hpeps_esvd_opts& o, const std::vector<uint64_t>& stream_ids,
+                         std::vector<DevTensor>& out, double* log_dev);
+
 // Exact contraction of a boundary MPS with a last row (its far legs of dim 1)
 // in the oriented frame (L2R); writes the (complex) scalar mantissa to
 // result_dev (2 doubles) and adds the logs to log_dev.

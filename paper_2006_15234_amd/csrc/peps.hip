@@ -17,6 +17,8 @@
 #include <cstring>
 
 #include "peps.h"
+#include <memory>
+
 #include "tape.h"
 
 namespace hp {
@@ -242,6 +244,83 @@ void absorb_row(Ctx& ctx, bool cplx, const std::vector<BndView>& bnd,
   }
 }
 
+void absorb_row_recorded(Ctx& ctx, bool cplx, const std::vector<BndView>& bnd,
+                         const std::vector<SiteView>& ket, const std::vector<SiteView>& bra, Dir dir,
+                         const hpeps_esvd_opts& o, const std::vector<uint64_t>& stream_ids,
+                         std::vector<DevTensor>& out, double* log_dev) {
+  if (!taping(ctx) || !ctx.checkpoint_rows) {
+    absorb_row(ctx, cplx, bnd, ket, bra, dir, o, stream_ids, out, log_dev);
+    return;
+  }
+  {
+    TapeSuspend unrecorded(ctx);  // the row's workspace is released at its end
+    absorb_row(ctx, cplx, bnd, ket, bra, dir, o, stream_ids, out, log_dev);
+  }
+  auto w = std::make_shared<RowCheckpoint>();
+  w->cplx = cplx;
+  w->bnd = bnd;
+  w->ket = ket;
+  w->bra = bra;
+  w->dir = dir;
+  w->o = o;
+  w->sids = stream_ids;
+  w->out = out;
+  TapeOp op;
+  op.kind = TapeOp::ROW;
+  op.row = w;
+  ctx.tape->record(op);
+}
+
+void row_backward(Ctx& ctx, const RowCheckpoint& r, Tape& main, double broadening) {
+  const int es = r.cplx ? 2 : 1;
+  bool any = false;
+  for (const auto& t : r.out) any = any || main.grad_if_live(t.p);
+  if (!any) return;
+  // the inputs that carry gradients; their adjoints in the main tape are
+  // allocated before the recompute's scope (they outlive it)
+  std::vector<std::pair<const void*, int64_t>> ins;
+  auto add = [&](const void* p, int64_t n) {
+    if (!main.depends(p)) return;
+    for (auto& e : ins)
+      if (e.first == p) {
+        e.second = std::max(e.second, n);
+        return;
+      }
+    ins.push_back({p, n});
+  };
+  for (const auto& b : r.bnd) add(b.p, b.extent);
+  for (const auto& t : r.ket) add(t.p, t.extent);
+  for (const auto& t : r.bra) add(t.p, t.extent);
+  std::vector<double*> gmain;
+  for (auto& e : ins) gmain.push_back(main.grad(ctx, e.first));
+  WsScope scope(ctx);
+  std::vector<DevTensor> out2 = r.out;
+  for (auto& t : out2) t.p = ctx.ws<double>(t.size() * es);
+  double* logd = ctx.ws<double>(1);
+  fill_zero(ctx, logd, sizeof(double));
+  Tape sub(r.cplx);
+  for (auto& e : ins) sub.mark_input(e.first, e.second);
+  ctx.tape = &sub;
+  try {
+    absorb_row(ctx, r.cplx, r.bnd, r.ket, r.bra, r.dir, r.o, r.sids, out2, logd);
+  } catch (...) {
+    ctx.tape = nullptr;
+    throw;
+  }
+  ctx.tape = nullptr;
+  for (size_t q = 0; q < r.out.size(); ++q) {
+    const double* g = main.grad_if_live(r.out[q].p);
+    if (g && sub.depends(out2[q].p))
+      HP_CHECK_HIP(hipMemcpyAsync(sub.grad(ctx, out2[q].p), g, out2[q].size() * es * sizeof(double),
+                                  hipMemcpyDeviceToDevice, ctx.stream));
+  }
+  sub.backward(ctx, broadening);
+  for (size_t i = 0; i < ins.size(); ++i) {
+    const double* g = sub.grad_if_live(ins[i].first);
+    if (g) axpy(ctx, gmain[i], g, 1.0, ins[i].second * es);
+  }
+}
+
 void contract_last_row(Ctx& ctx, bool cplx, const std::vector<BndView>& bnd,
                        const std::vector<SiteView>& ket, const std::vector<SiteView>& bra,
                        double* result_dev, double* log_dev, double** final_E) {
@@ -428,7 +507,7 @@ void boundary_pass(Ctx& ctx, const Lattice& ket, const Lattice& bra, Side side,
       for (auto v : shapes[q]) sz *= v;
       out[q].p = ctx.ws<double>(sz * es);
     }
-    absorb_row(ctx, cplx, bnd, kv, bv, dir, o, sids, out, log_dev);
+    absorb_row_recorded(ctx, cplx, bnd, kv, bv, dir, o, sids, out, log_dev);
     std::vector<DevTensor> env(ncol);
     for (int q = 0; q < ncol; ++q) env[dir == kL2R ? q : ncol - 1 - q] = out[q];
     envs.push_back(env);

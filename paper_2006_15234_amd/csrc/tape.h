@@ -16,7 +16,13 @@
 //   * einsumsvd:                zip_esvd_backward (forward recomputed from its
 //     recorded inputs: per-einsumsvd checkpoint and recompute);
 //   * exact carry:              carry_backward;
-//   * copy dst = src:           adj(src) += adj(dst).
+//   * copy dst = src:           adj(src) += adj(dst);
+//   * zip-up row (checkpoint):  the row ran unrecorded in the forward pass;
+//     the reverse walk reruns it from its recorded input boundary and sites
+//     on a tape of its own, seeds that tape with the adjoints of the row's
+//     outputs, walks it back and adds the adjoints of the row's inputs
+//     (per-row checkpoint and recompute: only the boundary MPS of each row
+//     is kept between the passes).
 // Only values that depend on an input marked with mark_input get adjoints.
 #pragma once
 #include <map>
@@ -25,10 +31,16 @@
 
 #include "esvd.h"
 
+#include <memory>
+
 namespace hp {
 
+struct RowCheckpoint;  // peps.h
+
 struct TapeOp {
-  enum Kind { GEMM, SCALE, ZIP, CARRY, COPY } kind = GEMM;
+  enum Kind { GEMM, SCALE, ZIP, CARRY, COPY, ROW } kind = GEMM;
+  // ROW
+  std::shared_ptr<const RowCheckpoint> row;
   bool cplx = false;
   // GEMM
   Prec prec = Prec::F64;
@@ -100,6 +112,8 @@ struct TapeSuspend {
 };
 
 bool taping(const Ctx& ctx);
+// reverse step of a checkpointed row (peps.hip): recompute, local tape, adjoints
+void row_backward(Ctx& ctx, const RowCheckpoint& r, Tape& main, double broadening);
 void tape_zip(Ctx& ctx, bool cplx, const ZipDims& z, const ZipLayout& L, const ZipOperands& op, int batch,
               const hpeps_esvd_opts& o, hpeps_absorb absorb, const ZipOut& out, void* U, void* R);
 void tape_carry(Ctx& ctx, bool cplx, const CarryDims& cd, const CarryLayout& cl, const void* Lm, const void* T,

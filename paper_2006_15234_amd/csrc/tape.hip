@@ -1,6 +1,7 @@
 // Reverse-mode tape (see tape.h).
 #include <algorithm>
 
+#include "peps.h"
 #include "tape.h"
 
 namespace hp {
@@ -103,6 +104,16 @@ void Tape::record(const TapeOp& op) {
         dep_.insert(r.R);
       }
       break;
+    case TapeOp::ROW: {
+      const RowCheckpoint& w = *r.row;
+      for (const auto& b : w.bnd) rd(b.p, b.extent);
+      for (const auto& t : w.ket) rd(t.p, t.extent);
+      for (const auto& t : w.bra) rd(t.p, t.extent);
+      for (const auto& o : w.out) note_write(o.p, o.size());
+      if (dep)
+        for (const auto& o : w.out) dep_.insert(o.p);
+      break;
+    }
     case TapeOp::CARRY: {
       rd(r.Lm, r.cl.nL * r.batch);
       rd(r.T, r.cl.nT * r.batch);
@@ -220,6 +231,9 @@ void Tape::backward(Ctx& ctx, double broadening) {
                           gV, gS, gT, gB);
         break;
       }
+      case TapeOp::ROW:
+        row_backward(ctx, *r.row, *this, broadening);
+        break;
       case TapeOp::CARRY: {
         const double* gVc = grad_if_live(r.V);
         if (!gVc) break;

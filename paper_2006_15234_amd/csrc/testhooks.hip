@@ -86,6 +86,12 @@ hpeps_status hpeps_test_strip_chunk_bytes(hpeps_ctx* ctx, int64_t bytes) {
   return HPEPS_OK;
 }
 
+hpeps_status hpeps_test_checkpoint_rows(hpeps_ctx* ctx, int32_t on) {
+  if (!ctx) return HPEPS_ERR_INVALID_ARG;
+  ctx->impl->checkpoint_rows = on != 0;
+  return HPEPS_OK;
+}
+
 hpeps_status hpeps_test_small_svd(hpeps_ctx* ctx, hpeps_dtype dtype, int64_t batch, int64_t k,
                                   const void* R, void* Z, double* sigma) {
   return guard_t(ctx, [&](hp::Ctx& c) {

@@ -157,3 +157,33 @@ def test_energy_gradient_8x8_d4_finite_differences(ctx, cplx):
             fd = fd + (vals[0] - vals[1]) / (2 * h) * part
         got = complex(g[i][j][idx].item())
         assert abs(fd - got) < 1e-6 * scale, (i, j, idx, fd, got)
+
+
+@pytest.mark.parametrize("kind", ["energy", "log_norm"])
+def test_row_checkpointing_matches_full_tape(kind):
+    """Per-row checkpointing of the boundary passes (only each row's input boundary is
+    kept; the row is rerun on its own tape in the reverse walk) gives the gradients of the
+    tape that records every intermediate, to 1e-12 of the largest entry (the adjoints of a
+    row's inputs are summed in another order), on the 8 x 8, D = 4 complex lattice of the
+    gradient workload, and needs less workspace."""
+    peps = synth.random_peps(8, 8, D=4, seed=0, complex_=True)
+    Hb = synth.heisenberg_bond_hamiltonian()
+    terms = [((s1, s2), Hb) for layer in synth.lattice_bonds(8, 8) for (s1, s2) in layer]
+    res = {}
+    for on in (1, 0):
+        c = hp.Context(0)
+        c.check(c.lib.hpeps_test_checkpoint_rows(c.h, on))
+        hp.workspace_peak(c, reset=True)
+        if kind == "energy":
+            v, g = hp.peps_energy_backward(c, dev_lattice(peps), terms, rank=16, oversample=8,
+                                           power_iters=1, seed=0)
+        else:
+            v, g = hp.peps_norm_backward(c, dev_lattice(peps), rank=16, oversample=8,
+                                         power_iters=1, seed=0)
+        res[on] = (v, [t.cpu().numpy() for row in g for t in row], hp.workspace_peak(c))
+    (v1, g1, peak1), (v0, g0, peak0) = res[1], res[0]
+    assert v1 == v0
+    scale = max(np.max(np.abs(x)) for x in g0)
+    for a, b in zip(g1, g0):
+        assert np.max(np.abs(a - b)) <= 1e-12 * scale
+    assert peak1 < peak0
