@@ -5,9 +5,15 @@
 
 namespace hp {
 
-// v + (v moved by the DPP control CTRL within the rows of ROW_MASK)
+// v + (v moved by the DPP control CTRL within the rows of ROW_MASK).  The add
+// is never contracted into an FMA with the product that made v: a lane would
+// then add its own unrounded product to its partner's rounded one, and the
+// butterfly sums would differ between lanes in the last bit.  Callers rely on
+// every lane of a row holding the same sum (rotation parameters computed in
+// each lane must agree).
 template <int CTRL, int ROW_MASK>
 __device__ __forceinline__ double dpp_add(double v) {
+#pragma clang fp contract(off)
   const long long x = __builtin_bit_cast(long long, v);
   const int lo = __builtin_amdgcn_update_dpp(0, (int)x, CTRL, ROW_MASK, 0xf, false);
   const int hi = __builtin_amdgcn_update_dpp(0, (int)(x >> 32), CTRL, ROW_MASK, 0xf, false);
