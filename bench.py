@@ -540,9 +540,9 @@ def main():
     dev = [torch.from_numpy(np.stack([t[j] for t in inst])).cuda() for j in range(4)]
     ctx = hp.Context(0)
 
-    def step(prec):
+    def step(prec, orth="cholqr"):
         return hp.einsumsvd_pair(ctx, *dev, rank=RANK, oversample=OVERS, power_iters=POW, seed=0,
-                                 stream_id=1, precision=prec, absorb=hp.ABSORB_NONE)
+                                 stream_id=1, precision=prec, absorb=hp.ABSORB_NONE, orth=orth)
 
     # the shipped choices cover this workload; anything new is tuned in the first warm-up step
     if not args.no_autotune and args.tune_cache and os.path.exists(args.tune_cache):
@@ -601,6 +601,17 @@ def main():
     s16 = out16[1].cpu().numpy()
     eps16 = float(np.max(np.abs(s16 - s64) / s64[:, :1]))
 
+    # the same FP64 step with the Gram-eigendecomposition orthogonalization (Alg. 5)
+    for _ in range(max(args.warmup, 1)):
+        step("f64", "eigh")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        oute = step("f64", "eigh")
+    torch.cuda.synchronize()
+    mse = (time.perf_counter() - t0) * 1e3 / args.steps
+    epse = float(np.max(np.abs(oute[1].cpu().numpy() - s64) / s64[:, :1]))
+
     roofline = dominant_roofline(dominant, prof, pair_alg_ratio(dominant))
     res = {
         "metric": "einsumsvd GFLOP/s & boundary-contraction sweep time vs plain FP64, same GPU, at fixed eps",
@@ -629,6 +640,8 @@ def main():
                        "ms_per_step": round(ms16, 4), "speedup_vs_f64": round(ms / ms16, 3),
                        "frac_of_bf16_peak": round(flops / (ms16 * 1e-3) / 1e12 / MFMA_BF16_PEAK_TFLOPS, 5),
                        "eps_sigma_vs_f64": eps16},
+        "orth_eigh": {"ms_per_step": round(mse, 4), "time_vs_cholqr": round(mse / ms, 3),
+                      "eps_sigma_vs_cholqr": epse},
         "autotune": not args.no_autotune,
         "kernel_classes": {n: class_entry(a, pair_alg_ratio(n))
                            for n, a in sorted(agg.items(), key=lambda x: -x[1]["ms"])},
@@ -646,7 +659,7 @@ def main():
     if args.c5 > 0:
         res["c5_gradient"] = c5_gradient(hp, args.c5)
     if args.d8 > 0:
-        del dev, out, out32, out16
+        del dev, out, out32, out16, oute
         res["variant_d8"] = d8_variant(hp, ctx, args.d8)
     if args.cpu_sample > 0:
         res["cpu_baseline"] = cpu_baseline(args.cpu_sample)

@@ -96,7 +96,20 @@ typedef struct hpeps_ctx hpeps_ctx;
  *                  mix the SplitMix64 output function (Steele, Lea & Flood,
  *                  OOPSLA 2014).  Instance b of a batch uses stream_id + b.
  *  jacobi_max_sweeps cap on the one-sided Jacobi sweeps of the small SVD
- *                  (0 selects the default, 40).                             */
+ *                  (0 selects the default, 40).
+ *  orth        how Alg. 4 orthogonalizes its panels.  HPEPS_ORTH_CHOLQR (0,
+ *              the default): CholeskyQR with a shifted first pass, a second
+ *              pass and a third one for flagged sketches, and a Householder
+ *              fallback for numerically rank-deficient ones.  HPEPS_ORTH_EIGH
+ *              (1): the reshape-avoiding orthogonalization of Alg. 5
+ *              (Sec. V-C) in the same pass structure: per pass the Gram matrix
+ *              G = Y^* Y, its eigendecomposition G = X Lambda X^* (from the
+ *              Cholesky factor G = C^* C and the one-sided Jacobi SVD of C^*,
+ *              accurate to eps kappa(Y)), and P = Y X Lambda^-1/2; the factor
+ *              of the final projection is R = P^* Y.  Forward calls only: the
+ *              adjoints differentiate the CholeskyQR path and reject 1.     */
+enum { HPEPS_ORTH_CHOLQR = 0, HPEPS_ORTH_EIGH = 1 };
+
 typedef struct {
   int64_t rank;
   int64_t oversample;
@@ -105,7 +118,7 @@ typedef struct {
   uint64_t seed;
   uint64_t stream_id;
   int32_t jacobi_max_sweeps;
-  int32_t reserved;
+  int32_t orth;           /* HPEPS_ORTH_CHOLQR (0) or HPEPS_ORTH_EIGH (1)     */
 } hpeps_esvd_opts;
 
 /* A strided dense tensor in device memory (the operands of hpeps_einsumsvd). */

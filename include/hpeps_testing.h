@@ -28,6 +28,13 @@ hpeps_status hpeps_test_gemm(hpeps_ctx* ctx, hpeps_dtype dtype, int64_t batch, i
 hpeps_status hpeps_test_orthogonalize(hpeps_ctx* ctx, hpeps_dtype dtype, int64_t batch, int64_t n,
                                       int64_t k, void* Y, void* P);
 
+/* Reshape-avoiding orthogonalization (Alg. 5: Gram matrix, its
+ * eigendecomposition, P = Y X Lambda^-1/2), in the two-pass form the
+ * einsumsvd runs with HPEPS_ORTH_EIGH (first pass shifted): Q [n,k] to P and
+ * R = Q^H Y [k,k] to R, Y [n,k] unchanged.  k <= 128, n >= k. */
+hpeps_status hpeps_test_orthogonalize_eigh(hpeps_ctx* ctx, hpeps_dtype dtype, int64_t batch, int64_t n,
+                                           int64_t k, const void* Y, void* P, void* R);
+
 /* Householder QR (the orthogonalization fallback for sketches flagged as
  * rank-deficient or very ill-conditioned; tall-skinny, one reduction level)
  * of every instance of Y [n,k] (unchanged): the orthonormal Q [n,k] to P and

@@ -31,6 +31,20 @@ def orthogonalize(Y):
     return np.linalg.qr(Y, mode="reduced")[0]
 
 
+def orthogonalize_gram_eigh(A):
+    """Reshape-avoiding orthogonalization (Alg. 5, Sec. V): the Gram matrix
+    G = A^* A, its eigendecomposition G = X Lambda X^*, R = Lambda^1/2 X^*,
+    P = R^-1 = X Lambda^-1/2 and Q = A P.  Returns (Q, R) with A = Q R and Q
+    an isometry (for full column rank A; it squares the condition number, so
+    Q's orthogonality degrades like eps kappa(A)^2)."""
+    G = A.conj().T @ A
+    lam, X = np.linalg.eigh(G)
+    lam = np.clip(lam, 0.0, None)
+    R = np.sqrt(lam)[:, None] * X.conj().T
+    P = X / np.sqrt(lam)[None, :]
+    return A @ P, R
+
+
 def randomized_svd(apply, apply_adj, n_rows, n_cols, m, q, omega):
     """Alg. 4 on an implicit operator A (n_rows x n_cols).
 

@@ -22,7 +22,7 @@ class HpepsError(RuntimeError):
 class EsvdOpts(C.Structure):
     _fields_ = [("rank", C.c_int64), ("oversample", C.c_int64), ("power_iters", C.c_int32),
                 ("sketch_precision", C.c_int32), ("seed", C.c_uint64), ("stream_id", C.c_uint64),
-                ("jacobi_max_sweeps", C.c_int32), ("reserved", C.c_int32)]
+                ("jacobi_max_sweeps", C.c_int32), ("orth", C.c_int32)]
 
 
 class EsvdInfo(C.Structure):
@@ -119,6 +119,7 @@ _SIGS = {
                                   C.c_int32, _P, _P, _P]),
     "hpeps_test_orthogonalize": (C.c_int, [_P, C.c_int, C.c_int64, C.c_int64, C.c_int64, _P, _P]),
     "hpeps_test_householder": (C.c_int, [_P, C.c_int, C.c_int64, C.c_int64, C.c_int64, _P, _P, _P]),
+    "hpeps_test_orthogonalize_eigh": (C.c_int, [_P, C.c_int, C.c_int64, C.c_int64, C.c_int64, _P, _P, _P]),
     "hpeps_test_strip_chunk_bytes": (C.c_int, [_P, C.c_int64]),
     "hpeps_test_checkpoint_rows": (C.c_int, [_P, C.c_int32]),
     "hpeps_test_small_svd": (C.c_int, [_P, C.c_int, C.c_int64, C.c_int64, _P, _P, _P]),

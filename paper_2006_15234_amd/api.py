@@ -29,11 +29,15 @@ def _dev(t, name):
     return C.c_void_p(t.data_ptr())
 
 
+_ORTH = {"cholqr": 0, "eigh": 1}
+
+
 def make_opts(rank, oversample=0, power_iters=0, precision="f64", seed=0, stream_id=0,
-              jacobi_max_sweeps=0):
+              jacobi_max_sweeps=0, orth="cholqr"):
+    """orth: "cholqr" (CholeskyQR2 + Householder fallback) or "eigh" (Alg. 5)."""
     return EsvdOpts(rank=int(rank), oversample=int(oversample), power_iters=int(power_iters),
                     sketch_precision=_PREC[precision], seed=int(seed), stream_id=int(stream_id),
-                    jacobi_max_sweeps=int(jacobi_max_sweeps), reserved=0)
+                    jacobi_max_sweeps=int(jacobi_max_sweeps), orth=_ORTH[orth])
 
 
 def _tensor_desc(t, conj, name):
@@ -64,7 +68,7 @@ def _network(subscripts, tensors, conj):
 
 
 def einsumsvd(ctx, subscripts, *tensors, conj=None, rank, oversample=0, power_iters=0, seed=0,
-              stream_id=0, absorb=ABSORB_NONE, log_scale=None, jacobi_max_sweeps=0):
+              stream_id=0, absorb=ABSORB_NONE, log_scale=None, jacobi_max_sweeps=0, orth="cholqr"):
     """einsumsvd of the network `subscripts` ("ab,bc->a|c": row legs left of '|', column
     legs right of it) over strided device tensors (conj[i]: operand i enters conjugated).
     Returns (U [row dims..., m'], sigma [m'], R [m', column dims...])."""
@@ -75,7 +79,7 @@ def einsumsvd(ctx, subscripts, *tensors, conj=None, rank, oversample=0, power_it
     if any(t.dtype != tensors[0].dtype for t in tensors):
         raise TypeError("operands must share one dtype")
     descs, ldims, rdims = _network(subscripts, tensors, conj)
-    o = make_opts(rank, oversample, power_iters, "f64", seed, stream_id, jacobi_max_sweeps)
+    o = make_opts(rank, oversample, power_iters, "f64", seed, stream_id, jacobi_max_sweeps, orth)
     rows, cols, mp = C.c_int64(), C.c_int64(), C.c_int64()
     ctx.check(ctx.lib.hpeps_einsumsvd_query(ctx.h, subscripts.encode(), len(tensors), descs, C.byref(o),
                                             C.byref(rows), C.byref(cols), C.byref(mp)))
@@ -92,7 +96,7 @@ def einsumsvd(ctx, subscripts, *tensors, conj=None, rank, oversample=0, power_it
 
 def einsumsvd_zipup(ctx, V, S, T, Bra=None, *, rank, oversample=0, power_iters=0, seed=0,
                     stream_id=0, precision="f64", absorb=ABSORB_CARRY, log_scale=None,
-                    jacobi_max_sweeps=0):
+                    jacobi_max_sweeps=0, orth="cholqr"):
     """Batched zip-up einsumsvd.  V [B,a,x,x,b,h,h], S [B,b,u,u,c], T/Bra [B,u,y,h,g,d].
     Returns (U [B,a,x,x,m'], sigma [B,m'], R [B,m',y,y,c,g,g])."""
     torch = _torch()
@@ -112,7 +116,7 @@ def einsumsvd_zipup(ctx, V, S, T, Bra=None, *, rank, oversample=0, power_iters=0
     sig = torch.empty((Bn, mp), dtype=torch.float64, device=V.device)
     R = torch.empty((Bn, mp, y, y, c, g, g), dtype=V.dtype, device=V.device)
     dims = (C.c_int64 * 9)(a, x, b, h, u, c, y, g, d)
-    o = make_opts(rank, oversample, power_iters, precision, seed, stream_id, jacobi_max_sweeps)
+    o = make_opts(rank, oversample, power_iters, precision, seed, stream_id, jacobi_max_sweeps, orth)
     ctx.sync_stream()
     ls = _dev(log_scale, "log_scale") if log_scale is not None else None
     ctx.check(ctx.lib.hpeps_einsumsvd_zipup(
@@ -123,7 +127,8 @@ def einsumsvd_zipup(ctx, V, S, T, Bra=None, *, rank, oversample=0, power_iters=0
 
 
 def einsumsvd_pair(ctx, Bl, Br, T1, T2, *, rank, oversample=0, power_iters=0, seed=0,
-                   stream_id=0, precision="f64", absorb=ABSORB_CARRY, jacobi_max_sweeps=0):
+                   stream_id=0, precision="f64", absorb=ABSORB_CARRY, jacobi_max_sweeps=0,
+                   orth="cholqr"):
     """Batched pair einsumsvd.  Bl, Br [B,m,D,D,m]; T1 [B,D,D,1,D,d]; T2 [B,D,D,D,1,d].
     Returns (U [B,m,D,D,m'], sigma [B,m'], R [B,m',D,D,m])."""
     torch = _torch()
@@ -140,7 +145,7 @@ def einsumsvd_pair(ctx, Bl, Br, T1, T2, *, rank, oversample=0, power_iters=0, se
     sig = torch.empty((Bn, mp), dtype=torch.float64, device=Bl.device)
     R = torch.empty((Bn, mp, D, D, m), dtype=Bl.dtype, device=Bl.device)
     dims = (C.c_int64 * 3)(m, D, d)
-    o = make_opts(rank, oversample, power_iters, precision, seed, stream_id, jacobi_max_sweeps)
+    o = make_opts(rank, oversample, power_iters, precision, seed, stream_id, jacobi_max_sweeps, orth)
     ctx.sync_stream()
     ctx.check(ctx.lib.hpeps_einsumsvd_pair(
         ctx.h, Bn, dt, dims, _dev(Bl, "Bl"), _dev(Br, "Br"), _dev(T1, "T1"), _dev(T2, "T2"),
@@ -316,13 +321,13 @@ def _peps_struct(sites, dtype_code, keep):
 
 
 def peps_norm(ctx, ket, bra=None, *, rank, oversample=0, power_iters=0, seed=0, precision="f64",
-              jacobi_max_sweeps=0):
+              jacobi_max_sweeps=0, orth="cholqr"):
     """<bra|ket> by boundary MPS.  Returns (log|v|, phase as complex)."""
     keep = []
     dt = _dtype_code(ket[0][0])
     pk = _peps_struct(ket, dt, keep)
     pb = _peps_struct(bra, dt, keep) if bra is not None else None
-    o = make_opts(rank, oversample, power_iters, precision, seed, 0, jacobi_max_sweeps)
+    o = make_opts(rank, oversample, power_iters, precision, seed, 0, jacobi_max_sweeps, orth)
     ln = C.c_double()
     ph = (C.c_double * 2)()
     ctx.sync_stream()

@@ -46,6 +46,7 @@ struct OrthWork {
   double* Rinv = nullptr;
   double* Racc = nullptr;
   int* flags = nullptr;
+  int mode = HPEPS_ORTH_CHOLQR;  // or HPEPS_ORTH_EIGH (Alg. 5)
 };
 
 // Output placement of the two factors: U[(a,x,X), i] at Urows + Ucol(i),

@@ -359,12 +359,81 @@ static void chain_rinv(Ctx& ctx, bool cplx, double* Rt, const double* Rinv, doub
                               ctx.stream));
 }
 
+// One pass of the reshape-avoiding orthogonalization (Alg. 5) on the Gram
+// matrix G = Y^H Y already in w.G: its eigendecomposition G = X Lambda X^*,
+// then P = Y X Lambda^-1/2.  The eigendecomposition is taken from the
+// Cholesky factor, G = C^H C (the CholeskyQR factor step of the same pass,
+// with its shift and flags), and the one-sided Jacobi SVD of
+// C^H = X Sigma W^*: X are G's eigenvectors and Lambda = Sigma^2, accurate to
+// eps kappa(C) = eps kappa(Y).  (A one-sided Jacobi on G itself works with
+// kappa(G)^2 = kappa(Y)^4: its vectors, and with them P's orthogonality,
+// would carry errors of order eps kappa(Y)^3.)  copy_flags: instances whose
+// flag is 0 get P = Y (the skipped third pass).
+static void eigh_pass(Ctx& ctx, bool cplx, const double* Y, double* P, int64_t n, int64_t k, int batch,
+                      const OrthWork& w, int pass, const int* copy_flags) {
+  WsScope scope(ctx);
+  const int es = cplx ? 2 : 1;
+  double* C = ctx.ws<double>((int64_t)batch * k * k * es);
+  double* X = ctx.ws<double>((int64_t)batch * k * k * es);
+  double* sig = ctx.ws<double>((int64_t)batch * k);
+  double* isig = ctx.ws<double>((int64_t)batch * k);
+  double* isig1 = ctx.ws<double>(batch);
+  int* sweeps = ctx.ws<int>(batch);
+  chol_inv(ctx, cplx, w.G, n, k, batch, pass, w.Rinv, C, w.flags, true);
+  jacobi_svd(ctx, cplx, C, k, batch, 40, X, sig, isig, isig1, nullptr, sweeps);
+  GemmDesc D;
+  D.M = n; D.K = k; D.N = k;
+  D.Am.add(n, k);
+  D.Ak.add(k, 1);
+  D.Bk.add(k, k);
+  D.Bn.add(k, 1);
+  D.Cm.add(n, k);
+  D.Cn.add(k, 1);
+  GemmCall c;
+  c.A = Y;
+  c.B = X;
+  c.C = P;
+  c.sA = c.sC = n * k;
+  c.sB = k * k;
+  c.batch = batch;
+  c.nscale = isig;
+  c.nscale_ld = k;
+  c.copy_if_zero = copy_flags;
+  gemm(ctx, cplx ? Prec::C128 : Prec::F64, D, c);
+  stats_reduce(ctx, nullptr, sweeps, batch, ctx.stats_dev);
+}
+
+// Alg. 5 in the pass structure of the CholeskyQR path: pass 1 (shifted when
+// ill-conditioned), pass 2, the Householder fallback for numerically
+// rank-deficient sketches (whose weak and null directions no Gram-based
+// factorization resolves), pass 3 for flagged instances.  Y is left intact;
+// Y2 is a scratch panel of Y's size.
+static void orthogonalize_eigh(Ctx& ctx, bool cplx, const double* Y, double* P, double* Y2, int64_t n, int64_t k,
+                               int batch, const OrthWork& w) {
+  HP_REQUIRE(!ctx.tape, HPEPS_ERR_UNSUPPORTED, "the Gram-eigendecomposition orthogonalization has no adjoint");
+  gram(ctx, cplx, Y, n, k, batch, w.G, nullptr);
+  eigh_pass(ctx, cplx, Y, P, n, k, batch, w, 1, nullptr);
+  gram(ctx, cplx, P, n, k, batch, w.G, nullptr);
+  eigh_pass(ctx, cplx, P, Y2, n, k, batch, w, 2, nullptr);
+  householder_qr(ctx, cplx, Y, n, k, batch, w.flags, FLAG_RANK_DEFICIENT, Y2, nullptr);
+  gram(ctx, cplx, Y2, n, k, batch, w.G, w.flags);
+  eigh_pass(ctx, cplx, Y2, P, n, k, batch, w, 3, w.flags);
+  stats_reduce(ctx, w.flags, nullptr, batch, ctx.stats_dev);
+}
+
 // Orthonormal basis of range(Y): result in P; Y is overwritten unless the
 // Householder fallback may run.  Rt_inv (optional, k x k per instance)
 // receives the inverse of the total factor R with Y = P R (the product of
 // the passes' inverses).
 void orthogonalize(Ctx& ctx, bool cplx, double* Y, double* P, int64_t n, int64_t k, int batch,
                    const OrthWork& w, double* Rt_inv) {
+  if (w.mode == HPEPS_ORTH_EIGH) {
+    HP_REQUIRE(!Rt_inv, HPEPS_ERR_UNSUPPORTED, "the Gram-eigendecomposition orthogonalization has no adjoint");
+    WsScope scope(ctx);
+    double* Y2 = ctx.ws<double>((int64_t)batch * n * k * (cplx ? 2 : 1));
+    orthogonalize_eigh(ctx, cplx, Y, P, Y2, n, k, batch, w);
+    return;
+  }
   WsScope scope(ctx);
   // (no fallback under a tape, recording or suspended: the reverse walk
   // differentiates, and a checkpointed row recomputes, the CholeskyQR path)
@@ -402,6 +471,29 @@ void orthogonalize(Ctx& ctx, bool cplx, double* Y, double* P, int64_t n, int64_t
 // R factor of the CholeskyQR of Y (accumulated over the passes) into Racc.
 void cholqr_r(Ctx& ctx, bool cplx, const double* Y, double* S1, double* S2, int64_t n,
                      int64_t k, int batch, const OrthWork& w) {
+  if (w.mode == HPEPS_ORTH_EIGH) {
+    // Y = Q R with Q = S2 and R = Q^H Y (exact to rounding once Q is
+    // orthonormal with range(Q) = range(Y))
+    orthogonalize_eigh(ctx, cplx, Y, S2, S1, n, k, batch, w);
+    GemmDesc D;
+    D.M = k; D.K = n; D.N = k;
+    D.Am.add(k, 1);
+    D.Ak.add(n, k);
+    D.Bk.add(n, k);
+    D.Bn.add(k, 1);
+    D.Cm.add(k, k);
+    D.Cn.add(k, 1);
+    GemmCall c;
+    c.A = S2;
+    c.B = Y;
+    c.C = w.Racc;
+    c.sA = c.sB = n * k;
+    c.sC = k * k;
+    c.batch = batch;
+    c.conjA = true;
+    gemm(ctx, cplx ? Prec::C128 : Prec::F64, D, c);
+    return;
+  }
   gram(ctx, cplx, Y, n, k, batch, w.G, nullptr);
   chol_inv(ctx, cplx, w.G, n, k, batch, 1, w.Rinv, w.Racc, w.flags);
   apply_rinv(ctx, cplx, Y, n, k, batch, w.Rinv, S1, nullptr);
@@ -442,6 +534,8 @@ void rsvd_finish(Ctx& ctx, bool cplx, int64_t rows, int64_t cols, int64_t k, int
   ow.Rinv = ctx.ws<double>(nb * k * k * es);
   ow.Racc = ctx.ws<double>(nb * k * k * es);
   ow.flags = ctx.ws<int>(nb);
+  HP_REQUIRE(o.orth == HPEPS_ORTH_CHOLQR || o.orth == HPEPS_ORTH_EIGH, HPEPS_ERR_INVALID_ARG, "unknown orth mode");
+  ow.mode = o.orth;
   double* Z = ctx.ws<double>(nb * k * k * es);
   double* sig = ctx.ws<double>(nb * k);
   double* isig = ctx.ws<double>(nb * k);

@@ -187,6 +187,7 @@ void zip_esvd_backward(Ctx& ctx, bool cplx, const ZipDims& z, const ZipLayout& L
   WsScope scope(ctx);
   HP_REQUIRE(broadening >= 0.0, HPEPS_ERR_INVALID_ARG, "broadening must be >= 0");
   HP_REQUIRE(o.sketch_precision == HPEPS_F64, HPEPS_ERR_DTYPE, "the adjoint runs in FP64 / complex128");
+  HP_REQUIRE(o.orth == HPEPS_ORTH_CHOLQR, HPEPS_ERR_UNSUPPORTED, "the adjoint differentiates the CholeskyQR path");
   HP_REQUIRE(absorb == HPEPS_ABSORB_NONE || absorb == HPEPS_ABSORB_RIGHT || absorb == HPEPS_ABSORB_CARRY,
              HPEPS_ERR_UNSUPPORTED, "the adjoint supports the NONE, RIGHT and CARRY absorb modes");
   const int64_t rows = z.rows(), cols = z.cols();

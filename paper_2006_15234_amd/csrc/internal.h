@@ -121,9 +121,10 @@ constexpr int FLAG_RANK_DEFICIENT = 16;  // pass 2's unshifted Cholesky broke do
 // CholeskyQR step on G (k x k, Hermitian): writes Rinv (k x k upper).  pass 1
 // may shift; flags[b] bit 1 is set when a third pass is needed, bit 2 on
 // non-finite values.  pass 3 is skipped (Rinv = I) unless bit 1 is set.
-// Racc (optional): pass 1 writes R, later passes Racc <- R Racc.
+// Racc (optional): pass 1 writes R, later passes Racc <- R Racc; with r_only
+// every pass writes its own R (the identity where pass 3 is skipped).
 void chol_inv(Ctx& ctx, bool cplx, const double* G, int64_t n_rows, int64_t k, int batch,
-              int pass, double* Rinv, double* Racc, int* flags);
+              int pass, double* Rinv, double* Racc, int* flags, bool r_only = false);
 // One-sided Jacobi SVD of K = Racc^H (k x k) per batch: writes Z (k x k,
 // left singular vectors of K in columns, sorted by descending sigma), sigma
 // (k), inv_sigma (k), inv_sigma1 (1); log_scale (optional) += log sigma_1;

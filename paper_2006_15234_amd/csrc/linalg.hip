@@ -114,7 +114,7 @@ size_t chol_lds_bytes(int k, bool cplx) { return (size_t)(k * k + 64) * (cplx ? 
 template <bool CPLX, bool TWO>
 __global__ __launch_bounds__(kCholThreads) void chol_inv_kernel(const double* Gall, long long n_rows,
                                                                  int k, int pass, double* Rinv_all,
-                                                                 double* Racc_all, int* flags) {
+                                                                 double* Racc_all, int* flags, int r_only) {
   using T = typename S<CPLX>::T;
   constexpr int kB = TWO ? 8 : 6;  // rows per wavefront and LDS round trip (k <= 49 or 113: one)
   extern __shared__ double smem[];
@@ -133,7 +133,9 @@ __global__ __launch_bounds__(kCholThreads) void chol_inv_kernel(const double* Ga
   auto write_identity = [&]() {
     for (int e = tid; e < kk; e += kCholThreads) {
       const int r = e / k;
-      Rinv[e] = (e - r * k == r) ? S<CPLX>::one() : S<CPLX>::zero();
+      const T v = (e - r * k == r) ? S<CPLX>::one() : S<CPLX>::zero();
+      Rinv[e] = v;
+      if (r_only && Racc) Racc[e] = v;
     }
   };
   if (pass == 3 && !(f & FLAG_THIRD_PASS)) {
@@ -257,9 +259,9 @@ __global__ __launch_bounds__(kCholThreads) void chol_inv_kernel(const double* Ga
     if (l < i) return S<CPLX>::zero();
     return l == i ? S<CPLX>::scale(S<CPLX>::one(), sq[i]) : S<CPLX>::scale(A[i * k + l], rs[i]);
   };
-  // Racc <- R (pass 1) or R * Racc (later passes; staged through Rinv)
+  // Racc <- R (pass 1, or r_only) or R * Racc (later passes; staged through Rinv)
   if (Racc) {
-    if (pass == 1) {
+    if (pass == 1 || r_only) {
       for (int e = tid; e < kk; e += kCholThreads) {
         const int i = e / k;
         Racc[e] = R_at(i, e - i * k);
@@ -917,14 +919,14 @@ void gram(Ctx& ctx, bool cplx, const void* Y, int64_t n, int64_t k, int batch, d
 }
 
 void chol_inv(Ctx& ctx, bool cplx, const double* G, int64_t n_rows, int64_t k, int batch, int pass,
-              double* Rinv, double* Racc, int* flags) {
+              double* Rinv, double* Racc, int* flags, bool r_only) {
   const size_t lds = chol_lds_bytes((int)k, cplx);
   HP_REQUIRE(k <= 128 && lds <= 160 * 1024 - 2048, HPEPS_ERR_UNSUPPORTED,
              "sketch width too large for the small factorizations (k <= 128, complex k <= 88)");
   const int rec = ctx.prof_begin("chol_inv");
   auto launch = [&](auto kern) {
     HP_CHECK_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    kern<<<batch, kCholThreads, lds, ctx.stream>>>(G, n_rows, (int)k, pass, Rinv, Racc, flags);
+    kern<<<batch, kCholThreads, lds, ctx.stream>>>(G, n_rows, (int)k, pass, Rinv, Racc, flags, r_only ? 1 : 0);
   };
   if (cplx)
     k > 64 ? launch(chol_inv_kernel<true, true>) : launch(chol_inv_kernel<true, false>);

@@ -70,6 +70,24 @@ hpeps_status hpeps_test_orthogonalize(hpeps_ctx* ctx, hpeps_dtype dtype, int64_t
   });
 }
 
+hpeps_status hpeps_test_orthogonalize_eigh(hpeps_ctx* ctx, hpeps_dtype dtype, int64_t batch, int64_t n,
+                                           int64_t k, const void* Y, void* P, void* R) {
+  return guard_t(ctx, [&](hp::Ctx& c) {
+    const bool cplx = cplx_of(dtype);
+    HP_REQUIRE(Y && P && R && batch >= 1 && n >= k && k >= 1 && k <= 128, HPEPS_ERR_INVALID_ARG,
+               "bad orthogonalize arguments");
+    const int es = cplx ? 2 : 1;
+    hp::OrthWork w;
+    w.G = c.ws<double>(batch * k * k * es);
+    w.Rinv = c.ws<double>(batch * k * k * es);
+    w.Racc = (double*)R;
+    w.flags = c.ws<int>(batch);
+    w.mode = HPEPS_ORTH_EIGH;
+    double* S1 = c.ws<double>(batch * n * k * es);
+    hp::cholqr_r(c, cplx, (const double*)Y, S1, (double*)P, n, k, (int)batch, w);
+  });
+}
+
 hpeps_status hpeps_test_householder(hpeps_ctx* ctx, hpeps_dtype dtype, int64_t batch, int64_t n, int64_t k,
                                     const void* Y, void* P, void* R) {
   return guard_t(ctx, [&](hp::Ctx& c) {

@@ -6,6 +6,7 @@ import ctypes as C
 import numpy as np
 import pytest
 
+from oracle import rsvd
 from oracle.network import zipup_operator
 
 torch = pytest.importorskip("torch")
@@ -167,6 +168,72 @@ def test_orthogonalize(ctx, cplx, nk):
         assert np.max(np.abs(P[b] @ (P[b].conj().T @ Q) - Q)) < 1e-12
 
 
+def _orth_eigh(ctx, Y, cplx):
+    B, n, k = Y.shape
+    dY = _dev(Y)
+    dP = torch.zeros_like(dY)
+    dR = torch.zeros((B, k, k), dtype=dY.dtype, device=dY.device)
+    ctx.sync_stream()
+    ctx.check(ctx.lib.hpeps_test_orthogonalize_eigh(ctx.h, hp.C128 if cplx else hp.F64, B, n, k,
+                                                    _p(dY), _p(dP), _p(dR)))
+    assert np.array_equal(dY.cpu().numpy(), Y)  # input left intact
+    return dP.cpu().numpy(), dR.cpu().numpy()
+
+
+@pytest.mark.parametrize("cplx", [False, True])
+@pytest.mark.parametrize("nk", [(8, 8), (100, 7), (1296, 44), (5000, 108), (300, 128)])
+def test_orthogonalize_eigh(ctx, cplx, nk):
+    """Alg. 5 (two passes, first shifted) against the oracle's single pass on
+    well-conditioned panels: same range (equal projectors), Q^H Q = I,
+    Q R = Y and R^H R = Y^H Y."""
+    n, k = nk
+    if cplx and k > 88:
+        pytest.skip("complex small factorizations are limited to k <= 88")
+    rng = np.random.default_rng(3 * n + k)
+    B = 2
+    Y = _rand(rng, (B, n, k), cplx)
+    P, R = _orth_eigh(ctx, Y, cplx)
+    for b in range(B):
+        Qo, Ro = rsvd.orthogonalize_gram_eigh(Y[b])
+        nrm = np.max(np.abs(Y[b]))
+        assert np.max(np.abs(P[b].conj().T @ P[b] - np.eye(k))) < 1e-13
+        assert np.max(np.abs(P[b] @ P[b].conj().T - Qo @ Qo.conj().T)) < 1e-12
+        assert np.max(np.abs(P[b] @ R[b] - Y[b])) < 1e-13 * k * nrm
+        G = Ro.conj().T @ Ro
+        assert np.max(np.abs(R[b].conj().T @ R[b] - G)) < 1e-12 * np.max(np.abs(G))
+
+
+def test_orthogonalize_eigh_ill_conditioned(ctx):
+    """kappa(Y) = 1e6 (kappa(G) = 1e12): one unshifted pass of Alg. 5 leaves Q
+    far from orthonormal (the oracle's single pass shows it); the shifted
+    second pass restores orthonormality and Q R = Y."""
+    rng = np.random.default_rng(4)
+    n, k = 2000, 40
+    U = np.linalg.qr(rng.standard_normal((n, k)))[0]
+    V = np.linalg.qr(rng.standard_normal((k, k)))[0]
+    Y = (U * np.logspace(0, -6, k)) @ V.T
+    Qo, _ = rsvd.orthogonalize_gram_eigh(Y)
+    assert np.max(np.abs(Qo.T @ Qo - np.eye(k))) > 1e-8
+    P, R = _orth_eigh(ctx, Y[None], False)
+    assert np.max(np.abs(P[0].T @ P[0] - np.eye(k))) < 1e-12
+    assert np.max(np.abs(P[0] @ R[0] - Y)) < 1e-13
+    assert np.max(np.abs(P[0] @ (P[0].T @ U) - U)) < 1e-9
+
+
+@pytest.mark.parametrize("cplx", [False, True])
+def test_orthogonalize_eigh_rank_deficient(ctx, cplx):
+    """Exact rank 9 in a 13-column panel: the Gram-based passes cannot
+    resolve the null directions, the Householder fallback replaces the panel;
+    Q is still orthonormal with Q R = Y."""
+    rng = np.random.default_rng(6)
+    n, k, r = 500, 13, 9
+    Y = (_rand(rng, (n, r), cplx) @ _rand(rng, (r, k), cplx))[None]
+    P, R = _orth_eigh(ctx, Y, cplx)
+    assert hp.get_info(ctx)["orth_householder"] >= 1
+    assert np.max(np.abs(P[0].conj().T @ P[0] - np.eye(k))) < 1e-13
+    assert np.max(np.abs(P[0] @ R[0] - Y[0])) < 1e-13 * np.max(np.abs(Y))
+
+
 def test_orthogonalize_ill_conditioned(ctx):
     """kappa ~ 1e12: the shifted first pass plus a third pass still orthonormalize."""
     rng = np.random.default_rng(0)
@@ -210,6 +277,32 @@ def test_small_svd(ctx, cplx, k):
         # Z spans the left singular subspaces: Z^H K K^H Z = diag(s^2)
         M = Z[b].conj().T @ K @ K.conj().T @ Z[b]
         assert np.max(np.abs(M - np.diag(s[b] ** 2))) < 1e-12 * ref[0] ** 2 * k
+
+
+@pytest.mark.parametrize("cplx", [False, True])
+@pytest.mark.parametrize("k", [16, 44, 108])
+def test_small_svd_near_identity(ctx, cplx, k):
+    """R = I + rounding-level noise (the factor of an already orthonormal
+    panel): every rotation is decided at the noise level, so the lanes that
+    share a column pair must agree bit for bit on the pair's inner products.
+    The singular values stay within a few eps of 1."""
+    if cplx and k > 88:
+        pytest.skip("complex small factorizations are limited to k <= 88")
+    rng = np.random.default_rng(100 + k)
+    B = 4
+    R = np.triu(_rand(rng, (B, k, k), cplx)) * 1e-15 + np.eye(k)
+    dR = _dev(R)
+    dZ = torch.zeros_like(dR)
+    ds = torch.zeros((B, k), dtype=torch.float64, device="cuda")
+    ctx.sync_stream()
+    ctx.check(ctx.lib.hpeps_test_small_svd(ctx.h, hp.C128 if cplx else hp.F64, B, k, _p(dR), _p(dZ),
+                                           _p(ds)))
+    Z, s = dZ.cpu().numpy(), ds.cpu().numpy()
+    for b in range(B):
+        K = R[b].conj().T
+        assert np.max(np.abs(s[b] - np.linalg.svd(K, compute_uv=False))) < 1e-13
+        M = Z[b].conj().T @ K @ K.conj().T @ Z[b]
+        assert np.max(np.abs(M - np.diag(s[b] ** 2))) < 1e-13
 
 
 @pytest.mark.parametrize("cplx", [False, True])

@@ -154,6 +154,50 @@ def test_rsvd_basis_invariance(monkeypatch):
     assert np.allclose((U0 * s0) @ V0, (U1 * s1) @ V1, atol=1e-11 * s0[0])
 
 
+@pytest.mark.parametrize("complex_", [False, True])
+def test_gram_eigh_orthogonalization(complex_):
+    """Alg. 5 against what it must produce: Q an isometry, A = Q R, R^* R the
+    Gram matrix, range(Q) = range(A) (same projector as a Householder QR)."""
+    rng = np.random.default_rng(11)
+    A = rng.standard_normal((300, 12))
+    if complex_:
+        A = A + 1j * rng.standard_normal((300, 12))
+    Q, R = rsvd.orthogonalize_gram_eigh(A)
+    assert np.max(np.abs(Q.conj().T @ Q - np.eye(12))) < 1e-13
+    assert np.max(np.abs(Q @ R - A)) < 1e-13 * np.max(np.abs(A))
+    assert np.max(np.abs(R.conj().T @ R - A.conj().T @ A)) < 1e-12 * np.linalg.norm(A, 2) ** 2
+    Qh = np.linalg.qr(A)[0]
+    assert np.max(np.abs(Q @ Q.conj().T - Qh @ Qh.conj().T)) < 1e-13
+
+
+def test_gram_eigh_orthogonal_columns():
+    """Special case: A with mutually orthogonal columns of distinct norms.  G
+    is diagonal, so Q is A with its columns normalized (up to a sign per
+    column) and R holds the norms."""
+    rng = np.random.default_rng(2)
+    Qh = np.linalg.qr(rng.standard_normal((40, 5)))[0]
+    norms = np.array([5.0, 0.5, 3.0, 2.0, 1.0])
+    A = Qh * norms
+    Q, R = rsvd.orthogonalize_gram_eigh(A)
+    order = np.argsort(norms)  # eigh sorts ascending
+    for j, c in enumerate(order):
+        assert abs(abs(Q[:, j] @ Qh[:, c]) - 1.0) < 1e-13
+        assert abs(np.linalg.norm(R[j]) - norms[c]) < 1e-13 * norms.max()
+
+
+def test_rsvd_gram_eigh_equals_householder(monkeypatch):
+    """Alg. 4 with Alg. 5 as its orthogonalization gives the same truncated SVD
+    as with Householder QR (the result depends on the ranges only)."""
+    rng = np.random.default_rng(7)
+    op = zipup_operator(*_zip_inputs(rng, 3, 2, 3, 2, 2, 3, 2, 2, 2, True))
+    om = sketch(4, 1, op.n_cols, 10)
+    U0, s0, V0 = rsvd.randomized_svd(op.apply, op.apply_adj, op.n_rows, op.n_cols, 6, 1, om)
+    monkeypatch.setattr(rsvd, "orthogonalize", lambda Y: rsvd.orthogonalize_gram_eigh(Y)[0])
+    U1, s1, V1 = rsvd.randomized_svd(op.apply, op.apply_adj, op.n_rows, op.n_cols, 6, 1, om)
+    assert np.allclose(s0, s1, rtol=1e-10)
+    assert np.allclose((U0 * s0) @ V0, (U1 * s1) @ V1, atol=1e-10 * s0[0])
+
+
 def test_rsvd_near_optimal_on_pair_network():
     """Halko-type bound: with oversampling and power iterations the error is
     close to the optimal rank-m error (soft check, reported ratio <= 1.5)."""
