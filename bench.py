@@ -415,6 +415,47 @@ def amplitudes(hp, args, count, n=16, D=8, m=56, p=8, q=1):
             "ms_single_amplitude": round(single * 1e3, 2)}, ctx
 
 
+def bmps_vs_ibmps(hp, batch, n=8, bonds=(2, 3, 4, 5, 6, 8, 10, 11), p=4, q=1, reps=3):
+    """The contraction benchmark of Fig. 8a / Table II on one GPU: an n x n
+    one-layer network (a PEPS with every physical leg fixed, nonnegative random
+    sites of bond D) contracted with boundary bond m = D, by BMPS (every einsumsvd
+    on the explicit matrix with a dense truncated SVD) and by IBMPS (the
+    randomized SVD on the implicit operator, oversample p, q power iterations),
+    for a batch of basis states per call.  D stops at 11: the dense SVD takes
+    min(rows, cols) = m D <= 128.  Reports the time per amplitude of each and the
+    difference of their log-amplitudes."""
+    import numpy as np
+    import torch
+
+    import synth
+    ctx = hp.Context(0)
+    rng = np.random.default_rng(0)
+    states = [[int(v) for v in rng.integers(0, 2, n * n)] for _ in range(batch)]
+    out = []
+    for D in bonds:
+        ket = [[np.abs(t) for t in row] for row in synth.random_peps(n, n, D, seed=D)]
+        dev = [[torch.from_numpy(np.ascontiguousarray(t)).cuda() for t in row] for row in ket]
+        row = {"D": D, "m": D}
+        res = {}
+        for method in ("explicit", "implicit"):
+            kw = dict(rank=D, method=method) if method == "explicit" else dict(rank=D, oversample=p, power_iters=q)
+            hp.peps_amplitudes(ctx, dev, states, **kw)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                la, _ = hp.peps_amplitudes(ctx, dev, states, **kw)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / reps
+            row[("bmps" if method == "explicit" else "ibmps") + "_ms_per_amplitude"] = round(dt * 1e3 / batch, 4)
+            res[method] = np.asarray(la)
+        row["ibmps_speedup"] = round(row["bmps_ms_per_amplitude"] / row["ibmps_ms_per_amplitude"], 3)
+        row["max_dlog_ibmps_vs_bmps"] = float(np.max(np.abs(res["explicit"] - res["implicit"])))
+        out.append(row)
+        del dev
+    return {"workload": f"{n}x{n} one-layer PEPS (every physical leg fixed, nonnegative sites), m = D, "
+                        f"IBMPS p={p} q={q}, {batch} amplitudes per call", "by_bond": out}
+
+
 def c4_ite(hp, sweeps, n=16, D=8, d=2, tau=0.01, J=1.0, hfield=3.0, m=32, p=8, q=1, plain_sweeps=5):
     """Batched imaginary-time evolution of an n x n transverse-field Ising PEPS: TEBD sweeps
     of QR-SVD updates over the four layers of non-overlapping bonds (bond dimensions grow
@@ -492,6 +533,11 @@ def main():
                     help="basis states per batched call in the one-layer amplitude block (0 disables it)")
     ap.add_argument("--amp-only", type=int, default=0, metavar="COUNT",
                     help="run only the amplitude block with COUNT basis states per call and print its JSON")
+    ap.add_argument("--bmps", type=int, default=32, metavar="BATCH",
+                    help="BMPS vs IBMPS over the bond on the 8x8 one-layer network, BATCH amplitudes per "
+                         "call (0 skips)")
+    ap.add_argument("--bmps-only", type=int, default=0, metavar="BATCH",
+                    help="run only the BMPS vs IBMPS block and print its JSON")
     ap.add_argument("--c5", type=int, default=2, metavar="REPS",
                     help="time the 8x8 D=4 complex energy gradient this many times (0 skips)")
     ap.add_argument("--c3", action="store_true",
@@ -521,6 +567,10 @@ def main():
 
     import paper_2006_15234_amd as hp
     import synth
+
+    if args.bmps_only > 0:
+        print(json.dumps(bmps_vs_ibmps(hp, args.bmps_only)))
+        return
 
     if args.amp_only > 0:
         out, actx = amplitudes(hp, args, args.amp_only)
@@ -656,6 +706,8 @@ def main():
     if args.amp > 0:
         res["amplitude"], actx = amplitudes(hp, args, args.amp)
         hp.autotune_import(ctx, hp.autotune_export(actx))   # its tuned products join the saved set
+    if args.bmps > 0:
+        res["bmps_vs_ibmps"] = bmps_vs_ibmps(hp, args.bmps)
     if args.c5 > 0:
         res["c5_gradient"] = c5_gradient(hp, args.c5)
     if args.d8 > 0:

@@ -107,8 +107,20 @@ typedef struct hpeps_ctx hpeps_ctx;
  *              Cholesky factor G = C^* C and the one-sided Jacobi SVD of C^*,
  *              accurate to eps kappa(Y)), and P = Y X Lambda^-1/2; the factor
  *              of the final projection is R = P^* Y.  Forward calls only: the
- *              adjoints differentiate the CholeskyQR path and reject 1.     */
+ *              adjoints differentiate the CholeskyQR path and reject 1.
+ *  method      HPEPS_ESVD_IMPLICIT (0, the default): the randomized SVD of
+ *              Alg. 4 on the implicit operator (IBMPS).  HPEPS_ESVD_EXPLICIT
+ *              (1): the network is contracted into its matrix and factored by
+ *              a dense truncated SVD (BMPS, Sec. III-B; Table II): the range
+ *              basis is exact (the identity when rows <= cols, else the
+ *              orthogonalized matrix), then the QR of the projection and the
+ *              one-sided Jacobi SVD of its R factor.  oversample,
+ *              power_iters, seed and stream_id are then unused;
+ *              min(rows, cols) <= 128 (88 complex); FP64 / complex128 only;
+ *              forward calls only.  Supported by hpeps_einsumsvd and the
+ *              amplitude calls; the others reject it.                       */
 enum { HPEPS_ORTH_CHOLQR = 0, HPEPS_ORTH_EIGH = 1 };
+enum { HPEPS_ESVD_IMPLICIT = 0, HPEPS_ESVD_EXPLICIT = 1 };
 
 typedef struct {
   int64_t rank;
@@ -119,6 +131,8 @@ typedef struct {
   uint64_t stream_id;
   int32_t jacobi_max_sweeps;
   int32_t orth;           /* HPEPS_ORTH_CHOLQR (0) or HPEPS_ORTH_EIGH (1)     */
+  int32_t method;         /* HPEPS_ESVD_IMPLICIT (0) or HPEPS_ESVD_EXPLICIT (1) */
+  int32_t reserved;       /* must be 0                                        */
 } hpeps_esvd_opts;
 
 /* A strided dense tensor in device memory (the operands of hpeps_einsumsvd). */

@@ -18,7 +18,9 @@ zip-up ApproxApply of Alg. 3):
   in rsvd.fix_gauge) of the implicit matrix with rows (a, x) and columns
   (y, c, g) of the network C[a,x,b,h] S[b,u,c] A[u,y,h,g]: U becomes the
   finished boundary tensor [a, x, m'] and (Sigma / sigma_1) V^* the next carry
-  [m', y, c, g];
+  [m', y, c, g].  With explicit=True (BMPS, Sec. III-B) the matrix is formed
+  and its truncated SVD taken by definition (rsvd.truncated_svd), with the
+  same canonical phase;
 * row n is contracted exactly, column by column, normalising the running
   vector.
 
@@ -32,7 +34,7 @@ rescaled first (the rescalings above keep every intermediate in range).
 """
 import numpy as np
 
-from .rsvd import randomized_svd, sketch_width
+from .rsvd import fix_gauge, randomized_svd, sketch_width, truncated_svd
 from .sketch import sketch, stream_id
 
 L2R, R2L = 0, 1
@@ -64,7 +66,7 @@ def first_row(row):
     return out, log_scale
 
 
-def zipup_l2r(bnd, row, m, p, q, seed, sids):
+def zipup_l2r(bnd, row, m, p, q, seed, sids, explicit=False):
     """Alg. 3 left to right on the one-layer network.  Returns (new boundary,
     log scale added); the boundary legs [a, x, b] are [left, down, right]."""
     n = len(row)
@@ -89,9 +91,13 @@ def zipup_l2r(bnd, row, m, p, q, seed, sids):
             return np.einsum("axbh,buc,uyhg,axk->ycgk", C.conj(), S.conj(), A.conj(), Y,
                              optimize=True).reshape(cols, -1)
 
-        k = sketch_width(m, p, rows, cols)
-        omega = sketch(seed, sids[j], cols, k)
-        U, s, Vh = randomized_svd(apply, apply_adj, rows, cols, m, q, omega)
+        if explicit:
+            M = np.einsum("axbh,buc,uyhg->axycg", C, S, A, optimize=True).reshape(rows, cols)
+            U, s, Vh = fix_gauge(*truncated_svd(M, m))
+        else:
+            k = sketch_width(m, p, rows, cols)
+            omega = sketch(seed, sids[j], cols, k)
+            U, s, Vh = randomized_svd(apply, apply_adj, rows, cols, m, q, omega)
         mp = s.shape[0]
         out.append(U.reshape(a, x, mp))
         C = ((s / s[0])[:, None] * Vh).reshape(mp, y, c, g)
@@ -101,13 +107,13 @@ def zipup_l2r(bnd, row, m, p, q, seed, sids):
     return out, log_scale
 
 
-def absorb_row(bnd, row, direction, m, p, q, seed, sids):
+def absorb_row(bnd, row, direction, m, p, q, seed, sids, explicit=False):
     """One zip-up in the given direction; sids[j] is the sketch stream of the
     einsumsvd that absorbs lattice column j."""
     if direction == L2R:
-        return zipup_l2r(bnd, row, m, p, q, seed, sids)
+        return zipup_l2r(bnd, row, m, p, q, seed, sids, explicit)
     out, ls = zipup_l2r([_mirror_bnd(S) for S in reversed(bnd)], [_mirror_site(A) for A in reversed(row)],
-                        m, p, q, seed, list(reversed(sids)))
+                        m, p, q, seed, list(reversed(sids)), explicit)
     return [_mirror_bnd(S) for S in reversed(out)], ls
 
 
@@ -123,9 +129,10 @@ def last_row(bnd, row):
     return E.reshape(()), log_scale
 
 
-def amplitude(ket, bits, m, p, q, seed):
-    """<bits|psi> by the one-layer boundary MPS.  Returns (log_abs, phase) with
-    <bits|psi> = phase * exp(log_abs); (-inf, 0) for an exactly zero slice."""
+def amplitude(ket, bits, m, p, q, seed, explicit=False):
+    """<bits|psi> by the one-layer boundary MPS (IBMPS, or BMPS with
+    explicit=True, where p, q and seed are unused).  Returns (log_abs, phase)
+    with <bits|psi> = phase * exp(log_abs); (-inf, 0) for an exactly zero slice."""
     layer = sliced_layer(ket, bits)
     if any(not np.any(A) for row in layer for A in row):
         return -np.inf, 0.0
@@ -137,7 +144,7 @@ def amplitude(ket, bits, m, p, q, seed):
         for t in range(1, nrow - 1):
             direction = L2R if t % 2 == 1 else R2L
             sids = [stream_id(0, nrow, ncol, t, j) for j in range(ncol)]
-            bnd, ls = absorb_row(bnd, layer[t], direction, m, p, q, seed, sids)
+            bnd, ls = absorb_row(bnd, layer[t], direction, m, p, q, seed, sids, explicit)
             log_scale += ls
     v, ls = last_row(bnd, layer[nrow - 1])
     return log_scale + ls + np.log(abs(v)), v / abs(v)

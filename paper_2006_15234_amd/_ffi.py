@@ -22,7 +22,7 @@ class HpepsError(RuntimeError):
 class EsvdOpts(C.Structure):
     _fields_ = [("rank", C.c_int64), ("oversample", C.c_int64), ("power_iters", C.c_int32),
                 ("sketch_precision", C.c_int32), ("seed", C.c_uint64), ("stream_id", C.c_uint64),
-                ("jacobi_max_sweeps", C.c_int32), ("orth", C.c_int32)]
+                ("jacobi_max_sweeps", C.c_int32), ("orth", C.c_int32), ("method", C.c_int32), ("reserved", C.c_int32)]
 
 
 class EsvdInfo(C.Structure):

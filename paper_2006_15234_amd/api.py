@@ -30,14 +30,17 @@ def _dev(t, name):
 
 
 _ORTH = {"cholqr": 0, "eigh": 1}
+_METHOD = {"implicit": 0, "explicit": 1}
 
 
 def make_opts(rank, oversample=0, power_iters=0, precision="f64", seed=0, stream_id=0,
-              jacobi_max_sweeps=0, orth="cholqr"):
-    """orth: "cholqr" (CholeskyQR2 + Householder fallback) or "eigh" (Alg. 5)."""
+              jacobi_max_sweeps=0, orth="cholqr", method="implicit"):
+    """orth: "cholqr" (CholeskyQR2 + Householder fallback) or "eigh" (Alg. 5);
+    method: "implicit" (randomized SVD, IBMPS) or "explicit" (dense SVD, BMPS)."""
     return EsvdOpts(rank=int(rank), oversample=int(oversample), power_iters=int(power_iters),
                     sketch_precision=_PREC[precision], seed=int(seed), stream_id=int(stream_id),
-                    jacobi_max_sweeps=int(jacobi_max_sweeps), orth=_ORTH[orth])
+                    jacobi_max_sweeps=int(jacobi_max_sweeps), orth=_ORTH[orth], method=_METHOD[method],
+                    reserved=0)
 
 
 def _tensor_desc(t, conj, name):
@@ -68,7 +71,8 @@ def _network(subscripts, tensors, conj):
 
 
 def einsumsvd(ctx, subscripts, *tensors, conj=None, rank, oversample=0, power_iters=0, seed=0,
-              stream_id=0, absorb=ABSORB_NONE, log_scale=None, jacobi_max_sweeps=0, orth="cholqr"):
+              stream_id=0, absorb=ABSORB_NONE, log_scale=None, jacobi_max_sweeps=0, orth="cholqr",
+              method="implicit"):
     """einsumsvd of the network `subscripts` ("ab,bc->a|c": row legs left of '|', column
     legs right of it) over strided device tensors (conj[i]: operand i enters conjugated).
     Returns (U [row dims..., m'], sigma [m'], R [m', column dims...])."""
@@ -79,7 +83,7 @@ def einsumsvd(ctx, subscripts, *tensors, conj=None, rank, oversample=0, power_it
     if any(t.dtype != tensors[0].dtype for t in tensors):
         raise TypeError("operands must share one dtype")
     descs, ldims, rdims = _network(subscripts, tensors, conj)
-    o = make_opts(rank, oversample, power_iters, "f64", seed, stream_id, jacobi_max_sweeps, orth)
+    o = make_opts(rank, oversample, power_iters, "f64", seed, stream_id, jacobi_max_sweeps, orth, method)
     rows, cols, mp = C.c_int64(), C.c_int64(), C.c_int64()
     ctx.check(ctx.lib.hpeps_einsumsvd_query(ctx.h, subscripts.encode(), len(tensors), descs, C.byref(o),
                                             C.byref(rows), C.byref(cols), C.byref(mp)))
@@ -336,7 +340,8 @@ def peps_norm(ctx, ket, bra=None, *, rank, oversample=0, power_iters=0, seed=0, 
     return ln.value, complex(ph[0], ph[1])
 
 
-def peps_amplitude(ctx, ket, bits, *, rank, oversample=0, power_iters=0, seed=0, jacobi_max_sweeps=0):
+def peps_amplitude(ctx, ket, bits, *, rank, oversample=0, power_iters=0, seed=0, jacobi_max_sweeps=0,
+                   method="implicit"):
     """<bits|psi> by the one-layer boundary MPS (bits: one int per site, row-major).
     Returns (log|a|, phase as complex); (-inf, 0) for an exactly zero slice."""
     keep = []
@@ -346,7 +351,7 @@ def peps_amplitude(ctx, ket, bits, *, rank, oversample=0, power_iters=0, seed=0,
     if len(bits) != nsites:
         raise ValueError("bits needs one entry per site")
     b = (C.c_int32 * nsites)(*[int(v) for v in bits])
-    o = make_opts(rank, oversample, power_iters, "f64", seed, 0, jacobi_max_sweeps)
+    o = make_opts(rank, oversample, power_iters, "f64", seed, 0, jacobi_max_sweeps, method=method)
     la = C.c_double()
     ph = (C.c_double * 2)()
     ctx.sync_stream()
@@ -354,7 +359,8 @@ def peps_amplitude(ctx, ket, bits, *, rank, oversample=0, power_iters=0, seed=0,
     return la.value, complex(ph[0], ph[1])
 
 
-def peps_amplitudes(ctx, ket, states, *, rank, oversample=0, power_iters=0, seed=0, jacobi_max_sweeps=0):
+def peps_amplitudes(ctx, ket, states, *, rank, oversample=0, power_iters=0, seed=0, jacobi_max_sweeps=0,
+                    method="implicit"):
     """<bits|psi> for a batch of basis states (``states``: sequences of one int per
     site, row-major), computed in lockstep.  Returns (log|a| list, phase list)."""
     keep = []
@@ -366,7 +372,7 @@ def peps_amplitudes(ctx, ket, states, *, rank, oversample=0, power_iters=0, seed
     if n < 1 or len(flat) != n * nsites:
         raise ValueError("states needs one entry per site for every state")
     b = (C.c_int32 * len(flat))(*flat)
-    o = make_opts(rank, oversample, power_iters, "f64", seed, 0, jacobi_max_sweeps)
+    o = make_opts(rank, oversample, power_iters, "f64", seed, 0, jacobi_max_sweeps, method=method)
     la = (C.c_double * n)()
     ph = (C.c_double * (2 * n))()
     ctx.sync_stream()

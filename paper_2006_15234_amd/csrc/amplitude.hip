@@ -127,7 +127,8 @@ void absorb_row(Ctx& ctx, bool cplx, int nb, const std::vector<Bnd>& bnd, const 
     HP_REQUIRE(S.n[0] == b && A.n[2] == h && S.n[1] == A.n[0], HPEPS_ERR_SHAPE, "row and boundary legs do not chain");
     const int64_t u = A.n[0], y = A.n[1], c = S.n[2], g = A.n[3];
     const int64_t rows = a * x, cols = y * c * g;
-    const int64_t k = sketch_width(o.rank, o.oversample, rows, cols);
+    const bool dense = o.method == HPEPS_ESVD_EXPLICIT;
+    const int64_t k = dense ? std::min(rows, cols) : sketch_width(o.rank, o.oversample, rows, cols);
     const int64_t mp = std::min<int64_t>(o.rank, k);
     HP_REQUIRE(k >= 1 && k <= (cplx ? 88 : 128), HPEPS_ERR_SHAPE, "sketch width k out of range");
     HP_REQUIRE(rows * mp <= rb.cap_u && mp * cols <= (q + 1 < n ? rb.cap_c : rb.cap_u), HPEPS_ERR_SHAPE,
@@ -153,10 +154,6 @@ void absorb_row(Ctx& ctx, bool cplx, int nb, const std::vector<Bnd>& bnd, const 
       contract2(ctx, cplx, tvz(A, "uyhg", nb, true), tview_rm(W1, "Zuchk", {nb, u, c, h, k}), "Zycgk", Y,
                 nb * cols * k);
     };
-    double* Om = ctx.ws<double>(cols * k * es);
-    sketch(ctx, Om, false, cols, k, 1, o.seed, 1 + ((uint64_t)lattice_row * n + col(q)), cplx);
-    double* Y0 = ctx.ws<double>(nb * rows * k * es);
-    fwd(Om, false, Y0);
     ZipOut zo;
     zo.Urows.add(rows, mp);
     zo.Ucol.add(mp, 1);
@@ -166,13 +163,35 @@ void absorb_row(Ctx& ctx, bool cplx, int nb, const std::vector<Bnd>& bnd, const 
     zo.nR = mp * cols;
     double* U = slot(col(q - 1));
     double* R = q + 1 < n ? rb.carries[1 - cur] : slot(col(q));
-    rsvd_finish(ctx, cplx, rows, cols, k, mp, nb, o, HPEPS_ABSORB_CARRY, zo, U, nullptr, R, logs, Y0,
-                [&](bool adjoint, const double* X, double* Y) {
-                  if (adjoint)
-                    adj(X, Y);
-                  else
-                    fwd(X, true, Y);
-                });
+    if (dense) {
+      // BMPS: the matrix of the network, A [Z,(a,x),(y,c,g)] or, when it is
+      // wide, A^* [Z,(y,c,g),(a,x)] (every operand conjugated), then its
+      // dense truncated SVD
+      const bool wide = rows <= cols;
+      double* Wt = ctx.ws<double>(nb * a * x * h * u * c * es);
+      double* M = ctx.ws<double>(nb * rows * cols * es);
+      contract2(ctx, cplx, tvz(Cv, "axbh", nb, wide), tvz(S, "buc", nb, wide), "Zaxhuc", Wt,
+                nb * a * x * h * u * c);
+      contract2(ctx, cplx, tview_rm(Wt, "Zaxhuc", {nb, a, x, h, u, c}), tvz(A, "uyhg", nb, wide),
+                wide ? "Zycgax" : "Zaxycg", M, nb * rows * cols);
+      dense_finish(ctx, cplx, rows, cols, mp, nb, o, HPEPS_ABSORB_CARRY, zo, U, nullptr, R, logs, M,
+                   [&](bool, const double* P, double* Bs) {
+                     contract2(ctx, cplx, tview_rm(M, "Zaxycg", {nb, a, x, y, c, g}, cplx),
+                               tview_rm(P, "Zaxk", {nb, a, x, k}), "Zycgk", Bs, nb * cols * k);
+                   });
+    } else {
+      double* Om = ctx.ws<double>(cols * k * es);
+      sketch(ctx, Om, false, cols, k, 1, o.seed, 1 + ((uint64_t)lattice_row * n + col(q)), cplx);
+      double* Y0 = ctx.ws<double>(nb * rows * k * es);
+      fwd(Om, false, Y0);
+      rsvd_finish(ctx, cplx, rows, cols, k, mp, nb, o, HPEPS_ABSORB_CARRY, zo, U, nullptr, R, logs, Y0,
+                  [&](bool adjoint, const double* X, double* Y) {
+                    if (adjoint)
+                      adj(X, Y);
+                    else
+                      fwd(X, true, Y);
+                  });
+    }
     // U [a, x, mp] in the sweep frame: lattice [left, x, right]
     Bnd uv;
     uv.p = U;
@@ -277,6 +296,8 @@ void amplitudes(Ctx& c, const hpeps_peps* ket, int64_t n_states, const int32_t* 
   HP_REQUIRE(opts->rank >= 1 && opts->oversample >= 0 && opts->power_iters >= 0 && opts->jacobi_max_sweeps >= 0,
              HPEPS_ERR_INVALID_ARG, "bad einsumsvd options");
   HP_REQUIRE(opts->sketch_precision == HPEPS_F64, HPEPS_ERR_DTYPE, "amplitudes run in FP64 / complex128");
+  HP_REQUIRE(opts->method == HPEPS_ESVD_IMPLICIT || opts->method == HPEPS_ESVD_EXPLICIT, HPEPS_ERR_INVALID_ARG,
+             "unknown einsumsvd method");
   const Lattice K = lattice_from_abi(ket);
   const bool cplx = K.cplx;
   const int es = cplx ? 2 : 1;

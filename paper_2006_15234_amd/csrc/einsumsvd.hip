@@ -154,6 +154,97 @@ void apply_network(Ctx& ctx, bool cplx, const Network& net, bool adjoint, const 
   }
 }
 
+// The network contracted into its matrix: A [rows][cols] (legs left + right),
+// or A^* [cols][rows] (legs right + left, every operand conjugated) with
+// `adjoint`.  Operands are taken greedily as in apply_network, starting from
+// the first.
+void form_network(Ctx& ctx, bool cplx, const Network& net, bool adjoint, double* M) {
+  WsScope scope(ctx);
+  std::vector<TView> rest = net.ops;
+  if (adjoint)
+    for (auto& v : rest) v.conj = cplx && !v.conj;
+  const std::string want = adjoint ? net.right + net.left : net.left + net.right;
+  const int64_t total = net.rows * net.cols;
+  if (rest.size() == 1) {
+    // one operand: a permuted copy, as a contraction with a one-element tensor
+    // over a unit leg
+    double* one = ctx.ws<double>(cplx ? 2 : 1);
+    fill_value(ctx, one, 1, 1.0, cplx);
+    TView op = rest[0];
+    op.legs += '@';
+    op.dims.push_back(1);
+    op.strides.push_back(0);
+    contract2(ctx, cplx, op, tview_rm(one, "@", {1}), want, M, total);
+    return;
+  }
+  TView cur = rest[0];
+  rest.erase(rest.begin());
+  while (!rest.empty()) {
+    int best = -1, best_shared = -1;
+    int64_t best_size = 0;
+    std::string best_out;
+    for (int i = 0; i < (int)rest.size(); ++i) {
+      std::string o;
+      int shared = 0;
+      for (char c : cur.legs)
+        if (rest[i].legs.find(c) == std::string::npos) o += c; else ++shared;
+      for (char c : rest[i].legs)
+        if (cur.legs.find(c) == std::string::npos) o += c;
+      const int64_t sz = vol(o, cur, rest[i]);
+      if (shared > best_shared || (shared == best_shared && sz < best_size)) {
+        best = i;
+        best_shared = shared;
+        best_size = sz;
+        best_out = o;
+      }
+    }
+    const TView op = rest[best];
+    rest.erase(rest.begin() + best);
+    if (rest.empty()) {
+      HP_REQUIRE(best_out.size() == want.size(), HPEPS_ERR_INVALID_ARG, "network legs do not close");
+      for (char c : want)
+        HP_REQUIRE(best_out.find(c) != std::string::npos, HPEPS_ERR_INVALID_ARG, "network legs do not close");
+      contract2(ctx, cplx, cur, op, want, M, total);
+    } else {
+      double* buf = ctx.ws<double>(best_size * (cplx ? 2 : 1));
+      const auto dims = contract2(ctx, cplx, cur, op, best_out, buf, best_size);
+      cur = tview_rm(buf, best_out, dims);
+    }
+  }
+}
+
+// The einsumsvd of BMPS: the explicit matrix and its dense truncated SVD.
+void einsumsvd_explicit(Ctx& ctx, bool cplx, const Network& net, const hpeps_esvd_opts& o, hpeps_absorb absorb,
+                        void* U, double* sigma, void* R, double* log_scale) {
+  WsScope scope(ctx);
+  const int64_t rows = net.rows, cols = net.cols;
+  const int64_t k = std::min(rows, cols);
+  const int64_t mp = std::min<int64_t>(o.rank, k);
+  HP_REQUIRE(k <= (cplx ? 88 : 128), HPEPS_ERR_SHAPE,
+             "explicit einsumsvd: min(rows, cols) must be <= 128 (88 complex)");
+  ctx.last_rank = mp;
+  ctx.last_k = k;
+  const int es = cplx ? 2 : 1;
+  double* M = ctx.ws<double>(rows * cols * es);
+  ZipOut out;
+  out.Urows.add(rows, mp);
+  out.Ucol.add(mp, 1);
+  out.Rrow.add(mp, cols);
+  out.Rcols.add(cols, 1);
+  out.nU = rows * mp;
+  out.nR = mp * cols;
+  const bool wide = rows <= cols;
+  form_network(ctx, cplx, net, wide, M);
+  std::vector<int64_t> mdims = net.ldims, pdims = net.ldims;
+  mdims.insert(mdims.end(), net.rdims.begin(), net.rdims.end());
+  pdims.push_back(k);
+  dense_finish(ctx, cplx, rows, cols, mp, 1, o, absorb, out, U, sigma, R, log_scale, M,
+               [&](bool, const double* P, double* Bs) {
+                 contract2(ctx, cplx, tview_rm(M, net.left + net.right, mdims, cplx),
+                           tview_rm(P, net.left + kSketchLeg, pdims), net.right + kSketchLeg, Bs, cols * k);
+               });
+}
+
 }  // namespace
 
 void einsumsvd_network(Ctx& ctx, bool cplx, const char* subscripts, int n_ops, const hpeps_tensor* ops,
@@ -162,6 +253,13 @@ void einsumsvd_network(Ctx& ctx, bool cplx, const char* subscripts, int n_ops, c
   WsScope scope(ctx);
   HP_REQUIRE(o.sketch_precision == HPEPS_F64, HPEPS_ERR_DTYPE, "network einsumsvd runs in FP64 / complex128");
   const Network net = parse(subscripts, n_ops, ops, cplx);
+  HP_REQUIRE(o.method == HPEPS_ESVD_IMPLICIT || o.method == HPEPS_ESVD_EXPLICIT, HPEPS_ERR_INVALID_ARG,
+             "unknown einsumsvd method");
+  if (o.method == HPEPS_ESVD_EXPLICIT) {
+    HP_REQUIRE(net.rows < (1LL << 31) && net.cols < (1LL << 31), HPEPS_ERR_UNSUPPORTED, "matrix dimension too large");
+    einsumsvd_explicit(ctx, cplx, net, o, absorb, U, sigma, R, log_scale);
+    return;
+  }
   const int64_t rows = net.rows, cols = net.cols;
   const int64_t k = sketch_width(o.rank, o.oversample, rows, cols);
   const int64_t mp = std::min<int64_t>(o.rank, k);

@@ -97,6 +97,13 @@ struct ZipOut;
 void rsvd_finish(Ctx& ctx, bool cplx, int64_t rows, int64_t cols, int64_t k, int64_t mp, int batch,
                  const hpeps_esvd_opts& o, hpeps_absorb absorb, const ZipOut& out, void* U, double* sigma,
                  void* R, double* log_scale, double* Y0, const ApplyFn& apply);
+// Truncated SVD of explicit matrices (BMPS's einsumsvd): M = A^* as
+// [batch][cols][rows] when rows <= cols, else M = A as [batch][rows][cols]
+// (overwritten), whose projection A^* P adj_apply(true, P, out) computes.
+// k = min(rows, cols) <= 128 (88 complex).
+void dense_finish(Ctx& ctx, bool cplx, int64_t rows, int64_t cols, int64_t mp, int batch, const hpeps_esvd_opts& o,
+                  hpeps_absorb absorb, const ZipOut& out, void* U, double* sigma, void* R, double* log_scale,
+                  double* M, const ApplyFn& adj_apply);
 
 // Randomized einsumsvd (Alg. 4) of the zip-up operator; operands are FP64 /
 // complex128 device arrays (instances back to back with the extents of L).

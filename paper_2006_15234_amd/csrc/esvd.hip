@@ -513,42 +513,30 @@ int64_t sketch_width(int64_t m, int64_t p, int64_t rows, int64_t cols) {
   return std::min(m + p, std::min(rows, cols));
 }
 
-// Alg. 4 after the first product: Y0 = A Omega (rows x k per instance) is
-// orthogonalized, the q power iterations and the projection B^* = A^* P run
-// through `apply` (A X for adj = false, A^* X for adj = true; FP64 /
-// complex128 panels), then the small SVD, the canonical phase and the two
-// factors follow.  Y0 is overwritten.
-void rsvd_finish(Ctx& ctx, bool cplx, int64_t rows, int64_t cols, int64_t k, int64_t mp, int batch,
-                 const hpeps_esvd_opts& o, hpeps_absorb absorb, const ZipOut& out, void* U, double* sigma,
-                 void* R, double* log_scale, double* Xr0, const ApplyFn& apply) {
+// The end of Alg. 4 from an orthonormal basis P of the range (Xr1, rows x k
+// per instance) and the projection B^* = A^* P (Xc0, cols x k): the R factor
+// of B^*, the small SVD, the canonical phase and the two factors.  Neither
+// panel is modified.
+static void project_svd(Ctx& ctx, bool cplx, int64_t rows, int64_t cols, int64_t k, int64_t mp, int batch,
+                        const hpeps_esvd_opts& o, hpeps_absorb absorb, const ZipOut& out, void* U, double* sigma,
+                        void* R, double* log_scale, const double* Xr1, const double* Xc0) {
   WsScope scope(ctx);
   const int es = cplx ? 2 : 1;
   const int64_t nb = batch;
   const int max_sweeps = o.jacobi_max_sweeps > 0 ? o.jacobi_max_sweeps : 40;
-  double* Xc0 = ctx.ws<double>(nb * cols * k * es);
   double* Xc1 = ctx.ws<double>(nb * cols * k * es);
   double* Xc2 = ctx.ws<double>(nb * cols * k * es);
-  double* Xr1 = ctx.ws<double>(nb * rows * k * es);
   OrthWork ow;
   ow.G = ctx.ws<double>(nb * k * k * es);
   ow.Rinv = ctx.ws<double>(nb * k * k * es);
   ow.Racc = ctx.ws<double>(nb * k * k * es);
   ow.flags = ctx.ws<int>(nb);
-  HP_REQUIRE(o.orth == HPEPS_ORTH_CHOLQR || o.orth == HPEPS_ORTH_EIGH, HPEPS_ERR_INVALID_ARG, "unknown orth mode");
   ow.mode = o.orth;
   double* Z = ctx.ws<double>(nb * k * k * es);
   double* sig = ctx.ws<double>(nb * k);
   double* isig = ctx.ws<double>(nb * k);
   double* isig1 = ctx.ws<double>(nb);
   int* sweeps = ctx.ws<int>(nb);
-  orthogonalize(ctx, cplx, Xr0, Xr1, rows, k, batch, ow);          // P in Xr1
-  for (int it = 0; it < o.power_iters; ++it) {
-    apply(true, Xr1, Xc0);
-    orthogonalize(ctx, cplx, Xc0, Xc1, cols, k, batch, ow);        // Q in Xc1
-    apply(false, Xc1, Xr0);
-    orthogonalize(ctx, cplx, Xr0, Xr1, rows, k, batch, ow);        // P in Xr1
-  }
-  apply(true, Xr1, Xc0);                                           // B^* = A^* P
   cholqr_r(ctx, cplx, Xc0, Xc1, Xc2, cols, k, batch, ow);          // R_B in Racc
   jacobi_svd(ctx, cplx, ow.Racc, k, batch, max_sweeps, Z, sig, isig, isig1,
              absorb == HPEPS_ABSORB_CARRY ? log_scale : nullptr, sweeps);
@@ -637,6 +625,79 @@ void rsvd_finish(Ctx& ctx, bool cplx, int64_t rows, int64_t cols, int64_t k, int
     gemm(ctx, p64, D, c);
   }
   if (sigma) copy_sigma(ctx, sig, k, mp, batch, sigma);
+}
+
+// Alg. 4 after the first product: Y0 = A Omega (rows x k per instance) is
+// orthogonalized, the q power iterations and the projection B^* = A^* P run
+// through `apply` (A X for adj = false, A^* X for adj = true; FP64 /
+// complex128 panels), then project_svd finishes.  Y0 is overwritten.
+void rsvd_finish(Ctx& ctx, bool cplx, int64_t rows, int64_t cols, int64_t k, int64_t mp, int batch,
+                 const hpeps_esvd_opts& o, hpeps_absorb absorb, const ZipOut& out, void* U, double* sigma,
+                 void* R, double* log_scale, double* Xr0, const ApplyFn& apply) {
+  WsScope scope(ctx);
+  const int es = cplx ? 2 : 1;
+  const int64_t nb = batch;
+  HP_REQUIRE(o.orth == HPEPS_ORTH_CHOLQR || o.orth == HPEPS_ORTH_EIGH, HPEPS_ERR_INVALID_ARG, "unknown orth mode");
+  HP_REQUIRE(o.method == HPEPS_ESVD_IMPLICIT || o.method == HPEPS_ESVD_EXPLICIT, HPEPS_ERR_INVALID_ARG,
+             "unknown einsumsvd method");
+  HP_REQUIRE(o.method == HPEPS_ESVD_IMPLICIT, HPEPS_ERR_UNSUPPORTED,
+             "this entry point runs the implicit (randomized) einsumsvd only");
+  double* Xc0 = ctx.ws<double>(nb * cols * k * es);
+  double* Xc1 = ctx.ws<double>(nb * cols * k * es);
+  double* Xr1 = ctx.ws<double>(nb * rows * k * es);
+  OrthWork ow;
+  ow.G = ctx.ws<double>(nb * k * k * es);
+  ow.Rinv = ctx.ws<double>(nb * k * k * es);
+  ow.Racc = ctx.ws<double>(nb * k * k * es);
+  ow.flags = ctx.ws<int>(nb);
+  ow.mode = o.orth;
+  orthogonalize(ctx, cplx, Xr0, Xr1, rows, k, batch, ow);          // P in Xr1
+  for (int it = 0; it < o.power_iters; ++it) {
+    apply(true, Xr1, Xc0);
+    orthogonalize(ctx, cplx, Xc0, Xc1, cols, k, batch, ow);        // Q in Xc1
+    apply(false, Xc1, Xr0);
+    orthogonalize(ctx, cplx, Xr0, Xr1, rows, k, batch, ow);        // P in Xr1
+  }
+  apply(true, Xr1, Xc0);                                           // B^* = A^* P
+  project_svd(ctx, cplx, rows, cols, k, mp, batch, o, absorb, out, U, sigma, R, log_scale, Xr1, Xc0);
+}
+
+// Truncated SVD of explicit matrices (the einsumsvd of BMPS, Sec. III-B:
+// the network contracted into its matrix, then a dense SVD).  The range
+// basis is exact instead of sketched: for rows <= cols, P = I and
+// B^* = A^* is M itself ([batch][cols][rows]); otherwise M = A
+// ([batch][rows][cols], overwritten) is orthogonalized to P and
+// B^* = A^* P comes from adj_apply.  The dense SVD is then the QR of B^*
+// and the one-sided Jacobi SVD of its R factor.
+void dense_finish(Ctx& ctx, bool cplx, int64_t rows, int64_t cols, int64_t mp, int batch, const hpeps_esvd_opts& o,
+                  hpeps_absorb absorb, const ZipOut& out, void* U, double* sigma, void* R, double* log_scale,
+                  double* M, const ApplyFn& adj_apply) {
+  WsScope scope(ctx);
+  const int es = cplx ? 2 : 1;
+  const int64_t nb = batch;
+  const int64_t k = std::min(rows, cols);
+  HP_REQUIRE(o.orth == HPEPS_ORTH_CHOLQR || o.orth == HPEPS_ORTH_EIGH, HPEPS_ERR_INVALID_ARG, "unknown orth mode");
+  HP_REQUIRE(!ctx.tape, HPEPS_ERR_UNSUPPORTED, "the explicit einsumsvd has no adjoint");
+  HP_REQUIRE(k >= 1 && k <= (cplx ? 88 : 128), HPEPS_ERR_SHAPE,
+             "explicit einsumsvd: min(rows, cols) must be <= 128 (88 complex)");
+  HP_REQUIRE(mp >= 1 && mp <= k, HPEPS_ERR_SHAPE, "kept rank out of range");
+  if (rows <= cols) {
+    double* P = ctx.ws<double>(nb * rows * rows * es);
+    fill_identity(ctx, P, rows, batch, cplx);
+    project_svd(ctx, cplx, rows, cols, k, mp, batch, o, absorb, out, U, sigma, R, log_scale, P, M);
+    return;
+  }
+  double* P = ctx.ws<double>(nb * rows * k * es);
+  double* Bs = ctx.ws<double>(nb * cols * k * es);
+  OrthWork ow;
+  ow.G = ctx.ws<double>(nb * k * k * es);
+  ow.Rinv = ctx.ws<double>(nb * k * k * es);
+  ow.Racc = ctx.ws<double>(nb * k * k * es);
+  ow.flags = ctx.ws<int>(nb);
+  ow.mode = o.orth;
+  orthogonalize(ctx, cplx, M, P, rows, k, batch, ow);
+  adj_apply(true, P, Bs);
+  project_svd(ctx, cplx, rows, cols, k, mp, batch, o, absorb, out, U, sigma, R, log_scale, P, Bs);
 }
 
 void zip_esvd(Ctx& ctx, bool cplx, const ZipDims& z, const ZipLayout& L, const ZipOperands& op64,

@@ -144,6 +144,8 @@ void fill_zero(Ctx& ctx, void* p, int64_t bytes);
 // p[0..n) = v (complex: real part v, imaginary part 0), by a kernel (no memset
 // nodes, so the call can sit in a captured graph)
 void fill_value(Ctx& ctx, double* p, int64_t n, double v, bool cplx);
+// p[b] = I (n x n, row-major) for b < batch, by a kernel
+void fill_identity(Ctx& ctx, double* p, int64_t n, int batch, bool cplx);
 // Canonical phase of singular pairs: U (row-major rows x mp per instance) is
 // the left factor P Z; column i of Z (k x k) is rotated so that the
 // projection of U[:, i] on a fixed counter-generated vector becomes real

@@ -1068,6 +1068,22 @@ void gather2d(Ctx& ctx, bool cplx, const void* src, int64_t sSrc, const IndexMap
   HP_CHECK_HIP(hipGetLastError());
 }
 
+namespace {
+__global__ void identity_kernel(double* p, long long n, long long total, int es) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= total) return;
+  const long long r = (e / n) % n, c = e % n;
+  p[e * es] = r == c ? 1.0 : 0.0;
+  if (es == 2) p[e * es + 1] = 0.0;
+}
+}  // namespace
+
+void fill_identity(Ctx& ctx, double* p, int64_t n, int batch, bool cplx) {
+  const long long total = (long long)batch * n * n;
+  identity_kernel<<<(unsigned)cdiv(total, 256), 256, 0, ctx.stream>>>(p, n, total, cplx ? 2 : 1);
+  HP_CHECK_HIP(hipGetLastError());
+}
+
 void sqrt_pair(Ctx& ctx, const double* s, int64_t n, double* sq, double* isq) {
   if (n <= 0) return;
   sqrt_pair_kernel<<<std::min<unsigned>(cdiv(n, 256), 1024), 256, 0, ctx.stream>>>(s, n, sq, isq);

@@ -77,3 +77,30 @@ def test_truncation_error_shrinks_with_rank():
         la, ph = amp.amplitude(ket, bits, m=m, p=4, q=2, seed=1)
         errs.append(abs(_value(la, ph) - ref) / np.abs(psi).max())
     assert errs[1] < 1e-12 < errs[0]
+
+
+@pytest.mark.parametrize("cplx", [False, True])
+def test_explicit_exact_regime_equals_state_vector(cplx):
+    """BMPS (explicit matrix, dense truncated SVD) with m covering every
+    boundary reproduces the exact amplitude."""
+    ket = synth.random_peps(4, 3, 2, seed=21, complex_=cplx)
+    psi = sv.peps_to_statevector(ket)
+    rng = np.random.default_rng(5)
+    for _ in range(3):
+        bits = rng.integers(0, 2, 12)
+        la, ph = amp.amplitude(ket, bits, m=64, p=0, q=0, seed=0, explicit=True)
+        assert abs(_value(la, ph) - psi[tuple(bits)]) <= 1e-12 * np.abs(psi).max()
+
+
+def test_explicit_is_the_limit_of_power_iterations():
+    """With truncation, every BMPS step keeps the exact rank-m truncated SVD;
+    the randomized SVD converges to it as the power iterations grow (the
+    spectrum of each zip-up matrix has a gap at m), so IBMPS with many power
+    iterations and oversampling reproduces BMPS."""
+    ket = synth.random_peps(4, 4, 2, seed=8)
+    bits = np.random.default_rng(2).integers(0, 2, 16)
+    le, pe = amp.amplitude(ket, bits, m=3, p=0, q=0, seed=0, explicit=True)
+    li, pi = amp.amplitude(ket, bits, m=3, p=5, q=60, seed=4)
+    assert abs(le - li) < 1e-9 and abs(pe - pi) < 1e-9
+    l0, _ = amp.amplitude(ket, bits, m=3, p=0, q=0, seed=4)
+    assert abs(le - l0) > 1e-6   # without power iterations the two differ
