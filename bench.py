@@ -456,6 +456,67 @@ def bmps_vs_ibmps(hp, batch, n=8, bonds=(2, 3, 4, 5, 6, 8, 10, 11), p=4, q=1, re
                         f"IBMPS p={p} q={q}, {batch} amplitudes per call", "by_bond": out}
 
 
+def caching(hp, sizes=(6, 12), D=4, m=16, p=4, q=1, tau=0.01, trotter_D=2):
+    """Sec. IV-B's caching measured as in Fig. 9: the energy of an n x n PEPS
+    (bond D, random sites) under a one-site operator on every site and a
+    two-site operator on every nearest-neighbour pair (the TFI terms -Z Z and
+    -3 X), with cached environments (two boundary passes plus strips) and
+    without (every term its own full contraction), same boundary bond m, beside
+    the time of one norm.  Then the Trotter-Taylor estimate of Eq. 6 (tau =
+    0.01) on bond-trotter_D lattices of the same sizes: phi grows every bond by
+    d^2 = 4 (bond 16 at D = 4 would need boundary panels beyond 4 GiB), timed
+    and compared with the cached energy of the same state."""
+    import numpy as np
+    import torch
+
+    import synth
+    X, Z = synth.PAULI["X"], synth.PAULI["Z"]
+    ZZ = -np.einsum("ac,bd->abcd", Z, Z)
+    ctx = hp.Context(0)
+    kw = dict(rank=m, oversample=p, power_iters=q, seed=0)
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = fn()
+        torch.cuda.synchronize()
+        return r, round(time.perf_counter() - t0, 4)
+
+    def lattice(n, bond):
+        ket = synth.random_peps(n, n, bond, seed=n)
+        dev = [[torch.from_numpy(np.ascontiguousarray(t)).cuda() for t in row] for row in ket]
+        bonds = [b for layer in synth.lattice_bonds(n, n) for b in layer]
+        terms = [(b, ZZ) for b in bonds] + [(((i, j),), -3.0 * X) for i in range(n) for j in range(n)]
+        return dev, bonds, terms
+
+    out, trot = [], []
+    for n in sizes:
+        dev, bonds, terms = lattice(n, D)
+        row = {"n": n, "terms": len(terms)}
+        hp.peps_energy(ctx, dev, terms, **kw)            # warm-up (workspace, tuning)
+        _, row["norm_s"] = timed(lambda: hp.peps_norm(ctx, dev, **kw))
+        rc, row["cached_s"] = timed(lambda: hp.peps_energy(ctx, dev, terms, **kw))
+        ru, row["uncached_s"] = timed(lambda: hp.peps_energy_uncached(ctx, dev, terms, **kw))
+        row["cached_energy_per_site"] = rc[0].real / (n * n)
+        row["uncached_energy_per_site"] = ru[0].real / (n * n)
+        row["caching_speedup"] = round(row["uncached_s"] / row["cached_s"], 2)
+        out.append(row)
+        del dev
+        dev, bonds, terms = lattice(n, trotter_D)
+        hams = synth.tfi_bond_hamiltonians(n, n, 1.0, 3.0)
+        gates = [(b, synth.bond_gate(hams[b], -tau)) for b in bonds]
+        hp.peps_trotter_expectation(ctx, dev, gates, tau, **kw)   # warm-up
+        rt, t_s = timed(lambda: hp.peps_trotter_expectation(ctx, dev, gates, tau, **kw))
+        rc, c_s = timed(lambda: hp.peps_energy(ctx, dev, terms, **kw))
+        trot.append({"n": n, "D": trotter_D, "trotter_s": t_s, "cached_s": c_s,
+                     "trotter_energy_per_site": rt[0].real / (n * n),
+                     "cached_energy_per_site": rc[0].real / (n * n)})
+        del dev
+    return {"workload": f"n x n PEPS, random sites; terms -ZZ on every bond and -3X on every site; "
+                        f"bond {D} for cached vs uncached, bond {trotter_D} for Eq. 6 (tau={tau}); "
+                        f"m={m} p={p} q={q}", "by_size": out, "trotter": trot}
+
+
 def c4_ite(hp, sweeps, n=16, D=8, d=2, tau=0.01, J=1.0, hfield=3.0, m=32, p=8, q=1, plain_sweeps=5):
     """Batched imaginary-time evolution of an n x n transverse-field Ising PEPS: TEBD sweeps
     of QR-SVD updates over the four layers of non-overlapping bonds (bond dimensions grow
@@ -538,6 +599,10 @@ def main():
                          "call (0 skips)")
     ap.add_argument("--bmps-only", type=int, default=0, metavar="BATCH",
                     help="run only the BMPS vs IBMPS block and print its JSON")
+    ap.add_argument("--no-caching", action="store_true",
+                    help="leave the cached vs uncached energy block (6x6 and 12x12, D=4) out of the full run")
+    ap.add_argument("--caching-only", action="store_true",
+                    help="run only the cached vs uncached energy block and print its JSON")
     ap.add_argument("--c5", type=int, default=2, metavar="REPS",
                     help="time the 8x8 D=4 complex energy gradient this many times (0 skips)")
     ap.add_argument("--c3", action="store_true",
@@ -567,6 +632,10 @@ def main():
 
     import paper_2006_15234_amd as hp
     import synth
+
+    if args.caching_only:
+        print(json.dumps(caching(hp)))
+        return
 
     if args.bmps_only > 0:
         print(json.dumps(bmps_vs_ibmps(hp, args.bmps_only)))
@@ -708,6 +777,8 @@ def main():
         hp.autotune_import(ctx, hp.autotune_export(actx))   # its tuned products join the saved set
     if args.bmps > 0:
         res["bmps_vs_ibmps"] = bmps_vs_ibmps(hp, args.bmps)
+    if not args.no_caching:
+        res["caching"] = caching(hp)
     if args.c5 > 0:
         res["c5_gradient"] = c5_gradient(hp, args.c5)
     if args.d8 > 0:

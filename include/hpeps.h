@@ -435,6 +435,37 @@ hpeps_status hpeps_peps_energy(hpeps_ctx* ctx, const hpeps_peps* ket, int32_t n_
                                const double* ops, const int64_t* op_offset,
                                const hpeps_esvd_opts* opts, double* energy, double* per_term);
 
+/* hpeps_peps_energy_uncached: Eq. 5 without the caching of Sec. IV-B, the
+ * baseline the cached call is measured against.  Every term is its own full
+ * boundary-MPS contraction <psi|H_t psi> / <psi|psi>, with H_t applied to the
+ * ket exactly: a one-site operator on its site's physical leg; a two-site
+ * operator G[P,Q,p,q] (out1, out2, in1, in2) by the elementary split
+ * G = sum_{Q,q} G[:,Q,:,q] (x) |Q><q| -- site 1 takes G[:,Q,:,q], site 2
+ * takes |Q><q|, and (Q, q) is appended to their shared bond (new index
+ * (b, Q, q) row-major: the bond grows from D to D d^2) -- and the bra
+ * zero-padded to the grown bond, which leaves the overlap unchanged.  Same
+ * arguments and outputs as hpeps_peps_energy (a real PEPS takes real
+ * operators only: HPEPS_ERR_DTYPE otherwise); n_terms + 1 contractions, all
+ * with the stream ids of hpeps_peps_norm.  Synchronises. */
+hpeps_status hpeps_peps_energy_uncached(hpeps_ctx* ctx, const hpeps_peps* ket, int32_t n_terms,
+                                        const int32_t* nsites, const int32_t* sites,
+                                        const double* ops, const int64_t* op_offset,
+                                        const hpeps_esvd_opts* opts, double* energy, double* per_term);
+
+/* hpeps_peps_trotter_expectation: the Trotter-Taylor estimate of Eq. 6,
+ * <H> ~ (<psi| prod_j G_j |psi> / <psi|psi> - 1) / tau with G_j = e^{tau H_j}
+ * supplied by the caller: n_gates nearest-neighbour gates, sites[4*j] =
+ * (i1, j1, i2, j2) (site 1 left of / above site 2), gates (host, complex128
+ * pairs) [n_gates][d,d,d,d] (out1, out2, in1, in2).  phi = prod_j G_j psi is
+ * applied exactly, gate by gate in the order given (the elementary split of
+ * hpeps_peps_energy_uncached: every bond a gate touches grows by d^2), and
+ * <psi|phi> is one boundary contraction against the zero-padded psi, beside
+ * the contraction of <psi|psi>.  Outputs (host): estimate[2] = {re, im},
+ * ratio[2] = <psi|phi> / <psi|psi> (may be NULL).  Synchronises. */
+hpeps_status hpeps_peps_trotter_expectation(hpeps_ctx* ctx, const hpeps_peps* ket, int32_t n_gates,
+                                            const int32_t* sites, const double* gates, double tau,
+                                            const hpeps_esvd_opts* opts, double* estimate, double* ratio);
+
 /* ---- gradients of peps_norm / peps_energy (reverse mode) -----------------
  * The paper evaluates these quantities; it does not differentiate them.
  * These calls give their gradients with respect to every site tensor, for

@@ -8,8 +8,19 @@ vertical term on rows i, i+1 uses a four-row strip.  Each term is the ratio
 strip(term) / strip(identity) evaluated with the same left/right strip
 environments, so all scale factors cancel.
 
-Uncached (test-only cross-check): every term is an independent full
-boundary-MPS contraction of <psi|H_t|psi>, divided by <psi|psi>.
+Uncached: every term is an independent full boundary-MPS contraction of
+<psi|H_t psi>, divided by <psi|psi>.  H_t psi is applied exactly: a one-site
+operator acts on its site's physical leg; a two-site operator G is split into
+d^2 products G = sum_{Q,q} G[:, Q, :, q] (x) |Q><q| (the elementary split: no
+decomposition to compute), the first factor entering site 1 and the second
+site 2, the pair index (Q, q) appended to their shared bond, which grows from
+D to D d^2 (bond index (b, Q, q) row-major).  The bra psi is zero-padded to
+the same bond dimensions, which leaves <psi|H_t psi> unchanged.
+
+Trotter-Taylor (Eq. 6): <H> ~ (<psi|prod_j e^{tau H_j}|psi> / <psi|psi> - 1)
+/ tau, with phi = prod_j G_j psi applied exactly gate by gate in the order
+given (every bond a gate touches grows by d^2) and <psi|phi> contracted
+against the zero-padded psi.
 
 A term is (sites, op): sites a tuple of (i, j); op is [2,2] (out, in) for one
 site or [2,2,2,2] (out1, out2, in1, in2) for two nearest-neighbour sites with
@@ -165,23 +176,81 @@ def _value(log_abs, phase):
     return phase * np.exp(log_abs)
 
 
+def apply_one_site(T, O):
+    """T'[u,d,l,r,P] = sum_p O[P,p] T[u,d,l,r,p]."""
+    return np.einsum("Pp,udlrp->udlrP", O, T)
+
+
+def apply_two_site_exact(S, T, G, vertical):
+    """Exact application of G[P,Q,p,q] (out1, out2, in1, in2) to the neighbour
+    sites S (left of / above) and T by the elementary split: S takes
+    G[:, Q, :, q], T takes |Q><q|, and the pair (Q, q) joins their shared bond
+    (new bond index (b, Q, q), row-major).  Returns (S', T')."""
+    d = G.shape[0]
+    E = np.zeros((d, d, d), dtype=G.dtype)          # E[Q, q, X] = delta(Q, X)
+    for a in range(d):
+        E[a, :, a] = 1.0
+    if vertical:
+        S2 = np.einsum("udlrp,PQpq->udQqlrP", S, G)
+        T2 = np.einsum("udlrq,QqX->uQqdlrX", T, E)
+        u, d1, l, r, P = S.shape
+        S2 = S2.reshape(u, d1 * d * d, l, r, d)
+        u2, dd, l2, r2, _ = T.shape
+        T2 = T2.reshape(u2 * d * d, dd, l2, r2, d)
+    else:
+        S2 = np.einsum("udlrp,PQpq->udlrQqP", S, G)
+        T2 = np.einsum("udlrq,QqX->udlQqrX", T, E)
+        u, d1, l, r, P = S.shape
+        S2 = S2.reshape(u, d1, l, r * d * d, d)
+        u2, dd, l2, r2, _ = T.shape
+        T2 = T2.reshape(u2, dd, l2 * d * d, r2, d)
+    return S2, T2
+
+
+def pad_site(T, shape):
+    """T zero-padded to ``shape`` (every leg at least as long as T's)."""
+    out = np.zeros(shape, dtype=T.dtype)
+    out[tuple(slice(0, n) for n in T.shape)] = T
+    return out
+
+
+def _overlap_ratio(phi, ket, m, p, q, seed, ln, ph):
+    """<ket|phi> / <ket|ket> with ket zero-padded to phi's shapes."""
+    bra = [[pad_site(t, f.shape) for t, f in zip(rk, rf)] for rk, rf in zip(ket, phi)]
+    l2, p2 = peps_norm(phi, m, p, q, seed, bra=bra)
+    return _value(l2 - ln, p2 / ph)
+
+
 def peps_energy_uncached(ket, terms, m, p, q, seed):
-    """Eq. 5 term by term: each <psi|H_t|psi> is its own boundary contraction."""
+    """Eq. 5 term by term: each <psi|H_t psi> is its own boundary contraction of
+    the exactly applied H_t psi against the zero-padded psi."""
     ln, ph = peps_norm(ket, m, p, q, seed)
     per_term = []
     for sites, op in terms:
+        phi = [[t for t in row] for row in ket]
         if len(sites) == 1:
-            parts = [((op,), sites)]
+            (i, j), = sites
+            phi[i][j] = apply_one_site(ket[i][j], op)
         else:
-            parts = [((A, B), sites) for A, B in operator_schmidt(op)]
-        val = 0.0
-        for ops, ss in parts:
-            mod = [[t for t in row] for row in ket]
-            for o, (i, j) in zip(ops, ss):
-                mod[i][j] = np.einsum("Pp,udlrp->udlrP", o, ket[i][j])
-            l2, p2 = peps_norm(mod, m, p, q, seed, bra=ket)
-            # <ket|O ket> : bra = ket (conjugated), ket = modified
-            val = val + _value(l2 - ln, p2 / ph)
-        per_term.append(val)
+            (i1, j1), (i2, j2) = sites
+            phi[i1][j1], phi[i2][j2] = apply_two_site_exact(ket[i1][j1], ket[i2][j2], op, i2 == i1 + 1)
+        per_term.append(_overlap_ratio(phi, ket, m, p, q, seed, ln, ph))
     per_term = np.array(per_term)
     return per_term.sum(), per_term
+
+
+def trotter_state(ket, gates):
+    """phi = prod_j G_j psi, gates applied exactly in the order given; gates is
+    a list of (((i1, j1), (i2, j2)), G[P,Q,p,q]) on nearest neighbours."""
+    phi = [[t for t in row] for row in ket]
+    for ((i1, j1), (i2, j2)), G in gates:
+        phi[i1][j1], phi[i2][j2] = apply_two_site_exact(phi[i1][j1], phi[i2][j2], G, i2 == i1 + 1)
+    return phi
+
+
+def trotter_expectation(ket, gates, tau, m, p, q, seed):
+    """Eq. 6: (<psi|phi> / <psi|psi> - 1) / tau with phi = trotter_state(ket,
+    gates) (gates e^{tau H_j}).  Returns (estimate, <psi|phi> / <psi|psi>)."""
+    ln, ph = peps_norm(ket, m, p, q, seed)
+    ratio = _overlap_ratio(trotter_state(ket, gates), ket, m, p, q, seed, ln, ph)
+    return (ratio - 1.0) / tau, ratio

@@ -12,7 +12,8 @@ from ._ffi import (  # noqa: F401
 )
 from .api import (  # noqa: F401
     einsumsvd, einsumsvd_zipup, einsumsvd_pair, einsumsvd_pair_backward, einsumsvd_pair_autograd,
-    peps_norm, peps_amplitude, peps_amplitudes, boundary_contract_row, peps_energy, peps_norm_backward, peps_energy_backward,
+    peps_norm, peps_amplitude, peps_amplitudes, boundary_contract_row, peps_energy, peps_energy_uncached,
+    peps_trotter_expectation, peps_norm_backward, peps_energy_backward,
     peps_energy_autograd,
     apply_two_site_gate, ItePlan, get_info, workspace_peak, sketch, make_opts, profile_start, profile_stop,
     profile_read, profile_by_shape, autotune_enable, autotune_export, autotune_import, autotune_save,

@@ -96,6 +96,10 @@ _SIGS = {
                                         _DP, _DP]),
     "hpeps_peps_energy": (C.c_int, [_P, C.POINTER(Peps), C.c_int32, C.POINTER(C.c_int32),
                                     C.POINTER(C.c_int32), _DP, _I64P, C.POINTER(EsvdOpts), _DP, _DP]),
+    "hpeps_peps_energy_uncached": (C.c_int, [_P, C.POINTER(Peps), C.c_int32, C.POINTER(C.c_int32),
+                                             C.POINTER(C.c_int32), _DP, _I64P, C.POINTER(EsvdOpts), _DP, _DP]),
+    "hpeps_peps_trotter_expectation": (C.c_int, [_P, C.POINTER(Peps), C.c_int32, C.POINTER(C.c_int32), _DP,
+                                                 C.c_double, C.POINTER(EsvdOpts), _DP, _DP]),
     "hpeps_peps_norm_backward": (C.c_int, [_P, C.POINTER(Peps), C.POINTER(EsvdOpts), C.c_double,
                                            C.POINTER(C.c_void_p), _DP]),
     "hpeps_peps_energy_backward": (C.c_int, [_P, C.POINTER(Peps), C.c_int32, C.POINTER(C.c_int32),

@@ -460,6 +460,42 @@ def peps_energy(ctx, ket, terms, *, rank, oversample=0, power_iters=0, seed=0, p
     return complex(e[0], e[1]), [complex(per[2 * t], per[2 * t + 1]) for t in range(n)]
 
 
+def peps_energy_uncached(ctx, ket, terms, *, rank, oversample=0, power_iters=0, seed=0):
+    """Eq. 5 without cached environments: every term <psi|H_t psi> / <psi|psi> is its
+    own boundary contraction of the exactly applied H_t psi.  Same terms and
+    returns as peps_energy."""
+    keep = []
+    dt = _dtype_code(ket[0][0])
+    pk = _peps_struct(ket, dt, keep)
+    n, ns, st, offs, ops = _terms_arrays(terms)
+    o = make_opts(rank, oversample, power_iters, "f64", seed, 0)
+    e = (C.c_double * 2)()
+    per = (C.c_double * (2 * max(n, 1)))()
+    ctx.sync_stream()
+    ctx.check(ctx.lib.hpeps_peps_energy_uncached(ctx.h, C.byref(pk), n, ns, st,
+                                                 ops.ctypes.data_as(C.POINTER(C.c_double)), offs,
+                                                 C.byref(o), e, per))
+    return complex(e[0], e[1]), [complex(per[2 * t], per[2 * t + 1]) for t in range(n)]
+
+
+def peps_trotter_expectation(ctx, ket, gates, tau, *, rank, oversample=0, power_iters=0, seed=0):
+    """Eq. 6: (<psi| prod_j G_j |psi> / <psi|psi> - 1) / tau with gates
+    [((i1, j1), (i2, j2)), G] (G = e^{tau H_j} as [d,d,d,d], applied exactly in
+    the order given).  Returns (estimate, overlap ratio), both complex."""
+    keep = []
+    dt = _dtype_code(ket[0][0])
+    pk = _peps_struct(ket, dt, keep)
+    n, _, st, _, ops = _terms_arrays(gates)
+    o = make_opts(rank, oversample, power_iters, "f64", seed, 0)
+    est = (C.c_double * 2)()
+    rat = (C.c_double * 2)()
+    ctx.sync_stream()
+    ctx.check(ctx.lib.hpeps_peps_trotter_expectation(ctx.h, C.byref(pk), n, st,
+                                                     ops.ctypes.data_as(C.POINTER(C.c_double)), float(tau),
+                                                     C.byref(o), est, rat))
+    return complex(est[0], est[1]), complex(rat[0], rat[1])
+
+
 def _grad_buffers(ket):
     torch = _torch()
     grads = [[torch.empty_like(t) for t in row] for row in ket]

@@ -554,6 +554,212 @@ void check_energy_args(const hpeps_esvd_opts* opts, int32_t n_terms, const int32
 }
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// Expectation values by whole contractions: Eq. 5 term by term without the
+// cached environments, and the Trotter-Taylor estimate of Eq. 6.  Operators
+// are applied exactly to the ket: a one-site operator on its site's physical
+// leg; a two-site operator G[P,Q,p,q] (out1, out2, in1, in2) by the
+// elementary split G = sum_{Q,q} G[:,Q,:,q] (x) |Q><q|: site 1 takes
+// G[:,Q,:,q], site 2 takes |Q><q|, and (Q, q) is appended to their shared
+// bond (index (b, Q, q) row-major, the bond grows from D to D d^2).  The bra
+// (the original state) is zero-padded to the grown bonds, which does not
+// change <psi|phi>.
+namespace hp {
+namespace {
+
+__global__ void pad_kernel(const double* src, long long s0, long long s1, long long s2, long long s3,
+                           long long s4, long long t1, long long t2, long long t3, long long t4, long long total,
+                           int es, double* dst) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= total) return;
+  long long r = e;
+  const long long a4 = r % t4; r /= t4;
+  const long long a3 = r % t3; r /= t3;
+  const long long a2 = r % t2; r /= t2;
+  const long long a1 = r % t1; r /= t1;
+  const long long a0 = r;
+  const bool in = a0 < s0 && a1 < s1 && a2 < s2 && a3 < s3 && a4 < s4;
+  const long long si = in ? (((a0 * s1 + a1) * s2 + a2) * s3 + a3) * s4 + a4 : 0;
+  for (int q = 0; q < es; ++q) dst[e * es + q] = in ? src[si * es + q] : 0.0;
+}
+
+// T zero-padded to dims (every leg at least as long as T's), in the workspace.
+DevTensor pad_site(Ctx& c, bool cplx, const DevTensor& T, const std::vector<int64_t>& dims) {
+  HP_REQUIRE(T.dims.size() == 5 && dims.size() == 5, HPEPS_ERR_SHAPE, "sites have five legs");
+  for (int q = 0; q < 5; ++q) HP_REQUIRE(dims[q] >= T.dims[q], HPEPS_ERR_SHAPE, "padding cannot shrink a leg");
+  DevTensor o;
+  o.dims = dims;
+  const long long total = o.size();
+  o.p = c.ws<double>(total * (cplx ? 2 : 1));
+  pad_kernel<<<cdiv(total, 256), 256, 0, c.stream>>>((const double*)T.p, T.dims[0], T.dims[1], T.dims[2],
+                                                      T.dims[3], T.dims[4], dims[1], dims[2], dims[3], dims[4],
+                                                      total, cplx ? 2 : 1, (double*)o.p);
+  HP_CHECK_HIP(hipGetLastError());
+  return o;
+}
+
+// A host operator (complex128 pairs, n entries) in the lattice's dtype on the
+// device; a real lattice takes real operators only.
+double* upload_op(Ctx& c, bool cplx, const double* op, int64_t n) {
+  double* dev = c.ws<double>(n * (cplx ? 2 : 1));
+  if (cplx) {
+    HP_CHECK_HIP(hipMemcpyAsync(dev, op, 2 * n * sizeof(double), hipMemcpyHostToDevice, c.stream));
+    return dev;
+  }
+  std::vector<double> re(n);
+  for (int64_t i = 0; i < n; ++i) {
+    HP_REQUIRE(op[2 * i + 1] == 0.0, HPEPS_ERR_DTYPE, "a complex operator needs a complex128 PEPS");
+    re[i] = op[2 * i];
+  }
+  HP_CHECK_HIP(hipMemcpyAsync(dev, re.data(), n * sizeof(double), hipMemcpyHostToDevice, c.stream));
+  HP_CHECK_HIP(hipStreamSynchronize(c.stream));  // re is released on return
+  return dev;
+}
+
+DevTensor apply_one(Ctx& c, bool cplx, const DevTensor& T, const double* O, int d) {
+  DevTensor o;
+  o.dims = T.dims;
+  o.p = c.ws<double>(o.size() * (cplx ? 2 : 1));
+  contract2(c, cplx, tview_rm(T.p, "udlrp", T.dims), tview_rm(O, "Pp", {d, d}), "udlrP", o.p, o.size());
+  return o;
+}
+
+// Exact two-site application (elementary split); E[w,Q,q,X] =
+// delta(w, q) delta(Q, X) (the d^2 x d^2 identity), so that site 2 becomes
+// sum_w T[.., w] E[w,Q,q,X] = delta(Q, X) T[.., q].
+void apply_two(Ctx& c, bool cplx, DevTensor& S, DevTensor& T, bool vertical, const double* G, const double* E,
+               int d) {
+  const TView g = tview_rm(G, "PQpq", {d, d, d, d});
+  const TView e = tview_rm(E, "wQqX", {d, d, d, d});
+  const int64_t dd = (int64_t)d * d;
+  DevTensor S2, T2;
+  if (vertical) {
+    S2.dims = {S.dims[0], S.dims[1] * dd, S.dims[2], S.dims[3], d};
+    T2.dims = {T.dims[0] * dd, T.dims[1], T.dims[2], T.dims[3], d};
+  } else {
+    S2.dims = {S.dims[0], S.dims[1], S.dims[2], S.dims[3] * dd, d};
+    T2.dims = {T.dims[0], T.dims[1], T.dims[2] * dd, T.dims[3], d};
+  }
+  S2.p = c.ws<double>(S2.size() * (cplx ? 2 : 1));
+  T2.p = c.ws<double>(T2.size() * (cplx ? 2 : 1));
+  contract2(c, cplx, tview_rm(S.p, "udlrp", S.dims), g, vertical ? "udQqlrP" : "udlrQqP", S2.p, S2.size());
+  contract2(c, cplx, tview_rm(T.p, "udlrw", T.dims), e, vertical ? "uQqdlrX" : "udlQqrX", T2.p, T2.size());
+  S = S2;
+  T = T2;
+}
+
+// <psi|phi> / <psi|psi> from two norm results (log, phase re, im).
+void ratio_of(const double* num, const double* den, double* out) {
+  const double m = std::exp(num[0] - den[0]);
+  // (a / b) with unit-modulus b: a * conj(b)
+  out[0] = m * (num[1] * den[1] + num[2] * den[2]);
+  out[1] = m * (num[2] * den[1] - num[1] * den[2]);
+}
+
+void read3(Ctx& c, const double* dev, double* h) {
+  HP_CHECK_HIP(hipMemcpyAsync(h, dev, 3 * sizeof(double), hipMemcpyDeviceToHost, c.stream));
+  HP_CHECK_HIP(hipStreamSynchronize(c.stream));
+  HP_REQUIRE(std::isfinite(h[0]) && std::isfinite(h[1]) && std::isfinite(h[2]), HPEPS_ERR_NUMERIC,
+             "non-finite overlap");
+}
+
+}  // namespace
+}  // namespace hp
+
+extern "C" hpeps_status hpeps_peps_energy_uncached(hpeps_ctx* ctx, const hpeps_peps* ket, int32_t n_terms,
+                                                   const int32_t* nsites, const int32_t* sites, const double* ops,
+                                                   const int64_t* op_offset, const hpeps_esvd_opts* opts,
+                                                   double* energy, double* per_term) {
+  using namespace hp;
+  return guard_e(ctx, [&](Ctx& c) {
+    check_energy_args(opts, n_terms, nsites, sites, ops, op_offset, energy);
+    const Lattice K = lattice_from_abi(ket);
+    check_terms(K, n_terms, nsites, sites, op_offset);
+    const bool cplx = K.cplx;
+    const int d = (int)K.sites[0].dims[4];
+    double* dev = c.ws<double>(3);
+    norm_lattices(c, K, K, *opts, dev);
+    double h0[3];
+    read3(c, dev, h0);
+    double* E = c.ws<double>((int64_t)d * d * d * d * (cplx ? 2 : 1));
+    fill_identity(c, E, (int64_t)d * d, 1, cplx);
+    double er = 0, ei = 0;
+    for (int t = 0; t < n_terms; ++t) {
+      WsScope scope(c);
+      const int* s = sites + 4 * t;
+      Lattice phi = K, bra = K;
+      const size_t a = (size_t)s[0] * K.ncol + s[1];
+      if (nsites[t] == 1) {
+        phi.sites[a] = apply_one(c, cplx, K.sites[a], upload_op(c, cplx, ops + 2 * op_offset[t], (int64_t)d * d), d);
+      } else {
+        const size_t b = (size_t)s[2] * K.ncol + s[3];
+        apply_two(c, cplx, phi.sites[a], phi.sites[b], s[2] == s[0] + 1,
+                  upload_op(c, cplx, ops + 2 * op_offset[t], (int64_t)d * d * d * d), E, d);
+        bra.sites[a] = pad_site(c, cplx, K.sites[a], phi.sites[a].dims);
+        bra.sites[b] = pad_site(c, cplx, K.sites[b], phi.sites[b].dims);
+      }
+      double* dv = c.ws<double>(3);
+      norm_lattices(c, phi, bra, *opts, dv);
+      double h[3], v[2];
+      read3(c, dv, h);
+      ratio_of(h, h0, v);
+      er += v[0];
+      ei += v[1];
+      if (per_term) {
+        per_term[2 * t] = v[0];
+        per_term[2 * t + 1] = v[1];
+      }
+    }
+    energy[0] = er;
+    energy[1] = ei;
+  });
+}
+
+extern "C" hpeps_status hpeps_peps_trotter_expectation(hpeps_ctx* ctx, const hpeps_peps* ket, int32_t n_gates,
+                                                       const int32_t* sites, const double* gates, double tau,
+                                                       const hpeps_esvd_opts* opts, double* estimate,
+                                                       double* ratio) {
+  using namespace hp;
+  return guard_e(ctx, [&](Ctx& c) {
+    HP_REQUIRE(opts && opts->rank >= 1 && opts->oversample >= 0 && opts->power_iters >= 0, HPEPS_ERR_INVALID_ARG,
+               "bad einsumsvd options");
+    HP_REQUIRE(n_gates >= 1 && sites && gates && estimate, HPEPS_ERR_INVALID_ARG, "null argument");
+    HP_REQUIRE(tau != 0.0 && std::isfinite(tau), HPEPS_ERR_INVALID_ARG, "tau must be finite and nonzero");
+    const Lattice K = lattice_from_abi(ket);
+    const bool cplx = K.cplx;
+    const int d = (int)K.sites[0].dims[4];
+    const int64_t g4 = (int64_t)d * d * d * d;
+    std::vector<int32_t> two(n_gates, 2);
+    std::vector<int64_t> off(n_gates);
+    for (int t = 0; t < n_gates; ++t) off[t] = t * g4;
+    check_terms(K, n_gates, two.data(), sites, off.data());
+    double* E = c.ws<double>((int64_t)d * d * d * d * (cplx ? 2 : 1));
+    fill_identity(c, E, (int64_t)d * d, 1, cplx);
+    // phi = prod_j G_j psi, gates in the order given
+    Lattice phi = K;
+    for (int t = 0; t < n_gates; ++t) {
+      const int* s = sites + 4 * t;
+      apply_two(c, cplx, phi.sites[(size_t)s[0] * K.ncol + s[1]], phi.sites[(size_t)s[2] * K.ncol + s[3]],
+                s[2] == s[0] + 1, upload_op(c, cplx, gates + 2 * off[t], g4), E, d);
+    }
+    Lattice bra = K;
+    for (size_t q = 0; q < K.sites.size(); ++q) bra.sites[q] = pad_site(c, cplx, K.sites[q], phi.sites[q].dims);
+    double* dv = c.ws<double>(6);
+    norm_lattices(c, phi, bra, *opts, dv);
+    norm_lattices(c, K, K, *opts, dv + 3);
+    double h1[3], h0[3], r[2];
+    read3(c, dv, h1);
+    read3(c, dv + 3, h0);
+    ratio_of(h1, h0, r);
+    estimate[0] = (r[0] - 1.0) / tau;
+    estimate[1] = r[1] / tau;
+    if (ratio) {
+      ratio[0] = r[0];
+      ratio[1] = r[1];
+    }
+  });
+}
+
 extern "C" hpeps_status hpeps_peps_energy(hpeps_ctx* ctx, const hpeps_peps* ket, int32_t n_terms,
                                           const int32_t* nsites, const int32_t* sites, const double* ops,
                                           const int64_t* op_offset, const hpeps_esvd_opts* opts, double* energy,

@@ -103,6 +103,10 @@ void write_site_grads(Ctx& ctx, const Tape& tape, const Lattice& K, void* const*
 // logarithms of the norms are added to log_dev.
 Lattice normalized_copy(Ctx& ctx, const Lattice& L, double* log_dev);
 
+// <bra|ket> by the boundary MPS (the lattices must have equal shapes):
+// dev[0] = log scale, dev[1..2] = unit-modulus phase (device, 3 doubles).
+void norm_lattices(Ctx& c, const Lattice& ket, const Lattice& bra, const hpeps_esvd_opts& o, double* dev);
+
 // Boundary pass from one side storing every intermediate boundary MPS:
 // envs[t] = boundary after the first t+1 rows seen from `side`.
 void boundary_pass(Ctx& ctx, const Lattice& ket, const Lattice& bra, Side side,

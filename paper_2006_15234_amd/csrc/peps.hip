@@ -587,6 +587,12 @@ void norm_run(hp::Ctx& c, const hp::Lattice& K, const hp::Lattice& B, const hpep
 }
 }  // namespace
 
+namespace hp {
+void norm_lattices(Ctx& c, const Lattice& ket, const Lattice& bra, const hpeps_esvd_opts& o, double* dev) {
+  norm_run(c, ket, bra, o, dev, nullptr);
+}
+}  // namespace hp
+
 extern "C" {
 
 hpeps_status hpeps_boundary_contract_row(hpeps_ctx* ctx, const hpeps_bmps* bnd, const hpeps_peps* ket,

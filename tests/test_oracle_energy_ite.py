@@ -172,3 +172,66 @@ def test_ite_bond_growth_and_truncation():
             assert max(T.shape[:4]) <= 3
     for s in spectra:
         assert np.isclose(np.linalg.norm(s), 1.0) and np.all(np.diff(s) <= 1e-15)
+
+
+@pytest.mark.parametrize("vertical", [False, True])
+def test_exact_two_site_application_matches_state_vector(vertical):
+    """The elementary split applies G exactly: the state vector of the updated
+    PEPS is G applied to the state vector (random complex G, both orientations)."""
+    peps = synth.random_peps(3, 3, D=2, seed=4, complex_=True)
+    rng = np.random.default_rng(6)
+    G = rng.standard_normal((2, 2, 2, 2)) + 1j * rng.standard_normal((2, 2, 2, 2))
+    (i1, j1), (i2, j2) = ((1, 1), (2, 1)) if vertical else ((1, 0), (1, 1))
+    mod = [[t for t in row] for row in peps]
+    mod[i1][j1], mod[i2][j2] = energy.apply_two_site_exact(peps[i1][j1], peps[i2][j2], G, vertical)
+    assert mod[i1][j1].shape[1 if vertical else 3] == 8
+    ref = sv.apply_two_site(sv.peps_to_statevector(peps), G, i1 * 3 + j1, i2 * 3 + j2)
+    assert np.allclose(sv.peps_to_statevector(mod), ref, rtol=0, atol=1e-13 * np.abs(ref).max())
+
+
+def test_uncached_energy_equals_brute_force():
+    peps = synth.random_peps(2, 3, D=2, seed=12, complex_=True)
+    terms = mixed_terms(2, 3, seed=5)
+    psi = sv.peps_to_statevector(peps)
+    ref = [sv.expectation(psi, [t], 3) for t in terms]
+    _, per = energy.peps_energy_uncached(peps, terms, BIG_M, 0, 0, 0)
+    assert np.allclose(per, ref, rtol=1e-10, atol=1e-11)
+
+
+def _trotter_reference(peps, gates):
+    psi = sv.peps_to_statevector(peps)
+    phi = psi
+    ncol = len(peps[0])
+    for ((i1, j1), (i2, j2)), G in gates:
+        phi = sv.apply_two_site(phi, G, i1 * ncol + j1, i2 * ncol + j2)
+    return np.vdot(psi, phi) / np.vdot(psi, psi)
+
+
+@pytest.mark.parametrize("shape", [(2, 3), (3, 2)])
+def test_trotter_expectation_exact_regime(shape):
+    """Eq. 6 with exact contractions equals the same Trotter product on the state
+    vector: <psi| prod_j e^{tau H_j} |psi> / <psi|psi> at 1e-12."""
+    nrow, ncol = shape
+    peps = synth.random_peps(nrow, ncol, D=2, seed=nrow + 7 * ncol, complex_=True)
+    tau = 0.05
+    gates = [((s1, s2), synth.bond_gate(H, -tau)) for (s1, s2), H in
+             synth.tfi_bond_hamiltonians(nrow, ncol, 1.0, 3.0).items()]
+    est, ratio = energy.trotter_expectation(peps, gates, tau, BIG_M, 0, 0, 0)
+    ref = _trotter_reference(peps, gates)
+    assert abs(ratio - ref) < 1e-12 * abs(ref)
+    assert abs(est - (ref - 1) / tau) < 1e-10
+
+
+def test_trotter_expectation_is_first_order_in_tau():
+    """The estimate approaches <H> linearly in tau: halving tau halves the error."""
+    nrow, ncol = 2, 3
+    peps = synth.random_peps(nrow, ncol, D=2, seed=3)
+    hams = synth.tfi_bond_hamiltonians(nrow, ncol, 1.0, 3.0)
+    exact = sv.expectation(sv.peps_to_statevector(peps), [((s1, s2), H) for (s1, s2), H in hams.items()],
+                           ncol).real
+    errs = []
+    for tau in (0.02, 0.01, 0.005):
+        gates = [((s1, s2), synth.bond_gate(H, -tau)) for (s1, s2), H in hams.items()]
+        est, _ = energy.trotter_expectation(peps, gates, tau, BIG_M, 0, 0, 0)
+        errs.append(abs(est.real - exact))
+    assert 1.7 < errs[0] / errs[1] < 2.3 and 1.7 < errs[1] / errs[2] < 2.3
