@@ -517,6 +517,86 @@ def caching(hp, sizes=(6, 12), D=4, m=16, p=4, q=1, tau=0.01, trotter_D=2):
                         f"m={m} p={p} q={q}", "by_size": out, "trotter": trot}
 
 
+def _j1j2_circuit(synth, nrow, ncol, tau, h):
+    """One Trotter step of exp(-tau H) for the J1-J2 model as a gate list: the
+    nearest-neighbour (J1) bonds, the diagonal (J2) bonds (run by the library
+    as SWAP chains) and the one-site fields."""
+    import numpy as np
+    ops, g2, g1 = [], [], []
+    for sites, op in synth.j1j2_terms(nrow, ncol, h=h):
+        if len(sites) == 2:
+            g2.append(np.real(synth.bond_gate(op, tau)))
+            ops.append((2, sites[0], sites[1], len(g2) - 1))
+        else:
+            w, V = np.linalg.eigh(op)
+            g1.append(np.real((V * np.exp(-tau * w)) @ V.conj().T))
+            ops.append((1, sites[0], len(g1) - 1))
+    return ops, np.array(g2), np.array(g1)
+
+
+def j1j2_vqe(hp, n=4, ranks=(2, 3, 4), tau=0.05, sweeps=150, vqe_layers=3, vqe_rank=4, vqe_m=16, vqe_evals=5):
+    """The application workloads of Sec. VI-D on one GPU.  ITE: the n x n J1-J2
+    model of Eq. 7 (J1 = 1, J2 = 0.5, fields h_x = h_z = 0.2; h_y = 0 keeps the
+    gates real) from a product state, `sweeps` Trotter steps of tau with
+    evolution bond r, the diagonal bonds as SWAP chains, one captured graph per
+    plan; then the energy (all J1, J2 and field terms) by the cached
+    contraction with m = r and m = r^2.  VQE: the R_y + CNOT ansatz with
+    `vqe_layers` layers (bond cap vqe_rank) applied to |0...0> and the J1-J2
+    energy with all fields h = 0.2 (m = vqe_m) for random angles: the time of
+    one energy evaluation of the optimiser loop."""
+    import numpy as np
+    import torch
+
+    import synth
+    ctx = hp.Context(0)
+    terms_ite = synth.j1j2_terms(n, n, h=(0.2, 0.0, 0.2))
+    ops, g2, g1 = _j1j2_circuit(synth, n, n, tau, (0.2, 0.0, 0.2))
+    ite_rows = []
+    for r in ranks:
+        init = [[torch.from_numpy(np.ascontiguousarray(t)).cuda() for t in row]
+                for row in synth.product_state_peps(n, n, seed=1)]
+        plan = hp.CircuitPlan(ctx, init, ops, g2, g1, r)
+        plan.run(1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plan.run(sweeps - 1)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        state = plan.state()
+        row = {"r": r, "ms_per_sweep": round(dt * 1e3 / (sweeps - 1), 3), "layers": plan.n_layers,
+               "updates_per_sweep": plan.n_bonds}
+        for m in sorted({r, r * r}):
+            e, _ = hp.peps_energy(ctx, state, terms_ite, rank=m, oversample=4, power_iters=1)
+            row[f"energy_per_site_m{m}"] = e.real / (n * n)
+        plan.close()
+        ite_rows.append(row)
+    # VQE ansatz evaluations
+    terms = synth.j1j2_terms(n, n)
+    vops = synth.vqe_ansatz_ops(n, n, vqe_layers)
+    zero = [[torch.tensor([1.0, 0.0], dtype=torch.float64, device="cuda").reshape(1, 1, 1, 1, 2)
+             for _ in range(n)] for _ in range(n)]
+    rng = np.random.default_rng(0)
+    times, energies = [], []
+    for it in range(vqe_evals + 1):
+        theta = rng.uniform(-np.pi, np.pi, n * n * vqe_layers)
+        g1v = np.array([synth.ry_gate(t) for t in theta])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plan = hp.CircuitPlan(ctx, zero, vops, synth.CNOT[None], g1v, vqe_rank)
+        plan.run(1)
+        e, _ = hp.peps_energy(ctx, plan.state(), terms, rank=vqe_m, oversample=4, power_iters=1)
+        torch.cuda.synchronize()
+        if it > 0:        # the first evaluation tunes and grows the workspace
+            times.append(time.perf_counter() - t0)
+            energies.append(e.real / (n * n))
+        plan.close()
+    return {"workload": f"{n}x{n} J1-J2 (J1=1, J2=0.5): ITE tau={tau}, {sweeps} sweeps, fields h_x=h_z=0.2; "
+                        f"VQE R_y+CNOT ansatz, {vqe_layers} layers, bond cap {vqe_rank}, fields 0.2, m={vqe_m}",
+            "ite": ite_rows,
+            "vqe": {"s_per_energy_evaluation": round(float(np.median(times)), 4),
+                    "energies_per_site": [round(x, 6) for x in energies]}}
+
+
 def c4_ite(hp, sweeps, n=16, D=8, d=2, tau=0.01, J=1.0, hfield=3.0, m=32, p=8, q=1, plain_sweeps=5):
     """Batched imaginary-time evolution of an n x n transverse-field Ising PEPS: TEBD sweeps
     of QR-SVD updates over the four layers of non-overlapping bonds (bond dimensions grow
@@ -603,6 +683,10 @@ def main():
                     help="leave the cached vs uncached energy block (6x6 and 12x12, D=4) out of the full run")
     ap.add_argument("--caching-only", action="store_true",
                     help="run only the cached vs uncached energy block and print its JSON")
+    ap.add_argument("--no-j1j2", action="store_true",
+                    help="leave the J1-J2 ITE / VQE ansatz block out of the full run")
+    ap.add_argument("--j1j2-only", action="store_true",
+                    help="run only the J1-J2 ITE / VQE ansatz block and print its JSON")
     ap.add_argument("--c5", type=int, default=2, metavar="REPS",
                     help="time the 8x8 D=4 complex energy gradient this many times (0 skips)")
     ap.add_argument("--c3", action="store_true",
@@ -632,6 +716,10 @@ def main():
 
     import paper_2006_15234_amd as hp
     import synth
+
+    if args.j1j2_only:
+        print(json.dumps(j1j2_vqe(hp)))
+        return
 
     if args.caching_only:
         print(json.dumps(caching(hp)))
@@ -779,6 +867,8 @@ def main():
         res["bmps_vs_ibmps"] = bmps_vs_ibmps(hp, args.bmps)
     if not args.no_caching:
         res["caching"] = caching(hp)
+    if not args.no_j1j2:
+        res["j1j2"] = j1j2_vqe(hp)
     if args.c5 > 0:
         res["c5_gradient"] = c5_gradient(hp, args.c5)
     if args.d8 > 0:

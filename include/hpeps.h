@@ -422,11 +422,14 @@ hpeps_status hpeps_peps_amplitudes(hpeps_ctx* ctx, const hpeps_peps* ket, int64_
 /* ---- peps_energy (Eq. 5 with cached environments, Sec. IV-B) ------------
  * Terms: n_terms entries; term t acts on nsites[t] (1 or 2) sites given by
  * sites[4t .. 4t+3] = {i1, j1, i2, j2} (nearest neighbours, site 1 left of or
- * above site 2); its operator is ops + op_offset[t] (host memory, complex128
- * pairs, [2,2] or [2,2,2,2]).  Every term value is strip(term)/strip(id),
- * where the strip is the exact contraction of the cached top environment,
- * the one (two, for vertical terms) PEPS rows of the term and the cached
- * bottom environment.  Environments come from two full boundary passes
+ * above site 2, or diagonal neighbours i2 = i1 + 1, j2 = j1 +- 1: the J2
+ * pairs of Eq. 7); its operator is ops + op_offset[t] (host memory,
+ * complex128 pairs, [2,2] or [2,2,2,2]).  Every term value is
+ * strip(term)/strip(id), where the strip is the exact contraction of the
+ * cached top environment, the one (two, for vertical and diagonal terms) PEPS
+ * rows of the term and the cached bottom environment; a diagonal term spans
+ * two columns of its strip.  (hpeps_peps_energy_uncached and
+ * hpeps_peps_energy_backward take nearest-neighbour terms only.)  Environments come from two full boundary passes
  * (top-down stream ids 1 + (i*ncol+j), bottom-up 1 + ((nrow+i)*ncol+j)).
  * Outputs (host): energy[2] = {re, im} of the sum, per_term[2*n_terms]
  * (may be NULL).  Synchronises. */
@@ -511,6 +514,14 @@ hpeps_status hpeps_peps_energy_backward(hpeps_ctx* ctx, const hpeps_peps* ket, i
  * peps->shapes (which must then be writable: pass a non-const array).
  * sigma_out (device, may be NULL) receives the D' kept values.
  * Synchronises (returns the new bond on the host). */
+/* ---- one-site operator (Eq. 3) --------------------------------------------
+ * out[u,d,l,r,P] = sum_p G[P,p] site[u,d,l,r,p] for one site tensor of
+ * shape dims[5] (row-major, device, dtype HPEPS_F64 or HPEPS_C128) and the
+ * device d x d gate G (same dtype); out (device, same shape) may alias site.
+ * Asynchronous on the context stream. */
+hpeps_status hpeps_apply_one_site_gate(hpeps_ctx* ctx, hpeps_dtype dtype, const int64_t* dims,
+                                       const void* site, const void* G, void* out);
+
 hpeps_status hpeps_apply_two_site_gate(hpeps_ctx* ctx, hpeps_peps* peps,
                                        const int64_t* capacity, int32_t i, int32_t j,
                                        int32_t axis, const void* G, int64_t max_rank,
@@ -554,8 +565,33 @@ hpeps_status hpeps_ite_plan_create(hpeps_ctx* ctx, const hpeps_peps* init,
                                    int32_t n_gates, const void* gates,
                                    const int32_t* bond_gate, int64_t max_rank,
                                    hpeps_ite_plan** out);
-/* Runs n_sweeps sweeps: use_graph = 1 replays the captured graph of the four
- * layer launches, 0 issues the four layer launches directly, 2 is the plain
+/* A plan over an arbitrary gate list (the TEBD sweep of a Hamiltonian with
+ * further-neighbour terms, such as the diagonal J2 bonds of Eq. 7, or the
+ * layers of a quantum circuit): n_ops operations, ops[6*t] = (kind, i1, j1,
+ * i2, j2, gate): kind 2 applies the two-site gate gates2[gate] ([d,d,d,d],
+ * out1, out2, in1, in2, FP64 host) to sites (i1, j1), (i2, j2) by the QR-SVD
+ * update of Alg. 1 with bonds truncated to max_rank; kind 1 applies the
+ * one-site gate gates1[gate] ([d,d], out, in, FP64 host) to site (i1, j1) as
+ * in Eq. 3 (i2, j2 ignored).  Two-site gates on sites that are not nearest
+ * neighbours run as SWAP chains (Sec. II-C): site 2's state is moved by SWAP
+ * gates along its row to site 1's column, then along that column until it
+ * neighbours site 1, the gate acts there (transposed when site 2 ends up
+ * left of or above site 1), and the SWAPs are undone in reverse order; every
+ * SWAP is itself a truncating QR-SVD update.  The operations are packed into
+ * layers (each one in the first layer after the last one touching its
+ * sites; one-site and two-site operations in separate layers), one launch
+ * per layer, and a sweep runs the whole list; hpeps_ite_run,
+ * hpeps_ite_spectra (two-site updates in layer order, SWAPs included),
+ * hpeps_ite_get_state and hpeps_ite_plan_destroy take the plan.  d <= 8. */
+hpeps_status hpeps_circuit_plan_create(hpeps_ctx* ctx, const hpeps_peps* init, int32_t n_gates2,
+                                       const double* gates2, int32_t n_gates1, const double* gates1,
+                                       int32_t n_ops, const int32_t* ops, int64_t max_rank,
+                                       hpeps_ite_plan** out);
+/* Number of layers of a plan's sweep and of its two-site updates (the rows
+ * of hpeps_ite_spectra). */
+hpeps_status hpeps_ite_plan_layers(hpeps_ite_plan* plan, int32_t* n_layers, int32_t* n_bonds);
+/* Runs n_sweeps sweeps: use_graph = 1 replays the captured graph of the
+ * layer launches, 0 issues the layer launches directly, 2 is the plain
  * form with one launch per bond (no graph; the baseline of the batched
  * forms).  All three compute the same updates. */
 hpeps_status hpeps_ite_run(hpeps_ite_plan* plan, int32_t n_sweeps, int32_t use_graph);

@@ -23,8 +23,10 @@ given (every bond a gate touches grows by d^2) and <psi|phi> contracted
 against the zero-padded psi.
 
 A term is (sites, op): sites a tuple of (i, j); op is [2,2] (out, in) for one
-site or [2,2,2,2] (out1, out2, in1, in2) for two nearest-neighbour sites with
-site 1 left of / above site 2.
+site or [2,2,2,2] (out1, out2, in1, in2) for two sites with site 1 left of /
+above site 2: nearest neighbours, or (cached path only) diagonal neighbours
+(i, j), (i + 1, j +- 1), the J2 pairs of Eq. 7, evaluated on the four-row
+strip of their two rows over their two columns.
 """
 import numpy as np
 
@@ -137,6 +139,44 @@ def _pair_terms(top, row1, row2, bot, terms_here, d, dtype):
     return out
 
 
+def _diag_terms(top, row1, row2, bot, terms_here, d, dtype):
+    """Four-row strip for diagonal terms between two lattice rows: site 1 at
+    (i, j) and site 2 at (i + 1, j +- 1).  With op = sum_k A_k (x) B_k, A_k acts
+    in site 1's column and B_k in site 2's, both columns between the left and
+    right environments."""
+    n = len(row1)
+    I = np.eye(d, dtype=dtype)
+    one = np.ones((1,) * 6, dtype=dtype)
+    Ls = [one]
+    for j in range(n):
+        Ls.append(_norm(_col4(Ls[-1], top[j], row1[j], I, row1[j], row2[j], I, row2[j], bot[j])))
+    Rs = [one]
+    for j in reversed(range(n)):
+        Tp, T1, _, Bt = _mirror3(top[j], row1[j], row1[j], bot[j])
+        T2 = row2[j].transpose(0, 1, 3, 2, 4)
+        Rs.append(_norm(_col4(Rs[-1], Tp, T1, I, T1, T2, I, T2, Bt)))
+    Rs = Rs[::-1]
+
+    def two_columns(a, ops_a, ops_b):
+        X = _col4(Ls[a], top[a], row1[a], ops_a[0], row1[a], row2[a], ops_a[1], row2[a], bot[a])
+        X = _col4(X, top[a + 1], row1[a + 1], ops_b[0], row1[a + 1], row2[a + 1], ops_b[1], row2[a + 1], bot[a + 1])
+        return np.vdot(Rs[a + 2].conj(), X)
+
+    out = []
+    for sites, op in terms_here:
+        (_, j1), (_, j2) = sites
+        a = min(j1, j2)
+        num = 0.0
+        for A, B in operator_schmidt(op):
+            if j1 < j2:   # site 1 in column a (upper row), site 2 in column a + 1 (lower row)
+                num = num + two_columns(a, (A, I), (I, B))
+            else:         # site 2 in column a (lower row), site 1 in column a + 1 (upper row)
+                num = num + two_columns(a, (I, B), (A, I))
+        den = two_columns(a, (I, I), (I, I))
+        out.append((sites, num / den))
+    return out
+
+
 def peps_energy_cached(ket, terms, m, p, q, seed):
     """Returns (energy, per-term values in the order of ``terms``)."""
     nrow, ncol = len(ket), len(ket[0])
@@ -162,11 +202,17 @@ def peps_energy_cached(ket, terms, m, p, q, seed):
                 values[k] = v
     for i in range(nrow - 1):
         here = [(k, t) for k, t in enumerate(terms)
-                if len(t[0]) == 2 and t[0][0][0] == i and t[0][1][0] == i + 1]
+                if len(t[0]) == 2 and t[0][0][0] == i and t[0][1][0] == i + 1 and t[0][0][1] == t[0][1][1]]
         if here:
             res = _pair_terms(top_of(i), ket[i], ket[i + 1], bot_of(i + 1),
                               [t for _, t in here], d, dtype)
             for (k, _), (_, v) in zip(here, res):
+                values[k] = v
+        diag = [(k, t) for k, t in enumerate(terms)
+                if len(t[0]) == 2 and t[0][0][0] == i and t[0][1][0] == i + 1 and t[0][0][1] != t[0][1][1]]
+        if diag:
+            res = _diag_terms(top_of(i), ket[i], ket[i + 1], bot_of(i + 1), [t for _, t in diag], d, dtype)
+            for (k, _), (_, v) in zip(diag, res):
                 values[k] = v
     per_term = np.array([values[k] for k in range(len(terms))])
     return per_term.sum(), per_term

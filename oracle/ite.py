@@ -93,3 +93,84 @@ def ite(peps, layers, gates, Dmax, n_sweeps):
     for _ in range(n_sweeps):
         spectra = ite_sweep(peps, layers, gates, Dmax)
     return peps, spectra
+
+
+def swap_gate(d):
+    """SWAP[P, Q, p, q] = delta(P, q) delta(Q, p)."""
+    S = np.zeros((d, d, d, d))
+    for a in range(d):
+        for b in range(d):
+            S[a, b, b, a] = 1.0
+    return S
+
+
+def apply_one_site(T, O):
+    """Eq. 3: T'[u,d,l,r,P] = sum_p O[P,p] T[u,d,l,r,p]."""
+    return np.einsum("Pp,udlrp->udlrP", O, T)
+
+
+def _bond_update(peps, a, b, G, Dmax):
+    """QR-SVD update of the neighbouring sites a and b with G acting on (a, b)
+    in that order; the update itself takes the left / top site first, so G is
+    transposed when b is left of or above a."""
+    (ia, ja), (ib, jb) = a, b
+    if (ia, ja + 1) == (ib, jb) or (ia + 1, ja) == (ib, jb):
+        s1, s2, g = a, b, G
+    else:
+        assert (ib, jb + 1) == (ia, ja) or (ib + 1, jb) == (ia, ja), "sites are not neighbours"
+        s1, s2, g = b, a, G.transpose(1, 0, 3, 2)
+    axis = HORIZ if s1[0] == s2[0] else VERT
+    T1n, T2n, s = qr_svd_update(peps[s1[0]][s1[1]], peps[s2[0]][s2[1]], g, axis, Dmax)
+    peps[s1[0]][s1[1]], peps[s2[0]][s2[1]] = T1n, T2n
+    return s
+
+
+def swap_path(a, b):
+    """Positions of site b's state on its way next to site a (Sec. II-C: a chain
+    of SWAP gates on neighbouring sites): along b's row to a's column, then
+    along that column, stopping at the first position adjacent to a."""
+    (ia, ja), (ib, jb) = a, b
+    path = [(ib, jb)]
+    i, j = ib, jb
+    while abs(i - ia) + abs(j - ja) != 1:
+        if i != ia and j != ja:
+            j += 1 if j < ja else -1
+        elif i == ia:
+            j += 1 if j < ja else -1
+        else:
+            i += 1 if i < ia else -1
+        path.append((i, j))
+    return path
+
+
+def apply_gate_any(peps, a, b, G, Dmax):
+    """A two-site gate on any two sites, in place: non-neighbours by moving b's
+    state with SWAP gates (swap_path), applying G next to a, and moving it back
+    (the SWAPs undone in reverse order).  Every update truncates to Dmax.
+    Returns the kept singular values of every update in order."""
+    d = G.shape[0]
+    S = swap_gate(d)
+    path = swap_path(a, b)
+    spectra = []
+    for p, q in zip(path[:-1], path[1:]):
+        spectra.append(_bond_update(peps, p, q, S, Dmax))
+    spectra.append(_bond_update(peps, a, path[-1], G, Dmax))
+    for p, q in reversed(list(zip(path[:-1], path[1:]))):
+        spectra.append(_bond_update(peps, p, q, S, Dmax))
+    return spectra
+
+
+def run_circuit(peps, ops, gates2, gates1, Dmax):
+    """Applies a gate list in order: (2, a, b, g) the two-site gate gates2[g] on
+    sites a, b (apply_gate_any), (1, a, g) the one-site gate gates1[g] on site a
+    (Eq. 3).  Returns (new PEPS, kept singular values of every two-site update
+    in order)."""
+    peps = [[t.copy() for t in row] for row in peps]
+    spectra = []
+    for op in ops:
+        if op[0] == 1:
+            (i, j), g = op[1], op[2]
+            peps[i][j] = apply_one_site(peps[i][j], gates1[g])
+        else:
+            spectra += apply_gate_any(peps, op[1], op[2], gates2[op[3]], Dmax)
+    return peps, spectra

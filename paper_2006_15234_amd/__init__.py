@@ -15,7 +15,7 @@ from .api import (  # noqa: F401
     peps_norm, peps_amplitude, peps_amplitudes, boundary_contract_row, peps_energy, peps_energy_uncached,
     peps_trotter_expectation, peps_norm_backward, peps_energy_backward,
     peps_energy_autograd,
-    apply_two_site_gate, ItePlan, get_info, workspace_peak, sketch, make_opts, profile_start, profile_stop,
+    apply_one_site_gate, apply_two_site_gate, ItePlan, CircuitPlan, get_info, workspace_peak, sketch, make_opts, profile_start, profile_stop,
     profile_read, profile_by_shape, autotune_enable, autotune_export, autotune_import, autotune_save,
     autotune_load,
 )

@@ -111,6 +111,10 @@ _SIGS = {
                                             C.c_int32, _P, C.c_int64, _I64P, _P]),
     "hpeps_ite_plan_create": (C.c_int, [_P, C.POINTER(Peps), C.c_int32, _P, C.POINTER(C.c_int32),
                                         C.c_int64, C.POINTER(C.c_void_p)]),
+    "hpeps_circuit_plan_create": (C.c_int, [_P, C.POINTER(Peps), C.c_int32, _DP, C.c_int32, _DP, C.c_int32,
+                                            C.POINTER(C.c_int32), C.c_int64, C.POINTER(C.c_void_p)]),
+    "hpeps_ite_plan_layers": (C.c_int, [_P, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
+    "hpeps_apply_one_site_gate": (C.c_int, [_P, C.c_int, _I64P, _P, _P, _P]),
     "hpeps_ite_run": (C.c_int, [_P, C.c_int32, C.c_int32]),
     "hpeps_ite_get_state": (C.c_int, [_P, _I64P, C.POINTER(C.c_void_p)]),
     "hpeps_ite_spectra": (C.c_int, [_P, _P]),

@@ -566,6 +566,21 @@ def peps_norm_backward(ctx, ket, *, rank, oversample=0, power_iters=0, seed=0, b
     return ln.value, grads
 
 
+def apply_one_site_gate(ctx, sites, i, j, G):
+    """Eq. 3 on sites[i][j] (list of rows of device tensors [u,d,l,r,p]) with
+    the device d x d gate G (out, in); returns the updated site tensor (a new
+    device tensor; the others are unchanged)."""
+    torch = _torch()
+    T = sites[i][j].contiguous()
+    out = torch.empty_like(T)
+    Gd = G.contiguous().to(T.dtype)
+    dims = (C.c_int64 * 5)(*T.shape)
+    ctx.sync_stream()
+    ctx.check(ctx.lib.hpeps_apply_one_site_gate(ctx.h, _dtype_code(T), dims, _dev(T, "site"), _dev(Gd, "G"),
+                                                _dev(out, "out")))
+    return out
+
+
 def apply_two_site_gate(ctx, sites, i, j, axis, G, max_rank, noalloc=False):
     """QR-SVD update (Alg. 1) of sites[i][j] and its right (axis 0) or lower
     (axis 1) neighbour with the gate G[out1,out2,in1,in2] (device tensor).
@@ -616,20 +631,28 @@ class ItePlan:
 
     def __init__(self, ctx, peps, gates, bond_gate, max_rank):
         keep = []
-        self.ctx = ctx
-        self.nrow, self.ncol = len(peps), len(peps[0])
-        self.dtype = peps[0][0].dtype
-        self.device = peps[0][0].device
+        self._setup(ctx, peps, max_rank)
         pk = _peps_struct(peps, _dtype_code(peps[0][0]), keep)
         bg = (C.c_int32 * len(bond_gate))(*bond_gate)
-        self.n_bonds = len(bond_gate)
-        self.max_rank = int(max_rank)
         self.gates = gates.contiguous()
         h = C.c_void_p()
         ctx.sync_stream()
         ctx.check(ctx.lib.hpeps_ite_plan_create(ctx.h, C.byref(pk), self.gates.shape[0],
                                                 _dev(self.gates, "gates"), bg, max_rank, C.byref(h)))
         self.h = h
+        self._count()
+
+    def _setup(self, ctx, peps, max_rank):
+        self.ctx = ctx
+        self.nrow, self.ncol = len(peps), len(peps[0])
+        self.dtype = peps[0][0].dtype
+        self.device = peps[0][0].device
+        self.max_rank = int(max_rank)
+
+    def _count(self):
+        nl, nb = C.c_int32(), C.c_int32()
+        self.ctx.check(self.ctx.lib.hpeps_ite_plan_layers(self.h, C.byref(nl), C.byref(nb)))
+        self.n_layers, self.n_bonds = nl.value, nb.value
 
     def run(self, n_sweeps, use_graph=True, per_bond=False):
         """use_graph: replay the captured sweep graph; per_bond: the plain form,
@@ -673,3 +696,34 @@ class ItePlan:
             self.close()
         except Exception:
             pass
+
+
+class CircuitPlan(ItePlan):
+    """A sweep over an arbitrary gate list (hpeps_circuit_plan_create): ops is a
+    list of (2, (i1, j1), (i2, j2), gate) two-site operations (any two sites:
+    non-neighbours run as SWAP chains) and (1, (i, j), gate) one-site
+    operations, in order; gates2 [n2, d, d, d, d] and gates1 [n1, d, d] are
+    host float64 arrays.  run / spectra / state / close as for ItePlan."""
+
+    def __init__(self, ctx, peps, ops, gates2, gates1, max_rank):
+        import numpy as np
+        keep = []
+        self._setup(ctx, peps, max_rank)
+        pk = _peps_struct(peps, _dtype_code(peps[0][0]), keep)
+        flat = []
+        for op in ops:
+            if op[0] == 1:
+                flat += [1, op[1][0], op[1][1], 0, 0, op[2]]
+            else:
+                flat += [2, op[1][0], op[1][1], op[2][0], op[2][1], op[3]]
+        arr = (C.c_int32 * len(flat))(*flat)
+        g2 = np.ascontiguousarray(np.asarray(gates2, dtype=np.float64).reshape(-1))
+        g1 = np.ascontiguousarray(np.asarray(gates1, dtype=np.float64).reshape(-1))
+        d = peps[0][0].shape[4]
+        h = C.c_void_p()
+        ctx.sync_stream()
+        ctx.check(ctx.lib.hpeps_circuit_plan_create(
+            ctx.h, C.byref(pk), g2.size // d ** 4, g2.ctypes.data_as(C.POINTER(C.c_double)),
+            g1.size // d ** 2, g1.ctypes.data_as(C.POINTER(C.c_double)), len(ops), arr, max_rank, C.byref(h)))
+        self.h = h
+        self._count()

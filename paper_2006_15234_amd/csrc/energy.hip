@@ -139,11 +139,12 @@ Ten transfer3(Ctx& ctx, bool cplx, const Ten& L, const BndView& top, const SiteV
   return res;
 }
 
-// One column of a four-layer strip: L[spec,t,l,L,m,M,b] -> L'[spec,s,r,R,n,N,c(,p,P,q,Q)].
+// One column of a four-layer strip: L[spec,t,l,L,m,M,b] -> L'[spec,s,r,R,n,N,c(,p,P)(,q,Q)]: the
+// upper row's physical legs stay open with open1, the lower row's with open2.
 Ten transfer4(Ctx& ctx, bool cplx, const Ten& L, const BndView& top, const SiteView& k1, const SiteView& b1,
-              const SiteView& k2, const SiteView& b2, const BndView& bot, bool open) {
+              const SiteView& k2, const SiteView& b2, const BndView& bot, bool open1, bool open2) {
   const std::string sp = spectators(L.legs, "tlLmMb");
-  const std::string o1 = open ? "pP" : "", o2 = open ? "qQ" : "";
+  const std::string o1 = open1 ? "pP" : "", o2 = open2 ? "qQ" : "";
   const std::string out = sp + "srRnNc" + o1 + o2;
   Ten res;
   res.legs = out;
@@ -171,9 +172,9 @@ Ten transfer4(Ctx& ctx, bool cplx, const Ten& L, const BndView& top, const SiteV
     WsScope scope(ctx);
     Ten x1 = contract(ctx, cplx, restrict_leg(L.view(), 'b', b0, len, cplx), bview(top, "tuUs"), s1);
     Ten x2 = contract(ctx, cplx, x1.view(), sview(k1, "uvlrp", false), s2);
-    Ten x3 = contract(ctx, cplx, x2.view(), sview(b1, open ? "UVLRP" : "UVLRp", true), s3);
+    Ten x3 = contract(ctx, cplx, x2.view(), sview(b1, open1 ? "UVLRP" : "UVLRp", true), s3);
     Ten x4 = contract(ctx, cplx, x3.view(), sview(k2, "vdmnq", false), s4);
-    Ten x5 = contract(ctx, cplx, x4.view(), sview(b2, open ? "VDMNQ" : "VDMNq", true), s5);
+    Ten x5 = contract(ctx, cplx, x4.view(), sview(b2, open2 ? "VDMNQ" : "VDMNq", true), s5);
     contract2(ctx, cplx, x5.view(), restrict_leg(bview(bot, "bdDc"), 'b', b0, len, cplx), out, res.p, res.size(),
               b0 > 0);
   }
@@ -306,7 +307,7 @@ __global__ void expect_bwd_kernel(const double* const* rdm, const double* const*
 namespace hp {
 
 void check_terms(const Lattice& K, int n_terms, const int32_t* nsites, const int32_t* sites,
-                 const int64_t* op_offset) {
+                 const int64_t* op_offset, bool diagonal) {
   const int nrow = K.nrow, ncol = K.ncol;
   for (int t = 0; t < n_terms; ++t) {
     const int* s = sites + 4 * t;
@@ -314,7 +315,10 @@ void check_terms(const Lattice& K, int n_terms, const int32_t* nsites, const int
     HP_REQUIRE(s[0] >= 0 && s[0] < nrow && s[1] >= 0 && s[1] < ncol, HPEPS_ERR_INVALID_ARG, "site out of range");
     if (nsites[t] == 2) {
       const bool horiz = s[2] == s[0] && s[3] == s[1] + 1, vert = s[3] == s[1] && s[2] == s[0] + 1;
-      HP_REQUIRE(horiz || vert, HPEPS_ERR_INVALID_ARG, "two-site terms must be nearest neighbours, site 1 first");
+      const bool diag = s[2] == s[0] + 1 && (s[3] == s[1] + 1 || s[3] == s[1] - 1) && s[3] >= 0 && s[3] < ncol;
+      HP_REQUIRE(horiz || vert || (diagonal && diag), HPEPS_ERR_INVALID_ARG,
+                 diagonal ? "two-site terms must be nearest or diagonal neighbours, site 1 first (above)"
+                          : "two-site terms must be nearest neighbours, site 1 first");
     }
     HP_REQUIRE(op_offset[t] >= 0, HPEPS_ERR_INVALID_ARG, "bad operator offset");
   }
@@ -433,31 +437,49 @@ std::vector<const double*> energy_rdms(Ctx& c, const Lattice& K, int n_terms, co
       BndView tv, btv;
       SiteView k1, k2;
       col(q, kL2R, tv, k1, k2, btv);
-      Ten x = transfer4(c, cplx, Lenv[q], tv, k1, k1, k2, k2, btv, false);
+      Ten x = transfer4(c, cplx, Lenv[q], tv, k1, k1, k2, k2, btv, false, false);
       normalize(c, cplx, x.p, x.size(), 1, logd);
       x.legs = "tlLmMb";
       Lenv[q + 1] = x;
       col(ncol - 1 - q, kR2L, tv, k1, k2, btv);
-      Ten y = transfer4(c, cplx, Renv[q], tv, k1, k1, k2, k2, btv, false);
+      Ten y = transfer4(c, cplx, Renv[q], tv, k1, k1, k2, k2, btv, false, false);
       normalize(c, cplx, y.p, y.size(), 1, logd);
       y.legs = "tlLmMb";
       Renv[q + 1] = y;
     }
-    std::map<int, const double*> cache;
+    // (column of site 1, column of site 2) -> rdm [p1,P1,p2,P2]
+    std::map<std::pair<int, int>, const double*> cache;
     for (int t : here) {
-      const int j = sites[4 * t + 1];
-      if (!cache.count(j)) {
+      const int j = sites[4 * t + 1], j2 = sites[4 * t + 3];
+      const auto key = std::make_pair(j, j2);
+      if (!cache.count(key)) {
         BndView tv, btv;
         SiteView k1, k2;
-        col(j, kL2R, tv, k1, k2, btv);
-        Ten y = transfer4(c, cplx, Lenv[j], tv, k1, k1, k2, k2, btv, true);  // srRnNcpPqQ
-        Ten R = Renv[ncol - 1 - j];
-        R.legs = "srRnNc";
         double* dst = rdm_store + (int64_t)t * slot;
-        contract2(c, cplx, y.view(), R.view(), "pPqQ", dst, slot / es);
-        cache[j] = dst;
+        if (j2 == j) {
+          col(j, kL2R, tv, k1, k2, btv);
+          Ten y = transfer4(c, cplx, Lenv[j], tv, k1, k1, k2, k2, btv, true, true);  // srRnNcpPqQ
+          Ten R = Renv[ncol - 1 - j];
+          R.legs = "srRnNc";
+          contract2(c, cplx, y.view(), R.view(), "pPqQ", dst, slot / es);
+        } else {
+          // diagonal pair over columns a < a + 1: the first column opens the
+          // site it holds, its open legs ride along as spectators (ef)
+          const int a = std::min(j, j2);
+          const bool first_upper = j < j2;  // down-right: the upper site is in column a
+          col(a, kL2R, tv, k1, k2, btv);
+          Ten y = transfer4(c, cplx, Lenv[a], tv, k1, k1, k2, k2, btv, first_upper, !first_upper);
+          y.legs = "tlLmMbef";
+          col(a + 1, kL2R, tv, k1, k2, btv);
+          Ten y2 = transfer4(c, cplx, y, tv, k1, k1, k2, k2, btv, !first_upper, first_upper);
+          Ten R = Renv[ncol - 2 - a];
+          R.legs = "srRnNc";
+          // y2 legs: ef (first column's open pair) + srRnNc + the second column's open pair
+          contract2(c, cplx, y2.view(), R.view(), first_upper ? "efqQ" : "pPef", dst, slot / es);
+        }
+        cache[key] = dst;
       }
-      rdm_ptr[t] = cache[j];
+      rdm_ptr[t] = cache[key];
     }
   }
   return rdm_ptr;
@@ -674,7 +696,7 @@ extern "C" hpeps_status hpeps_peps_energy_uncached(hpeps_ctx* ctx, const hpeps_p
   return guard_e(ctx, [&](Ctx& c) {
     check_energy_args(opts, n_terms, nsites, sites, ops, op_offset, energy);
     const Lattice K = lattice_from_abi(ket);
-    check_terms(K, n_terms, nsites, sites, op_offset);
+    check_terms(K, n_terms, nsites, sites, op_offset, false);
     const bool cplx = K.cplx;
     const int d = (int)K.sites[0].dims[4];
     double* dev = c.ws<double>(3);
@@ -732,7 +754,7 @@ extern "C" hpeps_status hpeps_peps_trotter_expectation(hpeps_ctx* ctx, const hpe
     std::vector<int32_t> two(n_gates, 2);
     std::vector<int64_t> off(n_gates);
     for (int t = 0; t < n_gates; ++t) off[t] = t * g4;
-    check_terms(K, n_gates, two.data(), sites, off.data());
+    check_terms(K, n_gates, two.data(), sites, off.data(), false);
     double* E = c.ws<double>((int64_t)d * d * d * d * (cplx ? 2 : 1));
     fill_identity(c, E, (int64_t)d * d, 1, cplx);
     // phi = prod_j G_j psi, gates in the order given
@@ -768,7 +790,7 @@ extern "C" hpeps_status hpeps_peps_energy(hpeps_ctx* ctx, const hpeps_peps* ket,
   return guard_e(ctx, [&](Ctx& c) {
     check_energy_args(opts, n_terms, nsites, sites, ops, op_offset, energy);
     Lattice K = lattice_from_abi(ket);
-    check_terms(K, n_terms, nsites, sites, op_offset);
+    check_terms(K, n_terms, nsites, sites, op_offset, true);
     const auto rdm = energy_rdms(c, K, n_terms, nsites, sites, *opts);
     const TermsDev t = term_values(c, K.cplx, (int)K.sites[0].dims[4], n_terms, nsites, ops, op_offset, rdm);
     read_energy(c, t, n_terms, energy, per_term);
@@ -785,7 +807,7 @@ extern "C" hpeps_status hpeps_peps_energy_backward(hpeps_ctx* ctx, const hpeps_p
     HP_REQUIRE(grads, HPEPS_ERR_INVALID_ARG, "null gradient array");
     HP_REQUIRE(broadening >= 0.0, HPEPS_ERR_INVALID_ARG, "broadening must be >= 0");
     Lattice K = lattice_from_abi(ket);
-    check_terms(K, n_terms, nsites, sites, op_offset);
+    check_terms(K, n_terms, nsites, sites, op_offset, false);
     for (size_t q = 0; q < K.sites.size(); ++q) HP_REQUIRE(grads[q], HPEPS_ERR_INVALID_ARG, "null gradient pointer");
     const int d = (int)K.sites[0].dims[4];
     Tape tape(K.cplx);

@@ -17,12 +17,16 @@
 // one per layer of non-overlapping bonds) is a static sequence that is
 // captured once in a HIP graph and replayed.
 #include <algorithm>
+#include <array>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <new>
 #include <string>
+#include <vector>
 
+#include "contract.h"
 #include "dpp.h"
 #include "peps.h"
 
@@ -32,10 +36,14 @@ struct hpeps_ite_plan {
   int64_t dmax = 0, cap = 0;
   double* sites = nullptr;
   int* dims = nullptr;
-  int* bonds[4] = {nullptr, nullptr, nullptr, nullptr};
-  int nb[4] = {0, 0, 0, 0};
-  double* gates = nullptr;
-  double* sigma = nullptr;  // per bond of a sweep (layer order): max_rank kept values
+  // layers of a sweep, in order: a two-site layer lists (s1, s2, axis, gate)
+  // per bond (s1 left of / above s2), a one-site layer (site, gate, 0, 0)
+  std::vector<int*> bonds;
+  std::vector<int> nb;
+  std::vector<char> onesite;
+  double* gates = nullptr;   // two-site gates [d,d,d,d]
+  double* gates1 = nullptr;  // one-site gates [d,d]
+  double* sigma = nullptr;  // per two-site bond of a sweep (layer order): max_rank kept values
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   hipStream_t gstream = nullptr;
@@ -548,6 +556,28 @@ void launch_layer(hipStream_t st, const IteArgs& a, int nb) {
   }
 }
 
+// One-site gates (Eq. 3) of a layer, in place: workgroup b applies the d x d
+// gate bonds[4 b + 1] to site bonds[4 b] fiber by fiber (the physical leg is
+// the contiguous one); a site appears at most once per layer.
+__global__ __launch_bounds__(kT) void onesite_kernel(IteArgs a, const double* gates1) {
+  const int s = a.bonds[4 * blockIdx.x], gi = a.bonds[4 * blockIdx.x + 1];
+  const int* dm = a.dims + 5 * s;
+  const int d = dm[4];
+  const long long fibers = (long long)dm[0] * dm[1] * dm[2] * dm[3];
+  const double* O = gates1 + (long long)gi * d * d;
+  double* site = a.sites + (long long)s * a.cap;
+  constexpr int kMaxD = 8;
+  for (long long f = threadIdx.x; f < fibers; f += blockDim.x) {
+    double x[kMaxD];
+    for (int q = 0; q < d; ++q) x[q] = site[f * d + q];
+    for (int P = 0; P < d; ++P) {
+      double acc = 0.0;
+      for (int q = 0; q < d; ++q) acc += O[P * d + q] * x[q];
+      site[f * d + P] = acc;
+    }
+  }
+}
+
 IteArgs plan_args(hpeps_ite_plan* p, int layer) {
   IteArgs a{};
   a.sites = p->sites;
@@ -557,7 +587,7 @@ IteArgs plan_args(hpeps_ite_plan* p, int layer) {
   a.gates = p->gates;
   a.dmax = (int)p->dmax;
   int off = 0;
-  for (int l = 0; l < layer; ++l) off += p->nb[l];
+  for (int l = 0; l < layer; ++l) off += p->onesite[l] ? 0 : p->nb[l];
   a.sigma = p->sigma + (int64_t)off * p->dmax;
   a.max_rows = (int)(p->dmax * p->dmax * p->dmax);
   return a;
@@ -599,8 +629,176 @@ void free_plan(hpeps_ite_plan* p) {
   (void)hipFree(p->dims);
   for (auto& b : p->bonds) (void)hipFree(b);
   (void)hipFree(p->gates);
+  (void)hipFree(p->gates1);
   (void)hipFree(p->sigma);
   delete p;
+}
+
+int total_bonds(const hpeps_ite_plan* p) {
+  int t = 0;
+  for (size_t l = 0; l < p->nb.size(); ++l) t += p->onesite[l] ? 0 : p->nb[l];
+  return t;
+}
+
+// One layer's launch (every entry its own workgroup).
+void launch_any(hpeps_ite_plan* p, hipStream_t st, int l, const hp::IteArgs& a, int n) {
+  if (n == 0) return;
+  if (p->onesite[l]) {
+    hp::onesite_kernel<<<n, hp::kT, 0, st>>>(a, p->gates1);
+    HP_CHECK_HIP(hipGetLastError());
+  } else {
+    hp::launch_layer(st, a, n);
+  }
+}
+
+// An operation of a compiled sweep: a two-site gate on a bond (s1 left of /
+// above s2) or a one-site gate.
+struct Op {
+  bool one;
+  int s1, s2, axis, gate;
+};
+
+// Builds the device side of a plan from the initial lattice, the layers of a
+// sweep and the gate tables (host, FP64).
+hpeps_ite_plan* build_plan(hp::Ctx& c, const hp::Lattice& L, int64_t max_rank, const std::vector<std::vector<Op>>& layers,
+                           const std::vector<double>& g2, const std::vector<double>& g1) {
+  const int d = (int)L.sites[0].dims[4];
+  hpeps_ite_plan* p = new hpeps_ite_plan();
+  try {
+    p->ctx = &c;
+    p->nrow = L.nrow;
+    p->ncol = L.ncol;
+    p->d = d;
+    p->dmax = max_rank;
+    p->cap = max_rank * max_rank * max_rank * max_rank * d;
+    const int ns = L.nrow * L.ncol;
+    HP_CHECK_HIP(hipMalloc(&p->sites, (size_t)ns * p->cap * sizeof(double)));
+    std::vector<int> dims(5 * ns);
+    for (int s = 0; s < ns; ++s) {
+      HP_CHECK_HIP(hipMemcpyAsync(p->sites + (int64_t)s * p->cap, L.sites[s].p, L.sites[s].size() * sizeof(double),
+                                  hipMemcpyDeviceToDevice, c.stream));
+      for (int e = 0; e < 5; ++e) dims[5 * s + e] = (int)L.sites[s].dims[e];
+    }
+    HP_CHECK_HIP(hipMalloc(&p->dims, dims.size() * sizeof(int)));
+    HP_CHECK_HIP(hipMemcpy(p->dims, dims.data(), dims.size() * sizeof(int), hipMemcpyHostToDevice));
+    for (const auto& layer : layers) {
+      std::vector<int> tb;
+      for (const Op& o : layer)
+        if (o.one) tb.insert(tb.end(), {o.s1, o.gate, 0, 0});
+        else tb.insert(tb.end(), {o.s1, o.s2, o.axis, o.gate});
+      int* dev = nullptr;
+      HP_CHECK_HIP(hipMalloc(&dev, std::max<size_t>(tb.size(), 4) * sizeof(int)));
+      p->bonds.push_back(dev);
+      p->nb.push_back((int)layer.size());
+      p->onesite.push_back(!layer.empty() && layer[0].one);
+      if (!tb.empty()) HP_CHECK_HIP(hipMemcpy(dev, tb.data(), tb.size() * sizeof(int), hipMemcpyHostToDevice));
+    }
+    HP_CHECK_HIP(hipMalloc(&p->gates, std::max<size_t>(g2.size(), 1) * sizeof(double)));
+    if (!g2.empty()) HP_CHECK_HIP(hipMemcpy(p->gates, g2.data(), g2.size() * sizeof(double), hipMemcpyHostToDevice));
+    HP_CHECK_HIP(hipMalloc(&p->gates1, std::max<size_t>(g1.size(), 1) * sizeof(double)));
+    if (!g1.empty()) HP_CHECK_HIP(hipMemcpy(p->gates1, g1.data(), g1.size() * sizeof(double), hipMemcpyHostToDevice));
+    const int total_nb = total_bonds(p);
+    HP_CHECK_HIP(hipMalloc(&p->sigma, (size_t)std::max(total_nb, 1) * max_rank * sizeof(double)));
+    HP_CHECK_HIP(hipMemsetAsync(p->sigma, 0, (size_t)std::max(total_nb, 1) * max_rank * sizeof(double), c.stream));
+    HP_CHECK_HIP(hipStreamSynchronize(c.stream));
+  } catch (...) {
+    free_plan(p);
+    throw;
+  }
+  return p;
+}
+
+// Compiles a gate list into layers.  A two-site gate on sites a, b that are
+// not nearest neighbours becomes a SWAP chain (Sec. II-C): b's state is moved
+// by SWAP gates along its row to a's column, then along that column until it
+// is a neighbour of a; the gate acts there; the SWAPs are undone in reverse
+// order.  A gate whose second site ends up left of or above the first is
+// applied transposed (G[Q,P,q,p]).  Each operation is placed in the first
+// layer after the last one that touches its sites (one-site and two-site
+// operations never share a layer), so every site sees its operations in list
+// order and no layer touches a site twice.
+std::vector<std::vector<Op>> compile_ops(int nrow, int ncol, int d, int n_ops, const int32_t* ops, int n2, int n1,
+                                         std::vector<double>& g2) {
+  const int64_t g4 = (int64_t)d * d * d * d;
+  // SWAP[P,Q,p,q] = delta(P,q) delta(Q,p), appended to the table
+  const int swap_id = n2;
+  std::vector<int> transposed(n2 + 1, -1);
+  {
+    std::vector<double> sw(g4, 0.0);
+    for (int P = 0; P < d; ++P)
+      for (int Q = 0; Q < d; ++Q) sw[((P * d + Q) * d + Q) * d + P] = 1.0;
+    g2.insert(g2.end(), sw.begin(), sw.end());
+    transposed[swap_id] = swap_id;
+  }
+  auto transpose_of = [&](int g) {
+    if (transposed[g] < 0) {
+      const int64_t base = (int64_t)g * g4;
+      std::vector<double> t(g4);
+      for (int P = 0; P < d; ++P)
+        for (int Q = 0; Q < d; ++Q)
+          for (int a = 0; a < d; ++a)
+            for (int b = 0; b < d; ++b) t[((Q * d + P) * d + b) * d + a] = g2[base + ((P * d + Q) * d + a) * d + b];
+      transposed[g] = (int)(g2.size() / g4);
+      g2.insert(g2.end(), t.begin(), t.end());
+    }
+    return transposed[g];
+  };
+  std::vector<Op> seq;
+  auto bond_op = [&](int ia, int ja, int ib, int jb, int g) {
+    // a, b nearest neighbours; oriented so that s1 is left of / above s2
+    const bool ab = (ia == ib && jb == ja + 1) || (ja == jb && ib == ia + 1);
+    const bool ba = (ia == ib && ja == jb + 1) || (ja == jb && ia == ib + 1);
+    HP_REQUIRE(ab || ba, HPEPS_ERR_INVALID_ARG, "internal: bond sites not adjacent");
+    Op o{false, 0, 0, 0, 0};
+    if (ab) {
+      o.s1 = ia * ncol + ja; o.s2 = ib * ncol + jb; o.gate = g;
+    } else {
+      o.s1 = ib * ncol + jb; o.s2 = ia * ncol + ja; o.gate = transpose_of(g);
+    }
+    o.axis = ia == ib ? 0 : 1;
+    seq.push_back(o);
+  };
+  for (int t = 0; t < n_ops; ++t) {
+    const int32_t* e = ops + 6 * t;
+    const int kind = e[0], i1 = e[1], j1 = e[2], i2 = e[3], j2 = e[4], g = e[5];
+    HP_REQUIRE(kind == 1 || kind == 2, HPEPS_ERR_INVALID_ARG, "operation kind must be 1 or 2");
+    HP_REQUIRE(i1 >= 0 && i1 < nrow && j1 >= 0 && j1 < ncol, HPEPS_ERR_INVALID_ARG, "site out of range");
+    if (kind == 1) {
+      HP_REQUIRE(g >= 0 && g < n1, HPEPS_ERR_INVALID_ARG, "one-site gate index out of range");
+      seq.push_back(Op{true, i1 * ncol + j1, -1, 0, g});
+      continue;
+    }
+    HP_REQUIRE(i2 >= 0 && i2 < nrow && j2 >= 0 && j2 < ncol, HPEPS_ERR_INVALID_ARG, "site out of range");
+    HP_REQUIRE(!(i1 == i2 && j1 == j2), HPEPS_ERR_INVALID_ARG, "a two-site gate needs two distinct sites");
+    HP_REQUIRE(g >= 0 && g < n2, HPEPS_ERR_INVALID_ARG, "two-site gate index out of range");
+    // the path of site b toward a
+    std::vector<std::array<int, 2>> path{{i2, j2}};
+    auto adjacent = [&](int i, int j) { return std::abs(i - i1) + std::abs(j - j1) == 1; };
+    int ci = i2, cj = j2;
+    while (!adjacent(ci, cj)) {
+      if (cj != j1 && !(ci == i1 && std::abs(cj - j1) == 1)) cj += cj < j1 ? 1 : -1;
+      else ci += ci < i1 ? 1 : -1;
+      path.push_back({ci, cj});
+    }
+    for (size_t q = 0; q + 1 < path.size(); ++q)
+      bond_op(path[q][0], path[q][1], path[q + 1][0], path[q + 1][1], swap_id);
+    bond_op(i1, j1, ci, cj, g);
+    for (size_t q = path.size() - 1; q >= 1; --q)
+      bond_op(path[q - 1][0], path[q - 1][1], path[q][0], path[q][1], swap_id);
+  }
+  // layering
+  std::vector<std::vector<Op>> layers;
+  std::vector<int> last(nrow * ncol, -1);
+  for (const Op& o : seq) {
+    int L = last[o.s1] + 1;
+    if (!o.one) L = std::max(L, last[o.s2] + 1);
+    while (L < (int)layers.size() && !layers[L].empty() && layers[L][0].one != o.one) ++L;
+    if (L >= (int)layers.size()) layers.resize(L + 1);
+    layers[L].push_back(o);
+    last[o.s1] = L;
+    if (!o.one) last[o.s2] = L;
+  }
+  return layers;
 }
 
 // layer lists of a lattice: horizontal bonds at even / odd columns, vertical
@@ -728,9 +926,8 @@ hpeps_status hpeps_ite_plan_create(hpeps_ctx* ctx, const hpeps_peps* init, int32
                                    hpeps_ite_plan** out) {
   if (!ctx || !out) return HPEPS_ERR_INVALID_ARG;
   hp::Ctx& c = *ctx->impl;
-  hpeps_ite_plan* p = nullptr;
-  hpeps_status st = guard_i(&c, [&] {
-    *out = nullptr;
+  *out = nullptr;
+  return guard_i(&c, [&] {
     HP_REQUIRE(gates && bond_gate && n_gates >= 1, HPEPS_ERR_INVALID_ARG, "null gates");
     hp::Lattice L = hp::lattice_from_abi(init);
     HP_REQUIRE(!L.cplx, HPEPS_ERR_DTYPE, "the batched QR-SVD sweep is FP64 real");
@@ -738,52 +935,49 @@ hpeps_status hpeps_ite_plan_create(hpeps_ctx* ctx, const hpeps_peps* init, int32
     hp::check_dims(max_rank, d);
     for (auto& t : L.sites)
       for (int e = 0; e < 4; ++e) HP_REQUIRE(t.dims[e] <= max_rank, HPEPS_ERR_SHAPE, "initial bond exceeds max_rank");
-    p = new hpeps_ite_plan();
-    p->ctx = &c;
-    p->nrow = L.nrow;
-    p->ncol = L.ncol;
-    p->d = d;
-    p->dmax = max_rank;
-    p->cap = max_rank * max_rank * max_rank * max_rank * d;
-    const int ns = L.nrow * L.ncol;
-    HP_CHECK_HIP(hipMalloc(&p->sites, (size_t)ns * p->cap * sizeof(double)));
-    std::vector<int> dims(5 * ns);
-    for (int s = 0; s < ns; ++s) {
-      HP_CHECK_HIP(hipMemcpyAsync(p->sites + (int64_t)s * p->cap, L.sites[s].p, L.sites[s].size() * sizeof(double),
-                                  hipMemcpyDeviceToDevice, c.stream));
-      for (int e = 0; e < 5; ++e) dims[5 * s + e] = (int)L.sites[s].dims[e];
-    }
-    HP_CHECK_HIP(hipMalloc(&p->dims, dims.size() * sizeof(int)));
-    HP_CHECK_HIP(hipMemcpy(p->dims, dims.data(), dims.size() * sizeof(int), hipMemcpyHostToDevice));
-    auto layers = lattice_layers(L.nrow, L.ncol);
+    const auto ll = lattice_layers(L.nrow, L.ncol);
+    std::vector<std::vector<Op>> layers(4);
     int q = 0;
-    for (int l = 0; l < 4; ++l) {
-      std::vector<int> tb;
-      for (auto& bd : layers[l]) {
+    for (int l = 0; l < 4; ++l)
+      for (auto& bd : ll[l]) {
         const int gi = bond_gate[q++];
         HP_REQUIRE(gi >= 0 && gi < n_gates, HPEPS_ERR_INVALID_ARG, "gate index out of range");
-        tb.insert(tb.end(), {bd[0], bd[1], bd[2], gi});
+        layers[l].push_back(Op{false, bd[0], bd[1], bd[2], gi});
       }
-      p->nb[l] = (int)layers[l].size();
-      if (!tb.empty()) {
-        HP_CHECK_HIP(hipMalloc(&p->bonds[l], tb.size() * sizeof(int)));
-        HP_CHECK_HIP(hipMemcpy(p->bonds[l], tb.data(), tb.size() * sizeof(int), hipMemcpyHostToDevice));
-      }
-    }
-    const size_t gsz = (size_t)n_gates * d * d * d * d * sizeof(double);
-    HP_CHECK_HIP(hipMalloc(&p->gates, gsz));
-    HP_CHECK_HIP(hipMemcpyAsync(p->gates, gates, gsz, hipMemcpyDeviceToDevice, c.stream));
-    int total_nb = 0;
-    for (int l = 0; l < 4; ++l) total_nb += p->nb[l];
-    HP_CHECK_HIP(hipMalloc(&p->sigma, (size_t)std::max(total_nb, 1) * max_rank * sizeof(double)));
-    HP_CHECK_HIP(hipMemsetAsync(p->sigma, 0, (size_t)std::max(total_nb, 1) * max_rank * sizeof(double), c.stream));
-    HP_CHECK_HIP(hipStreamSynchronize(c.stream));
+    std::vector<double> g2((size_t)n_gates * d * d * d * d);
+    HP_CHECK_HIP(hipMemcpy(g2.data(), gates, g2.size() * sizeof(double), hipMemcpyDeviceToHost));
+    *out = build_plan(c, L, max_rank, layers, g2, {});
   });
-  if (st != HPEPS_OK) {
-    free_plan(p);
-    return st;
-  }
-  *out = p;
+}
+
+hpeps_status hpeps_circuit_plan_create(hpeps_ctx* ctx, const hpeps_peps* init, int32_t n_gates2,
+                                       const double* gates2, int32_t n_gates1, const double* gates1,
+                                       int32_t n_ops, const int32_t* ops, int64_t max_rank,
+                                       hpeps_ite_plan** out) {
+  if (!ctx || !out) return HPEPS_ERR_INVALID_ARG;
+  hp::Ctx& c = *ctx->impl;
+  *out = nullptr;
+  return guard_i(&c, [&] {
+    HP_REQUIRE(n_gates2 >= 0 && n_gates1 >= 0 && n_ops >= 1 && ops, HPEPS_ERR_INVALID_ARG, "null operations");
+    HP_REQUIRE((n_gates2 == 0 || gates2) && (n_gates1 == 0 || gates1), HPEPS_ERR_INVALID_ARG, "null gates");
+    hp::Lattice L = hp::lattice_from_abi(init);
+    HP_REQUIRE(!L.cplx, HPEPS_ERR_DTYPE, "the batched QR-SVD sweep is FP64 real");
+    const int d = (int)L.sites[0].dims[4];
+    hp::check_dims(max_rank, d);
+    HP_REQUIRE(d <= 8, HPEPS_ERR_UNSUPPORTED, "one-site gates support d <= 8");
+    for (auto& t : L.sites)
+      for (int e = 0; e < 4; ++e) HP_REQUIRE(t.dims[e] <= max_rank, HPEPS_ERR_SHAPE, "initial bond exceeds max_rank");
+    std::vector<double> g2(gates2, gates2 + (size_t)n_gates2 * d * d * d * d);
+    std::vector<double> g1(gates1, gates1 + (size_t)n_gates1 * d * d);
+    const auto layers = compile_ops(L.nrow, L.ncol, d, n_ops, ops, n_gates2, n_gates1, g2);
+    *out = build_plan(c, L, max_rank, layers, g2, g1);
+  });
+}
+
+hpeps_status hpeps_ite_plan_layers(hpeps_ite_plan* p, int32_t* n_layers, int32_t* n_bonds) {
+  if (!p) return HPEPS_ERR_INVALID_ARG;
+  if (n_layers) *n_layers = (int32_t)p->nb.size();
+  if (n_bonds) *n_bonds = total_bonds(p);
   return HPEPS_OK;
 }
 
@@ -791,20 +985,21 @@ hpeps_status hpeps_ite_run(hpeps_ite_plan* p, int32_t n_sweeps, int32_t use_grap
   if (!p || n_sweeps < 0) return HPEPS_ERR_INVALID_ARG;
   hp::Ctx& c = *p->ctx;
   return guard_i(&c, [&] {
+    const int nl = (int)p->nb.size();
     auto sweep = [&](hipStream_t st) {
-      for (int l = 0; l < 4; ++l) hp::launch_layer(st, hp::plan_args(p, l), p->nb[l]);
+      for (int l = 0; l < nl; ++l) launch_any(p, st, l, hp::plan_args(p, l), p->nb[l]);
     };
     if (use_graph == 2) {
       // plain form: one launch per bond, no graph (the baseline the batched
       // layer launches and their graph replay are measured against)
       for (int s = 0; s < n_sweeps; ++s)
-        for (int l = 0; l < 4; ++l) {
+        for (int l = 0; l < nl; ++l) {
           hp::IteArgs a = hp::plan_args(p, l);
           for (int b = 0; b < p->nb[l]; ++b) {
             hp::IteArgs ab = a;
             ab.bonds = a.bonds + 4 * b;
-            ab.sigma = a.sigma + (int64_t)b * p->dmax;
-            hp::launch_layer(c.stream, ab, 1);
+            ab.sigma = p->onesite[l] ? a.sigma : a.sigma + (int64_t)b * p->dmax;
+            launch_any(p, c.stream, l, ab, 1);
           }
         }
       HP_CHECK_HIP(hipGetLastError());
@@ -860,8 +1055,7 @@ hpeps_status hpeps_ite_spectra(hpeps_ite_plan* p, double* out) {
   if (!p || !out) return HPEPS_ERR_INVALID_ARG;
   hp::Ctx& c = *p->ctx;
   return guard_i(&c, [&] {
-    int total = 0;
-    for (int l = 0; l < 4; ++l) total += p->nb[l];
+    const int total = total_bonds(p);
     HP_CHECK_HIP(hipMemcpyAsync(out, p->sigma, (size_t)total * p->dmax * sizeof(double), hipMemcpyDeviceToDevice,
                                 c.stream));
   });
@@ -872,6 +1066,29 @@ hpeps_status hpeps_ite_plan_destroy(hpeps_ite_plan* p) {
   (void)hipStreamSynchronize(p->ctx->stream);
   free_plan(p);
   return HPEPS_OK;
+}
+
+hpeps_status hpeps_apply_one_site_gate(hpeps_ctx* ctx, hpeps_dtype dtype, const int64_t* dims, const void* site,
+                                       const void* G, void* out) {
+  if (!ctx) return HPEPS_ERR_INVALID_ARG;
+  hp::Ctx& c = *ctx->impl;
+  return guard_i(&c, [&] {
+    c.ws_reset();
+    HP_REQUIRE(dims && site && G && out, HPEPS_ERR_INVALID_ARG, "null argument");
+    HP_REQUIRE(dtype == HPEPS_F64 || dtype == HPEPS_C128, HPEPS_ERR_DTYPE, "one-site gates run in FP64 / complex128");
+    const bool cplx = dtype == HPEPS_C128;
+    std::vector<int64_t> dv(dims, dims + 5);
+    int64_t n = 1;
+    for (auto x : dv) {
+      HP_REQUIRE(x >= 1, HPEPS_ERR_SHAPE, "dimensions must be >= 1");
+      n *= x;
+    }
+    const int64_t d = dv[4];
+    // through the workspace, so that out may alias site
+    void* tmp = c.ws<double>(n * (cplx ? 2 : 1));
+    hp::contract2(c, cplx, hp::tview_rm(site, "udlrp", dv), hp::tview_rm(G, "Pp", {d, d}), "udlrP", tmp, n);
+    HP_CHECK_HIP(hipMemcpyAsync(out, tmp, (size_t)n * (cplx ? 16 : 8), hipMemcpyDeviceToDevice, c.stream));
+  });
 }
 
 hpeps_status hpeps_apply_two_site_gate(hpeps_ctx* ctx, hpeps_peps* peps, const int64_t* capacity, int32_t i,

@@ -24,7 +24,8 @@ import numpy as np
 __all__ = [
     "site_shape", "random_peps", "random_boundary_tensor", "product_state_peps",
     "pair_instance", "PAULI", "tfi_bond_hamiltonians", "heisenberg_bond_hamiltonian",
-    "bond_gate", "lattice_bonds", "coordination",
+    "bond_gate", "lattice_bonds", "coordination", "diagonal_bonds", "j1j2_terms", "ry_gate", "CNOT",
+    "vqe_ansatz_ops",
 ]
 
 
@@ -160,3 +161,57 @@ def bond_gate(Hb, tau):
     w, V = np.linalg.eigh(M)
     G = (V * np.exp(-tau * w)) @ V.conj().T
     return np.ascontiguousarray(G.reshape(2, 2, 2, 2))
+
+
+def diagonal_bonds(nrow, ncol):
+    """Diagonally adjacent pairs ((k, l), (k+1, l+1)) and ((k, l), (k+1, l-1))."""
+    down_right = [((i, j), (i + 1, j + 1)) for i in range(nrow - 1) for j in range(ncol - 1)]
+    down_left = [((i, j), (i + 1, j - 1)) for i in range(nrow - 1) for j in range(1, ncol)]
+    return down_right + down_left
+
+
+def j1j2_terms(nrow, ncol, J1=(1.0, 1.0, 1.0), J2=(0.5, 0.5, 0.5), h=(0.2, 0.2, 0.2)):
+    """The J1-J2 Heisenberg model in Pauli form (the paper's Eq. 7): J1 (x, y, z)
+    couplings on nearest neighbours, J2 on diagonal neighbours, field h on every
+    site.  Returns a list of (sites, op): two-site ops [2,2,2,2] (out1, out2,
+    in1, in2) and one-site ops [2,2], complex128."""
+    X, Y, Z = PAULI["X"], PAULI["Y"], PAULI["Z"]
+
+    def coupling(J):
+        return J[0] * _kron4(X, X) + J[1] * _kron4(Y, Y) + J[2] * _kron4(Z, Z)
+
+    terms = [(b, coupling(J1)) for layer in lattice_bonds(nrow, ncol) for b in layer]
+    terms += [(b, coupling(J2)) for b in diagonal_bonds(nrow, ncol)]
+    terms += [(((i, j),), h[0] * X + h[1] * Y + h[2] * Z) for i in range(nrow) for j in range(ncol)]
+    return terms
+
+
+def ry_gate(theta):
+    """R_y(theta) = exp(-i theta Y / 2) (a real rotation)."""
+    c, s = np.cos(theta / 2), np.sin(theta / 2)
+    return np.array([[c, -s], [s, c]])
+
+
+# CNOT[P, Q, p, q] = delta(P, p) delta(Q, q xor p): site 1 controls site 2
+CNOT = np.zeros((2, 2, 2, 2))
+for _p in range(2):
+    for _q in range(2):
+        CNOT[_p, _q ^ _p, _p, _q] = 1.0
+
+
+def vqe_ansatz_ops(nrow, ncol, n_layers):
+    """The VQE ansatz circuit of the paper's Sec. VI-D as a gate list: each layer
+    applies R_y to every qubit, then a CNOT to every nearest-neighbour pair (in
+    the order of lattice_bonds).  Returns ops [(1, site, k) for the k-th R_y
+    angle] + [(2, s1, s2, 0) for CNOT], with one angle per qubit and layer."""
+    ops = []
+    k = 0
+    for _ in range(n_layers):
+        for i in range(nrow):
+            for j in range(ncol):
+                ops.append((1, (i, j), k))
+                k += 1
+        for layer in lattice_bonds(nrow, ncol):
+            for (s1, s2) in layer:
+                ops.append((2, s1, s2, 0))
+    return ops

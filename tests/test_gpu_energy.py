@@ -132,3 +132,40 @@ def test_energy_of_evolved_tfi_state(ctx):
     assert np.max(np.abs(np.array(per) - po)) < 1e-10 * np.max(np.abs(po))
     assert abs(e - eo) < 1e-10 * abs(eo)
     assert e.real < 0
+
+
+@pytest.mark.parametrize("case", [
+    # nrow, ncol, D, m, p, q, complex
+    (3, 3, 2, 4, 2, 1, True),
+    (4, 4, 2, 6, 4, 1, False),
+    (4, 3, 3, 5, 3, 0, True),
+])
+def test_j1j2_energy_with_diagonal_terms_matches_oracle(ctx, case):
+    """The J1-J2 Hamiltonian of Eq. 7: diagonal (J2) terms in both directions
+    on four-row strips beside the nearest-neighbour and field terms, truncated
+    environments, every term against the oracle at 1e-10."""
+    nrow, ncol, D, m, p, q, cplx = case
+    peps = synth.random_peps(nrow, ncol, D, seed=nrow * 7 + ncol, complex_=cplx)
+    terms = synth.j1j2_terms(nrow, ncol)
+    e_ref, per_ref = energy.peps_energy_cached(peps, terms, m, p, q, seed=2)
+    e, per = hp.peps_energy(ctx, dev_lattice(peps), terms, rank=m, oversample=p, power_iters=q, seed=2)
+    assert np.max(np.abs(np.array(per) - per_ref)) <= 1e-10 * max(1.0, np.max(np.abs(per_ref)))
+    assert abs(e - e_ref) <= 1e-10 * max(1.0, abs(e_ref)) * len(terms)
+
+
+def test_j1j2_energy_exact_regime(ctx):
+    peps = synth.random_peps(3, 4, 2, seed=5, complex_=True)
+    terms = synth.j1j2_terms(3, 4)
+    psi = sv.peps_to_statevector(peps)
+    ref = np.array([sv.expectation(psi, [t], 4) for t in terms])
+    _, per = hp.peps_energy(ctx, dev_lattice(peps), terms, rank=64)
+    assert np.max(np.abs(np.array(per) - ref)) <= 1e-10
+
+
+def test_diagonal_terms_rejected_where_unsupported(ctx):
+    peps = synth.random_peps(2, 2, 2, seed=5)
+    terms = [(((0, 0), (1, 1)), np.real(synth.heisenberg_bond_hamiltonian()))]
+    with pytest.raises(hp.HpepsError):
+        hp.peps_energy_uncached(ctx, dev_lattice(peps), terms, rank=4)
+    with pytest.raises(hp.HpepsError):
+        hp.peps_energy_backward(ctx, dev_lattice(peps), terms, rank=4)

@@ -235,3 +235,16 @@ def test_trotter_expectation_is_first_order_in_tau():
         est, _ = energy.trotter_expectation(peps, gates, tau, BIG_M, 0, 0, 0)
         errs.append(abs(est.real - exact))
     assert 1.7 < errs[0] / errs[1] < 2.3 and 1.7 < errs[1] / errs[2] < 2.3
+
+
+@pytest.mark.parametrize("shape,cplx", [((3, 3), True), ((3, 4), False), ((4, 3), True)])
+def test_cached_energy_with_diagonal_terms_equals_brute_force(shape, cplx):
+    """J1-J2 terms (Eq. 7): nearest, both diagonal directions and fields, each
+    term against the state vector in the exact regime."""
+    nrow, ncol = shape
+    peps = synth.random_peps(nrow, ncol, D=2, seed=nrow * ncol, complex_=cplx)
+    terms = synth.j1j2_terms(nrow, ncol)
+    psi = sv.peps_to_statevector(peps)
+    ref = [sv.expectation(psi, [t], ncol) for t in terms]
+    _, per = energy.peps_energy_cached(peps, terms, m=BIG_M, p=0, q=0, seed=0)
+    assert np.allclose(per, ref, rtol=1e-10, atol=1e-11)
