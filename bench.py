@@ -853,27 +853,40 @@ def main():
         "kernel_classes": {n: class_entry(a, pair_alg_ratio(n))
                            for n, a in sorted(agg.items(), key=lambda x: -x[1]["ms"])},
     }
+    def progress(name):
+        print(f"[bench] {name} done", file=sys.stderr, flush=True)
+
+    progress("einsumsvd pair")
     res["c1_norm_latency"] = c1_latency(hp)
+    progress("c1")
     if not args.no_c3:
         res["c3_norm"], ctx3 = c3_norm(hp, args)
         hp.autotune_import(ctx, hp.autotune_export(ctx3))
         del ctx3
+        progress("c3")
     if args.c4 > 0:
         res["c4_ite"] = c4_ite(hp, args.c4)
+        progress("c4")
     if args.amp > 0:
         res["amplitude"], actx = amplitudes(hp, args, args.amp)
         hp.autotune_import(ctx, hp.autotune_export(actx))   # its tuned products join the saved set
+        progress("amplitudes")
     if args.bmps > 0:
         res["bmps_vs_ibmps"] = bmps_vs_ibmps(hp, args.bmps)
+        progress("bmps vs ibmps")
     if not args.no_caching:
         res["caching"] = caching(hp)
+        progress("caching")
     if not args.no_j1j2:
         res["j1j2"] = j1j2_vqe(hp)
+        progress("j1j2")
     if args.c5 > 0:
         res["c5_gradient"] = c5_gradient(hp, args.c5)
+        progress("c5")
     if args.d8 > 0:
         del dev, out, out32, out16, oute
         res["variant_d8"] = d8_variant(hp, ctx, args.d8)
+        progress("d8")
     if args.cpu_sample > 0:
         res["cpu_baseline"] = cpu_baseline(args.cpu_sample)
     if args.save_tune_cache:
