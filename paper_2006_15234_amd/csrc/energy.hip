@@ -355,113 +355,147 @@ std::vector<const double*> energy_rdms(Ctx& c, const Lattice& K, int n_terms, co
   const int64_t slot = (int64_t)d * d * d * d * es;
   double* rdm_store = c.ws<double>(std::max<int64_t>(n_terms, 1) * slot);
 
-  // three-layer strips: one-site and horizontal terms
+  // a strip's inputs for the checkpoint: its environments and sites
+  auto strip_inputs = [&](const std::vector<DevTensor>& top, const std::vector<DevTensor>& bot, int r0, int r1) {
+    std::vector<std::pair<const void*, int64_t>> in;
+    for (int j = 0; j < ncol; ++j) {
+      in.push_back({top[j].p, top[j].size()});
+      in.push_back({bot[j].p, bot[j].size()});
+      for (int r = r0; r <= r1; ++r) in.push_back({Kn.at(r, j).p, Kn.at(r, j).size()});
+    }
+    return in;
+  };
+
+  // three-layer strips: one-site and horizontal terms (each strip one
+  // checkpointed segment under a tape)
   for (int i = 0; i < nrow; ++i) {
     std::vector<int> here;
     for (int t = 0; t < n_terms; ++t)
       if (sites[4 * t] == i && (nsites[t] == 1 || sites[4 * t + 2] == i)) here.push_back(t);
     if (here.empty()) continue;
-    WsScope strip_scope(c);
-    const auto& top = top_of(i);
-    const auto& bot = bot_of(i);
-    auto col = [&](int j, Dir dir, BndView& tv, SiteView& kv, SiteView& bv, BndView& btv) {
-      tv = orient_bnd(top[j], dir);
-      kv = orient_site(Kn.at(i, j), kTop, dir);
-      bv = kv;
-      btv = orient_bnd(bot[j], dir);
-    };
-    std::vector<Ten> Lenv(ncol + 1), Renv(ncol + 1);
-    Lenv[0] = ones(c, cplx, "tlLb");
-    Renv[0] = ones(c, cplx, "tlLb");
-    for (int q = 0; q < ncol; ++q) {
-      BndView tv, btv;
-      SiteView kv, bv;
-      col(q, kL2R, tv, kv, bv, btv);
-      Ten x = transfer3(c, cplx, Lenv[q], tv, kv, bv, btv, false);
-      normalize(c, cplx, x.p, x.size(), 1, logd);
-      x.legs = "tlLb";
-      Lenv[q + 1] = x;
-      col(ncol - 1 - q, kR2L, tv, kv, bv, btv);
-      Ten y = transfer3(c, cplx, Renv[q], tv, kv, bv, btv, false);
-      normalize(c, cplx, y.p, y.size(), 1, logd);
-      y.legs = "tlLb";
-      Renv[q + 1] = y;
-    }
-    std::map<std::pair<int, int>, const double*> cache;  // (j, 1|2) -> rdm
+    // one reduced density matrix per (column, kind)
+    std::vector<std::pair<int, int>> keys;
+    std::vector<std::pair<void*, int64_t>> outs;
     for (int t : here) {
-      const int j = sites[4 * t + 1];
-      const int kind = nsites[t];
-      auto key = std::make_pair(j, kind);
-      if (!cache.count(key)) {
+      const auto key = std::make_pair((int)sites[4 * t + 1], (int)nsites[t]);
+      size_t k = 0;
+      while (k < keys.size() && keys[k] != key) ++k;
+      if (k == keys.size()) {
+        keys.push_back(key);
+        outs.push_back({rdm_store + (int64_t)t * slot, slot / es});
+      }
+      rdm_ptr[t] = (const double*)outs[k].first;
+    }
+    const std::vector<DevTensor> top = top_of(i), bot = bot_of(i);
+    std::vector<DevTensor> row;
+    for (int j = 0; j < ncol; ++j) row.push_back(Kn.at(i, j));
+    auto run = [cplx, ncol, top, bot, row, keys, logd, slot, es](Ctx& c, const std::vector<void*>& dst) {
+      WsScope strip_scope(c);
+      auto col = [&](int j, Dir dir, BndView& tv, SiteView& kv, SiteView& bv, BndView& btv) {
+        tv = orient_bnd(top[j], dir);
+        kv = orient_site(row[j], kTop, dir);
+        bv = kv;
+        btv = orient_bnd(bot[j], dir);
+      };
+      std::vector<Ten> Lenv(ncol + 1), Renv(ncol + 1);
+      Lenv[0] = ones(c, cplx, "tlLb");
+      Renv[0] = ones(c, cplx, "tlLb");
+      for (int q = 0; q < ncol; ++q) {
+        BndView tv, btv;
+        SiteView kv, bv;
+        col(q, kL2R, tv, kv, bv, btv);
+        Ten x = transfer3(c, cplx, Lenv[q], tv, kv, bv, btv, false);
+        normalize(c, cplx, x.p, x.size(), 1, logd);
+        x.legs = "tlLb";
+        Lenv[q + 1] = x;
+        col(ncol - 1 - q, kR2L, tv, kv, bv, btv);
+        Ten y = transfer3(c, cplx, Renv[q], tv, kv, bv, btv, false);
+        normalize(c, cplx, y.p, y.size(), 1, logd);
+        y.legs = "tlLb";
+        Renv[q + 1] = y;
+      }
+      for (size_t k = 0; k < keys.size(); ++k) {
+        const int j = keys[k].first, kind = keys[k].second;
         BndView tv, btv;
         SiteView kv, bv;
         col(j, kL2R, tv, kv, bv, btv);
-        double* dst = rdm_store + (int64_t)t * slot;
         Ten y = transfer3(c, cplx, Lenv[j], tv, kv, bv, btv, true);  // srRcpP
         if (kind == 1) {
           Ten R = Renv[ncol - 1 - j];
           R.legs = "srRc";
-          contract2(c, cplx, y.view(), R.view(), "pP", dst, slot / es);
+          contract2(c, cplx, y.view(), R.view(), "pP", dst[k], slot / es);
         } else {
           y.legs = "tlLbef";
           col(j + 1, kL2R, tv, kv, bv, btv);
           Ten y2 = transfer3(c, cplx, y, tv, kv, bv, btv, true);  // efsrRcpP
           Ten R = Renv[ncol - 2 - j];
           R.legs = "srRc";
-          contract2(c, cplx, y2.view(), R.view(), "efpP", dst, slot / es);
+          contract2(c, cplx, y2.view(), R.view(), "efpP", dst[k], slot / es);
         }
-        cache[key] = dst;
       }
-      rdm_ptr[t] = cache[key];
-    }
+    };
+    run_segment(c, cplx, strip_inputs(top, bot, i, i), outs, run);
   }
-  // four-layer strips: vertical terms
+  // four-layer strips: vertical and diagonal terms
   for (int i = 0; i + 1 < nrow; ++i) {
     std::vector<int> here;
     for (int t = 0; t < n_terms; ++t)
       if (nsites[t] == 2 && sites[4 * t] == i && sites[4 * t + 2] == i + 1) here.push_back(t);
     if (here.empty()) continue;
-    WsScope strip_scope(c);
-    const auto& top = top_of(i);
-    const auto& bot = bot_of(i + 1);
-    auto col = [&](int j, Dir dir, BndView& tv, SiteView& k1, SiteView& k2, BndView& btv) {
-      tv = orient_bnd(top[j], dir);
-      k1 = orient_site(Kn.at(i, j), kTop, dir);
-      k2 = orient_site(Kn.at(i + 1, j), kTop, dir);
-      btv = orient_bnd(bot[j], dir);
-    };
-    std::vector<Ten> Lenv(ncol + 1), Renv(ncol + 1);
-    Lenv[0] = ones(c, cplx, "tlLmMb");
-    Renv[0] = ones(c, cplx, "tlLmMb");
-    for (int q = 0; q < ncol; ++q) {
-      BndView tv, btv;
-      SiteView k1, k2;
-      col(q, kL2R, tv, k1, k2, btv);
-      Ten x = transfer4(c, cplx, Lenv[q], tv, k1, k1, k2, k2, btv, false, false);
-      normalize(c, cplx, x.p, x.size(), 1, logd);
-      x.legs = "tlLmMb";
-      Lenv[q + 1] = x;
-      col(ncol - 1 - q, kR2L, tv, k1, k2, btv);
-      Ten y = transfer4(c, cplx, Renv[q], tv, k1, k1, k2, k2, btv, false, false);
-      normalize(c, cplx, y.p, y.size(), 1, logd);
-      y.legs = "tlLmMb";
-      Renv[q + 1] = y;
-    }
     // (column of site 1, column of site 2) -> rdm [p1,P1,p2,P2]
-    std::map<std::pair<int, int>, const double*> cache;
+    std::vector<std::pair<int, int>> keys;
+    std::vector<std::pair<void*, int64_t>> outs;
     for (int t : here) {
-      const int j = sites[4 * t + 1], j2 = sites[4 * t + 3];
-      const auto key = std::make_pair(j, j2);
-      if (!cache.count(key)) {
+      const auto key = std::make_pair((int)sites[4 * t + 1], (int)sites[4 * t + 3]);
+      size_t k = 0;
+      while (k < keys.size() && keys[k] != key) ++k;
+      if (k == keys.size()) {
+        keys.push_back(key);
+        outs.push_back({rdm_store + (int64_t)t * slot, slot / es});
+      }
+      rdm_ptr[t] = (const double*)outs[k].first;
+    }
+    const std::vector<DevTensor> top = top_of(i), bot = bot_of(i + 1);
+    std::vector<DevTensor> r1, r2;
+    for (int j = 0; j < ncol; ++j) {
+      r1.push_back(Kn.at(i, j));
+      r2.push_back(Kn.at(i + 1, j));
+    }
+    auto run = [cplx, ncol, top, bot, r1, r2, keys, logd, slot, es](Ctx& c, const std::vector<void*>& dst) {
+      WsScope strip_scope(c);
+      auto col = [&](int j, Dir dir, BndView& tv, SiteView& k1, SiteView& k2, BndView& btv) {
+        tv = orient_bnd(top[j], dir);
+        k1 = orient_site(r1[j], kTop, dir);
+        k2 = orient_site(r2[j], kTop, dir);
+        btv = orient_bnd(bot[j], dir);
+      };
+      std::vector<Ten> Lenv(ncol + 1), Renv(ncol + 1);
+      Lenv[0] = ones(c, cplx, "tlLmMb");
+      Renv[0] = ones(c, cplx, "tlLmMb");
+      for (int q = 0; q < ncol; ++q) {
         BndView tv, btv;
         SiteView k1, k2;
-        double* dst = rdm_store + (int64_t)t * slot;
+        col(q, kL2R, tv, k1, k2, btv);
+        Ten x = transfer4(c, cplx, Lenv[q], tv, k1, k1, k2, k2, btv, false, false);
+        normalize(c, cplx, x.p, x.size(), 1, logd);
+        x.legs = "tlLmMb";
+        Lenv[q + 1] = x;
+        col(ncol - 1 - q, kR2L, tv, k1, k2, btv);
+        Ten y = transfer4(c, cplx, Renv[q], tv, k1, k1, k2, k2, btv, false, false);
+        normalize(c, cplx, y.p, y.size(), 1, logd);
+        y.legs = "tlLmMb";
+        Renv[q + 1] = y;
+      }
+      for (size_t k = 0; k < keys.size(); ++k) {
+        const int j = keys[k].first, j2 = keys[k].second;
+        BndView tv, btv;
+        SiteView k1, k2;
         if (j2 == j) {
           col(j, kL2R, tv, k1, k2, btv);
           Ten y = transfer4(c, cplx, Lenv[j], tv, k1, k1, k2, k2, btv, true, true);  // srRnNcpPqQ
           Ten R = Renv[ncol - 1 - j];
           R.legs = "srRnNc";
-          contract2(c, cplx, y.view(), R.view(), "pPqQ", dst, slot / es);
+          contract2(c, cplx, y.view(), R.view(), "pPqQ", dst[k], slot / es);
         } else {
           // diagonal pair over columns a < a + 1: the first column opens the
           // site it holds, its open legs ride along as spectators (ef)
@@ -475,12 +509,11 @@ std::vector<const double*> energy_rdms(Ctx& c, const Lattice& K, int n_terms, co
           Ten R = Renv[ncol - 2 - a];
           R.legs = "srRnNc";
           // y2 legs: ef (first column's open pair) + srRnNc + the second column's open pair
-          contract2(c, cplx, y2.view(), R.view(), first_upper ? "efqQ" : "pPef", dst, slot / es);
+          contract2(c, cplx, y2.view(), R.view(), first_upper ? "efqQ" : "pPef", dst[k], slot / es);
         }
-        cache[key] = dst;
       }
-      rdm_ptr[t] = cache[key];
-    }
+    };
+    run_segment(c, cplx, strip_inputs(top, bot, i, i + 1), outs, run);
   }
   return rdm_ptr;
 }

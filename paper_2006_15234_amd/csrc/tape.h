@@ -17,6 +17,7 @@
 //     recorded inputs: per-einsumsvd checkpoint and recompute);
 //   * exact carry:              carry_backward;
 //   * copy dst = src:           adj(src) += adj(dst);
+//   * segment (checkpoint):     an energy strip, handled like a row below;
 //   * zip-up row (checkpoint):  the row ran unrecorded in the forward pass;
 //     the reverse walk reruns it from its recorded input boundary and sites
 //     on a tape of its own, seeds that tape with the adjoints of the row's
@@ -25,6 +26,7 @@
 //     is kept between the passes).
 // Only values that depend on an input marked with mark_input get adjoints.
 #pragma once
+#include <functional>
 #include <map>
 #include <set>
 #include <vector>
@@ -37,10 +39,22 @@ namespace hp {
 
 struct RowCheckpoint;  // peps.h
 
+// A checkpointed segment of the forward pass (one energy strip): its inputs
+// and outputs, and a closure that reruns it writing the outputs to the given
+// buffers (in the order of `outputs`).
+struct SegmentCheckpoint {
+  bool cplx = false;
+  std::vector<std::pair<const void*, int64_t>> inputs;   // (pointer, elements)
+  std::vector<std::pair<void*, int64_t>> outputs;        // (pointer, elements)
+  std::function<void(Ctx&, const std::vector<void*>&)> rerun;
+};
+
 struct TapeOp {
-  enum Kind { GEMM, SCALE, ZIP, CARRY, COPY, ROW } kind = GEMM;
+  enum Kind { GEMM, SCALE, ZIP, CARRY, COPY, ROW, SEG } kind = GEMM;
   // ROW
   std::shared_ptr<const RowCheckpoint> row;
+  // SEG
+  std::shared_ptr<const SegmentCheckpoint> seg;
   bool cplx = false;
   // GEMM
   Prec prec = Prec::F64;
@@ -114,6 +128,12 @@ struct TapeSuspend {
 bool taping(const Ctx& ctx);
 // reverse step of a checkpointed row (peps.hip): recompute, local tape, adjoints
 void row_backward(Ctx& ctx, const RowCheckpoint& r, Tape& main, double broadening);
+// Runs `run` (writing the listed outputs) unrecorded and records one segment
+// op in its place when a tape records with Ctx::checkpoint_rows; otherwise
+// runs it recorded (or plainly, without a tape).
+void run_segment(Ctx& ctx, bool cplx, const std::vector<std::pair<const void*, int64_t>>& inputs,
+                 const std::vector<std::pair<void*, int64_t>>& outputs,
+                 std::function<void(Ctx&, const std::vector<void*>&)> run);
 void tape_zip(Ctx& ctx, bool cplx, const ZipDims& z, const ZipLayout& L, const ZipOperands& op, int batch,
               const hpeps_esvd_opts& o, hpeps_absorb absorb, const ZipOut& out, void* U, void* R);
 void tape_carry(Ctx& ctx, bool cplx, const CarryDims& cd, const CarryLayout& cl, const void* Lm, const void* T,

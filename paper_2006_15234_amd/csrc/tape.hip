@@ -20,6 +20,8 @@ int64_t batched(int64_t one, int64_t stride, int batch) { return one + (int64_t)
 }  // namespace
 
 bool taping(const Ctx& ctx) { return ctx.tape && ctx.tape->active(); }
+
+void segment_backward(Ctx& ctx, const SegmentCheckpoint& g, Tape& main, double broadening);
 bool tape_keeps_workspace(const Ctx& ctx) { return taping(ctx); }
 
 TapeSuspend::TapeSuspend(Ctx& ctx) : c(ctx) {
@@ -104,6 +106,13 @@ void Tape::record(const TapeOp& op) {
         dep_.insert(r.R);
       }
       break;
+    case TapeOp::SEG: {
+      for (const auto& e : r.seg->inputs) rd(e.first, e.second);
+      for (const auto& e : r.seg->outputs) note_write(e.first, e.second);
+      if (dep)
+        for (const auto& e : r.seg->outputs) dep_.insert(e.first);
+      break;
+    }
     case TapeOp::ROW: {
       const RowCheckpoint& w = *r.row;
       for (const auto& b : w.bnd) rd(b.p, b.extent);
@@ -234,6 +243,9 @@ void Tape::backward(Ctx& ctx, double broadening) {
       case TapeOp::ROW:
         row_backward(ctx, *r.row, *this, broadening);
         break;
+      case TapeOp::SEG:
+        segment_backward(ctx, *r.seg, *this, broadening);
+        break;
       case TapeOp::CARRY: {
         const double* gVc = grad_if_live(r.V);
         if (!gVc) break;
@@ -310,6 +322,78 @@ void tape_carry(Ctx& ctx, bool, const CarryDims& cd, const CarryLayout& cl, cons
   op.V = V;
   op.batch = batch;
   ctx.tape->record(op);
+}
+
+void run_segment(Ctx& ctx, bool cplx, const std::vector<std::pair<const void*, int64_t>>& inputs,
+                 const std::vector<std::pair<void*, int64_t>>& outputs,
+                 std::function<void(Ctx&, const std::vector<void*>&)> run) {
+  std::vector<void*> outs;
+  for (const auto& e : outputs) outs.push_back(e.first);
+  if (!taping(ctx) || !ctx.checkpoint_rows) {
+    run(ctx, outs);
+    return;
+  }
+  {
+    TapeSuspend unrecorded(ctx);  // the segment's workspace is released at its end
+    WsScope scope(ctx);
+    run(ctx, outs);
+  }
+  auto seg = std::make_shared<SegmentCheckpoint>();
+  seg->cplx = cplx;
+  seg->inputs = inputs;
+  seg->outputs = outputs;
+  seg->rerun = std::move(run);
+  TapeOp op;
+  op.kind = TapeOp::SEG;
+  op.seg = seg;
+  ctx.tape->record(op);
+}
+
+// The reverse step of a checkpointed segment: rerun it on a tape of its own
+// into fresh outputs, seed that tape with the adjoints of the recorded
+// outputs, walk it back and add the adjoints of the inputs.
+void segment_backward(Ctx& ctx, const SegmentCheckpoint& g, Tape& main, double broadening) {
+  const int es = g.cplx ? 2 : 1;
+  bool any = false;
+  for (const auto& e : g.outputs) any = any || main.grad_if_live(e.first);
+  if (!any) return;
+  std::vector<std::pair<const void*, int64_t>> ins;
+  for (const auto& e : g.inputs) {
+    if (!main.depends(e.first)) continue;
+    bool seen = false;
+    for (auto& x : ins)
+      if (x.first == e.first) {
+        x.second = std::max(x.second, e.second);
+        seen = true;
+      }
+    if (!seen) ins.push_back(e);
+  }
+  std::vector<double*> gmain;
+  for (auto& e : ins) gmain.push_back(main.grad(ctx, e.first));
+  WsScope scope(ctx);
+  std::vector<void*> outs;
+  for (const auto& e : g.outputs) outs.push_back(ctx.ws<double>(e.second * es));
+  Tape sub(g.cplx);
+  for (auto& e : ins) sub.mark_input(e.first, e.second);
+  ctx.tape = &sub;
+  try {
+    g.rerun(ctx, outs);
+  } catch (...) {
+    ctx.tape = nullptr;
+    throw;
+  }
+  ctx.tape = nullptr;
+  for (size_t q = 0; q < g.outputs.size(); ++q) {
+    const double* gm = main.grad_if_live(g.outputs[q].first);
+    if (gm && sub.depends(outs[q]))
+      HP_CHECK_HIP(hipMemcpyAsync(sub.grad(ctx, outs[q]), gm, g.outputs[q].second * es * sizeof(double),
+                                  hipMemcpyDeviceToDevice, ctx.stream));
+  }
+  sub.backward(ctx, broadening);
+  for (size_t i = 0; i < ins.size(); ++i) {
+    const double* gs = sub.grad_if_live(ins[i].first);
+    if (gs) axpy(ctx, gmain[i], gs, 1.0, ins[i].second * es);
+  }
 }
 
 }  // namespace hp
