@@ -281,6 +281,7 @@ __global__ __launch_bounds__(kT) void qrsvd_bond_kernel(IteArgs a) {
   __shared__ double Th[kMaxTh * kMaxTh];                    // Theta, column-major (col * nr + row)
   __shared__ double J[kMaxTh * kMaxTh];                     // right vectors, column-major
   __shared__ double tau1[kMaxC], tau2[kMaxC];
+  __shared__ double tauT[kMaxTh], alphaT[kMaxTh];  // Householder QR of Theta
   __shared__ double red[kT / 64];
   __shared__ double sig[kMaxTh], sv[kMaxTh];
   __shared__ long long coff1[kMaxC], coff2[kMaxC];
@@ -351,12 +352,90 @@ __global__ __launch_bounds__(kT) void qrsvd_bond_kernel(IteArgs a) {
       }
     Th[e] = acc;
   }
-  for (int e = tid; e < nc * nc; e += kT) J[e] = (e / nc == e % nc) ? 1.0 : 0.0;
   __syncthreads();
 
-  // ---- one-sided Jacobi on the columns of Theta (J accumulates) ----------
+  // ---- Theta = Q R (Householder), K = R^T, Q explicit --------------------
+  // One-sided Jacobi on the columns of K = R^T converges in far fewer sweeps
+  // than on Theta itself (the rows of R are graded: 6-8 sweeps instead of
+  // 14-18 on the spectra of these updates); the rotations are mirrored on
+  // the columns of Q, so that at the end Theta = (Q J) Sigma W^T with
+  // W = K J Sigma^-1: the left vectors are Q's rotated columns, the right
+  // vectors K's rotated columns normalised.  Q is accumulated in J's
+  // storage during the factorization, K then overwrites Theta's.
+  double fro2 = 0;
+  {
+    double f2 = 0;
+    for (int e = tid; e < nr * nc; e += kT) f2 += Th[e] * Th[e];
+    f2 = wave_sum(f2);
+    if (lane == 0) red[wave] = f2;
+    __syncthreads();
+    for (int w = 0; w < nw; ++w) fro2 += red[w];
+  }
+  const int nk = min(nr, nc);
+  // Q accumulates Q := Q H_j (nr x nr, in J's storage); 16-lane groups own a
+  // trailing column of Theta and a row of Q each (lanes: rows / columns gl
+  // and gl + 16), with DPP row sums for the dot products
+  const int qg = tid >> 4, ql = tid & 15;
+  for (int e = tid; e < nr * nr; e += kT) J[e] = (e / nr == e % nr) ? 1.0 : 0.0;
+  __syncthreads();
+  for (int j = 0; j < nk; ++j) {
+    if (qg == 0) {
+      const double x0 = ql >= j && ql < nr ? Th[j * nr + ql] : 0.0;
+      const double x1 = ql + 16 >= j && ql + 16 < nr ? Th[j * nr + ql + 16] : 0.0;
+      const double n2 = row_sum16(x0 * x0 + x1 * x1);
+      if (ql == 0) {
+        const double xj = Th[j * nr + j];
+        const double al = n2 > 0 ? -copysign(sqrt(n2), xj) : 0.0;
+        const double v0 = xj - al;
+        const double vn2 = n2 - xj * xj + v0 * v0;
+        tauT[j] = vn2 > 0 ? 2.0 / vn2 : 0.0;
+        alphaT[j] = al;
+        Th[j * nr + j] = v0;  // v: rows >= j of column j
+      }
+    }
+    __syncthreads();
+    const double t = tauT[j];
+    const double v0r = ql >= j && ql < nr ? Th[j * nr + ql] : 0.0;
+    const double v1r = ql + 16 >= j && ql + 16 < nr ? Th[j * nr + ql + 16] : 0.0;
+    // trailing columns l = j + 1 + qg (+ 16): y -= tau (v^T y) v over rows >= j
+    for (int l = j + 1 + qg; l < nc; l += 16) {
+      double* y = Th + l * nr;
+      const double y0 = ql < nr ? y[ql] : 0.0, y1 = ql + 16 < nr ? y[ql + 16] : 0.0;
+      const double w = t * row_sum16(v0r * y0 + v1r * y1);
+      if (ql >= j && ql < nr) y[ql] = y0 - w * v0r;
+      if (ql + 16 >= j && ql + 16 < nr) y[ql + 16] = y1 - w * v1r;
+    }
+    // rows i = qg (+ 16) of Q: q -= tau (q . v) v^T over columns >= j
+    for (int i = qg; i < nr; i += 16) {
+      const double q0 = ql < nr ? J[ql * nr + i] : 0.0, q1 = ql + 16 < nr ? J[(ql + 16) * nr + i] : 0.0;
+      const double w = t * row_sum16(q0 * v0r + q1 * v1r);
+      if (ql >= j && ql < nr) J[ql * nr + i] = q0 - w * v0r;
+      if (ql + 16 >= j && ql + 16 < nr) J[(ql + 16) * nr + i] = q1 - w * v1r;
+    }
+    __syncthreads();
+  }
+  // K[c][i] = R[c][i] (row c of R as column c of K, length nc) in Theta's
+  // storage, through registers (the two layouts overlap)
+  double kv[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int e = tid + q * kT;
+    const int c = e / nc, i = e - c * nc;
+    kv[q] = (e >= nk * nc || i < c) ? 0.0 : (i == c ? alphaT[c] : Th[i * nr + c]);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int e = tid + q * kT;
+    if (e < nk * nc) Th[e] = kv[q];
+  }
+  __syncthreads();
+  // the roles of the two buffers below: K in Th (column c at c * nc, length
+  // nc), Q in J (column c at c * nr, length nr)
+
+  // ---- one-sided Jacobi on the columns of K (Q's columns rotated alike) --
   // A pair (x, y) with Gram entries a2 = |x|^2, b2 = |y|^2, g = x.y is
-  // rotated while |g| exceeds both sqrt(nr) eps |x| |y| (relative
+  // rotated while |g| exceeds both sqrt(nc) eps |x| |y| (relative
   // convergence) and delta ||Theta||_F max(|x|, |y|), delta = 512 eps.
   // Leaving a pair unrotated moves its singular values by at most
   // |g| / max(|x|, |y|) (the degenerate case) and the two-site product by
@@ -365,19 +444,10 @@ __global__ __launch_bounds__(kT) void qrsvd_bond_kernel(IteArgs a) {
   // stops the rotations among columns of rounding noise (rank-deficient
   // Theta near product states), whose correlations stay O(1) relative to
   // their norms.
-  {
-    double f2 = 0;
-    for (int e = tid; e < nr * nc; e += kT) f2 += Th[e] * Th[e];
-    f2 = wave_sum(f2);
-    if (lane == 0) red[wave] = f2;
-  }
-  __syncthreads();
-  double fro2 = 0;
-  for (int w = 0; w < nw; ++w) fro2 += red[w];
   const double acc2 = 0x1p-86 * fro2;  // (delta ||Theta||_F)^2, delta = 512 eps = 2^-43
-  const int n = (nc + 1) / 2 * 2;
-  const double tol2 = (double)nr * 0x1p-104;  // (sqrt(nr) eps)^2
-  // one 16-lane group per column pair (nc <= 32: at most 16 pairs per round,
+  const int n = (nk + 1) / 2 * 2;
+  const double tol2 = (double)nc * 0x1p-104;  // (sqrt(nc) eps)^2
+  // one 16-lane group per column pair (nk <= 32: at most 16 pairs per round,
   // all in flight at once); a group reduces over the rows with DPP row sums
   const int grp = tid >> 4, gl = tid & 15;
   for (int sweep = 0; sweep < 60; ++sweep) {
@@ -386,7 +456,7 @@ __global__ __launch_bounds__(kT) void qrsvd_bond_kernel(IteArgs a) {
     for (int round = 0; round < n - 1; ++round) {
       // circle positions; (pos - 1 + round) mod (n - 1) by one conditional
       // subtraction (both terms are below n - 1)
-      int ca = nc, cb = nc;
+      int ca = nk, cb = nk;
       if (grp < n / 2) {
         int ta = grp - 1 + round;
         ta -= ta >= n - 1 ? n - 1 : 0;
@@ -395,18 +465,18 @@ __global__ __launch_bounds__(kT) void qrsvd_bond_kernel(IteArgs a) {
         tb -= tb >= n - 1 ? n - 1 : 0;
         cb = 1 + tb;
       }
-      const bool act = ca < nc && cb < nc;
-      double* x = Th + (act ? ca : 0) * nr;
-      double* y = Th + (act ? cb : 0) * nr;
-      // rows gl and gl + 16 of the pair (nr, nc <= 32)
-      const bool in0 = act && gl < nr, in1 = act && gl + 16 < nr;
+      const bool act = ca < nk && cb < nk;
+      double* x = Th + (act ? ca : 0) * nc;
+      double* y = Th + (act ? cb : 0) * nc;
+      // rows gl and gl + 16 of the pair (nc <= 32)
+      const bool in0 = act && gl < nc, in1 = act && gl + 16 < nc;
       const double x0 = in0 ? x[gl] : 0.0, y0 = in0 ? y[gl] : 0.0;
       const double x1 = in1 ? x[gl + 16] : 0.0, y1 = in1 ? y[gl + 16] : 0.0;
       double a2 = x0 * x0 + x1 * x1, b2 = y0 * y0 + y1 * y1, gm = x0 * y0 + x1 * y1;
       a2 = row_sum16(a2);
       b2 = row_sum16(b2);
       gm = row_sum16(gm);
-      // |gm| > sqrt(nr) eps sqrt(a2 b2) without square roots; the rotation
+      // |gm| > sqrt(nc) eps sqrt(a2 b2) without square roots; the rotation
       // t = tan(theta) = sign(dl) 2 gm / (|dl| + sqrt(dl^2 + 4 gm^2)), dl = b2 - a2
       if (act && gm * gm > tol2 * a2 * b2 && gm * gm > acc2 * fmax(a2, b2)) {
         const double dl = b2 - a2;
@@ -420,18 +490,18 @@ __global__ __launch_bounds__(kT) void qrsvd_bond_kernel(IteArgs a) {
           x[gl + 16] = c * x1 - sn * y1;
           y[gl + 16] = sn * x1 + c * y1;
         }
-        double* jx = J + ca * nc;
-        double* jy = J + cb * nc;
-        const bool j0 = gl < nc, j1 = gl + 16 < nc;
-        const double jx0 = j0 ? jx[gl] : 0.0, jy0 = j0 ? jy[gl] : 0.0;
-        const double jx1 = j1 ? jx[gl + 16] : 0.0, jy1 = j1 ? jy[gl + 16] : 0.0;
+        double* qx = J + ca * nr;
+        double* qy = J + cb * nr;
+        const bool j0 = gl < nr, j1 = gl + 16 < nr;
+        const double qx0 = j0 ? qx[gl] : 0.0, qy0 = j0 ? qy[gl] : 0.0;
+        const double qx1 = j1 ? qx[gl + 16] : 0.0, qy1 = j1 ? qy[gl + 16] : 0.0;
         if (j0) {
-          jx[gl] = c * jx0 - sn * jy0;
-          jy[gl] = sn * jx0 + c * jy0;
+          qx[gl] = c * qx0 - sn * qy0;
+          qy[gl] = sn * qx0 + c * qy0;
         }
         if (j1) {
-          jx[gl + 16] = c * jx1 - sn * jy1;
-          jy[gl + 16] = sn * jx1 + c * jy1;
+          qx[gl + 16] = c * qx1 - sn * qy1;
+          qy[gl + 16] = sn * qx1 + c * qy1;
         }
         if (gl == 0) rot = 1;
       }
@@ -441,20 +511,20 @@ __global__ __launch_bounds__(kT) void qrsvd_bond_kernel(IteArgs a) {
     __syncthreads();
     if (done) break;
   }
-  for (int c = wave; c < nc; c += nw) {
+  for (int c = wave; c < nk; c += nw) {
     double a2 = 0;
-    for (int r = lane; r < nr; r += 64) a2 += Th[(long long)c * nr + r] * Th[(long long)c * nr + r];
+    for (int r = lane; r < nc; r += 64) a2 += Th[(long long)c * nc + r] * Th[(long long)c * nc + r];
     a2 = wave_sum(a2);
     if (lane == 0) sig[c] = sqrt(a2);
   }
   __syncthreads();
-  const int Dn = min(a.dmax, min(nr, nc));
+  const int Dn = min(a.dmax, nk);
   // descending order, ties by index: the rank of value i is the number of
   // values that precede it
-  if (tid < nc) {
+  if (tid < nk) {
     const double v = sig[tid];
     int rank = 0;
-    for (int j = 0; j < nc; ++j) rank += (sig[j] > v) || (sig[j] == v && j < tid);
+    for (int j = 0; j < nk; ++j) rank += (sig[j] > v) || (sig[j] == v && j < tid);
     perm[rank] = tid;
   }
   __syncthreads();
@@ -487,8 +557,8 @@ __global__ __launch_bounds__(kT) void qrsvd_bond_kernel(IteArgs a) {
           const int c = perm[b];
           const double sg = sig[c];
           const double rs = sqrt(sv[b]);
-          if (s == 0) v = sg > 0 ? Th[(long long)c * nr + row * d + aa] / sg * rs : 0.0;  // X[(row,aa),b]
-          else v = J[(long long)c * nc + aa * k2 + row] * rs;                               // Y[(aa,row),b]
+          if (s == 0) v = J[(long long)c * nr + row * d + aa] * rs;                         // X[(row,aa),b]
+          else v = sg > 0 ? Th[(long long)c * nc + aa * k2 + row] / sg * rs : 0.0;          // Y[(aa,row),b]
         }
         B[q][col] = v;
       }
