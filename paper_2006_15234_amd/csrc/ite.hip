@@ -472,16 +472,27 @@ __global__ __launch_bounds__(kT) void qrsvd_bond_kernel(IteArgs a) {
       const bool in0 = act && gl < nc, in1 = act && gl + 16 < nc;
       const double x0 = in0 ? x[gl] : 0.0, y0 = in0 ? y[gl] : 0.0;
       const double x1 = in1 ? x[gl + 16] : 0.0, y1 = in1 ? y[gl + 16] : 0.0;
+      // Q's rows of the pair, loaded with the pair (off the critical path)
+      double* qx = J + (act ? ca : 0) * nr;
+      double* qy = J + (act ? cb : 0) * nr;
+      const bool j0 = act && gl < nr, j1 = act && gl + 16 < nr;
+      const double qx0 = j0 ? qx[gl] : 0.0, qy0 = j0 ? qy[gl] : 0.0;
+      const double qx1 = j1 ? qx[gl + 16] : 0.0, qy1 = j1 ? qy[gl + 16] : 0.0;
       double a2 = x0 * x0 + x1 * x1, b2 = y0 * y0 + y1 * y1, gm = x0 * y0 + x1 * y1;
       a2 = row_sum16(a2);
       b2 = row_sum16(b2);
       gm = row_sum16(gm);
-      // |gm| > sqrt(nc) eps sqrt(a2 b2) without square roots; the rotation
-      // t = tan(theta) = sign(dl) 2 gm / (|dl| + sqrt(dl^2 + 4 gm^2)), dl = b2 - a2
+      // |gm| > sqrt(nc) eps sqrt(a2 b2) without square roots.  The rotation
+      // (|theta| <= pi/4, tan 2 theta = 2 gm / dl, dl = b2 - a2) by two
+      // reciprocal square roots: with r = (dl^2 + 4 gm^2)^-1/2,
+      // C = cos 2 theta = |dl| r, S = sin 2 theta = sign(dl) 2 gm r and
+      // u = (2 (1 + C))^-1/2: cos theta = (1 + C) u, sin theta = S u.
       if (act && gm * gm > tol2 * a2 * b2 && gm * gm > acc2 * fmax(a2, b2)) {
         const double dl = b2 - a2;
-        const double t = (dl >= 0 ? 2.0 : -2.0) * gm / (fabs(dl) + sqrt(dl * dl + 4.0 * gm * gm));
-        const double c = rsqrt(1.0 + t * t), sn = c * t;  // 1 + t^2 in [1, 2]
+        const double r = rsqrt(dl * dl + 4.0 * gm * gm);
+        const double C = fabs(dl) * r, S = (dl >= 0 ? 2.0 : -2.0) * gm * r;
+        const double u = rsqrt(2.0 + 2.0 * C);
+        const double c = (1.0 + C) * u, sn = S * u;
         if (in0) {
           x[gl] = c * x0 - sn * y0;
           y[gl] = sn * x0 + c * y0;
@@ -490,11 +501,6 @@ __global__ __launch_bounds__(kT) void qrsvd_bond_kernel(IteArgs a) {
           x[gl + 16] = c * x1 - sn * y1;
           y[gl + 16] = sn * x1 + c * y1;
         }
-        double* qx = J + ca * nr;
-        double* qy = J + cb * nr;
-        const bool j0 = gl < nr, j1 = gl + 16 < nr;
-        const double qx0 = j0 ? qx[gl] : 0.0, qy0 = j0 ? qy[gl] : 0.0;
-        const double qx1 = j1 ? qx[gl + 16] : 0.0, qy1 = j1 ? qy[gl + 16] : 0.0;
         if (j0) {
           qx[gl] = c * qx0 - sn * qy0;
           qy[gl] = sn * qx0 + c * qy0;
