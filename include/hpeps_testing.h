@@ -71,7 +71,7 @@ hpeps_status hpeps_test_zip_apply(hpeps_ctx* ctx, hpeps_dtype dtype, int64_t bat
                                   const void* X, void* Y);
 
 /* Forces the launch variant of every following GEMM of the context (tile
- * shape index 0..9, K-step multiple 1 or 2, split-K count or 0 for the
+ * shape index 0..14, K-step multiple 1 or 2, split-K count or 0 for the
  * heuristic), so that the tests can cover each kernel instantiation;
  * tile = -1 returns to the normal selection.  Unknown or unsupported tile
  * indices fall back to the heuristic. */

@@ -854,6 +854,13 @@ const Cfg kCfgs[] = {
     {1, 4, 1, 4},  // 7: 16 x 256
     {4, 1, 4, 1},  // 8: 256 x 16
     {1, 4, 2, 2},  // 9: 32 x 128
+    // shapes that fit the bond-sized dimensions with little padding:
+    // M = 100 (112), M = 200 (208), N = 72 (80), N = 100 or 108 (112)
+    {1, 4, 7, 1},   // 10: 112 x 64
+    {1, 4, 13, 1},  // 11: 208 x 64
+    {4, 1, 1, 5},   // 12: 64 x 80
+    {4, 1, 2, 5},   // 13: 128 x 80
+    {4, 1, 1, 7},   // 14: 64 x 112
 };
 constexpr int kNumCfgs = sizeof(kCfgs) / sizeof(kCfgs[0]);
 
@@ -861,11 +868,13 @@ constexpr int kNumCfgs = sizeof(kCfgs) / sizeof(kCfgs[0]);
 // MFMA tiles per wavefront fit the register file
 bool cfg_ok(int ci, bool cplx) { return !cplx || kCfgs[ci].TM * kCfgs[ci].TN <= 4; }
 // the 32-deep K-step doubles the staging registers: complex products and the
-// 16-tile 128 x 128 shape would spill
-bool ks_ok(int ci, int ks, bool cplx) { return ks == 1 || (ks == 2 && !cplx && ci != 6); }
+// shapes of more than 8 MFMA tiles per wavefront would spill
+bool ks_ok(int ci, int ks, bool cplx) {
+  return ks == 1 || (ks == 2 && !cplx && kCfgs[ci].TM * kCfgs[ci].TN <= 8);
+}
 // BF16 products need 32-deep K-steps (one v_mfma_f32_16x16x32_bf16 per tile and step)
 bool ks_ok(int ci, int ks, Prec prec) {
-  if (prec == Prec::BF16) return ks == 2 && ci != 6;
+  if (prec == Prec::BF16) return ks == 2 && kCfgs[ci].TM * kCfgs[ci].TN <= 8;
   return ks_ok(ci, ks, prec == Prec::C128);
 }
 
@@ -893,11 +902,11 @@ double tile_cost(const Cfg& c, int64_t M, int64_t N, int64_t K, int64_t batch, d
   return t / std::min(1.0, blocks / 512.0);
 }
 
-int pick_cfg(int64_t M, int64_t N, int64_t K, int64_t batch, bool cplx, double elt) {
+int pick_cfg(int64_t M, int64_t N, int64_t K, int64_t batch, Prec prec, double elt) {
   int best = 0;
   double bc = 1e300;
   for (int i = 0; i < kNumCfgs; ++i) {
-    if (!cfg_ok(i, cplx)) continue;
+    if (!cfg_ok(i, prec == Prec::C128) || !ks_ok(i, prec == Prec::BF16 ? 2 : 1, prec)) continue;
     const double c = tile_cost(kCfgs[i], M, N, K, batch, elt);
     if (c < bc * 0.999) {
       bc = c;
@@ -936,7 +945,12 @@ void launch_cfg(int ci, unsigned grid, size_t lds, hipStream_t st, const GemmArg
     case 6: launch_one<TC, CPLX, TIn, TOut, 2, 2, 4, 4, KS>(grid, lds, st, a); break;
     case 7: launch_one<TC, CPLX, TIn, TOut, 1, 4, 1, 4, KS>(grid, lds, st, a); break;
     case 8: launch_one<TC, CPLX, TIn, TOut, 4, 1, 4, 1, KS>(grid, lds, st, a); break;
-    default: launch_one<TC, CPLX, TIn, TOut, 1, 4, 2, 2, KS>(grid, lds, st, a); break;
+    case 9: launch_one<TC, CPLX, TIn, TOut, 1, 4, 2, 2, KS>(grid, lds, st, a); break;
+    case 10: launch_one<TC, CPLX, TIn, TOut, 1, 4, 7, 1, KS>(grid, lds, st, a); break;
+    case 11: launch_one<TC, CPLX, TIn, TOut, 1, 4, 13, 1, KS>(grid, lds, st, a); break;
+    case 12: launch_one<TC, CPLX, TIn, TOut, 4, 1, 1, 5, KS>(grid, lds, st, a); break;
+    case 13: launch_one<TC, CPLX, TIn, TOut, 4, 1, 2, 5, KS>(grid, lds, st, a); break;
+    default: launch_one<TC, CPLX, TIn, TOut, 4, 1, 1, 7, KS>(grid, lds, st, a); break;
   }
 }
 
@@ -986,12 +1000,12 @@ Plan make_plan(Prec prec, const GemmDesc& d, const GemmCall& c, const GemmArgs& 
   Plan p;
   p.ci = (v.cfg >= 0 && v.cfg < kNumCfgs && cfg_ok(v.cfg, cplx))
              ? v.cfg
-             : pick_cfg(d.M, d.N, d.K, c.batch, cplx,
+             : pick_cfg(d.M, d.N, d.K, c.batch, prec,
                         prec == Prec::F32 ? 4.0 : prec == Prec::BF16 ? 2.0 : (cplx ? 16.0 : 8.0));
   p.ks = v.ks == 1 || v.ks == 2 ? v.ks : 1;
   if (prec == Prec::BF16) {
     p.ks = 2;
-    if (p.ci == 6) p.ci = 5;
+    if (!ks_ok(p.ci, 2, prec)) p.ci = 5;
   }
   if (!ks_ok(p.ci, p.ks, prec)) p.ks = 1;
   const Cfg cf = kCfgs[p.ci];

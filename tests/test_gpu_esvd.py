@@ -179,6 +179,31 @@ def test_pair_bf16_sketch(ctx, shape):
         assert np.max(np.abs(Ui.T @ Ui - np.eye(rank))) < 1e-10
 
 
+@pytest.mark.parametrize("tile", range(15))
+@pytest.mark.parametrize("precision,tol", [("f32", 1e-4), ("bf16", 3e-2)])
+def test_pair_mixed_every_tile(ctx, tile, precision, tol):
+    """Every GEMM tile shape forced on every product of an FP32 and a BF16 einsumsvd (BF16
+    takes 32-deep K-steps and maps the shapes of more than 8 MFMA tiles per wavefront to
+    128 x 64): singular values within the precision's tolerance of the FP64 oracle."""
+    m, D, d, rank, p, q = 20, 4, 2, 24, 8, 2
+    inst = [synth.pair_instance(m, D, d, seed=11, instance=i) for i in range(2)]
+    st = [np.stack([t[j] for t in inst]) for j in range(4)]
+    try:
+        ctx.check(ctx.lib.hpeps_test_gemm_variant(ctx.h, tile, 2 if precision == "bf16" else 1, 0))
+        U, s, R = hp.einsumsvd_pair(ctx, *[_dev(t) for t in st], rank=rank, oversample=p,
+                                    power_iters=q, seed=1, stream_id=5, precision=precision,
+                                    absorb=hp.ABSORB_NONE)
+        s = s.cpu().numpy()
+    finally:
+        ctx.check(ctx.lib.hpeps_test_gemm_variant(ctx.h, -1, 1, 0))
+    for i in range(2):
+        op = pair_operator(*inst[i])
+        k = rsvd.sketch_width(rank, p, op.n_rows, op.n_cols)
+        om = oracle_sketch(1, 5 + i, op.n_cols, k)
+        _, so, _ = rsvd.randomized_svd(op.apply, op.apply_adj, op.n_rows, op.n_cols, rank, q, om)
+        assert np.max(np.abs(s[i] - so)) <= tol * so[0]
+
+
 def test_pair_full_size_bf16(ctx):
     """The benchmarked configuration in BF16: instances 0 and 63, singular values normwise
     within 3e-2 of the FP64 oracle."""

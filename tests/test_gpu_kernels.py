@@ -56,7 +56,7 @@ def test_gemm(ctx, cplx, shape, trans):
         assert np.max(np.abs(out[b] - ref)) <= 1e-13 * max(1.0, np.abs(ref).max()) * np.sqrt(K)
 
 
-N_TILES = 10  # tile shapes of the GEMM (0..9; complex products use those of <= 4 tiles per wave)
+N_TILES = 15  # tile shapes of the GEMM (0..14; complex products use those of <= 4 tiles per wave)
 
 
 @pytest.mark.parametrize("tile", range(N_TILES))
