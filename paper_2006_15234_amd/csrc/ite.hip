@@ -2,17 +2,20 @@
 // sweeps for imaginary-time evolution (Sec. II-D).
 //
 // One workgroup updates one bond entirely on chip:
-//   1. each site is matricized as (other legs) x (shared bond, p) while it
-//      is gathered into registers (thread t owns rows t, t + 256, ...); when
-//      it has more rows than columns it is Householder-QR factored there,
-//      one barrier per column, otherwise Q = I and R is the site itself;
+//   1. both sites are matricized as (other legs) x (shared bond, p) while
+//      they are gathered into LDS (thread t owns rows t, t + NT, ... of
+//      both; 512 threads for the 512-row sites of bond 8); a site with more
+//      rows than columns is Householder-QR factored there, the two sites
+//      side by side with one barrier per column, otherwise Q = I and R is
+//      the site itself;
 //   2. Theta = G R1 R2 (d^2 x d^2 gate, tiny);
-//   3. one-sided Jacobi SVD of Theta (<= 32 x 32) in LDS with accumulated
-//      right vectors, truncation to D' = min(Dmax, rows, cols), normalisation
-//      of the kept values and the sqrt(s) split;
-//   4. T' = Q [R~; 0] by applying the reflectors still held in registers in
-//      reverse order, scattered straight into the canonical [u,d,l,r,p]
-//      layout with the new bond.
+//   3. Theta = Q_T R_T (Householder, Q_T accumulated), then one-sided Jacobi
+//      on the columns of R_T^T with Q_T's columns rotated alike (<= 32 x 32,
+//      in LDS), truncation to D' = min(Dmax, rows, cols), normalisation of
+//      the kept values and the sqrt(s) split;
+//   4. T' = Q [R~; 0] by applying the parked reflectors in reverse order
+//      (both sites side by side), scattered straight into the canonical
+//      [u,d,l,r,p] layout with the new bond.
 // Bond dimensions live in a device table, so a whole sweep (four launches,
 // one per layer of non-overlapping bonds) is a static sequence that is
 // captured once in a HIP graph and replayed.
@@ -100,197 +103,250 @@ __device__ __forceinline__ long long row_off(const SiteGeom& g, int row) {
 // Cross-wavefront sums of the partials of one column step.  Every thread
 // adds the four wavefronts' values; buffers alternate between steps so that
 // one barrier per step suffices (a wavefront can be at most one step ahead).
+template <int NT>
 struct StepBuf {
-  double part[2][kT / 64][kMaxC];
+  double part[2][NT / 64][kMaxC];
   double row[2][kMaxC];  // snapshot of the pivot row
 };
 
-// Wavefront sums of 16 values per lane by recursive halving: in stage k
-// (partner lane ^ 2^k) a lane keeps the half of its remaining values that
-// its bit k selects and adds the partner's copy of that half, so after four
-// stages lane i holds the sum over its 16-lane row of value
-// bitrev4(i & 15); two more exchanges add the four rows.  17 shuffles
-// instead of 16 separate wavefront reductions.
-__device__ __forceinline__ int bitrev4(int i) {
-  return ((i & 1) << 3) | ((i & 2) << 1) | ((i & 4) >> 1) | ((i & 8) >> 3);
+// Wavefront sums of 16 values per lane by recursive halving, on DPP lane
+// moves: each stage pairs a lane with a partner in its 16-lane row that
+// differs in one more bit of the lane index (row mirror: bit 3, half-row
+// mirror: bit 2, quad permutations: bits 1 and 0); the lane keeps the half of
+// its remaining values that this bit selects and adds the partner's copy of
+// it, so that after four stages lane i holds the row sum of value i & 15.
+// Two shuffles then add the four rows.  The adds are not contracted (the
+// partner's values are rounded sums).
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov(double v) {
+  const long long x = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)x, CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(x >> 32), CTRL, 0xf, 0xf, false);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned)lo);
 }
 __device__ __forceinline__ double wave_reduce_scatter16(const double (&v)[16], int lane) {
+#pragma clang fp contract(off)
   double a[8], b[4], c[2];
-  bool hi = lane & 1;
+  bool hi = lane & 8;
 #pragma unroll
-  for (int i = 0; i < 8; ++i) a[i] = (hi ? v[i + 8] : v[i]) + __shfl_xor(hi ? v[i] : v[i + 8], 1);
-  hi = lane & 2;
-#pragma unroll
-  for (int i = 0; i < 4; ++i) b[i] = (hi ? a[i + 4] : a[i]) + __shfl_xor(hi ? a[i] : a[i + 4], 2);
+  for (int i = 0; i < 8; ++i) a[i] = (hi ? v[i + 8] : v[i]) + dpp_mov<0x140>(hi ? v[i] : v[i + 8]);  // row_mirror
   hi = lane & 4;
 #pragma unroll
-  for (int i = 0; i < 2; ++i) c[i] = (hi ? b[i + 2] : b[i]) + __shfl_xor(hi ? b[i] : b[i + 2], 4);
-  hi = lane & 8;
-  double d = (hi ? c[1] : c[0]) + __shfl_xor(hi ? c[0] : c[1], 8);
+  for (int i = 0; i < 4; ++i) b[i] = (hi ? a[i + 4] : a[i]) + dpp_mov<0x141>(hi ? a[i] : a[i + 4]);  // half mirror
+  hi = lane & 2;
+#pragma unroll
+  for (int i = 0; i < 2; ++i) c[i] = (hi ? b[i + 2] : b[i]) + dpp_mov<0x4e>(hi ? b[i] : b[i + 2]);  // [2,3,0,1]
+  hi = lane & 1;
+  double d = (hi ? c[1] : c[0]) + dpp_mov<0xb1>(hi ? c[0] : c[1]);  // quad_perm [1,0,3,2]
   d += __shfl_xor(d, 16);
   d += __shfl_xor(d, 32);
   return d;
 }
 
-// Householder QR of the rows x cols matricization P (LDS, column-major with
-// leading dimension LD): thread t owns rows t, t + kT, ... and only ever
-// touches those rows of P.  One barrier per column: the pivot row's owner
-// publishes it, every thread reduces x^T y_l over its rows for all l >= j at
-// once (x = column j, y_l = column l, rows >= j), and the reflector
-// v = x - alpha e_j (H = I - tau v v^T) follows in every thread from
-// ||x||^2, x_j and those sums (v^T y_l = x^T y_l - alpha y_l[j]).
-// Afterwards column j of P holds v below and on the diagonal, tau[j] and row
-// j of R (ld kMaxC) are in LDS.
-template <int RPT, int MC, int LD>
-__device__ __forceinline__ void house_factor(double* P, int cols, double* R, double* tau, StepBuf& sb, int& step) {
+// w[l] = x of lane l (l < MC), the same in every lane (scalar registers).
+template <int MC>
+__device__ __forceinline__ void lanes_to_scalars(double x, double (&w)[MC]) {
+  const long long b = __builtin_bit_cast(long long, x);
+#pragma unroll
+  for (int l = 0; l < MC; ++l) {
+    const int lo = __builtin_amdgcn_readlane((int)b, l);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+    w[l] = __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned)lo);
+  }
+}
+
+// Totals of the per-wavefront sums part[w][v] (v < 16) over the NT / 64
+// wavefronts, for every v, in every thread: lane L adds the partials of
+// value L & 15 of the wavefronts congruent to L >> 4 mod 4, two shuffles add
+// the four rows, and the 16 totals (the same in every lane) are read out of
+// lanes 0..15 into scalar registers.
+template <int NT, int MC>
+__device__ __forceinline__ void cross_wave_totals(const double (*part)[kMaxC], int lane, double (&w)[MC]) {
+  double t = 0.0;
+#pragma unroll
+  for (int q = 0; q < (NT / 64 + 3) / 4; ++q) {
+    const int wv = (lane >> 4) + 4 * q;
+    if (wv < NT / 64) t += part[wv][lane & 15];
+  }
+  t += __shfl_xor(t, 16);
+  t += __shfl_xor(t, 32);
+  lanes_to_scalars<MC>(t, w);
+}
+
+// Householder QR of the two site matricizations at once (P[s]: rows x
+// cols[s], LDS, column-major with leading dimension LD; cols[s] = 0 skips a
+// site): thread t owns rows t, t + NT, ... of both and only ever touches
+// those rows.  One barrier per column step, shared by the two sites: the
+// pivot row's owner publishes it, every thread reduces x^T y_l over its rows
+// for all l >= j at once (x = column j, y_l = column l, rows >= j), and the
+// reflector v = x - alpha e_j (H = I - tau v v^T) follows in every thread
+// from ||x||^2, x_j and those sums (v^T y_l = x^T y_l - alpha y_l[j]).
+// Afterwards column j of P[s] holds v below and on the diagonal, tau[s][j]
+// and row j of R[s] (ld kMaxC) are in LDS.
+template <int NT, int RPT, int MC, int LD>
+__device__ __forceinline__ void house_factor2(double* const (&P)[2], const int (&cols)[2], double* const (&R)[2],
+                                              double* const (&tau)[2], StepBuf<NT> (&sb)[2], int& step) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  for (int j = 0; j < cols; ++j) {
+  const int nj = max(cols[0], cols[1]);
+  for (int j = 0; j < nj; ++j) {
     const int buf = step++ & 1;
-    const double* x = P + j * LD;
-    if (tid == j) {
+    double xr[2][RPT];
 #pragma unroll
-      for (int l = 0; l < MC; ++l)
-        if (l >= j && l < cols) sb.row[buf][l] = P[l * LD + j];
-    }
-    // every load is in range (P has MC columns of LD rows): load all, then
-    // mask, so that the loads of a step form one batch without branches
-    double xr[RPT];
+    for (int s = 0; s < 2; ++s) {
+      if (j >= cols[s]) continue;  // same in every thread
+      const double* x = P[s] + j * LD;
+      // the pivot row j < 16 belongs to lane j of wavefront 0, whose other
+      // lanes copy it (in program order after its last update)
+      if (tid < MC) sb[s].row[buf][tid] = P[s][tid * LD + j];
+      // every load is in range (P has MC columns of LD rows): load all, then
+      // mask, so that the loads of a step form one batch without branches
 #pragma unroll
-    for (int q = 0; q < RPT; ++q) {
-      const double xv = x[tid + q * kT];
-      xr[q] = tid + q * kT >= j ? xv : 0.0;
-    }
-    double pv[16];
-#pragma unroll
-    for (int l = 0; l < 16; ++l) {
-      double sacc = 0.0;
-      if (l < MC) {
-#pragma unroll
-        for (int q = 0; q < RPT; ++q) sacc += xr[q] * P[l * LD + tid + q * kT];
+      for (int q = 0; q < RPT; ++q) {
+        const double xv = x[tid + q * NT];
+        xr[s][q] = tid + q * NT >= j ? xv : 0.0;
       }
-      pv[l] = (l >= j && l < cols) ? sacc : 0.0;
-    }
-    {
+      // unmasked: columns past cols[s] are zero, and the sums of columns
+      // up to j are never used
+      double pv[16];
+#pragma unroll
+      for (int l = 0; l < 16; ++l) {
+        double sacc = 0.0;
+        if (l < MC) {
+#pragma unroll
+          for (int q = 0; q < RPT; ++q) sacc += xr[s][q] * P[s][l * LD + tid + q * NT];
+        }
+        pv[l] = sacc;
+      }
       const double tot = wave_reduce_scatter16(pv, lane);
-      if (lane < 16 && bitrev4(lane) < MC) sb.part[buf][wave][bitrev4(lane)] = tot;
+      if (lane < MC) sb[s].part[buf][wave][lane] = tot;
     }
     __syncthreads();
-    double w[MC];
 #pragma unroll
-    for (int l = 0; l < MC; ++l) {
-      double t = 0.0;
+    for (int s = 0; s < 2; ++s) {
+      if (j >= cols[s]) continue;
+      double w[MC];
+      cross_wave_totals<NT, MC>(sb[s].part[buf], lane, w);
+      double nrm2 = 0.0;
 #pragma unroll
-      for (int wv = 0; wv < kT / 64; ++wv) t += sb.part[buf][wv][l];
-      w[l] = t;
-    }
-    double nrm2 = 0.0;
-#pragma unroll
-    for (int l = 0; l < MC; ++l)
-      if (l == j) nrm2 = w[l];
-    const double x0 = sb.row[buf][j];
-    if (nrm2 == 0.0) {  // zero column: H = I, R[j, :] = 0 (the pivot row is zero too)
-      if (tid == j) {
-        tau[j] = 0.0;
-        for (int l = 0; l < cols; ++l) R[j * kMaxC + l] = 0.0;
+      for (int l = 0; l < MC; ++l)
+        if (l == j) nrm2 = w[l];
+      const double x0 = sb[s].row[buf][j];
+      if (nrm2 == 0.0) {  // zero column: H = I, R[j, :] = 0 (the pivot row is zero too)
+        if (tid < cols[s]) R[s][j * kMaxC + tid] = 0.0;
+        if (tid == 0) tau[s][j] = 0.0;
+        continue;
       }
-      continue;
-    }
-    const double alpha = -copysign(sqrt(nrm2), x0);
-    const double v0 = x0 - alpha;
-    const double vn2 = nrm2 - x0 * x0 + v0 * v0;
-    const double t = vn2 > 0 ? 2.0 / vn2 : 0.0;
+      const double alpha = -copysign(sqrt(nrm2), x0);
+      const double v0 = x0 - alpha;
+      const double vn2 = nrm2 - x0 * x0 + v0 * v0;
+      const double t = vn2 > 0 ? 2.0 / vn2 : 0.0;
 #pragma unroll
-    for (int l = 0; l < MC; ++l) {
-      const double wl = t * (w[l] - alpha * sb.row[buf][l]);  // tau v^T y_l
-      w[l] = (l > j && l < cols) ? wl : 0.0;
-    }
-    // rows below j have v = 0 and columns up to j have w = 0: those stores
-    // write back the loaded values, so the update needs no branches
+      for (int l = 0; l < MC; ++l) {
+        const double wl = t * (w[l] - alpha * sb[s].row[buf][l]);  // tau v^T y_l
+        w[l] = (l > j && l < cols[s]) ? wl : 0.0;
+      }
+      // rows below j have v = 0 and columns up to j have w = 0: those stores
+      // write back the loaded values, so the update needs no branches
 #pragma unroll
-    for (int q = 0; q < RPT; ++q) {
-      const int r = tid + q * kT;
-      const double v = r == j ? v0 : xr[q];
-      double y[MC];
+      for (int q = 0; q < RPT; ++q) {
+        const int r = tid + q * NT;
+        const double v = r == j ? v0 : xr[s][q];
+        double y[MC];
 #pragma unroll
-      for (int l = 0; l < MC; ++l) y[l] = P[l * LD + r];
+        for (int l = 0; l < MC; ++l) y[l] = P[s][l * LD + r];
 #pragma unroll
-      for (int l = 0; l < MC; ++l) P[l * LD + r] = l == j && r == j ? v0 : y[l] - w[l] * v;
-    }
-    if (tid == j) {
-      tau[j] = t;
-      for (int l = 0; l < cols; ++l) R[j * kMaxC + l] = l < j ? 0.0 : (l == j ? alpha : P[l * LD + j]);
+        for (int l = 0; l < MC; ++l) P[s][l * LD + r] = l == j && r == j ? v0 : y[l] - w[l] * v;
+      }
+      // row j of R from the updated pivot row (lane j of wavefront 0 wrote it
+      // above, in program order before these reads)
+      if (tid < cols[s]) R[s][j * kMaxC + tid] = tid < j ? 0.0 : (tid == j ? alpha : P[s][tid * LD + j]);
+      if (tid == 0) tau[s][j] = t;
     }
   }
 }
 
-// B := H_0 H_1 ... H_{cols-1} B for the reflectors of house_factor in P (same
-// row ownership), B (registers, RPT rows x MC columns) with ncol columns; one
-// barrier per reflector.
-template <int RPT, int MC, int LD>
-__device__ __forceinline__ void house_apply(const double* P, int cols, const double* tau, double (&B)[RPT][MC],
-                                            int ncol, StepBuf& sb, int& step) {
+// B[s] := H_0 H_1 ... H_{cols[s]-1} B[s] for the reflectors of house_factor2
+// in P[s] (same row ownership), for both sites at once; B[s] (registers, RPT
+// rows x MC columns) has ncol columns.  One barrier per reflector index,
+// shared by the two sites; an index whose reflectors are both the identity
+// (tau = 0, the same value in every thread) is skipped.
+template <int NT, int RPT, int MC, int LD>
+__device__ __forceinline__ void house_apply2(const double* const (&P)[2], const int (&cols)[2],
+                                             const double* const (&tau)[2], double (&B)[2][RPT][MC], int ncol,
+                                             StepBuf<NT> (&sb)[2], int& step) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  for (int j = cols - 1; j >= 0; --j) {
-    const double t = tau[j];
-    if (t == 0.0) continue;  // same value in every thread
+  for (int j = max(cols[0], cols[1]) - 1; j >= 0; --j) {
+    double t[2];
+#pragma unroll
+    for (int s = 0; s < 2; ++s) t[s] = j < cols[s] ? tau[s][j] : 0.0;
+    if (t[0] == 0.0 && t[1] == 0.0) continue;
     const int buf = step++ & 1;
-    double v[RPT];
+    double v[2][RPT];
 #pragma unroll
-    for (int q = 0; q < RPT; ++q) {
-      const double pvq = P[j * LD + tid + q * kT];
-      v[q] = tid + q * kT >= j ? pvq : 0.0;
-    }
-    double pv[16];
+    for (int s = 0; s < 2; ++s) {
+      if (t[s] == 0.0) continue;
 #pragma unroll
-    for (int c = 0; c < 16; ++c) {
-      double sacc = 0.0;
-      if (c < MC) {
-#pragma unroll
-        for (int q = 0; q < RPT; ++q) sacc += v[q] * B[q][c < MC ? c : 0];
+      for (int q = 0; q < RPT; ++q) {
+        const double pvq = P[s][j * LD + tid + q * NT];
+        v[s][q] = tid + q * NT >= j ? pvq : 0.0;
       }
-      pv[c] = c < ncol ? sacc : 0.0;
-    }
-    {
+      double pv[16];  // columns past ncol are zero
+#pragma unroll
+      for (int c = 0; c < 16; ++c) {
+        double sacc = 0.0;
+        if (c < MC) {
+#pragma unroll
+          for (int q = 0; q < RPT; ++q) sacc += v[s][q] * B[s][q][c < MC ? c : 0];
+        }
+        pv[c] = sacc;
+      }
       const double tot = wave_reduce_scatter16(pv, lane);
-      if (lane < 16 && bitrev4(lane) < MC) sb.part[buf][wave][bitrev4(lane)] = tot;
+      if (lane < MC) sb[s].part[buf][wave][lane] = tot;
     }
     __syncthreads();
 #pragma unroll
-    for (int c = 0; c < MC; ++c) {
-      double sum = 0.0;
+    for (int s = 0; s < 2; ++s) {
+      if (t[s] == 0.0) continue;
+      double tot[MC];
+      cross_wave_totals<NT, MC>(sb[s].part[buf], lane, tot);
 #pragma unroll
-      for (int wv = 0; wv < kT / 64; ++wv) sum += sb.part[buf][wv][c];
-      const double wc = c < ncol ? t * sum : 0.0;
+      for (int c = 0; c < MC; ++c) {
+        const double wc = c < ncol ? t[s] * tot[c] : 0.0;
 #pragma unroll
-      for (int q = 0; q < RPT; ++q) B[q][c] -= wc * v[q];
+        for (int q = 0; q < RPT; ++q) B[s][q][c] -= wc * v[s][q];
+      }
     }
   }
 }
 
 // One bond per workgroup (Alg. 1): both site matricizations are gathered
-// into registers and QR-factored (QR skipped when a site has no more rows
-// than columns), the reflectors are parked in LDS, Theta = G R1 R2 is
-// decomposed by one-sided Jacobi in LDS, and each new site Q [R~; 0] is
-// formed in registers and scattered into the [u,d,l,r,p] layout with the new
-// bond.  RPT rows and MC columns per thread; dynamic LDS: two column-major
-// RPT kT x MC reflector blocks.
-template <int RPT, int MC>
-__global__ __launch_bounds__(kT) void qrsvd_bond_kernel(IteArgs a) {
-  extern __shared__ double park[];                          // [2][MC][RPT kT]
+// into LDS and QR-factored together (QR skipped when a site has no more rows
+// than columns), the reflectors stay parked there, Theta = G R1 R2 is
+// decomposed by a QR-preconditioned one-sided Jacobi in LDS, and the new
+// sites Q [R~; 0] are formed in registers and scattered into the
+// [u,d,l,r,p] layout with the new bond.  NT threads, RPT rows and MC columns
+// per thread; dynamic LDS: two column-major RPT NT x MC reflector blocks.
+// The panels' LDS leaves room for one workgroup per CU, i.e. NT / 256
+// wavefronts per SIMD: the register allocator may use that budget to keep
+// more LDS loads in flight.
+template <int NT, int RPT, int MC>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT / 256, NT / 256)))
+void qrsvd_bond_kernel(IteArgs a) {
+  extern __shared__ double park[];                          // [2][MC][RPT NT]
   __shared__ double R1[kMaxC * kMaxC], R2[kMaxC * kMaxC];  // k x cols, ld kMaxC
   __shared__ double Th[kMaxTh * kMaxTh];                    // Theta, column-major (col * nr + row)
   __shared__ double J[kMaxTh * kMaxTh];                     // right vectors, column-major
   __shared__ double tau1[kMaxC], tau2[kMaxC];
   __shared__ double tauT[kMaxTh], alphaT[kMaxTh];  // Householder QR of Theta
-  __shared__ double red[kT / 64];
+  __shared__ double red[NT / 64];
   __shared__ double sig[kMaxTh], sv[kMaxTh];
   __shared__ long long coff1[kMaxC], coff2[kMaxC];
-  __shared__ StepBuf sb;
+  __shared__ StepBuf<NT> sb[2];
   __shared__ int perm[kMaxTh];
   __shared__ int rot;
   __shared__ SiteGeom g1, g2, go[2];
-  constexpr int LD = RPT * kT;
-  const int bi = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = kT / 64;
+  constexpr int LD = RPT * NT;
+  const int bi = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = NT / 64;
   const int s1 = a.bonds[4 * bi], s2 = a.bonds[4 * bi + 1], axis = a.bonds[4 * bi + 2];
   if (tid == 0) {
     site_geom(a.dims + 5 * s1, axis == 0 ? 3 : 1, g1);
@@ -311,26 +367,32 @@ __global__ __launch_bounds__(kT) void qrsvd_bond_kernel(IteArgs a) {
 
   // ---- gather and factor both sites (matricizations in LDS) -------------
   const bool qr1 = g1.rows > g1.cols, qr2 = g2.rows > g2.cols;
+#pragma unroll
   for (int s = 0; s < 2; ++s) {
     const SiteGeom& g = s == 0 ? g1 : g2;
     const long long* coff = s == 0 ? coff1 : coff2;
     const double* site = s == 0 ? site1 : site2;
-    double* R = s == 0 ? R1 : R2;
     double* P = park + (long long)s * MC * LD;
 #pragma unroll
     for (int q = 0; q < RPT; ++q) {
-      const int r = tid + q * kT;
+      const int r = tid + q * NT;
       const bool in = r < g.rows;
       const long long ro = in ? row_off(g, r) : 0;
 #pragma unroll
       for (int c = 0; c < MC; ++c) P[c * LD + r] = (in && c < g.cols) ? site[ro + coff[c]] : 0.0;
     }
-    if (s == 0 ? qr1 : qr2) {
-      house_factor<RPT, MC, LD>(P, g.cols, R, s == 0 ? tau1 : tau2, sb, step);
-    } else if (tid < g.rows) {
+    if (!(s == 0 ? qr1 : qr2) && tid < g.rows) {
       // no QR: R is the matricization itself (rows <= cols <= 16: thread r owns row r)
+      double* R = s == 0 ? R1 : R2;
       for (int c = 0; c < g.cols; ++c) R[tid * kMaxC + c] = P[c * LD + tid];
     }
+  }
+  double* const Pf[2] = {park, park + (long long)MC * LD};
+  const int qcols[2] = {qr1 ? g1.cols : 0, qr2 ? g2.cols : 0};
+  {
+    double* const Rf[2] = {R1, R2};
+    double* const tf[2] = {tau1, tau2};
+    house_factor2<NT, RPT, MC, LD>(Pf, qcols, Rf, tf, sb, step);
   }
   __syncthreads();
   const int k1 = qr1 ? g1.cols : g1.rows;
@@ -338,7 +400,7 @@ __global__ __launch_bounds__(kT) void qrsvd_bond_kernel(IteArgs a) {
 
   // ---- Theta[(k1,a),(b,l)] = sum_{h,i,j} G[a,b,i,j] R1[k1,(h,i)] R2[l,(h,j)] ----
   const int nr = k1 * d, nc = d * k2;
-  for (int e = tid; e < nr * nc; e += kT) {
+  for (int e = tid; e < nr * nc; e += NT) {
     const int col = e / nr, row = e - col * nr;
     const int kk1 = row / d, aa = row - kk1 * d, bb = col / k2, ll = col - bb * k2;
     double acc = 0;
@@ -365,7 +427,7 @@ __global__ __launch_bounds__(kT) void qrsvd_bond_kernel(IteArgs a) {
   double fro2 = 0;
   {
     double f2 = 0;
-    for (int e = tid; e < nr * nc; e += kT) f2 += Th[e] * Th[e];
+    for (int e = tid; e < nr * nc; e += NT) f2 += Th[e] * Th[e];
     f2 = wave_sum(f2);
     if (lane == 0) red[wave] = f2;
     __syncthreads();
@@ -376,7 +438,7 @@ __global__ __launch_bounds__(kT) void qrsvd_bond_kernel(IteArgs a) {
   // trailing column of Theta and a row of Q each (lanes: rows / columns gl
   // and gl + 16), with DPP row sums for the dot products
   const int qg = tid >> 4, ql = tid & 15;
-  for (int e = tid; e < nr * nr; e += kT) J[e] = (e / nr == e % nr) ? 1.0 : 0.0;
+  for (int e = tid; e < nr * nr; e += NT) J[e] = (e / nr == e % nr) ? 1.0 : 0.0;
   __syncthreads();
   for (int j = 0; j < nk; ++j) {
     if (qg == 0) {
@@ -398,7 +460,7 @@ __global__ __launch_bounds__(kT) void qrsvd_bond_kernel(IteArgs a) {
     const double v0r = ql >= j && ql < nr ? Th[j * nr + ql] : 0.0;
     const double v1r = ql + 16 >= j && ql + 16 < nr ? Th[j * nr + ql + 16] : 0.0;
     // trailing columns l = j + 1 + qg (+ 16): y -= tau (v^T y) v over rows >= j
-    for (int l = j + 1 + qg; l < nc; l += 16) {
+    for (int l = j + 1 + qg; l < nc; l += NT / 16) {
       double* y = Th + l * nr;
       const double y0 = ql < nr ? y[ql] : 0.0, y1 = ql + 16 < nr ? y[ql + 16] : 0.0;
       const double w = t * row_sum16(v0r * y0 + v1r * y1);
@@ -406,7 +468,7 @@ __global__ __launch_bounds__(kT) void qrsvd_bond_kernel(IteArgs a) {
       if (ql + 16 >= j && ql + 16 < nr) y[ql + 16] = y1 - w * v1r;
     }
     // rows i = qg (+ 16) of Q: q -= tau (q . v) v^T over columns >= j
-    for (int i = qg; i < nr; i += 16) {
+    for (int i = qg; i < nr; i += NT / 16) {
       const double q0 = ql < nr ? J[ql * nr + i] : 0.0, q1 = ql + 16 < nr ? J[(ql + 16) * nr + i] : 0.0;
       const double w = t * row_sum16(q0 * v0r + q1 * v1r);
       if (ql >= j && ql < nr) J[ql * nr + i] = q0 - w * v0r;
@@ -416,17 +478,18 @@ __global__ __launch_bounds__(kT) void qrsvd_bond_kernel(IteArgs a) {
   }
   // K[c][i] = R[c][i] (row c of R as column c of K, length nc) in Theta's
   // storage, through registers (the two layouts overlap)
-  double kv[4];
+  constexpr int KV = kMaxTh * kMaxTh / NT;
+  double kv[KV];
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int e = tid + q * kT;
+  for (int q = 0; q < KV; ++q) {
+    const int e = tid + q * NT;
     const int c = e / nc, i = e - c * nc;
     kv[q] = (e >= nk * nc || i < c) ? 0.0 : (i == c ? alphaT[c] : Th[i * nr + c]);
   }
   __syncthreads();
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int e = tid + q * kT;
+  for (int q = 0; q < KV; ++q) {
+    const int e = tid + q * NT;
     if (e < nk * nc) Th[e] = kv[q];
   }
   __syncthreads();
@@ -546,15 +609,14 @@ __global__ __launch_bounds__(kT) void qrsvd_bond_kernel(IteArgs a) {
 
   // ---- new sites: T' = Q [R~; 0] with columns (b, p) ---------------------
   const int ncol_out = Dn * d;
+  double B[2][RPT][MC];
+#pragma unroll
   for (int s = 0; s < 2; ++s) {
-    const SiteGeom& g = s == 0 ? g1 : g2;
-    const bool qr = s == 0 ? qr1 : qr2;
     const int kk = s == 0 ? k1 : k2;
-    double B[RPT][MC];
     // R~[kk, (b, a)] in the rows the thread owns (rows >= kk are zero)
 #pragma unroll
     for (int q = 0; q < RPT; ++q) {
-      const int row = tid + q * kT;
+      const int row = tid + q * NT;
 #pragma unroll
       for (int col = 0; col < MC; ++col) {
         double v = 0.0;
@@ -566,31 +628,42 @@ __global__ __launch_bounds__(kT) void qrsvd_bond_kernel(IteArgs a) {
           if (s == 0) v = J[(long long)c * nr + row * d + aa] * rs;                         // X[(row,aa),b]
           else v = sg > 0 ? Th[(long long)c * nc + aa * k2 + row] / sg * rs : 0.0;          // Y[(aa,row),b]
         }
-        B[q][col] = v;
+        B[s][q][col] = v;
       }
     }
-    if (qr)
-      house_apply<RPT, MC, LD>(park + (long long)s * MC * LD, g.cols, s == 0 ? tau1 : tau2, B, ncol_out, sb, step);
-    // scatter into the canonical layout with the new shared dimension
-    if (tid == 0) {
+  }
+  {
+    const double* const Pc[2] = {Pf[0], Pf[1]};
+    const double* const tc[2] = {tau1, tau2};
+    house_apply2<NT, RPT, MC, LD>(Pc, qcols, tc, B, ncol_out, sb, step);
+  }
+  // scatter into the canonical layout with the new shared dimension
+  if (tid == 0) {
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      const SiteGeom& g = s == 0 ? g1 : g2;
       go[s] = g;
       go[s].dims[g.shared] = Dn;
       go[s].st[4] = 1;
       for (int i = 3; i >= 0; --i) go[s].st[i] = go[s].st[i + 1] * go[s].dims[i + 1];
     }
-    __syncthreads();
+  }
+  __syncthreads();
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+    const SiteGeom& g = s == 0 ? g1 : g2;
     double* site = s == 0 ? site1 : site2;
     const long long sst = go[s].st[g.shared];
 #pragma unroll
     for (int q = 0; q < RPT; ++q) {
-      const int r = tid + q * kT;
+      const int r = tid + q * NT;
       if (r >= g.rows) continue;
       const long long ro = row_off(go[s], r);
 #pragma unroll
       for (int col = 0; col < MC; ++col) {
         if (col < ncol_out) {
           const int b = col / d, aa = col - b * d;
-          site[ro + b * sst + aa] = B[q][col];
+          site[ro + b * sst + aa] = B[s][q][col];
         }
       }
     }
@@ -601,8 +674,6 @@ __global__ __launch_bounds__(kT) void qrsvd_bond_kernel(IteArgs a) {
   }
 }
 
-int rows_per_thread(int max_rows) { return (max_rows + kT - 1) / kT; }
-
 void check_dims(int64_t dmax, int d) {
   HP_REQUIRE(dmax >= 1 && d >= 1, HPEPS_ERR_INVALID_ARG, "bad bond or physical dimension");
   HP_REQUIRE(dmax * d * d <= kMaxTh, HPEPS_ERR_UNSUPPORTED, "QR-SVD kernel supports D d^2 <= 32");
@@ -610,26 +681,30 @@ void check_dims(int64_t dmax, int d) {
              "QR-SVD kernel supports D d <= 16 and D^3 <= 768");
 }
 
-// Variants: rows per thread x register columns.  D^3 > 512 needs D >= 9,
-// hence d = 1 and at most 9 columns.
+// Variants: threads x rows per thread x register columns.  Up to 512 rows
+// each thread owns one row of both sites (512 threads: two wavefronts per
+// SIMD hide each other's LDS round trips; the LDS of the two 512 x 16
+// panels allows one workgroup per CU).  D^3 > 512 needs D >= 9, hence d = 1
+// and at most 9 columns.
 void launch_layer(hipStream_t st, const IteArgs& a, int nb) {
   if (nb == 0) return;
   // the dynamic LDS limit is raised once per variant and process
   static std::once_flag once[3];
-  auto go = [&](auto kern, int rpt, int mc) {
-    const size_t lds = (size_t)2 * mc * rpt * kT * sizeof(double);
+  auto go = [&](auto kern, int v, int nt, int rpt, int mc) {
+    const size_t lds = (size_t)2 * mc * rpt * nt * sizeof(double);
     hipError_t e = hipSuccess;
-    std::call_once(once[rpt - 1], [&] {
+    std::call_once(once[v], [&] {
       e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     });
     HP_CHECK_HIP(e);
-    kern<<<nb, kT, lds, st>>>(a);
+    kern<<<nb, nt, lds, st>>>(a);
   };
-  switch (rows_per_thread(a.max_rows)) {
-    case 1: go(qrsvd_bond_kernel<1, kMaxC>, 1, kMaxC); break;
-    case 2: go(qrsvd_bond_kernel<2, kMaxC>, 2, kMaxC); break;
-    default: go(qrsvd_bond_kernel<3, 9>, 3, 9); break;
-  }
+  if (a.max_rows <= kT)
+    go(qrsvd_bond_kernel<kT, 1, kMaxC>, 0, kT, 1, kMaxC);
+  else if (a.max_rows <= 2 * kT)
+    go(qrsvd_bond_kernel<2 * kT, 1, kMaxC>, 1, 2 * kT, 1, kMaxC);
+  else
+    go(qrsvd_bond_kernel<kT, 3, 9>, 2, kT, 3, 9);
 }
 
 // One-site gates (Eq. 3) of a layer, in place: workgroup b applies the d x d
