@@ -368,13 +368,20 @@ __global__ __launch_bounds__(kJacMaxThreads) void jacobi_kernel(const double* Ra
       if constexpr (CPLX) gi = row_sum16(gi);
       const double g2 = gr * gr + gi * gi;
       if (active && a2 > 0 && b2 > 0 && g2 > tol2 * a2 * b2) {
-        const double ga = CPLX ? sqrt(g2) : fabs(gr);
-        const double inv_ga = 1.0 / ga;
-        const double zeta = 0.5 * (b2 - a2) * inv_ga;
-        const double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-        const double c = rsqrt(1.0 + t * t), s = c * t;  // 1 + t^2 in [1, 2]
+        // The rotation angle (|theta| <= pi/4, tan 2 theta = 2 |gamma| / dl,
+        // dl = b2 - a2) by reciprocal square roots, no division: with
+        // r = (dl^2 + 4 |gamma|^2)^-1/2, cos 2 theta = |dl| r and
+        // u = (2 + 2 cos 2 theta)^-1/2, cos theta = (1 + cos 2 theta) u and
+        // sin theta = sign(dl) 2 |gamma| r u.
+        const double dl = b2 - a2;
+        const double r = rsqrt(dl * dl + 4.0 * g2);
+        const double C2 = fabs(dl) * r;
+        const double u = rsqrt(2.0 + 2.0 * C2);
+        const double c = (1.0 + C2) * u;
+        const double inv_ga = CPLX ? rsqrt(g2) : 1.0;
+        const double s = (dl >= 0 ? 2.0 : -2.0) * r * u * (CPLX ? g2 * inv_ga : fabs(gr));
         // y~ = conj(e) y with e = gamma / |gamma|, then a real rotation of (x, y~)
-        const double er = gr * inv_ga, ei = gi * inv_ga;
+        const double er = CPLX ? gr * inv_ga : (gr >= 0 ? 1.0 : -1.0), ei = gi * inv_ga;
 #pragma unroll
         for (int h = 0; h < ROWS; ++h) {
           const int r = li + 16 * h;
