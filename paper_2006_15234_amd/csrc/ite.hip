@@ -343,7 +343,7 @@ void qrsvd_bond_kernel(IteArgs a) {
   __shared__ long long coff1[kMaxC], coff2[kMaxC];
   __shared__ StepBuf<NT> sb[2];
   __shared__ int perm[kMaxTh];
-  __shared__ int rot;
+  __shared__ int rot, chk;
   __shared__ SiteGeom g1, g2, go[2];
   constexpr int LD = RPT * NT;
   const int bi = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = NT / 64;
@@ -572,13 +572,41 @@ void qrsvd_bond_kernel(IteArgs a) {
           qx[gl + 16] = c * qx1 - sn * qy1;
           qy[gl + 16] = sn * qx1 + c * qy1;
         }
-        if (gl == 0) rot = 1;
+        if (gl == 0) atomicAdd(&rot, 1);
       }
       __syncthreads();
     }
-    const bool done = rot == 0;
+    const int nrot = rot;
     __syncthreads();
-    if (done) break;
+    if (nrot == 0) break;
+    if (nrot <= nk) {
+      // Few rotations left: test every pair against the rotation thresholds
+      // at once (one pair per thread, one barrier) instead of a sweep of
+      // n - 1 rounds that would find none to rotate (no column changes in
+      // such a sweep, so it makes exactly these tests).
+      if (tid == 0) chk = 0;
+      __syncthreads();
+      for (int pq = tid; pq < nk * (nk - 1) / 2; pq += NT) {
+        int ca = 0, rem = pq;
+        while (rem >= nk - 1 - ca) {
+          rem -= nk - 1 - ca;
+          ++ca;
+        }
+        const int cb = ca + 1 + rem;
+        const double* x = Th + ca * nc;
+        const double* y = Th + cb * nc;
+        double a2 = 0.0, b2 = 0.0, gm = 0.0;
+        for (int i = 0; i < nc; ++i) {
+          a2 += x[i] * x[i];
+          b2 += y[i] * y[i];
+          gm += x[i] * y[i];
+        }
+        if (gm * gm > tol2 * a2 * b2 && gm * gm > acc2 * fmax(a2, b2)) chk = 1;
+      }
+      __syncthreads();
+      const bool conv = chk == 0;
+      if (conv) break;
+    }
   }
   for (int c = wave; c < nk; c += nw) {
     double a2 = 0;
