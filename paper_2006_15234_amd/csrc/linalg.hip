@@ -829,45 +829,81 @@ __global__ void fill_value_kernel(double* p, long long n, double v, int cplx) {
 }
 
 // Canonical phase of the singular vectors: for each column i < mp of the
-// left factor U = P Z (row-major rows x mp, one instance per block), the
-// projection z = w . U[:, i] on the fixed vector w (the sketch generator's
-// values for seed 0, stream 0, one column) is made real positive by rotating
-// column i of Z by conj(z)/|z|.  A projection on a generic vector is immune
-// to the exact magnitude ties that the ket/bra symmetry of <psi|psi>
-// networks creates between entries.
+// left factor U = P Z (row-major rows x mp), the projection z = w . U[:, i]
+// on the fixed vector w (the sketch generator's values for seed 0, stream 0,
+// one column) is made real positive by rotating column i of Z by
+// conj(z)/|z|.  A projection on a generic vector is immune to the exact
+// magnitude ties that the ket/bra symmetry of <psi|psi> networks creates
+// between entries.
+//
+// Pass 1 spreads the rows over the chip: block (c, b) takes rows
+// [c kGaugeRows, (c + 1) kGaugeRows) of instance b, forms w for them once in
+// LDS, and accumulates w_r U[r, i] with threads on consecutive columns of a
+// row (coalesced), two rows at a time; its sums per column go to
+// part[b][c][i].  Pass 2 adds the chunks in order (deterministic) and
+// applies the phases to Z.
+constexpr int kGaugeRows = 256;
+
 template <bool CPLX>
-__global__ __launch_bounds__(256) void gauge_fix_kernel(const double* Uall, long long rows, int mp, double* Zall,
-                                                        int k) {
+__global__ __launch_bounds__(256) void gauge_partial_kernel(const double* Uall, long long rows, int mp,
+                                                            int nchunks, double* part) {
   using T = typename S<CPLX>::T;
-  const int b = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int c = blockIdx.x, b = blockIdx.y, tid = threadIdx.x;
   const T* U = reinterpret_cast<const T*>(Uall) + (long long)b * rows * mp;
-  T* Z = reinterpret_cast<T*>(Zall) + (long long)b * k * k;
-  __shared__ T phase[128];  // mp <= k <= 128
+  __shared__ double w[kGaugeRows];
+  __shared__ double acc[2][128][2];
+  const long long r0 = (long long)c * kGaugeRows;
   const uint64_t base = mix64(mix64(0ull) + 0ull);
-  // one wavefront per column (wave-uniform loop): lanes stride the rows, the
-  // projection is one wavefront sum
-  for (int i = wave; i < mp; i += 4) {
-    double zr = 0.0, zi = 0.0;
-    for (long long r = lane; r < rows; r += 64) {
-      const uint64_t h = mix64(base + (uint64_t)(r + 1) * 0x9E3779B97F4A7C15ull);
-      const double w = 2.0 * (double)(h >> 11) * 0x1p-53 - 1.0;
+  {
+    const long long r = r0 + tid;
+    const uint64_t h = mix64(base + (uint64_t)(r + 1) * 0x9E3779B97F4A7C15ull);
+    w[tid] = 2.0 * (double)(h >> 11) * 0x1p-53 - 1.0;
+  }
+  __syncthreads();
+  const int i = tid & 127, half = tid >> 7;
+  double zr = 0.0, zi = 0.0;
+  if (i < mp) {
+    const long long rend = min(rows, r0 + kGaugeRows);
+    for (long long r = r0 + half; r < rend; r += 2) {
+      const double wr = w[r - r0];
       const T u = U[r * mp + i];
       if constexpr (CPLX) {
-        zr += w * u.re;
-        zi += w * u.im;
+        zr += wr * u.re;
+        zi += wr * u.im;
       } else {
-        zr += w * u;
+        zr += wr * u;
       }
     }
-    zr = wave_sum(zr);
-    if constexpr (CPLX) zi = wave_sum(zi);
-    if (lane == 0) {
-      if constexpr (CPLX) {
-        const double m = sqrt(zr * zr + zi * zi);
-        phase[i] = m > 0 ? T{zr / m, -zi / m} : T{1.0, 0.0};  // conj(z)/|z|
-      } else {
-        phase[i] = zr < 0 ? -1.0 : 1.0;
-      }
+  }
+  acc[half][i][0] = zr;
+  acc[half][i][1] = zi;
+  __syncthreads();
+  if (tid < mp) {
+    double* o = part + (((long long)b * nchunks + c) * mp + tid) * 2;
+    o[0] = acc[0][tid][0] + acc[1][tid][0];
+    o[1] = acc[0][tid][1] + acc[1][tid][1];
+  }
+}
+
+template <bool CPLX>
+__global__ __launch_bounds__(256) void gauge_apply_kernel(const double* part, int nchunks, int mp, double* Zall,
+                                                          int k) {
+  using T = typename S<CPLX>::T;
+  const int b = blockIdx.x, tid = threadIdx.x;
+  T* Z = reinterpret_cast<T*>(Zall) + (long long)b * k * k;
+  __shared__ T phase[128];  // mp <= k <= 128
+  if (tid < mp) {
+    double zr = 0.0, zi = 0.0;
+    for (int c = 0; c < nchunks; ++c) {
+      const double* o = part + (((long long)b * nchunks + c) * mp + tid) * 2;
+      zr += o[0];
+      zi += o[1];
+    }
+    if constexpr (CPLX) {
+      const double m = sqrt(zr * zr + zi * zi);
+      phase[tid] = m > 0 ? T{zr / m, -zi / m} : T{1.0, 0.0};  // conj(z)/|z|
+    } else {
+      phase[tid] = zr < 0 ? -1.0 : 1.0;
     }
   }
   __syncthreads();
@@ -1124,10 +1160,18 @@ void fill_value(Ctx& ctx, double* p, int64_t n, double v, bool cplx) {
 void gauge_fix(Ctx& ctx, bool cplx, const double* U, int64_t rows, int64_t mp, double* Z, int64_t k,
                int batch) {
   HP_REQUIRE(mp >= 1 && mp <= k && k <= 128, HPEPS_ERR_SHAPE, "canonical phase: k above 128");
-  if (cplx)
-    gauge_fix_kernel<true><<<batch, 256, 0, ctx.stream>>>(U, rows, (int)mp, Z, (int)k);
-  else
-    gauge_fix_kernel<false><<<batch, 256, 0, ctx.stream>>>(U, rows, (int)mp, Z, (int)k);
+  HP_REQUIRE(rows >= 1, HPEPS_ERR_SHAPE, "canonical phase: no rows");
+  const int64_t nchunks = cdiv(rows, (int64_t)kGaugeRows);
+  HP_REQUIRE(nchunks < 65536 && batch < 65536, HPEPS_ERR_UNSUPPORTED, "canonical phase: too many rows");
+  double* part = ctx.ws<double>(2 * nchunks * mp * batch);
+  const dim3 g1((unsigned)nchunks, (unsigned)batch);
+  if (cplx) {
+    gauge_partial_kernel<true><<<g1, 256, 0, ctx.stream>>>(U, rows, (int)mp, (int)nchunks, part);
+    gauge_apply_kernel<true><<<batch, 256, 0, ctx.stream>>>(part, (int)nchunks, (int)mp, Z, (int)k);
+  } else {
+    gauge_partial_kernel<false><<<g1, 256, 0, ctx.stream>>>(U, rows, (int)mp, (int)nchunks, part);
+    gauge_apply_kernel<false><<<batch, 256, 0, ctx.stream>>>(part, (int)nchunks, (int)mp, Z, (int)k);
+  }
   HP_CHECK_HIP(hipGetLastError());
 }
 
