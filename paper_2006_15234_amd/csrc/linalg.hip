@@ -309,7 +309,7 @@ __global__ __launch_bounds__(kJacMaxThreads) void jacobi_kernel(const double* Ra
   extern __shared__ double smem[];
   const int n = (k + 1) / 2 * 2;  // even number of columns (one zero column if k is odd)
   T* Kc = reinterpret_cast<T*>(smem);  // column-major: Kc[c * k + r]
-  __shared__ int rotated;
+  __shared__ int rotated, chk;
   __shared__ int perm[128];
   __shared__ double nrm[128];
   const int b = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
@@ -399,16 +399,56 @@ __global__ __launch_bounds__(kJacMaxThreads) void jacobi_kernel(const double* Ra
             }
           }
         }
-        if (li == 0) rotated = 1;
+        if (li == 0) atomicAdd(&rotated, 1);
       }
       __syncthreads();
     }
-    if (!rotated) {
+    const int nrot = rotated;
+    if (nrot == 0) {
       converged = true;
       ++sweep;
       break;
     }
     __syncthreads();
+    if (nrot <= k && k <= 64) {
+      // Few rotations left: test every pair against the rotation threshold
+      // in one pass (counted as the confirming sweep) instead of a sweep of
+      // n - 1 rounds that would find none to rotate (no column changes in
+      // such a sweep, so it makes exactly these tests).  Above k = 64 the
+      // pass (one pair per thread, k rows each) costs more than it saves.
+      if (tid == 0) chk = 0;
+      __syncthreads();
+      for (int pq = tid; pq < k * (k - 1) / 2; pq += nt) {
+        int ca = 0, rem = pq;
+        while (rem >= k - 1 - ca) {
+          rem -= k - 1 - ca;
+          ++ca;
+        }
+        const int cb = ca + 1 + rem;
+        const T* xc = Kc + ca * k;
+        const T* yc = Kc + cb * k;
+        double a2 = 0, b2 = 0, gr = 0, gi = 0;
+        for (int r = 0; r < k; ++r) {
+          const T x = xc[r], y = yc[r];
+          a2 += S<CPLX>::abs2(x);
+          b2 += S<CPLX>::abs2(y);
+          if constexpr (CPLX) {
+            const cd g = cmul(cconj(x), y);
+            gr += g.re;
+            gi += g.im;
+          } else {
+            gr += x * y;
+          }
+        }
+        if (a2 > 0 && b2 > 0 && gr * gr + gi * gi > tol2 * a2 * b2) chk = 1;
+      }
+      __syncthreads();
+      if (chk == 0) {
+        converged = true;
+        sweep += 2;
+        break;
+      }
+    }
   }
   // singular values = column norms; sort descending (stable in column index)
   for (int c = wave; c < k; c += nw) {
