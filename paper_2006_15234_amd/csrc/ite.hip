@@ -5,17 +5,18 @@
 //   1. both sites are matricized as (other legs) x (shared bond, p) while
 //      they are gathered into LDS (thread t owns rows t, t + NT, ... of
 //      both; 512 threads for the 512-row sites of bond 8); a site with more
-//      rows than columns is Householder-QR factored there, the two sites
-//      side by side with one barrier per column, otherwise Q = I and R is
-//      the site itself;
+//      rows than columns is QR-factored there by CholeskyQR2 (explicit Q),
+//      or, when its Gram is too ill-conditioned for that, by Householder
+//      reflections (the two sites side by side, one barrier per column);
+//      otherwise Q = I and R is the site itself;
 //   2. Theta = G R1 R2 (d^2 x d^2 gate, tiny);
 //   3. Theta = Q_T R_T (Householder, Q_T accumulated), then one-sided Jacobi
 //      on the columns of R_T^T with Q_T's columns rotated alike (<= 32 x 32,
 //      in LDS), truncation to D' = min(Dmax, rows, cols), normalisation of
 //      the kept values and the sqrt(s) split;
-//   4. T' = Q [R~; 0] by applying the parked reflectors in reverse order
-//      (both sites side by side), scattered straight into the canonical
-//      [u,d,l,r,p] layout with the new bond.
+//   4. T' = Q [R~; 0], one product per row with the explicit Q or the parked
+//      reflectors applied in reverse order, scattered straight into the
+//      canonical [u,d,l,r,p] layout with the new bond.
 // Bond dimensions live in a device table, so a whole sweep (four launches,
 // one per layer of non-overlapping bonds) is a static sequence that is
 // captured once in a HIP graph and replayed.
@@ -319,9 +320,193 @@ __device__ __forceinline__ void house_apply2(const double* const (&P)[2], const 
   }
 }
 
+// Packed upper triangle of a 16 x 16 symmetric matrix: (a, b), a <= b, at
+// a * 16 - a (a - 1) / 2 + b - a (136 entries).
+__host__ __device__ constexpr int upk(int a, int b) { return a * 16 - a * (a - 1) / 2 + (b - a); }
+// (a, b) of packed entry idx (144 slots: 136 entries, then (0, 0))
+struct UpkTable {
+  int a[144], b[144];
+};
+__host__ __device__ constexpr UpkTable make_upk() {
+  UpkTable t{};
+  int idx = 0;
+  for (int a = 0; a < 16; ++a)
+    for (int b = a; b < 16; ++b) {
+      t.a[idx] = a;
+      t.b[idx] = b;
+      ++idx;
+    }
+  for (; idx < 144; ++idx) t.a[idx] = t.b[idx] = 0;
+  return t;
+}
+
+// CholeskyQR2 of the site matricizations P[s] (rows[s] x cols[s], LDS,
+// column-major, ld LD) that have on[s]: two passes of Gram -> Cholesky ->
+// Q := A R^-1, so that P[s] ends as the explicit Q and R[s] (row-major, ld
+// kMaxC) as R = R_2 R_1.  Each pass: (A) the two halves of the workgroup form
+// the two sites' Grams (a thread takes rows lt, lt + NT / 2, ...: 16 products
+// per chunk of the packed upper triangle, DPP reduce-scatter per wavefront,
+// partial sums to LDS); (B) one wavefront per site adds the partials and
+// factors the Gram in registers (lane l holds column l; readlane broadcasts
+// row j of R); (C) every thread solves q R = a for its rows (forward
+// substitution with R from LDS).  A site whose Cholesky breaks down, whose
+// first-pass pivots span more than 1e12 (condition number beyond about 1e6,
+// where CholeskyQR2 loses accuracy) or whose second-pass pivots are not near
+// 1 gets fail[s] = 1 and is left to the Householder path (its P[s] must then
+// be gathered again: the first pass may have overwritten it).
+// scratch: 2 (NT / 128) 144 partials + 2 x 256 pass factors + 2 x 16
+// reciprocal diagonals (at most 1696 doubles).
+template <int NT, int RPT, int MC, int LD>
+__device__ void cholqr2_sites(double* P0, double* P1, bool on0, bool on1, int rows0, int rows1, int cols0,
+                              int cols1, double* R0, double* R1, double* scratch, int* fail) {
+  constexpr int WPS = NT / 128;  // wavefronts per site in the Gram phase
+  constexpr int TPS = NT / 2;    // threads per site
+  constexpr int RQ = 2 * RPT;    // rows per thread in the Gram phase
+  constexpr int NCH = 9;         // chunks of 16 packed entries (136 used)
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  double* part = scratch;                      // [2][WPS][NCH * 16]
+  double* Rp = scratch + 2 * WPS * NCH * 16;   // [2][256]: this pass's factor
+  double* rdi = Rp + 2 * 256;                  // [2][16]: its reciprocal diagonal
+  auto Psel = [&](int s) { return s == 0 ? P0 : P1; };
+  auto Rsel = [&](int s) { return s == 0 ? R0 : R1; };
+  auto on = [&](int s) { return s == 0 ? on0 : on1; };
+  auto nrows = [&](int s) { return s == 0 ? rows0 : rows1; };
+  auto ncols = [&](int s) { return s == 0 ? cols0 : cols1; };
+  if (tid < 2) fail[tid] = 0;
+  for (int pass = 0; pass < 2; ++pass) {
+    __syncthreads();  // P final from the previous pass (or the gather); fail reset
+    // ---- (A) Gram partial sums ----
+    {
+      const int s = wave / WPS, wl = wave % WPS, lt = tid % TPS;
+      if (on(s)) {  // wavefront-uniform
+        double x[RQ][MC];
+#pragma unroll
+        for (int q = 0; q < RQ; ++q) {
+          const int r = lt + TPS * q;
+          const bool in = r < nrows(s);
+#pragma unroll
+          for (int c = 0; c < MC; ++c) x[q][c] = in && c < ncols(s) ? Psel(s)[c * LD + (in ? r : 0)] : 0.0;
+        }
+        constexpr UpkTable kU = make_upk();
+#pragma unroll
+        for (int ch = 0; ch < NCH; ++ch) {
+          double pv[16];
+#pragma unroll
+          for (int v = 0; v < 16; ++v) {
+            const int idx = ch * 16 + v;
+            const int a = kU.a[idx], b = kU.b[idx];  // constants after unrolling
+            double acc = 0.0;
+            if (idx < 136 && a < MC && b < MC) {
+#pragma unroll
+              for (int q = 0; q < RQ; ++q) acc += x[q][a < MC ? a : 0] * x[q][b < MC ? b : 0];
+            }
+            pv[v] = acc;
+          }
+          const double tot = wave_reduce_scatter16(pv, lane);
+          if (lane < 16) part[(s * WPS + wl) * NCH * 16 + ch * 16 + lane] = tot;
+        }
+      }
+    }
+    __syncthreads();
+    // ---- (B) Cholesky of each Gram by one wavefront ----
+    {
+      const int s = wave / WPS;
+      if (wave % WPS == 0 && on(s)) {  // wavefronts 0 and WPS
+        const int n = ncols(s), l = lane & 15;
+        double g[16];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+          const int a = i < l ? i : l, b = i < l ? l : i;
+          double t = 0.0;
+#pragma unroll
+          for (int w = 0; w < WPS; ++w) t += part[(s * WPS + w) * NCH * 16 + upk(a, b)];
+          g[i] = t;
+        }
+        double dmin = 1e300, dmax = 0.0;
+        bool bad = false;
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+          if (j >= n || bad) continue;  // uniform; no break, so that j stays a constant
+          const long long gj = __builtin_bit_cast(long long, g[j]);
+          const double d = __builtin_bit_cast(
+              double, ((long long)__builtin_amdgcn_readlane((int)(gj >> 32), j) << 32) |
+                          (long long)(unsigned)__builtin_amdgcn_readlane((int)gj, j));
+          if (!(d > 0.0) || !isfinite(d)) {
+            bad = true;
+            continue;
+          }
+          dmin = fmin(dmin, d);
+          dmax = fmax(dmax, d);
+          const double rjj = sqrt(d), inv = 1.0 / rjj;
+          const double rjl = l > j ? g[j] * inv : (l == j ? rjj : 0.0);  // R[j][l]
+          if (lane < 16) Rp[s * 256 + j * 16 + lane] = rjl;
+          if (lane == 0) rdi[s * 16 + j] = inv;
+          const long long rb = __builtin_bit_cast(long long, rjl);
+#pragma unroll
+          for (int i = 0; i < 16; ++i) {
+            if (i <= j) continue;
+            const double rji = __builtin_bit_cast(
+                double, ((long long)__builtin_amdgcn_readlane((int)(rb >> 32), i) << 32) |
+                            (long long)(unsigned)__builtin_amdgcn_readlane((int)rb, i));
+            g[i] -= rji * rjl;  // G[i][l] -= R[j][i] R[j][l]
+          }
+        }
+        if (pass == 0 && !bad && dmin < 1e-12 * dmax) bad = true;
+        if (pass == 1 && !bad && (dmin < 0.5 || dmax > 2.0)) bad = true;
+        if (lane == 0 && bad) fail[s] = 1;
+      }
+    }
+    __syncthreads();
+    // ---- (C) Q := A R^-1 row by row (thread t owns rows t, t + NT, ...) ----
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      if (!on(s) || fail[s]) continue;  // uniform
+      const double* Rs = Rp + s * 256;
+#pragma unroll
+      for (int q = 0; q < RPT; ++q) {
+        const int r = tid + NT * q;
+        double x[MC];
+#pragma unroll
+        for (int c = 0; c < MC; ++c) x[c] = Psel(s)[c * LD + r];
+#pragma unroll
+        for (int c = 0; c < MC; ++c) {
+          double t = x[c];
+#pragma unroll
+          for (int m = 0; m < MC; ++m)
+            if (m < c) t -= x[m] * Rs[m * 16 + c];
+          x[c] = c < ncols(s) ? t * rdi[s * 16 + c] : 0.0;
+        }
+        if (r < nrows(s)) {
+#pragma unroll
+          for (int c = 0; c < MC; ++c) Psel(s)[c * LD + r] = x[c];
+        }
+      }
+    }
+    // ---- R := R_pass R (the Cholesky wavefronts; lane l owns column l) ----
+    {
+      const int s = wave / WPS;
+      if (wave % WPS == 0 && on(s) && !fail[s] && lane < 16) {
+        const int l = lane;
+        double col[16];
+#pragma unroll
+        for (int m = 0; m < 16; ++m) col[m] = pass == 0 ? (m == l ? 1.0 : 0.0) : Rsel(s)[m * kMaxC + l];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+          double t = 0.0;
+#pragma unroll
+          for (int m = 0; m < 16; ++m)
+            if (m >= i) t += Rp[s * 256 + i * 16 + m] * col[m];
+          Rsel(s)[i * kMaxC + l] = i < ncols(s) && l < ncols(s) ? t : 0.0;
+        }
+      }
+    }
+  }
+  __syncthreads();
+}
+
 // One bond per workgroup (Alg. 1): both site matricizations are gathered
 // into LDS and QR-factored together (QR skipped when a site has no more rows
-// than columns), the reflectors stay parked there, Theta = G R1 R2 is
+// than columns), Q (explicit, or as reflectors) stays there, Theta = G R1 R2 is
 // decomposed by a QR-preconditioned one-sided Jacobi in LDS, and the new
 // sites Q [R~; 0] are formed in registers and scattered into the
 // [u,d,l,r,p] layout with the new bond.  NT threads, RPT rows and MC columns
@@ -334,8 +519,12 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT / 256, NT
 void qrsvd_bond_kernel(IteArgs a) {
   extern __shared__ double park[];                          // [2][MC][RPT NT]
   __shared__ double R1[kMaxC * kMaxC], R2[kMaxC * kMaxC];  // k x cols, ld kMaxC
-  __shared__ double Th[kMaxTh * kMaxTh];                    // Theta, column-major (col * nr + row)
-  __shared__ double J[kMaxTh * kMaxTh];                     // right vectors, column-major
+  // Theta (column-major, col * nr + row) and Q / right vectors (column-major),
+  // one array so that the site factorization can use both as scratch first
+  __shared__ double ThJ[2 * kMaxTh * kMaxTh];
+  double* const Th = ThJ;
+  double* const J = ThJ + kMaxTh * kMaxTh;
+  __shared__ int cqf[2];  // CholeskyQR2 left a site to the Householder path
   __shared__ double tau1[kMaxC], tau2[kMaxC];
   __shared__ double tauT[kMaxTh], alphaT[kMaxTh];  // Householder QR of Theta
   __shared__ double red[NT / 64];
@@ -388,7 +577,29 @@ void qrsvd_bond_kernel(IteArgs a) {
     }
   }
   double* const Pf[2] = {park, park + (long long)MC * LD};
-  const int qcols[2] = {qr1 ? g1.cols : 0, qr2 ? g2.cols : 0};
+  cholqr2_sites<NT, RPT, MC, LD>(park, park + (long long)MC * LD, qr1, qr2, g1.rows, g2.rows, g1.cols, g2.cols, R1,
+                                 R2, ThJ, cqf);
+  // sites that CholeskyQR2 could not take: gathered again and Householder-QR
+  // factored (reflectors parked in P)
+  const bool hh1 = qr1 && cqf[0] != 0, hh2 = qr2 && cqf[1] != 0;
+  const bool ex1 = qr1 && !hh1, ex2 = qr2 && !hh2;  // explicit Q in P
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+    if (!(s == 0 ? hh1 : hh2)) continue;  // uniform
+    const SiteGeom& g = s == 0 ? g1 : g2;
+    const long long* coff = s == 0 ? coff1 : coff2;
+    const double* site = s == 0 ? site1 : site2;
+    double* P = park + (long long)s * MC * LD;
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+      const int r = tid + q * NT;
+      const bool in = r < g.rows;
+      const long long ro = in ? row_off(g, r) : 0;
+#pragma unroll
+      for (int c = 0; c < MC; ++c) P[c * LD + r] = (in && c < g.cols) ? site[ro + coff[c]] : 0.0;
+    }
+  }
+  const int qcols[2] = {hh1 ? g1.cols : 0, hh2 ? g2.cols : 0};
   {
     double* const Rf[2] = {R1, R2};
     double* const tf[2] = {tau1, tau2};
@@ -637,26 +848,56 @@ void qrsvd_bond_kernel(IteArgs a) {
 
   // ---- new sites: T' = Q [R~; 0] with columns (b, p) ---------------------
   const int ncol_out = Dn * d;
+  // R~[kk, (b, a)] of a site: X[(row,aa),b] from Q_T's rotated columns (site 1)
+  // or Y[(aa,row),b] from K's normalised columns (site 2), times sqrt(s_b)
+  auto rtilde = [&](int s, int row, int col) -> double {
+    const int b = col / d, aa = col - b * d;
+    const int c = perm[b];
+    const double sg = sig[c];
+    const double rs = sqrt(sv[b]);
+    if (s == 0) return J[(long long)c * nr + row * d + aa] * rs;
+    return sg > 0 ? Th[(long long)c * nc + aa * k2 + row] / sg * rs : 0.0;
+  };
+  // explicit-Q sites: R~ into R1 / R2 (free since Theta was formed), then
+  // every row is Q[row, :] R~
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+    if (!(s == 0 ? ex1 : ex2)) continue;
+    const int kk = s == 0 ? k1 : k2;
+    double* Rs = s == 0 ? R1 : R2;
+    for (int e = tid; e < kk * ncol_out; e += NT) {
+      const int row = e / ncol_out, col = e - row * ncol_out;
+      Rs[row * kMaxC + col] = rtilde(s, row, col);
+    }
+  }
+  __syncthreads();
   double B[2][RPT][MC];
 #pragma unroll
   for (int s = 0; s < 2; ++s) {
     const int kk = s == 0 ? k1 : k2;
-    // R~[kk, (b, a)] in the rows the thread owns (rows >= kk are zero)
 #pragma unroll
     for (int q = 0; q < RPT; ++q) {
       const int row = tid + q * NT;
+      if (s == 0 ? ex1 : ex2) {
+        const double* Ps = park + (long long)s * MC * LD;
+        const double* Rs = s == 0 ? R1 : R2;
+        double qr[MC];
 #pragma unroll
-      for (int col = 0; col < MC; ++col) {
-        double v = 0.0;
-        if (row < kk && col < ncol_out) {
-          const int b = col / d, aa = col - b * d;
-          const int c = perm[b];
-          const double sg = sig[c];
-          const double rs = sqrt(sv[b]);
-          if (s == 0) v = J[(long long)c * nr + row * d + aa] * rs;                         // X[(row,aa),b]
-          else v = sg > 0 ? Th[(long long)c * nc + aa * k2 + row] / sg * rs : 0.0;          // Y[(aa,row),b]
+        for (int c = 0; c < MC; ++c) qr[c] = Ps[c * LD + row];
+#pragma unroll
+        for (int col = 0; col < MC; ++col) {
+          double acc = 0.0;
+          if (col < ncol_out) {
+#pragma unroll
+            for (int c = 0; c < MC; ++c)
+              if (c < kk) acc += qr[c] * Rs[c * kMaxC + col];
+          }
+          B[s][q][col] = acc;
         }
-        B[s][q][col] = v;
+      } else {
+        // R~ in the rows the thread owns (rows >= kk are zero)
+#pragma unroll
+        for (int col = 0; col < MC; ++col) B[s][q][col] = row < kk && col < ncol_out ? rtilde(s, row, col) : 0.0;
       }
     }
   }
