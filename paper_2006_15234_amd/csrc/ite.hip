@@ -57,6 +57,8 @@ struct hpeps_ite_plan {
 namespace hp {
 namespace {
 
+typedef double v4d __attribute__((ext_vector_type(4)));
+
 constexpr int kT = 256;     // threads per bond workgroup
 constexpr int kMaxTh = 32;  // Theta is at most 32 x 32 (D d^2 <= 32)
 constexpr int kMaxC = 16;   // columns of a site matricization (shared bond x p) <= 16
@@ -323,49 +325,30 @@ __device__ __forceinline__ void house_apply2(const double* const (&P)[2], const 
 // Packed upper triangle of a 16 x 16 symmetric matrix: (a, b), a <= b, at
 // a * 16 - a (a - 1) / 2 + b - a (136 entries).
 __host__ __device__ constexpr int upk(int a, int b) { return a * 16 - a * (a - 1) / 2 + (b - a); }
-// (a, b) of packed entry idx (144 slots: 136 entries, then (0, 0))
-struct UpkTable {
-  int a[144], b[144];
-};
-__host__ __device__ constexpr UpkTable make_upk() {
-  UpkTable t{};
-  int idx = 0;
-  for (int a = 0; a < 16; ++a)
-    for (int b = a; b < 16; ++b) {
-      t.a[idx] = a;
-      t.b[idx] = b;
-      ++idx;
-    }
-  for (; idx < 144; ++idx) t.a[idx] = t.b[idx] = 0;
-  return t;
-}
-
 // CholeskyQR2 of the site matricizations P[s] (rows[s] x cols[s], LDS,
 // column-major, ld LD) that have on[s]: two passes of Gram -> Cholesky ->
 // Q := A R^-1, so that P[s] ends as the explicit Q and R[s] (row-major, ld
 // kMaxC) as R = R_2 R_1.  Each pass: (A) the two halves of the workgroup form
-// the two sites' Grams (a thread takes rows lt, lt + NT / 2, ...: 16 products
-// per chunk of the packed upper triangle, DPP reduce-scatter per wavefront,
-// partial sums to LDS); (B) one wavefront per site adds the partials and
-// factors the Gram in registers (lane l holds column l; readlane broadcasts
-// row j of R); (C) every thread solves q R = a for its rows (forward
+// the two sites' Grams on the matrix cores (each wavefront a block of rows;
+// the upper triangle of each wavefront's 16 x 16 MFMA product goes to LDS);
+// (B) one wavefront per site adds the partials and factors the Gram in
+// registers (lane l holds column l; row j of R goes back to every lane
+// through LDS); (C) every thread solves q R = a for its rows (forward
 // substitution with R from LDS).  A site whose Cholesky breaks down, whose
 // first-pass pivots span more than 1e12 (condition number beyond about 1e6,
 // where CholeskyQR2 loses accuracy) or whose second-pass pivots are not near
 // 1 gets fail[s] = 1 and is left to the Householder path (its P[s] must then
 // be gathered again: the first pass may have overwritten it).
-// scratch: 2 (NT / 128) 144 partials + 2 x 256 pass factors + 2 x 16
-// reciprocal diagonals (at most 1696 doubles).
+// scratch: 2 (NT / 128) 136 partials + 2 x 256 pass factors + 2 x 16
+// reciprocal diagonals (at most 1632 doubles).
 template <int NT, int RPT, int MC, int LD>
 __device__ void cholqr2_sites(double* P0, double* P1, bool on0, bool on1, int rows0, int rows1, int cols0,
                               int cols1, double* R0, double* R1, double* scratch, int* fail) {
   constexpr int WPS = NT / 128;  // wavefronts per site in the Gram phase
   constexpr int TPS = NT / 2;    // threads per site
-  constexpr int RQ = 2 * RPT;    // rows per thread in the Gram phase
-  constexpr int NCH = 9;         // chunks of 16 packed entries (136 used)
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  double* part = scratch;                      // [2][WPS][NCH * 16]
-  double* Rp = scratch + 2 * WPS * NCH * 16;   // [2][256]: this pass's factor
+  double* part = scratch;                 // [2][WPS][136]
+  double* Rp = scratch + 2 * WPS * 136;   // [2][256]: this pass's factor
   double* rdi = Rp + 2 * 256;                  // [2][16]: its reciprocal diagonal
   auto Psel = [&](int s) { return s == 0 ? P0 : P1; };
   auto Rsel = [&](int s) { return s == 0 ? R0 : R1; };
@@ -375,35 +358,25 @@ __device__ void cholqr2_sites(double* P0, double* P1, bool on0, bool on1, int ro
   if (tid < 2) fail[tid] = 0;
   for (int pass = 0; pass < 2; ++pass) {
     __syncthreads();  // P final from the previous pass (or the gather); fail reset
-    // ---- (A) Gram partial sums ----
+    // ---- (A) Gram partial sums on the matrix cores ----
+    // G = A^T A over a wavefront's rows: v_mfma_f64_16x16x4 with A^T as the
+    // first and A as the second operand, so that lane (li, lk) feeds the same
+    // element A[r0 + lk][li] to both; accumulator r holds G[lk + 4 r][li].
     {
-      const int s = wave / WPS, wl = wave % WPS, lt = tid % TPS;
+      const int s = wave / WPS, wl = wave % WPS;
       if (on(s)) {  // wavefront-uniform
-        double x[RQ][MC];
-#pragma unroll
-        for (int q = 0; q < RQ; ++q) {
-          const int r = lt + TPS * q;
-          const bool in = r < nrows(s);
-#pragma unroll
-          for (int c = 0; c < MC; ++c) x[q][c] = in && c < ncols(s) ? Psel(s)[c * LD + (in ? r : 0)] : 0.0;
+        const int li = lane & 15, lk = lane >> 4;
+        const double* Ps = Psel(s) + (li < MC ? li : 0) * LD + wl * (LD / WPS) + lk;
+        v4d acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 8
+        for (int kb = 0; kb < LD / WPS / 4; ++kb) {
+          const double x = li < MC ? Ps[4 * kb] : 0.0;
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(x, x, acc, 0, 0, 0);
         }
-        constexpr UpkTable kU = make_upk();
 #pragma unroll
-        for (int ch = 0; ch < NCH; ++ch) {
-          double pv[16];
-#pragma unroll
-          for (int v = 0; v < 16; ++v) {
-            const int idx = ch * 16 + v;
-            const int a = kU.a[idx], b = kU.b[idx];  // constants after unrolling
-            double acc = 0.0;
-            if (idx < 136 && a < MC && b < MC) {
-#pragma unroll
-              for (int q = 0; q < RQ; ++q) acc += x[q][a < MC ? a : 0] * x[q][b < MC ? b : 0];
-            }
-            pv[v] = acc;
-          }
-          const double tot = wave_reduce_scatter16(pv, lane);
-          if (lane < 16) part[(s * WPS + wl) * NCH * 16 + ch * 16 + lane] = tot;
+        for (int r = 0; r < 4; ++r) {
+          const int ra = lk + 4 * r;
+          if (ra <= li) part[(s * WPS + wl) * 136 + upk(ra, li)] = acc[r];
         }
       }
     }
@@ -419,7 +392,7 @@ __device__ void cholqr2_sites(double* P0, double* P1, bool on0, bool on1, int ro
           const int a = i < l ? i : l, b = i < l ? l : i;
           double t = 0.0;
 #pragma unroll
-          for (int w = 0; w < WPS; ++w) t += part[(s * WPS + w) * NCH * 16 + upk(a, b)];
+          for (int w = 0; w < WPS; ++w) t += part[(s * WPS + w) * 136 + upk(a, b)];
           g[i] = t;
         }
         double dmin = 1e300, dmax = 0.0;
@@ -437,18 +410,16 @@ __device__ void cholqr2_sites(double* P0, double* P1, bool on0, bool on1, int ro
           }
           dmin = fmin(dmin, d);
           dmax = fmax(dmax, d);
-          const double rjj = sqrt(d), inv = 1.0 / rjj;
+          const double inv = rsqrt(d), rjj = d * inv;
           const double rjl = l > j ? g[j] * inv : (l == j ? rjj : 0.0);  // R[j][l]
           if (lane < 16) Rp[s * 256 + j * 16 + lane] = rjl;
           if (lane == 0) rdi[s * 16 + j] = inv;
-          const long long rb = __builtin_bit_cast(long long, rjl);
+          // row j of R back to every lane through LDS (this wavefront wrote
+          // it just above: program order)
 #pragma unroll
           for (int i = 0; i < 16; ++i) {
             if (i <= j) continue;
-            const double rji = __builtin_bit_cast(
-                double, ((long long)__builtin_amdgcn_readlane((int)(rb >> 32), i) << 32) |
-                            (long long)(unsigned)__builtin_amdgcn_readlane((int)rb, i));
-            g[i] -= rji * rjl;  // G[i][l] -= R[j][i] R[j][l]
+            g[i] -= Rp[s * 256 + j * 16 + i] * rjl;  // G[i][l] -= R[j][i] R[j][l]
           }
         }
         if (pass == 0 && !bad && dmin < 1e-12 * dmax) bad = true;
@@ -487,17 +458,21 @@ __device__ void cholqr2_sites(double* P0, double* P1, bool on0, bool on1, int ro
       const int s = wave / WPS;
       if (wave % WPS == 0 && on(s) && !fail[s] && lane < 16) {
         const int l = lane;
-        double col[16];
+        double col[16], out[16];
 #pragma unroll
         for (int m = 0; m < 16; ++m) col[m] = pass == 0 ? (m == l ? 1.0 : 0.0) : Rsel(s)[m * kMaxC + l];
+        // every read before the first write (the compiler cannot tell the two
+        // LDS arrays apart, and would otherwise wait on each read in turn)
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
           double t = 0.0;
 #pragma unroll
           for (int m = 0; m < 16; ++m)
             if (m >= i) t += Rp[s * 256 + i * 16 + m] * col[m];
-          Rsel(s)[i * kMaxC + l] = i < ncols(s) && l < ncols(s) ? t : 0.0;
+          out[i] = t;
         }
+#pragma unroll
+        for (int i = 0; i < 16; ++i) Rsel(s)[i * kMaxC + l] = i < ncols(s) && l < ncols(s) ? out[i] : 0.0;
       }
     }
   }
@@ -510,7 +485,7 @@ __device__ void cholqr2_sites(double* P0, double* P1, bool on0, bool on1, int ro
 // decomposed by a QR-preconditioned one-sided Jacobi in LDS, and the new
 // sites Q [R~; 0] are formed in registers and scattered into the
 // [u,d,l,r,p] layout with the new bond.  NT threads, RPT rows and MC columns
-// per thread; dynamic LDS: two column-major RPT NT x MC reflector blocks.
+// per thread; dynamic LDS: two column-major (RPT NT + 1) x MC panel blocks.
 // The panels' LDS leaves room for one workgroup per CU, i.e. NT / 256
 // wavefronts per SIMD: the register allocator may use that budget to keep
 // more LDS loads in flight.
@@ -534,7 +509,9 @@ void qrsvd_bond_kernel(IteArgs a) {
   __shared__ int perm[kMaxTh];
   __shared__ int rot, chk;
   __shared__ SiteGeom g1, g2, go[2];
-  constexpr int LD = RPT * NT;
+  // odd leading dimension: accesses that stride across columns (the 16 lanes
+  // of an MFMA operand, the pivot-row copies) fall in distinct LDS banks
+  constexpr int LD = RPT * NT + 1;
   const int bi = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = NT / 64;
   const int s1 = a.bonds[4 * bi], s2 = a.bonds[4 * bi + 1], axis = a.bonds[4 * bi + 2];
   if (tid == 0) {
@@ -960,7 +937,7 @@ void launch_layer(hipStream_t st, const IteArgs& a, int nb) {
   // the dynamic LDS limit is raised once per variant and process
   static std::once_flag once[3];
   auto go = [&](auto kern, int v, int nt, int rpt, int mc) {
-    const size_t lds = (size_t)2 * mc * rpt * nt * sizeof(double);
+    const size_t lds = (size_t)2 * mc * (rpt * nt + 1) * sizeof(double);
     hipError_t e = hipSuccess;
     std::call_once(once[v], [&] {
       e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
