@@ -11,12 +11,23 @@ namespace hp {
 // butterfly sums would differ between lanes in the last bit.  Callers rely on
 // every lane of a row holding the same sum (rotation parameters computed in
 // each lane must agree).
+//
+// With every row enabled (ROW_MASK 0xf, a move within each row) no lane keeps
+// the destination's old value, so the plain DPP move is used and the
+// compiler does not zero the destination first; a partial row mask (the row
+// broadcasts) leaves the other rows at the old value 0, which adds nothing.
 template <int CTRL, int ROW_MASK>
 __device__ __forceinline__ double dpp_add(double v) {
 #pragma clang fp contract(off)
   const long long x = __builtin_bit_cast(long long, v);
-  const int lo = __builtin_amdgcn_update_dpp(0, (int)x, CTRL, ROW_MASK, 0xf, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, (int)(x >> 32), CTRL, ROW_MASK, 0xf, false);
+  int lo, hi;
+  if constexpr (ROW_MASK == 0xf) {
+    lo = __builtin_amdgcn_mov_dpp((int)x, CTRL, 0xf, 0xf, false);
+    hi = __builtin_amdgcn_mov_dpp((int)(x >> 32), CTRL, 0xf, 0xf, false);
+  } else {
+    lo = __builtin_amdgcn_update_dpp(0, (int)x, CTRL, ROW_MASK, 0xf, false);
+    hi = __builtin_amdgcn_update_dpp(0, (int)(x >> 32), CTRL, ROW_MASK, 0xf, false);
+  }
   return v + __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned)lo);
 }
 
