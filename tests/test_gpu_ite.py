@@ -54,6 +54,44 @@ def test_two_site_gate_parity(ctx, axis, D, Dmax):
     assert np.array_equal(h[0][0], peps[0][0])
 
 
+def _condition_site(T, shared, cond, rng):
+    """T with the singular values of its (other legs) x (shared bond, p) matricization
+    replaced by a geometric sequence from 1 down to 1 / cond."""
+    perm = [a for a in range(4) if a != shared] + [shared, 4]
+    Tp = T.transpose(perm)
+    M = Tp.reshape(-1, T.shape[shared] * T.shape[4])
+    U, _, Vt = np.linalg.svd(M, full_matrices=False)
+    s = np.geomspace(1.0, 1.0 / cond, M.shape[1])
+    rng.shuffle(s)
+    return ((U * s) @ Vt).reshape(Tp.shape).transpose(np.argsort(perm)).copy()
+
+
+@pytest.mark.parametrize("axis", [0, 1])
+@pytest.mark.parametrize("cond1,cond2", [(1e8, 1.0), (1.0, 1e8), (1e8, 1e8), (1e4, 1e5)])
+def test_two_site_gate_ill_conditioned_sites(ctx, axis, cond1, cond2):
+    """Bond 8 sites (512 x 16 matricizations) with prescribed condition numbers: a site
+    beyond about 1e6 is left to the Householder path, the others are factored by
+    CholeskyQR2, in the same update (both mixed cases, both sites on either path).  The
+    kept values at 1e-12 and the two-site product at 1e-12 of its largest entry against
+    the oracle's Householder QR-SVD."""
+    nrow, ncol = (3, 4) if axis == 0 else (4, 3)
+    peps = synth.random_peps(nrow, ncol, D=8, seed=31 + axis)
+    rng = np.random.default_rng(7)
+    i, j = 1, 1
+    i2, j2 = (i, j + 1) if axis == 0 else (i + 1, j)
+    peps[i][j] = _condition_site(peps[i][j], 3 if axis == 0 else 1, cond1, rng)
+    peps[i2][j2] = _condition_site(peps[i2][j2], 2 if axis == 0 else 0, cond2, rng)
+    H = rng.standard_normal((4, 4))
+    G = synth.bond_gate((H + H.T).reshape(2, 2, 2, 2), 0.3)
+    T1n, T2n, s = ite.qr_svd_update(peps[i][j], peps[i2][j2], G, axis, 8)
+    new, sg = hp.apply_two_site_gate(ctx, dev_lattice(peps), i, j, axis, torch.from_numpy(G).cuda(), 8)
+    h = host_lattice(new)
+    assert h[i][j].shape == T1n.shape and h[i2][j2].shape == T2n.shape
+    assert np.max(np.abs(sg.cpu().numpy() - s)) < 1e-12
+    pa, pb = _pair_product(h[i][j], h[i2][j2], axis), _pair_product(T1n, T2n, axis)
+    assert np.max(np.abs(pa - pb)) < 1e-12 * np.max(np.abs(pb))
+
+
 def _tfi_plan_inputs(nrow, ncol, tau, J=1.0, hfield=3.0):
     layers = synth.lattice_bonds(nrow, ncol)
     hams = synth.tfi_bond_hamiltonians(nrow, ncol, J, hfield)
