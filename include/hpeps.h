@@ -593,7 +593,8 @@ hpeps_status hpeps_ite_plan_layers(hpeps_ite_plan* plan, int32_t* n_layers, int3
 /* Runs n_sweeps sweeps: use_graph = 1 replays the captured graph of the
  * layer launches, 0 issues the layer launches directly, 2 is the plain
  * form with one launch per bond (no graph; the baseline of the batched
- * forms).  All three compute the same updates. */
+ * forms).  All three compute the same updates; other values of use_graph
+ * (and n_sweeps < 0) return INVALID_ARG. */
 hpeps_status hpeps_ite_run(hpeps_ite_plan* plan, int32_t n_sweeps, int32_t use_graph);
 /* Kept singular values of every bond update of the most recent sweep (Alg. 1
  * step: the truncated spectrum of Theta normalised to unit 2-norm), bond by

@@ -932,25 +932,36 @@ void check_dims(int64_t dmax, int d) {
 // SIMD hide each other's LDS round trips; the LDS of the two 512 x 16
 // panels allows one workgroup per CU).  D^3 > 512 needs D >= 9, hence d = 1
 // and at most 9 columns.
+template <int NT, int RPT, int MC>
+struct BondVariant {
+  static constexpr int nt = NT, rpt = RPT, mc = MC;
+};
+
 void launch_layer(hipStream_t st, const IteArgs& a, int nb) {
   if (nb == 0) return;
   // the dynamic LDS limit is raised once per variant and process
   static std::once_flag once[3];
-  auto go = [&](auto kern, int v, int nt, int rpt, int mc) {
-    const size_t lds = (size_t)2 * mc * (rpt * nt + 1) * sizeof(double);
+  // the kernel is launched by name, never through a pointer to it (such a
+  // launch has run nothing, without an error, in host code built with
+  // instrumentation); the tag carries the variant's template arguments
+  auto go = [&](auto t, int v) {
+    using T = decltype(t);
+    constexpr int NT = T::nt, RPT = T::rpt, MC = T::mc;
+    const size_t lds = (size_t)2 * MC * (RPT * NT + 1) * sizeof(double);
     hipError_t e = hipSuccess;
     std::call_once(once[v], [&] {
-      e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      e = hipFuncSetAttribute((const void*)&qrsvd_bond_kernel<NT, RPT, MC>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     });
     HP_CHECK_HIP(e);
-    kern<<<nb, nt, lds, st>>>(a);
+    qrsvd_bond_kernel<NT, RPT, MC><<<nb, NT, lds, st>>>(a);
   };
   if (a.max_rows <= kT)
-    go(qrsvd_bond_kernel<kT, 1, kMaxC>, 0, kT, 1, kMaxC);
+    go(BondVariant<kT, 1, kMaxC>{}, 0);
   else if (a.max_rows <= 2 * kT)
-    go(qrsvd_bond_kernel<2 * kT, 1, kMaxC>, 1, 2 * kT, 1, kMaxC);
+    go(BondVariant<2 * kT, 1, kMaxC>{}, 1);
   else
-    go(qrsvd_bond_kernel<kT, 3, 9>, 2, kT, 3, 9);
+    go(BondVariant<kT, 3, 9>{}, 2);
 }
 
 // One-site gates (Eq. 3) of a layer, in place: workgroup b applies the d x d
@@ -1379,7 +1390,7 @@ hpeps_status hpeps_ite_plan_layers(hpeps_ite_plan* p, int32_t* n_layers, int32_t
 }
 
 hpeps_status hpeps_ite_run(hpeps_ite_plan* p, int32_t n_sweeps, int32_t use_graph) {
-  if (!p || n_sweeps < 0) return HPEPS_ERR_INVALID_ARG;
+  if (!p || n_sweeps < 0 || use_graph < 0 || use_graph > 2) return HPEPS_ERR_INVALID_ARG;
   hp::Ctx& c = *p->ctx;
   return guard_i(&c, [&] {
     const int nl = (int)p->nb.size();

@@ -15,6 +15,7 @@
 // with the k x k matrix resident in LDS (up to 128 KB of the 160 KB).
 #include <algorithm>
 #include <cmath>
+#include <type_traits>
 
 #include "dpp.h"
 #include "internal.h"
@@ -1007,14 +1008,22 @@ void chol_inv(Ctx& ctx, bool cplx, const double* G, int64_t n_rows, int64_t k, i
   HP_REQUIRE(k <= 128 && lds <= 160 * 1024 - 2048, HPEPS_ERR_UNSUPPORTED,
              "sketch width too large for the small factorizations (k <= 128, complex k <= 88)");
   const int rec = ctx.prof_begin("chol_inv");
-  auto launch = [&](auto kern) {
-    HP_CHECK_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    kern<<<batch, kCholThreads, lds, ctx.stream>>>(G, n_rows, (int)k, pass, Rinv, Racc, flags, r_only ? 1 : 0);
+  // kernels are launched by name (a launch through a pointer to the kernel
+  // has run nothing, without an error, in host code built with
+  // instrumentation); the tags carry the template arguments
+  auto launch = [&](auto cplx_c, auto big_c) {
+    constexpr bool C = decltype(cplx_c)::value, BIG = decltype(big_c)::value;
+    HP_CHECK_HIP(hipFuncSetAttribute((const void*)&chol_inv_kernel<C, BIG>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    chol_inv_kernel<C, BIG><<<batch, kCholThreads, lds, ctx.stream>>>(G, n_rows, (int)k, pass, Rinv, Racc, flags,
+                                                                      r_only ? 1 : 0);
   };
+  using T = std::true_type;
+  using F = std::false_type;
   if (cplx)
-    k > 64 ? launch(chol_inv_kernel<true, true>) : launch(chol_inv_kernel<true, false>);
+    k > 64 ? launch(T{}, T{}) : launch(T{}, F{});
   else
-    k > 64 ? launch(chol_inv_kernel<false, true>) : launch(chol_inv_kernel<false, false>);
+    k > 64 ? launch(F{}, T{}) : launch(F{}, F{});
   HP_CHECK_HIP(hipGetLastError());
   ctx.prof_end(rec, (double)batch * k * k * k / 3.0 * (cplx ? 4 : 1), 0.0);
 }
@@ -1039,22 +1048,26 @@ void jacobi_svd(Ctx& ctx, bool cplx, const double* Racc, int64_t k, int batch, i
       }
     }
   } end_rec{ctx, rec};
-  auto launch = [&](auto kern) {
-    HP_CHECK_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    kern<<<batch, threads, lds, ctx.stream>>>(Racc, (int)k, max_sweeps, Z, sigma, inv_sigma, inv_sigma1, log_scale,
-                                              stats);
+  // launched by name, never through a pointer to the kernel (the tags carry
+  // the template arguments)
+  auto launch = [&](auto cplx_c, auto rows_c) {
+    constexpr bool C = decltype(cplx_c)::value;
+    constexpr int RB = decltype(rows_c)::value;
+    HP_CHECK_HIP(hipFuncSetAttribute((const void*)&jacobi_kernel<C, RB>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)lds));
+    jacobi_kernel<C, RB><<<batch, threads, lds, ctx.stream>>>(Racc, (int)k, max_sweeps, Z, sigma, inv_sigma,
+                                                              inv_sigma1, log_scale, stats);
   };
   auto by_rows = [&](auto cplx_c) {
-    constexpr bool C = decltype(cplx_c)::value;
     switch ((k + 15) / 16) {
-      case 1: launch(jacobi_kernel<C, 1>); break;
-      case 2: launch(jacobi_kernel<C, 2>); break;
-      case 3: launch(jacobi_kernel<C, 3>); break;
-      case 4: launch(jacobi_kernel<C, 4>); break;
-      case 5: launch(jacobi_kernel<C, 5>); break;
-      case 6: launch(jacobi_kernel<C, 6>); break;
-      case 7: launch(jacobi_kernel<C, 7>); break;
-      default: launch(jacobi_kernel<C, 8>); break;
+      case 1: launch(cplx_c, std::integral_constant<int, 1>{}); break;
+      case 2: launch(cplx_c, std::integral_constant<int, 2>{}); break;
+      case 3: launch(cplx_c, std::integral_constant<int, 3>{}); break;
+      case 4: launch(cplx_c, std::integral_constant<int, 4>{}); break;
+      case 5: launch(cplx_c, std::integral_constant<int, 5>{}); break;
+      case 6: launch(cplx_c, std::integral_constant<int, 6>{}); break;
+      case 7: launch(cplx_c, std::integral_constant<int, 7>{}); break;
+      default: launch(cplx_c, std::integral_constant<int, 8>{}); break;
     }
   };
   if (cplx)
