@@ -266,6 +266,24 @@ hpeps_status hpeps_einsumsvd_query(hpeps_ctx* ctx, const char* subscripts, int32
                                    const hpeps_tensor* ops, const hpeps_esvd_opts* opts, int64_t* rows,
                                    int64_t* cols, int64_t* rank_kept);
 
+/* ---- batched einsumsvd of an arbitrary network (Sec. II-C, Alg. 4) ------
+ * `batch` independent instances of the network of hpeps_einsumsvd, each
+ * factorized on its own.  Every operand has one more dimension than its
+ * subscript term, the leading one, of extent `batch`; its stride is the
+ * instance stride and must be at least one instance's extent (instances are
+ * disjoint; a stride that does not meet this is SHAPE).  The subscripts
+ * name only the per-instance legs.  Instance b draws its sketch from stream
+ * opts->stream_id + b, so it equals hpeps_einsumsvd on that instance's
+ * operands with stream_id + b.  Each product of the network runs once for
+ * all instances (one batched gathered GEMM), and so does every later stage.
+ * Outputs (device, caller-owned, contiguous): U [batch][row legs..., m'],
+ * sigma [batch][m'] (may be NULL), R [batch][m'][column legs...];
+ * log_scale [batch] for the CARRY mode.  batch < 1 is INVALID_ARG; other
+ * errors as for hpeps_einsumsvd. */
+hpeps_status hpeps_einsumsvd_batched(hpeps_ctx* ctx, hpeps_dtype dtype, int64_t batch, const char* subscripts,
+                                     int32_t n_ops, const hpeps_tensor* ops, const hpeps_esvd_opts* opts,
+                                     hpeps_absorb absorb, void* U, double* sigma, void* R, double* log_scale);
+
 /* ---- einsumsvd on the zip-up network (Alg. 3 inner step, Alg. 4) -------
  * One einsumsvd of boundary contraction: the carry V[a,x,X,b,h,H] of the
  * previous column, the boundary tensor S[b,u,U,c], the ket site

@@ -78,6 +78,8 @@ _SIGS = {
                                C.c_uint64, _P]),
     "hpeps_einsumsvd": (C.c_int, [_P, C.c_int, C.c_char_p, C.c_int32, C.POINTER(Tensor),
                                   C.POINTER(EsvdOpts), C.c_int, _P, _P, _P, _P]),
+    "hpeps_einsumsvd_batched": (C.c_int, [_P, C.c_int, C.c_int64, C.c_char_p, C.c_int32, C.POINTER(Tensor),
+                                          C.POINTER(EsvdOpts), C.c_int, _P, _P, _P, _P]),
     "hpeps_einsumsvd_query": (C.c_int, [_P, C.c_char_p, C.c_int32, C.POINTER(Tensor),
                                         C.POINTER(EsvdOpts), _I64P, _I64P, _I64P]),
     "hpeps_einsumsvd_zipup": (C.c_int, [_P, C.c_int64, C.c_int, _I64P, _P, _P, _P, _P,

@@ -98,6 +98,39 @@ def einsumsvd(ctx, subscripts, *tensors, conj=None, rank, oversample=0, power_it
     return U, sig, R
 
 
+def einsumsvd_batched(ctx, subscripts, *tensors, conj=None, rank, oversample=0, power_iters=0, seed=0,
+                      stream_id=0, absorb=ABSORB_NONE, log_scale=None, jacobi_max_sweeps=0, orth="cholqr",
+                      method="implicit"):
+    """einsumsvd of `batch` instances of the network `subscripts` at once: every operand has a
+    leading instance dimension (the subscripts name the per-instance legs); instance b draws its
+    sketch from stream stream_id + b.  Returns (U [B, row dims..., m'], sigma [B, m'],
+    R [B, m', column dims...])."""
+    torch = _torch()
+    if not tensors:
+        raise ValueError("no operands")
+    batch = tensors[0].shape[0]
+    if any(t.dim() < 2 or t.shape[0] != batch for t in tensors):
+        raise ValueError("every operand needs the same leading batch dimension")
+    dt = _dtype_code(tensors[0])
+    if any(t.dtype != tensors[0].dtype for t in tensors):
+        raise TypeError("operands must share one dtype")
+    one, ldims, rdims = _network(subscripts, [t[0] for t in tensors], conj)
+    descs, _, _ = _network(subscripts, tensors, conj)
+    o = make_opts(rank, oversample, power_iters, "f64", seed, stream_id, jacobi_max_sweeps, orth, method)
+    rows, cols, mp = C.c_int64(), C.c_int64(), C.c_int64()
+    ctx.check(ctx.lib.hpeps_einsumsvd_query(ctx.h, subscripts.encode(), len(tensors), one, C.byref(o),
+                                            C.byref(rows), C.byref(cols), C.byref(mp)))
+    dev = tensors[0].device
+    U = torch.empty((batch, *ldims, mp.value), dtype=tensors[0].dtype, device=dev)
+    sig = torch.empty((batch, mp.value), dtype=torch.float64, device=dev)
+    R = torch.empty((batch, mp.value, *rdims), dtype=tensors[0].dtype, device=dev)
+    ctx.sync_stream()
+    ctx.check(ctx.lib.hpeps_einsumsvd_batched(
+        ctx.h, dt, batch, subscripts.encode(), len(tensors), descs, C.byref(o), absorb, _dev(U, "U"),
+        _dev(sig, "sigma"), _dev(R, "R"), _dev(log_scale, "log_scale") if log_scale is not None else None))
+    return U, sig, R
+
+
 def einsumsvd_zipup(ctx, V, S, T, Bra=None, *, rank, oversample=0, power_iters=0, seed=0,
                     stream_id=0, precision="f64", absorb=ABSORB_CARRY, log_scale=None,
                     jacobi_max_sweeps=0, orth="cholqr"):

@@ -211,6 +211,25 @@ hpeps_status hpeps_einsumsvd(hpeps_ctx* ctx, hpeps_dtype dtype, const char* subs
   });
 }
 
+hpeps_status hpeps_einsumsvd_batched(hpeps_ctx* ctx, hpeps_dtype dtype, int64_t batch, const char* subscripts,
+                                     int32_t n_ops, const hpeps_tensor* ops, const hpeps_esvd_opts* opts,
+                                     hpeps_absorb absorb, void* U, double* sigma, void* R, double* log_scale) {
+  if (!ctx) return HPEPS_ERR_INVALID_ARG;
+  return guard(ctx, [&] {
+    check_opts(opts);
+    const bool cplx = is_cplx(dtype);
+    HP_REQUIRE(batch >= 1, HPEPS_ERR_INVALID_ARG, "batch must be >= 1");
+    HP_REQUIRE(U && R, HPEPS_ERR_INVALID_ARG, "null output");
+    HP_REQUIRE(absorb >= HPEPS_ABSORB_CARRY && absorb <= HPEPS_ABSORB_SQRT, HPEPS_ERR_INVALID_ARG,
+               "bad absorb mode");
+    HP_REQUIRE(absorb != HPEPS_ABSORB_CARRY || log_scale, HPEPS_ERR_INVALID_ARG,
+               "the CARRY mode needs log_scale");
+    hp::Ctx& c = *ctx->impl;
+    c.ws_reset();
+    hp::einsumsvd_network(c, cplx, subscripts, n_ops, ops, *opts, absorb, U, sigma, R, log_scale, batch);
+  });
+}
+
 hpeps_status hpeps_einsumsvd_query(hpeps_ctx* ctx, const char* subscripts, int32_t n_ops,
                                    const hpeps_tensor* ops, const hpeps_esvd_opts* opts, int64_t* rows,
                                    int64_t* cols, int64_t* rank_kept) {

@@ -16,18 +16,43 @@ namespace hp {
 namespace {
 
 constexpr char kSketchLeg = '#';  // the panel's k leg (never a subscript letter)
+constexpr char kBatchLeg = '$';   // the instance leg of the batched form (likewise)
 
 struct Network {
   std::vector<TView> ops;
   std::string left, right;               // open legs of the rows / columns, in order
   std::vector<int64_t> ldims, rdims;
   int64_t rows = 1, cols = 1;
+  // batched form: every operand carries the instance leg kBatchLeg (its
+  // leading dimension); 0 for the single network
+  int64_t batch = 0;
+  std::string bl() const { return batch ? std::string(1, kBatchLeg) : std::string(); }
+  std::vector<int64_t> bd() const { return batch ? std::vector<int64_t>{batch} : std::vector<int64_t>{}; }
 };
+
+// Legs of the product of the running tensor `cur` with `op` (the legs of
+// either that the other lacks; the instance leg first and kept) and the
+// number of legs they share besides it.
+std::string product_legs(const Network& net, const TView& cur, const TView& op, int* shared) {
+  std::string o = net.bl();
+  *shared = 0;
+  for (char c : cur.legs) {
+    if (c == kBatchLeg) continue;
+    if (op.legs.find(c) == std::string::npos) o += c; else ++*shared;
+  }
+  for (char c : op.legs)
+    if (c != kBatchLeg && cur.legs.find(c) == std::string::npos) o += c;
+  return o;
+}
 
 bool leg_char(char c) { return (c >= 'a' && c <= 'z') || (c >= 'A' && c <= 'Z'); }
 
-Network parse(const char* subscripts, int n_ops, const hpeps_tensor* ops, bool cplx) {
+// batch 0: the single network; batch >= 1: every operand has one more,
+// leading, dimension of extent `batch` (the instance leg), whose stride is
+// at least one instance's extent.
+Network parse(const char* subscripts, int n_ops, const hpeps_tensor* ops, bool cplx, int64_t batch = 0) {
   HP_REQUIRE(subscripts && ops && n_ops >= 1 && n_ops <= 64, HPEPS_ERR_INVALID_ARG, "bad einsumsvd operands");
+  HP_REQUIRE(batch >= 0 && batch < (1LL << 31), HPEPS_ERR_INVALID_ARG, "bad batch count");
   const std::string s(subscripts);
   const auto arrow = s.find("->");
   HP_REQUIRE(arrow != std::string::npos, HPEPS_ERR_INVALID_ARG, "subscripts need '->'");
@@ -36,6 +61,8 @@ Network parse(const char* subscripts, int n_ops, const hpeps_tensor* ops, bool c
   HP_REQUIRE(bar != std::string::npos && rhs.find('|', bar + 1) == std::string::npos, HPEPS_ERR_INVALID_ARG,
              "the output needs exactly one '|' between row legs and column legs");
   Network net;
+  net.batch = batch;
+  const int lead = batch ? 1 : 0;
   net.left = rhs.substr(0, bar);
   net.right = rhs.substr(bar + 1);
   HP_REQUIRE(!net.left.empty() && !net.right.empty(), HPEPS_ERR_INVALID_ARG, "empty row or column legs");
@@ -56,11 +83,12 @@ Network parse(const char* subscripts, int n_ops, const hpeps_tensor* ops, bool c
     const std::string& t = terms[i];
     const hpeps_tensor& o = ops[i];
     HP_REQUIRE(o.data, HPEPS_ERR_INVALID_ARG, "null operand");
-    HP_REQUIRE(o.ndim >= 1 && o.ndim <= 8 && (int)t.size() == o.ndim, HPEPS_ERR_SHAPE,
-               "operand " + std::to_string(i) + ": legs and ndim differ");
-    std::vector<int64_t> dims(o.shape, o.shape + o.ndim), strides(o.strides, o.strides + o.ndim);
+    HP_REQUIRE(o.ndim >= 1 + lead && o.ndim <= 8 && (int)t.size() + lead == o.ndim, HPEPS_ERR_SHAPE,
+               "operand " + std::to_string(i) + (batch ? ": legs + 1 (the batch dimension) and ndim differ"
+                                                       : ": legs and ndim differ"));
+    std::vector<int64_t> dims(o.shape + lead, o.shape + o.ndim), strides(o.strides + lead, o.strides + o.ndim);
     int64_t extent = 1;
-    for (int q = 0; q < o.ndim; ++q) {
+    for (int q = 0; q < (int)t.size(); ++q) {
       const char c = t[q];
       HP_REQUIRE(leg_char(c), HPEPS_ERR_INVALID_ARG, "legs are letters a-z, A-Z");
       HP_REQUIRE(t.find(c) == (size_t)q, HPEPS_ERR_INVALID_ARG, "a leg repeated within one operand");
@@ -72,7 +100,20 @@ Network parse(const char* subscripts, int n_ops, const hpeps_tensor* ops, bool c
       dim[(int)c] = dims[q];
       ++count[(int)c];
     }
-    net.ops.push_back(tview(o.data, t, dims, strides, extent, cplx && o.conj != 0));
+    if (batch) {
+      // instances are disjoint blocks: the batch stride covers one instance
+      HP_REQUIRE(o.shape[0] == batch, HPEPS_ERR_SHAPE,
+                 "operand " + std::to_string(i) + ": leading dimension differs from the batch count");
+      const int64_t bs = batch == 1 ? std::max<int64_t>(o.strides[0], extent) : o.strides[0];
+      HP_REQUIRE(bs >= extent, HPEPS_ERR_SHAPE,
+                 "operand " + std::to_string(i) + ": batch stride smaller than one instance");
+      dims.insert(dims.begin(), batch);
+      strides.insert(strides.begin(), bs);
+      extent = batch * bs;
+      net.ops.push_back(tview(o.data, std::string(1, kBatchLeg) + t, dims, strides, extent, cplx && o.conj != 0));
+    } else {
+      net.ops.push_back(tview(o.data, t, dims, strides, extent, cplx && o.conj != 0));
+    }
   }
   for (char c : net.left + net.right) {
     HP_REQUIRE(leg_char(c), HPEPS_ERR_INVALID_ARG, "legs are letters a-z, A-Z");
@@ -110,9 +151,10 @@ void apply_network(Ctx& ctx, bool cplx, const Network& net, bool adjoint, const 
   WsScope scope(ctx);
   const std::string& in = adjoint ? net.left : net.right;
   const std::string& out = adjoint ? net.right : net.left;
-  std::vector<int64_t> idims = adjoint ? net.ldims : net.rdims;
+  std::vector<int64_t> idims = net.bd();
+  for (int64_t d : adjoint ? net.ldims : net.rdims) idims.push_back(d);
   idims.push_back(k);
-  TView cur = tview_rm(X, in + kSketchLeg, idims);
+  TView cur = tview_rm(X, net.bl() + in + kSketchLeg, idims);
   std::vector<TView> rest = net.ops;
   if (adjoint)
     for (auto& v : rest) v.conj = cplx && !v.conj;
@@ -121,12 +163,8 @@ void apply_network(Ctx& ctx, bool cplx, const Network& net, bool adjoint, const 
     int64_t best_size = 0;
     std::string best_out;
     for (int i = 0; i < (int)rest.size(); ++i) {
-      std::string o;
       int shared = 0;
-      for (char c : cur.legs)
-        if (rest[i].legs.find(c) == std::string::npos) o += c; else ++shared;
-      for (char c : rest[i].legs)
-        if (cur.legs.find(c) == std::string::npos) o += c;
+      const std::string o = product_legs(net, cur, rest[i], &shared);
       const int64_t sz = vol(o, cur, rest[i]);
       if (shared > best_shared || (shared == best_shared && sz < best_size)) {
         best = i;
@@ -139,7 +177,7 @@ void apply_network(Ctx& ctx, bool cplx, const Network& net, bool adjoint, const 
     rest.erase(rest.begin() + best);
     if (rest.empty()) {
       // the legs left must be the output legs and the panel leg
-      std::string want = out + kSketchLeg;
+      std::string want = net.bl() + out + kSketchLeg;
       HP_REQUIRE(best_out.size() == want.size(), HPEPS_ERR_INVALID_ARG, "network legs do not close");
       for (char c : want)
         HP_REQUIRE(best_out.find(c) != std::string::npos, HPEPS_ERR_INVALID_ARG, "network legs do not close");
@@ -163,8 +201,8 @@ void form_network(Ctx& ctx, bool cplx, const Network& net, bool adjoint, double*
   std::vector<TView> rest = net.ops;
   if (adjoint)
     for (auto& v : rest) v.conj = cplx && !v.conj;
-  const std::string want = adjoint ? net.right + net.left : net.left + net.right;
-  const int64_t total = net.rows * net.cols;
+  const std::string want = net.bl() + (adjoint ? net.right + net.left : net.left + net.right);
+  const int64_t total = std::max<int64_t>(net.batch, 1) * net.rows * net.cols;
   if (rest.size() == 1) {
     // one operand: a permuted copy, as a contraction with a one-element tensor
     // over a unit leg
@@ -184,12 +222,8 @@ void form_network(Ctx& ctx, bool cplx, const Network& net, bool adjoint, double*
     int64_t best_size = 0;
     std::string best_out;
     for (int i = 0; i < (int)rest.size(); ++i) {
-      std::string o;
       int shared = 0;
-      for (char c : cur.legs)
-        if (rest[i].legs.find(c) == std::string::npos) o += c; else ++shared;
-      for (char c : rest[i].legs)
-        if (cur.legs.find(c) == std::string::npos) o += c;
+      const std::string o = product_legs(net, cur, rest[i], &shared);
       const int64_t sz = vol(o, cur, rest[i]);
       if (shared > best_shared || (shared == best_shared && sz < best_size)) {
         best = i;
@@ -225,7 +259,8 @@ void einsumsvd_explicit(Ctx& ctx, bool cplx, const Network& net, const hpeps_esv
   ctx.last_rank = mp;
   ctx.last_k = k;
   const int es = cplx ? 2 : 1;
-  double* M = ctx.ws<double>(rows * cols * es);
+  const int nb = (int)std::max<int64_t>(net.batch, 1);
+  double* M = ctx.ws<double>(nb * rows * cols * es);
   ZipOut out;
   out.Urows.add(rows, mp);
   out.Ucol.add(mp, 1);
@@ -235,13 +270,17 @@ void einsumsvd_explicit(Ctx& ctx, bool cplx, const Network& net, const hpeps_esv
   out.nR = mp * cols;
   const bool wide = rows <= cols;
   form_network(ctx, cplx, net, wide, M);
-  std::vector<int64_t> mdims = net.ldims, pdims = net.ldims;
+  std::vector<int64_t> mdims = net.bd(), pdims = net.bd();
+  mdims.insert(mdims.end(), net.ldims.begin(), net.ldims.end());
   mdims.insert(mdims.end(), net.rdims.begin(), net.rdims.end());
+  pdims.insert(pdims.end(), net.ldims.begin(), net.ldims.end());
   pdims.push_back(k);
-  dense_finish(ctx, cplx, rows, cols, mp, 1, o, absorb, out, U, sigma, R, log_scale, M,
+  const std::string b = net.bl();
+  dense_finish(ctx, cplx, rows, cols, mp, nb, o, absorb, out, U, sigma, R, log_scale, M,
                [&](bool, const double* P, double* Bs) {
-                 contract2(ctx, cplx, tview_rm(M, net.left + net.right, mdims, cplx),
-                           tview_rm(P, net.left + kSketchLeg, pdims), net.right + kSketchLeg, Bs, cols * k);
+                 contract2(ctx, cplx, tview_rm(M, b + net.left + net.right, mdims, cplx),
+                           tview_rm(P, b + net.left + kSketchLeg, pdims), b + net.right + kSketchLeg, Bs,
+                           nb * cols * k);
                });
 }
 
@@ -249,10 +288,10 @@ void einsumsvd_explicit(Ctx& ctx, bool cplx, const Network& net, const hpeps_esv
 
 void einsumsvd_network(Ctx& ctx, bool cplx, const char* subscripts, int n_ops, const hpeps_tensor* ops,
                        const hpeps_esvd_opts& o, hpeps_absorb absorb, void* U, double* sigma, void* R,
-                       double* log_scale) {
+                       double* log_scale, int64_t batch) {
   WsScope scope(ctx);
   HP_REQUIRE(o.sketch_precision == HPEPS_F64, HPEPS_ERR_DTYPE, "network einsumsvd runs in FP64 / complex128");
-  const Network net = parse(subscripts, n_ops, ops, cplx);
+  const Network net = parse(subscripts, n_ops, ops, cplx, batch);
   HP_REQUIRE(o.method == HPEPS_ESVD_IMPLICIT || o.method == HPEPS_ESVD_EXPLICIT, HPEPS_ERR_INVALID_ARG,
              "unknown einsumsvd method");
   if (o.method == HPEPS_ESVD_EXPLICIT) {
@@ -268,9 +307,11 @@ void einsumsvd_network(Ctx& ctx, bool cplx, const char* subscripts, int n_ops, c
   ctx.last_rank = mp;
   ctx.last_k = k;
   const int es = cplx ? 2 : 1;
-  double* Om = ctx.ws<double>(cols * k * es);
-  double* Y0 = ctx.ws<double>(rows * k * es);
-  sketch(ctx, Om, false, cols, k, 1, o.seed, o.stream_id, cplx);
+  // instance b of a batch draws its sketch from stream stream_id + b
+  const int nb = (int)std::max<int64_t>(net.batch, 1);
+  double* Om = ctx.ws<double>(nb * cols * k * es);
+  double* Y0 = ctx.ws<double>(nb * rows * k * es);
+  sketch(ctx, Om, false, cols, k, nb, o.seed, o.stream_id, cplx);
   apply_network(ctx, cplx, net, false, Om, Y0, k);
   ZipOut out;
   out.Urows.add(rows, mp);
@@ -279,7 +320,7 @@ void einsumsvd_network(Ctx& ctx, bool cplx, const char* subscripts, int n_ops, c
   out.Rcols.add(cols, 1);
   out.nU = rows * mp;
   out.nR = mp * cols;
-  rsvd_finish(ctx, cplx, rows, cols, k, mp, 1, o, absorb, out, U, sigma, R, log_scale, Y0,
+  rsvd_finish(ctx, cplx, rows, cols, k, mp, nb, o, absorb, out, U, sigma, R, log_scale, Y0,
               [&](bool adj, const double* X, double* Y) { apply_network(ctx, cplx, net, adj, X, Y, k); });
 }
 

@@ -113,10 +113,12 @@ void zip_esvd(Ctx& ctx, bool cplx, const ZipDims& z, const ZipLayout& L, const Z
 
 // einsumsvd of an arbitrary network given by subscripts ("ab,bc->a|c"):
 // rows are the open legs left of '|', columns those right of it; FP64 /
-// complex128, one instance.  U [rows, m'] and R [m', cols] row-major.
+// complex128.  U [rows, m'] and R [m', cols] row-major.  batch 0: one
+// network; batch >= 1: every operand has a leading instance dimension and
+// the outputs are [batch][...] (sigma [batch][m'], log_scale [batch]).
 void einsumsvd_network(Ctx& ctx, bool cplx, const char* subscripts, int n_ops, const hpeps_tensor* ops,
                        const hpeps_esvd_opts& o, hpeps_absorb absorb, void* U, double* sigma, void* R,
-                       double* log_scale);
+                       double* log_scale, int64_t batch = 0);
 void einsumsvd_query(const char* subscripts, int n_ops, const hpeps_tensor* ops, const hpeps_esvd_opts& o,
                      int64_t* rows, int64_t* cols, int64_t* rank);
 
