@@ -74,8 +74,20 @@ def cpu_baseline(n_inst):
     dt = time.perf_counter() - t0
     np.asarray(0)
     return {"value": n_inst * step_flops() / dt / 1e9, "unit": "GFLOP/s", "cores": threads,
-            "kind": "oracle",
+            "cpu": cpu_model(), "kind": "oracle",
             "sample": f"{n_inst} of the {BATCH} instances, FP64 NumPy oracle, {dt:.1f} s"}
+
+
+def cpu_model():
+    """The host CPU's model name (Linux /proc/cpuinfo), or None where it is not readable."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def measured_traffic(kernel):
