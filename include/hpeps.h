@@ -266,6 +266,31 @@ hpeps_status hpeps_einsumsvd_query(hpeps_ctx* ctx, const char* subscripts, int32
                                    const hpeps_tensor* ops, const hpeps_esvd_opts* opts, int64_t* rows,
                                    int64_t* cols, int64_t* rank_kept);
 
+/* ---- adjoint of the network einsumsvd (reverse mode, Sec. II-C, Alg. 4) --
+ * Gradients of a real loss of the outputs of hpeps_einsumsvd with respect
+ * to every operand, for the same subscripts, operands and options (the
+ * sketch is held fixed; the CholeskyQR orthogonalization, the small SVD and
+ * the canonical phase are differentiated as computed).  dU [row legs...,
+ * m'] and dR [m', column legs...] are the cotangents of U and R (device,
+ * contiguous, the dtype of the call), dsigma [m'] that of sigma (device
+ * double; NULL = 0).  broadening as for hpeps_einsumsvd_pair_backward (the
+ * Lorentzian d / (d^2 + broadening * s_1^4), 0 = the exact derivative).
+ * grads: n_ops device pointers (host array); grads[i]
+ * receives the gradient of operand i, contiguous row-major over that
+ * operand's subscript legs (its shape), overwritten; NULL skips operand i.
+ * Complex gradients follow the conjugate-Wirtinger convention
+ * (dL/dRe + i dL/dIm), which also holds for operands entered conjugated.
+ * The k sketched singular values must be nonzero: the reverse walk uses
+ * all k right singular vectors V = B Z Sigma^-1 of the projection, so a
+ * network of exact rank below k = min(rank + oversample, rows, cols) gives
+ * unbounded gradients (keep rank + oversample within the network's rank).
+ * Absorb modes NONE and RIGHT (others UNSUPPORTED); method IMPLICIT and orth
+ * CHOLQR only; errors otherwise as hpeps_einsumsvd. */
+hpeps_status hpeps_einsumsvd_backward(hpeps_ctx* ctx, hpeps_dtype dtype, const char* subscripts, int32_t n_ops,
+                                      const hpeps_tensor* ops, const hpeps_esvd_opts* opts, hpeps_absorb absorb,
+                                      double broadening, const void* dU, const double* dsigma, const void* dR,
+                                      void* const* grads);
+
 /* ---- batched einsumsvd of an arbitrary network (Sec. II-C, Alg. 4) ------
  * `batch` independent instances of the network of hpeps_einsumsvd, each
  * factorized on its own.  Every operand has one more dimension than its
@@ -341,9 +366,8 @@ hpeps_status hpeps_einsumsvd_pair(hpeps_ctx* ctx, int64_t batch, hpeps_dtype dty
  * SVD backward are Lorentzian-broadened, d / (d^2 + broadening * s_1^4) with
  * d = s_j^2 - s_i^2 (0 where d = 0); broadening = 0 gives the exact
  * derivative, a small value (1e-12) bounds the gradient of (near-)degenerate
- * spectra.  The result is the exact derivative of the algorithm for losses
- * that do not depend on the phase of the singular vectors (the canonical
- * phase choice is not differentiated).
+ * spectra.  The result is the exact derivative of the algorithm, the
+ * canonical phase choice of the singular pairs included.
  *   absorb: HPEPS_ABSORB_NONE or RIGHT, as in the forward call; the
  *   sketch_precision of opts must be HPEPS_F64.  Workspace: a few times the
  *   forward call's (all panels of the power iteration are kept).

@@ -116,3 +116,48 @@ def pair_einsumsvd_vjp(Bl, Br, T1, T2, m, q, omega, right, dU, ds, dR):
          + torch.real((torch.tensor(dR, dtype=dt).conj() * R).sum()))
     L.backward()
     return [t.grad.numpy() for t in ts]
+
+
+def network_apply(subscripts, ts, conj):
+    """A X and A^* Y for the network `subscripts` ("ab,bc->a|c") over the torch tensors ts
+    (operand i conjugated where conj[i]): the matrix A[(row legs), (column legs)] of the
+    network (Sec. II-C) contracted explicitly."""
+    lhs, rhs = subscripts.split("->")
+    left, right = rhs.split("|")
+    ops = [t.conj() if c else t for t, c in zip(ts, conj)]
+    A = torch.einsum(lhs + "->" + left + right, *ops)
+    rows = int(np.prod(A.shape[:len(left)]))
+    cols = int(np.prod(A.shape[len(left):]))
+    A = A.reshape(rows, cols)
+    return (lambda X: A @ X), (lambda Y: A.conj().T @ Y), rows, cols
+
+
+def network_einsumsvd_vjp(subscripts, tensors, conj, m, q, omega, right, dU, ds, dR):
+    """Gradients of L = Re<dU, U> + <ds, s> + Re<dR, R> (R = V^* or diag(s) V^*, U: rows x m',
+    R: m' x cols) of Alg. 4 with the fixed sketch omega on the network's matrix, with respect
+    to every operand (numpy arrays in and out; conjugate-Wirtinger for complex operands)."""
+    cplx = any(np.iscomplexobj(t) for t in tensors) or np.iscomplexobj(omega)
+    dt = torch.complex128 if cplx else torch.float64
+    ts = [torch.tensor(np.asarray(t), dtype=dt, requires_grad=True) for t in tensors]
+    fwd, adj, _, _ = network_apply(subscripts, ts, conj or [False] * len(ts))
+    U, s, Vh = randomized_svd(fwd, adj, m, q, torch.tensor(omega, dtype=dt))
+    R = s.to(dt)[:, None] * Vh if right else Vh
+    L = (torch.real((torch.tensor(dU, dtype=dt).conj() * U).sum())
+         + (torch.tensor(ds) * s).sum()
+         + torch.real((torch.tensor(dR, dtype=dt).conj() * R).sum()))
+    L.backward()
+    return [t.grad.numpy() for t in ts]
+
+
+def network_einsumsvd_vjp_loss(subscripts, tensors, conj, m, q, omega, right, dU, ds, dR):
+    """The loss of network_einsumsvd_vjp alone (for finite differences)."""
+    cplx = any(np.iscomplexobj(t) for t in tensors) or np.iscomplexobj(omega)
+    dt = torch.complex128 if cplx else torch.float64
+    with torch.no_grad():
+        ts = [torch.tensor(np.asarray(t), dtype=dt) for t in tensors]
+        fwd, adj, _, _ = network_apply(subscripts, ts, conj or [False] * len(ts))
+        U, s, Vh = randomized_svd(fwd, adj, m, q, torch.tensor(omega, dtype=dt))
+        R = s.to(dt)[:, None] * Vh if right else Vh
+        return float(torch.real((torch.tensor(dU, dtype=dt).conj() * U).sum())
+                     + (torch.tensor(ds) * s).sum()
+                     + torch.real((torch.tensor(dR, dtype=dt).conj() * R).sum()))

@@ -78,6 +78,9 @@ _SIGS = {
                                C.c_uint64, _P]),
     "hpeps_einsumsvd": (C.c_int, [_P, C.c_int, C.c_char_p, C.c_int32, C.POINTER(Tensor),
                                   C.POINTER(EsvdOpts), C.c_int, _P, _P, _P, _P]),
+    "hpeps_einsumsvd_backward": (C.c_int, [_P, C.c_int, C.c_char_p, C.c_int32, C.POINTER(Tensor),
+                                           C.POINTER(EsvdOpts), C.c_int, C.c_double, _P, _P, _P,
+                                           C.POINTER(C.c_void_p)]),
     "hpeps_einsumsvd_batched": (C.c_int, [_P, C.c_int, C.c_int64, C.c_char_p, C.c_int32, C.POINTER(Tensor),
                                           C.POINTER(EsvdOpts), C.c_int, _P, _P, _P, _P]),
     "hpeps_einsumsvd_query": (C.c_int, [_P, C.c_char_p, C.c_int32, C.POINTER(Tensor),

@@ -98,6 +98,41 @@ def einsumsvd(ctx, subscripts, *tensors, conj=None, rank, oversample=0, power_it
     return U, sig, R
 
 
+def einsumsvd_backward(ctx, subscripts, *tensors, dU, dsigma=None, dR, conj=None, rank, oversample=0,
+                       power_iters=0, seed=0, stream_id=0, absorb=ABSORB_NONE, jacobi_max_sweeps=0,
+                       broadening=0.0):
+    """Vector-Jacobian product of einsumsvd on the same network, operands and options
+    (absorb NONE or RIGHT): the cotangents dU, dsigma (None = 0), dR of its outputs give the
+    conjugate-Wirtinger gradient of the real loss with respect to every operand (contiguous,
+    the operands' shapes)."""
+    torch = _torch()
+    if not tensors:
+        raise ValueError("no operands")
+    dt = _dtype_code(tensors[0])
+    if any(t.dtype != tensors[0].dtype for t in tensors):
+        raise TypeError("operands must share one dtype")
+    descs, ldims, rdims = _network(subscripts, tensors, conj)
+    o = make_opts(rank, oversample, power_iters, "f64", seed, stream_id, jacobi_max_sweeps)
+    rows, cols, mp = C.c_int64(), C.c_int64(), C.c_int64()
+    ctx.check(ctx.lib.hpeps_einsumsvd_query(ctx.h, subscripts.encode(), len(tensors), descs, C.byref(o),
+                                            C.byref(rows), C.byref(cols), C.byref(mp)))
+    if tuple(dU.shape) != (*ldims, mp.value) or tuple(dR.shape) != (mp.value, *rdims) \
+            or (dsigma is not None and tuple(dsigma.shape) != (mp.value,)):
+        raise ValueError("cotangent shapes do not match the outputs")
+    for t, nm in ((dU, "dU"), (dR, "dR")):
+        if t.dtype != tensors[0].dtype or not t.is_contiguous():
+            raise TypeError(f"{nm} must be contiguous with the dtype of the operands")
+    if dsigma is not None and dsigma.dtype != torch.float64:
+        raise TypeError("dsigma must be float64")
+    grads = [torch.empty(t.shape, dtype=t.dtype, device=t.device) for t in tensors]
+    gptrs = (C.c_void_p * len(grads))(*[_dev(g, "grad") for g in grads])
+    ctx.sync_stream()
+    ctx.check(ctx.lib.hpeps_einsumsvd_backward(
+        ctx.h, dt, subscripts.encode(), len(tensors), descs, C.byref(o), absorb, float(broadening),
+        _dev(dU, "dU"), _dev(dsigma, "dsigma") if dsigma is not None else None, _dev(dR, "dR"), gptrs))
+    return grads
+
+
 def einsumsvd_batched(ctx, subscripts, *tensors, conj=None, rank, oversample=0, power_iters=0, seed=0,
                       stream_id=0, absorb=ABSORB_NONE, log_scale=None, jacobi_max_sweeps=0, orth="cholqr",
                       method="implicit"):

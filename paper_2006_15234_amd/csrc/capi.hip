@@ -230,6 +230,23 @@ hpeps_status hpeps_einsumsvd_batched(hpeps_ctx* ctx, hpeps_dtype dtype, int64_t 
   });
 }
 
+hpeps_status hpeps_einsumsvd_backward(hpeps_ctx* ctx, hpeps_dtype dtype, const char* subscripts, int32_t n_ops,
+                                      const hpeps_tensor* ops, const hpeps_esvd_opts* opts, hpeps_absorb absorb,
+                                      double broadening, const void* dU, const double* dsigma, const void* dR,
+                                      void* const* grads) {
+  if (!ctx) return HPEPS_ERR_INVALID_ARG;
+  return guard(ctx, [&] {
+    check_opts(opts);
+    const bool cplx = is_cplx(dtype);
+    HP_REQUIRE(absorb == HPEPS_ABSORB_NONE || absorb == HPEPS_ABSORB_RIGHT, HPEPS_ERR_UNSUPPORTED,
+               "the adjoint supports the NONE and RIGHT absorb modes");
+    hp::Ctx& c = *ctx->impl;
+    c.ws_reset();
+    hp::einsumsvd_network_backward(c, cplx, subscripts, n_ops, ops, *opts, absorb, broadening, dU, dsigma, dR,
+                                   grads);
+  });
+}
+
 hpeps_status hpeps_einsumsvd_query(hpeps_ctx* ctx, const char* subscripts, int32_t n_ops,
                                    const hpeps_tensor* ops, const hpeps_esvd_opts* opts, int64_t* rows,
                                    int64_t* cols, int64_t* rank_kept) {

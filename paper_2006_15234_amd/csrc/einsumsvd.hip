@@ -247,6 +247,43 @@ void form_network(Ctx& ctx, bool cplx, const Network& net, bool adjoint, double*
   }
 }
 
+// Contracts the tensors `ts` greedily (as apply_network, from the first)
+// into C, row-major in the order of `want`, adding to what C holds.
+void contract_all(Ctx& ctx, bool cplx, const Network& net, std::vector<TView> ts, const std::string& want, void* C,
+                  int64_t c_elems) {
+  WsScope scope(ctx);
+  TView cur = ts[0];
+  ts.erase(ts.begin());
+  while (!ts.empty()) {
+    int best = -1, best_shared = -1;
+    int64_t best_size = 0;
+    std::string best_out;
+    for (int i = 0; i < (int)ts.size(); ++i) {
+      int shared = 0;
+      const std::string o = product_legs(net, cur, ts[i], &shared);
+      const int64_t sz = vol(o, cur, ts[i]);
+      if (shared > best_shared || (shared == best_shared && sz < best_size)) {
+        best = i;
+        best_shared = shared;
+        best_size = sz;
+        best_out = o;
+      }
+    }
+    const TView op = ts[best];
+    ts.erase(ts.begin() + best);
+    if (ts.empty()) {
+      HP_REQUIRE(best_out.size() == want.size(), HPEPS_ERR_INVALID_ARG, "network legs do not close");
+      for (char c : want)
+        HP_REQUIRE(best_out.find(c) != std::string::npos, HPEPS_ERR_INVALID_ARG, "network legs do not close");
+      contract2(ctx, cplx, cur, op, want, C, c_elems, true);
+    } else {
+      double* buf = ctx.ws<double>(best_size * (cplx ? 2 : 1));
+      const auto dims = contract2(ctx, cplx, cur, op, best_out, buf, best_size);
+      cur = tview_rm(buf, best_out, dims);
+    }
+  }
+}
+
 // The einsumsvd of BMPS: the explicit matrix and its dense truncated SVD.
 void einsumsvd_explicit(Ctx& ctx, bool cplx, const Network& net, const hpeps_esvd_opts& o, hpeps_absorb absorb,
                         void* U, double* sigma, void* R, double* log_scale) {
@@ -322,6 +359,68 @@ void einsumsvd_network(Ctx& ctx, bool cplx, const char* subscripts, int n_ops, c
   out.nR = mp * cols;
   rsvd_finish(ctx, cplx, rows, cols, k, mp, nb, o, absorb, out, U, sigma, R, log_scale, Y0,
               [&](bool adj, const double* X, double* Y) { apply_network(ctx, cplx, net, adj, X, Y, k); });
+}
+
+// Adjoint of the network einsumsvd.  The reverse walk through Alg. 4 gives
+// the operator's cotangent as rank-k terms Abar = sum_t L_t R_t^H; the
+// gradient of operand i is the network without operand i, closed by L_t on
+// the row legs and R_t on the column legs (summed over the k leg and the
+// terms).  Gradients follow the conjugate-Wirtinger convention (dL/dRe +
+// i dL/dIm): for an operand that enters as itself the contraction takes L_t,
+// conj(R_t) and every other operand conjugated once more; for one that
+// enters conjugated, conj(L_t), R_t and the others as they enter.
+void einsumsvd_network_backward(Ctx& ctx, bool cplx, const char* subscripts, int n_ops, const hpeps_tensor* ops,
+                                const hpeps_esvd_opts& o, hpeps_absorb absorb, double broadening, const void* dU,
+                                const double* dsigma, const void* dR, void* const* grads, int64_t batch) {
+  WsScope scope(ctx);
+  HP_REQUIRE(o.method == HPEPS_ESVD_IMPLICIT, HPEPS_ERR_UNSUPPORTED,
+             "the adjoint differentiates the randomized (implicit) einsumsvd");
+  HP_REQUIRE(grads && dU && dR, HPEPS_ERR_INVALID_ARG, "null argument");
+  const Network net = parse(subscripts, n_ops, ops, cplx, batch);
+  const int64_t rows = net.rows, cols = net.cols;
+  const int64_t k = sketch_width(o.rank, o.oversample, rows, cols);
+  const int64_t mp = std::min<int64_t>(o.rank, k);
+  HP_REQUIRE(k >= 1 && k <= (cplx ? 88 : 128), HPEPS_ERR_SHAPE, "sketch width k out of range");
+  HP_REQUIRE(rows < (1LL << 31) && cols < (1LL << 31), HPEPS_ERR_UNSUPPORTED, "matrix dimension too large");
+  const int nb = (int)std::max<int64_t>(net.batch, 1);
+  const int es = cplx ? 2 : 1;
+  ZipOut out;
+  out.Urows.add(rows, mp);
+  out.Ucol.add(mp, 1);
+  out.Rrow.add(mp, cols);
+  out.Rcols.add(cols, 1);
+  out.nU = rows * mp;
+  out.nR = mp * cols;
+  RankTerms terms;
+  rsvd_backward_terms(ctx, cplx, rows, cols, nb, o, absorb, broadening, out, dU, dsigma, dR,
+                      [&](bool adj, const double* X, double* Y) { apply_network(ctx, cplx, net, adj, X, Y, k); },
+                      terms);
+  const std::string b = net.bl();
+  std::vector<int64_t> ldk = net.bd(), rdk = net.bd();
+  ldk.insert(ldk.end(), net.ldims.begin(), net.ldims.end());
+  ldk.push_back(k);
+  rdk.insert(rdk.end(), net.rdims.begin(), net.rdims.end());
+  rdk.push_back(k);
+  for (int i = 0; i < n_ops; ++i) {
+    if (!grads[i]) continue;
+    const TView& oi = net.ops[i];
+    int64_t n = 1;
+    for (int64_t d : oi.dims) n *= d;
+    fill_zero(ctx, grads[i], n * es * 8);
+    const bool flip = !oi.conj;
+    for (const auto& t : terms) {
+      std::vector<TView> ts;
+      ts.push_back(tview_rm(t.first, b + net.left + kSketchLeg, ldk, cplx && !flip));
+      ts.push_back(tview_rm(t.second, b + net.right + kSketchLeg, rdk, cplx && flip));
+      for (int j = 0; j < n_ops; ++j) {
+        if (j == i) continue;
+        TView v = net.ops[j];
+        v.conj = cplx && (v.conj != flip);
+        ts.push_back(v);
+      }
+      contract_all(ctx, cplx, net, ts, oi.legs, grads[i], n);
+    }
+  }
 }
 
 void einsumsvd_query(const char* subscripts, int n_ops, const hpeps_tensor* ops, const hpeps_esvd_opts& o,

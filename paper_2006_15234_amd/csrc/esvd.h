@@ -1,6 +1,7 @@
 // einsumsvd internals shared by the ABI entry points and the boundary code.
 #pragma once
 #include <functional>
+#include <utility>
 #include "internal.h"
 
 namespace hp {
@@ -90,6 +91,8 @@ int64_t sketch_width(int64_t m, int64_t p, int64_t rows, int64_t cols);
 // A X (adj = false, X: cols x k) or A^* X (adj = true, X: rows x k) of an
 // implicit operator, FP64 / complex128 panels, row-major per instance.
 using ApplyFn = std::function<void(bool adj, const double* X, double* Y)>;
+// Rank-k terms (L_t, R_t) of an operator cotangent Abar = sum_t L_t R_t^H.
+using RankTerms = std::vector<std::pair<const double*, const double*>>;
 
 struct ZipOut;
 // Alg. 4 from the first product Y0 = A Omega on (orthogonalizations, power
@@ -119,6 +122,18 @@ void zip_esvd(Ctx& ctx, bool cplx, const ZipDims& z, const ZipLayout& L, const Z
 void einsumsvd_network(Ctx& ctx, bool cplx, const char* subscripts, int n_ops, const hpeps_tensor* ops,
                        const hpeps_esvd_opts& o, hpeps_absorb absorb, void* U, double* sigma, void* R,
                        double* log_scale, int64_t batch = 0);
+// Reverse mode of Alg. 4 up to the operator (see esvd_grad.hip): recomputes
+// the forward pass through `apply` and appends the operator cotangent's
+// rank-k terms to `terms` (buffers in the caller's workspace scope).
+void rsvd_backward_terms(Ctx& ctx, bool cplx, int64_t rows, int64_t cols, int batch, const hpeps_esvd_opts& o,
+                         hpeps_absorb absorb, double broadening, const ZipOut& out, const void* dU,
+                         const double* dsigma, const void* dR, const ApplyFn& apply, RankTerms& terms);
+// Adjoint of einsumsvd_network (batch 0: one network): gradients of every
+// operand (grads[i] row-major over operand i's legs, [batch] first when
+// batched; NULL skips it) for the output cotangents dU, dsigma, dR.
+void einsumsvd_network_backward(Ctx& ctx, bool cplx, const char* subscripts, int n_ops, const hpeps_tensor* ops,
+                                const hpeps_esvd_opts& o, hpeps_absorb absorb, double broadening, const void* dU,
+                                const double* dsigma, const void* dR, void* const* grads, int64_t batch = 0);
 void einsumsvd_query(const char* subscripts, int n_ops, const hpeps_tensor* ops, const hpeps_esvd_opts& o,
                      int64_t* rows, int64_t* cols, int64_t* rank);
 

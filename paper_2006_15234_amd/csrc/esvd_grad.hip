@@ -179,32 +179,30 @@ static void zip_vjp_term(Ctx& ctx, bool cplx, const ZipDims& z, const ZipLayout&
   }
 }
 
-void zip_esvd_backward(Ctx& ctx, bool cplx, const ZipDims& z, const ZipLayout& L,
-                       const ZipOperands& op, int batch, const hpeps_esvd_opts& o,
-                       hpeps_absorb absorb, double broadening, const ZipOut& out, const void* dU,
-                       const double* dsigma, const void* dR, void* gV, void* gS, void* gT,
-                       void* gBra) {
-  WsScope scope(ctx);
+// Reverse mode of Alg. 4 up to the operator: the forward pass is recomputed
+// through `apply` (A X for adj = false, A^* X for adj = true), keeping every
+// panel, and then walked back through the factors, the canonical phase, the
+// small SVD, the projection and the power iterations.  The cotangent of the
+// operator comes out as a sum of rank-k terms Abar = sum_t L_t R_t^H (L_t
+// rows x k, R_t cols x k per instance), appended to `terms`; their buffers
+// live in the caller's workspace scope.
+void rsvd_backward_terms(Ctx& ctx, bool cplx, int64_t rows, int64_t cols, int batch, const hpeps_esvd_opts& o,
+                         hpeps_absorb absorb, double broadening, const ZipOut& out, const void* dU,
+                         const double* dsigma, const void* dR, const ApplyFn& apply, RankTerms& terms) {
   HP_REQUIRE(broadening >= 0.0, HPEPS_ERR_INVALID_ARG, "broadening must be >= 0");
   HP_REQUIRE(o.sketch_precision == HPEPS_F64, HPEPS_ERR_DTYPE, "the adjoint runs in FP64 / complex128");
   HP_REQUIRE(o.orth == HPEPS_ORTH_CHOLQR, HPEPS_ERR_UNSUPPORTED, "the adjoint differentiates the CholeskyQR path");
   HP_REQUIRE(absorb == HPEPS_ABSORB_NONE || absorb == HPEPS_ABSORB_RIGHT || absorb == HPEPS_ABSORB_CARRY,
              HPEPS_ERR_UNSUPPORTED, "the adjoint supports the NONE, RIGHT and CARRY absorb modes");
-  const int64_t rows = z.rows(), cols = z.cols();
   const int64_t k = sketch_width(o.rank, o.oversample, rows, cols);
   const int64_t mp = std::min<int64_t>(o.rank, k);
   HP_REQUIRE(k >= 1 && k <= (cplx ? 88 : 128), HPEPS_ERR_SHAPE, "sketch width out of range");
-  const Prec p = cplx ? Prec::C128 : Prec::F64;
   const int es = cplx ? 2 : 1;
   const int64_t nb = batch, q = o.power_iters;
   const int max_sweeps = o.jacobi_max_sweeps > 0 ? o.jacobi_max_sweeps : 40;
   auto R_ = [&](int64_t n) { return ctx.ws<double>(nb * n * es); };
 
   // ---- forward recompute, keeping the panels
-  ZipWork w;
-  w.W1 = R_(z.u * z.h * z.d * z.y * z.c * z.g * k);
-  w.W2 = R_(zip_w2_elems(z, k));
-  w.W3 = R_(z.b * z.h * z.h * k);
   OrthWork ow;
   ow.G = R_(k * k);
   ow.Rinv = R_(k * k);
@@ -227,15 +225,15 @@ void zip_esvd_backward(Ctx& ctx, bool cplx, const ZipDims& z, const ZipLayout& L
   int* sweeps = ctx.ws<int>(nb);
 
   sketch(ctx, Om, false, cols, k, batch, o.seed, o.stream_id, cplx);
-  zip_apply(ctx, p, z, L, op, batch, k, false, Om, Xr, true, w);
+  apply(false, Om, Xr);
   orthogonalize(ctx, cplx, Xr, Ps[0], rows, k, batch, ow, RP[0]);
   for (int64_t i = 0; i < q; ++i) {
-    zip_apply(ctx, p, z, L, op, batch, k, true, Ps[i], Xc, true, w);
+    apply(true, Ps[i], Xc);
     orthogonalize(ctx, cplx, Xc, Qs[i], cols, k, batch, ow, RQ[i]);
-    zip_apply(ctx, p, z, L, op, batch, k, false, Qs[i], Xr, true, w);
+    apply(false, Qs[i], Xr);
     orthogonalize(ctx, cplx, Xr, Ps[i + 1], rows, k, batch, ow, RP[i + 1]);
   }
-  zip_apply(ctx, p, z, L, op, batch, k, true, Ps[q], B, true, w);
+  apply(true, Ps[q], B);
   cholqr_r(ctx, cplx, B, Xc, Xc2, cols, k, batch, ow);
   jacobi_svd(ctx, cplx, ow.Racc, k, batch, max_sweeps, Z, sig, isig, isig1, nullptr, sweeps);
   double* Ut = R_(rows * mp);
@@ -284,11 +282,10 @@ void zip_esvd_backward(Ctx& ctx, bool cplx, const ZipDims& z, const ZipLayout& L
   axpy_colscale(ctx, cplx, T1, Vbar, isig, cols, k, batch);
 
   // operator cotangent terms Abar += L_t R_t^H
-  std::vector<std::pair<const double*, const double*>> terms;
   double* MbarH = R_(cols * k);
   pg(ctx, cplx, batch, cols, k, k, T1, Op::N, k, cols * k, Z, Op::H, k, k * k, MbarH, k, cols * k);
   terms.push_back({Ps[q], MbarH});
-  zip_apply(ctx, p, z, L, op, batch, k, false, MbarH, Xr, true, w);
+  apply(false, MbarH, Xr);
   axpy(ctx, Pbar, Xr, 1.0, nb * rows * k * es);
 
   // ---- reverse through the power iterations
@@ -296,15 +293,41 @@ void zip_esvd_backward(Ctx& ctx, bool cplx, const ZipDims& z, const ZipLayout& L
     double* Yb = R_(rows * k);
     orth_backward(ctx, cplx, batch, rows, k, Ps[i], RP[i], Pbar, Yb);
     terms.push_back({Yb, Qs[i - 1]});
-    zip_apply(ctx, p, z, L, op, batch, k, true, Yb, Xc, true, w);       // Qbar = A^* Ybar
+    apply(true, Yb, Xc);       // Qbar = A^* Ybar
     double* Zb = R_(cols * k);
     orth_backward(ctx, cplx, batch, cols, k, Qs[i - 1], RQ[i - 1], Xc, Zb);
     terms.push_back({Ps[i - 1], Zb});
-    zip_apply(ctx, p, z, L, op, batch, k, false, Zb, Pbar, true, w);    // Pbar = A Zbar
+    apply(false, Zb, Pbar);    // Pbar = A Zbar
   }
   double* Yb0 = R_(rows * k);
   orth_backward(ctx, cplx, batch, rows, k, Ps[0], RP[0], Pbar, Yb0);
   terms.push_back({Yb0, Om});
+
+}
+
+void zip_esvd_backward(Ctx& ctx, bool cplx, const ZipDims& z, const ZipLayout& L,
+                       const ZipOperands& op, int batch, const hpeps_esvd_opts& o,
+                       hpeps_absorb absorb, double broadening, const ZipOut& out, const void* dU,
+                       const double* dsigma, const void* dR, void* gV, void* gS, void* gT,
+                       void* gBra) {
+  WsScope scope(ctx);
+  const int64_t rows = z.rows(), cols = z.cols();
+  const int64_t k = sketch_width(o.rank, o.oversample, rows, cols);
+  HP_REQUIRE(k >= 1 && k <= (cplx ? 88 : 128), HPEPS_ERR_SHAPE, "sketch width out of range");
+  const Prec p = cplx ? Prec::C128 : Prec::F64;
+  const int es = cplx ? 2 : 1;
+  const int64_t nb = batch;
+  auto R_ = [&](int64_t n) { return ctx.ws<double>(nb * n * es); };
+  ZipWork w;
+  w.W1 = R_(z.u * z.h * z.d * z.y * z.c * z.g * k);
+  w.W2 = R_(zip_w2_elems(z, k));
+  w.W3 = R_(z.b * z.h * z.h * k);
+  RankTerms terms;
+  rsvd_backward_terms(ctx, cplx, rows, cols, batch, o, absorb, broadening, out, dU, dsigma, dR,
+                      [&](bool adj, const double* X, double* Y) {
+                        zip_apply(ctx, p, z, L, op, batch, k, adj, X, Y, true, w);
+                      },
+                      terms);
 
   // ---- tensor gradients (accumulated: gT and gBra may be one buffer)
   ZipWork wL, wR;

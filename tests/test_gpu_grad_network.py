@@ -1,0 +1,110 @@
+"""GPU parity of the adjoint of the network einsumsvd (hpeps_einsumsvd_backward)
+against the gradient oracle (torch autograd of Alg. 4 with the same sketch on the
+network's explicit matrix), and against the pair adjoint on the pair network."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import grad as og
+from oracle import rsvd
+from oracle.sketch import sketch as oracle_sketch
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+hp = pytest.importorskip("paper_2006_15234_amd")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    return hp.Context(0)
+
+
+def _dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def _c(rng, cplx, *shape):
+    x = rng.standard_normal(shape)
+    return x + 1j * rng.standard_normal(shape) if cplx else x
+
+
+@pytest.mark.parametrize("cplx", [False, True])
+@pytest.mark.parametrize("absorb", [hp.ABSORB_NONE, hp.ABSORB_RIGHT])
+@pytest.mark.parametrize("q", [0, 2])
+def test_network_backward_vs_oracle(ctx, cplx, absorb, q):
+    """A[a,b,c] B[c,d,e] conj(C[e,f,a]) read as ((b,d), f), B a transposed view, truncated
+    sketch: every operand's gradient at 1e-9 of the largest entry.  The matrix has rank
+    a e = 12 >= k = 10, so every sketched singular value is nonzero."""
+    rng = np.random.default_rng(50 + q)
+    da, db, dc, dd, de, df = 3, 5, 4, 4, 4, 17
+    A = _c(rng, cplx, da, db, dc)
+    Bt = _c(rng, cplx, de, dd, dc)
+    Cc = _c(rng, cplx, de, df, da)
+    rank, p, seed, sid = 6, 4, 8, 3
+    subs, conj = "abc,cde,efa->bd|f", [False, False, True]
+    rows, cols = db * dd, df
+    k = rsvd.sketch_width(rank, p, rows, cols)
+    dU = _c(rng, cplx, db, dd, rank)
+    ds = rng.standard_normal(rank)
+    dR = _c(rng, cplx, rank, df)
+    gs = hp.einsumsvd_backward(ctx, subs, _dev(A), _dev(Bt).permute(2, 1, 0), _dev(Cc), conj=conj,
+                               dU=_dev(dU), dsigma=_dev(ds), dR=_dev(dR), rank=rank, oversample=p,
+                               power_iters=q, seed=seed, stream_id=sid, absorb=absorb)
+    ref = og.network_einsumsvd_vjp(subs, [A, Bt.transpose(2, 1, 0), Cc], conj, rank, q,
+                                   oracle_sketch(seed, sid, cols, k), absorb == hp.ABSORB_RIGHT,
+                                   dU.reshape(rows, rank), ds, dR)
+    scale = max(np.max(np.abs(r)) for r in ref)
+    for i, (g, r) in enumerate(zip(gs, ref)):
+        assert tuple(g.shape) == r.shape
+        assert np.max(np.abs(g.cpu().numpy() - r)) <= 1e-9 * scale, i
+
+
+def test_network_backward_equals_pair_backward(ctx):
+    """On the pair network (T1 and T2 entering as ket and as conjugated bra) the generic
+    adjoint equals the pair adjoint, whose T1 / T2 gradients sum both entries."""
+    m, D, d, rank, p, q = 9, 3, 2, 12, 6, 1
+    inst = synth.pair_instance(m, D, d, seed=23, instance=0, complex_=True)
+    dev = [_dev(t) for t in inst]
+    rows = m * D * D
+    mp = rank
+    rng = np.random.default_rng(9)
+    dU = _c(rng, True, m, D, D, mp)
+    dR = _c(rng, True, mp, D, D, m)
+    ds = rng.standard_normal(mp)
+    kw = dict(rank=rank, oversample=p, power_iters=q, seed=5, stream_id=17, absorb=hp.ABSORB_RIGHT)
+    gp = hp.einsumsvd_pair_backward(ctx, *[t[None] for t in dev], _dev(dU[None]), _dev(ds[None]), _dev(dR[None]),
+                                    **kw)
+    t1 = dev[2][:, :, 0]
+    t2 = dev[3][:, :, :, 0]
+    gn = hp.einsumsvd_backward(ctx, "auUb,bvVc,uxhp,UXHp,vyhq,VYHq->axX|yYc", dev[0], dev[1], t1, t1, t2, t2,
+                               conj=[False, False, False, True, False, True], dU=_dev(dU), dsigma=_dev(ds),
+                               dR=_dev(dR), **kw)
+    gp = [g[0].cpu().numpy() for g in gp]
+    gn = [g.cpu().numpy() for g in gn]
+    scale = max(np.max(np.abs(g)) for g in gp)
+    assert rows == dU.reshape(-1, mp).shape[0]
+    assert np.max(np.abs(gn[0] - gp[0])) <= 1e-10 * scale
+    assert np.max(np.abs(gn[1] - gp[1])) <= 1e-10 * scale
+    assert np.max(np.abs(gn[2] + gn[3] - gp[2][:, :, 0])) <= 1e-10 * scale
+    assert np.max(np.abs(gn[4] + gn[5] - gp[3][:, :, :, 0])) <= 1e-10 * scale
+
+
+def test_network_backward_without_dsigma_and_errors(ctx):
+    """dsigma None is a zero cotangent; CARRY is rejected (A B has full rank 6 = k)."""
+    rng = np.random.default_rng(12)
+    A, B = rng.standard_normal((6, 6)), rng.standard_normal((6, 8))
+    dU, dR = rng.standard_normal((6, 4)), rng.standard_normal((4, 8))
+    kw = dict(rank=4, oversample=2, power_iters=1, seed=1)
+    g0 = hp.einsumsvd_backward(ctx, "ab,bc->a|c", _dev(A), _dev(B), dU=_dev(dU), dR=_dev(dR), **kw)
+    g1 = hp.einsumsvd_backward(ctx, "ab,bc->a|c", _dev(A), _dev(B), dU=_dev(dU), dR=_dev(dR),
+                               dsigma=torch.zeros(4, dtype=torch.float64, device="cuda"), **kw)
+    for a, b in zip(g0, g1):
+        assert torch.equal(a, b)
+    ref = og.network_einsumsvd_vjp("ab,bc->a|c", [A, B], None, 4, 1, oracle_sketch(1, 0, 8, 6), False,
+                                   dU, np.zeros(4), dR)
+    scale = max(np.max(np.abs(r)) for r in ref)
+    for g, r in zip(g0, ref):
+        assert np.max(np.abs(g.cpu().numpy() - r)) <= 1e-9 * scale
+    with pytest.raises(Exception):
+        hp.einsumsvd_backward(ctx, "ab,bc->a|c", _dev(A), _dev(B), dU=_dev(dU), dR=_dev(dR),
+                              absorb=hp.ABSORB_CARRY, **kw)

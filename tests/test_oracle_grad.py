@@ -144,3 +144,61 @@ def test_grad_oracle_phase_dependent_loss(right):
                     vals.append(_vjp_loss(ts, rank, q, omega, right, dU, ds, dR))
                 fd = fd + (vals[0] - vals[1]) / (2 * h) * part
             assert abs(fd - grads[ti][idx]) < 1e-6 * scale, (ti, idx)
+
+
+PAIR_NET = "auUb,bvVc,uxhp,UXHp,vyhq,VYHq->axX|yYc"
+
+
+@pytest.mark.parametrize("cplx", [False, True])
+@pytest.mark.parametrize("right", [False, True])
+def test_network_grad_oracle_equals_pair_oracle(cplx, right):
+    """The network gradient oracle (explicit matrix of any network) on the pair network
+    equals the pair oracle (the operator as a chain of contractions): T1 and T2 enter twice,
+    as ket and as conjugated bra, and their gradients are the sums of the two entries'."""
+    m, D, d, rank, p, q = 3, 2, 2, 4, 3, 1
+    inst = synth.pair_instance(m, D, d, seed=17, instance=0, complex_=cplx)
+    Bl, Br, T1, T2 = inst
+    op = pair_operator(*inst)
+    k = min(rank + p, op.n_rows, op.n_cols)
+    omega = oracle_sketch(5, 2, op.n_cols, k)
+    rng = np.random.default_rng(4)
+    c = (lambda *s: rng.standard_normal(s) + 1j * rng.standard_normal(s)) if cplx else \
+        (lambda *s: rng.standard_normal(s))
+    dU, ds, dR = c(op.n_rows, rank), rng.standard_normal(rank), c(rank, op.n_cols)
+    gp = og.pair_einsumsvd_vjp(*inst, rank, q, omega, right, dU, ds, dR)
+    t1, t2 = T1[:, :, 0], T2[:, :, :, 0]
+    gn = og.network_einsumsvd_vjp(PAIR_NET, [Bl, Br, t1, t1, t2, t2], [False, False, False, True, False, True],
+                                  rank, q, omega, right, dU, ds, dR)
+    scale = max(np.max(np.abs(g)) for g in gp)
+    assert np.max(np.abs(gn[0] - gp[0])) < 1e-10 * scale
+    assert np.max(np.abs(gn[1] - gp[1])) < 1e-10 * scale
+    assert np.max(np.abs(gn[2] + gn[3] - gp[2][:, :, 0])) < 1e-10 * scale
+    assert np.max(np.abs(gn[4] + gn[5] - gp[3][:, :, :, 0])) < 1e-10 * scale
+
+
+def test_network_grad_oracle_finite_differences():
+    """Central finite differences (Re and Im parts) of the network loss, on a three-operand
+    network with a conjugated operand and a truncated sketch (q = 1)."""
+    rng = np.random.default_rng(6)
+    c = lambda *s: rng.standard_normal(s) + 1j * rng.standard_normal(s)
+    A, B, Cc = c(2, 3, 4), c(4, 3, 2), c(2, 5, 2)
+    subs, conj = "abc,cde,efa->bd|f", [False, False, True]
+    rank, q = 3, 1
+    omega = oracle_sketch(3, 1, 5, 4)
+    dU, ds, dR = c(9, rank), rng.standard_normal(rank), c(rank, 5)
+    inst = [A, B, Cc]
+    grads = og.network_einsumsvd_vjp(subs, inst, conj, rank, q, omega, True, dU, ds, dR)
+    h = 1e-6
+    for ti, t in enumerate(inst):
+        scale = np.max(np.abs(grads[ti]))
+        for _ in range(6):
+            idx = tuple(rng.integers(0, s_) for s_ in t.shape)
+            fd = 0.0
+            for part in (1.0, 1j):
+                vals = []
+                for sgn in (1, -1):
+                    ts = [x.copy() for x in inst]
+                    ts[ti][idx] += sgn * h * part
+                    vals.append(og.network_einsumsvd_vjp_loss(subs, ts, conj, rank, q, omega, True, dU, ds, dR))
+                fd = fd + (vals[0] - vals[1]) / (2 * h) * part
+            assert abs(fd - grads[ti][idx]) < 1e-6 * scale, (ti, idx)
