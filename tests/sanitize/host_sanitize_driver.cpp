@@ -1,12 +1,14 @@
 // Host-side AddressSanitizer / UndefinedBehaviorSanitizer run of the C ABI.
 // Built by build.sh with the library's host code instrumented (device code is
-// not: -fsanitize only after -Xarch_host), it walks the entry points a user
-// reaches first -- context, subscript parsing with malformed input, an
-// einsumsvd of a small network, the autotune JSON round trip with malformed
-// input, a PEPS norm, an ITE plan in its three launch forms, the
-// allocation-free gate update and the profiler -- and checks every status.
-// Exit status 0 when every call returned what it should; a sanitizer report
-// aborts with its own status.
+// not: -fsanitize only after -Xarch_host).  It first checks host <-> device
+// copies and the stages of the randomized SVD against host arithmetic, then
+// walks the entry points a user reaches first -- context, subscript parsing
+// with malformed input, an einsumsvd of a small network, its batched form
+// and its adjoint, the autotune JSON round trip with malformed input, a PEPS
+// norm, an ITE plan in its three launch forms, the allocation-free gate
+// update and the profiler -- and checks every status.  Exit status 0 when
+// every call returned what it should; a sanitizer report aborts with its own
+// status.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -263,6 +265,77 @@ int main() {
   std::fprintf(stderr, "einsumsvd sigma %g %g %g  k %lld extra %d numeric %d householder %d sweeps %d\n", hs[0],
                hs[1], hs[2], (long long)info.sketch_width, info.orth_extra_passes, info.numeric_errors,
                info.orth_householder, info.jacobi_sweeps);
+
+  // ---- batched form of the network: instance 1 equals the single call with stream_id + 1 ----
+  {
+    double* A2 = dev_copy(randn(2 * a * b, g));
+    double* B2 = dev_copy(randn(2 * b * c, g));
+    hpeps_tensor bops[2];
+    std::memset(bops, 0, sizeof(bops));
+    const int64_t bsh[2][3] = {{2, a, b}, {2, b, c}}, bst[2][3] = {{a * b, b, 1}, {b * c, c, 1}};
+    bops[0].data = A2;
+    bops[1].data = B2;
+    for (int t = 0; t < 2; ++t) {
+      bops[t].ndim = 3;
+      for (int q = 0; q < 3; ++q) {
+        bops[t].shape[q] = bsh[t][q];
+        bops[t].strides[q] = bst[t][q];
+      }
+    }
+    double *U2 = nullptr, *R2 = nullptr, *s2 = nullptr;
+    if (hipMalloc(&U2, 2 * a * 3 * sizeof(double)) != hipSuccess ||
+        hipMalloc(&R2, 2 * 3 * c * sizeof(double)) != hipSuccess || hipMalloc(&s2, 6 * sizeof(double)) != hipSuccess)
+      std::abort();
+    EXPECT(hpeps_einsumsvd_batched(ctx, HPEPS_F64, 2, "ab,bc->a|c", 2, bops, &o3, HPEPS_ABSORB_NONE, U2, s2, R2,
+                                   nullptr),
+           HPEPS_OK);
+    hpeps_tensor one[2] = {ops[0], ops[1]};
+    one[0].data = A2 + a * b;
+    one[1].data = B2 + b * c;
+    hpeps_esvd_opts o3b = o3;
+    o3b.stream_id += 1;
+    EXPECT(hpeps_einsumsvd(ctx, HPEPS_F64, "ab,bc->a|c", 2, one, &o3b, HPEPS_ABSORB_NONE, U, sg, R, nullptr),
+           HPEPS_OK);
+    const std::vector<double> sb = host_copy(s2, 6), s1 = host_copy(sg, 3);
+    for (int i = 0; i < 3; ++i) CHECK(std::fabs(sb[3 + i] - s1[i]) <= 1e-12 * s1[0]);
+    EXPECT(hpeps_einsumsvd_batched(ctx, HPEPS_F64, 0, "ab,bc->a|c", 2, bops, &o3, HPEPS_ABSORB_NONE, U2, s2, R2,
+                                   nullptr),
+           HPEPS_ERR_INVALID_ARG);
+    bops[0].strides[0] = 0;  // overlapping instances
+    EXPECT(hpeps_einsumsvd_batched(ctx, HPEPS_F64, 2, "ab,bc->a|c", 2, bops, &o3, HPEPS_ABSORB_NONE, U2, s2, R2,
+                                   nullptr),
+           HPEPS_ERR_SHAPE);
+    for (double* p : {A2, B2, U2, R2, s2}) (void)hipFree(p);
+  }
+
+  // ---- adjoint of a network of full rank 6 = k (6 x 6 times 6 x 7) ----
+  {
+    double* A3 = dev_copy(randn(36, g));
+    double* B3 = dev_copy(randn(42, g));
+    hpeps_tensor ops3[2] = {ops[0], ops[1]};
+    ops3[0].data = A3;
+    ops3[0].shape[1] = 6;
+    ops3[0].strides[0] = 6;
+    ops3[1].data = B3;
+    ops3[1].shape[0] = 6;
+    double* dU3 = dev_copy(randn(6 * 3, g));
+    double* dR3 = dev_copy(randn(3 * 7, g));
+    double *g0 = nullptr, *g1 = nullptr;
+    if (hipMalloc(&g0, 36 * sizeof(double)) != hipSuccess || hipMalloc(&g1, 42 * sizeof(double)) != hipSuccess)
+      std::abort();
+    void* gp[2] = {g0, g1};
+    EXPECT(hpeps_einsumsvd_backward(ctx, HPEPS_F64, "ab,bc->a|c", 2, ops3, &o3, HPEPS_ABSORB_NONE, 0.0, dU3, nullptr,
+                                    dR3, gp),
+           HPEPS_OK);
+    bool finite = true;
+    for (double v : host_copy(g0, 36)) finite = finite && std::isfinite(v);
+    for (double v : host_copy(g1, 42)) finite = finite && std::isfinite(v);
+    CHECK(finite);
+    EXPECT(hpeps_einsumsvd_backward(ctx, HPEPS_F64, "ab,bc->a|c", 2, ops3, &o3, HPEPS_ABSORB_CARRY, 0.0, dU3,
+                                    nullptr, dR3, gp),
+           HPEPS_ERR_UNSUPPORTED);
+    for (double* p : {A3, B3, dU3, dR3, g0, g1}) (void)hipFree(p);
+  }
 
   // ---- autotune JSON: export (size query, then the text) and imports ----
   int64_t need = 0;
