@@ -832,6 +832,26 @@ def main():
     mse = (time.perf_counter() - t0) * 1e3 / args.steps
     epse = float(np.max(np.abs(oute[1].cpu().numpy() - s64) / s64[:, :1]))
 
+    # the same FP64 step through the generic batched network call (subscripts, greedy
+    # contraction order) instead of the hand-ordered pair stages
+    t1v = dev[2][:, :, :, 0]
+    t2v = dev[3][:, :, :, :, 0]
+
+    def step_net():
+        return hp.einsumsvd_batched(ctx, "auUb,bvVc,uxhp,UXHp,vyhq,VYHq->axX|yYc", dev[0], dev[1], t1v, t1v,
+                                    t2v, t2v, conj=[False, False, False, True, False, True], rank=RANK,
+                                    oversample=OVERS, power_iters=POW, seed=0, stream_id=1,
+                                    absorb=hp.ABSORB_NONE)
+    for _ in range(max(args.warmup, 1)):
+        step_net()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        outn = step_net()
+    torch.cuda.synchronize()
+    msn = (time.perf_counter() - t0) * 1e3 / args.steps
+    epsn = float(np.max(np.abs(outn[1].cpu().numpy() - s64) / s64[:, :1]))
+
     roofline = dominant_roofline(dominant, prof, pair_alg_ratio(dominant))
     res = {
         "metric": "einsumsvd GFLOP/s & boundary-contraction sweep time vs plain FP64, same GPU, at fixed eps",
@@ -862,6 +882,8 @@ def main():
                        "eps_sigma_vs_f64": eps16},
         "orth_eigh": {"ms_per_step": round(mse, 4), "time_vs_cholqr": round(mse / ms, 3),
                       "eps_sigma_vs_cholqr": epse},
+        "network_batched": {"ms_per_step": round(msn, 4), "time_vs_pair_call": round(msn / ms, 3),
+                            "eps_sigma_vs_pair_call": epsn},
         "autotune": not args.no_autotune,
         "kernel_classes": {n: class_entry(a, pair_alg_ratio(n))
                            for n, a in sorted(agg.items(), key=lambda x: -x[1]["ms"])},

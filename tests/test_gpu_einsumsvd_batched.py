@@ -158,3 +158,27 @@ def test_batched_layout_errors(ctx):
     st = ctx.lib.hpeps_einsumsvd_batched(ctx.h, hp.F64, 0, b"ab,bc->a|c", 2, descs, C.byref(o),
                                          hp.ABSORB_NONE, out.data_ptr(), None, out.data_ptr(), None)
     assert st != 0
+
+
+def test_batched_pair_network_full_size(ctx):
+    """The benchmarked configuration (pair network m=36, D=6, d=2, rank 36, p=8, q=2, 64
+    instances) through the batched network call: every instance's singular values and
+    factor product equal the specialised batched pair call (parity-tested against the
+    oracle) at 1e-10 relative to sigma_1."""
+    import synth
+    m, D, d, rank, p, q, B = 36, 6, 2, 36, 8, 2, 64
+    inst = [synth.pair_instance(m, D, d, seed=0, instance=i) for i in range(B)]
+    st = [_dev(np.stack([x[t] for x in inst])) for t in range(4)]
+    kw = dict(rank=rank, oversample=p, power_iters=q, seed=0, stream_id=1, absorb=hp.ABSORB_RIGHT)
+    U0, s0, R0 = hp.einsumsvd_pair(ctx, *st, **kw)
+    t1 = st[2][:, :, :, 0]           # [B,u,x,h,p] strided view
+    t2 = st[3][:, :, :, :, 0]        # [B,v,y,h,q] strided view
+    U, s, R = hp.einsumsvd_batched(ctx, "auUb,bvVc,uxhp,UXHp,vyhq,VYHq->axX|yYc", st[0], st[1], t1, t1, t2, t2,
+                                   conj=[False, False, False, True, False, True], **kw)
+    s0 = s0.cpu().numpy()
+    s = s.cpu().numpy()
+    assert np.max(np.abs(s - s0) / s0[:, :1]) <= 1e-10
+    for i in (0, 17, 63):
+        P0 = _product(U0[i].cpu().numpy(), s0[i], R0[i].cpu().numpy(), hp.ABSORB_RIGHT)
+        P = _product(U[i].cpu().numpy(), s0[i], R[i].cpu().numpy(), hp.ABSORB_RIGHT)
+        assert np.max(np.abs(P - P0)) <= 1e-10 * s0[i, 0], i
