@@ -11,7 +11,7 @@ from ._ffi import (  # noqa: F401
     HpepsError, Context, EsvdOpts, lib_path, load_library, symbols,
 )
 from .api import (  # noqa: F401
-    einsumsvd, einsumsvd_batched, einsumsvd_backward, einsumsvd_zipup, einsumsvd_pair, einsumsvd_pair_backward, einsumsvd_pair_autograd,
+    einsumsvd, einsumsvd_batched, einsumsvd_backward, einsumsvd_autograd, einsumsvd_zipup, einsumsvd_pair, einsumsvd_pair_backward, einsumsvd_pair_autograd,
     peps_norm, peps_amplitude, peps_amplitudes, boundary_contract_row, peps_energy, peps_energy_uncached,
     peps_trotter_expectation, peps_norm_backward, peps_energy_backward,
     peps_energy_autograd,

@@ -291,6 +291,37 @@ def einsumsvd_pair_autograd(ctx, Bl, Br, T1, T2, *, rank, oversample=0, power_it
     return _PairEsvd.apply(Bl, Br, T1, T2)
 
 
+def einsumsvd_autograd(ctx, subscripts, *tensors, conj=None, rank, oversample=0, power_iters=0, seed=0,
+                       stream_id=0, absorb=ABSORB_NONE, jacobi_max_sweeps=0, broadening=0.0):
+    """einsumsvd of the network `subscripts` as a differentiable torch function (absorb NONE
+    or RIGHT): forward and backward both run in the library (the backward recomputes the
+    forward with the same sketch), and gradients flow to every operand."""
+    torch = _torch()
+    kw = dict(rank=rank, oversample=oversample, power_iters=power_iters, seed=seed,
+              stream_id=stream_id, absorb=absorb, jacobi_max_sweeps=jacobi_max_sweeps)
+
+    class _NetworkEsvd(torch.autograd.Function):
+        @staticmethod
+        def forward(fctx, *ts):
+            fctx.save_for_backward(*ts)
+            U, s, R = einsumsvd(ctx, subscripts, *ts, conj=conj, **kw)
+            fctx.shapes = (tuple(U.shape), tuple(R.shape))
+            return U, s, R
+
+        @staticmethod
+        def backward(fctx, gU, gs, gR):
+            ts = fctx.saved_tensors
+            su, sr = fctx.shapes
+            dt, dev = ts[0].dtype, ts[0].device
+            gU = torch.zeros(su, dtype=dt, device=dev) if gU is None else gU.contiguous()
+            gR = torch.zeros(sr, dtype=dt, device=dev) if gR is None else gR.contiguous()
+            gs = None if gs is None else gs.contiguous()
+            return tuple(einsumsvd_backward(ctx, subscripts, *ts, dU=gU, dsigma=gs, dR=gR, conj=conj,
+                                            broadening=broadening, **kw))
+
+    return _NetworkEsvd.apply(*tensors)
+
+
 def sketch(ctx, n, k, batch=1, seed=0, stream_id=0, precision="f64", device="cuda"):
     """The sketch an einsumsvd with (seed, stream_id) draws: [batch, n, k]."""
     torch = _torch()

@@ -108,3 +108,31 @@ def test_network_backward_without_dsigma_and_errors(ctx):
     with pytest.raises(Exception):
         hp.einsumsvd_backward(ctx, "ab,bc->a|c", _dev(A), _dev(B), dU=_dev(dU), dR=_dev(dR),
                               absorb=hp.ABSORB_CARRY, **kw)
+
+
+@pytest.mark.parametrize("cplx", [False, True])
+def test_network_autograd_wrapper(ctx, cplx):
+    """einsumsvd_autograd inside an ordinary torch loss (one operand a permuted view of a
+    leaf, one entering conjugated): the leaves' .grad equal the gradient oracle at 1e-9."""
+    rng = np.random.default_rng(61)
+    A = _c(rng, cplx, 3, 5, 4)
+    Bt = _c(rng, cplx, 4, 4, 4)
+    Cc = _c(rng, cplx, 4, 17, 3)
+    rank, p, q, seed, sid = 6, 4, 1, 2, 5
+    subs, conj = "abc,cde,efa->bd|f", [False, False, True]
+    dU = _c(rng, cplx, 5, 4, rank)
+    ds = rng.standard_normal(rank)
+    dR = _c(rng, cplx, rank, 17)
+    leaves = [_dev(x).requires_grad_(True) for x in (A, Bt, Cc)]
+    U, s, R = hp.einsumsvd_autograd(ctx, subs, leaves[0], leaves[1].permute(2, 1, 0), leaves[2], conj=conj,
+                                    rank=rank, oversample=p, power_iters=q, seed=seed, stream_id=sid,
+                                    absorb=hp.ABSORB_RIGHT)
+    loss = (torch.real((_dev(dU).conj() * U).sum()) + (_dev(ds) * s).sum()
+            + torch.real((_dev(dR).conj() * R).sum()))
+    loss.backward()
+    ref = og.network_einsumsvd_vjp(subs, [A, Bt.transpose(2, 1, 0), Cc], conj, rank, q,
+                                   oracle_sketch(seed, sid, 17, 10), True, dU.reshape(20, rank), ds, dR)
+    ref[1] = ref[1].transpose(2, 1, 0)   # gradient of the leaf behind the permuted view
+    scale = max(np.max(np.abs(r)) for r in ref)
+    for i, (leaf, r) in enumerate(zip(leaves, ref)):
+        assert np.max(np.abs(leaf.grad.cpu().numpy() - r)) <= 1e-9 * scale, i
