@@ -1,8 +1,9 @@
 """Gradient reference for einsumsvd (test infrastructure only).
 
 A plain torch-CPU (float64 / complex128) restatement of the randomized SVD of
-Alg. 4 on the pair network, differentiated by torch autograd with the sketch
-held fixed: every QR (Householder, torch.linalg.qr) and the final SVD
+Alg. 4 on the pair network (as a chain of contractions) and on the explicit
+matrix of any network given by subscripts (Sec. II-C), differentiated by torch
+autograd with the sketch held fixed: every QR (Householder, torch.linalg.qr) and the final SVD
 (torch.linalg.svd) are differentiated as they stand.  Nothing here is shared
 with the GPU path; the inputs come from ``synth`` and the sketch from
 ``oracle.sketch``.
