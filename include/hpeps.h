@@ -465,8 +465,10 @@ hpeps_status hpeps_peps_amplitudes(hpeps_ctx* ctx, const hpeps_peps* ket, int64_
  * Terms: n_terms entries; term t acts on nsites[t] (1 or 2) sites given by
  * sites[4t .. 4t+3] = {i1, j1, i2, j2} (nearest neighbours, site 1 left of or
  * above site 2, or diagonal neighbours i2 = i1 + 1, j2 = j1 +- 1: the J2
- * pairs of Eq. 7); its operator is ops + op_offset[t] (host memory,
- * complex128 pairs, [2,2] or [2,2,2,2]).  Every term value is
+ * pairs of Eq. 7); its operator (host memory, complex128 as interleaved
+ * {re, im} pairs, [2,2] or [2,2,2,2]) starts op_offset[t] complex entries
+ * into ops, i.e. at the double ops + 2 * op_offset[t]; the call reads up to
+ * the end of the operator that ends last.  Every term value is
  * strip(term)/strip(id), where the strip is the exact contraction of the
  * cached top environment, the one (two, for vertical and diagonal terms) PEPS
  * rows of the term and the cached bottom environment; a diagonal term spans

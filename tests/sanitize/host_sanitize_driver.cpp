@@ -5,10 +5,10 @@
 // walks the entry points a user reaches first -- context, subscript parsing
 // with malformed input, an einsumsvd of a small network, its batched form
 // and its adjoint, the autotune JSON round trip with malformed input, a PEPS
-// norm, an ITE plan in its three launch forms, the allocation-free gate
-// update and the profiler -- and checks every status.  Exit status 0 when
-// every call returned what it should; a sanitizer report aborts with its own
-// status.
+// norm, an amplitude, an energy and the norm's gradient, an ITE plan in its
+// three launch forms, the allocation-free gate update and the profiler --
+// and checks every status.  Exit status 0 when every call returned what it
+// should; a sanitizer report aborts with its own status.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -363,6 +363,59 @@ int main() {
   hpeps_esvd_opts obad = o4;
   obad.rank = 0;
   EXPECT(hpeps_peps_norm(ctx, &P, nullptr, &obad, &ln, ph), HPEPS_ERR_INVALID_ARG);
+
+  // ---- amplitude <0...0|psi> and a bit out of range ----
+  {
+    std::vector<int32_t> bits(9, 0);
+    double la = 0, aph[2] = {0, 0};
+    EXPECT(hpeps_peps_amplitude(ctx, &P, bits.data(), &o4, &la, aph), HPEPS_OK);
+    CHECK(std::isfinite(la) && std::isfinite(aph[0]) && std::isfinite(aph[1]));
+    bits[4] = 2;
+    EXPECT(hpeps_peps_amplitude(ctx, &P, bits.data(), &o4, &la, aph), HPEPS_ERR_INVALID_ARG);
+  }
+
+  // ---- energy of a ZZ bond and a one-site X; a term on non-neighbours ----
+  {
+    std::vector<double> zz(32, 0.0), xop(8, 0.0), ops_h;
+    const double zs[2] = {1.0, -1.0};
+    for (int a2 = 0; a2 < 2; ++a2)
+      for (int b2 = 0; b2 < 2; ++b2) zz[2 * ((a2 * 2 + b2) * 4 + a2 * 2 + b2)] = zs[a2] * zs[b2];
+    xop[2 * 1] = xop[2 * 2] = 1.0;  // X = [[0, 1], [1, 0]] as complex pairs
+    ops_h.insert(ops_h.end(), zz.begin(), zz.end());
+    ops_h.insert(ops_h.end(), xop.begin(), xop.end());
+    const int32_t nsites[2] = {2, 1};
+    int32_t sites[8] = {0, 0, 0, 1, 1, 1, 0, 0};
+    const int64_t off[2] = {0, 16};  // in complex entries: the X operator follows the 16 of ZZ
+    double e[2] = {0, 0}, per[4] = {0, 0, 0, 0};
+    EXPECT(hpeps_peps_energy(ctx, &P, 2, nsites, sites, ops_h.data(), off, &o4, e, per), HPEPS_OK);
+    CHECK(std::isfinite(e[0]) && std::fabs(e[0] - (per[0] + per[2])) <= 1e-10 * (1 + std::fabs(e[0])));
+    sites[2] = 2;
+    sites[3] = 2;  // (0,0) with (2,2): not neighbours
+    CHECK(hpeps_peps_energy(ctx, &P, 2, nsites, sites, ops_h.data(), off, &o4, e, per) != HPEPS_OK);
+  }
+
+  // ---- gradient of log<psi|psi> with respect to every site; a null gradient pointer ----
+  {
+    std::vector<void*> gr(9, nullptr);
+    std::vector<size_t> gn(9, 1);
+    for (int t = 0; t < 9; ++t) {
+      for (int q = 0; q < 5; ++q) gn[t] *= (size_t)L.shapes[5 * t + q];
+      if (hipMalloc(&gr[t], gn[t] * sizeof(double)) != hipSuccess) std::abort();
+    }
+    double lg = 0;
+    EXPECT(hpeps_peps_norm_backward(ctx, &P, &o4, 0.0, gr.data(), &lg), HPEPS_OK);
+    CHECK(std::isfinite(lg));
+    std::fprintf(stderr, "log<psi|psi>: norm %.15g, norm_backward %.15g\n", ln, lg);
+    bool fin = true;
+    for (int t = 0; t < 9; ++t)
+      for (double v : host_copy((const double*)gr[t], gn[t])) fin = fin && std::isfinite(v);
+    CHECK(fin);
+    void* keep = gr[4];
+    gr[4] = nullptr;
+    EXPECT(hpeps_peps_norm_backward(ctx, &P, &o4, 0.0, gr.data(), &lg), HPEPS_ERR_INVALID_ARG);
+    gr[4] = keep;
+    for (void* q : gr) (void)hipFree(q);
+  }
 
   // ---- ITE plan: graph, direct layers, one launch per bond ----
   Lattice I = make_lattice(3, 4, 1, g);
